@@ -1,0 +1,245 @@
+"""CPU FP64 oracle for the screened-force + ionization step (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never links, loads or
+calls it, and the two share no code.
+
+The arithmetic lives in ``md_oracle.c`` (plain C, FP64, contraction disabled);
+this module compiles it with gcc and exposes thin ctypes wrappers over numpy
+arrays, plus a reference trajectory driver that composes the steps in the
+paper's order (ionize, screened forces, integrate).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "md_oracle.c")
+_LIB = os.path.join(_HERE, "libmd_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+             "-shared", "-fPIC"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library with gcc (FP contraction disabled)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            L = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+            L.orc_kappa_from_lambda.argtypes = [i64, P, P]
+            L.orc_debye_length_nm.argtypes = [f64, f64]
+            L.orc_debye_length_nm.restype = f64
+            L.orc_rates_from_fractions.argtypes = [i64, i32, P, P]
+            L.orc_forces.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i32, P, P, P, i32,
+                                     P, P, P, P, P, P]
+            L.orc_forces.restype = i64
+            L.orc_forces_rows.argtypes = [i64, P, P, P, i32, P, f64, P, P, P, P, P, i32, P, P,
+                                          P, i32, P, P, P, P, P, i32]
+            L.orc_forces_rows.restype = i64
+            L.orc_pairs.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i64]
+            L.orc_pairs.restype = i64
+            L.orc_pair_r2.argtypes = [i32, P, P, P, P, i64, i64]
+            L.orc_pair_r2.restype = f64
+            L.orc_philox4x32_10.argtypes = [P, P, P]
+            L.orc_ionize.argtypes = [i64, P, P, P, P, P, i32, P, P, P, i64]
+            L.orc_ionize.restype = i64
+            L.orc_vv.argtypes = [i64, i32, f64, P, P, P, P, P, P, P, P, P, P]
+            L.orc_ekin.argtypes = [i64, P, P, P, P, P, P]
+            _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ------------------------------------------------------------------ schedules
+
+def kappa_from_lambda(lambda_d) -> np.ndarray:
+    lam = _c(lambda_d, np.float64)
+    out = np.empty_like(lam)
+    lib().orc_kappa_from_lambda(lam.size, _p(lam), _p(out))
+    return out
+
+
+def debye_length_nm(te_ev: float, ne_m3: float) -> float:
+    return float(lib().orc_debye_length_nm(te_ev, ne_m3))
+
+
+def rates_from_fractions(P) -> np.ndarray:
+    P = _c(P, np.float64)
+    S = P.shape[0] - 1
+    Z = P.shape[1] - 1
+    out = np.zeros_like(P)
+    lib().orc_rates_from_fractions(S, Z, _p(P), _p(out))
+    return out
+
+
+# ------------------------------------------------------------------ forces
+
+def forces(sys, q=None, kappa=None, x=None, y=None, z=None, per_atom=True):
+    """Brute-force FP64 forces for all systems of ``sys`` at positions (x, y, z)
+    (default: the system's own), charges q and per-system kappa.
+    Returns dict(fx, fy, fz, e_atom, a_atom, epot, npairs)."""
+    x = _c(sys.x if x is None else x, np.float64)
+    y = _c(sys.y if y is None else y, np.float64)
+    z = _c(sys.z if z is None else z, np.float64)
+    q = _c(sys.q if q is None else q, np.int8)
+    B = sys.n_systems
+    if kappa is None:
+        kappa = kappa_from_lambda(sys.lambda_d[:, 0])
+    kappa = _c(np.broadcast_to(kappa, (B,)), np.float64)
+    n = x.shape[0]
+    out = {k: np.empty(n) for k in ("fx", "fy", "fz", "e_atom", "a_atom")}
+    epot = np.empty(B)
+    box = None if sys.box is None else _c(sys.box, np.float64)
+    npairs = lib().orc_forces(B, _p(_c(sys.sys_offsets, np.int64)), int(sys.periodic), _p(box),
+                              sys.rc, _p(x), _p(y), _p(z), _p(q),
+                              _p(_c(sys.type, np.uint8)), sys.n_types,
+                              _p(_c(sys.c6, np.float64)), _p(_c(sys.c12, np.float64)),
+                              _p(kappa), int(sys.screen_lj), _p(out["fx"]), _p(out["fy"]),
+                              _p(out["fz"]), _p(out["e_atom"]), _p(out["a_atom"]), _p(epot))
+    out["epot"] = epot
+    out["npairs"] = int(npairs)
+    return out
+
+
+def forces_rows(sys, rows, q=None, kappa=None, x=None, y=None, z=None, n_threads=0):
+    """F_i, e_i, A_i of the listed atoms against every atom of their system
+    (OpenMP over rows)."""
+    x = _c(sys.x if x is None else x, np.float64)
+    y = _c(sys.y if y is None else y, np.float64)
+    z = _c(sys.z if z is None else z, np.float64)
+    q = _c(sys.q if q is None else q, np.int8)
+    rows = _c(rows, np.int64)
+    offs = _c(sys.sys_offsets, np.int64)
+    sys_of_row = np.searchsorted(offs, rows, side="right").astype(np.int64) - 1
+    B = sys.n_systems
+    if kappa is None:
+        kappa = kappa_from_lambda(sys.lambda_d[:, 0])
+    kappa = _c(np.broadcast_to(kappa, (B,)), np.float64)
+    m = rows.shape[0]
+    out = {k: np.empty(m) for k in ("fx", "fy", "fz", "e_atom", "a_atom")}
+    box = None if sys.box is None else _c(sys.box, np.float64)
+    hits = lib().orc_forces_rows(m, _p(rows), _p(sys_of_row), _p(offs), int(sys.periodic),
+                                 _p(box), sys.rc, _p(x), _p(y), _p(z), _p(q),
+                                 _p(_c(sys.type, np.uint8)), sys.n_types,
+                                 _p(_c(sys.c6, np.float64)), _p(_c(sys.c12, np.float64)),
+                                 _p(kappa), int(sys.screen_lj), _p(out["fx"]), _p(out["fy"]),
+                                 _p(out["fz"]), _p(out["e_atom"]), _p(out["a_atom"]),
+                                 int(n_threads))
+    out["hits"] = int(hits)
+    return out
+
+
+def pairs(sys, x=None, y=None, z=None, max_pairs=None) -> np.ndarray:
+    """The pair set S as an int64 array of shape (|S|, 2), i < j, i-major."""
+    x = _c(sys.x if x is None else x, np.float64)
+    y = _c(sys.y if y is None else y, np.float64)
+    z = _c(sys.z if z is None else z, np.float64)
+    box = None if sys.box is None else _c(sys.box, np.float64)
+    offs = _c(sys.sys_offsets, np.int64)
+    cap = max_pairs if max_pairs is not None else 1 << 16
+    while True:
+        oi = np.empty(cap, dtype=np.int64)
+        oj = np.empty(cap, dtype=np.int64)
+        cnt = lib().orc_pairs(sys.n_systems, _p(offs), int(sys.periodic), _p(box), sys.rc,
+                              _p(x), _p(y), _p(z), _p(oi), _p(oj), cap)
+        if cnt <= cap:
+            return np.stack([oi[:cnt], oj[:cnt]], axis=1)
+        cap = int(cnt)
+
+
+def pair_r2(periodic, box, x, y, z, i, j) -> float:
+    box = None if box is None else _c(box, np.float64)
+    return float(lib().orc_pair_r2(int(periodic), _p(box), _p(_c(x, np.float64)),
+                                   _p(_c(y, np.float64)), _p(_c(z, np.float64)), i, j))
+
+
+# ------------------------------------------------------------------ random numbers / charges
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def ionize(sys, q, step: int, g_step=None) -> int:
+    """Apply ionization step ``step`` (>= 1) to ``q`` in place; returns the jump count."""
+    assert q.dtype == np.int8 and q.flags.c_contiguous
+    if g_step is None:
+        g_step = sys.g[:, step]
+    g_step = _c(g_step, np.float64)
+    return int(lib().orc_ionize(sys.n_systems, _p(_c(sys.sys_offsets, np.int64)),
+                                _p(_c(sys.elem, np.uint8)), _p(_c(sys.atom_id, np.uint32)),
+                                _p(q), _p(_c(sys.qmax, np.int8)), sys.base.shape[1],
+                                _p(_c(sys.base, np.float64)), _p(g_step),
+                                _p(_c(sys.seeds, np.uint64)), int(step)))
+
+
+# ------------------------------------------------------------------ integrator
+
+def vv(phase, dt, inv_mass, f, pos, vel):
+    """In-place velocity-Verlet phase on (pos, vel) tuples of float64 arrays."""
+    fx, fy, fz = (_c(a, np.float64) for a in f)
+    for a in (*pos, *vel):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_vv(pos[0].shape[0], int(phase), float(dt), _p(_c(inv_mass, np.float64)),
+                 _p(fx), _p(fy), _p(fz), _p(pos[0]), _p(pos[1]), _p(pos[2]), _p(vel[0]),
+                 _p(vel[1]), _p(vel[2]))
+
+
+def ekin(sys, vx, vy, vz) -> np.ndarray:
+    out = np.empty(sys.n_systems)
+    lib().orc_ekin(sys.n_systems, _p(_c(sys.sys_offsets, np.int64)),
+                   _p(_c(sys.inv_mass, np.float64)), _p(_c(vx, np.float64)),
+                   _p(_c(vy, np.float64)), _p(_c(vz, np.float64)), _p(out))
+    return out
+
+
+def run(sys, n_steps, record_every=1, ionize_on=True):
+    """Reference trajectory: F0 = F(x0, q0, kappa[0]); then for s = 1..n_steps:
+    v += h F; x += dt v; ionize(s); F = F(x, q, kappa[s]); v += h F.
+    Returns dict with final state and per-recorded-step charges, E_pot, E_kin."""
+    x, y, z = sys.x.copy(), sys.y.copy(), sys.z.copy()
+    vx, vy, vz = sys.vx.copy(), sys.vy.copy(), sys.vz.copy()
+    q = sys.q.copy()
+    kap = kappa_from_lambda(sys.lambda_d)
+    F = forces(sys, q=q, kappa=kap[:, 0], x=x, y=y, z=z)
+    rec = {"q": [q.copy()], "epot": [F["epot"].copy()], "ekin": [ekin(sys, vx, vy, vz)]}
+    for s in range(1, n_steps + 1):
+        vv(0, sys.dt, sys.inv_mass, (F["fx"], F["fy"], F["fz"]), (x, y, z), (vx, vy, vz))
+        if ionize_on:
+            ionize(sys, q, s)
+        F = forces(sys, q=q, kappa=kap[:, s], x=x, y=y, z=z)
+        vv(1, sys.dt, sys.inv_mass, (F["fx"], F["fy"], F["fz"]), (x, y, z), (vx, vy, vz))
+        if s % record_every == 0:
+            rec["q"].append(q.copy())
+            rec["epot"].append(F["epot"].copy())
+            rec["ekin"].append(ekin(sys, vx, vy, vz))
+    return {"x": x, "y": y, "z": z, "vx": vx, "vy": vy, "vz": vz, "q": q, "F": F, **rec}

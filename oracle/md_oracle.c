@@ -1,0 +1,374 @@
+/*
+ * md_oracle.c -- plain FP64 CPU oracle for the screened-force + ionization step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or call
+ * this file: only the tests, the smoke check and the benchmark's CPU-baseline leg
+ * use it.  It shares no code, header, table or constant generator with the GPU
+ * library.
+ *
+ * Build:  gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ * Every floating-point operation is a separately rounded IEEE-754 binary64
+ * operation in the order written (contraction is disabled), so the pair set,
+ * the ionization draws and the integrator updates are bit-reproducible.
+ *
+ * What it computes (arXiv 2401.03180):
+ *  - kappa = 1/lambda_D per force evaluation; Debye length from (T_e, n_e)
+ *    (section II.A, Eq. 3).
+ *  - The pair set S: all pairs inside one system whose minimum-image distance is
+ *    below the cutoff rc (section II.B: cutoff chosen where the screened force is
+ *    negligible; plain truncation).  Brute force over all pairs.
+ *  - Pair potential phi = (k_e q_i q_j / r + c12/r^12 - c6/r^6) exp(-r/lambda_D)
+ *    (section II.A, Eq. 2 screened Coulomb; Eq. 8 screened Lennard-Jones) and the
+ *    force -d(phi)/dr along the pair axis.
+ *  - Stochastic integer charges (section II.A: charges are integers assigned
+ *    stochastically so that ensemble averages follow the CR charge-state
+ *    fractions; section II.B: no partial charges).  Reading used: each step every
+ *    atom below its maximum charge gains +1 with probability
+ *    p = min(1, base[e][q] * g[b][s]), decided by a Philox4x32-10 draw keyed by
+ *    (atom, step, system) and the system seed.
+ *  - The ionization-probability table from CR charge-state fractions for a
+ *    sequential +1 process (reading of section II.A's statement that the
+ *    stochastic charges average to the CR fractions).
+ *  - Velocity-Verlet integration of Newton's equation (section II.B, Eq. 12;
+ *    the paper uses leap-frog, which yields the same positions).
+ *
+ * Philox4x32-10 follows its published definition (Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_KE 138.935457644382   /* 1/(4 pi eps0) in kJ mol^-1 nm e^-2 */
+
+/* ------------------------------------------------------------------------ */
+/* Schedules (section II.A, Eq. 3)                                          */
+/* ------------------------------------------------------------------------ */
+
+/* kappa = 1/lambda_D; an infinite Debye length means no screening. */
+void orc_kappa_from_lambda(int64_t n, const double* lambda_d, double* kappa)
+{
+    for (int64_t k = 0; k < n; ++k)
+        kappa[k] = isinf(lambda_d[k]) ? 0.0 : 1.0 / lambda_d[k];
+}
+
+/* Debye length lambda_D = sqrt(eps0 k_B T_e / (n_e e^2)) with T_e in eV
+ * (k_B T_e = T_e * e joule) and n_e in m^-3; returned in nm. */
+double orc_debye_length_nm(double te_ev, double ne_m3)
+{
+    const double eps0 = 8.8541878128e-12;     /* F/m (CODATA 2018) */
+    const double e = 1.602176634e-19;         /* C (exact) */
+    double kt = te_ev * e;                    /* joule */
+    double lam = sqrt(eps0 * kt / (ne_m3 * e * e));
+    return lam * 1e9;
+}
+
+/* Per-step ionization probabilities for a sequential +1 process from
+ * charge-state fractions P[s][q], s = 0..S, q = 0..Z:
+ *   flux out of charge q during step s  J_q(s) = sum_{q'>q} (P_q'(s) - P_q'(s-1)),
+ *   p_q(s) = J_q(s) / P_q(s-1)  (0 where P_q(s-1) == 0), clamped to [0, 1].
+ * Output p[s][q] for s = 1..S (row 0 is set to 0). */
+void orc_rates_from_fractions(int64_t S, int32_t Z, const double* P, double* p)
+{
+    int32_t nq = Z + 1;
+    for (int32_t q = 0; q < nq; ++q) p[q] = 0.0;
+    for (int64_t s = 1; s <= S; ++s) {
+        const double* prev = P + (s - 1) * nq;
+        const double* cur = P + s * nq;
+        double* out = p + s * nq;
+        for (int32_t q = 0; q < nq; ++q) {
+            double flux = 0.0;
+            for (int32_t qq = q + 1; qq < nq; ++qq) flux += cur[qq] - prev[qq];
+            double v = prev[q] > 0.0 ? flux / prev[q] : 0.0;
+            if (v < 0.0) v = 0.0;
+            if (v > 1.0) v = 1.0;
+            out[q] = (q == Z) ? 0.0 : v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair predicate and pair force (section II.A Eq. 2 and Eq. 8, II.B cutoff) */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t periodic;
+    double L[3], invL[3];
+    double rc2;
+} orc_geom;
+
+static void geom_init(orc_geom* g, int periodic, const double* box, double rc)
+{
+    g->periodic = periodic;
+    for (int k = 0; k < 3; ++k) {
+        g->L[k] = periodic ? box[k] : 0.0;
+        g->invL[k] = periodic ? 1.0 / box[k] : 0.0;
+    }
+    g->rc2 = rc * rc;
+}
+
+/* Minimum-image separation d = x_i - x_j and r2 = (dx*dx + dy*dy) + dz*dz. */
+static inline double pair_r2(const orc_geom* g, const double* x, const double* y,
+                             const double* z, int64_t i, int64_t j, double d[3])
+{
+    d[0] = x[i] - x[j];
+    d[1] = y[i] - y[j];
+    d[2] = z[i] - z[j];
+    if (g->periodic) {
+        for (int k = 0; k < 3; ++k) d[k] = d[k] - g->L[k] * rint(d[k] * g->invL[k]);
+    }
+    double r2 = d[0] * d[0] + d[1] * d[1];
+    r2 = r2 + d[2] * d[2];
+    return r2;
+}
+
+/* Screened pair energy phi and scalar force f (F_i = f * d, F_j = -f * d). */
+static inline void pair_phi_f(double r2, double qiqj_ke, double c6, double c12,
+                              double kappa, int screen_lj, double* phi, double* f)
+{
+    double r = sqrt(r2);
+    double rinv2 = 1.0 / r2;
+    double rinv6 = rinv2 * rinv2 * rinv2;
+    double s = exp(-kappa * r);
+    double uc = qiqj_ke / r;
+    double lj12 = c12 * rinv6 * rinv6;
+    double lj6 = c6 * rinv6;
+    double ulj = lj12 - lj6;
+    double wlj = 12.0 * lj12 - 6.0 * lj6;           /* -r d(uLJ)/dr */
+    if (screen_lj) {
+        *phi = (uc + ulj) * s;
+        *f = ((uc + wlj) + (uc + ulj) * (kappa * r)) * s * rinv2;
+    } else {
+        *phi = uc * s + ulj;
+        *f = (uc + uc * (kappa * r)) * s * rinv2 + wlj * rinv2;
+    }
+}
+
+/* Brute-force forces and energies over all i<j pairs of every system.
+ *   kappa[b]  screening constant of system b for this force evaluation.
+ *   e_atom[i] = 1/2 sum_j phi_ij ;  a_atom[i] = sum_j |f_ij| r_ij ;
+ *   epot[b]   = sum over pairs of system b.
+ * Any of e_atom, a_atom, epot may be NULL.  Returns |S|. */
+int64_t orc_forces(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
+                   const double* box, double rc, const double* x, const double* y,
+                   const double* z, const int8_t* q, const uint8_t* type, int32_t n_types,
+                   const double* c6, const double* c12, const double* kappa,
+                   int32_t screen_lj, double* fx, double* fy, double* fz,
+                   double* e_atom, double* a_atom, double* epot)
+{
+    int64_t npairs = 0;
+    int64_t n = sys_off[n_sys];
+    for (int64_t i = 0; i < n; ++i) {
+        fx[i] = fy[i] = fz[i] = 0.0;
+        if (e_atom) e_atom[i] = 0.0;
+        if (a_atom) a_atom[i] = 0.0;
+    }
+    for (int64_t b = 0; b < n_sys; ++b) {
+        orc_geom g;
+        geom_init(&g, periodic, periodic ? box + 3 * b : NULL, rc);
+        double esum = 0.0;
+        for (int64_t i = sys_off[b]; i < sys_off[b + 1]; ++i) {
+            for (int64_t j = i + 1; j < sys_off[b + 1]; ++j) {
+                double d[3];
+                double r2 = pair_r2(&g, x, y, z, i, j, d);
+                if (!(r2 < g.rc2)) continue;
+                if (r2 <= 0.0) abort();   /* coincident atoms: undefined */
+                int tt = type[i] * n_types + type[j];
+                double qq = ORC_KE * ((double)q[i] * (double)q[j]);
+                double phi, f;
+                pair_phi_f(r2, qq, c6[tt], c12[tt], kappa[b], screen_lj, &phi, &f);
+                fx[i] += f * d[0]; fy[i] += f * d[1]; fz[i] += f * d[2];
+                fx[j] -= f * d[0]; fy[j] -= f * d[1]; fz[j] -= f * d[2];
+                if (e_atom) { e_atom[i] += 0.5 * phi; e_atom[j] += 0.5 * phi; }
+                if (a_atom) {
+                    double mag = fabs(f) * sqrt(r2);
+                    a_atom[i] += mag; a_atom[j] += mag;
+                }
+                esum += phi;
+                ++npairs;
+            }
+        }
+        if (epot) epot[b] = esum;
+    }
+    return npairs;
+}
+
+/* Rows mode: for the listed atoms i, F_i, e_i and A_i against every j of the same
+ * system (full j loop, so rows are independent; OpenMP over rows).
+ * sys_of_row[r] is the system of row r.  Used for sub-box checks of large
+ * systems and for the CPU timing baseline.  Returns the number of (i, j) hits. */
+int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_of_row,
+                        const int64_t* sys_off, int32_t periodic, const double* box, double rc,
+                        const double* x, const double* y, const double* z, const int8_t* q,
+                        const uint8_t* type, int32_t n_types, const double* c6,
+                        const double* c12, const double* kappa, int32_t screen_lj,
+                        double* fx, double* fy, double* fz, double* e_atom, double* a_atom,
+                        int32_t n_threads)
+{
+    int64_t hits = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : hits)
+#endif
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t i = rows[r];
+        int64_t b = sys_of_row[r];
+        orc_geom g;
+        geom_init(&g, periodic, periodic ? box + 3 * b : NULL, rc);
+        double F[3] = {0.0, 0.0, 0.0}, e = 0.0, a = 0.0;
+        for (int64_t j = sys_off[b]; j < sys_off[b + 1]; ++j) {
+            if (j == i) continue;
+            double d[3];
+            double r2 = pair_r2(&g, x, y, z, i, j, d);
+            if (!(r2 < g.rc2)) continue;
+            int tt = type[i] * n_types + type[j];
+            double qq = ORC_KE * ((double)q[i] * (double)q[j]);
+            double phi, f;
+            pair_phi_f(r2, qq, c6[tt], c12[tt], kappa[b], screen_lj, &phi, &f);
+            F[0] += f * d[0]; F[1] += f * d[1]; F[2] += f * d[2];
+            e += 0.5 * phi;
+            a += fabs(f) * sqrt(r2);
+            ++hits;
+        }
+        fx[r] = F[0]; fy[r] = F[1]; fz[r] = F[2];
+        if (e_atom) e_atom[r] = e;
+        if (a_atom) a_atom[r] = a;
+    }
+    return hits;
+}
+
+/* The pair set S as (i, j) with i < j (global caller indices), in i-major order.
+ * Writes at most max pairs; returns |S|. */
+int64_t orc_pairs(int64_t n_sys, const int64_t* sys_off, int32_t periodic, const double* box,
+                  double rc, const double* x, const double* y, const double* z,
+                  int64_t* out_i, int64_t* out_j, int64_t max)
+{
+    int64_t cnt = 0;
+    for (int64_t b = 0; b < n_sys; ++b) {
+        orc_geom g;
+        geom_init(&g, periodic, periodic ? box + 3 * b : NULL, rc);
+        for (int64_t i = sys_off[b]; i < sys_off[b + 1]; ++i)
+            for (int64_t j = i + 1; j < sys_off[b + 1]; ++j) {
+                double d[3];
+                double r2 = pair_r2(&g, x, y, z, i, j, d);
+                if (r2 < g.rc2) {
+                    if (cnt < max) { out_i[cnt] = i; out_j[cnt] = j; }
+                    ++cnt;
+                }
+            }
+    }
+    return cnt;
+}
+
+/* Squared minimum-image distance of one pair (for adversarial predicate tests). */
+double orc_pair_r2(int32_t periodic, const double* box, const double* x, const double* y,
+                   const double* z, int64_t i, int64_t j)
+{
+    orc_geom g;
+    geom_init(&g, periodic, box, 0.0);
+    double d[3];
+    return pair_r2(&g, x, y, z, i, j, d);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11)                                     */
+/* ------------------------------------------------------------------------ */
+
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ionization update                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* One ionization step s >= 1 for every atom.  g_step[b] = g[b][s].  An atom of
+ * element e with charge q < qmax[e] gains +1 iff u < floor(p * 2^32), where
+ * p = min(1, base[e*Q + q] * g_step[b]) and u is word 0 of
+ * Philox4x32-10(counter = (atom_id, s, b, 0), key = (seed_b low, seed_b high)).
+ * Returns the number of atoms that were ionized. */
+int64_t orc_ionize(int64_t n_sys, const int64_t* sys_off, const uint8_t* elem,
+                   const uint32_t* atom_id, int8_t* q, const int8_t* qmax, int32_t Q,
+                   const double* base, const double* g_step, const uint64_t* seeds,
+                   int64_t step)
+{
+    int64_t jumps = 0;
+    for (int64_t b = 0; b < n_sys; ++b) {
+        uint32_t key[2] = {(uint32_t)(seeds[b] & 0xFFFFFFFFu), (uint32_t)(seeds[b] >> 32)};
+        for (int64_t a = sys_off[b]; a < sys_off[b + 1]; ++a) {
+            int e = elem[a];
+            int qa = q[a];
+            if (qa >= qmax[e]) continue;
+            double p = base[e * Q + qa] * g_step[b];
+            if (p > 1.0) p = 1.0;
+            uint64_t thresh = (uint64_t)floor(p * 4294967296.0);
+            uint32_t ctr[4] = {atom_id[a], (uint32_t)step, (uint32_t)b, 0u};
+            uint32_t r[4];
+            orc_philox4x32_10(ctr, key, r);
+            if ((uint64_t)r[0] < thresh) {
+                q[a] = (int8_t)(qa + 1);
+                ++jumps;
+            }
+        }
+    }
+    return jumps;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Velocity Verlet (section II.B, Eq. 12)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* phase 0: v += h F ; x += dt v.   phase 1: v += h F.   h = (0.5 dt) / m. */
+void orc_vv(int64_t n, int32_t phase, double dt, const double* inv_mass, const double* fx,
+            const double* fy, const double* fz, double* x, double* y, double* z, double* vx,
+            double* vy, double* vz)
+{
+    double hdt = 0.5 * dt;
+    for (int64_t a = 0; a < n; ++a) {
+        double h = hdt * inv_mass[a];
+        vx[a] = vx[a] + h * fx[a];
+        vy[a] = vy[a] + h * fy[a];
+        vz[a] = vz[a] + h * fz[a];
+        if (phase == 0) {
+            x[a] = x[a] + dt * vx[a];
+            y[a] = y[a] + dt * vy[a];
+            z[a] = z[a] + dt * vz[a];
+        }
+    }
+}
+
+/* Kinetic energy per system: 1/2 sum m v^2. */
+void orc_ekin(int64_t n_sys, const int64_t* sys_off, const double* inv_mass, const double* vx,
+              const double* vy, const double* vz, double* ekin)
+{
+    for (int64_t b = 0; b < n_sys; ++b) {
+        double s = 0.0;
+        for (int64_t a = sys_off[b]; a < sys_off[b + 1]; ++a) {
+            double v2 = vx[a] * vx[a] + vy[a] * vy[a];
+            v2 = v2 + vz[a] * vz[a];
+            s += 0.5 * v2 / inv_mass[a];
+        }
+        ekin[b] = s;
+    }
+}

@@ -1,0 +1,54 @@
+"""The seeded generators hit the stated atom counts, densities and element mixes."""
+import numpy as np
+import pytest
+
+from paper_2401_03180_amd import synth
+
+
+def test_water_small():
+    s = synth.water_small()
+    assert s.n_atoms == 1536 and s.periodic
+    assert s.mass_density_g_cm3() == pytest.approx(1.0, abs=0.01)
+    assert np.all(np.bincount(s.elem) == [512, 1024])
+    assert s.rc < 0.5 * s.box.min()
+    # rigid geometry: O-H 0.1 nm
+    P = s.positions()
+    assert np.allclose(np.linalg.norm(P[1::3] - P[0::3], axis=1), 0.1, atol=1e-12)
+    # zero net momentum
+    m = 1 / s.inv_mass
+    assert abs((m * s.vx).sum()) < 1e-9
+
+
+def test_water_pulse_schedule():
+    s = synth.water_pulse()
+    assert s.n_atoms == 98304
+    assert s.mass_density_g_cm3() == pytest.approx(1.0, abs=0.01)
+    assert s.lambda_d[0, 0] == 1.0 and s.lambda_d[0, 1000] == pytest.approx(0.15)
+    assert s.g[0].argmax() == 500 and s.g[0].max() == pytest.approx(1.0)
+    assert s.base.max() == 5e-3
+
+
+def test_protein_mix():
+    s = synth.protein_crystal()
+    assert s.n_atoms == 524288
+    assert np.all(np.bincount(s.elem) == synth.PROTEIN_COUNTS)
+    assert s.mass_density_g_cm3() == pytest.approx(1.29, abs=0.01)
+    assert list(s.qmax) == [1, 6, 7, 8, 16]
+
+
+def test_methane_clusters():
+    s = synth.methane_clusters()
+    n = np.diff(s.sys_offsets)
+    assert s.n_systems == 256 and not s.periodic
+    assert n.min() >= 1000 and n.max() <= 20000 and np.all(n % 5 == 0)
+    assert 1.3e6 < s.n_atoms < 2.0e6
+    assert len(set(s.seeds.tolist())) == 256
+    # per-system atom ids restart at zero
+    assert s.atom_id[s.sys_offsets[1]] == 0
+
+
+def test_water_large_counts():
+    s = synth.water_large(n_per_dim=16, L=34.8 / 7)
+    assert s.n_atoms % 3 == 1
+    full = synth.water_large()
+    assert full.n_atoms == 4194304
