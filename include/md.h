@@ -1,0 +1,267 @@
+/*
+ * md.h -- C ABI of the MI355X screened-force + ionization step library (libmd_hip.so).
+ *
+ * The library advances atoms that interact through spherically symmetric two-body
+ * potentials: a Debye-screened Coulomb term between integer-charged ions and a
+ * Lennard-Jones term modulated by the same screening factor, both truncated at a
+ * cutoff (arXiv 2401.03180, section II.A Eq. 2 and Eq. 8; section II.B on the
+ * screening-reduced cutoff).  Every step the integer charges change stochastically
+ * (section II.A: charges are assigned stochastically so that ensemble averages
+ * follow the collisional-radiative charge-state fractions; section II.B: no partial
+ * charges), and Newton's equation is integrated (section II.B, Eq. 12).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Units: nm, ps, amu, kJ/mol, elementary charge.  Forces in kJ mol^-1 nm^-1.
+ *  Atoms of B independent systems are concatenated; system b owns atoms
+ *  [sys_offsets[b], sys_offsets[b+1]).  Per-atom arrays are structure-of-arrays
+ *  in the caller's atom order, contiguous, in device memory (hipMalloc'd or torch
+ *  CUDA tensors) unless a parameter says "host".  The caller owns every per-atom
+ *  array; the library owns only its context workspace, allocated by
+ *  md_bind_tables (no device allocation happens in the per-step calls; only
+ *  md_debug_pairs allocates), so the asynchronous calls can be captured in a HIP
+ *  graph.
+ *  `stream` is a hipStream_t (0 = the null stream).  Asynchronous calls enqueue
+ *  work on `stream` and return after argument validation; errors found on the
+ *  device are latched in a device error word (MD_FLAG_*) and reported by
+ *  md_sync_check.  No call aborts or throws; every failure is a status code with a
+ *  message available from md_last_error.  One context serves one stream at a time
+ *  and is not thread-safe.
+ *
+ *  Step counter: the context keeps a device step counter k = index of the latest
+ *  force evaluation.  k = 0 selects kappa[.][0] for the initial forces; phase 0 of
+ *  md_integrate_vv advances it to s = k + 1; md_ionize_step and the following
+ *  md_screened_forces use s; phase 1 leaves it unchanged.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_ctx md_ctx;           /* opaque, library-owned */
+typedef void* md_stream;                /* a hipStream_t */
+
+typedef enum md_status {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,        /* null pointer, size or enum out of range */
+    MD_ERR_HIP = -2,        /* a HIP runtime call failed */
+    MD_ERR_CAPACITY = -3,   /* more atoms/types/elements than the context was sized for */
+    MD_ERR_GEOMETRY = -4,   /* periodic box too small for the cutoff (need L >= 2 (rc + skin)) */
+    MD_ERR_DEVICE = -5,     /* the device error word is non-zero (see MD_FLAG_*) */
+    MD_ERR_STATE = -6       /* call out of order (e.g. forces before tables or cells) */
+} md_status;
+
+typedef enum md_precision {
+    MD_FP64 = 0,            /* plain FP64 pair arithmetic and accumulation */
+    MD_FP32_KAHAN = 1       /* FP32 pair arithmetic, FP32 + compensated per-atom sums */
+} md_precision;
+
+/* Device error word bits (latched until md_clear_flags). */
+#define MD_FLAG_CELL_OVERFLOW 0x1u   /* grid/cluster capacity exceeded during a build */
+#define MD_FLAG_LIST_OVERFLOW 0x2u   /* neighbour-list capacity exceeded: pairs may be missing */
+#define MD_FLAG_SKIN 0x4u            /* forces were evaluated (or MD_BUILD_CHECK ran) while some
+                                        atom had moved more than skin/2 since the last build */
+#define MD_FLAG_NONFINITE 0x8u       /* non-finite position seen by a build */
+#define MD_FLAG_STEP 0x10u           /* step counter outside the bound schedule tables */
+#define MD_FLAG_BAD_INPUT 0x20u      /* a type, element or charge outside its table (the entry
+                                        was clamped or skipped) */
+
+#define MD_MAX_TYPES 8
+#define MD_MAX_ELEMENTS 8
+#define MD_MAX_CHARGE_STATES 128
+
+typedef struct md_config {
+    int32_t n_systems;          /* B >= 1 */
+    int32_t n_types;            /* Lennard-Jones types, 1..MD_MAX_TYPES */
+    int32_t n_elements;         /* ionizable elements, 1..MD_MAX_ELEMENTS */
+    int32_t n_charge_states;    /* Q: row length of the base[] table, 1..MD_MAX_CHARGE_STATES */
+    int32_t periodic;           /* 1: rectangular periodic box per system; 0: vacuum */
+    int32_t screen_lj;          /* 1: LJ multiplied by exp(-r/lambda_D) (Eq. 8); 0: plain LJ */
+    double rc;                  /* cutoff, nm (pairs with r^2 < rc^2 interact) */
+    double skin;                /* Verlet buffer, nm (> 0) */
+    int64_t capacity_atoms;     /* >= sys_offsets[B]; every workspace is sized from it */
+    int32_t cluster_group;      /* i-clusters per force work-group: 1, 2, 4 or 8 (0 = 4) */
+    int32_t max_neighbors;      /* per-atom neighbour-list capacity (0 = derived) */
+    double density_hint;        /* upper bound on atoms per nm^3 used for sizing (0 = 130) */
+} md_config;
+
+/* Build modes of md_build_cells. */
+#define MD_BUILD_AUTO 0         /* rebuild on the first call and then on every nstlist-th call
+                                   (md_set_nstlist, default 10); between rebuilds every force
+                                   call latches MD_FLAG_SKIN if some atom has moved more than
+                                   skin/2 since the last build (its lists may miss pairs) */
+#define MD_BUILD_FORCE 1        /* rebuild now */
+#define MD_BUILD_CHECK 2        /* never rebuild; latch MD_FLAG_SKIN if a rebuild was due */
+
+/* Create a context for B systems.  sys_offsets: host int64[B+1], non-decreasing,
+ * sys_offsets[0] = 0, sys_offsets[B] <= capacity_atoms.  Validates the
+ * configuration and binds the context to the current HIP device; the device
+ * workspace is allocated by md_bind_tables.  On failure *out is NULL. */
+md_status md_create(const md_config* cfg, const int64_t* sys_offsets, md_ctx** out);
+
+/* Release the context and its device workspace (synchronizes the device). */
+md_status md_destroy(md_ctx* ctx);
+
+/* Message describing the last non-MD_OK status returned for ctx (never NULL;
+ * ctx may be NULL for errors of md_create). */
+const char* md_last_error(const md_ctx* ctx);
+
+/* Copy the per-run tables (all HOST arrays, FP64 unless stated) into the context
+ * and size / allocate its device workspace (a second call re-allocates):
+ *   box       [B*3]  periodic box lengths per system (NULL when vacuum);
+ *   c6, c12   [T*T]  Lennard-Jones coefficients, symmetric (c6 = 4 eps sigma^6,
+ *                    c12 = 4 eps sigma^12);
+ *   qmax      int8 [E]  highest charge reachable per element;
+ *   lambda_d  [B*(S+1)] Debye length per system and force evaluation k = 0..S
+ *                    (section II.A, Eq. 3); +inf means unscreened.  The library stores
+ *                    kappa = 1/lambda_d;
+ *   base      [E*Q]  per-(element, charge) per-step ionization probability scale;
+ *   g         [B*(S+1)] per-system pulse envelope for ionization steps s = 1..S
+ *                    (entry 0 unused);
+ *   seeds     uint64 [B] per-system random seeds;
+ *   n_steps   S >= 0.
+ * Synchronous.  Resets the step counter to 0 and the error word to 0.  Fails with
+ * MD_ERR_GEOMETRY when a periodic box edge is below 2 (rc + skin). */
+md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const double* c12,
+                         const int8_t* qmax, const double* lambda_d, const double* base,
+                         const double* g, const uint64_t* seeds, int64_t n_steps);
+
+/* Set the device step counter (asynchronous, graph-capturable). */
+md_status md_set_step(md_ctx* ctx, int64_t step, md_stream stream);
+
+/* Read the device step counter (synchronizes `stream`). */
+md_status md_get_step(md_ctx* ctx, int64_t* step, md_stream stream);
+
+/* Neighbour search (section II.B: the screening-reduced cutoff bounds the pairs
+ * that are evaluated).  x, y, z: device FP64 [N] current positions (never
+ * wrapped by the library); type: uint8 [N] Lennard-Jones types (the same array
+ * must be passed to md_screened_forces).  Builds the grid binning, the 8-atom
+ * clusters, the cluster-group candidate tables and the per-atom neighbour codes
+ * covering every pair within rc + skin, and records the build positions for the
+ * displacement test (the largest displacement is tracked by phase 0 of
+ * md_integrate_vv).  `mode` is one of MD_BUILD_*.  Asynchronous. */
+md_status md_build_cells(md_ctx* ctx, const double* x, const double* y, const double* z,
+                         const uint8_t* type, int32_t mode, md_stream stream);
+
+/* Number of md_build_cells(MD_BUILD_AUTO) calls between rebuilds (>= 1). */
+md_status md_set_nstlist(md_ctx* ctx, int32_t nstlist);
+
+/* Stochastic integer ionization for the current step s (>= 1, the device step
+ * counter): every atom a of system b with element e = elem[a] and charge
+ * q[a] < qmax[e] gains +1 iff  u < floor(min(1, base[e][q] * g[b][s]) * 2^32),
+ * where u is word 0 of Philox4x32-10 with counter (atom_id[a], s, b, 0) and key
+ * (low, high 32 bits of seeds[b]).  elem: uint8 [N]; atom_id: uint32 [N] (the
+ * atom's index inside its system); q: int8 [N], updated in place. */
+md_status md_ionize_step(md_ctx* ctx, const uint8_t* elem, const uint32_t* atom_id, int8_t* q,
+                         md_stream stream);
+
+/* Screened pair forces (section II.A Eq. 2 + Eq. 8).  For every pair (i, j) of one
+ * system whose minimum-image separation d = x_i - x_j has
+ * r^2 = (dx*dx + dy*dy) + dz*dz < rc*rc (FP64, exactly as written), with
+ * s = exp(-kappa r), kappa = 1/lambda_d[b][k] at the current step k:
+ *   phi = (k_e q_i q_j / r + c12/r^12 - c6/r^6) s,   F_i = -F_j = f d,
+ *   f = ((k_e q_i q_j / r + 12 c12/r^12 - 6 c6/r^6) + (phi/s) kappa r) s / r^2.
+ * x, y, z: FP64 [N]; q: int8 [N]; type: uint8 [N] (< n_types).  fx, fy, fz: FP64 [N]
+ * outputs, overwritten in caller order.  epot: device FP64 [B] (sum of phi per
+ * system) or NULL.  Requires a prior md_build_cells on positions within skin/2.
+ * MD_FP32_KAHAN decides membership with an error-bounded FP32 test and re-decides
+ * every pair inside the error band with the FP64 expression above, so the set of
+ * interacting pairs is identical for both precisions. */
+md_status md_screened_forces(md_ctx* ctx, md_precision prec, const double* x, const double* y,
+                             const double* z, const int8_t* q, const uint8_t* type, double* fx,
+                             double* fy, double* fz, double* epot, md_stream stream);
+
+/* Velocity-Verlet half steps (section II.B, Eq. 12), FP64, element-wise with no
+ * contraction, h = (0.5 dt) * inv_mass[a]:
+ *   phase 0: v += h F; x += dt v; then advance the step counter; also tracks the
+ *            largest displacement since the last build;
+ *   phase 1: v += h F; if ekin != NULL, ekin[b] = sum 1/2 m v^2 per system.
+ * inv_mass, fx, fy, fz: FP64 [N]; x..vz: FP64 [N] in/out; ekin: device FP64 [B]. */
+md_status md_integrate_vv(md_ctx* ctx, int32_t phase, double dt, const double* inv_mass,
+                          const double* fx, const double* fy, const double* fz, double* x,
+                          double* y, double* z, double* vx, double* vy, double* vz,
+                          double* ekin, md_stream stream);
+
+/* Synchronize `stream`; return MD_ERR_DEVICE if the error word is non-zero.
+ * flags (host, may be NULL) receives the word. */
+md_status md_sync_check(md_ctx* ctx, md_stream stream, uint32_t* flags);
+
+/* Clear the device error word (asynchronous). */
+md_status md_clear_flags(md_ctx* ctx, md_stream stream);
+
+/* Debug export of the interacting pair set exactly as md_screened_forces decides
+ * it for `prec` at positions x, y, z with charges q (runs the same force kernel):
+ * writes up to max pairs (i, j), i < j, as caller indices into ij (HOST int32
+ * [2*max], unordered) and their count into *n_pairs.  Synchronous; allocates
+ * temporary device buffers. */
+md_status md_debug_pairs(md_ctx* ctx, md_precision prec, const double* x, const double* y,
+                         const double* z, const int8_t* q, int64_t* n_pairs, int32_t* ij,
+                         int64_t max, md_stream stream);
+
+/* Every array a full step touches (all device pointers, caller order). */
+typedef struct md_step_args {
+    md_precision prec;
+    double dt;
+    double *x, *y, *z, *vx, *vy, *vz;
+    double *fx, *fy, *fz;           /* forces of the current positions (in/out) */
+    const double* inv_mass;
+    const uint8_t* elem;
+    const uint8_t* type;
+    const uint32_t* atom_id;
+    int8_t* q;
+    double* epot;                   /* device FP64 [B] or NULL */
+    double* ekin;                   /* device FP64 [B] or NULL */
+} md_step_args;
+
+/* One full step in the order of the method: md_integrate_vv phase 0 (kick + drift,
+ * step counter s = k + 1), md_ionize_step (step s), md_build_cells(build_mode),
+ * md_screened_forces (kappa of step s), md_integrate_vv phase 1 (kick).  The forces
+ * in fx, fy, fz must be those of the current positions on entry (call
+ * md_screened_forces once before the first step).  Asynchronous. */
+md_status md_step(md_ctx* ctx, const md_step_args* args, int32_t build_mode, md_stream stream);
+
+/* HIP-graph form of md_step: records one step (with a rebuild when with_rebuild is
+ * 1, with MD_BUILD_CHECK otherwise) on `stream` (not the null stream) into an
+ * executable graph.  Replaying it runs the step with no host work; the step
+ * counter, schedules and random streams advance on the device.  The pointers in
+ * args are baked into the graph. */
+typedef struct md_graph md_graph;
+md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t with_rebuild,
+                          md_stream stream, md_graph** out);
+md_status md_graph_launch(md_graph* graph, md_stream stream);
+md_status md_graph_destroy(md_graph* graph);
+
+typedef struct md_stats {
+    int64_t n_atoms, n_clusters, n_groups, n_entries;   /* from the last build */
+    int64_t n_list_codes;                               /* sum of per-atom list lengths */
+    int64_t max_list_len, list_capacity;                /* per atom */
+    int64_t max_group_entries, group_entry_capacity;
+    int64_t n_builds;                                   /* builds executed on the device */
+    int32_t cluster_group;
+    uint32_t flags;
+} md_stats;
+
+/* Synchronize `stream` and report build statistics. */
+md_status md_get_stats(md_ctx* ctx, md_stats* out, md_stream stream);
+
+/* Host helpers for the per-step schedules (FP64, no device work). */
+
+/* Debye length (section II.A, Eq. 3) in nm for electron temperature te_ev (eV) and
+ * free-electron density ne_m3 (m^-3). */
+double md_debye_length_nm(double te_ev, double ne_m3);
+
+/* Per-step ionization probabilities of a sequential +1 process from charge-state
+ * fractions (reading of section II.A: the stochastic integer charges average to
+ * the CR fractions).  P: host [(S+1)*(Z+1)] fractions per step s and charge q;
+ * p: host [(S+1)*(Z+1)] output, p[s][q] = (sum_{q'>q} P[s][q'] - P[s-1][q']) /
+ * P[s-1][q] clamped to [0, 1] (0 where P[s-1][q] == 0, for q == Z and for s == 0). */
+md_status md_rates_from_fractions(int64_t S, int32_t Z, const double* P, double* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MD_H */

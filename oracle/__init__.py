@@ -53,7 +53,7 @@ def lib():
                                      P, P, P, P, P, P]
             L.orc_forces.restype = i64
             L.orc_forces_rows.argtypes = [i64, P, P, P, i32, P, f64, P, P, P, P, P, i32, P, P,
-                                          P, i32, P, P, P, P, P, i32]
+                                          P, i32, P, P, P, P, P, P, i32]
             L.orc_forces_rows.restype = i64
             L.orc_pairs.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i64]
             L.orc_pairs.restype = i64
@@ -143,6 +143,7 @@ def forces_rows(sys, rows, q=None, kappa=None, x=None, y=None, z=None, n_threads
     kappa = _c(np.broadcast_to(kappa, (B,)), np.float64)
     m = rows.shape[0]
     out = {k: np.empty(m) for k in ("fx", "fy", "fz", "e_atom", "a_atom")}
+    out["row_hits"] = np.empty(m, dtype=np.int64)
     box = None if sys.box is None else _c(sys.box, np.float64)
     hits = lib().orc_forces_rows(m, _p(rows), _p(sys_of_row), _p(offs), int(sys.periodic),
                                  _p(box), sys.rc, _p(x), _p(y), _p(z), _p(q),
@@ -150,7 +151,7 @@ def forces_rows(sys, rows, q=None, kappa=None, x=None, y=None, z=None, n_threads
                                  _p(_c(sys.c6, np.float64)), _p(_c(sys.c12, np.float64)),
                                  _p(kappa), int(sys.screen_lj), _p(out["fx"]), _p(out["fy"]),
                                  _p(out["fz"]), _p(out["e_atom"]), _p(out["a_atom"]),
-                                 int(n_threads))
+                                 _p(out["row_hits"]), int(n_threads))
     out["hits"] = int(hits)
     return out
 

@@ -200,14 +200,15 @@ int64_t orc_forces(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
 /* Rows mode: for the listed atoms i, F_i, e_i and A_i against every j of the same
  * system (full j loop, so rows are independent; OpenMP over rows).
  * sys_of_row[r] is the system of row r.  Used for sub-box checks of large
- * systems and for the CPU timing baseline.  Returns the number of (i, j) hits. */
+ * systems and for the CPU timing baseline.  row_hits[r] (may be NULL) receives the
+ * number of partners of row r.  Returns the number of (i, j) hits. */
 int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_of_row,
                         const int64_t* sys_off, int32_t periodic, const double* box, double rc,
                         const double* x, const double* y, const double* z, const int8_t* q,
                         const uint8_t* type, int32_t n_types, const double* c6,
                         const double* c12, const double* kappa, int32_t screen_lj,
                         double* fx, double* fy, double* fz, double* e_atom, double* a_atom,
-                        int32_t n_threads)
+                        int64_t* row_hits, int32_t n_threads)
 {
     int64_t hits = 0;
 #ifdef _OPENMP
@@ -220,6 +221,7 @@ int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_
         orc_geom g;
         geom_init(&g, periodic, periodic ? box + 3 * b : NULL, rc);
         double F[3] = {0.0, 0.0, 0.0}, e = 0.0, a = 0.0;
+        int64_t h = 0;
         for (int64_t j = sys_off[b]; j < sys_off[b + 1]; ++j) {
             if (j == i) continue;
             double d[3];
@@ -232,8 +234,10 @@ int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_
             F[0] += f * d[0]; F[1] += f * d[1]; F[2] += f * d[2];
             e += 0.5 * phi;
             a += fabs(f) * sqrt(r2);
-            ++hits;
+            ++h;
         }
+        hits += h;
+        if (row_hits) row_hits[r] = h;
         fx[r] = F[0]; fy[r] = F[1]; fz[r] = F[2];
         if (e_atom) e_atom[r] = e;
         if (a_atom) a_atom[r] = a;

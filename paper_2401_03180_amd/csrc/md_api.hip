@@ -1,0 +1,654 @@
+// md_api.hip -- host side of the C ABI declared in include/md.h: argument
+// validation, workspace sizing and allocation, table upload and launch order.
+#include <math.h>
+#include <string.h>
+#include <stdarg.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <new>
+
+#include "md_internal.h"
+#include "md_launch.h"
+
+using namespace md;
+
+struct md_ctx {
+    Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+md_status fail(Ctx* c, md_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf; else g_create_err = buf;
+    return s;
+}
+
+#define HIP_TRY(c, expr)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((c), MD_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, int64_t count)
+{
+    if (count <= 0) count = 1;
+    return hipMalloc((void**)p, sizeof(T) * (size_t)count);
+}
+
+void free_all(Ctx* c)
+{
+    void* ptrs[] = {c->dsc, c->d_sys_off, c->d_sys_of_atom, c->d_grid, c->d_sys_lo, c->d_sys_hi,
+                    c->d_sys_grp0, c->d_c6, c->d_c12, c->d_lj32, c->d_qmax, c->d_kappa,
+                    c->d_base, c->d_g, c->d_seeds, c->d_key, c->d_rank, c->d_img,
+                    c->d_bin_cnt, c->d_bin_start, c->d_sorted, c->d_scan_tmp, c->d_col_ncl,
+                    c->d_col_ngrp, c->d_col_cl0, c->d_col_grp0, c->d_cl_lo, c->d_cl_hi,
+                    c->d_cl_nt, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_qs,
+                    c->d_ts, c->d_groups, c->d_ent, c->d_nb, c->d_grp_epot, c->d_xref,
+                    c->d_partial};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+bool null_any(std::initializer_list<const void*> ps)
+{
+    for (const void* p : ps)
+        if (!p) return true;
+    return false;
+}
+
+hipStream_t S(md_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char* md_last_error(const md_ctx* ctx)
+{
+    return ctx ? ctx->c.err.c_str() : g_create_err.c_str();
+}
+
+md_status md_create(const md_config* cfg, const int64_t* sys_offsets, md_ctx** out)
+{
+    if (!out) return fail(nullptr, MD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg || !sys_offsets) return fail(nullptr, MD_ERR_ARG, "cfg or sys_offsets is NULL");
+    if (cfg->n_systems < 1) return fail(nullptr, MD_ERR_ARG, "n_systems must be >= 1");
+    if (cfg->n_types < 1 || cfg->n_types > MD_MAX_TYPES)
+        return fail(nullptr, MD_ERR_CAPACITY, "n_types must be in [1, %d]", MD_MAX_TYPES);
+    if (cfg->n_elements < 1 || cfg->n_elements > MD_MAX_ELEMENTS)
+        return fail(nullptr, MD_ERR_CAPACITY, "n_elements must be in [1, %d]", MD_MAX_ELEMENTS);
+    if (cfg->n_charge_states < 1 || cfg->n_charge_states > MD_MAX_CHARGE_STATES)
+        return fail(nullptr, MD_ERR_CAPACITY, "n_charge_states must be in [1, %d]",
+                    MD_MAX_CHARGE_STATES);
+    if (!(cfg->rc > 0.0) || !(cfg->skin > 0.0) || !isfinite(cfg->rc) || !isfinite(cfg->skin))
+        return fail(nullptr, MD_ERR_ARG, "rc and skin must be finite and > 0");
+    const int G = cfg->cluster_group ? cfg->cluster_group : 4;
+    if (G != 1 && G != 2 && G != 4 && G != 8)
+        return fail(nullptr, MD_ERR_ARG, "cluster_group must be 1, 2, 4 or 8");
+    if (sys_offsets[0] != 0) return fail(nullptr, MD_ERR_ARG, "sys_offsets[0] must be 0");
+    for (int b = 0; b < cfg->n_systems; ++b)
+        if (sys_offsets[b + 1] < sys_offsets[b])
+            return fail(nullptr, MD_ERR_ARG, "sys_offsets must be non-decreasing");
+    const int64_t N = sys_offsets[cfg->n_systems];
+    if (N > cfg->capacity_atoms)
+        return fail(nullptr, MD_ERR_CAPACITY, "%lld atoms exceed capacity_atoms %lld",
+                    (long long)N, (long long)cfg->capacity_atoms);
+    if (N >= (int64_t)1 << 30) return fail(nullptr, MD_ERR_CAPACITY, "at most 2^30 atoms");
+    md_ctx* ctx = new (std::nothrow) md_ctx();
+    if (!ctx) return fail(nullptr, MD_ERR_CAPACITY, "host allocation failed");
+    Ctx* c = &ctx->c;
+    c->cfg = *cfg;
+    c->B = cfg->n_systems;
+    c->N = N;
+    c->G = G;
+    c->sys_off.assign(sys_offsets, sys_offsets + c->B + 1);
+    c->rlist = cfg->rc + cfg->skin;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
+                                                   c->device);
+    int lds = 0;
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, MD_ERR_HIP, "no HIP device: %s", hipGetErrorString(e));
+    }
+    c->max_lds = (size_t)lds;
+    *out = ctx;
+    return MD_OK;
+}
+
+md_status md_destroy(md_ctx* ctx)
+{
+    if (!ctx) return MD_OK;
+    (void)hipDeviceSynchronize();
+    free_all(&ctx->c);
+    delete ctx;
+    return MD_OK;
+}
+
+static md_status size_and_allocate(Ctx* c)
+{
+    const md_config& cfg = c->cfg;
+    const int64_t N = c->N;
+    const int B = c->B;
+    const double rho = cfg.density_hint > 0 ? cfg.density_hint : 130.0;
+    const double rl = c->rlist;
+    const double a = cbrt(8.0 / rho);
+
+    // periodic grids are fixed by the boxes
+    std::vector<GridSys> grids(B);
+    int64_t cols = 0, bins = 0;
+    if (cfg.periodic) {
+        for (int b = 0; b < B; ++b) {
+            GridSys g{};
+            const double* L = &c->box[3 * b];
+            const double vol = L[0] * L[1] * L[2];
+            const int64_t nb = c->sys_off[b + 1] - c->sys_off[b];
+            const double wt = nb > 0 ? cbrt(8.0 * vol / (double)nb) : std::max({L[0], L[1], L[2]});
+            g.n[0] = std::max(1, (int)(L[0] / wt));
+            g.n[1] = std::max(1, (int)(L[1] / wt));
+            g.n[2] = std::max(1, (int)(L[2] / (0.25 * wt)));
+            for (int k = 0; k < 3; ++k) {
+                g.origin[k] = 0.0;
+                g.L[k] = L[k];
+                g.invL[k] = 1.0 / L[k];
+                g.w[k] = L[k] / g.n[k];
+                g.inv_w[k] = 1.0 / g.w[k];
+            }
+            g.periodic = 1;
+            g.col_off = (int32_t)cols;
+            g.bin_off = (int32_t)bins;
+            cols += (int64_t)g.n[0] * g.n[1];
+            bins += (int64_t)g.n[0] * g.n[1] * g.n[2];
+            grids[b] = g;
+        }
+        c->cap_cols = cols;
+        c->cap_bins = bins;
+    } else {
+        c->cap_cols = N / 8 + B + 1;
+        c->cap_bins = 2 * N + 16 * (int64_t)B + 1;
+    }
+    if (c->cap_bins >= ((int64_t)kScanTile * kScanTile - 1) || c->cap_bins >= INT32_MAX / 2)
+        return fail(c, MD_ERR_CAPACITY, "grid too large (%lld bins)", (long long)c->cap_bins);
+    c->cap_clusters = N / kCluster + c->cap_cols + B + 1;
+    c->cap_slots = c->cap_clusters * kCluster;
+    c->cap_groups = c->cap_clusters;
+
+    // group candidate-table capacity from the rounded-box volume around a group
+    int G = c->G;
+    int E_cap = 0;
+    for (;;) {
+        const double X = 2.0 * a, Y = 2.0 * a, Z = (G + 1) * a;
+        const double V = X * Y * Z + 2.0 * rl * (X * Y + X * Z + Y * Z) +
+                         M_PI * rl * rl * (X + Y + Z) + 4.0 / 3.0 * M_PI * rl * rl * rl;
+        const int est = (int)(V * rho / kCluster * 1.25) + 16;
+        const int lds_cap = (int)((c->max_lds - 2048) / (kCluster * sizeof(float4) + 4)) - 1;
+        E_cap = std::min({est, kMaxGroupEntries, lds_cap});
+        if (E_cap >= est || G == 1) break;
+        G /= 2;
+    }
+    if (E_cap < 32) return fail(c, MD_ERR_CAPACITY, "LDS too small for the candidate table");
+    c->G = G;
+    c->E_cap = E_cap;
+    int nb_cap = cfg.max_neighbors;
+    if (nb_cap <= 0) nb_cap = (int)(4.0 / 3.0 * M_PI * rl * rl * rl * rho * 1.2) + 16;
+    nb_cap = (nb_cap + 7) & ~7;
+    c->nb_cap = nb_cap;
+    c->nb_T = nb_cap / 8;
+    c->cap_partials = vv_partials_needed(N, B);
+
+    // allocation
+    HIP_TRY(c, dalloc(&c->dsc, 1));
+    HIP_TRY(c, dalloc(&c->d_sys_off, B + 1));
+    HIP_TRY(c, dalloc(&c->d_sys_of_atom, N));
+    HIP_TRY(c, dalloc(&c->d_grid, B));
+    HIP_TRY(c, dalloc(&c->d_sys_lo, 3 * B));
+    HIP_TRY(c, dalloc(&c->d_sys_hi, 3 * B));
+    HIP_TRY(c, dalloc(&c->d_sys_grp0, B + 1));
+    HIP_TRY(c, dalloc(&c->d_key, N));
+    HIP_TRY(c, dalloc(&c->d_rank, N));
+    HIP_TRY(c, dalloc(&c->d_img, N));
+    HIP_TRY(c, dalloc(&c->d_bin_cnt, c->cap_bins + 1));
+    HIP_TRY(c, dalloc(&c->d_bin_start, c->cap_bins + 1));
+    HIP_TRY(c, dalloc(&c->d_sorted, N));
+    HIP_TRY(c, dalloc(&c->d_scan_tmp, kScanTile + 64));
+    HIP_TRY(c, dalloc(&c->d_col_ncl, c->cap_cols + 1));
+    HIP_TRY(c, dalloc(&c->d_col_ngrp, c->cap_cols + 1));
+    HIP_TRY(c, dalloc(&c->d_col_cl0, c->cap_cols + 1));
+    HIP_TRY(c, dalloc(&c->d_col_grp0, c->cap_cols + 1));
+    HIP_TRY(c, dalloc(&c->d_cl_lo, 3 * c->cap_clusters));
+    HIP_TRY(c, dalloc(&c->d_cl_hi, 3 * c->cap_clusters));
+    HIP_TRY(c, dalloc(&c->d_cl_nt, c->cap_clusters));
+    HIP_TRY(c, dalloc(&c->d_perm, c->cap_slots));
+    HIP_TRY(c, dalloc(&c->d_slot_img, c->cap_slots));
+    HIP_TRY(c, dalloc(&c->d_inv_perm, N));
+    HIP_TRY(c, dalloc(&c->d_xs, 3 * c->cap_slots));
+    HIP_TRY(c, dalloc(&c->d_qs, c->cap_slots));
+    HIP_TRY(c, dalloc(&c->d_ts, c->cap_slots));
+    HIP_TRY(c, dalloc(&c->d_groups, c->cap_groups));
+    HIP_TRY(c, dalloc(&c->d_ent, c->cap_groups * (int64_t)E_cap));
+    HIP_TRY(c, dalloc(&c->d_nb, c->cap_clusters * (int64_t)c->nb_T * 64));
+    HIP_TRY(c, dalloc(&c->d_grp_epot, c->cap_groups));
+    HIP_TRY(c, dalloc(&c->d_xref, 3 * N));
+    HIP_TRY(c, dalloc(&c->d_partial, c->cap_partials));
+
+    // initial contents
+    DevScalars h{};
+    h.need_rebuild = 1;
+    h.n_cols = (int32_t)(cfg.periodic ? cols : 0);
+    h.n_bins = (int32_t)(cfg.periodic ? bins : 0);
+    HIP_TRY(c, hipMemcpy(c->dsc, &h, sizeof h, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_sys_off, c->sys_off.data(), sizeof(int64_t) * (B + 1),
+                         hipMemcpyHostToDevice));
+    {
+        std::vector<int32_t> soa(std::max<int64_t>(N, 1));
+        for (int b = 0; b < B; ++b)
+            for (int64_t i = c->sys_off[b]; i < c->sys_off[b + 1]; ++i) soa[i] = b;
+        HIP_TRY(c, hipMemcpy(c->d_sys_of_atom, soa.data(), sizeof(int32_t) * std::max<int64_t>(N, 1),
+                             hipMemcpyHostToDevice));
+    }
+    if (cfg.periodic)
+        HIP_TRY(c, hipMemcpy(c->d_grid, grids.data(), sizeof(GridSys) * B, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemset(c->d_perm, 0xFF, sizeof(int32_t) * c->cap_slots));
+    HIP_TRY(c, hipMemset(c->d_cl_nt, 0, sizeof(int32_t) * c->cap_clusters));
+    HIP_TRY(c, hipMemset(c->d_groups, 0, sizeof(Group) * c->cap_groups));
+    HIP_TRY(c, hipMemset(c->d_xref, 0, sizeof(double) * 3 * std::max<int64_t>(N, 1)));
+    HIP_TRY(c, hipMemset(c->d_sys_grp0, 0, sizeof(int32_t) * (B + 1)));
+    HIP_TRY(c, hipMemset(c->d_grp_epot, 0, sizeof(double) * c->cap_groups));
+    HIP_TRY(c, force_kernel_setup(c));
+    return MD_OK;
+}
+
+md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const double* c12,
+                         const int8_t* qmax, const double* lambda_d, const double* base,
+                         const double* g, const uint64_t* seeds, int64_t n_steps)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (null_any({c6, c12, qmax, lambda_d, base, g, seeds}))
+        return fail(c, MD_ERR_ARG, "a table pointer is NULL");
+    if (n_steps < 0) return fail(c, MD_ERR_ARG, "n_steps must be >= 0");
+    if (c->cfg.periodic && !box) return fail(c, MD_ERR_ARG, "periodic systems need box");
+    const int B = c->B, T = c->cfg.n_types, E = c->cfg.n_elements, Q = c->cfg.n_charge_states;
+    if (c->cfg.periodic) {
+        for (int b = 0; b < B; ++b)
+            for (int k = 0; k < 3; ++k) {
+                const double L = box[3 * b + k];
+                if (!(L > 0.0) || !isfinite(L))
+                    return fail(c, MD_ERR_ARG, "box[%d][%d] must be finite and > 0", b, k);
+                if (L < 2.0 * c->rlist * (1.0 + 1e-4))
+                    return fail(c, MD_ERR_GEOMETRY,
+                                "box edge %.6g < 2 (rc + skin) = %.6g: images would overlap", L,
+                                2.0 * c->rlist);
+            }
+    }
+    for (int i = 0; i < T; ++i)
+        for (int j = 0; j < T; ++j)
+            if (c6[i * T + j] != c6[j * T + i] || c12[i * T + j] != c12[j * T + i])
+                return fail(c, MD_ERR_ARG, "c6/c12 tables must be symmetric");
+    for (int e = 0; e < E; ++e)
+        if (qmax[e] < 0) return fail(c, MD_ERR_ARG, "qmax must be >= 0");
+    if (c->tables_bound) {
+        (void)hipDeviceSynchronize();
+        free_all(c);
+        Ctx fresh;
+        fresh.cfg = c->cfg; fresh.B = c->B; fresh.N = c->N; fresh.G = c->cfg.cluster_group ? c->cfg.cluster_group : 4;
+        fresh.sys_off = c->sys_off; fresh.rlist = c->rlist; fresh.device = c->device;
+        fresh.n_cu = c->n_cu; fresh.max_lds = c->max_lds;
+        *c = fresh;
+    }
+    c->box.assign(c->cfg.periodic ? box : nullptr, c->cfg.periodic ? box + 3 * B : nullptr);
+    c->n_steps = n_steps;
+    c->T = T; c->E = E; c->Q = Q;
+    md_status s = size_and_allocate(c);
+    if (s != MD_OK) return s;
+    const int64_t S1 = n_steps + 1;
+    std::vector<double> kappa((size_t)B * S1);
+    for (size_t i = 0; i < kappa.size(); ++i) {
+        const double lam = lambda_d[i];
+        if (!(lam > 0.0)) return fail(c, MD_ERR_ARG, "lambda_d must be > 0 (+inf: unscreened)");
+        kappa[i] = isinf(lam) ? 0.0 : 1.0 / lam;
+    }
+    std::vector<float> lj32(2 * T * T);
+    for (int i = 0; i < T * T; ++i) {
+        lj32[2 * i] = (float)c6[i];
+        lj32[2 * i + 1] = (float)c12[i];
+    }
+    HIP_TRY(c, dalloc(&c->d_c6, T * T));
+    HIP_TRY(c, dalloc(&c->d_c12, T * T));
+    HIP_TRY(c, dalloc(&c->d_lj32, 2 * T * T));
+    HIP_TRY(c, dalloc(&c->d_qmax, E));
+    HIP_TRY(c, dalloc(&c->d_kappa, B * S1));
+    HIP_TRY(c, dalloc(&c->d_base, (int64_t)E * Q));
+    HIP_TRY(c, dalloc(&c->d_g, B * S1));
+    HIP_TRY(c, dalloc(&c->d_seeds, B));
+    HIP_TRY(c, hipMemcpy(c->d_c6, c6, sizeof(double) * T * T, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_c12, c12, sizeof(double) * T * T, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_lj32, lj32.data(), sizeof(float) * 2 * T * T, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_qmax, qmax, E, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_kappa, kappa.data(), sizeof(double) * B * S1, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_base, base, sizeof(double) * E * Q, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_g, g, sizeof(double) * B * S1, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_seeds, seeds, sizeof(uint64_t) * B, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipDeviceSynchronize());
+    c->tables_bound = true;
+    c->built = false;
+    c->build_calls_since = 0;
+    return MD_OK;
+}
+
+md_status md_set_step(md_ctx* ctx, int64_t step, md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    launch_set_step(c, step, S(stream));
+    HIP_TRY(c, hipGetLastError());
+    return MD_OK;
+}
+
+md_status md_get_step(md_ctx* ctx, int64_t* step, md_stream stream)
+{
+    if (!ctx || !step) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    HIP_TRY(c, hipStreamSynchronize(S(stream)));
+    HIP_TRY(c, hipMemcpy(step, &c->dsc->step, sizeof(int64_t), hipMemcpyDeviceToHost));
+    return MD_OK;
+}
+
+md_status md_set_nstlist(md_ctx* ctx, int32_t nstlist)
+{
+    if (!ctx) return MD_ERR_ARG;
+    if (nstlist < 1) return fail(&ctx->c, MD_ERR_ARG, "nstlist must be >= 1");
+    ctx->c.nstlist = nstlist;
+    return MD_OK;
+}
+
+md_status md_build_cells(md_ctx* ctx, const double* x, const double* y, const double* z,
+                         const uint8_t* type, int32_t mode, md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (null_any({x, y, z, type}) && c->N > 0) return fail(c, MD_ERR_ARG, "NULL array");
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    if (mode != MD_BUILD_AUTO && mode != MD_BUILD_FORCE && mode != MD_BUILD_CHECK)
+        return fail(c, MD_ERR_ARG, "unknown build mode %d", mode);
+    bool rebuild = mode == MD_BUILD_FORCE || !c->built;
+    if (mode == MD_BUILD_AUTO && !rebuild) rebuild = ++c->build_calls_since >= c->nstlist;
+    if (mode == MD_BUILD_CHECK && c->built) {
+        launch_skin_check(c, S(stream));
+    } else if (rebuild) {
+        launch_build(c, x, y, z, type, S(stream));
+        c->built = true;
+        c->build_calls_since = 0;
+        c->host_builds++;
+    }
+    HIP_TRY(c, hipGetLastError());
+    return MD_OK;
+}
+
+md_status md_ionize_step(md_ctx* ctx, const uint8_t* elem, const uint32_t* atom_id, int8_t* q,
+                         md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (null_any({elem, atom_id, q}) && c->N > 0) return fail(c, MD_ERR_ARG, "NULL array");
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    launch_ionize(c, elem, atom_id, q, S(stream));
+    HIP_TRY(c, hipGetLastError());
+    return MD_OK;
+}
+
+md_status md_screened_forces(md_ctx* ctx, md_precision prec, const double* x, const double* y,
+                             const double* z, const int8_t* q, const uint8_t* type, double* fx,
+                             double* fy, double* fz, double* epot, md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (null_any({x, y, z, q, type, fx, fy, fz}) && c->N > 0)
+        return fail(c, MD_ERR_ARG, "NULL array");
+    if (prec != MD_FP64 && prec != MD_FP32_KAHAN) return fail(c, MD_ERR_ARG, "unknown precision");
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    if (!c->built) return fail(c, MD_ERR_STATE, "md_build_cells has not run");
+    launch_repack(c, x, y, z, q, S(stream));
+    HIP_TRY(c, launch_forces(c, prec, fx, fy, fz, epot, nullptr, 0, S(stream)));
+    return MD_OK;
+}
+
+md_status md_integrate_vv(md_ctx* ctx, int32_t phase, double dt, const double* inv_mass,
+                          const double* fx, const double* fy, const double* fz, double* x,
+                          double* y, double* z, double* vx, double* vy, double* vz,
+                          double* ekin, md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (phase != 0 && phase != 1) return fail(c, MD_ERR_ARG, "phase must be 0 or 1");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, MD_ERR_ARG, "dt must be finite and > 0");
+    if (null_any({inv_mass, fx, fy, fz, x, y, z, vx, vy, vz}) && c->N > 0)
+        return fail(c, MD_ERR_ARG, "NULL array");
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    launch_vv(c, phase, dt, inv_mass, fx, fy, fz, x, y, z, vx, vy, vz, ekin, S(stream));
+    HIP_TRY(c, hipGetLastError());
+    return MD_OK;
+}
+
+md_status md_sync_check(md_ctx* ctx, md_stream stream, uint32_t* flags)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound) {
+        if (flags) *flags = 0;
+        return MD_OK;
+    }
+    HIP_TRY(c, hipStreamSynchronize(S(stream)));
+    uint32_t f = 0;
+    HIP_TRY(c, hipMemcpy(&f, &c->dsc->flags, sizeof f, hipMemcpyDeviceToHost));
+    if (flags) *flags = f;
+    if (f) return fail(c, MD_ERR_DEVICE, "device error word 0x%x", f);
+    return MD_OK;
+}
+
+md_status md_clear_flags(md_ctx* ctx, md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound) return MD_OK;
+    launch_clear_flags(c, S(stream));
+    HIP_TRY(c, hipGetLastError());
+    return MD_OK;
+}
+
+md_status md_debug_pairs(md_ctx* ctx, md_precision prec, const double* x, const double* y,
+                         const double* z, const int8_t* q, int64_t* n_pairs, int32_t* ij,
+                         int64_t max, md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (null_any({x, y, z, q, n_pairs}) || (max > 0 && !ij))
+        return fail(c, MD_ERR_ARG, "NULL argument");
+    if (max < 0) return fail(c, MD_ERR_ARG, "max must be >= 0");
+    if (!c->tables_bound || !c->built) return fail(c, MD_ERR_STATE, "no build");
+    hipStream_t st = S(stream);
+    int2* buf = nullptr;
+    double* f = nullptr;
+    HIP_TRY(c, dalloc(&buf, std::max<int64_t>(max, 1)));
+    hipError_t e = dalloc(&f, 3 * std::max<int64_t>(c->N, 1));
+    if (e != hipSuccess) { (void)hipFree(buf); return fail(c, MD_ERR_HIP, "allocation failed"); }
+    e = hipMemsetAsync(&c->dsc->pair_count, 0, sizeof(unsigned long long), st);
+    if (e == hipSuccess) {
+        launch_repack(c, x, y, z, q, st);
+        e = launch_forces(c, prec, f, f + c->N, f + 2 * c->N, nullptr, buf, max, st);
+    }
+    unsigned long long cnt = 0;
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = hipMemcpy(&cnt, &c->dsc->pair_count, sizeof cnt, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && max > 0)
+        e = hipMemcpy(ij, buf, sizeof(int2) * std::min<int64_t>((int64_t)cnt, max),
+                      hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    (void)hipFree(f);
+    if (e != hipSuccess) return fail(c, MD_ERR_HIP, "debug pair export: %s", hipGetErrorString(e));
+    *n_pairs = (int64_t)cnt;
+    return MD_OK;
+}
+
+md_status md_get_stats(md_ctx* ctx, md_stats* out, md_stream stream)
+{
+    if (!ctx || !out) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    memset(out, 0, sizeof *out);
+    out->n_atoms = c->N;
+    out->cluster_group = c->G;
+    out->list_capacity = c->nb_cap;
+    out->group_entry_capacity = c->E_cap;
+    if (!c->tables_bound) return MD_OK;
+    HIP_TRY(c, hipStreamSynchronize(S(stream)));
+    DevScalars h;
+    HIP_TRY(c, hipMemcpy(&h, c->dsc, sizeof h, hipMemcpyDeviceToHost));
+    out->n_clusters = h.n_clusters;
+    out->n_groups = h.n_groups;
+    out->n_list_codes = h.n_codes;
+    out->max_list_len = h.max_list;
+    out->max_group_entries = h.max_entries;
+    out->n_builds = h.n_builds;
+    out->flags = h.flags;
+    int64_t ne = 0;
+    if (h.n_groups > 0) {
+        std::vector<Group> gr(h.n_groups);
+        HIP_TRY(c, hipMemcpy(gr.data(), c->d_groups, sizeof(Group) * h.n_groups,
+                             hipMemcpyDeviceToHost));
+        for (const Group& x : gr) ne += x.nent;
+    }
+    out->n_entries = ne;
+    return MD_OK;
+}
+
+double md_debye_length_nm(double te_ev, double ne_m3)
+{
+    // lambda_D = sqrt(eps0 k_B T_e / (n_e e^2)) with k_B T_e = T_e[eV] * e
+    const double eps0 = 8.8541878128e-12, e = 1.602176634e-19;
+    if (!(te_ev > 0.0) || !(ne_m3 > 0.0)) return NAN;
+    return sqrt(eps0 * te_ev / (ne_m3 * e)) * 1e9;
+}
+
+md_status md_rates_from_fractions(int64_t S, int32_t Z, const double* P, double* p)
+{
+    if (!P || !p || S < 0 || Z < 0) return MD_ERR_ARG;
+    const int32_t nq = Z + 1;
+    for (int32_t q = 0; q < nq; ++q) p[q] = 0.0;
+    for (int64_t s = 1; s <= S; ++s) {
+        const double* prev = P + (s - 1) * nq;
+        const double* cur = P + s * nq;
+        // flux out of charge q = growth of every higher charge state
+        double above = 0.0;
+        for (int32_t q = Z; q >= 0; --q) {
+            double v = 0.0;
+            if (q < Z && prev[q] > 0.0) v = above / prev[q];
+            p[s * nq + q] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+            above += cur[q] - prev[q];
+        }
+    }
+    return MD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ full step and graphs
+
+struct md_graph {
+    md_ctx* ctx;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+static md_status step_impl(md_ctx* ctx, const md_step_args* a, int32_t build_mode, md_stream st)
+{
+    md_status s = md_integrate_vv(ctx, 0, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y,
+                                  a->z, a->vx, a->vy, a->vz, nullptr, st);
+    if (s == MD_OK) s = md_ionize_step(ctx, a->elem, a->atom_id, a->q, st);
+    if (s == MD_OK) s = md_build_cells(ctx, a->x, a->y, a->z, a->type, build_mode, st);
+    if (s == MD_OK)
+        s = md_screened_forces(ctx, a->prec, a->x, a->y, a->z, a->q, a->type, a->fx, a->fy, a->fz,
+                               a->epot, st);
+    if (s == MD_OK)
+        s = md_integrate_vv(ctx, 1, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y, a->z,
+                            a->vx, a->vy, a->vz, a->ekin, st);
+    return s;
+}
+
+md_status md_step(md_ctx* ctx, const md_step_args* args, int32_t build_mode, md_stream stream)
+{
+    if (!ctx || !args) return MD_ERR_ARG;
+    return step_impl(ctx, args, build_mode, stream);
+}
+
+md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t with_rebuild,
+                          md_stream stream, md_graph** out)
+{
+    if (!ctx || !args || !out) return MD_ERR_ARG;
+    *out = nullptr;
+    Ctx* c = &ctx->c;
+    if (!stream) return fail(c, MD_ERR_ARG, "graph capture needs a non-null stream");
+    if (!c->built) return fail(c, MD_ERR_STATE, "build cells before capturing a step");
+    hipStream_t st = S(stream);
+    HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const md_status s = step_impl(ctx, args, with_rebuild ? MD_BUILD_FORCE : MD_BUILD_CHECK,
+                                  stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (s != MD_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return fail(c, MD_ERR_HIP, "capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(c, MD_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e2));
+    }
+    md_graph* g = new (std::nothrow) md_graph{ctx, graph, exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(c, MD_ERR_CAPACITY, "host allocation failed");
+    }
+    *out = g;
+    return MD_OK;
+}
+
+md_status md_graph_launch(md_graph* graph, md_stream stream)
+{
+    if (!graph) return MD_ERR_ARG;
+    const hipError_t e = hipGraphLaunch(graph->exec, S(stream));
+    if (e != hipSuccess)
+        return fail(&graph->ctx->c, MD_ERR_HIP, "graph launch failed: %s", hipGetErrorString(e));
+    return MD_OK;
+}
+
+md_status md_graph_destroy(md_graph* graph)
+{
+    if (!graph) return MD_OK;
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    return MD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,636 @@
+// md_build.hip -- neighbour search.
+//
+// The screening-reduced cutoff (arXiv 2401.03180, section II.B) bounds the pairs
+// that are ever evaluated.  A build turns caller-ordered positions into
+//   1. a per-system grid of x-y columns with fine z bins; a counting sort puts
+//      the atoms of every column in z order (ties by atom index, so the order is
+//      deterministic);
+//   2. clusters of 8 consecutive atoms of a column ("slots"; the last cluster of a
+//      column is padded) with FP64 bounding boxes;
+//   3. groups of up to G consecutive clusters of a column; for each group the
+//      candidate table of (cluster, periodic shift) entries whose bounding box
+//      lies within rc + skin of the group's box;
+//   4. for every atom a compacted list of 16-bit codes naming the staged
+//      candidate atoms within rc + skin (entry * 8 + lane | type << 13).
+// The lists stay valid while no atom moves more than skin/2 from its build
+// position.
+#include "md_internal.h"
+#include "md_launch.h"
+
+namespace md {
+
+constexpr float kFar = 1.0e4f;   // staged coordinate of padding slots
+
+__device__ inline int find_sys_by_col(const GridSys* grid, int B, int c)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (grid[mid].col_off <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// largest k in [0, n] with arr[k] <= v (arr non-decreasing, arr[0] <= v)
+__device__ inline int upper_index(const int32_t* arr, int n, int v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (arr[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_build_begin(DevScalars* d)
+{
+    d->max_entries = 0;
+    d->max_list = 0;
+    d->n_codes = 0;
+}
+
+__global__ void k_build_done(DevScalars* d)
+{
+    d->need_rebuild = 0;
+    d->disp2_bits = 0ull;
+    d->n_builds += 1;
+}
+
+// ---------------------------------------------------------------- vacuum grids
+
+__global__ void __launch_bounds__(256) k_sys_bbox(const double* x, const double* y,
+                                                  const double* z, const int64_t* sys_off,
+                                                  double* lo, double* hi, DevScalars* dsc)
+{
+    __shared__ double s_v[6][4];
+    const int b = blockIdx.x;
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    for (int64_t a = sys_off[b] + threadIdx.x; a < sys_off[b + 1]; a += blockDim.x) {
+        const double p[3] = {x[a], y[a], z[a]};
+        for (int k = 0; k < 3; ++k) {
+            if (!isfinite(p[k])) { bad = true; continue; }
+            mn[k] = fmin(mn[k], p[k]);
+            mx[k] = fmax(mx[k], p[k]);
+        }
+    }
+    if (bad) set_flag(dsc, MD_FLAG_NONFINITE);
+    for (int k = 0; k < 3; ++k)
+        for (int off = 32; off > 0; off >>= 1) {
+            mn[k] = fmin(mn[k], __shfl_xor(mn[k], off, 64));
+            mx[k] = fmax(mx[k], __shfl_xor(mx[k], off, 64));
+        }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) { s_v[k][wv] = mn[k]; s_v[3 + k][wv] = mx[k]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k) {
+            double a = s_v[k][0], c = s_v[3 + k][0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+                a = fmin(a, s_v[k][w]);
+                c = fmax(c, s_v[3 + k][w]);
+            }
+            if (!(a <= c)) { a = 0.0; c = 0.0; }     // empty system
+            lo[b * 3 + k] = a;
+            hi[b * 3 + k] = c;
+        }
+    }
+}
+
+// One block: grid dimensions of every vacuum system (columns of about 8 atoms'
+// cross-section, z bins a quarter of that), bounded by per-system budgets so the
+// totals never exceed the capacities; then the global column / bin offsets.
+__global__ void __launch_bounds__(256) k_grid_vacuum(const double* lo, const double* hi,
+                                                     const int64_t* sys_off, int B,
+                                                     GridSys* grid, DevScalars* dsc)
+{
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        const int64_t nb = sys_off[b + 1] - sys_off[b];
+        GridSys g;
+        double ext[3];
+        for (int k = 0; k < 3; ++k) {
+            const double e = hi[b * 3 + k] - lo[b * 3 + k];
+            const double margin = 1e-6 * (1.0 + e);
+            ext[k] = fmax(e, 1e-3) + 2.0 * margin;
+            g.origin[k] = lo[b * 3 + k] - margin;
+            g.L[k] = 0.0;
+            g.invL[k] = 0.0;
+        }
+        const double vol = ext[0] * ext[1] * ext[2];
+        const double rho = (double)(nb > 0 ? nb : 1) / vol;
+        double wt = cbrt(8.0 / rho);
+        const int64_t col_budget = nb / 8 + 1;
+        int nx, ny;
+        for (;;) {
+            nx = max(1, (int)(ext[0] / wt));
+            ny = max(1, (int)(ext[1] / wt));
+            if ((int64_t)nx * ny <= col_budget) break;
+            wt *= 1.25;
+        }
+        const int64_t bin_budget = 2 * nb + 16;
+        int nz = max(1, (int)(ext[2] / (0.25 * wt)));
+        while ((int64_t)nx * ny * nz > bin_budget && nz > 1) nz = max(1, nz / 2);
+        g.n[0] = nx; g.n[1] = ny; g.n[2] = nz;
+        g.w[0] = ext[0] / nx; g.w[1] = ext[1] / ny; g.w[2] = ext[2] / nz;
+        for (int k = 0; k < 3; ++k) g.inv_w[k] = 1.0 / g.w[k];
+        g.periodic = 0;
+        g.col_off = nx * ny;            // counts for now; offsets below
+        g.bin_off = nx * ny * nz;
+        grid[b] = g;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int cols = 0, bins = 0;
+        for (int b = 0; b < B; ++b) {
+            const int nc = grid[b].col_off, nbn = grid[b].bin_off;
+            grid[b].col_off = cols;
+            grid[b].bin_off = bins;
+            cols += nc;
+            bins += nbn;
+        }
+        dsc->n_cols = cols;
+        dsc->n_bins = bins;
+    }
+}
+
+// ---------------------------------------------------------------- binning + sort
+
+struct BinArgs {
+    int64_t N;
+    const double *x, *y, *z;
+    const int32_t* sys_of_atom;
+    const GridSys* grid;
+    int32_t* bin_cnt;
+    int32_t* key;
+    int32_t* rank;
+    int32_t* img;
+    double* xref;
+    int64_t cap_bins;
+    DevScalars* dsc;
+};
+
+__global__ void __launch_bounds__(256) k_bin(BinArgs A)
+{
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= A.N) return;
+    const GridSys g = A.grid[A.sys_of_atom[a]];
+    const double p[3] = {A.x[a], A.y[a], A.z[a]};
+    int c[3], im[3] = {0, 0, 0};
+    bool bad = false;
+    for (int k = 0; k < 3; ++k) {
+        double v = p[k];
+        if (!isfinite(v)) { bad = true; v = 0.0; }
+        double w;
+        if (g.periodic) {
+            const double kk = floor(v * g.invL[k]);
+            if (fabs(kk) > 500.0) bad = true;
+            im[k] = (int)fmin(fmax(kk, -500.0), 500.0);
+            w = v - (double)im[k] * g.L[k];
+        } else {
+            w = v - g.origin[k];
+        }
+        const double cf = fmin(fmax(floor(w * g.inv_w[k]), 0.0), (double)(g.n[k] - 1));
+        c[k] = (int)cf;
+    }
+    if (bad) set_flag(A.dsc, MD_FLAG_NONFINITE);
+    int bin = g.bin_off + (c[0] * g.n[1] + c[1]) * g.n[2] + c[2];
+    if (bin >= A.cap_bins) { set_flag(A.dsc, MD_FLAG_CELL_OVERFLOW); bin = (int)A.cap_bins - 1; }
+    A.rank[a] = atomicAdd(&A.bin_cnt[bin], 1);
+    A.key[a] = bin;
+    A.img[a] = pack_img(im[0], im[1], im[2]);
+    A.xref[a] = p[0];
+    A.xref[A.N + a] = p[1];
+    A.xref[2 * A.N + a] = p[2];
+}
+
+__global__ void __launch_bounds__(256) k_scatter(int64_t N, const int32_t* key,
+                                                 const int32_t* rank, const int32_t* bin_start,
+                                                 int32_t* sorted)
+{
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    sorted[bin_start[key[a]] + rank[a]] = (int32_t)a;
+}
+
+// Order the atoms of each bin by caller index (bins hold a few atoms).
+__global__ void __launch_bounds__(256) k_bin_sort(const int32_t* bin_start, int32_t* sorted,
+                                                  int64_t cap_bins, const DevScalars* dsc)
+{
+    const int nbins = dsc->n_bins;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nbins && b < cap_bins;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const int s = bin_start[b], e = bin_start[b + 1];
+        if (e - s < 2 || e - s > 128) continue;
+        for (int i = s + 1; i < e; ++i) {
+            const int v = sorted[i];
+            int j = i - 1;
+            while (j >= s && sorted[j] > v) { sorted[j + 1] = sorted[j]; --j; }
+            sorted[j + 1] = v;
+        }
+    }
+}
+
+// Per column: clusters = ceil(atoms / 8); groups = ceil(clusters / G).
+__global__ void __launch_bounds__(256) k_col_count(const GridSys* grid, int B,
+                                                   const int32_t* bin_start, int32_t* col_ncl,
+                                                   int32_t* col_ngrp, int64_t cap_cols, int G,
+                                                   const DevScalars* dsc)
+{
+    const int ncols = dsc->n_cols;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c <= cap_cols;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int ncl = 0;
+        if (c < ncols) {
+            const int b = find_sys_by_col(grid, B, (int)c);
+            const GridSys& g = grid[b];
+            const int nz = g.n[2];
+            const int bin0 = g.bin_off + ((int)c - g.col_off) * nz;
+            const int natoms = bin_start[bin0 + nz] - bin_start[bin0];
+            ncl = (natoms + kCluster - 1) / kCluster;
+        }
+        col_ncl[c] = ncl;
+        col_ngrp[c] = (ncl + G - 1) / G;
+    }
+}
+
+struct ClusterArgs {
+    const double *x, *y, *z;
+    const uint8_t* type;
+    const GridSys* grid;
+    int B;
+    const int32_t* bin_start;
+    const int32_t* sorted;
+    const int32_t* col_cl0;
+    const int32_t* col_grp0;
+    const int32_t* img;
+    int32_t* perm;
+    int32_t* inv_perm;
+    int32_t* slot_img;
+    uint8_t* ts;
+    double* cl_lo;
+    double* cl_hi;
+    Group* groups;
+    int32_t* sys_grp0;
+    int64_t cap_clusters;
+    int G;
+    int T;
+    DevScalars* dsc;
+};
+
+__global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
+{
+    const int ncols = A.dsc->n_cols;
+    int total = A.col_cl0[ncols];
+    const int ngroups = A.col_grp0[ncols];
+    const int64_t gid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid0 == 0) {
+        if (total > A.cap_clusters) set_flag(A.dsc, MD_FLAG_CELL_OVERFLOW);
+        A.dsc->n_clusters = min((int64_t)total, A.cap_clusters);
+        A.dsc->n_groups = min((int64_t)ngroups, A.cap_clusters);
+        A.dsc->n_slots = kCluster * min((int64_t)total, A.cap_clusters);
+        A.sys_grp0[A.B] = min((int64_t)ngroups, A.cap_clusters);
+    }
+    if (gid0 < A.B) A.sys_grp0[gid0] = min(A.col_grp0[A.grid[gid0].col_off], (int)A.cap_clusters);
+    total = (int)min((int64_t)total, A.cap_clusters);
+    for (int64_t cl = gid0; cl < total; cl += (int64_t)gridDim.x * blockDim.x) {
+        const int c = upper_index(A.col_cl0, ncols, (int)cl);
+        const int b = find_sys_by_col(A.grid, A.B, c);
+        const GridSys& g = A.grid[b];
+        const int nz = g.n[2];
+        const int bin0 = g.bin_off + (c - g.col_off) * nz;
+        const int k = (int)cl - A.col_cl0[c];
+        const int abeg = A.bin_start[bin0] + kCluster * k;
+        const int aend = A.bin_start[bin0 + nz];
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int l = 0; l < kCluster; ++l) {
+            const int64_t slot = cl * kCluster + l;
+            const int src = abeg + l;
+            if (src < aend) {
+                const int a = A.sorted[src];
+                const int32_t im = A.img[a];
+                A.perm[slot] = a;
+                A.inv_perm[a] = (int32_t)slot;
+                A.slot_img[slot] = im;
+                int ty = A.type[a];
+                if (ty >= A.T) { set_flag(A.dsc, MD_FLAG_BAD_INPUT); ty = A.T - 1; }
+                A.ts[slot] = (uint8_t)ty;
+                const double p[3] = {A.x[a], A.y[a], A.z[a]};
+                for (int d = 0; d < 3; ++d) {
+                    const double w = g.periodic ? p[d] - (double)unpack_img(im, d) * g.L[d] : p[d];
+                    lo[d] = fmin(lo[d], w);
+                    hi[d] = fmax(hi[d], w);
+                }
+            } else {
+                A.perm[slot] = -1;
+                A.slot_img[slot] = 0;
+                A.ts[slot] = 0;
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            A.cl_lo[cl * 3 + d] = lo[d];
+            A.cl_hi[cl * 3 + d] = hi[d];
+        }
+        if (k % A.G == 0) {
+            const int ncl_col = A.col_cl0[c + 1] - A.col_cl0[c];
+            const int grp = A.col_grp0[c] + k / A.G;
+            if (grp < A.cap_clusters) {
+                A.groups[grp].cl0 = (int)cl;
+                A.groups[grp].ncl = min(A.G, ncl_col - k);
+                A.groups[grp].sys = b;
+                A.groups[grp].nent = 0;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- group candidate tables
+
+struct EntryArgs {
+    const GridSys* grid;
+    const int32_t* col_cl0;
+    const double* cl_lo;
+    const double* cl_hi;
+    Group* groups;
+    uint32_t* ent;
+    int E_cap;
+    double rlist;
+    DevScalars* dsc;
+};
+
+// One wave per group.  Candidates are visited in a fixed order and appended with a
+// ballot prefix, so the table is deterministic.
+__global__ void __launch_bounds__(256) k_group_entries(EntryArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int ngroups = A.dsc->n_groups;
+    const double rl = A.rlist, rl2 = rl * rl;
+    for (int64_t g = wave0; g < ngroups; g += nwaves) {
+        Group gr = A.groups[g];
+        const GridSys gs = A.grid[gr.sys];
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = lane < gr.ncl ? A.cl_lo[(gr.cl0 + lane) * 3 + d] : INFINITY;
+            hi[d] = lane < gr.ncl ? A.cl_hi[(gr.cl0 + lane) * 3 + d] : -INFINITY;
+            for (int off = 32; off > 0; off >>= 1) {
+                lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, 64));
+                hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, 64));
+            }
+        }
+        // an empty or non-finite box (non-finite positions are flagged by the binning)
+        // gets no candidates
+        bool finite_box = true;
+        for (int d = 0; d < 3; ++d) finite_box = finite_box && isfinite(lo[d]) && isfinite(hi[d]);
+        int cr[2][2] = {{0, -1}, {0, -1}};
+        if (finite_box) {
+            for (int d = 0; d < 2; ++d) {
+                const double o = gs.periodic ? 0.0 : gs.origin[d];
+                const double f0 = floor((lo[d] - rl - o) * gs.inv_w[d]);
+                const double f1 = floor((hi[d] + rl - o) * gs.inv_w[d]);
+                // images -1, 0, +1 only (the box edge is at least 2 (rc + skin))
+                const double lim0 = gs.periodic ? -gs.n[d] : 0.0;
+                const double lim1 = gs.periodic ? 2.0 * gs.n[d] - 1.0 : gs.n[d] - 1.0;
+                cr[d][0] = (int)fmax(f0, lim0);
+                cr[d][1] = (int)fmin(f1, lim1);
+            }
+        }
+        const int nsz = gs.periodic ? 3 : 1;
+        int count = 0;
+        for (int cx = cr[0][0]; cx <= cr[0][1]; ++cx) {
+            const int cxw = ((cx % gs.n[0]) + gs.n[0]) % gs.n[0];
+            const int sx = (cx - cxw) / gs.n[0];
+            if (sx < -1 || sx > 1) continue;
+            for (int cy = cr[1][0]; cy <= cr[1][1]; ++cy) {
+                const int cyw = ((cy % gs.n[1]) + gs.n[1]) % gs.n[1];
+                const int sy = (cy - cyw) / gs.n[1];
+                if (sy < -1 || sy > 1) continue;
+                const int col = gs.col_off + cxw * gs.n[1] + cyw;
+                const int j0 = A.col_cl0[col], j1 = A.col_cl0[col + 1];
+                const int cand = (j1 - j0) * nsz;
+                for (int base = 0; base < cand; base += 64) {
+                    const int cidx = base + lane;
+                    bool pass = false;
+                    int J = 0, sz = 0;
+                    if (cidx < cand) {
+                        J = j0 + cidx / nsz;
+                        sz = nsz == 3 ? cidx % 3 - 1 : 0;
+                        const int sh[3] = {sx, sy, sz};
+                        double d2 = 0.0;
+                        for (int d = 0; d < 3; ++d) {
+                            const double s = gs.periodic ? sh[d] * gs.L[d] : 0.0;
+                            const double jl = A.cl_lo[J * 3 + d] + s, jh = A.cl_hi[J * 3 + d] + s;
+                            const double gap = fmax(0.0, fmax(jl - hi[d], lo[d] - jh));
+                            d2 += gap * gap;
+                        }
+                        pass = d2 < rl2;
+                    }
+                    const unsigned long long bal = __ballot(pass);
+                    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+                    if (pass) {
+                        const int pos = count + before;
+                        if (pos < A.E_cap)
+                            A.ent[g * A.E_cap + pos] = (uint32_t)J | ((uint32_t)(sx + 1) << 26) |
+                                                       ((uint32_t)(sy + 1) << 28) |
+                                                       ((uint32_t)(sz + 1) << 30);
+                    }
+                    count += __popcll(bal);
+                }
+            }
+        }
+        if (lane == 0) {
+            for (int d = 0; d < 3; ++d) {
+                if (!finite_box) { lo[d] = 0.0; hi[d] = 0.0; }
+                A.groups[g].lo[d] = lo[d];
+                A.groups[g].hi[d] = hi[d];
+                A.groups[g].c[d] = 0.5 * (lo[d] + hi[d]);
+            }
+            A.groups[g].nent = min(count, A.E_cap);
+            atomicMax(&A.dsc->max_entries, count);
+            if (count > A.E_cap) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- per-atom codes
+
+struct ListArgs {
+    const double *x, *y, *z;     // build positions (caller order)
+    const GridSys* grid;
+    const Group* groups;
+    const uint32_t* ent;
+    const int32_t* perm;
+    const int32_t* slot_img;
+    const uint8_t* ts;
+    uint16_t* nb;
+    int32_t* cl_nt;
+    int E_cap, nb_cap, nb_T;
+    float thr2;                 // (rc + skin)^2 with a relative margin
+    DevScalars* dsc;
+};
+
+__device__ inline float3 frame_coords(const double* x, const double* y, const double* z, int a,
+                                      int32_t img, uint32_t en, const GridSys& gs,
+                                      const double* c)
+{
+    const int sh[3] = {(int)((en >> 26) & 3u) - 1, (int)((en >> 28) & 3u) - 1,
+                       (int)((en >> 30) & 3u) - 1};
+    const double p[3] = {x[a], y[a], z[a]};
+    float r[3];
+    for (int d = 0; d < 3; ++d) {
+        double w = p[d];
+        if (gs.periodic) w = w - (double)(unpack_img(img, d) - sh[d]) * gs.L[d];
+        r[d] = (float)(w - c[d]);
+    }
+    return make_float3(r[0], r[1], r[2]);
+}
+
+__global__ void __launch_bounds__(512) k_atom_lists(ListArgs A)
+{
+    extern __shared__ float4 s_dyn[];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    float4* s_pos = s_dyn;
+    uint32_t* s_ent = reinterpret_cast<uint32_t*>(s_dyn + (A.E_cap * kCluster + 1));
+    const int ngroups = A.dsc->n_groups;
+    const uint16_t sentinel = (uint16_t)(A.E_cap * kCluster);
+    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const Group gr = A.groups[g];
+        const GridSys gs = A.grid[gr.sys];
+        const int nst = gr.nent * kCluster;
+        for (int idx = tid; idx < nst; idx += blockDim.x) {
+            const int e = idx >> 3, jl = idx & 7;
+            const uint32_t en = A.ent[(int64_t)g * A.E_cap + e];
+            if (jl == 0) s_ent[e] = en;
+            const int64_t slot = (int64_t)(en & kEntClusterMask) * kCluster + jl;
+            const int a = A.perm[slot];
+            float4 v;
+            if (a >= 0) {
+                const float3 f = frame_coords(A.x, A.y, A.z, a, A.slot_img[slot], en, gs, gr.c);
+                v = make_float4(f.x, f.y, f.z, (float)A.ts[slot]);
+            } else {
+                v = make_float4(kFar, kFar, kFar, -1.0f);
+            }
+            s_pos[idx] = v;
+        }
+        __syncthreads();
+        if (w < gr.ncl) {
+            const int I = gr.cl0 + w;
+            const int il = lane >> 3, k = lane & 7;
+            const int64_t slot_i = (int64_t)I * kCluster + il;
+            const int ai = A.perm[slot_i];
+            float3 xi = make_float3(-kFar, -kFar, -kFar);
+            if (ai >= 0) xi = frame_coords(A.x, A.y, A.z, ai, A.slot_img[slot_i], 0x54000000u, gs, gr.c);
+            int cnt = 0;
+            uint16_t* out = A.nb + (int64_t)I * A.nb_T * 64 + il * 8;
+            for (int e = 0; e < gr.nent; ++e) {
+                const int j = e * kCluster + k;
+                const float4 pj = s_pos[j];
+                const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const uint32_t en = s_ent[e];
+                const bool self = ((en & kEntClusterMask) == (uint32_t)I) &&
+                                  ((en >> 26) == 0x15u) && (k == il);
+                const bool pass = (ai >= 0) && (pj.w >= 0.0f) && (r2 < A.thr2) && !self;
+                const unsigned long long bal = __ballot(pass);
+                const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
+                if (pass) {
+                    const int pos = cnt + __popc(mine & ((1u << k) - 1u));
+                    if (pos < A.nb_cap)
+                        out[(pos >> 3) * 64 + (pos & 7)] =
+                            (uint16_t)(j | ((int)pj.w << kCodeIdxBits));
+                }
+                cnt += __popc(mine);
+            }
+            int mx = cnt;
+            for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+            const int nt = min((mx + 7) >> 3, A.nb_T);
+            for (int t = 0; t < nt; ++t) {
+                const int pos = t * 8 + k;
+                if (pos >= cnt) out[t * 64 + k] = sentinel;
+            }
+            if (lane == 0) {
+                A.cl_nt[I] = nt;
+                atomicMax(&A.dsc->max_list, mx);
+                if (mx > A.nb_cap) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
+            }
+            if (k == 0) atomicAdd((unsigned long long*)&A.dsc->n_codes, (unsigned long long)cnt);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- orchestration
+
+void launch_build(Ctx* c, const double* x, const double* y, const double* z,
+                  const uint8_t* type, hipStream_t st)
+{
+    const int64_t N = c->N;
+    hipLaunchKernelGGL(k_build_begin, dim3(1), dim3(1), 0, st, c->dsc);
+    if (!c->cfg.periodic) {
+        hipLaunchKernelGGL(k_sys_bbox, dim3(c->B), dim3(256), 0, st, x, y, z, c->d_sys_off,
+                           c->d_sys_lo, c->d_sys_hi, c->dsc);
+        hipLaunchKernelGGL(k_grid_vacuum, dim3(1), dim3(256), 0, st, c->d_sys_lo, c->d_sys_hi,
+                           c->d_sys_off, c->B, c->d_grid, c->dsc);
+    }
+    launch_fill_i32(c->d_bin_cnt, c->cap_bins + 1, 0, st);
+    if (N > 0) {
+        BinArgs A{N, x, y, z, c->d_sys_of_atom, c->d_grid, c->d_bin_cnt, c->d_key, c->d_rank,
+                  c->d_img, c->d_xref, c->cap_bins, c->dsc};
+        hipLaunchKernelGGL(k_bin, dim3(div_up(N, 256)), dim3(256), 0, st, A);
+    }
+    launch_scan(c->d_bin_cnt, c->d_bin_start, c->cap_bins + 1, c->d_scan_tmp, nullptr, st);
+    if (N > 0)
+        hipLaunchKernelGGL(k_scatter, dim3(div_up(N, 256)), dim3(256), 0, st, N, c->d_key,
+                           c->d_rank, c->d_bin_start, c->d_sorted);
+    const int fill_blocks = (int)std::min<int64_t>(div_up(c->cap_bins, 256), 2048);
+    hipLaunchKernelGGL(k_bin_sort, dim3(fill_blocks), dim3(256), 0, st, c->d_bin_start,
+                       c->d_sorted, c->cap_bins, c->dsc);
+    const int col_blocks = (int)std::min<int64_t>(div_up(c->cap_cols + 1, 256), 2048);
+    hipLaunchKernelGGL(k_col_count, dim3(col_blocks), dim3(256), 0, st, c->d_grid, c->B,
+                       c->d_bin_start, c->d_col_ncl, c->d_col_ngrp, c->cap_cols, c->G, c->dsc);
+    launch_scan(c->d_col_ncl, c->d_col_cl0, c->cap_cols + 1, c->d_scan_tmp, nullptr, st);
+    launch_scan(c->d_col_ngrp, c->d_col_grp0, c->cap_cols + 1, c->d_scan_tmp, nullptr, st);
+    {
+        ClusterArgs A{x, y, z, type, c->d_grid, c->B, c->d_bin_start, c->d_sorted,
+                      c->d_col_cl0, c->d_col_grp0, c->d_img, c->d_perm, c->d_inv_perm,
+                      c->d_slot_img, c->d_ts, c->d_cl_lo, c->d_cl_hi, c->d_groups,
+                      c->d_sys_grp0, c->cap_clusters, c->G, c->T, c->dsc};
+        const int nb = (int)std::min<int64_t>(div_up(std::max<int64_t>(c->cap_clusters, c->B), 256),
+                                              4096);
+        hipLaunchKernelGGL(k_clusters, dim3(nb), dim3(256), 0, st, A);
+    }
+    {
+        EntryArgs A{c->d_grid, c->d_col_cl0, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
+                    c->E_cap, c->rlist, c->dsc};
+        const int nb = (int)std::min<int64_t>(div_up(c->cap_groups, 4), (int64_t)c->n_cu * 16);
+        hipLaunchKernelGGL(k_group_entries, dim3(std::max(nb, 1)), dim3(256), 0, st, A);
+    }
+    {
+        const double m = c->rlist * (1.0 + 1e-5);
+        ListArgs A{x, y, z, c->d_grid, c->d_groups, c->d_ent, c->d_perm, c->d_slot_img, c->d_ts,
+                   c->d_nb, c->d_cl_nt, c->E_cap, c->nb_cap, c->nb_T, (float)(m * m), c->dsc};
+        const size_t lds = (size_t)(c->E_cap * kCluster + 1) * sizeof(float4) +
+                           (size_t)c->E_cap * sizeof(uint32_t);
+        const int nb = (int)std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * 4);
+        hipLaunchKernelGGL(k_atom_lists, dim3(std::max(nb, 1)), dim3(64 * c->G), lds, st, A);
+    }
+    hipLaunchKernelGGL(k_build_done, dim3(1), dim3(1), 0, st, c->dsc);
+}
+
+__global__ void k_skin_check(DevScalars* d)
+{
+    if (d->need_rebuild) d->flags |= MD_FLAG_SKIN;
+}
+
+void launch_skin_check(Ctx* c, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_skin_check, dim3(1), dim3(1), 0, st, c->dsc);
+}
+
+size_t atom_lists_lds_bytes(int E_cap)
+{
+    return (size_t)(E_cap * kCluster + 1) * sizeof(float4) + (size_t)E_cap * sizeof(uint32_t);
+}
+
+}  // namespace md

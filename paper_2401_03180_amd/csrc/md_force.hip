@@ -1,0 +1,555 @@
+// md_force.hip -- screened pair forces (arXiv 2401.03180, section II.A: Eq. 2
+// Debye-screened Coulomb between integer charges, Eq. 8 Lennard-Jones modulated
+// by the same exp(-r / lambda_D); section II.B: plain truncation at rc).
+//
+// Work decomposition (full neighbour lists, no atomics, deterministic):
+//   * a persistent work-group pulls cluster groups from a queue;
+//   * it stages every candidate atom of the group's table in LDS, converted once to
+//     FP32 coordinates relative to the group's frame origin (FP64 subtraction, one
+//     rounding), with the charge in .w;
+//   * each 64-lane wave owns one 8-atom i-cluster: lane = 8 * i + k walks codes
+//     k, k+8, ... of atom i's compacted list, so all 64 lanes evaluate distinct
+//     pairs; the 8 partial sums of an atom are combined at the end.
+// FP32 path: pair arithmetic in FP32; per-lane sums in FP32 over chunks of 8 terms,
+// folded into a Kahan (sum, compensation) pair; cross-lane combination and the
+// output in FP64.  Membership uses an FP32 distance whose rounding error is
+// bounded; pairs inside the error band are re-decided with the FP64 expression,
+// so the pair set equals the FP64 definition.
+// FP64 path: the plain comparison form, every pair in FP64 from the caller's
+// positions with the exact membership expression.
+#include "md_internal.h"
+#include "md_launch.h"
+
+namespace md {
+
+constexpr float kFarF = 1.0e4f;
+constexpr int kForceBlockMax = 64 * kMaxGroup;
+
+// ------------------------------------------------------------------ repack (per step)
+
+// Gather positions and charges into slot order; reset the force work queue;
+// latch MD_FLAG_SKIN if the lists are stale.
+__global__ void __launch_bounds__(256) k_repack(const double* x, const double* y,
+                                                const double* z, const int8_t* q,
+                                                const int32_t* perm, double* xs, int8_t* qs,
+                                                int64_t cap_slots, DevScalars* dsc)
+{
+    const int64_t n = dsc->n_slots;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i0 == 0) {
+        dsc->work_force = 0u;
+        if (dsc->need_rebuild) atomicOr(&dsc->flags, MD_FLAG_SKIN);
+    }
+    for (int64_t s = i0; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+        const int a = perm[s];
+        if (a >= 0) {
+            xs[s] = x[a];
+            xs[cap_slots + s] = y[a];
+            xs[2 * cap_slots + s] = z[a];
+            qs[s] = q[a];
+        } else {
+            xs[s] = NAN;
+            xs[cap_slots + s] = NAN;
+            xs[2 * cap_slots + s] = NAN;
+            qs[s] = 0;
+        }
+    }
+}
+
+void launch_repack(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
+                   hipStream_t st)
+{
+    const int nb = (int)std::min<int64_t>(div_up(c->cap_slots, 256), (int64_t)c->n_cu * 8);
+    hipLaunchKernelGGL(k_repack, dim3(std::max(nb, 1)), dim3(256), 0, st, x, y, z, q, c->d_perm,
+                       c->d_xs, c->d_qs, c->cap_slots, c->dsc);
+}
+
+// ------------------------------------------------------------------ shared pieces
+
+struct ForceArgs {
+    const Group* groups;
+    const uint32_t* ent;
+    const uint16_t* nb;
+    const int32_t* cl_nt;
+    const int32_t* perm;
+    const int32_t* slot_img;
+    const double* xs;            // slot-order FP64 positions (SoA, stride cap_slots)
+    const int8_t* qs;
+    const uint8_t* ts;
+    const GridSys* grid;
+    const double* kappa;         // B * S1
+    int64_t S1;
+    const float* lj32;           // T*T (c6, c12)
+    const double* c6;
+    const double* c12;
+    int T;
+    double rc2;                  // rc * rc (FP64, rounded once)
+    int E_cap, nb_T;
+    int64_t cap_slots;
+    double *fx, *fy, *fz;
+    double* grp_epot;
+    double* epot;
+    const int32_t* sys_grp0;
+    int B;
+    DevScalars* dsc;
+    int2* emit;
+    int64_t emit_max;
+};
+
+// Sum of grp_epot over each system's groups in a fixed order (deterministic),
+// executed by the last work-group to finish.
+__device__ void finalize_epot(const ForceArgs& A, double* s_red)
+{
+    for (int b = 0; b < A.B; ++b) {
+        const int g0 = A.sys_grp0[b], g1 = A.sys_grp0[b + 1];
+        double t = 0.0;
+        for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x)
+            t += __hip_atomic_load(&A.grp_epot[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += s_red[w];
+            A.epot[b] = s;
+        }
+    }
+}
+
+// Completion ticket; returns true in every thread of the last work-group.
+__device__ bool last_group_done(uint32_t* ticket, int* s_flag)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned t = atomicAdd(ticket, 1u);
+        *s_flag = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    const bool last = *s_flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* gbl(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
+__device__ inline int64_t slot_of_code(const uint32_t* ent_g, uint32_t idx)
+{
+    const uint32_t en = ent_g[idx >> 3];
+    return (int64_t)(en & kEntClusterMask) * kCluster + (idx & 7u);
+}
+
+// FP64 re-decision of one pair (rare path of the FP32 kernel).
+__device__ __noinline__ int recheck_pair(const uint32_t* ent_g, const double* xs, int64_t cs,
+                                         int64_t slot_i, uint32_t idx, const GridSys* gsp,
+                                         double rc2)
+{
+    const int64_t slot_j = slot_of_code(ent_g, idx);
+    const GridSys gs = *gsp;
+    const double r2 = pair_r2_exact(xs[slot_i], xs[cs + slot_i], xs[2 * cs + slot_i], xs[slot_j],
+                                    xs[cs + slot_j], xs[2 * cs + slot_j], gs);
+    return r2 < rc2 ? 1 : 0;
+}
+
+__device__ __noinline__ void emit_pair(const uint32_t* ent_g, const int32_t* perm, int ai,
+                                       uint32_t idx, unsigned long long* counter, int2* out,
+                                       int64_t max)
+{
+    const int64_t slot_j = slot_of_code(ent_g, idx);
+    const int aj = perm[slot_j];
+    if (ai < aj) {
+        const unsigned long long p = atomicAdd(counter, 1ull);
+        if ((int64_t)p < max) out[p] = make_int2(ai, aj);
+    }
+}
+
+// Step counter clamped to the bound schedule (MD_FLAG_STEP latched otherwise).
+__device__ inline int64_t clamp_step(const ForceArgs& A)
+{
+    int64_t s = A.dsc->step;
+    if (s < 0 || s >= A.S1) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&A.dsc->flags, MD_FLAG_STEP);
+        s = s < 0 ? 0 : A.S1 - 1;
+    }
+    return s;
+}
+
+__device__ inline void kahan_add(float& s, float& c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Combine the 8 lanes of one atom (lanes 8i .. 8i+7) in FP64.
+__device__ inline double reduce8(double v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ FP32 kernel
+
+template <bool ENERGY, bool EMIT, bool SCREEN_LJ>
+__global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
+{
+    extern __shared__ float4 s_j[];
+    __shared__ float2 s_lj[MD_MAX_TYPES * MD_MAX_TYPES];
+    __shared__ float s_m[kMaxGroup];
+    __shared__ double s_e[kMaxGroup];
+    __shared__ int s_g, s_flag;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    const int64_t step = clamp_step(A);
+    const int ngroups = A.dsc->n_groups;
+    for (int i = tid; i < A.T * A.T; i += blockDim.x)
+        s_lj[i] = make_float2(A.lj32[2 * i], A.lj32[2 * i + 1]);
+    const int sentinel = A.E_cap * kCluster;
+    if (tid == 0) s_j[sentinel] = make_float4(kFarF, kFarF, kFarF, 0.0f);
+    const float rc2f = (float)A.rc2;
+    const int64_t cs = A.cap_slots;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_g = (int)atomicAdd(&A.dsc->work_force, 1u);
+        __syncthreads();
+        const int g = s_g;
+        if (g >= ngroups) break;
+        const Group gr = A.groups[g];
+        const GridSys gs = A.grid[gr.sys];
+        const double kap = A.kappa[(int64_t)gr.sys * A.S1 + step];
+
+        // ---- stage the candidate atoms in the group frame
+        float m = 0.0f;
+        const int nst = gr.nent * kCluster;
+        for (int idx = tid; idx < nst; idx += blockDim.x) {
+            const uint32_t en = A.ent[(int64_t)g * A.E_cap + (idx >> 3)];
+            const int64_t slot = (int64_t)(en & kEntClusterMask) * kCluster + (idx & 7);
+            const int a = A.perm[slot];
+            float4 v = make_float4(kFarF, kFarF, kFarF, 0.0f);
+            if (a >= 0) {
+                const int32_t im = A.slot_img[slot];
+                const int sh[3] = {(int)((en >> 26) & 3u) - 1, (int)((en >> 28) & 3u) - 1,
+                                   (int)((en >> 30) & 3u) - 1};
+                float r[3];
+                for (int d = 0; d < 3; ++d) {
+                    double p = A.xs[d * cs + slot];
+                    if (gs.periodic) p = p - (double)(unpack_img(im, d) - sh[d]) * gs.L[d];
+                    r[d] = (float)(p - gr.c[d]);
+                    m = fmaxf(m, fabsf(r[d]));
+                }
+                v = make_float4(r[0], r[1], r[2], (float)A.qs[slot]);
+            }
+            s_j[idx] = v;
+        }
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+        if (lane == 0) s_m[w] = m;
+        __syncthreads();
+        m = s_m[0];
+        for (int k = 1; k < nw; ++k) m = fmaxf(m, s_m[k]);
+        // Rounding bound of the FP32 r^2 near the cutoff: each staged coordinate
+        // carries <= u|x| error (u = 2^-24), so |d32 - d| <= u (2m + |d|) per axis and
+        // |r2_32 - r2| <= 2 sqrt(3) rc u (2m + rc) + 3 u rc^2; doubled for margin.
+        const float u = 5.9604645e-8f;
+        const float rcf = sqrtf(rc2f);
+        const float band = 2.0f * (3.4641016f * rcf * u * (2.0f * m + rcf) + 3.0f * u * rc2f) +
+                           1e-12f;
+        const float lo2 = rc2f - band;
+
+        double e_w = 0.0;
+        if (w < gr.ncl) {
+            const int I = gr.cl0 + w;
+            const int il = lane >> 3;
+            const int64_t slot_i = (int64_t)I * kCluster + il;
+            const int ai = A.perm[slot_i];
+            float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f;
+            int tb = 0;
+            if (ai >= 0) {
+                const int32_t im = A.slot_img[slot_i];
+                float r[3];
+                for (int d = 0; d < 3; ++d) {
+                    double p = A.xs[d * cs + slot_i];
+                    if (gs.periodic) p = p - (double)unpack_img(im, d) * gs.L[d];
+                    r[d] = (float)(p - gr.c[d]);
+                }
+                xi = r[0]; yi = r[1]; zi = r[2];
+                qike = (float)(kKe * (double)A.qs[slot_i]);
+                tb = A.ts[slot_i] * A.T;
+            }
+            const float kapf = (float)kap;
+            const float nkl2 = (float)(-kap * 1.4426950408889634);   // -kappa log2(e)
+            const int nt = A.cl_nt[I];
+            const auto cp = gbl(A.nb + (int64_t)I * A.nb_T * 64 + lane);
+            const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
+            const GridSys* gsp = A.grid + gr.sys;
+            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            double eacc = 0.0;
+            uint32_t code_next = nt > 0 ? (uint32_t)cp[0] : (uint32_t)sentinel;
+            for (int t = 0; t < nt; ++t) {
+                const uint32_t code = code_next;
+                if (t + 1 < nt) code_next = cp[(t + 1) * 64];
+                const uint32_t idx = code & kCodeIdxMask;
+                const int tj = (int)(code >> kCodeIdxBits);
+                const float4 pj = s_j[idx];
+                const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                bool in = r2 < lo2;
+                const bool amb = fabsf(r2 - rc2f) <= band;
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(amb) != 0ull, 0)) {
+                    if (amb) in = recheck_pair(ent_g, A.xs, cs, slot_i, idx, gsp, A.rc2) != 0;
+                }
+                if (EMIT) {
+                    if (in) emit_pair(ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit,
+                                      A.emit_max);
+                }
+                const float rinv = in ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+                const float r = r2 * rinv;
+                const float s = __builtin_amdgcn_exp2f(r * nkl2);
+                const float rinv2 = rinv * rinv;
+                const float rinv6 = rinv2 * rinv2 * rinv2;
+                const float uc = qike * pj.w * rinv;
+                const float2 lj = s_lj[tb + tj];
+                const float l6 = lj.x * rinv6;
+                const float l12 = lj.y * rinv6 * rinv6;
+                const float kr = r * kapf;
+                float f, e;
+                if (SCREEN_LJ) {
+                    const float uu = uc + (l12 - l6);
+                    const float wv = fmaf(-6.0f, l6, fmaf(12.0f, l12, uc));
+                    f = fmaf(uu, kr, wv) * s * rinv2;
+                    e = uu * s;
+                } else {
+                    const float wl = fmaf(-6.0f, l6, 12.0f * l12);
+                    f = fmaf(uc * s, 1.0f + kr, wl) * rinv2;
+                    e = fmaf(uc, s, l12 - l6);
+                }
+                ax = fmaf(f, dx, ax);
+                ay = fmaf(f, dy, ay);
+                az = fmaf(f, dz, az);
+                if (ENERGY) eacc += (double)e;
+                if ((t & 7) == 7) {
+                    kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
+                    ax = ay = az = 0.0f;
+                }
+            }
+            kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
+            // true per-lane sum = s - c; combine the atom's 8 lanes in FP64
+            const double Fx = reduce8((double)sx - (double)cx);
+            const double Fy = reduce8((double)sy - (double)cy);
+            const double Fz = reduce8((double)sz - (double)cz);
+            if ((lane & 7) == 0 && ai >= 0) {
+                A.fx[ai] = Fx;
+                A.fy[ai] = Fy;
+                A.fz[ai] = Fz;
+            }
+            if (ENERGY) {
+                for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
+                e_w = 0.5 * eacc;     // each pair is visited from both atoms
+            }
+        }
+        if (ENERGY) {
+            if (lane == 0) s_e[w] = e_w;
+            __syncthreads();
+            if (tid == 0) {
+                double t = 0.0;
+                for (int k = 0; k < nw; ++k) t += s_e[k];
+                A.grp_epot[g] = t;
+            }
+        }
+    }
+    if (ENERGY) {
+        if (last_group_done(&A.dsc->ticket_force, &s_flag)) {
+            __shared__ double s_red[kMaxGroup];
+            finalize_epot(A, s_red);
+            if (tid == 0) A.dsc->ticket_force = 0u;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ FP64 kernel
+
+template <bool ENERGY, bool EMIT, bool SCREEN_LJ>
+__global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
+{
+    __shared__ double s_e[kMaxGroup];
+    __shared__ int s_g, s_flag;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    const int64_t step = clamp_step(A);
+    const int ngroups = A.dsc->n_groups;
+    const uint32_t sentinel = (uint32_t)(A.E_cap * kCluster);
+    const int64_t cs = A.cap_slots;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_g = (int)atomicAdd(&A.dsc->work_force, 1u);
+        __syncthreads();
+        const int g = s_g;
+        if (g >= ngroups) break;
+        const Group gr = A.groups[g];
+        const GridSys gs = A.grid[gr.sys];
+        const double kap = A.kappa[(int64_t)gr.sys * A.S1 + step];
+        double e_w = 0.0;
+        if (w < gr.ncl) {
+            const int I = gr.cl0 + w;
+            const int il = lane >> 3;
+            const int64_t slot_i = (int64_t)I * kCluster + il;
+            const int ai = A.perm[slot_i];
+            double xi = 0.0, yi = 0.0, zi = 0.0, qi = 0.0;
+            int ti = 0;
+            if (ai >= 0) {
+                xi = A.xs[slot_i]; yi = A.xs[cs + slot_i]; zi = A.xs[2 * cs + slot_i];
+                qi = kKe * (double)A.qs[slot_i];
+                ti = A.ts[slot_i];
+            }
+            const int nt = A.cl_nt[I];
+            const auto cp = gbl(A.nb + (int64_t)I * A.nb_T * 64 + lane);
+            const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
+            double Fx = 0.0, Fy = 0.0, Fz = 0.0, eacc = 0.0;
+            for (int t = 0; t < nt; ++t) {
+                const uint32_t code = cp[t * 64];
+                const uint32_t idx = code & kCodeIdxMask;
+                if (idx == sentinel || ai < 0) continue;
+                const int64_t slot_j = slot_of_code(ent_g, idx);
+                const double xj = A.xs[slot_j], yj = A.xs[cs + slot_j], zj = A.xs[2 * cs + slot_j];
+                double dx, dy, dz, r2;
+                {
+#pragma clang fp contract(off)
+                    dx = xi - xj;
+                    dy = yi - yj;
+                    dz = zi - zj;
+                    if (gs.periodic) {
+                        dx = dx - gs.L[0] * rint(dx * gs.invL[0]);
+                        dy = dy - gs.L[1] * rint(dy * gs.invL[1]);
+                        dz = dz - gs.L[2] * rint(dz * gs.invL[2]);
+                    }
+                    r2 = dx * dx + dy * dy;
+                    r2 = r2 + dz * dz;
+                }
+                if (!(r2 < A.rc2)) continue;
+                if (EMIT)
+                    emit_pair(ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit, A.emit_max);
+                const int tj = (int)(code >> kCodeIdxBits);
+                const double c6 = A.c6[ti * A.T + tj], c12 = A.c12[ti * A.T + tj];
+                const double r = sqrt(r2);
+                const double rinv2 = 1.0 / r2;
+                const double rinv6 = rinv2 * rinv2 * rinv2;
+                const double s = exp(-kap * r);
+                const double uc = qi * (double)A.qs[slot_j] / r;
+                const double l12 = c12 * rinv6 * rinv6, l6 = c6 * rinv6;
+                double f, e;
+                if (SCREEN_LJ) {
+                    const double uu = uc + (l12 - l6);
+                    f = ((uc + 12.0 * l12 - 6.0 * l6) + uu * (kap * r)) * s * rinv2;
+                    e = uu * s;
+                } else {
+                    f = (uc + uc * (kap * r)) * s * rinv2 + (12.0 * l12 - 6.0 * l6) * rinv2;
+                    e = uc * s + (l12 - l6);
+                }
+                Fx += f * dx;
+                Fy += f * dy;
+                Fz += f * dz;
+                if (ENERGY) eacc += e;
+            }
+            Fx = reduce8(Fx);
+            Fy = reduce8(Fy);
+            Fz = reduce8(Fz);
+            if ((lane & 7) == 0 && ai >= 0) {
+                A.fx[ai] = Fx;
+                A.fy[ai] = Fy;
+                A.fz[ai] = Fz;
+            }
+            if (ENERGY) {
+                for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
+                e_w = 0.5 * eacc;
+            }
+        }
+        if (ENERGY) {
+            if (lane == 0) s_e[w] = e_w;
+            __syncthreads();
+            if (tid == 0) {
+                double t = 0.0;
+                for (int k = 0; k < nw; ++k) t += s_e[k];
+                A.grp_epot[g] = t;
+            }
+        }
+    }
+    if (ENERGY) {
+        if (last_group_done(&A.dsc->ticket_force, &s_flag)) {
+            __shared__ double s_red[kMaxGroup];
+            finalize_epot(A, s_red);
+            if (tid == 0) A.dsc->ticket_force = 0u;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+size_t force32_lds_bytes(int E_cap) { return (size_t)(E_cap * kCluster + 1) * sizeof(float4); }
+
+template <bool E, bool M, bool S>
+static void set_lds_attr(size_t lds)
+{
+    (void)hipFuncSetAttribute((const void*)k_force32<E, M, S>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t force_kernel_setup(Ctx* c)
+{
+    const size_t lds = force32_lds_bytes(c->E_cap);
+    set_lds_attr<false, false, false>(lds); set_lds_attr<false, false, true>(lds);
+    set_lds_attr<true, false, false>(lds);  set_lds_attr<true, false, true>(lds);
+    set_lds_attr<false, true, false>(lds);  set_lds_attr<false, true, true>(lds);
+    set_lds_attr<true, true, false>(lds);   set_lds_attr<true, true, true>(lds);
+    return hipGetLastError();
+}
+
+template <bool E, bool M, bool S>
+static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks, hipStream_t st)
+{
+    const dim3 blk(64 * c->G);
+    if (prec == MD_FP32_KAHAN)
+        hipLaunchKernelGGL((k_force32<E, M, S>), dim3(blocks), blk, force32_lds_bytes(c->E_cap), st,
+                           A);
+    else
+        hipLaunchKernelGGL((k_force64<E, M, S>), dim3(blocks), blk, 0, st, A);
+}
+
+hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, double* fz,
+                         double* epot, int2* emit, int64_t emit_max, hipStream_t st)
+{
+    ForceArgs A;
+    A.groups = c->d_groups; A.ent = c->d_ent; A.nb = c->d_nb; A.cl_nt = c->d_cl_nt;
+    A.perm = c->d_perm; A.slot_img = c->d_slot_img; A.xs = c->d_xs; A.qs = c->d_qs; A.ts = c->d_ts;
+    A.grid = c->d_grid; A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
+    A.lj32 = c->d_lj32; A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T;
+    A.rc2 = c->cfg.rc * c->cfg.rc;
+    A.E_cap = c->E_cap; A.nb_T = c->nb_T; A.cap_slots = c->cap_slots;
+    A.fx = fx; A.fy = fy; A.fz = fz;
+    A.grp_epot = c->d_grp_epot; A.epot = epot; A.sys_grp0 = c->d_sys_grp0; A.B = c->B;
+    A.dsc = c->dsc; A.emit = emit; A.emit_max = emit_max;
+    // persistent grid: enough work-groups to fill every CU a few times over
+    const int per_cu = prec == MD_FP32_KAHAN
+                           ? std::max<int>(1, (int)(c->max_lds / std::max<size_t>(
+                                                        force32_lds_bytes(c->E_cap), 1)))
+                           : 4;
+    const int blocks = (int)std::max<int64_t>(
+        1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * std::min(per_cu, 8)));
+    const bool E = epot != nullptr, M = emit != nullptr, S = c->cfg.screen_lj != 0;
+    if (E) {
+        if (M) { if (S) launch_one<true, true, true>(c, prec, A, blocks, st); else launch_one<true, true, false>(c, prec, A, blocks, st); }
+        else   { if (S) launch_one<true, false, true>(c, prec, A, blocks, st); else launch_one<true, false, false>(c, prec, A, blocks, st); }
+    } else {
+        if (M) { if (S) launch_one<false, true, true>(c, prec, A, blocks, st); else launch_one<false, true, false>(c, prec, A, blocks, st); }
+        else   { if (S) launch_one<false, false, true>(c, prec, A, blocks, st); else launch_one<false, false, false>(c, prec, A, blocks, st); }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace md

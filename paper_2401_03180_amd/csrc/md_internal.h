@@ -1,0 +1,186 @@
+// md_internal.h -- context layout, constants and device helpers shared by the
+// library's translation units (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "md.h"
+
+namespace md {
+
+// Coulomb constant 1/(4 pi eps0) in kJ mol^-1 nm e^-2 (CODATA 2018 e, N_A, eps0).
+constexpr double kKe = 138.935457644382;
+
+constexpr int kCluster = 8;          // atoms per cluster (one i-cluster per 64-lane wave)
+constexpr int kWave = 64;
+constexpr int kMaxGroup = 8;         // i-clusters per force work-group
+constexpr int kCodeIdxBits = 13;     // neighbour code: staged-atom index | type << 13
+constexpr uint32_t kCodeIdxMask = (1u << kCodeIdxBits) - 1u;
+constexpr int kMaxGroupEntries = (1 << kCodeIdxBits) / kCluster - 1;   // 1023
+constexpr uint32_t kEntClusterMask = (1u << 26) - 1u;                  // group entry: J | shift << 26
+constexpr int kScanBlock = 1024;
+constexpr int kScanPerThread = 4;
+constexpr int kScanTile = kScanBlock * kScanPerThread;
+
+// Per-system grid used to bin atoms into columns (x, y) and fine z bins.
+struct GridSys {
+    double origin[3];
+    double w[3];        // column widths in x, y; z-bin width in z
+    double inv_w[3];
+    double L[3];        // periodic box lengths (0 when vacuum)
+    double invL[3];
+    int32_t n[3];       // columns in x, y; bins in z
+    int32_t col_off;    // first global column of this system
+    int32_t bin_off;    // first global bin
+    int32_t periodic;
+};
+
+// A work-group's set of i-clusters: consecutive clusters of one column.
+struct Group {
+    double lo[3], hi[3];    // bounding box of its atoms at build time (wrapped frame)
+    double c[3];            // frame origin (box centre)
+    int32_t cl0, ncl;       // first cluster, number of clusters (<= cluster_group)
+    int32_t sys;
+    int32_t nent;           // candidate (cluster, shift) entries
+};
+
+// Device-resident scalars (one allocation).
+struct DevScalars {
+    int64_t step;               // index of the latest force evaluation
+    uint32_t flags;             // MD_FLAG_* error word
+    int32_t need_rebuild;       // set when a displacement exceeds skin/2
+    unsigned long long disp2_bits;  // max squared displacement since build (double bits)
+    int32_t n_cols, n_bins, n_clusters, n_groups;
+    int32_t n_slots;
+    int32_t max_entries;        // largest group entry count of the last build
+    int32_t max_list;           // largest per-atom list length of the last build
+    int64_t n_codes;            // total list codes of the last build
+    int64_t n_builds;
+    uint32_t work_force;        // work-queue counter of the force kernel
+    uint32_t ticket_force;      // completion ticket of the force kernel
+    uint32_t ticket_vv;         // completion ticket of the integrator
+    uint32_t ticket_build;      // completion ticket of the list kernel
+    unsigned long long pair_count;  // debug pair export counter
+};
+
+struct Ctx {
+    md_config cfg;
+    int B = 0;
+    int64_t N = 0;
+    std::string err;
+    bool tables_bound = false;
+    bool built = false;
+    int device = 0;
+    int n_cu = 0;
+    size_t max_lds = 65536;
+
+    // host copies
+    std::vector<int64_t> sys_off;
+    std::vector<double> box;       // B*3 (periodic)
+    int64_t n_steps = 0;
+    int32_t T = 0, E = 0, Q = 0;
+    int32_t G = 4;                 // i-clusters per group
+    int32_t E_cap = 0;             // entries per group
+    int32_t nb_cap = 0;            // per-atom list capacity (multiple of 8)
+    int32_t nb_T = 0;              // nb_cap / 8
+    double rlist = 0.0;            // rc + skin
+
+    // capacities
+    int64_t cap_cols = 0, cap_bins = 0, cap_clusters = 0, cap_slots = 0, cap_groups = 0;
+    int64_t cap_partials = 0;
+
+    // device buffers
+    DevScalars* dsc = nullptr;
+    int64_t* d_sys_off = nullptr;        // B+1
+    int32_t* d_sys_of_atom = nullptr;    // N
+    GridSys* d_grid = nullptr;           // B
+    double* d_sys_lo = nullptr;          // B*3 (vacuum bounding boxes)
+    double* d_sys_hi = nullptr;
+    int32_t* d_sys_grp0 = nullptr;       // B+1 first group per system
+    // tables
+    double* d_c6 = nullptr;   double* d_c12 = nullptr;     // T*T
+    float* d_lj32 = nullptr;                               // T*T*2 (c6, c12) float
+    int8_t* d_qmax = nullptr;                              // E
+    double* d_kappa = nullptr;                             // B*(S+1)
+    double* d_base = nullptr;                              // E*Q
+    double* d_g = nullptr;                                 // B*(S+1)
+    uint64_t* d_seeds = nullptr;                           // B
+    // binning
+    int32_t* d_key = nullptr;      // N bin of each atom
+    int32_t* d_rank = nullptr;     // N rank inside the bin
+    int32_t* d_img = nullptr;      // N packed periodic image of each atom at build
+    int32_t* d_bin_cnt = nullptr;  // cap_bins + 1
+    int32_t* d_bin_start = nullptr;// cap_bins + 1
+    int32_t* d_sorted = nullptr;   // N atoms in bin order
+    int32_t* d_scan_tmp = nullptr; // block sums for the scans
+    // columns
+    int32_t* d_col_ncl = nullptr;  int32_t* d_col_ngrp = nullptr;      // cap_cols + 1
+    int32_t* d_col_cl0 = nullptr;  int32_t* d_col_grp0 = nullptr;      // cap_cols + 1
+    // clusters / slots
+    double* d_cl_lo = nullptr;     double* d_cl_hi = nullptr;          // cap_clusters*3
+    int32_t* d_cl_nt = nullptr;                                        // cap_clusters
+    int32_t* d_perm = nullptr;     // cap_slots: caller atom of each slot (-1 = padding)
+    int32_t* d_slot_img = nullptr; // cap_slots: packed image of the slot's atom
+    int32_t* d_inv_perm = nullptr; // N
+    double* d_xs = nullptr;        // cap_slots*3 positions in slot order (SoA x|y|z)
+    int8_t* d_qs = nullptr;        // cap_slots charges in slot order
+    uint8_t* d_ts = nullptr;       // cap_slots types in slot order (build time)
+    // groups and lists
+    Group* d_groups = nullptr;     // cap_groups
+    uint32_t* d_ent = nullptr;     // cap_groups * E_cap
+    uint16_t* d_nb = nullptr;      // cap_clusters * nb_T * 64
+    double* d_grp_epot = nullptr;  // cap_groups
+    // integrator
+    double* d_xref = nullptr;      // N*3 build positions
+    double* d_partial = nullptr;   // cap_partials (kinetic-energy block partials)
+    int build_calls_since = 0;
+    int nstlist = 10;
+    int64_t host_builds = 0;
+};
+
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- device helpers
+
+// Packed periodic image (kx, ky, kz), 10 signed bits each.
+__host__ __device__ inline int32_t pack_img(int kx, int ky, int kz)
+{
+    return ((kx & 1023) << 20) | ((ky & 1023) << 10) | (kz & 1023);
+}
+__host__ __device__ inline int unpack_img(int32_t v, int axis)
+{
+    int s = (axis == 0) ? 20 : (axis == 1 ? 10 : 0);
+    int t = (v >> s) & 1023;
+    return (t & 512) ? t - 1024 : t;
+}
+
+__device__ inline void set_flag(DevScalars* d, uint32_t f)
+{
+    atomicOr(&d->flags, f);
+}
+
+// Minimum-image squared distance with every operation a separately rounded FP64
+// operation in this order (no contraction): d = a - b; d -= L rint(d * (1/L));
+// r2 = (dx*dx + dy*dy) + dz*dz.  This is the membership test of the pair set.
+__device__ inline double pair_r2_exact(double xi, double yi, double zi, double xj, double yj,
+                                       double zj, const GridSys& g)
+{
+#pragma clang fp contract(off)
+    double dx = xi - xj;
+    double dy = yi - yj;
+    double dz = zi - zj;
+    if (g.periodic) {
+        dx = dx - g.L[0] * rint(dx * g.invL[0]);
+        dy = dy - g.L[1] * rint(dy * g.invL[1]);
+        dz = dz - g.L[2] * rint(dz * g.invL[2]);
+    }
+    double r2 = dx * dx + dy * dy;
+    r2 = r2 + dz * dz;
+    return r2;
+}
+
+}  // namespace md

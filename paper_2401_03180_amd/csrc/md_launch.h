@@ -1,0 +1,34 @@
+// md_launch.h -- host-side launchers implemented in the kernel translation units.
+#pragma once
+
+#include "md_internal.h"
+
+namespace md {
+
+// md_step.hip
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+void launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, const int32_t* gate,
+                 hipStream_t st);
+void launch_ionize(Ctx* c, const uint8_t* elem, const uint32_t* atom_id, int8_t* q,
+                   hipStream_t st);
+void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const double* fx,
+               const double* fy, const double* fz, double* x, double* y, double* z, double* vx,
+               double* vy, double* vz, double* ekin, hipStream_t st);
+int64_t vv_partials_needed(int64_t N, int B);
+void launch_set_step(Ctx* c, int64_t step, hipStream_t st);
+void launch_clear_flags(Ctx* c, hipStream_t st);
+
+// md_build.hip
+void launch_build(Ctx* c, const double* x, const double* y, const double* z, const uint8_t* type,
+                  hipStream_t st);
+void launch_skin_check(Ctx* c, hipStream_t st);
+
+// md_force.hip
+void launch_repack(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
+                   hipStream_t st);
+hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, double* fz,
+                         double* epot, int2* emit, int64_t emit_max, hipStream_t st);
+size_t force32_lds_bytes(int E_cap);
+hipError_t force_kernel_setup(Ctx* c);
+
+}  // namespace md

@@ -1,0 +1,325 @@
+// md_step.hip -- element-wise per-step kernels: ionization, velocity Verlet,
+// slot repacking, and the generic scan / fill utilities used by the build.
+#include "md_internal.h"
+#include "md_launch.h"
+
+namespace md {
+
+// ------------------------------------------------------------------ utilities
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    int blocks = (int)std::min<int64_t>(div_up(n, 256), 4096);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, st, p, n, v);
+}
+
+// Exclusive prefix sum within a block of kScanBlock threads, kScanPerThread values
+// per thread.  Returns the block total.
+__device__ int block_scan_exclusive(int (&v)[kScanPerThread], int* s_warp)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int t = 0;
+    for (int k = 0; k < kScanPerThread; ++k) { int x = v[k]; v[k] = t; t += x; }
+    // inclusive scan of per-thread totals across the wave
+    int inc = t;
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_warp[wv] = inc;
+    __syncthreads();
+    if (wv == 0) {
+        int nw = blockDim.x >> 6;
+        int x = lane < nw ? s_warp[lane] : 0;
+        int xi = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            int y = __shfl_up(xi, off, 64);
+            if (lane >= off) xi += y;
+        }
+        if (lane < nw) s_warp[lane] = xi - x;       // exclusive wave offsets
+        if (lane == nw - 1) s_warp[64] = xi;         // block total
+    }
+    __syncthreads();
+    int base = s_warp[wv] + (inc - t);
+    for (int k = 0; k < kScanPerThread; ++k) v[k] += base;
+    int total = s_warp[64];
+    __syncthreads();
+    return total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_local(const int32_t* in, int32_t* out,
+                                                           int64_t n, int32_t* block_sums,
+                                                           const int32_t* gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ int s_warp[65];
+    int v[kScanPerThread];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
+    for (int k = 0; k < kScanPerThread; ++k) v[k] = (base + k < n) ? in[base + k] : 0;
+    int total = block_scan_exclusive(v, s_warp);
+    for (int k = 0; k < kScanPerThread; ++k)
+        if (base + k < n) out[base + k] = v[k];
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_sums(int32_t* block_sums, int nb,
+                                                          const int32_t* gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ int s_warp[65];
+    int v[kScanPerThread];
+    int base = threadIdx.x * kScanPerThread;
+    for (int k = 0; k < kScanPerThread; ++k) v[k] = (base + k < nb) ? block_sums[base + k] : 0;
+    block_scan_exclusive(v, s_warp);
+    for (int k = 0; k < kScanPerThread; ++k)
+        if (base + k < nb) block_sums[base + k] = v[k];
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_add(int32_t* out, int64_t n,
+                                                         const int32_t* block_sums,
+                                                         const int32_t* gate)
+{
+    if (gate && *gate == 0) return;
+    int add = block_sums[blockIdx.x];
+    if (add == 0) return;
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
+    for (int k = 0; k < kScanPerThread; ++k)
+        if (base + k < n) out[base + k] += add;
+}
+
+// Exclusive scan of in[0..n) into out[0..n).  n <= kScanTile^2.  `gate` (device
+// int, may be NULL): the kernels do nothing when *gate == 0.
+void launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, const int32_t* gate,
+                 hipStream_t st)
+{
+    if (n <= 0) return;
+    int nb = (int)div_up(n, kScanTile);
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, st, in, out, n, tmp, gate);
+    if (nb > 1) {
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, tmp, nb, gate);
+        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, st, out, n, tmp, gate);
+    }
+}
+
+// ------------------------------------------------------------------ Philox4x32-10
+
+// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten rounds of
+// two 32x32->64 multiplications with the round key bumped by the Weyl constants
+// between rounds.  Returns word 0 of the output block.
+__device__ inline uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
+        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
+        const uint32_t n0 = hiB ^ c1 ^ k0;
+        const uint32_t n2 = hiA ^ c3 ^ k1;
+        c0 = n0; c1 = loB; c2 = n2; c3 = loA;
+        k0 += kWeylA; k1 += kWeylB;
+    }
+    return c0;
+}
+
+// ------------------------------------------------------------------ ionization
+
+__global__ void __launch_bounds__(256) k_ionize(int64_t N, const int32_t* sys_of_atom,
+                                                const uint8_t* elem, const uint32_t* atom_id,
+                                                int8_t* q, const int8_t* qmax, const double* base,
+                                                int32_t E, int32_t Q, const double* g, int64_t S1,
+                                                const uint64_t* seeds, DevScalars* dsc)
+{
+    const int64_t s = dsc->step;
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    if (s < 1 || s >= S1) {
+        if (a == 0) set_flag(dsc, MD_FLAG_STEP);
+        return;
+    }
+    const int e = elem[a];
+    const int qa = q[a];
+    if (e >= E || qa < 0 || qa >= Q) {
+        set_flag(dsc, MD_FLAG_BAD_INPUT);
+        return;
+    }
+    if (qa >= qmax[e]) return;
+    const int b = sys_of_atom[a];
+    double p = base[e * Q + qa] * g[b * S1 + s];
+    p = p > 1.0 ? 1.0 : p;
+    const uint64_t thresh = (uint64_t)floor(p * 4294967296.0);
+    const uint64_t seed = seeds[b];
+    const uint32_t u = philox_word0(atom_id[a], (uint32_t)s, (uint32_t)b, 0u, (uint32_t)seed,
+                                    (uint32_t)(seed >> 32));
+    if ((uint64_t)u < thresh) q[a] = (int8_t)(qa + 1);
+}
+
+void launch_ionize(Ctx* c, const uint8_t* elem, const uint32_t* atom_id, int8_t* q,
+                   hipStream_t st)
+{
+    if (c->N == 0) return;
+    hipLaunchKernelGGL(k_ionize, dim3(div_up(c->N, 256)), dim3(256), 0, st, c->N,
+                       c->d_sys_of_atom, elem, atom_id, q, c->d_qmax, c->d_base, c->E, c->Q, c->d_g,
+                       c->n_steps + 1, c->d_seeds, c->dsc);
+}
+
+// ------------------------------------------------------------------ velocity Verlet
+
+constexpr int kVvBlock = 256;
+
+struct VvArgs {
+    int64_t N;
+    double dt, hdt, thr2;
+    const double* inv_mass;
+    const double *fx, *fy, *fz;
+    double *x, *y, *z, *vx, *vy, *vz;
+    const double* xref;          // N*3 build positions
+    double* partial;             // nblocks + B
+    double* ekin;
+    const int64_t* sys_off;
+    const int32_t* sys_of_atom;
+    int B;
+    DevScalars* dsc;
+};
+
+__device__ double block_sum_d(double v, double* s)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) s[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += s[k];
+    return t;   // valid in thread 0
+}
+
+template <int PHASE, bool EKIN>
+__global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A)
+{
+#pragma clang fp contract(off)
+    __shared__ double s_red[kVvBlock / 64];
+    __shared__ int s_last;
+    const int64_t a = blockIdx.x * (int64_t)kVvBlock + threadIdx.x;
+    double d2 = 0.0, ke = 0.0;
+    if (a < A.N) {
+        const double h = A.hdt * A.inv_mass[a];
+        double vx = A.vx[a] + h * A.fx[a];
+        double vy = A.vy[a] + h * A.fy[a];
+        double vz = A.vz[a] + h * A.fz[a];
+        A.vx[a] = vx; A.vy[a] = vy; A.vz[a] = vz;
+        if (PHASE == 0) {
+            const double x = A.x[a] + A.dt * vx;
+            const double y = A.y[a] + A.dt * vy;
+            const double z = A.z[a] + A.dt * vz;
+            A.x[a] = x; A.y[a] = y; A.z[a] = z;
+            const double ex = x - A.xref[a], ey = y - A.xref[A.N + a], ez = z - A.xref[2 * A.N + a];
+            d2 = ex * ex + ey * ey + ez * ez;
+        } else if (EKIN) {
+            double v2 = vx * vx + vy * vy;
+            v2 = v2 + vz * vz;
+            ke = 0.5 * v2 / A.inv_mass[a];
+        }
+    }
+    if (PHASE == 0) {
+        for (int off = 32; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, 64));
+        if ((threadIdx.x & 63) == 0 && d2 > 0.0) {
+            atomicMax(&A.dsc->disp2_bits, (unsigned long long)__double_as_longlong(d2));
+            if (d2 > A.thr2) atomicExch(&A.dsc->need_rebuild, 1);
+        }
+    }
+    if (PHASE == 1 && EKIN) {
+        // per-system partial of this block, stored at index block + system
+        const int64_t a0 = (int64_t)blockIdx.x * kVvBlock;
+        const int64_t a1 = min(A.N, a0 + kVvBlock) - 1;
+        const int b0 = A.sys_of_atom[a0], b1 = A.sys_of_atom[a1];
+        const int myb = a < A.N ? A.sys_of_atom[a] : -1;
+        for (int b = b0; b <= b1; ++b) {
+            double t = block_sum_d(myb == b ? ke : 0.0, s_red);
+            if (threadIdx.x == 0) A.partial[blockIdx.x + b] = t;
+        }
+    }
+    // completion ticket: the last block advances the step or finalizes E_kin
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(&A.dsc->ticket_vv, 1u);
+        s_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (PHASE == 0) {
+        if (threadIdx.x == 0) {
+            A.dsc->step += 1;
+            A.dsc->ticket_vv = 0;
+        }
+        return;
+    }
+    if (EKIN) {
+        for (int b = 0; b < A.B; ++b) {
+            const int64_t s0 = A.sys_off[b], s1 = A.sys_off[b + 1];
+            double t = 0.0;
+            if (s1 > s0) {
+                const int64_t k0 = s0 / kVvBlock, k1 = (s1 - 1) / kVvBlock;
+                for (int64_t k = k0 + threadIdx.x; k <= k1; k += kVvBlock)
+                    t += __hip_atomic_load(&A.partial[k + b], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            t = block_sum_d(t, s_red);
+            if (threadIdx.x == 0) A.ekin[b] = t;
+        }
+    }
+    if (threadIdx.x == 0) A.dsc->ticket_vv = 0;
+}
+
+void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const double* fx,
+               const double* fy, const double* fz, double* x, double* y, double* z, double* vx,
+               double* vy, double* vz, double* ekin, hipStream_t st)
+{
+    if (c->N == 0) return;
+    VvArgs A;
+    A.N = c->N; A.dt = dt; A.hdt = 0.5 * dt;
+    const double half_skin = 0.5 * c->cfg.skin;
+    A.thr2 = half_skin * half_skin;
+    A.inv_mass = inv_mass; A.fx = fx; A.fy = fy; A.fz = fz;
+    A.x = x; A.y = y; A.z = z; A.vx = vx; A.vy = vy; A.vz = vz;
+    A.xref = c->d_xref; A.partial = c->d_partial; A.ekin = ekin;
+    A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
+    const int nb = (int)div_up(c->N, kVvBlock);
+    if (phase == 0)
+        hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A);
+    else if (ekin)
+        hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A);
+    else
+        hipLaunchKernelGGL((k_vv<1, false>), dim3(nb), dim3(kVvBlock), 0, st, A);
+}
+
+int64_t vv_partials_needed(int64_t N, int B) { return div_up(N, kVvBlock) + B + 1; }
+
+// ------------------------------------------------------------------ device scalars
+
+__global__ void k_set_step(DevScalars* d, int64_t step) { d->step = step; }
+__global__ void k_clear_flags(DevScalars* d) { d->flags = 0u; }
+
+void launch_set_step(Ctx* c, int64_t step, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, st, c->dsc, step);
+}
+
+void launch_clear_flags(Ctx* c, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(1), 0, st, c->dsc);
+}
+
+}  // namespace md

@@ -1,0 +1,83 @@
+"""The C-ABI library loads and exports every symbol include/md.h declares; its host
+helpers agree with the oracle; and without a GPU its calls fail with status codes
+(CPU only: no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_03180_amd import md
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "md.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = md.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(md.EXPORTED)
+
+
+def test_debye_length_helper_matches_oracle():
+    for te, ne in [(10.0, 1e29), (1.0, 1e26), (250.0, 3e28), (0.5, 7e27)]:
+        assert md.md_debye_length_nm(te, ne) == pytest.approx(oracle.debye_length_nm(te, ne),
+                                                              rel=1e-14)
+    assert np.isnan(md.md_debye_length_nm(-1.0, 1e28))
+
+
+def test_rates_helper_matches_oracle():
+    rng = np.random.default_rng(7)
+    S, Z = 60, 8
+    p = rng.uniform(0, 0.2, size=(S + 1, Z + 1))
+    p[:, Z] = 0
+    p[0] = 0
+    P = np.zeros((S + 1, Z + 1))
+    P[0, 0] = 1.0
+    for s in range(1, S + 1):
+        P[s] = P[s - 1] * (1 - p[s])
+        P[s, 1:] += P[s - 1, :-1] * p[s, :-1]
+    a = md.md_rates_from_fractions(P)
+    b = oracle.rates_from_fractions(P)
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-15)
+
+
+def test_struct_layout_matches_header():
+    # md_config: 6 int32, 2 double, int64, 2 int32, double
+    assert ctypes.sizeof(md.md_config) == 6 * 4 + 2 * 8 + 8 + 2 * 4 + 8
+    assert ctypes.sizeof(md.md_stats) == 10 * 8 + 2 * 4
+
+
+def test_create_validates_arguments_without_gpu():
+    cfg = md.md_config(n_systems=1, n_types=2, n_elements=2, n_charge_states=9, periodic=1,
+                       screen_lj=1, rc=1.0, skin=0.1, capacity_atoms=10)
+    with pytest.raises(md.MDError) as e:
+        md.md_create(cfg, np.array([0, 20]))          # more atoms than capacity
+    assert e.value.status == md.MD_ERR_CAPACITY
+    bad = md.md_config(n_systems=1, n_types=20, n_elements=2, n_charge_states=9, periodic=1,
+                       rc=1.0, skin=0.1, capacity_atoms=10)
+    with pytest.raises(md.MDError) as e:
+        md.md_create(bad, np.array([0, 5]))
+    assert e.value.status == md.MD_ERR_CAPACITY
+    neg = md.md_config(n_systems=1, n_types=1, n_elements=1, n_charge_states=2, rc=-1.0,
+                       skin=0.1, capacity_atoms=10)
+    with pytest.raises(md.MDError) as e:
+        md.md_create(neg, np.array([0, 5]))
+    assert e.value.status == md.MD_ERR_ARG
+
+
+def test_null_context_is_an_argument_error():
+    L = md.lib()
+    assert L.md_build_cells(None, None, None, None, None, 0, None) == md.MD_ERR_ARG
+    assert L.md_screened_forces(None, 0, *([None] * 9), None) == md.MD_ERR_ARG
+    assert L.md_destroy(None) == md.MD_OK

@@ -1,0 +1,435 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same
+seeded inputs.  Pair sets and integer charges must be bit-exact, the integrator
+bit-exact given identical forces, and per-atom forces within
+e_F = max_i |dF_i| / A_i <= 1e-10 (FP64 path) / 1e-5 (FP32 path)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_03180_amd import synth
+from gpu_util import force_error, oracle_kappa, random_charges, require_gpu, say, sorted_pairs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-5}          # MD_FP64, MD_FP32_KAHAN
+PRECS = [0, 1]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def make_engine(sys, prec, **kw):
+    from paper_2401_03180_amd.md import Engine
+    return Engine(sys, prec, **kw)
+
+
+def set_q(eng, q):
+    import torch
+    eng.q.copy_(torch.as_tensor(q, dtype=torch.int8))
+
+
+def gpu_forces(eng, prec):
+    eng.forces(prec=prec, energy=True)
+    eng.sync_check()
+    return (eng.host("fx"), eng.host("fy"), eng.host("fz")), eng.host("epot")
+
+
+# ------------------------------------------------------------------ small bulk water
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_water_small_pairs_forces_energy(prec):
+    s = synth.water_small()
+    s.q = random_charges(s, 1)
+    say("water_small pairs/forces prec", prec)
+    eng = make_engine(s, prec)
+    set_q(eng, s.q)
+    eng.build()
+    F, epot = gpu_forces(eng, prec)
+    ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 0))
+    assert force_error(F, ref) <= TOL[prec]
+    esc = np.abs(ref["e_atom"]).sum() * 2
+    assert abs(epot[0] - ref["epot"][0]) <= TOL[prec] * esc
+    gp = sorted_pairs(eng.debug_pairs(prec=prec))
+    op = oracle.pairs(s)
+    assert gp.shape == op.shape and np.array_equal(gp, op)
+    st = eng.stats()
+    assert st["flags"] == 0 and st["n_builds"] == 1
+    eng.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_forces_with_other_screening_and_unscreened_lj(prec):
+    s = synth.water_small()
+    s.q = random_charges(s, 2, hi=9)
+    s.lambda_d[:] = np.inf              # kappa = 0: plain Coulomb
+    s.screen_lj = False
+    say("unscreened prec", prec)
+    eng = make_engine(s, prec)
+    set_q(eng, s.q)
+    eng.build()
+    F, _ = gpu_forces(eng, prec)
+    ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 0))
+    assert force_error(F, ref) <= TOL[prec]
+    eng.close()
+
+
+def _adversarial_system():
+    """Pairs of atoms placed so that their FP64 r^2 straddles rc^2 by a few ulp, along
+    axes, diagonals and across the periodic seam; pairs are 3 nm apart from each other."""
+    rc, L = 1.0, 12.0
+    rng = np.random.default_rng(5)
+    P = []
+    centers = synth.lattice_sites(4, 3.0)
+    dirs = [np.array([1.0, 0, 0]), np.array([0, 1.0, 0]), np.array([0.6, 0.8, 0]),
+            np.array([0.48, 0.6, 0.64])]
+    k = 0
+    for c in centers:
+        d = dirs[k % len(dirs)]
+        scale = rc * (1.0 + (k % 9 - 4) * 2.0 ** -52)
+        a = c.copy()
+        if k % 7 == 3:
+            a[0] = 0.2 * rng.random()       # straddle the x seam: partner at negative x
+            b = a - d * scale
+        else:
+            b = a + d * scale
+        P += [a, b]
+        k += 1
+    P = np.array(P)
+    n = P.shape[0]
+    z = np.zeros(n)
+    return synth.System(
+        name="adv", x=P[:, 0].copy(), y=P[:, 1].copy(), z=P[:, 2].copy(), vx=z.copy(),
+        vy=z.copy(), vz=z.copy(), elem=np.zeros(n, np.uint8), type=np.zeros(n, np.uint8),
+        atom_id=np.arange(n, dtype=np.uint32), inv_mass=np.ones(n),
+        q=np.ones(n, np.int8), sys_offsets=np.array([0, n], np.int64), periodic=True,
+        box=np.array([[L, L, L]]), rc=rc, skin=0.1, dt=1e-4, n_steps=1,
+        lambda_d=np.full((1, 2), 0.3), g=np.ones((1, 2)), base=np.zeros((1, 2)),
+        qmax=np.array([1], np.int8), c6=np.zeros((1, 1)), c12=np.zeros((1, 1)),
+        seeds=np.array([3], np.uint64))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_adversarial_cutoff_pairs(prec):
+    s = _adversarial_system()
+    op = oracle.pairs(s)
+    assert 0 < op.shape[0] < s.n_atoms // 2      # some at-cutoff pairs are in, some out
+    say("adversarial prec", prec)
+    eng = make_engine(s, prec)
+    eng.build()
+    gp = sorted_pairs(eng.debug_pairs(prec=prec))
+    assert np.array_equal(gp, op)
+    eng.close()
+
+
+# ------------------------------------------------------------------ ionization, integrator
+
+def test_ionization_bit_exact_every_step():
+    s = synth.water_small(n_steps=200)
+    say("ionize water_small 200 steps")
+    eng = make_engine(s, 1)
+    q = s.q.copy()
+    for step in range(1, 201):
+        eng.set_step(step)
+        eng.ionize()
+        oracle.ionize(s, q, step)
+        if step % 20 == 0 or step < 5:
+            assert np.array_equal(eng.host("q"), q), step
+    assert np.array_equal(eng.host("q"), q)
+    assert q.sum() > 0
+    eng.sync_check()
+    eng.close()
+
+
+def test_ionization_pulse_window_bit_exact():
+    s = synth.water_pulse()
+    s.base[:] = np.where(s.base > 0, 0.2, 0.0)      # large probabilities: many jumps
+    say("ionize water_pulse window")
+    eng = make_engine(s, 1)
+    q = s.q.copy()
+    for step in range(480, 521):
+        eng.set_step(step)
+        eng.ionize()
+        oracle.ionize(s, q, step)
+    assert np.array_equal(eng.host("q"), q)
+    assert (q > 0).mean() > 0.5
+    eng.close()
+
+
+def test_integrator_bit_exact_given_forces():
+    import torch
+    s = synth.water_small()
+    say("integrator bit-exact")
+    eng = make_engine(s, 0)
+    rng = np.random.default_rng(9)
+    F = [rng.standard_normal(s.n_atoms) * 500.0 for _ in range(3)]
+    for t, f in zip((eng.fx, eng.fy, eng.fz), F):
+        t.copy_(torch.as_tensor(f))
+    pos = [s.x.copy(), s.y.copy(), s.z.copy()]
+    vel = [s.vx.copy(), s.vy.copy(), s.vz.copy()]
+    eng.set_step(0)
+    for rep in range(3):
+        eng.vv(0)
+        oracle.vv(0, s.dt, s.inv_mass, F, pos, vel)
+        eng.vv(1, ekin=True)
+        oracle.vv(1, s.dt, s.inv_mass, F, pos, vel)
+    for name, ref in zip(("x", "y", "z", "vx", "vy", "vz"), (*pos, *vel)):
+        assert np.array_equal(eng.host(name), ref), name
+    assert eng.get_step() == 3
+    ek = oracle.ekin(s, *vel)
+    assert eng.host("ekin")[0] == pytest.approx(ek[0], rel=1e-13)
+    eng.close()
+
+
+# ------------------------------------------------------------------ full steps
+
+def _run_engine(eng, n, build_mode):
+    eng.set_step(0)
+    eng.build()
+    eng.forces(energy=True)
+    qs, ep = [], []
+    for _ in range(n):
+        eng.step(build_mode=build_mode)
+        qs.append(eng.host("q"))
+        ep.append(eng.host("epot")[0])
+    eng.sync_check()
+    return qs, ep
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_trajectory_against_oracle(prec):
+    """20 full steps (ionize + forces + VV) of the small water box: charges bit-exact
+    every step; positions within a bound set by the force tolerance."""
+    s = synth.water_small(n_steps=20)
+    s.base[:] = np.where(s.base > 0, 0.05, 0.0)
+    say("trajectory prec", prec)
+    eng = make_engine(s, prec, nstlist=5)
+    qs, ep = _run_engine(eng, 20, 0)
+    ref = oracle.run(s, 20)
+    for k in range(20):
+        assert np.array_equal(qs[k], ref["q"][k + 1]), k
+    tol = 1e-9 if prec == 0 else 2e-6
+    for name in ("x", "y", "z"):
+        assert np.max(np.abs(eng.host(name) - ref[name])) < tol, name
+    eps = np.abs(np.array(ep) - np.array(ref["epot"][1:])[:, 0]).max()
+    assert eps <= (1e-9 if prec == 0 else 1e-4) * np.abs(ref["epot"][-1][0]) + 1e-6
+    eng.close()
+
+
+# ------------------------------------------------------------------ full-size bench workload
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_water_pulse_sampled_rows(prec):
+    """98,304-atom pulse box in the benchmark's configuration: forces, and the number of
+    partners of every sampled atom, against the oracle's full-j rows."""
+    s = synth.water_pulse()
+    s.q = random_charges(s, 3, hi=4)
+    say("water_pulse sampled rows prec", prec)
+    eng = make_engine(s, prec)
+    set_q(eng, s.q)
+    eng.set_step(700)
+    eng.build()
+    F, _ = gpu_forces(eng, prec)
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(s.n_atoms, 2000, replace=False))
+    ref = oracle.forces_rows(s, rows, q=s.q, kappa=oracle_kappa(s, 700))
+    Fg = tuple(f[rows] for f in F)
+    assert force_error(Fg, ref) <= TOL[prec]
+    pairs = eng.debug_pairs(prec=prec)
+    cnt = np.bincount(pairs.reshape(-1), minlength=s.n_atoms)
+    assert np.array_equal(cnt[rows], ref["row_hits"])
+    eng.close()
+
+
+# ------------------------------------------------------------------ batched vacuum clusters
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_vacuum_batched_clusters(prec):
+    s = synth.methane_clusters(n_clusters=5, lo=300, hi=4000, n_steps=10)
+    s.q = random_charges(s, 4)
+    k = 3
+    say("methane batched prec", prec)
+    eng = make_engine(s, prec, density_hint=100.0)
+    set_q(eng, s.q)
+    eng.set_step(k)
+    eng.build()
+    F, epot = gpu_forces(eng, prec)
+    ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, k))
+    assert force_error(F, ref) <= TOL[prec]
+    for b in range(s.n_systems):
+        a0, a1 = s.sys_offsets[b], s.sys_offsets[b + 1]
+        assert abs(epot[b] - ref["epot"][b]) <= TOL[prec] * 2 * np.abs(ref["e_atom"][a0:a1]).sum()
+    gp = sorted_pairs(eng.debug_pairs(prec=prec))
+    assert np.array_equal(gp, oracle.pairs(s))
+    eng.close()
+    # every system alone gives the same pair set and forces within tolerance
+    for b in (0, 3):
+        a0, a1 = int(s.sys_offsets[b]), int(s.sys_offsets[b + 1])
+        sb = s.copy()
+        for name in ("x", "y", "z", "vx", "vy", "vz", "elem", "type", "atom_id", "inv_mass", "q"):
+            setattr(sb, name, getattr(s, name)[a0:a1].copy())
+        sb.sys_offsets = np.array([0, a1 - a0], np.int64)
+        sb.lambda_d = s.lambda_d[b:b + 1].copy()
+        sb.g = s.g[b:b + 1].copy()
+        sb.seeds = s.seeds[b:b + 1].copy()
+        say("methane single system", b, "prec", prec)
+        e1 = make_engine(sb, prec, density_hint=100.0)
+        set_q(e1, sb.q)
+        e1.set_step(k)
+        e1.build()
+        F1, _ = gpu_forces(e1, prec)
+        for c in range(3):
+            assert np.allclose(F1[c], F[c][a0:a1], rtol=0, atol=TOL[prec] * ref["a_atom"][a0:a1].max())
+        p1 = sorted_pairs(e1.debug_pairs(prec=prec)) + a0
+        sel = (gp[:, 0] >= a0) & (gp[:, 0] < a1)
+        assert np.array_equal(p1, gp[sel])
+        e1.close()
+
+
+# ------------------------------------------------------------------ graphs
+
+def test_graph_replay_matches_eager():
+    """Captured steps replayed several times, with eager work and synchronizations in
+    between, reproduce the eager steps bit for bit (deterministic kernels)."""
+    import torch
+    s = synth.water_small(n_steps=12)
+    s.base[:] = np.where(s.base > 0, 0.05, 0.0)
+    say("graph vs eager")
+    ea = make_engine(s, 1)
+    eb = make_engine(s, 1)
+    for e in (ea, eb):
+        e.set_step(0)
+        e.build()
+        e.forces(energy=False)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        g_reb = eb.graph(True, stream)
+        g_chk = eb.graph(False, stream)
+    # capture does not execute; restart both from the same state
+    for step in range(12):
+        reb = step % 4 == 3
+        ea.step(build_mode=1 if reb else 2, energy=False, ekin=False)
+        torch.cuda.synchronize()
+        from paper_2401_03180_amd.md import md_graph_launch
+        md_graph_launch(g_reb if reb else g_chk, stream)
+        stream.synchronize()
+        _ = eb.host("x")                       # eager work between replays
+        for name in ("x", "vx", "q", "fx"):
+            assert np.array_equal(ea.host(name), eb.host(name)), (step, name)
+    assert ea.get_step() == eb.get_step() == 12
+    ea.sync_check()
+    eb.sync_check()
+    ea.close()
+    eb.close()
+
+
+# ------------------------------------------------------------------ edge cases / errors
+
+def _tiny_system(n, periodic=True, L=5.0, seed=0, nsys=1):
+    """n atoms on randomly chosen sites of a jittered 0.4 nm lattice (no close contacts)."""
+    rng = np.random.default_rng(seed)
+    m = max(2, int(L / 0.4))
+    sites = synth.lattice_sites(m, L / m)
+    P = sites[rng.permutation(sites.shape[0])[:n]] + rng.uniform(-0.05, 0.05, size=(n, 3))
+    z = np.zeros(n)
+    offs = np.linspace(0, n, nsys + 1).astype(np.int64)
+    atom_id = np.concatenate([np.arange(offs[b + 1] - offs[b]) for b in range(nsys)]).astype(np.uint32)
+    return synth.System(
+        name="tiny", x=P[:, 0].copy(), y=P[:, 1].copy(), z=P[:, 2].copy(), vx=z.copy(),
+        vy=z.copy(), vz=z.copy(), elem=np.zeros(n, np.uint8), type=np.zeros(n, np.uint8),
+        atom_id=atom_id, inv_mass=np.ones(n), q=rng.integers(0, 3, n).astype(np.int8),
+        sys_offsets=offs, periodic=periodic,
+        box=np.tile([[L, L, L]], (nsys, 1)) if periodic else None, rc=1.0, skin=0.1,
+        dt=1e-4, n_steps=4, lambda_d=np.full((nsys, 5), 0.3), g=np.ones((nsys, 5)),
+        base=np.full((1, 3), 0.5), qmax=np.array([2], np.int8), c6=np.full((1, 1), 1e-3),
+        c12=np.full((1, 1), 1e-6), seeds=np.arange(1, nsys + 1, dtype=np.uint64))
+
+
+@pytest.mark.parametrize("n,periodic,nsys", [(1, True, 1), (13, True, 1), (37, False, 1),
+                                             (50, False, 3), (203, True, 2)])
+def test_ragged_and_degenerate_sizes(n, periodic, nsys):
+    s = _tiny_system(n, periodic, nsys=nsys)
+    for prec in PRECS:
+        say("ragged n", n, "periodic", periodic, "nsys", nsys, "prec", prec)
+        eng = make_engine(s, prec)
+        set_q(eng, s.q)
+        eng.build()
+        F, _ = gpu_forces(eng, prec)
+        ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 0))
+        assert force_error(F, ref) <= TOL[prec]
+        assert np.array_equal(sorted_pairs(eng.debug_pairs(prec=prec)), oracle.pairs(s))
+        eng.close()
+
+
+def test_empty_system_in_batch():
+    s = _tiny_system(40, periodic=False, nsys=2)
+    s.sys_offsets = np.array([0, 0, 40], np.int64)
+    s.atom_id = np.arange(40, dtype=np.uint32)
+    say("empty system in batch")
+    eng = make_engine(s, 1)
+    set_q(eng, s.q)
+    eng.build()
+    F, epot = gpu_forces(eng, 1)
+    ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 0))
+    assert force_error(F, ref) <= 1e-5
+    assert epot[0] == 0.0
+    eng.close()
+
+
+def test_box_too_small_is_geometry_error():
+    from paper_2401_03180_amd.md import MDError, MD_ERR_GEOMETRY
+    s = _tiny_system(20, True, L=2.1)
+    with pytest.raises(MDError) as e:
+        make_engine(s, 1)
+    assert e.value.status == MD_ERR_GEOMETRY
+
+
+def test_device_flags_are_reported():
+    import torch
+    from paper_2401_03180_amd import md
+    s = _tiny_system(64, True)
+    eng = make_engine(s, 1)
+    eng.build()
+    # step counter beyond the bound tables
+    say("flag: step")
+    eng.set_step(s.n_steps + 3)
+    eng.ionize()
+    assert eng.sync_check(raise_on_flags=False) & md.MD_FLAG_STEP
+    md.md_clear_flags(eng.ctx)
+    assert eng.sync_check() == 0
+    # displacement beyond skin/2 without a rebuild
+    say("flag: skin")
+    eng.set_step(0)
+    eng.x.add_(0.2)
+    eng.vv(0)                      # zero velocity, zero force: tracks the displacement
+    eng.forces()
+    assert eng.sync_check(raise_on_flags=False) & md.MD_FLAG_SKIN
+    md.md_clear_flags(eng.ctx)
+    eng.build()
+    eng.forces()
+    assert eng.sync_check() == 0
+    # non-finite position
+    say("flag: nonfinite")
+    x = eng.x.clone()
+    eng.x[5] = float("nan")
+    eng.build()
+    assert eng.sync_check(raise_on_flags=False) & md.MD_FLAG_NONFINITE
+    eng.x.copy_(x)
+    md.md_clear_flags(eng.ctx)
+    # type outside the table
+    say("flag: bad type")
+    eng.type[3] = 7
+    eng.build()
+    assert eng.sync_check(raise_on_flags=False) & md.MD_FLAG_BAD_INPUT
+    eng.close()
+    # neighbour list too small
+    say("flag: list overflow")
+    s2 = synth.water_small()
+    e2 = make_engine(s2, 1, max_neighbors=16)
+    e2.build()
+    assert e2.sync_check(raise_on_flags=False) & md.MD_FLAG_LIST_OVERFLOW
+    e2.close()
