@@ -90,10 +90,10 @@ typedef struct md_config {
 } md_config;
 
 /* Build modes of md_build_cells. */
-#define MD_BUILD_AUTO 0         /* rebuild on the first call and then on every nstlist-th call
-                                   (md_set_nstlist, default 10); between rebuilds every force
-                                   call latches MD_FLAG_SKIN if some atom has moved more than
-                                   skin/2 since the last build (its lists may miss pairs) */
+#define MD_BUILD_AUTO 0         /* device-decided: the build kernels are enqueued but do their
+                                   work only if phase 0 of md_integrate_vv found an atom that
+                                   moved more than skin/2 since the last build (no host
+                                   round trip, graph-capturable); the first build always runs */
 #define MD_BUILD_FORCE 1        /* rebuild now */
 #define MD_BUILD_CHECK 2        /* never rebuild; latch MD_FLAG_SKIN if a rebuild was due */
 
@@ -147,8 +147,6 @@ md_status md_get_step(md_ctx* ctx, int64_t* step, md_stream stream);
 md_status md_build_cells(md_ctx* ctx, const double* x, const double* y, const double* z,
                          const uint8_t* type, int32_t mode, md_stream stream);
 
-/* Number of md_build_cells(MD_BUILD_AUTO) calls between rebuilds (>= 1). */
-md_status md_set_nstlist(md_ctx* ctx, int32_t nstlist);
 
 /* Stochastic integer ionization for the current step s (>= 1, the device step
  * counter): every atom a of system b with element e = elem[a] and charge
@@ -224,16 +222,25 @@ typedef struct md_step_args {
  * md_screened_forces once before the first step).  Asynchronous. */
 md_status md_step(md_ctx* ctx, const md_step_args* args, int32_t build_mode, md_stream stream);
 
-/* HIP-graph form of md_step: records one step (with a rebuild when with_rebuild is
- * 1, with MD_BUILD_CHECK otherwise) on `stream` (not the null stream) into an
- * executable graph.  Replaying it runs the step with no host work; the step
- * counter, schedules and random streams advance on the device.  The pointers in
- * args are baked into the graph. */
+/* HIP-graph form of md_step: records one step with the given MD_BUILD_* mode on
+ * `stream` (not the null stream) into an executable graph, without executing it.
+ * Replaying it runs the step with no host work; the step counter, schedules,
+ * random streams and (with MD_BUILD_AUTO) list rebuilds advance on the device.
+ * The pointers in args are baked into the graph. */
 typedef struct md_graph md_graph;
-md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t with_rebuild,
+md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t build_mode,
                           md_stream stream, md_graph** out);
 md_status md_graph_launch(md_graph* graph, md_stream stream);
 md_status md_graph_destroy(md_graph* graph);
+
+/* Benchmark helper: runs the force evaluation of md_screened_forces `reps` times
+ * on `stream` and times the force kernel alone with HIP events recorded on that
+ * stream around each launch (the slot repack that precedes every launch is outside
+ * the timed intervals).  *avg_ms receives the mean kernel time.  Synchronous. */
+md_status md_time_forces(md_ctx* ctx, md_precision prec, const double* x, const double* y,
+                         const double* z, const int8_t* q, const uint8_t* type, double* fx,
+                         double* fy, double* fz, double* epot, int32_t reps, float* avg_ms,
+                         md_stream stream);
 
 typedef struct md_stats {
     int64_t n_atoms, n_clusters, n_groups, n_entries;   /* from the last build */

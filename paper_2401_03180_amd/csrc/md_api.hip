@@ -51,8 +51,8 @@ void free_all(Ctx* c)
     void* ptrs[] = {c->dsc, c->d_sys_off, c->d_sys_of_atom, c->d_grid, c->d_sys_lo, c->d_sys_hi,
                     c->d_sys_grp0, c->d_c6, c->d_c12, c->d_lj32, c->d_qmax, c->d_kappa,
                     c->d_base, c->d_g, c->d_seeds, c->d_key, c->d_rank, c->d_img,
-                    c->d_bin_cnt, c->d_bin_start, c->d_sorted, c->d_scan_tmp, c->d_col_ncl,
-                    c->d_col_ngrp, c->d_col_cl0, c->d_col_grp0, c->d_cl_lo, c->d_cl_hi,
+                    c->d_bin_cnt, c->d_bin_start, c->d_sorted, c->d_scan_tmp, c->d_col_cnt,
+                    c->d_col_pre, c->d_cl_lo, c->d_cl_hi,
                     c->d_cl_nt, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_qs,
                     c->d_ts, c->d_groups, c->d_ent, c->d_nb, c->d_grp_epot, c->d_xref,
                     c->d_partial};
@@ -224,10 +224,8 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, dalloc(&c->d_bin_start, c->cap_bins + 1));
     HIP_TRY(c, dalloc(&c->d_sorted, N));
     HIP_TRY(c, dalloc(&c->d_scan_tmp, kScanTile + 64));
-    HIP_TRY(c, dalloc(&c->d_col_ncl, c->cap_cols + 1));
-    HIP_TRY(c, dalloc(&c->d_col_ngrp, c->cap_cols + 1));
-    HIP_TRY(c, dalloc(&c->d_col_cl0, c->cap_cols + 1));
-    HIP_TRY(c, dalloc(&c->d_col_grp0, c->cap_cols + 1));
+    HIP_TRY(c, dalloc(&c->d_col_cnt, c->cap_cols + 1));
+    HIP_TRY(c, dalloc(&c->d_col_pre, c->cap_cols + 1));
     HIP_TRY(c, dalloc(&c->d_cl_lo, 3 * c->cap_clusters));
     HIP_TRY(c, dalloc(&c->d_cl_hi, 3 * c->cap_clusters));
     HIP_TRY(c, dalloc(&c->d_cl_nt, c->cap_clusters));
@@ -262,6 +260,7 @@ static md_status size_and_allocate(Ctx* c)
     if (cfg.periodic)
         HIP_TRY(c, hipMemcpy(c->d_grid, grids.data(), sizeof(GridSys) * B, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemset(c->d_perm, 0xFF, sizeof(int32_t) * c->cap_slots));
+    HIP_TRY(c, hipMemset(c->d_bin_cnt, 0, sizeof(int32_t) * (c->cap_bins + 1)));
     HIP_TRY(c, hipMemset(c->d_cl_nt, 0, sizeof(int32_t) * c->cap_clusters));
     HIP_TRY(c, hipMemset(c->d_groups, 0, sizeof(Group) * c->cap_groups));
     HIP_TRY(c, hipMemset(c->d_xref, 0, sizeof(double) * 3 * std::max<int64_t>(N, 1)));
@@ -345,7 +344,6 @@ md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const
     HIP_TRY(c, hipDeviceSynchronize());
     c->tables_bound = true;
     c->built = false;
-    c->build_calls_since = 0;
     return MD_OK;
 }
 
@@ -369,14 +367,6 @@ md_status md_get_step(md_ctx* ctx, int64_t* step, md_stream stream)
     return MD_OK;
 }
 
-md_status md_set_nstlist(md_ctx* ctx, int32_t nstlist)
-{
-    if (!ctx) return MD_ERR_ARG;
-    if (nstlist < 1) return fail(&ctx->c, MD_ERR_ARG, "nstlist must be >= 1");
-    ctx->c.nstlist = nstlist;
-    return MD_OK;
-}
-
 md_status md_build_cells(md_ctx* ctx, const double* x, const double* y, const double* z,
                          const uint8_t* type, int32_t mode, md_stream stream)
 {
@@ -386,15 +376,14 @@ md_status md_build_cells(md_ctx* ctx, const double* x, const double* y, const do
     if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
     if (mode != MD_BUILD_AUTO && mode != MD_BUILD_FORCE && mode != MD_BUILD_CHECK)
         return fail(c, MD_ERR_ARG, "unknown build mode %d", mode);
-    bool rebuild = mode == MD_BUILD_FORCE || !c->built;
-    if (mode == MD_BUILD_AUTO && !rebuild) rebuild = ++c->build_calls_since >= c->nstlist;
     if (mode == MD_BUILD_CHECK && c->built) {
         launch_skin_check(c, S(stream));
-    } else if (rebuild) {
-        launch_build(c, x, y, z, type, S(stream));
+    } else if (mode == MD_BUILD_FORCE || !c->built) {
+        launch_build(c, x, y, z, type, true, S(stream));
         c->built = true;
-        c->build_calls_since = 0;
-        c->host_builds++;
+    } else {
+        // device-gated: the build kernels run only when the rebuild request is set
+        launch_build(c, x, y, z, type, false, S(stream));
     }
     HIP_TRY(c, hipGetLastError());
     return MD_OK;
@@ -425,6 +414,39 @@ md_status md_screened_forces(md_ctx* ctx, md_precision prec, const double* x, co
     if (!c->built) return fail(c, MD_ERR_STATE, "md_build_cells has not run");
     launch_repack(c, x, y, z, q, S(stream));
     HIP_TRY(c, launch_forces(c, prec, fx, fy, fz, epot, nullptr, 0, S(stream)));
+    return MD_OK;
+}
+
+md_status md_time_forces(md_ctx* ctx, md_precision prec, const double* x, const double* y,
+                         const double* z, const int8_t* q, const uint8_t* type, double* fx,
+                         double* fy, double* fz, double* epot, int32_t reps, float* avg_ms,
+                         md_stream stream)
+{
+    if (!ctx || !avg_ms || reps < 1) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (null_any({x, y, z, q, type, fx, fy, fz}) && c->N > 0)
+        return fail(c, MD_ERR_ARG, "NULL array");
+    if (!c->tables_bound || !c->built) return fail(c, MD_ERR_STATE, "no build");
+    hipStream_t st = S(stream);
+    std::vector<hipEvent_t> ev(2 * reps, nullptr);
+    for (auto& e : ev) HIP_TRY(c, hipEventCreate(&e));
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        launch_repack(c, x, y, z, q, st);
+        err = hipEventRecord(ev[2 * r], st);
+        if (err == hipSuccess) err = launch_forces(c, prec, fx, fy, fz, epot, nullptr, 0, st);
+        if (err == hipSuccess) err = hipEventRecord(ev[2 * r + 1], st);
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    double total = 0.0;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        float ms = 0.f;
+        err = hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
+        total += ms;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess) return fail(c, MD_ERR_HIP, "timing failed: %s", hipGetErrorString(err));
+    *avg_ms = (float)(total / reps);
     return MD_OK;
 }
 
@@ -598,7 +620,7 @@ md_status md_step(md_ctx* ctx, const md_step_args* args, int32_t build_mode, md_
     return step_impl(ctx, args, build_mode, stream);
 }
 
-md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t with_rebuild,
+md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t build_mode,
                           md_stream stream, md_graph** out)
 {
     if (!ctx || !args || !out) return MD_ERR_ARG;
@@ -608,8 +630,7 @@ md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t with_re
     if (!c->built) return fail(c, MD_ERR_STATE, "build cells before capturing a step");
     hipStream_t st = S(stream);
     HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    const md_status s = step_impl(ctx, args, with_rebuild ? MD_BUILD_FORCE : MD_BUILD_CHECK,
-                                  stream);
+    const md_status s = step_impl(ctx, args, build_mode, stream);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &graph);
     if (s != MD_OK) {

@@ -42,26 +42,21 @@ __device__ inline int upper_index(const int32_t* arr, int n, int v)
     return lo;
 }
 
-__global__ void k_build_begin(DevScalars* d)
-{
-    d->max_entries = 0;
-    d->max_list = 0;
-    d->n_codes = 0;
-}
+// Every build kernel takes `gate`: NULL runs it unconditionally (forced build);
+// otherwise it returns at once unless *gate (the device rebuild request) is set.
+__device__ inline bool gated_off(const int32_t* gate) { return gate && *gate == 0; }
 
-__global__ void k_build_done(DevScalars* d)
-{
-    d->need_rebuild = 0;
-    d->disp2_bits = 0ull;
-    d->n_builds += 1;
-}
+__device__ inline int col_cl0(const int64_t* pre, int c) { return (int)(pre[c] & 0xFFFFFFFFll); }
+__device__ inline int col_grp0(const int64_t* pre, int c) { return (int)(pre[c] >> 32); }
 
 // ---------------------------------------------------------------- vacuum grids
 
 __global__ void __launch_bounds__(256) k_sys_bbox(const double* x, const double* y,
                                                   const double* z, const int64_t* sys_off,
-                                                  double* lo, double* hi, DevScalars* dsc)
+                                                  double* lo, double* hi, DevScalars* dsc,
+                                                  const int32_t* gate)
 {
+    if (gated_off(gate)) return;
     __shared__ double s_v[6][4];
     const int b = blockIdx.x;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -103,8 +98,10 @@ __global__ void __launch_bounds__(256) k_sys_bbox(const double* x, const double*
 // totals never exceed the capacities; then the global column / bin offsets.
 __global__ void __launch_bounds__(256) k_grid_vacuum(const double* lo, const double* hi,
                                                      const int64_t* sys_off, int B,
-                                                     GridSys* grid, DevScalars* dsc)
+                                                     GridSys* grid, DevScalars* dsc,
+                                                     const int32_t* gate)
 {
+    if (gated_off(gate)) return;
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
         const int64_t nb = sys_off[b + 1] - sys_off[b];
         GridSys g;
@@ -168,12 +165,11 @@ struct BinArgs {
     double* xref;
     int64_t cap_bins;
     DevScalars* dsc;
+    const int32_t* gate;
 };
 
-__global__ void __launch_bounds__(256) k_bin(BinArgs A)
+__device__ inline void bin_one(const BinArgs& A, int64_t a)
 {
-    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (a >= A.N) return;
     const GridSys g = A.grid[A.sys_of_atom[a]];
     const double p[3] = {A.x[a], A.y[a], A.z[a]};
     int c[3], im[3] = {0, 0, 0};
@@ -204,22 +200,72 @@ __global__ void __launch_bounds__(256) k_bin(BinArgs A)
     A.xref[2 * A.N + a] = p[2];
 }
 
-__global__ void __launch_bounds__(256) k_scatter(int64_t N, const int32_t* key,
-                                                 const int32_t* rank, const int32_t* bin_start,
-                                                 int32_t* sorted)
+__global__ void __launch_bounds__(256) k_bin(BinArgs A)
 {
-    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (a >= N) return;
-    sorted[bin_start[key[a]] + rank[a]] = (int32_t)a;
+    if (gated_off(A.gate)) return;
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid == 0) {
+        A.dsc->max_entries = 0;
+        A.dsc->max_list = 0;
+        A.dsc->n_codes = 0;
+    }
+    for (int64_t a = gid; a < A.N; a += (int64_t)gridDim.x * blockDim.x)
+        bin_one(A, a);
 }
 
-// Order the atoms of each bin by caller index (bins hold a few atoms).
-__global__ void __launch_bounds__(256) k_bin_sort(const int32_t* bin_start, int32_t* sorted,
-                                                  int64_t cap_bins, const DevScalars* dsc)
+
+// Scatter atoms into bin order, and count clusters / groups per column (packed
+// as ngroups << 32 | nclusters so one 64-bit scan yields both prefixes).
+struct ScatterArgs {
+    int64_t N;
+    const int32_t* key;
+    const int32_t* rank;
+    const int32_t* bin_start;
+    int32_t* sorted;
+    const GridSys* grid;
+    int B;
+    int64_t* col_cnt;
+    int64_t cap_cols;
+    int G;
+    const DevScalars* dsc;
+    const int32_t* gate;
+};
+
+__global__ void __launch_bounds__(256) k_scatter_cols(ScatterArgs A)
 {
+    if (gated_off(A.gate)) return;
+    const int ncols = A.dsc->n_cols;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t a = gid; a < A.N; a += stride)
+        A.sorted[A.bin_start[A.key[a]] + A.rank[a]] = (int32_t)a;
+    for (int64_t c = gid; c <= A.cap_cols; c += stride) {
+        int ncl = 0;
+        if (c < ncols) {
+            const int b = find_sys_by_col(A.grid, A.B, (int)c);
+            const GridSys& g = A.grid[b];
+            const int nz = g.n[2];
+            const int bin0 = g.bin_off + ((int)c - g.col_off) * nz;
+            const int natoms = A.bin_start[bin0 + nz] - A.bin_start[bin0];
+            ncl = (natoms + kCluster - 1) / kCluster;
+        }
+        const int ngrp = (ncl + A.G - 1) / A.G;
+        A.col_cnt[c] = ((int64_t)ngrp << 32) | (int64_t)ncl;
+    }
+}
+
+// Order the atoms of each bin by caller index (bins hold a few atoms), and clear
+// the bin counters for the next build.
+__global__ void __launch_bounds__(256) k_bin_sort(const int32_t* bin_start, int32_t* sorted,
+                                                  int32_t* bin_cnt, int64_t cap_bins,
+                                                  const DevScalars* dsc, const int32_t* gate)
+{
+    if (gated_off(gate)) return;
     const int nbins = dsc->n_bins;
-    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nbins && b < cap_bins;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < cap_bins;
          b += (int64_t)gridDim.x * blockDim.x) {
+        bin_cnt[b] = 0;
+        if (b >= nbins) continue;
         const int s = bin_start[b], e = bin_start[b + 1];
         if (e - s < 2 || e - s > 128) continue;
         for (int i = s + 1; i < e; ++i) {
@@ -231,29 +277,6 @@ __global__ void __launch_bounds__(256) k_bin_sort(const int32_t* bin_start, int3
     }
 }
 
-// Per column: clusters = ceil(atoms / 8); groups = ceil(clusters / G).
-__global__ void __launch_bounds__(256) k_col_count(const GridSys* grid, int B,
-                                                   const int32_t* bin_start, int32_t* col_ncl,
-                                                   int32_t* col_ngrp, int64_t cap_cols, int G,
-                                                   const DevScalars* dsc)
-{
-    const int ncols = dsc->n_cols;
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c <= cap_cols;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        int ncl = 0;
-        if (c < ncols) {
-            const int b = find_sys_by_col(grid, B, (int)c);
-            const GridSys& g = grid[b];
-            const int nz = g.n[2];
-            const int bin0 = g.bin_off + ((int)c - g.col_off) * nz;
-            const int natoms = bin_start[bin0 + nz] - bin_start[bin0];
-            ncl = (natoms + kCluster - 1) / kCluster;
-        }
-        col_ncl[c] = ncl;
-        col_ngrp[c] = (ncl + G - 1) / G;
-    }
-}
-
 struct ClusterArgs {
     const double *x, *y, *z;
     const uint8_t* type;
@@ -261,8 +284,7 @@ struct ClusterArgs {
     int B;
     const int32_t* bin_start;
     const int32_t* sorted;
-    const int32_t* col_cl0;
-    const int32_t* col_grp0;
+    const int64_t* col_pre;
     const int32_t* img;
     int32_t* perm;
     int32_t* inv_perm;
@@ -276,14 +298,28 @@ struct ClusterArgs {
     int G;
     int T;
     DevScalars* dsc;
+    const int32_t* gate;
 };
+
+// largest column c in [0, n] whose first cluster index is <= v
+__device__ inline int column_of_cluster(const int64_t* pre, int n, int v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (col_cl0(pre, mid) <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
 {
+    if (gated_off(A.gate)) return;
     const int ncols = A.dsc->n_cols;
-    int total = A.col_cl0[ncols];
-    const int ngroups = A.col_grp0[ncols];
+    int total = col_cl0(A.col_pre, ncols);
+    const int ngroups = col_grp0(A.col_pre, ncols);
     const int64_t gid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (gid0 == 0) {
         if (total > A.cap_clusters) set_flag(A.dsc, MD_FLAG_CELL_OVERFLOW);
         A.dsc->n_clusters = min((int64_t)total, A.cap_clusters);
@@ -291,15 +327,16 @@ __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
         A.dsc->n_slots = kCluster * min((int64_t)total, A.cap_clusters);
         A.sys_grp0[A.B] = min((int64_t)ngroups, A.cap_clusters);
     }
-    if (gid0 < A.B) A.sys_grp0[gid0] = min(A.col_grp0[A.grid[gid0].col_off], (int)A.cap_clusters);
+    for (int64_t b = gid0; b < A.B; b += stride)
+        A.sys_grp0[b] = min(col_grp0(A.col_pre, A.grid[b].col_off), (int)A.cap_clusters);
     total = (int)min((int64_t)total, A.cap_clusters);
-    for (int64_t cl = gid0; cl < total; cl += (int64_t)gridDim.x * blockDim.x) {
-        const int c = upper_index(A.col_cl0, ncols, (int)cl);
+    for (int64_t cl = gid0; cl < total; cl += stride) {
+        const int c = column_of_cluster(A.col_pre, ncols, (int)cl);
         const int b = find_sys_by_col(A.grid, A.B, c);
         const GridSys& g = A.grid[b];
         const int nz = g.n[2];
         const int bin0 = g.bin_off + (c - g.col_off) * nz;
-        const int k = (int)cl - A.col_cl0[c];
+        const int k = (int)cl - col_cl0(A.col_pre, c);
         const int abeg = A.bin_start[bin0] + kCluster * k;
         const int aend = A.bin_start[bin0 + nz];
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -332,8 +369,8 @@ __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
             A.cl_hi[cl * 3 + d] = hi[d];
         }
         if (k % A.G == 0) {
-            const int ncl_col = A.col_cl0[c + 1] - A.col_cl0[c];
-            const int grp = A.col_grp0[c] + k / A.G;
+            const int ncl_col = col_cl0(A.col_pre, c + 1) - col_cl0(A.col_pre, c);
+            const int grp = col_grp0(A.col_pre, c) + k / A.G;
             if (grp < A.cap_clusters) {
                 A.groups[grp].cl0 = (int)cl;
                 A.groups[grp].ncl = min(A.G, ncl_col - k);
@@ -348,7 +385,7 @@ __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
 
 struct EntryArgs {
     const GridSys* grid;
-    const int32_t* col_cl0;
+    const int64_t* col_pre;
     const double* cl_lo;
     const double* cl_hi;
     Group* groups;
@@ -356,12 +393,14 @@ struct EntryArgs {
     int E_cap;
     double rlist;
     DevScalars* dsc;
+    const int32_t* gate;
 };
 
 // One wave per group.  Candidates are visited in a fixed order and appended with a
 // ballot prefix, so the table is deterministic.
 __global__ void __launch_bounds__(256) k_group_entries(EntryArgs A)
 {
+    if (gated_off(A.gate)) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -407,7 +446,7 @@ __global__ void __launch_bounds__(256) k_group_entries(EntryArgs A)
                 const int sy = (cy - cyw) / gs.n[1];
                 if (sy < -1 || sy > 1) continue;
                 const int col = gs.col_off + cxw * gs.n[1] + cyw;
-                const int j0 = A.col_cl0[col], j1 = A.col_cl0[col + 1];
+                const int j0 = col_cl0(A.col_pre, col), j1 = col_cl0(A.col_pre, col + 1);
                 const int cand = (j1 - j0) * nsz;
                 for (int base = 0; base < cand; base += 64) {
                     const int cidx = base + lane;
@@ -468,6 +507,7 @@ struct ListArgs {
     int E_cap, nb_cap, nb_T;
     float thr2;                 // (rc + skin)^2 with a relative margin
     DevScalars* dsc;
+    const int32_t* gate;
 };
 
 __device__ inline float3 frame_coords(const double* x, const double* y, const double* z, int a,
@@ -488,7 +528,9 @@ __device__ inline float3 frame_coords(const double* x, const double* y, const do
 
 __global__ void __launch_bounds__(512) k_atom_lists(ListArgs A)
 {
+    if (gated_off(A.gate)) return;
     extern __shared__ float4 s_dyn[];
+    __shared__ int s_last;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     float4* s_pos = s_dyn;
     uint32_t* s_ent = reinterpret_cast<uint32_t*>(s_dyn + (A.E_cap * kCluster + 1));
@@ -558,64 +600,84 @@ __global__ void __launch_bounds__(512) k_atom_lists(ListArgs A)
         }
         __syncthreads();
     }
+    // the last work-group to finish closes the build: lists are fresh again
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&A.dsc->ticket_build, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (s_last && tid == 0) {
+        __threadfence();
+        A.dsc->ticket_build = 0u;
+        A.dsc->need_rebuild = 0;
+        A.dsc->disp2_bits = 0ull;
+        A.dsc->n_builds += 1;
+    }
 }
 
 // ---------------------------------------------------------------- orchestration
 
+size_t atom_lists_lds_bytes(int E_cap)
+{
+    return (size_t)(E_cap * kCluster + 1) * sizeof(float4) + (size_t)E_cap * sizeof(uint32_t);
+}
+
 void launch_build(Ctx* c, const double* x, const double* y, const double* z,
-                  const uint8_t* type, hipStream_t st)
+                  const uint8_t* type, bool force, hipStream_t st)
 {
     const int64_t N = c->N;
-    hipLaunchKernelGGL(k_build_begin, dim3(1), dim3(1), 0, st, c->dsc);
+    const int32_t* gate = force ? nullptr : &c->dsc->need_rebuild;
+    const int wide = std::max(1, c->n_cu * 8);
     if (!c->cfg.periodic) {
         hipLaunchKernelGGL(k_sys_bbox, dim3(c->B), dim3(256), 0, st, x, y, z, c->d_sys_off,
-                           c->d_sys_lo, c->d_sys_hi, c->dsc);
+                           c->d_sys_lo, c->d_sys_hi, c->dsc, gate);
         hipLaunchKernelGGL(k_grid_vacuum, dim3(1), dim3(256), 0, st, c->d_sys_lo, c->d_sys_hi,
-                           c->d_sys_off, c->B, c->d_grid, c->dsc);
+                           c->d_sys_off, c->B, c->d_grid, c->dsc, gate);
     }
-    launch_fill_i32(c->d_bin_cnt, c->cap_bins + 1, 0, st);
-    if (N > 0) {
-        BinArgs A{N, x, y, z, c->d_sys_of_atom, c->d_grid, c->d_bin_cnt, c->d_key, c->d_rank,
-                  c->d_img, c->d_xref, c->cap_bins, c->dsc};
-        hipLaunchKernelGGL(k_bin, dim3(div_up(N, 256)), dim3(256), 0, st, A);
-    }
-    launch_scan(c->d_bin_cnt, c->d_bin_start, c->cap_bins + 1, c->d_scan_tmp, nullptr, st);
-    if (N > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(div_up(N, 256)), dim3(256), 0, st, N, c->d_key,
-                           c->d_rank, c->d_bin_start, c->d_sorted);
-    const int fill_blocks = (int)std::min<int64_t>(div_up(c->cap_bins, 256), 2048);
-    hipLaunchKernelGGL(k_bin_sort, dim3(fill_blocks), dim3(256), 0, st, c->d_bin_start,
-                       c->d_sorted, c->cap_bins, c->dsc);
-    const int col_blocks = (int)std::min<int64_t>(div_up(c->cap_cols + 1, 256), 2048);
-    hipLaunchKernelGGL(k_col_count, dim3(col_blocks), dim3(256), 0, st, c->d_grid, c->B,
-                       c->d_bin_start, c->d_col_ncl, c->d_col_ngrp, c->cap_cols, c->G, c->dsc);
-    launch_scan(c->d_col_ncl, c->d_col_cl0, c->cap_cols + 1, c->d_scan_tmp, nullptr, st);
-    launch_scan(c->d_col_ngrp, c->d_col_grp0, c->cap_cols + 1, c->d_scan_tmp, nullptr, st);
     {
-        ClusterArgs A{x, y, z, type, c->d_grid, c->B, c->d_bin_start, c->d_sorted,
-                      c->d_col_cl0, c->d_col_grp0, c->d_img, c->d_perm, c->d_inv_perm,
-                      c->d_slot_img, c->d_ts, c->d_cl_lo, c->d_cl_hi, c->d_groups,
-                      c->d_sys_grp0, c->cap_clusters, c->G, c->T, c->dsc};
-        const int nb = (int)std::min<int64_t>(div_up(std::max<int64_t>(c->cap_clusters, c->B), 256),
-                                              4096);
+        BinArgs A{N, x, y, z, c->d_sys_of_atom, c->d_grid, c->d_bin_cnt, c->d_key, c->d_rank,
+                  c->d_img, c->d_xref, c->cap_bins, c->dsc, gate};
+        const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(N, 256), wide));
+        hipLaunchKernelGGL(k_bin, dim3(nb), dim3(256), 0, st, A);
+    }
+    launch_scan(c->d_bin_cnt, c->d_bin_start, c->cap_bins + 1,
+                reinterpret_cast<int32_t*>(c->d_scan_tmp), gate, st);
+    {
+        ScatterArgs A{N, c->d_key, c->d_rank, c->d_bin_start, c->d_sorted, c->d_grid, c->B,
+                      c->d_col_cnt, c->cap_cols, c->G, c->dsc, gate};
+        const int nb = (int)std::max<int64_t>(
+            1, std::min<int64_t>(div_up(std::max<int64_t>(N, c->cap_cols + 1), 256), wide));
+        hipLaunchKernelGGL(k_scatter_cols, dim3(nb), dim3(256), 0, st, A);
+    }
+    {
+        const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(c->cap_bins, 256), wide));
+        hipLaunchKernelGGL(k_bin_sort, dim3(nb), dim3(256), 0, st, c->d_bin_start, c->d_sorted,
+                           c->d_bin_cnt, c->cap_bins, c->dsc, gate);
+    }
+    launch_scan64(c->d_col_cnt, c->d_col_pre, c->cap_cols + 1, c->d_scan_tmp, gate, st);
+    {
+        ClusterArgs A{x, y, z, type, c->d_grid, c->B, c->d_bin_start, c->d_sorted, c->d_col_pre,
+                      c->d_img, c->d_perm, c->d_inv_perm, c->d_slot_img, c->d_ts, c->d_cl_lo,
+                      c->d_cl_hi, c->d_groups, c->d_sys_grp0, c->cap_clusters, c->G, c->T,
+                      c->dsc, gate};
+        const int nb = (int)std::max<int64_t>(
+            1, std::min<int64_t>(div_up(std::max<int64_t>(c->cap_clusters, c->B), 256), wide));
         hipLaunchKernelGGL(k_clusters, dim3(nb), dim3(256), 0, st, A);
     }
     {
-        EntryArgs A{c->d_grid, c->d_col_cl0, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
-                    c->E_cap, c->rlist, c->dsc};
+        EntryArgs A{c->d_grid, c->d_col_pre, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
+                    c->E_cap, c->rlist, c->dsc, gate};
         const int nb = (int)std::min<int64_t>(div_up(c->cap_groups, 4), (int64_t)c->n_cu * 16);
         hipLaunchKernelGGL(k_group_entries, dim3(std::max(nb, 1)), dim3(256), 0, st, A);
     }
     {
         const double m = c->rlist * (1.0 + 1e-5);
         ListArgs A{x, y, z, c->d_grid, c->d_groups, c->d_ent, c->d_perm, c->d_slot_img, c->d_ts,
-                   c->d_nb, c->d_cl_nt, c->E_cap, c->nb_cap, c->nb_T, (float)(m * m), c->dsc};
-        const size_t lds = (size_t)(c->E_cap * kCluster + 1) * sizeof(float4) +
-                           (size_t)c->E_cap * sizeof(uint32_t);
+                   c->d_nb, c->d_cl_nt, c->E_cap, c->nb_cap, c->nb_T, (float)(m * m), c->dsc,
+                   gate};
         const int nb = (int)std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * 4);
-        hipLaunchKernelGGL(k_atom_lists, dim3(std::max(nb, 1)), dim3(64 * c->G), lds, st, A);
+        hipLaunchKernelGGL(k_atom_lists, dim3(std::max(nb, 1)), dim3(64 * c->G),
+                           atom_lists_lds_bytes(c->E_cap), st, A);
     }
-    hipLaunchKernelGGL(k_build_done, dim3(1), dim3(1), 0, st, c->dsc);
 }
 
 __global__ void k_skin_check(DevScalars* d)
@@ -628,9 +690,5 @@ void launch_skin_check(Ctx* c, hipStream_t st)
     hipLaunchKernelGGL(k_skin_check, dim3(1), dim3(1), 0, st, c->dsc);
 }
 
-size_t atom_lists_lds_bytes(int E_cap)
-{
-    return (size_t)(E_cap * kCluster + 1) * sizeof(float4) + (size_t)E_cap * sizeof(uint32_t);
-}
 
 }  // namespace md

@@ -116,10 +116,9 @@ struct Ctx {
     int32_t* d_bin_cnt = nullptr;  // cap_bins + 1
     int32_t* d_bin_start = nullptr;// cap_bins + 1
     int32_t* d_sorted = nullptr;   // N atoms in bin order
-    int32_t* d_scan_tmp = nullptr; // block sums for the scans
-    // columns
-    int32_t* d_col_ncl = nullptr;  int32_t* d_col_ngrp = nullptr;      // cap_cols + 1
-    int32_t* d_col_cl0 = nullptr;  int32_t* d_col_grp0 = nullptr;      // cap_cols + 1
+    int64_t* d_scan_tmp = nullptr; // block sums for the scans
+    // columns: (groups << 32 | clusters) per column and its exclusive prefix
+    int64_t* d_col_cnt = nullptr;  int64_t* d_col_pre = nullptr;       // cap_cols + 1
     // clusters / slots
     double* d_cl_lo = nullptr;     double* d_cl_hi = nullptr;          // cap_clusters*3
     int32_t* d_cl_nt = nullptr;                                        // cap_clusters
@@ -137,9 +136,6 @@ struct Ctx {
     // integrator
     double* d_xref = nullptr;      // N*3 build positions
     double* d_partial = nullptr;   // cap_partials (kinetic-energy block partials)
-    int build_calls_since = 0;
-    int nstlist = 10;
-    int64_t host_builds = 0;
 };
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }

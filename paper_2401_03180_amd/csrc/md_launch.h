@@ -9,6 +9,8 @@ namespace md {
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 void launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, const int32_t* gate,
                  hipStream_t st);
+void launch_scan64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, const int32_t* gate,
+                   hipStream_t st);
 void launch_ionize(Ctx* c, const uint8_t* elem, const uint32_t* atom_id, int8_t* q,
                    hipStream_t st);
 void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const double* fx,
@@ -20,7 +22,7 @@ void launch_clear_flags(Ctx* c, hipStream_t st);
 
 // md_build.hip
 void launch_build(Ctx* c, const double* x, const double* y, const double* z, const uint8_t* type,
-                  hipStream_t st);
+                  bool force, hipStream_t st);
 void launch_skin_check(Ctx* c, hipStream_t st);
 
 // md_force.hip

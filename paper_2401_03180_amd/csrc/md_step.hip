@@ -23,90 +23,105 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st)
 
 // Exclusive prefix sum within a block of kScanBlock threads, kScanPerThread values
 // per thread.  Returns the block total.
-__device__ int block_scan_exclusive(int (&v)[kScanPerThread], int* s_warp)
+template <class T>
+__device__ T block_scan_exclusive(T (&v)[kScanPerThread], T* s_warp)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    int t = 0;
-    for (int k = 0; k < kScanPerThread; ++k) { int x = v[k]; v[k] = t; t += x; }
+    T t = 0;
+    for (int k = 0; k < kScanPerThread; ++k) { T x = v[k]; v[k] = t; t += x; }
     // inclusive scan of per-thread totals across the wave
-    int inc = t;
+    T inc = t;
     for (int off = 1; off < 64; off <<= 1) {
-        int y = __shfl_up(inc, off, 64);
+        T y = __shfl_up(inc, off, 64);
         if (lane >= off) inc += y;
     }
     if (lane == 63) s_warp[wv] = inc;
     __syncthreads();
     if (wv == 0) {
         int nw = blockDim.x >> 6;
-        int x = lane < nw ? s_warp[lane] : 0;
-        int xi = x;
+        T x = lane < nw ? s_warp[lane] : (T)0;
+        T xi = x;
         for (int off = 1; off < 64; off <<= 1) {
-            int y = __shfl_up(xi, off, 64);
+            T y = __shfl_up(xi, off, 64);
             if (lane >= off) xi += y;
         }
         if (lane < nw) s_warp[lane] = xi - x;       // exclusive wave offsets
         if (lane == nw - 1) s_warp[64] = xi;         // block total
     }
     __syncthreads();
-    int base = s_warp[wv] + (inc - t);
+    T base = s_warp[wv] + (inc - t);
     for (int k = 0; k < kScanPerThread; ++k) v[k] += base;
-    int total = s_warp[64];
+    T total = s_warp[64];
     __syncthreads();
     return total;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_local(const int32_t* in, int32_t* out,
-                                                           int64_t n, int32_t* block_sums,
-                                                           const int32_t* gate)
+// `gate` (device int, may be NULL): the scan kernels do nothing when *gate == 0.
+template <class T>
+__global__ void __launch_bounds__(kScanBlock) k_scan_local(const T* in, T* out, int64_t n,
+                                                           T* block_sums, const int32_t* gate)
 {
     if (gate && *gate == 0) return;
-    __shared__ int s_warp[65];
-    int v[kScanPerThread];
+    __shared__ T s_warp[65];
+    T v[kScanPerThread];
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
-    for (int k = 0; k < kScanPerThread; ++k) v[k] = (base + k < n) ? in[base + k] : 0;
-    int total = block_scan_exclusive(v, s_warp);
+    for (int k = 0; k < kScanPerThread; ++k) v[k] = (base + k < n) ? in[base + k] : (T)0;
+    T total = block_scan_exclusive<T>(v, s_warp);
     for (int k = 0; k < kScanPerThread; ++k)
         if (base + k < n) out[base + k] = v[k];
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_sums(int32_t* block_sums, int nb,
+template <class T>
+__global__ void __launch_bounds__(kScanBlock) k_scan_sums(T* block_sums, int nb,
                                                           const int32_t* gate)
 {
     if (gate && *gate == 0) return;
-    __shared__ int s_warp[65];
-    int v[kScanPerThread];
+    __shared__ T s_warp[65];
+    T v[kScanPerThread];
     int base = threadIdx.x * kScanPerThread;
-    for (int k = 0; k < kScanPerThread; ++k) v[k] = (base + k < nb) ? block_sums[base + k] : 0;
-    block_scan_exclusive(v, s_warp);
+    for (int k = 0; k < kScanPerThread; ++k) v[k] = (base + k < nb) ? block_sums[base + k] : (T)0;
+    block_scan_exclusive<T>(v, s_warp);
     for (int k = 0; k < kScanPerThread; ++k)
         if (base + k < nb) block_sums[base + k] = v[k];
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_add(int32_t* out, int64_t n,
-                                                         const int32_t* block_sums,
+template <class T>
+__global__ void __launch_bounds__(kScanBlock) k_scan_add(T* out, int64_t n, const T* block_sums,
                                                          const int32_t* gate)
 {
     if (gate && *gate == 0) return;
-    int add = block_sums[blockIdx.x];
+    T add = block_sums[blockIdx.x];
     if (add == 0) return;
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
     for (int k = 0; k < kScanPerThread; ++k)
         if (base + k < n) out[base + k] += add;
 }
 
-// Exclusive scan of in[0..n) into out[0..n).  n <= kScanTile^2.  `gate` (device
-// int, may be NULL): the kernels do nothing when *gate == 0.
-void launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, const int32_t* gate,
-                 hipStream_t st)
+// Exclusive scan of in[0..n) into out[0..n).  n <= kScanTile^2; tmp holds kScanTile
+// values of type T.
+template <class T>
+static void scan_impl(const T* in, T* out, int64_t n, T* tmp, const int32_t* gate, hipStream_t st)
 {
     if (n <= 0) return;
     int nb = (int)div_up(n, kScanTile);
-    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, st, in, out, n, tmp, gate);
+    hipLaunchKernelGGL(k_scan_local<T>, dim3(nb), dim3(kScanBlock), 0, st, in, out, n, tmp, gate);
     if (nb > 1) {
-        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, tmp, nb, gate);
-        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, st, out, n, tmp, gate);
+        hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(kScanBlock), 0, st, tmp, nb, gate);
+        hipLaunchKernelGGL(k_scan_add<T>, dim3(nb), dim3(kScanBlock), 0, st, out, n, tmp, gate);
     }
+}
+
+void launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, const int32_t* gate,
+                 hipStream_t st)
+{
+    scan_impl<int32_t>(in, out, n, tmp, gate, st);
+}
+
+void launch_scan64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, const int32_t* gate,
+                   hipStream_t st)
+{
+    scan_impl<int64_t>(in, out, n, tmp, gate, st);
 }
 
 // ------------------------------------------------------------------ Philox4x32-10

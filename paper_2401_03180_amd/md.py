@@ -21,14 +21,14 @@ MD_ERR_GEOMETRY, MD_ERR_DEVICE, MD_ERR_STATE = -4, -5, -6
 MD_FP64, MD_FP32_KAHAN = 0, 1
 MD_BUILD_AUTO, MD_BUILD_FORCE, MD_BUILD_CHECK = 0, 1, 2
 MD_FLAG_CELL_OVERFLOW, MD_FLAG_LIST_OVERFLOW, MD_FLAG_SKIN = 0x1, 0x2, 0x4
-MD_FLAG_NONFINITE, MD_FLAG_STEP = 0x8, 0x10
+MD_FLAG_NONFINITE, MD_FLAG_STEP, MD_FLAG_BAD_INPUT = 0x8, 0x10, 0x20
 MD_MAX_TYPES, MD_MAX_ELEMENTS, MD_MAX_CHARGE_STATES = 8, 8, 128
 
 EXPORTED = (
     "md_create", "md_destroy", "md_last_error", "md_bind_tables", "md_set_step", "md_get_step",
-    "md_build_cells", "md_set_nstlist", "md_ionize_step", "md_screened_forces",
+    "md_build_cells", "md_ionize_step", "md_screened_forces",
     "md_integrate_vv", "md_sync_check", "md_clear_flags", "md_debug_pairs", "md_get_stats",
-    "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
+    "md_time_forces", "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
     "md_rates_from_fractions",
 )
 
@@ -83,13 +83,14 @@ def lib():
             "md_create": [P, P, P], "md_destroy": [P], "md_last_error": [P],
             "md_bind_tables": [P, P, P, P, P, P, P, P, P, i64],
             "md_set_step": [P, i64, P], "md_get_step": [P, P, P],
-            "md_build_cells": [P, P, P, P, P, i32, P], "md_set_nstlist": [P, i32],
+            "md_build_cells": [P, P, P, P, P, i32, P],
             "md_ionize_step": [P, P, P, P, P],
             "md_screened_forces": [P, ctypes.c_int, P, P, P, P, P, P, P, P, P, P],
             "md_integrate_vv": [P, i32, f64, P, P, P, P, P, P, P, P, P, P, P, P],
             "md_sync_check": [P, P, P], "md_clear_flags": [P, P],
             "md_debug_pairs": [P, ctypes.c_int, P, P, P, P, P, P, i64, P],
             "md_get_stats": [P, P, P], "md_step": [P, P, i32, P],
+            "md_time_forces": [P, ctypes.c_int, P, P, P, P, P, P, P, P, P, i32, P, P],
             "md_graph_create": [P, P, i32, P, P], "md_graph_launch": [P, P],
             "md_graph_destroy": [P], "md_debye_length_nm": [f64, f64],
             "md_rates_from_fractions": [i64, i32, P, P],
@@ -160,10 +161,6 @@ def md_get_step(ctx, stream=None) -> int:
     return v.value
 
 
-def md_set_nstlist(ctx, n):
-    _check(ctx, lib().md_set_nstlist(ctx, int(n)))
-
-
 def md_build_cells(ctx, x, y, z, type_, mode=MD_BUILD_FORCE, stream=None):
     _check(ctx, lib().md_build_cells(ctx, _ptr(x), _ptr(y), _ptr(z), _ptr(type_), int(mode),
                                      _stream(stream)))
@@ -209,6 +206,14 @@ def md_debug_pairs(ctx, prec, x, y, z, q, max_pairs, stream=None) -> np.ndarray:
     return buf[:n.value]
 
 
+def md_time_forces(ctx, prec, x, y, z, q, type_, fx, fy, fz, epot, reps, stream=None) -> float:
+    ms = ctypes.c_float()
+    _check(ctx, lib().md_time_forces(ctx, int(prec), _ptr(x), _ptr(y), _ptr(z), _ptr(q),
+                                     _ptr(type_), _ptr(fx), _ptr(fy), _ptr(fz), _ptr(epot),
+                                     int(reps), ctypes.byref(ms), _stream(stream)))
+    return ms.value
+
+
 def md_get_stats(ctx, stream=None) -> dict:
     s = md_stats()
     _check(ctx, lib().md_get_stats(ctx, ctypes.byref(s), _stream(stream)))
@@ -219,9 +224,9 @@ def md_step(ctx, args: md_step_args, build_mode=MD_BUILD_AUTO, stream=None):
     _check(ctx, lib().md_step(ctx, ctypes.byref(args), int(build_mode), _stream(stream)))
 
 
-def md_graph_create(ctx, args: md_step_args, with_rebuild, stream):
+def md_graph_create(ctx, args: md_step_args, build_mode, stream):
     h = ctypes.c_void_p()
-    _check(ctx, lib().md_graph_create(ctx, ctypes.byref(args), int(with_rebuild),
+    _check(ctx, lib().md_graph_create(ctx, ctypes.byref(args), int(build_mode),
                                       _stream(stream), ctypes.byref(h)))
     return h
 
@@ -258,7 +263,7 @@ class Engine:
     """
 
     def __init__(self, sys, precision=MD_FP32_KAHAN, cluster_group=0, skin=None,
-                 density_hint=0.0, nstlist=10, max_neighbors=0, device="cuda"):
+                 density_hint=0.0, max_neighbors=0, device="cuda"):
         import torch
         self.torch = torch
         self.sys = sys
@@ -294,7 +299,6 @@ class Engine:
         self.ctx = md_create(cfg, sys.sys_offsets)
         md_bind_tables(self.ctx, sys.box, sys.c6, sys.c12, sys.qmax, sys.lambda_d, sys.base,
                        sys.g, sys.seeds, sys.n_steps)
-        md_set_nstlist(self.ctx, nstlist)
         self.graphs = {}
 
     def close(self):
@@ -343,6 +347,11 @@ class Engine:
     def step(self, build_mode=MD_BUILD_AUTO, energy=True, ekin=True, stream=None):
         md_step(self.ctx, self.step_args(energy, ekin), build_mode, stream)
 
+    def time_forces(self, reps=20, prec=None, energy=True, stream=None):
+        return md_time_forces(self.ctx, self.prec if prec is None else prec, self.x, self.y,
+                              self.z, self.q, self.type, self.fx, self.fy, self.fz,
+                              self.epot if energy else None, reps, stream)
+
     def set_step(self, k, stream=None):
         md_set_step(self.ctx, k, stream)
 
@@ -362,11 +371,12 @@ class Engine:
                            self.q, max_pairs)
         return p
 
-    def graph(self, with_rebuild, stream, energy=False, ekin=False):
-        key = (bool(with_rebuild), energy, ekin)
+    def graph(self, build_mode, stream, energy=False, ekin=False):
+        """Executable graph of one full step (captured once per argument set)."""
+        key = (int(build_mode), energy, ekin)
         if key not in self.graphs:
             self.graphs[key] = md_graph_create(self.ctx, self.step_args(energy, ekin),
-                                               with_rebuild, stream)
+                                               build_mode, stream)
         return self.graphs[key]
 
     def host(self, name):

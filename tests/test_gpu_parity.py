@@ -206,7 +206,7 @@ def test_trajectory_against_oracle(prec):
     s = synth.water_small(n_steps=20)
     s.base[:] = np.where(s.base > 0, 0.05, 0.0)
     say("trajectory prec", prec)
-    eng = make_engine(s, prec, nstlist=5)
+    eng = make_engine(s, prec)
     qs, ep = _run_engine(eng, 20, 0)
     ref = oracle.run(s, 20)
     for k in range(20):
@@ -307,15 +307,15 @@ def test_graph_replay_matches_eager():
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
-        g_reb = eb.graph(True, stream)
-        g_chk = eb.graph(False, stream)
-    # capture does not execute; restart both from the same state
+        g_reb = eb.graph(1, stream)          # forced rebuild every step
+        g_auto = eb.graph(0, stream)         # device-decided rebuild
+    # capture does not execute anything; both engines start from the same state
     for step in range(12):
         reb = step % 4 == 3
-        ea.step(build_mode=1 if reb else 2, energy=False, ekin=False)
+        ea.step(build_mode=1 if reb else 0, energy=False, ekin=False)
         torch.cuda.synchronize()
         from paper_2401_03180_amd.md import md_graph_launch
-        md_graph_launch(g_reb if reb else g_chk, stream)
+        md_graph_launch(g_reb if reb else g_auto, stream)
         stream.synchronize()
         _ = eb.host("x")                       # eager work between replays
         for name in ("x", "vx", "q", "fx"):
