@@ -172,7 +172,11 @@ def main():
     value = n * a.steps / (r32["ms"] * 1e-3)
     extra = {"flags": r32["flags"], "rebuilds_timed": r32["builds"],
              "pairs_in_cutoff": r32["pairs"], "list_codes": r32["stats"]["n_list_codes"],
-             "groups": r32["stats"]["n_groups"], "cluster_group": r32["stats"]["cluster_group"]}
+             "groups": r32["stats"]["n_groups"], "cluster_group": r32["stats"]["cluster_group"],
+             "max_group_entries": r32["stats"]["max_group_entries"],
+             "group_entry_capacity": r32["stats"]["group_entry_capacity"],
+             "max_list_len": r32["stats"]["max_list_len"],
+             "list_capacity": r32["stats"]["list_capacity"]}
     if not a.no_fp64:
         sys64 = make_system(a.config, S)
         r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, a.cluster_group, a.skin,

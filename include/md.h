@@ -62,7 +62,9 @@ typedef enum md_precision {
 
 /* Device error word bits (latched until md_clear_flags). */
 #define MD_FLAG_CELL_OVERFLOW 0x1u   /* grid/cluster capacity exceeded during a build */
-#define MD_FLAG_LIST_OVERFLOW 0x2u   /* neighbour-list capacity exceeded: pairs may be missing */
+#define MD_FLAG_LIST_OVERFLOW 0x2u   /* neighbour-list capacity exceeded: pairs may be missing
+                                        (the per-atom lists are written by the first
+                                        md_screened_forces after a build, which latches it) */
 #define MD_FLAG_SKIN 0x4u            /* forces were evaluated (or MD_BUILD_CHECK ran) while some
                                         atom had moved more than skin/2 since the last build */
 #define MD_FLAG_NONFINITE 0x8u       /* non-finite position seen by a build */

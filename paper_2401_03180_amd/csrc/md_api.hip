@@ -53,8 +53,8 @@ void free_all(Ctx* c)
                     c->d_base, c->d_g, c->d_seeds, c->d_key, c->d_rank, c->d_img,
                     c->d_bin_cnt, c->d_bin_start, c->d_sorted, c->d_scan_tmp, c->d_col_cnt,
                     c->d_col_pre, c->d_cl_lo, c->d_cl_hi,
-                    c->d_cl_nt, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_qs,
-                    c->d_ts, c->d_groups, c->d_ent, c->d_nb, c->d_grp_epot, c->d_xref,
+                    c->d_cl_nt, c->d_cl_len, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_qs,
+                    c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
                     c->d_partial};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -125,6 +125,11 @@ md_status md_create(const md_config* cfg, const int64_t* sys_offsets, md_ctx** o
         return fail(nullptr, MD_ERR_HIP, "no HIP device: %s", hipGetErrorString(e));
     }
     c->max_lds = (size_t)lds;
+    int lds_cu = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              c->device) != hipSuccess || lds_cu <= 0)
+        lds_cu = lds;
+    c->lds_per_cu = (size_t)std::max(lds_cu, lds);
     *out = ctx;
     return MD_OK;
 }
@@ -143,8 +148,21 @@ static md_status size_and_allocate(Ctx* c)
     const md_config& cfg = c->cfg;
     const int64_t N = c->N;
     const int B = c->B;
-    const double rho = cfg.density_hint > 0 ? cfg.density_hint : 130.0;
     const double rl = c->rlist;
+    // sizing density: the hint, else 1.1 x the densest periodic box, else 130 / nm^3
+    double rho = cfg.density_hint;
+    if (!(rho > 0.0)) {
+        rho = 130.0;
+        if (cfg.periodic) {
+            double mx = 0.0;
+            for (int b = 0; b < B; ++b) {
+                const double* L = &c->box[3 * b];
+                mx = std::max(mx, (double)(c->sys_off[b + 1] - c->sys_off[b]) /
+                                      (L[0] * L[1] * L[2]));
+            }
+            rho = std::max(1.1 * mx, 1.0);
+        }
+    }
     const double a = cbrt(8.0 / rho);
 
     // periodic grids are fixed by the boxes
@@ -186,16 +204,20 @@ static md_status size_and_allocate(Ctx* c)
     c->cap_slots = c->cap_clusters * kCluster;
     c->cap_groups = c->cap_clusters;
 
-    // group candidate-table capacity from the rounded-box volume around a group
+    // group candidate-table capacity from the rounded-box volume around a group; the
+    // force and list kernels stage one group's candidates in LDS, so the capacity is
+    // also bounded by the LDS of one work-group (the group size shrinks if needed)
     int G = c->G;
     int E_cap = 0;
     for (;;) {
         const double X = 2.0 * a, Y = 2.0 * a, Z = (G + 1) * a;
         const double V = X * Y * Z + 2.0 * rl * (X * Y + X * Z + Y * Z) +
                          M_PI * rl * rl * (X + Y + Z) + 4.0 / 3.0 * M_PI * rl * rl * rl;
-        const int est = (int)(V * rho / kCluster * 1.25) + 16;
-        const int lds_cap = (int)((c->max_lds - 2048) / (kCluster * sizeof(float4) + 4)) - 1;
-        E_cap = std::min({est, kMaxGroupEntries, lds_cap});
+        const int est = (int)(V * rho / kCluster * 1.35) + 16;
+        E_cap = std::min(est, kMaxGroupEntries);
+        while (E_cap > 32 && (atom_lists_lds_bytes(E_cap, 2 * G) + 1024 > c->max_lds ||
+                              force32_lds_bytes(E_cap) + 8192 > c->max_lds))
+            E_cap -= 8;
         if (E_cap >= est || G == 1) break;
         G /= 2;
     }
@@ -206,7 +228,9 @@ static md_status size_and_allocate(Ctx* c)
     if (nb_cap <= 0) nb_cap = (int)(4.0 / 3.0 * M_PI * rl * rl * rl * rho * 1.2) + 16;
     nb_cap = (nb_cap + 7) & ~7;
     c->nb_cap = nb_cap;
-    c->nb_T = nb_cap / 8;
+    // two half-lists per atom (entries of even / odd index), each with some slack
+    c->nb_cap_h = ((nb_cap / 2 + nb_cap / 16 + 8) + 31) & ~31;     // rows of 32 codes
+    c->nb_Th = c->nb_cap_h / 8;
     c->cap_partials = vv_partials_needed(N, B);
 
     // allocation
@@ -228,7 +252,8 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, dalloc(&c->d_col_pre, c->cap_cols + 1));
     HIP_TRY(c, dalloc(&c->d_cl_lo, 3 * c->cap_clusters));
     HIP_TRY(c, dalloc(&c->d_cl_hi, 3 * c->cap_clusters));
-    HIP_TRY(c, dalloc(&c->d_cl_nt, c->cap_clusters));
+    HIP_TRY(c, dalloc(&c->d_cl_nt, 2 * c->cap_clusters));
+    HIP_TRY(c, dalloc(&c->d_cl_len, 2 * c->cap_clusters));
     HIP_TRY(c, dalloc(&c->d_perm, c->cap_slots));
     HIP_TRY(c, dalloc(&c->d_slot_img, c->cap_slots));
     HIP_TRY(c, dalloc(&c->d_inv_perm, N));
@@ -237,7 +262,8 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, dalloc(&c->d_ts, c->cap_slots));
     HIP_TRY(c, dalloc(&c->d_groups, c->cap_groups));
     HIP_TRY(c, dalloc(&c->d_ent, c->cap_groups * (int64_t)E_cap));
-    HIP_TRY(c, dalloc(&c->d_nb, c->cap_clusters * (int64_t)c->nb_T * 64));
+    HIP_TRY(c, dalloc(&c->d_ent_mask, c->cap_groups * (int64_t)E_cap));
+    HIP_TRY(c, dalloc(&c->d_nb, c->cap_clusters * 2 * (int64_t)c->nb_Th * 64));
     HIP_TRY(c, dalloc(&c->d_grp_epot, c->cap_groups));
     HIP_TRY(c, dalloc(&c->d_xref, 3 * N));
     HIP_TRY(c, dalloc(&c->d_partial, c->cap_partials));
@@ -261,7 +287,8 @@ static md_status size_and_allocate(Ctx* c)
         HIP_TRY(c, hipMemcpy(c->d_grid, grids.data(), sizeof(GridSys) * B, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemset(c->d_perm, 0xFF, sizeof(int32_t) * c->cap_slots));
     HIP_TRY(c, hipMemset(c->d_bin_cnt, 0, sizeof(int32_t) * (c->cap_bins + 1)));
-    HIP_TRY(c, hipMemset(c->d_cl_nt, 0, sizeof(int32_t) * c->cap_clusters));
+    HIP_TRY(c, hipMemset(c->d_cl_nt, 0, sizeof(int32_t) * 2 * c->cap_clusters));
+    HIP_TRY(c, hipMemset(c->d_cl_len, 0, sizeof(int32_t) * 2 * c->cap_clusters));
     HIP_TRY(c, hipMemset(c->d_groups, 0, sizeof(Group) * c->cap_groups));
     HIP_TRY(c, hipMemset(c->d_xref, 0, sizeof(double) * 3 * std::max<int64_t>(N, 1)));
     HIP_TRY(c, hipMemset(c->d_sys_grp0, 0, sizeof(int32_t) * (B + 1)));
@@ -535,7 +562,7 @@ md_status md_get_stats(md_ctx* ctx, md_stats* out, md_stream stream)
     memset(out, 0, sizeof *out);
     out->n_atoms = c->N;
     out->cluster_group = c->G;
-    out->list_capacity = c->nb_cap;
+    out->list_capacity = c->nb_cap_h;
     out->group_entry_capacity = c->E_cap;
     if (!c->tables_bound) return MD_OK;
     HIP_TRY(c, hipStreamSynchronize(S(stream)));
@@ -543,18 +570,34 @@ md_status md_get_stats(md_ctx* ctx, md_stats* out, md_stream stream)
     HIP_TRY(c, hipMemcpy(&h, c->dsc, sizeof h, hipMemcpyDeviceToHost));
     out->n_clusters = h.n_clusters;
     out->n_groups = h.n_groups;
-    out->n_list_codes = h.n_codes;
-    out->max_list_len = h.max_list;
-    out->max_group_entries = h.max_entries;
     out->n_builds = h.n_builds;
     out->flags = h.flags;
-    int64_t ne = 0;
+    int64_t ne = 0, max_e = 0, codes = 0, max_l = 0;
     if (h.n_groups > 0) {
         std::vector<Group> gr(h.n_groups);
         HIP_TRY(c, hipMemcpy(gr.data(), c->d_groups, sizeof(Group) * h.n_groups,
                              hipMemcpyDeviceToHost));
-        for (const Group& x : gr) ne += x.nent;
+        for (const Group& x : gr) {
+            ne += x.nent;
+            max_e = std::max<int64_t>(max_e, x.nent_raw);
+        }
     }
+    if (h.n_clusters > 0) {
+        // list lengths: rows give the code count up to padding; the longest half-list per
+        // cluster is kept exactly
+        std::vector<int32_t> len(2 * (size_t)h.n_clusters), nt(2 * (size_t)h.n_clusters);
+        HIP_TRY(c, hipMemcpy(len.data(), c->d_cl_len, sizeof(int32_t) * len.size(),
+                             hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(nt.data(), c->d_cl_nt, sizeof(int32_t) * nt.size(),
+                             hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < len.size(); ++i) {
+            max_l = std::max<int64_t>(max_l, len[i]);
+            codes += (int64_t)nt[i] * 32 * kCluster;    // padded code slots
+        }
+    }
+    out->n_list_codes = codes;
+    out->max_list_len = max_l;
+    out->max_group_entries = max_e;
     out->n_entries = ne;
     return MD_OK;
 }

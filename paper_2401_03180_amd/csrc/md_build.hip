@@ -42,6 +42,17 @@ __device__ inline int upper_index(const int32_t* arr, int n, int v)
     return lo;
 }
 
+// End of a candidate-table build: the per-atom lists are now pending (the next
+// force evaluation rebuilds them), the displacement reference is the new one.
+__global__ void k_build_done(DevScalars* d, const int32_t* gate)
+{
+    if (gate && *gate == 0) return;
+    d->need_rebuild = 0;
+    d->lists_pending = 1;
+    d->disp2_bits = 0ull;
+    d->n_builds += 1;
+}
+
 // Every build kernel takes `gate`: NULL runs it unconditionally (forced build);
 // otherwise it returns at once unless *gate (the device rebuild request) is set.
 __device__ inline bool gated_off(const int32_t* gate) { return gate && *gate == 0; }
@@ -204,11 +215,6 @@ __global__ void __launch_bounds__(256) k_bin(BinArgs A)
 {
     if (gated_off(A.gate)) return;
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gid == 0) {
-        A.dsc->max_entries = 0;
-        A.dsc->max_list = 0;
-        A.dsc->n_codes = 0;
-    }
     for (int64_t a = gid; a < A.N; a += (int64_t)gridDim.x * blockDim.x)
         bin_one(A, a);
 }
@@ -290,6 +296,8 @@ struct ClusterArgs {
     int32_t* inv_perm;
     int32_t* slot_img;
     uint8_t* ts;
+    double* xs;
+    int64_t cap_slots;
     double* cl_lo;
     double* cl_hi;
     Group* groups;
@@ -353,6 +361,7 @@ __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
                 if (ty >= A.T) { set_flag(A.dsc, MD_FLAG_BAD_INPUT); ty = A.T - 1; }
                 A.ts[slot] = (uint8_t)ty;
                 const double p[3] = {A.x[a], A.y[a], A.z[a]};
+                for (int d = 0; d < 3; ++d) A.xs[d * A.cap_slots + slot] = p[d];
                 for (int d = 0; d < 3; ++d) {
                     const double w = g.periodic ? p[d] - (double)unpack_img(im, d) * g.L[d] : p[d];
                     lo[d] = fmin(lo[d], w);
@@ -362,6 +371,7 @@ __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
                 A.perm[slot] = -1;
                 A.slot_img[slot] = 0;
                 A.ts[slot] = 0;
+                for (int d = 0; d < 3; ++d) A.xs[d * A.cap_slots + slot] = NAN;
             }
         }
         for (int d = 0; d < 3; ++d) {
@@ -390,24 +400,32 @@ struct EntryArgs {
     const double* cl_hi;
     Group* groups;
     uint32_t* ent;
+    uint8_t* ent_mask;
     int E_cap;
     double rlist;
     DevScalars* dsc;
     const int32_t* gate;
 };
 
-// One wave per group.  Candidates are visited in a fixed order and appended with a
-// ballot prefix, so the table is deterministic.
-__global__ void __launch_bounds__(256) k_group_entries(EntryArgs A)
+// One work-group (4 waves) per group.  The candidate columns are dealt round-robin
+// to the waves; each wave appends its passing (cluster, shift) candidates in a
+// fixed order with a ballot prefix, and the four wave lists are concatenated in
+// wave order, so the table is deterministic.
+constexpr int kEntryWaves = 4;
+
+__global__ void __launch_bounds__(64 * kEntryWaves) k_group_entries(EntryArgs A)
 {
     if (gated_off(A.gate)) return;
+    extern __shared__ uint32_t s_eb[];                     // [waves][E_cap] entries
+    uint8_t* s_mb = reinterpret_cast<uint8_t*>(s_eb + kEntryWaves * A.E_cap);  // masks
+    __shared__ int s_cnt[kEntryWaves];
+    __shared__ double s_cb[kMaxGroup][6];
     const int lane = threadIdx.x & 63;
-    const int64_t wave0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ngroups = A.dsc->n_groups;
     const double rl = A.rlist, rl2 = rl * rl;
-    for (int64_t g = wave0; g < ngroups; g += nwaves) {
-        Group gr = A.groups[g];
+    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const Group gr = A.groups[g];
         const GridSys gs = A.grid[gr.sys];
         double lo[3], hi[3];
         for (int d = 0; d < 3; ++d) {
@@ -435,107 +453,182 @@ __global__ void __launch_bounds__(256) k_group_entries(EntryArgs A)
                 cr[d][1] = (int)fmin(f1, lim1);
             }
         }
-        const int nsz = gs.periodic ? 3 : 1;
+        const int ncy = cr[1][1] - cr[1][0] + 1;
+        const int ncol = (cr[0][1] - cr[0][0] + 1) * max(ncy, 0);
+        uint32_t* my_e = s_eb + w * A.E_cap;
+        uint8_t* my_m = s_mb + w * A.E_cap;
+        // bounding boxes of the group's own clusters (for the reach masks)
+        if (threadIdx.x < gr.ncl * 6) {
+            const int c = threadIdx.x / 6, d = threadIdx.x % 6;
+            s_cb[c][d] = d < 3 ? A.cl_lo[(gr.cl0 + c) * 3 + d] : A.cl_hi[(gr.cl0 + c) * 3 + d - 3];
+        }
+        __syncthreads();
         int count = 0;
-        for (int cx = cr[0][0]; cx <= cr[0][1]; ++cx) {
+        for (int ci = w; ci < ncol; ci += kEntryWaves) {
+            const int cx = cr[0][0] + ci / ncy, cy = cr[1][0] + ci % ncy;
             const int cxw = ((cx % gs.n[0]) + gs.n[0]) % gs.n[0];
             const int sx = (cx - cxw) / gs.n[0];
-            if (sx < -1 || sx > 1) continue;
-            for (int cy = cr[1][0]; cy <= cr[1][1]; ++cy) {
-                const int cyw = ((cy % gs.n[1]) + gs.n[1]) % gs.n[1];
-                const int sy = (cy - cyw) / gs.n[1];
-                if (sy < -1 || sy > 1) continue;
-                const int col = gs.col_off + cxw * gs.n[1] + cyw;
-                const int j0 = col_cl0(A.col_pre, col), j1 = col_cl0(A.col_pre, col + 1);
-                const int cand = (j1 - j0) * nsz;
-                for (int base = 0; base < cand; base += 64) {
-                    const int cidx = base + lane;
-                    bool pass = false;
-                    int J = 0, sz = 0;
-                    if (cidx < cand) {
-                        J = j0 + cidx / nsz;
-                        sz = nsz == 3 ? cidx % 3 - 1 : 0;
-                        const int sh[3] = {sx, sy, sz};
-                        double d2 = 0.0;
-                        for (int d = 0; d < 3; ++d) {
-                            const double s = gs.periodic ? sh[d] * gs.L[d] : 0.0;
-                            const double jl = A.cl_lo[J * 3 + d] + s, jh = A.cl_hi[J * 3 + d] + s;
-                            const double gap = fmax(0.0, fmax(jl - hi[d], lo[d] - jh));
-                            d2 += gap * gap;
-                        }
-                        pass = d2 < rl2;
+            const int cyw = ((cy % gs.n[1]) + gs.n[1]) % gs.n[1];
+            const int sy = (cy - cyw) / gs.n[1];
+            if (sx < -1 || sx > 1 || sy < -1 || sy > 1) continue;
+            const int col = gs.col_off + cxw * gs.n[1] + cyw;
+            const int j0 = col_cl0(A.col_pre, col), j1 = col_cl0(A.col_pre, col + 1);
+            const double shx = gs.periodic ? sx * gs.L[0] : 0.0;
+            const double shy = gs.periodic ? sy * gs.L[1] : 0.0;
+            for (int base = j0; base < j1; base += 64) {
+                // each lane tests one cluster J of the column for every z image
+                const int J = base + lane;
+                double jlo[3] = {0, 0, 0}, jhi[3] = {0, 0, 0};
+                double dxy2 = INFINITY;
+                if (J < j1) {
+                    for (int d = 0; d < 3; ++d) {
+                        jlo[d] = A.cl_lo[(int64_t)J * 3 + d];
+                        jhi[d] = A.cl_hi[(int64_t)J * 3 + d];
                     }
+                    jlo[0] += shx; jhi[0] += shx;
+                    jlo[1] += shy; jhi[1] += shy;
+                    const double gx = fmax(0.0, fmax(jlo[0] - hi[0], lo[0] - jhi[0]));
+                    const double gy = fmax(0.0, fmax(jlo[1] - hi[1], lo[1] - jhi[1]));
+                    dxy2 = gx * gx + gy * gy;
+                }
+                for (int sz = gs.periodic ? -1 : 0; sz <= (gs.periodic ? 1 : 0); ++sz) {
+                    const double shz = gs.periodic ? sz * gs.L[2] : 0.0;
+                    const double zl = jlo[2] + shz, zh = jhi[2] + shz;
+                    const double gz = fmax(0.0, fmax(zl - hi[2], lo[2] - zh));
+                    const bool pass = dxy2 + gz * gz < rl2;
                     const unsigned long long bal = __ballot(pass);
-                    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+                    if (bal == 0ull) continue;
+                    uint32_t cmask = 0u;
                     if (pass) {
-                        const int pos = count + before;
-                        if (pos < A.E_cap)
-                            A.ent[g * A.E_cap + pos] = (uint32_t)J | ((uint32_t)(sx + 1) << 26) |
-                                                       ((uint32_t)(sy + 1) << 28) |
-                                                       ((uint32_t)(sz + 1) << 30);
+                        // which clusters of the group this candidate can reach
+                        for (int c = 0; c < gr.ncl; ++c) {
+                            const double ax = fmax(0.0, fmax(jlo[0] - s_cb[c][3], s_cb[c][0] - jhi[0]));
+                            const double ay = fmax(0.0, fmax(jlo[1] - s_cb[c][4], s_cb[c][1] - jhi[1]));
+                            const double az = fmax(0.0, fmax(zl - s_cb[c][5], s_cb[c][2] - zh));
+                            if (ax * ax + ay * ay + az * az < rl2) cmask |= 1u << c;
+                        }
+                        const int pos = count + __popcll(bal & ((1ull << lane) - 1ull));
+                        if (pos < A.E_cap) {
+                            my_e[pos] = (uint32_t)J | ((uint32_t)(sx + 1) << 26) |
+                                        ((uint32_t)(sy + 1) << 28) | ((uint32_t)(sz + 1) << 30);
+                            my_m[pos] = (uint8_t)cmask;
+                        }
                     }
                     count += __popcll(bal);
                 }
             }
         }
-        if (lane == 0) {
+        if (lane == 0) s_cnt[w] = count;
+        __syncthreads();
+        int off = 0, total = 0;
+        for (int v = 0; v < kEntryWaves; ++v) {
+            if (v < w) off += s_cnt[v];
+            total += s_cnt[v];
+        }
+        const int mine = min(count, A.E_cap);
+        for (int i = lane; i < mine; i += 64) {
+            const int pos = off + i;
+            if (pos < A.E_cap) {
+                A.ent[(int64_t)g * A.E_cap + pos] = my_e[i];
+                A.ent_mask[(int64_t)g * A.E_cap + pos] = my_m[i];
+            }
+        }
+        if (threadIdx.x == 0) {
             for (int d = 0; d < 3; ++d) {
                 if (!finite_box) { lo[d] = 0.0; hi[d] = 0.0; }
                 A.groups[g].lo[d] = lo[d];
                 A.groups[g].hi[d] = hi[d];
                 A.groups[g].c[d] = 0.5 * (lo[d] + hi[d]);
             }
-            A.groups[g].nent = min(count, A.E_cap);
-            atomicMax(&A.dsc->max_entries, count);
-            if (count > A.E_cap) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
+            A.groups[g].nent = min(total, A.E_cap);
+            A.groups[g].nent_raw = total;
+            if (total > A.E_cap) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
         }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------- per-atom codes
 
+__host__ __device__ inline int wl_capacity(int E_cap) { return E_cap / 2 + 8; }
+
+// Byte offsets of the list kernel's LDS pieces, each 16-byte aligned.
+struct LdsLayout {
+    int ent, mask, wl, ring, total;
+};
+__host__ __device__ inline LdsLayout lists_lds_layout(int E_cap, int waves)
+{
+    auto up = [](int v) { return (v + 15) & ~15; };
+    LdsLayout L;
+    L.ent = up((E_cap * kCluster + 1) * 16);
+    L.mask = L.ent + up(E_cap * 4);
+    L.wl = L.mask + up(E_cap);
+    L.ring = L.wl + up(waves * wl_capacity(E_cap) * 2);
+    L.total = L.ring + waves * kCluster * 64 * 2;
+    return L;
+}
+
 struct ListArgs {
-    const double *x, *y, *z;     // build positions (caller order)
+    const double* xs;            // slot-order positions at build time (SoA, stride cap_slots)
+    int64_t cap_slots;
     const GridSys* grid;
     const Group* groups;
     const uint32_t* ent;
-    const int32_t* perm;
+    const uint8_t* ent_mask;
     const int32_t* slot_img;
     const uint8_t* ts;
     uint16_t* nb;
     int32_t* cl_nt;
-    int E_cap, nb_cap, nb_T;
-    float thr2;                 // (rc + skin)^2 with a relative margin
+    int32_t* cl_len;
+    int E_cap, nb_cap_h, nb_Th;  // per-half list capacity per atom, and its /8
+    int wl_cap;                  // per-wave entry-list capacity
+    float thr2;                  // (rc + skin)^2 with a relative margin
     DevScalars* dsc;
     const int32_t* gate;
 };
 
-__device__ inline float3 frame_coords(const double* x, const double* y, const double* z, int a,
-                                      int32_t img, uint32_t en, const GridSys& gs,
-                                      const double* c)
+// FP32 coordinates of slot `slot` in the group frame, shifted by the entry's image;
+// padding slots (NaN positions) are placed far away and flagged with valid = false.
+__device__ inline float3 staged_coords(const double* xs, int64_t cs, int64_t slot, int32_t img,
+                                       uint32_t en, const GridSys& gs, const double* c,
+                                       bool* valid)
 {
-    const int sh[3] = {(int)((en >> 26) & 3u) - 1, (int)((en >> 28) & 3u) - 1,
-                       (int)((en >> 30) & 3u) - 1};
-    const double p[3] = {x[a], y[a], z[a]};
+    const double p0 = xs[slot];
+    *valid = p0 == p0;
     float r[3];
     for (int d = 0; d < 3; ++d) {
-        double w = p[d];
-        if (gs.periodic) w = w - (double)(unpack_img(img, d) - sh[d]) * gs.L[d];
-        r[d] = (float)(w - c[d]);
+        double v = xs[d * cs + slot];
+        if (gs.periodic) {
+            const int sh = (int)((en >> (26 + 2 * d)) & 3u) - 1;
+            v = v - (double)(unpack_img(img, d) - sh) * gs.L[d];
+        }
+        r[d] = *valid ? (float)(v - c[d]) : kFar;
     }
     return make_float3(r[0], r[1], r[2]);
 }
 
-__global__ void __launch_bounds__(512) k_atom_lists(ListArgs A)
+// One work-group per group, two waves per cluster: wave (c, h) scans the entries
+// e = h, h + 2, ... that can reach cluster c and writes, for each of its 8 atoms, the
+// compacted codes of partners within rc + skin into that atom's half-list h.  The
+// force kernel's wave (c, h) consumes half-list h.
+__global__ void __launch_bounds__(1024) k_atom_lists(ListArgs A)
 {
     if (gated_off(A.gate)) return;
     extern __shared__ float4 s_dyn[];
-    __shared__ int s_last;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    float4* s_pos = s_dyn;
-    uint32_t* s_ent = reinterpret_cast<uint32_t*>(s_dyn + (A.E_cap * kCluster + 1));
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int cw = w >> 1, h = w & 1;
+    // LDS carve-out (16-byte aligned pieces, sizes as in atom_lists_lds_bytes)
+    char* lds = reinterpret_cast<char*>(s_dyn);
+    const LdsLayout L = lists_lds_layout(A.E_cap, (int)(blockDim.x >> 6));
+    float4* s_pos = reinterpret_cast<float4*>(lds);
+    uint32_t* s_ent = reinterpret_cast<uint32_t*>(lds + L.ent);
+    uint8_t* s_mask = reinterpret_cast<uint8_t*>(lds + L.mask);
+    uint16_t* s_wl = reinterpret_cast<uint16_t*>(lds + L.wl);
+    uint16_t* s_ring = reinterpret_cast<uint16_t*>(lds + L.ring);
     const int ngroups = A.dsc->n_groups;
     const uint16_t sentinel = (uint16_t)(A.E_cap * kCluster);
+    const int64_t cs = A.cap_slots;
     for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const Group gr = A.groups[g];
         const GridSys gs = A.grid[gr.sys];
@@ -543,82 +636,115 @@ __global__ void __launch_bounds__(512) k_atom_lists(ListArgs A)
         for (int idx = tid; idx < nst; idx += blockDim.x) {
             const int e = idx >> 3, jl = idx & 7;
             const uint32_t en = A.ent[(int64_t)g * A.E_cap + e];
-            if (jl == 0) s_ent[e] = en;
-            const int64_t slot = (int64_t)(en & kEntClusterMask) * kCluster + jl;
-            const int a = A.perm[slot];
-            float4 v;
-            if (a >= 0) {
-                const float3 f = frame_coords(A.x, A.y, A.z, a, A.slot_img[slot], en, gs, gr.c);
-                v = make_float4(f.x, f.y, f.z, (float)A.ts[slot]);
-            } else {
-                v = make_float4(kFar, kFar, kFar, -1.0f);
+            if (jl == 0) {
+                s_ent[e] = en;
+                s_mask[e] = A.ent_mask[(int64_t)g * A.E_cap + e];
             }
-            s_pos[idx] = v;
+            const int64_t slot = (int64_t)(en & kEntClusterMask) * kCluster + jl;
+            bool ok;
+            const float3 f = staged_coords(A.xs, cs, slot, A.slot_img[slot], en, gs, gr.c, &ok);
+            s_pos[idx] = make_float4(f.x, f.y, f.z, ok ? (float)A.ts[slot] : -1.0f);
         }
         __syncthreads();
-        if (w < gr.ncl) {
-            const int I = gr.cl0 + w;
+        if (cw < gr.ncl) {
+            const int I = gr.cl0 + cw;
             const int il = lane >> 3, k = lane & 7;
+            // this wave's entries: parity h and reachable from cluster cw, in order;
+            // e_self is the cluster's own unshifted entry (its diagonal is excluded)
+            uint16_t* wl = s_wl + w * A.wl_cap;
+            int ne = 0, e_self = -1;
+            for (int base = 0; base < gr.nent; base += 64) {
+                const int e = base + lane;
+                bool take = false;
+                if (e < gr.nent && (e & 1) == h) {
+                    take = ((s_mask[e] >> cw) & 1u) != 0u;
+                    const uint32_t en = s_ent[e];
+                    if ((en & kEntClusterMask) == (uint32_t)I && (en >> 26) == 0x15u) e_self = e;
+                }
+                const unsigned long long bal = __ballot(take);
+                if (take) {
+                    const int pos = ne + __popcll(bal & ((1ull << lane) - 1ull));
+                    if (pos < A.wl_cap) wl[pos] = (uint16_t)e;
+                }
+                ne += __popcll(bal);
+            }
+            for (int off = 32; off > 0; off >>= 1) e_self = max(e_self, __shfl_xor(e_self, off, 64));
+            ne = min(ne, A.wl_cap);
             const int64_t slot_i = (int64_t)I * kCluster + il;
-            const int ai = A.perm[slot_i];
-            float3 xi = make_float3(-kFar, -kFar, -kFar);
-            if (ai >= 0) xi = frame_coords(A.x, A.y, A.z, ai, A.slot_img[slot_i], 0x54000000u, gs, gr.c);
+            bool ok_i;
+            const float3 xi = staged_coords(A.xs, cs, slot_i, A.slot_img[slot_i], 0x54000000u, gs,
+                                            gr.c, &ok_i);
             int cnt = 0;
-            uint16_t* out = A.nb + (int64_t)I * A.nb_T * 64 + il * 8;
-            for (int e = 0; e < gr.nent; ++e) {
+            uint16_t* out = A.nb + ((int64_t)I * 2 + h) * A.nb_Th * 64;
+            // Codes pass through a 2-row ring in LDS, ordered by their owner lane, so
+            // every completed row (32 codes of one atom = 64 contiguous bytes of the
+            // list) is written with one 8-byte store per lane.
+            uint16_t* ring = s_ring + w * (kCluster * 64);
+            auto ring_at = [&](int atom, int pos) -> uint16_t& {
+                // owner lane pos % 8, iteration t = pos / 8 -> (row parity, lane, t % 4)
+                return ring[atom * 64 + ((pos >> 5) & 1) * 32 + (pos & 7) * 4 + ((pos >> 3) & 3)];
+            };
+            auto flush_row = [&](int row) {
+                // lane (il, k) writes codes of iterations 4 row .. 4 row + 3
+                const uint64_t v = *reinterpret_cast<const uint64_t*>(
+                    &ring[il * 64 + (row & 1) * 32 + k * 4]);
+                if ((row + 1) * 32 <= A.nb_cap_h)
+                    *reinterpret_cast<uint64_t*>(&out[((int64_t)row * 64 + il * 8 + k) * 4]) = v;
+            };
+            auto test = [&](int e) {
                 const int j = e * kCluster + k;
                 const float4 pj = s_pos[j];
                 const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
                 const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                const uint32_t en = s_ent[e];
-                const bool self = ((en & kEntClusterMask) == (uint32_t)I) &&
-                                  ((en >> 26) == 0x15u) && (k == il);
-                const bool pass = (ai >= 0) && (pj.w >= 0.0f) && (r2 < A.thr2) && !self;
+                const bool pass = ok_i && (pj.w >= 0.0f) && (r2 < A.thr2) &&
+                                  !(e == e_self && k == il);
                 const unsigned long long bal = __ballot(pass);
                 const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
                 if (pass) {
                     const int pos = cnt + __popc(mine & ((1u << k) - 1u));
-                    if (pos < A.nb_cap)
-                        out[(pos >> 3) * 64 + (pos & 7)] =
-                            (uint16_t)(j | ((int)pj.w << kCodeIdxBits));
+                    ring_at(il, pos) = (uint16_t)(j | ((int)pj.w << kCodeIdxBits));
                 }
+                const int before = cnt;
                 cnt += __popc(mine);
+                __builtin_amdgcn_wave_barrier();
+                if ((cnt >> 5) != (before >> 5)) flush_row(before >> 5);   // a row completed
+                __builtin_amdgcn_wave_barrier();
+            };
+            int i = 0;
+            for (; i + 1 < ne; i += 2) {
+                const int e0 = wl[i], e1 = wl[i + 1];
+                test(e0);
+                test(e1);
             }
+            if (i < ne) test(wl[i]);
             int mx = cnt;
             for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
-            const int nt = min((mx + 7) >> 3, A.nb_T);
-            for (int t = 0; t < nt; ++t) {
-                const int pos = t * 8 + k;
-                if (pos >= cnt) out[t * 64 + k] = sentinel;
+            // rows of 4 iterations (32 codes per atom); pad and write the open rows
+            const int nrow = min((mx + 31) >> 5, A.nb_Th >> 2);
+            for (int row = cnt >> 5; row < nrow; ++row) {
+                for (int p = 0; p < 4; ++p) {
+                    const int pos = row * 32 + p * 8 + k;
+                    if (pos >= cnt) ring_at(il, pos) = sentinel;
+                }
+                __builtin_amdgcn_wave_barrier();
+                flush_row(row);
+                __builtin_amdgcn_wave_barrier();
             }
             if (lane == 0) {
-                A.cl_nt[I] = nt;
-                atomicMax(&A.dsc->max_list, mx);
-                if (mx > A.nb_cap) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
+                A.cl_nt[(int64_t)I * 2 + h] = nrow;
+                A.cl_len[(int64_t)I * 2 + h] = mx;
+                if (mx > A.nb_cap_h || ne >= A.wl_cap) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
             }
-            if (k == 0) atomicAdd((unsigned long long*)&A.dsc->n_codes, (unsigned long long)cnt);
         }
         __syncthreads();
-    }
-    // the last work-group to finish closes the build: lists are fresh again
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(&A.dsc->ticket_build, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (s_last && tid == 0) {
-        __threadfence();
-        A.dsc->ticket_build = 0u;
-        A.dsc->need_rebuild = 0;
-        A.dsc->disp2_bits = 0ull;
-        A.dsc->n_builds += 1;
     }
 }
 
 // ---------------------------------------------------------------- orchestration
 
-size_t atom_lists_lds_bytes(int E_cap)
+size_t atom_lists_lds_bytes(int E_cap, int waves)
 {
-    return (size_t)(E_cap * kCluster + 1) * sizeof(float4) + (size_t)E_cap * sizeof(uint32_t);
+    return lists_lds_layout(E_cap, waves).total;
 }
 
 void launch_build(Ctx* c, const double* x, const double* y, const double* z,
@@ -656,28 +782,40 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
     launch_scan64(c->d_col_cnt, c->d_col_pre, c->cap_cols + 1, c->d_scan_tmp, gate, st);
     {
         ClusterArgs A{x, y, z, type, c->d_grid, c->B, c->d_bin_start, c->d_sorted, c->d_col_pre,
-                      c->d_img, c->d_perm, c->d_inv_perm, c->d_slot_img, c->d_ts, c->d_cl_lo,
-                      c->d_cl_hi, c->d_groups, c->d_sys_grp0, c->cap_clusters, c->G, c->T,
-                      c->dsc, gate};
+                      c->d_img, c->d_perm, c->d_inv_perm, c->d_slot_img, c->d_ts, c->d_xs,
+                      c->cap_slots, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_sys_grp0,
+                      c->cap_clusters, c->G, c->T, c->dsc, gate};
         const int nb = (int)std::max<int64_t>(
             1, std::min<int64_t>(div_up(std::max<int64_t>(c->cap_clusters, c->B), 256), wide));
         hipLaunchKernelGGL(k_clusters, dim3(nb), dim3(256), 0, st, A);
     }
     {
         EntryArgs A{c->d_grid, c->d_col_pre, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
-                    c->E_cap, c->rlist, c->dsc, gate};
-        const int nb = (int)std::min<int64_t>(div_up(c->cap_groups, 4), (int64_t)c->n_cu * 16);
-        hipLaunchKernelGGL(k_group_entries, dim3(std::max(nb, 1)), dim3(256), 0, st, A);
-    }
-    {
-        const double m = c->rlist * (1.0 + 1e-5);
-        ListArgs A{x, y, z, c->d_grid, c->d_groups, c->d_ent, c->d_perm, c->d_slot_img, c->d_ts,
-                   c->d_nb, c->d_cl_nt, c->E_cap, c->nb_cap, c->nb_T, (float)(m * m), c->dsc,
-                   gate};
+                    c->d_ent_mask, c->E_cap, c->rlist, c->dsc, gate};
         const int nb = (int)std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * 4);
-        hipLaunchKernelGGL(k_atom_lists, dim3(std::max(nb, 1)), dim3(64 * c->G),
-                           atom_lists_lds_bytes(c->E_cap), st, A);
+        const size_t lds = (size_t)kEntryWaves * c->E_cap * (sizeof(uint32_t) + 1);
+        hipLaunchKernelGGL(k_group_entries, dim3(std::max(nb, 1)), dim3(64 * kEntryWaves), lds,
+                           st, A);
     }
+    hipLaunchKernelGGL(k_build_done, dim3(1), dim3(1), 0, st, c->dsc, gate);
+}
+
+// Per-atom lists for the FP64 path (the FP32 force kernel builds them itself):
+// runs only while lists are pending after a candidate-table build.
+__global__ void k_lists_done(DevScalars* d) { d->lists_pending = 0; }
+
+void launch_lists(Ctx* c, hipStream_t st)
+{
+    const int32_t* gate = &c->dsc->lists_pending;
+    const double m = c->rlist * (1.0 + 1e-5);
+    ListArgs A{c->d_xs, c->cap_slots, c->d_grid, c->d_groups, c->d_ent, c->d_ent_mask,
+               c->d_slot_img, c->d_ts, c->d_nb, c->d_cl_nt, c->d_cl_len, c->E_cap, c->nb_cap_h,
+               c->nb_Th, wl_capacity(c->E_cap), (float)(m * m), c->dsc, gate};
+    const size_t lds = atom_lists_lds_bytes(c->E_cap, 2 * c->G);
+    const int per_cu = (int)std::max<size_t>(1, c->lds_per_cu / (lds + 1024));
+    const int nb = (int)std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu);
+    hipLaunchKernelGGL(k_atom_lists, dim3(std::max(nb, 1)), dim3(128 * c->G), lds, st, A);
+    hipLaunchKernelGGL(k_lists_done, dim3(1), dim3(1), 0, st, c->dsc);
 }
 
 __global__ void k_skin_check(DevScalars* d)

@@ -23,7 +23,8 @@
 namespace md {
 
 constexpr float kFarF = 1.0e4f;
-constexpr int kForceBlockMax = 64 * kMaxGroup;
+constexpr int kMaxWpc = 2;        // waves per i-cluster (FP32 kernel): one per half-list
+constexpr int kForceBlockMax = 64 * kMaxGroup * kMaxWpc;
 
 // ------------------------------------------------------------------ repack (per step)
 
@@ -69,8 +70,8 @@ void launch_repack(Ctx* c, const double* x, const double* y, const double* z, co
 struct ForceArgs {
     const Group* groups;
     const uint32_t* ent;
-    const uint16_t* nb;
-    const int32_t* cl_nt;
+    uint16_t* nb;
+    int32_t* cl_nt;
     const int32_t* perm;
     const int32_t* slot_img;
     const double* xs;            // slot-order FP64 positions (SoA, stride cap_slots)
@@ -84,7 +85,7 @@ struct ForceArgs {
     const double* c12;
     int T;
     double rc2;                  // rc * rc (FP64, rounded once)
-    int E_cap, nb_T;
+    int E_cap, nb_Th;
     int64_t cap_slots;
     double *fx, *fy, *fz;
     double* grp_epot;
@@ -94,42 +95,35 @@ struct ForceArgs {
     DevScalars* dsc;
     int2* emit;
     int64_t emit_max;
+    int wpc;
+    // list (re)build inside the FP32 kernel
+    int32_t* cl_len;
+    const uint8_t* ent_mask;
+    int nb_cap_h;
+    float thr2;                  // ((rc + skin)(1 + 1e-5))^2
 };
 
-// Sum of grp_epot over each system's groups in a fixed order (deterministic),
-// executed by the last work-group to finish.
-__device__ void finalize_epot(const ForceArgs& A, double* s_red)
+// One block after every force launch: the per-system energy as the sum of the
+// group energies in a fixed order (deterministic), and the end of a pending list
+// rebuild.
+__global__ void __launch_bounds__(256) k_force_finalize(const double* grp_epot, double* epot,
+                                                        const int32_t* sys_grp0, int B,
+                                                        DevScalars* dsc)
 {
-    for (int b = 0; b < A.B; ++b) {
-        const int g0 = A.sys_grp0[b], g1 = A.sys_grp0[b + 1];
-        double t = 0.0;
-        for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x)
-            t += __hip_atomic_load(&A.grp_epot[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += s_red[w];
-            A.epot[b] = s;
+    __shared__ double s_red[4];
+    if (epot) {
+        for (int b = 0; b < B; ++b) {
+            const int g0 = sys_grp0[b], g1 = sys_grp0[b + 1];
+            double t = 0.0;
+            for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) t += grp_epot[g];
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;
+            __syncthreads();
+            if (threadIdx.x == 0) epot[b] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
         }
     }
-}
-
-// Completion ticket; returns true in every thread of the last work-group.
-__device__ bool last_group_done(uint32_t* ticket, int* s_flag)
-{
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(ticket, 1u);
-        *s_flag = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    const bool last = *s_flag != 0;
-    if (last) __threadfence();
-    return last;
+    if (threadIdx.x == 0) dsc->lists_pending = 0;
 }
 
 template <class T>
@@ -156,14 +150,24 @@ __device__ __noinline__ int recheck_pair(const uint32_t* ent_g, const double* xs
     return r2 < rc2 ? 1 : 0;
 }
 
-__device__ __noinline__ void emit_pair(const uint32_t* ent_g, const int32_t* perm, int ai,
-                                       uint32_t idx, unsigned long long* counter, int2* out,
-                                       int64_t max)
+// Debug export: every lane whose pair is inside the cutoff with ai < aj appends
+// (ai, aj); one atomic per wave reserves the slots.
+__device__ __noinline__ void emit_pairs(bool in, const uint32_t* ent_g, const int32_t* perm,
+                                        int ai, uint32_t idx, unsigned long long* counter,
+                                        int2* out, int64_t max)
 {
-    const int64_t slot_j = slot_of_code(ent_g, idx);
-    const int aj = perm[slot_j];
-    if (ai < aj) {
-        const unsigned long long p = atomicAdd(counter, 1ull);
+    int aj = -1;
+    if (in) aj = perm[slot_of_code(ent_g, idx)];
+    const bool take = in && ai < aj;
+    const unsigned long long bal = __builtin_amdgcn_ballot_w64(take);
+    if (bal == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    unsigned long long base = 0;
+    const int leader = __builtin_ctzll(bal);
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(bal));
+    base = __shfl(base, leader, 64);
+    if (take) {
+        const unsigned long long p = base + __popcll(bal & ((1ull << lane) - 1ull));
         if ((int64_t)p < max) out[p] = make_int2(ai, aj);
     }
 }
@@ -196,6 +200,56 @@ __device__ inline double reduce8(double v)
     return v;
 }
 
+// Rebuild the half-list `half` of cluster I from the staged candidates: the codes
+// (staged index | type << 13) of partners within rc + skin, compacted per atom in
+// entry order; rows of 32 codes per atom padded with the sentinel.
+__device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int il, int k,
+                                int ai, float xi, float yi, float zi, int nent,
+                                const float4* s_j, const uint8_t* s_mask,
+                                const __attribute__((address_space(1))) uint32_t* ent_gl,
+                                int sentinel)
+{
+    const int lane = threadIdx.x & 63;
+    int cnt = 0;
+    uint16_t* out = A.nb + ((int64_t)I * 2 + half) * A.nb_Th * 64;
+    for (int e = half; e < nent; e += 2) {
+        if (((s_mask[e] >> cw) & 1u) == 0u) continue;   // out of this cluster's reach
+        const uint32_t en = ent_gl[e];
+        const int j = e * kCluster + k;
+        const float4 pj = s_j[j];
+        const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const bool self = ((en & kEntClusterMask) == (uint32_t)I) && ((en >> 26) == 0x15u) &&
+                          (k == il);
+        const bool pass = (ai >= 0) && (r2 < A.thr2) && !self;
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
+        const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
+        if (pass) {
+            const int pos = cnt + __popc(mine & ((1u << k) - 1u));
+            if (pos < A.nb_cap_h) {
+                const int tj = A.ts[(int64_t)(en & kEntClusterMask) * kCluster + k];
+                const int t = pos >> 3;
+                out[((t >> 2) * 64 + il * 8 + (pos & 7)) * 4 + (t & 3)] =
+                    (uint16_t)(j | (tj << kCodeIdxBits));
+            }
+        }
+        cnt += __popc(mine);
+    }
+    int mx = cnt;
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+    const int nrow = min((mx + 31) >> 5, A.nb_Th >> 2);
+    for (int pos = (cnt + 7 - k) / 8 * 8 + k; pos < nrow * 32; pos += 8) {
+        const int t = pos >> 3;
+        out[((t >> 2) * 64 + il * 8 + k) * 4 + (t & 3)] = (uint16_t)sentinel;
+    }
+    if (lane == 0) {
+        A.cl_nt[(int64_t)I * 2 + half] = nrow;
+        A.cl_len[(int64_t)I * 2 + half] = mx;
+        if (mx > A.nb_cap_h) atomicOr(&A.dsc->flags, MD_FLAG_LIST_OVERFLOW);
+    }
+    return nrow;
+}
+
 // ------------------------------------------------------------------ FP32 kernel
 
 template <bool ENERGY, bool EMIT, bool SCREEN_LJ>
@@ -203,51 +257,79 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 {
     extern __shared__ float4 s_j[];
     __shared__ float2 s_lj[MD_MAX_TYPES * MD_MAX_TYPES];
-    __shared__ float s_m[kMaxGroup];
-    __shared__ double s_e[kMaxGroup];
-    __shared__ int s_g, s_flag;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    __shared__ float s_m[kForceBlockMax / 64];
+    __shared__ double s_part[kForceBlockMax / 64][kCluster][4];
+    __shared__ int s_g;
+    const int tid = threadIdx.x, lane = tid & 63, nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index (uniform)
+    const int wpc = A.wpc;                     // waves per i-cluster
+    const int cw = w / wpc, half = w - cw * wpc;
+    const int il = lane >> 3, k8 = lane & 7;
     const int64_t step = clamp_step(A);
     const int ngroups = A.dsc->n_groups;
+    // candidate tables were rebuilt: (re)build the per-atom half-lists first
+    const bool rebuild = __builtin_amdgcn_readfirstlane(A.dsc->lists_pending) != 0;
     for (int i = tid; i < A.T * A.T; i += blockDim.x)
         s_lj[i] = make_float2(A.lj32[2 * i], A.lj32[2 * i + 1]);
     const int sentinel = A.E_cap * kCluster;
+    uint8_t* s_mask = reinterpret_cast<uint8_t*>(s_j + sentinel + 1);
     if (tid == 0) s_j[sentinel] = make_float4(kFarF, kFarF, kFarF, 0.0f);
     const float rc2f = (float)A.rc2;
     const int64_t cs = A.cap_slots;
+    const auto xs_g = gbl(A.xs);
 
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) s_g = (int)atomicAdd(&A.dsc->work_force, 1u);
-        __syncthreads();
-        const int g = s_g;
-        if (g >= ngroups) break;
+    // the first group of every work-group is its own index; later ones come from a
+    // shared counter (no burst of same-address atomics at launch)
+    for (int g = blockIdx.x; g < ngroups;) {
         const Group gr = A.groups[g];
         const GridSys gs = A.grid[gr.sys];
         const double kap = A.kappa[(int64_t)gr.sys * A.S1 + step];
+        const auto ent_gl = gbl(A.ent + (int64_t)g * A.E_cap);
 
-        // ---- stage the candidate atoms in the group frame
+        // ---- stage the candidate atoms in the group frame (padding slots hold NaN
+        //      positions and are never inside the cutoff)
         float m = 0.0f;
         const int nst = gr.nent * kCluster;
-        for (int idx = tid; idx < nst; idx += blockDim.x) {
-            const uint32_t en = A.ent[(int64_t)g * A.E_cap + (idx >> 3)];
-            const int64_t slot = (int64_t)(en & kEntClusterMask) * kCluster + (idx & 7);
-            const int a = A.perm[slot];
-            float4 v = make_float4(kFarF, kFarF, kFarF, 0.0f);
-            if (a >= 0) {
-                const int32_t im = A.slot_img[slot];
-                const int sh[3] = {(int)((en >> 26) & 3u) - 1, (int)((en >> 28) & 3u) - 1,
-                                   (int)((en >> 30) & 3u) - 1};
+        constexpr int U = 4;
+        for (int base = tid; base < nst; base += U * blockDim.x) {
+            uint32_t en[U];
+            int64_t slot[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * blockDim.x;
+                en[u] = idx < nst ? (uint32_t)ent_gl[idx >> 3] : 0x54000000u;
+                slot[u] = (int64_t)(en[u] & kEntClusterMask) * kCluster + (idx & 7);
+            }
+            double p[U][3];
+            int32_t im[U];
+            float qv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * blockDim.x;
+                const bool ok = idx < nst;
+                for (int d = 0; d < 3; ++d) p[u][d] = ok ? (double)xs_g[d * cs + slot[u]] : 0.0;
+                im[u] = ok ? A.slot_img[slot[u]] : 0;
+                qv[u] = ok ? (float)A.qs[slot[u]] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * blockDim.x;
+                if (idx >= nst) continue;
+                // padding slots (NaN positions) go far away, outside every cutoff
+                const bool pad = p[u][0] != p[u][0];
                 float r[3];
                 for (int d = 0; d < 3; ++d) {
-                    double p = A.xs[d * cs + slot];
-                    if (gs.periodic) p = p - (double)(unpack_img(im, d) - sh[d]) * gs.L[d];
-                    r[d] = (float)(p - gr.c[d]);
-                    m = fmaxf(m, fabsf(r[d]));
+                    double v = p[u][d];
+                    if (gs.periodic) {
+                        const int sh = (int)((en[u] >> (26 + 2 * d)) & 3u) - 1;
+                        v = v - (double)(unpack_img(im[u], d) - sh) * gs.L[d];
+                    }
+                    r[d] = pad ? kFarF : (float)(v - gr.c[d]);
+                    if (!pad) m = fmaxf(m, fabsf(r[d]));
                 }
-                v = make_float4(r[0], r[1], r[2], (float)A.qs[slot]);
+                s_j[idx] = make_float4(r[0], r[1], r[2], pad ? 0.0f : qv[u]);
+                if (rebuild && (idx & 7) == 0) s_mask[idx >> 3] = A.ent_mask[(int64_t)g * A.E_cap + (idx >> 3)];
             }
-            s_j[idx] = v;
         }
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
         if (lane == 0) s_m[w] = m;
@@ -263,21 +345,21 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                            1e-12f;
         const float lo2 = rc2f - band;
 
-        double e_w = 0.0;
-        if (w < gr.ncl) {
-            const int I = gr.cl0 + w;
-            const int il = lane >> 3;
+        double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ea = 0.0;
+        int ai = -1;
+        if (cw < gr.ncl) {
+            const int I = gr.cl0 + cw;
             const int64_t slot_i = (int64_t)I * kCluster + il;
-            const int ai = A.perm[slot_i];
+            ai = A.perm[slot_i];
             float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f;
             int tb = 0;
             if (ai >= 0) {
                 const int32_t im = A.slot_img[slot_i];
                 float r[3];
                 for (int d = 0; d < 3; ++d) {
-                    double p = A.xs[d * cs + slot_i];
-                    if (gs.periodic) p = p - (double)unpack_img(im, d) * gs.L[d];
-                    r[d] = (float)(p - gr.c[d]);
+                    double v = A.xs[d * cs + slot_i];
+                    if (gs.periodic) v = v - (double)unpack_img(im, d) * gs.L[d];
+                    r[d] = (float)(v - gr.c[d]);
                 }
                 xi = r[0]; yi = r[1]; zi = r[2];
                 qike = (float)(kKe * (double)A.qs[slot_i]);
@@ -285,17 +367,25 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             }
             const float kapf = (float)kap;
             const float nkl2 = (float)(-kap * 1.4426950408889634);   // -kappa log2(e)
-            const int nt = A.cl_nt[I];
-            const auto cp = gbl(A.nb + (int64_t)I * A.nb_T * 64 + lane);
+            // wave-uniform row count and list base (scalar loop control / addressing);
+            // each lane reads its next 4 codes with one 8-byte load, two rows ahead
+            int nr;
+            if (rebuild) {
+                nr = build_half_list(A, I, half, cw, il, k8, ai, xi, yi, zi, gr.nent, s_j,
+                                     s_mask, ent_gl, sentinel);
+                __threadfence();      // the wave reads back codes other lanes wrote
+            } else {
+                nr = A.cl_nt[(int64_t)I * 2 + half];
+            }
+            nr = __builtin_amdgcn_readfirstlane(nr);
+            const auto cp = gbl(reinterpret_cast<const uint64_t*>(
+                                A.nb + ((int64_t)I * 2 + half) * A.nb_Th * 64)) + lane;
             const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
             const GridSys* gsp = A.grid + gr.sys;
             float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-            float ax = 0.f, ay = 0.f, az = 0.f;
+            float ax = 0.f, ay = 0.f, az = 0.f, ea = 0.f;
             double eacc = 0.0;
-            uint32_t code_next = nt > 0 ? (uint32_t)cp[0] : (uint32_t)sentinel;
-            for (int t = 0; t < nt; ++t) {
-                const uint32_t code = code_next;
-                if (t + 1 < nt) code_next = cp[(t + 1) * 64];
+            auto pair = [&](uint32_t code) {
                 const uint32_t idx = code & kCodeIdxMask;
                 const int tj = (int)(code >> kCodeIdxBits);
                 const float4 pj = s_j[idx];
@@ -306,10 +396,8 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 if (__builtin_expect(__builtin_amdgcn_ballot_w64(amb) != 0ull, 0)) {
                     if (amb) in = recheck_pair(ent_g, A.xs, cs, slot_i, idx, gsp, A.rc2) != 0;
                 }
-                if (EMIT) {
-                    if (in) emit_pair(ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit,
-                                      A.emit_max);
-                }
+                if (EMIT) emit_pairs(in, ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit,
+                                     A.emit_max);
                 const float rinv = in ? __builtin_amdgcn_rsqf(r2) : 0.0f;
                 const float r = r2 * rinv;
                 const float s = __builtin_amdgcn_exp2f(r * nkl2);
@@ -334,43 +422,60 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 ax = fmaf(f, dx, ax);
                 ay = fmaf(f, dy, ay);
                 az = fmaf(f, dz, az);
-                if (ENERGY) eacc += (double)e;
-                if ((t & 7) == 7) {
+                if (ENERGY) ea += e;
+            };
+            const uint64_t sent4 = 0x0001000100010001ull * (uint64_t)sentinel;
+            uint64_t v0 = nr > 0 ? (uint64_t)cp[0] : sent4;
+            uint64_t v1 = nr > 1 ? (uint64_t)cp[64] : sent4;
+            for (int r = 0; r < nr; ++r) {
+                const uint64_t cur = v0;
+                v0 = v1;
+                if (r + 2 < nr) v1 = cp[(r + 2) * 64];
+                const uint32_t lo = (uint32_t)cur, hi = (uint32_t)(cur >> 32);
+                pair(lo & 0xFFFFu);
+                pair(lo >> 16);
+                pair(hi & 0xFFFFu);
+                pair(hi >> 16);
+                if (r & 1) {      // fold every 8 terms into the compensated sums
                     kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
-                    ax = ay = az = 0.0f;
+                    if (ENERGY) eacc += (double)ea;
+                    ax = ay = az = ea = 0.0f;
                 }
             }
+            if (ENERGY) eacc += (double)ea;
             kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
             // true per-lane sum = s - c; combine the atom's 8 lanes in FP64
-            const double Fx = reduce8((double)sx - (double)cx);
-            const double Fy = reduce8((double)sy - (double)cy);
-            const double Fz = reduce8((double)sz - (double)cz);
-            if ((lane & 7) == 0 && ai >= 0) {
-                A.fx[ai] = Fx;
-                A.fy[ai] = Fy;
-                A.fz[ai] = Fz;
-            }
-            if (ENERGY) {
-                for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
-                e_w = 0.5 * eacc;     // each pair is visited from both atoms
-            }
+            Fx = reduce8((double)sx - (double)cx);
+            Fy = reduce8((double)sy - (double)cy);
+            Fz = reduce8((double)sz - (double)cz);
+            if (ENERGY) Ea = reduce8(eacc);
         }
-        if (ENERGY) {
-            if (lane == 0) s_e[w] = e_w;
-            __syncthreads();
-            if (tid == 0) {
-                double t = 0.0;
-                for (int k = 0; k < nw; ++k) t += s_e[k];
-                A.grp_epot[g] = t;
-            }
+        // combine the waves of each cluster in a fixed order (deterministic)
+        if ((lane & 7) == 0) {
+            s_part[w][il][0] = Fx;
+            s_part[w][il][1] = Fy;
+            s_part[w][il][2] = Fz;
+            s_part[w][il][3] = Ea;
         }
-    }
-    if (ENERGY) {
-        if (last_group_done(&A.dsc->ticket_force, &s_flag)) {
-            __shared__ double s_red[kMaxGroup];
-            finalize_epot(A, s_red);
-            if (tid == 0) A.dsc->ticket_force = 0u;
+        __syncthreads();
+        if (half == 0 && (lane & 7) == 0 && ai >= 0) {
+            double F[3] = {0.0, 0.0, 0.0};
+            for (int h = 0; h < wpc; ++h)
+                for (int d = 0; d < 3; ++d) F[d] += s_part[w + h][il][d];
+            A.fx[ai] = F[0];
+            A.fy[ai] = F[1];
+            A.fz[ai] = F[2];
         }
+        if (ENERGY && tid == 0) {
+            double t = 0.0;
+            for (int k = 0; k < nw; ++k)
+                for (int i = 0; i < kCluster; ++i) t += s_part[k][i][3];
+            A.grp_epot[g] = 0.5 * t;       // each pair is visited from both atoms
+        }
+        __syncthreads();
+        if (tid == 0) s_g = (int)(gridDim.x + atomicAdd(&A.dsc->work_force, 1u));
+        __syncthreads();
+        g = s_g;
     }
 }
 
@@ -380,18 +485,13 @@ template <bool ENERGY, bool EMIT, bool SCREEN_LJ>
 __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
 {
     __shared__ double s_e[kMaxGroup];
-    __shared__ int s_g, s_flag;
+    __shared__ int s_g;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
     const int64_t step = clamp_step(A);
     const int ngroups = A.dsc->n_groups;
     const uint32_t sentinel = (uint32_t)(A.E_cap * kCluster);
     const int64_t cs = A.cap_slots;
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) s_g = (int)atomicAdd(&A.dsc->work_force, 1u);
-        __syncthreads();
-        const int g = s_g;
-        if (g >= ngroups) break;
+    for (int g = blockIdx.x; g < ngroups;) {
         const Group gr = A.groups[g];
         const GridSys gs = A.grid[gr.sys];
         const double kap = A.kappa[(int64_t)gr.sys * A.S1 + step];
@@ -408,12 +508,12 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
                 qi = kKe * (double)A.qs[slot_i];
                 ti = A.ts[slot_i];
             }
-            const int nt = A.cl_nt[I];
-            const auto cp = gbl(A.nb + (int64_t)I * A.nb_T * 64 + lane);
             const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
             double Fx = 0.0, Fy = 0.0, Fz = 0.0, eacc = 0.0;
-            for (int t = 0; t < nt; ++t) {
-                const uint32_t code = cp[t * 64];
+            for (int hh = 0; hh < 2; ++hh)
+            for (int t = 0, nt = 4 * A.cl_nt[(int64_t)I * 2 + hh]; t < nt; ++t) {
+                const uint32_t code = gbl(A.nb + ((int64_t)I * 2 + hh) * A.nb_Th * 64)
+                                         [((t >> 2) * 64 + lane) * 4 + (t & 3)];
                 const uint32_t idx = code & kCodeIdxMask;
                 if (idx == sentinel || ai < 0) continue;
                 const int64_t slot_j = slot_of_code(ent_g, idx);
@@ -434,7 +534,8 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
                 }
                 if (!(r2 < A.rc2)) continue;
                 if (EMIT)
-                    emit_pair(ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit, A.emit_max);
+                    emit_pairs(true, ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit,
+                               A.emit_max);
                 const int tj = (int)(code >> kCodeIdxBits);
                 const double c6 = A.c6[ti * A.T + tj], c12 = A.c12[ti * A.T + tj];
                 const double r = sqrt(r2);
@@ -479,19 +580,20 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
                 A.grp_epot[g] = t;
             }
         }
-    }
-    if (ENERGY) {
-        if (last_group_done(&A.dsc->ticket_force, &s_flag)) {
-            __shared__ double s_red[kMaxGroup];
-            finalize_epot(A, s_red);
-            if (tid == 0) A.dsc->ticket_force = 0u;
-        }
+        __syncthreads();
+        if (tid == 0) s_g = (int)(gridDim.x + atomicAdd(&A.dsc->work_force, 1u));
+        __syncthreads();
+        g = s_g;
     }
 }
 
 // ------------------------------------------------------------------ launch
 
-size_t force32_lds_bytes(int E_cap) { return (size_t)(E_cap * kCluster + 1) * sizeof(float4); }
+size_t force32_lds_bytes(int E_cap)
+{
+    // staged candidates (+ the far sentinel) and the per-entry reach masks
+    return (size_t)(E_cap * kCluster + 1) * sizeof(float4) + (size_t)((E_cap + 15) & ~15);
+}
 
 template <bool E, bool M, bool S>
 static void set_lds_attr(size_t lds)
@@ -502,6 +604,9 @@ static void set_lds_attr(size_t lds)
 
 hipError_t force_kernel_setup(Ctx* c)
 {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, (const void*)k_force32<true, false, true>) == hipSuccess)
+        c->force32_static_lds = fa.sharedSizeBytes;
     const size_t lds = force32_lds_bytes(c->E_cap);
     set_lds_attr<false, false, false>(lds); set_lds_attr<false, false, true>(lds);
     set_lds_attr<true, false, false>(lds);  set_lds_attr<true, false, true>(lds);
@@ -513,12 +618,11 @@ hipError_t force_kernel_setup(Ctx* c)
 template <bool E, bool M, bool S>
 static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks, hipStream_t st)
 {
-    const dim3 blk(64 * c->G);
     if (prec == MD_FP32_KAHAN)
-        hipLaunchKernelGGL((k_force32<E, M, S>), dim3(blocks), blk, force32_lds_bytes(c->E_cap), st,
-                           A);
+        hipLaunchKernelGGL((k_force32<E, M, S>), dim3(blocks), dim3(64 * c->G * A.wpc),
+                           force32_lds_bytes(c->E_cap), st, A);
     else
-        hipLaunchKernelGGL((k_force64<E, M, S>), dim3(blocks), blk, 0, st, A);
+        hipLaunchKernelGGL((k_force64<E, M, S>), dim3(blocks), dim3(64 * c->G), 0, st, A);
 }
 
 hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, double* fz,
@@ -530,17 +634,28 @@ hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, doub
     A.grid = c->d_grid; A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
     A.lj32 = c->d_lj32; A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T;
     A.rc2 = c->cfg.rc * c->cfg.rc;
-    A.E_cap = c->E_cap; A.nb_T = c->nb_T; A.cap_slots = c->cap_slots;
+    A.E_cap = c->E_cap; A.nb_Th = c->nb_Th; A.cap_slots = c->cap_slots;
     A.fx = fx; A.fy = fy; A.fz = fz;
     A.grp_epot = c->d_grp_epot; A.epot = epot; A.sys_grp0 = c->d_sys_grp0; A.B = c->B;
     A.dsc = c->dsc; A.emit = emit; A.emit_max = emit_max;
-    // persistent grid: enough work-groups to fill every CU a few times over
-    const int per_cu = prec == MD_FP32_KAHAN
-                           ? std::max<int>(1, (int)(c->max_lds / std::max<size_t>(
-                                                        force32_lds_bytes(c->E_cap), 1)))
-                           : 4;
+    A.wpc = kMaxWpc;
+    A.cl_len = c->d_cl_len; A.ent_mask = c->d_ent_mask; A.nb_cap_h = c->nb_cap_h;
+    {
+        const double m = c->rlist * (1.0 + 1e-5);
+        A.thr2 = (float)(m * m);
+    }
+    if (prec == MD_FP64) launch_lists(c, st);     // the FP32 kernel builds its own lists
+    // persistent grid: as many work-groups as fit on every CU at once (LDS, waves)
+    int per_cu;
+    if (prec == MD_FP32_KAHAN) {
+        const size_t lds = force32_lds_bytes(c->E_cap) + c->force32_static_lds;
+        per_cu = (int)std::max<size_t>(1, c->lds_per_cu / lds);
+        per_cu = std::min(per_cu, std::max(1, 32 / (c->G * A.wpc)));
+    } else {
+        per_cu = std::max(1, 16 / c->G);
+    }
     const int blocks = (int)std::max<int64_t>(
-        1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * std::min(per_cu, 8)));
+        1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu));
     const bool E = epot != nullptr, M = emit != nullptr, S = c->cfg.screen_lj != 0;
     if (E) {
         if (M) { if (S) launch_one<true, true, true>(c, prec, A, blocks, st); else launch_one<true, true, false>(c, prec, A, blocks, st); }
@@ -549,6 +664,8 @@ hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, doub
         if (M) { if (S) launch_one<false, true, true>(c, prec, A, blocks, st); else launch_one<false, true, false>(c, prec, A, blocks, st); }
         else   { if (S) launch_one<false, false, true>(c, prec, A, blocks, st); else launch_one<false, false, false>(c, prec, A, blocks, st); }
     }
+    hipLaunchKernelGGL(k_force_finalize, dim3(1), dim3(256), 0, st, c->d_grp_epot, epot,
+                       c->d_sys_grp0, c->B, c->dsc);
     return hipGetLastError();
 }
 

@@ -45,7 +45,9 @@ struct Group {
     double c[3];            // frame origin (box centre)
     int32_t cl0, ncl;       // first cluster, number of clusters (<= cluster_group)
     int32_t sys;
-    int32_t nent;           // candidate (cluster, shift) entries
+    int32_t nent;           // candidate (cluster, shift) entries kept (<= capacity)
+    int32_t nent_raw;       // candidates found (a larger value means overflow)
+    int32_t pad_;
 };
 
 // Device-resident scalars (one allocation).
@@ -53,17 +55,12 @@ struct DevScalars {
     int64_t step;               // index of the latest force evaluation
     uint32_t flags;             // MD_FLAG_* error word
     int32_t need_rebuild;       // set when a displacement exceeds skin/2
+    int32_t lists_pending;      // candidate tables rebuilt; per-atom lists not yet rebuilt
     unsigned long long disp2_bits;  // max squared displacement since build (double bits)
     int32_t n_cols, n_bins, n_clusters, n_groups;
     int32_t n_slots;
-    int32_t max_entries;        // largest group entry count of the last build
-    int32_t max_list;           // largest per-atom list length of the last build
-    int64_t n_codes;            // total list codes of the last build
     int64_t n_builds;
     uint32_t work_force;        // work-queue counter of the force kernel
-    uint32_t ticket_force;      // completion ticket of the force kernel
-    uint32_t ticket_vv;         // completion ticket of the integrator
-    uint32_t ticket_build;      // completion ticket of the list kernel
     unsigned long long pair_count;  // debug pair export counter
 };
 
@@ -76,7 +73,9 @@ struct Ctx {
     bool built = false;
     int device = 0;
     int n_cu = 0;
-    size_t max_lds = 65536;
+    size_t max_lds = 65536;        // per work-group
+    size_t lds_per_cu = 65536;
+    size_t force32_static_lds = 8192;
 
     // host copies
     std::vector<int64_t> sys_off;
@@ -85,8 +84,9 @@ struct Ctx {
     int32_t T = 0, E = 0, Q = 0;
     int32_t G = 4;                 // i-clusters per group
     int32_t E_cap = 0;             // entries per group
-    int32_t nb_cap = 0;            // per-atom list capacity (multiple of 8)
-    int32_t nb_T = 0;              // nb_cap / 8
+    int32_t nb_cap = 0;            // per-atom list capacity (both halves)
+    int32_t nb_cap_h = 0;          // per-atom capacity of one half-list (multiple of 8)
+    int32_t nb_Th = 0;             // nb_cap_h / 8
     double rlist = 0.0;            // rc + skin
 
     // capacities
@@ -121,7 +121,8 @@ struct Ctx {
     int64_t* d_col_cnt = nullptr;  int64_t* d_col_pre = nullptr;       // cap_cols + 1
     // clusters / slots
     double* d_cl_lo = nullptr;     double* d_cl_hi = nullptr;          // cap_clusters*3
-    int32_t* d_cl_nt = nullptr;                                        // cap_clusters
+    int32_t* d_cl_nt = nullptr;    // cap_clusters * 2: rows (32 codes per atom) of each half-list
+    int32_t* d_cl_len = nullptr;   // cap_clusters * 2: longest half-list of the cluster (stats)
     int32_t* d_perm = nullptr;     // cap_slots: caller atom of each slot (-1 = padding)
     int32_t* d_slot_img = nullptr; // cap_slots: packed image of the slot's atom
     int32_t* d_inv_perm = nullptr; // N
@@ -131,7 +132,8 @@ struct Ctx {
     // groups and lists
     Group* d_groups = nullptr;     // cap_groups
     uint32_t* d_ent = nullptr;     // cap_groups * E_cap
-    uint16_t* d_nb = nullptr;      // cap_clusters * nb_T * 64
+    uint8_t* d_ent_mask = nullptr; // cap_groups * E_cap: group clusters each entry can reach
+    uint16_t* d_nb = nullptr;      // cap_clusters * 2 * nb_Th * 64
     double* d_grp_epot = nullptr;  // cap_groups
     // integrator
     double* d_xref = nullptr;      // N*3 build positions

@@ -198,7 +198,8 @@ struct VvArgs {
     const double *fx, *fy, *fz;
     double *x, *y, *z, *vx, *vy, *vz;
     const double* xref;          // N*3 build positions
-    double* partial;             // nblocks + B
+    double* partial;             // nblocks + B (kinetic-energy partials)
+    double* disp_partial;        // nblocks (displacement maxima)
     double* ekin;
     const int64_t* sys_off;
     const int32_t* sys_of_atom;
@@ -224,7 +225,6 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A)
 {
 #pragma clang fp contract(off)
     __shared__ double s_red[kVvBlock / 64];
-    __shared__ int s_last;
     const int64_t a = blockIdx.x * (int64_t)kVvBlock + threadIdx.x;
     double d2 = 0.0, ke = 0.0;
     if (a < A.N) {
@@ -247,10 +247,14 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A)
         }
     }
     if (PHASE == 0) {
+        // block maximum of the squared displacement since the last build
         for (int off = 32; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, 64));
-        if ((threadIdx.x & 63) == 0 && d2 > 0.0) {
-            atomicMax(&A.dsc->disp2_bits, (unsigned long long)__double_as_longlong(d2));
-            if (d2 > A.thr2) atomicExch(&A.dsc->need_rebuild, 1);
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = d2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = s_red[0];
+            for (int k = 1; k < kVvBlock / 64; ++k) m = fmax(m, s_red[k]);
+            A.disp_partial[blockIdx.x] = m;
         }
     }
     if (PHASE == 1 && EKIN) {
@@ -264,45 +268,47 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A)
             if (threadIdx.x == 0) A.partial[blockIdx.x + b] = t;
         }
     }
-    // completion ticket: the last block advances the step or finalizes E_kin
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(&A.dsc->ticket_vv, 1u);
-        s_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
+
+// One block: after phase 0, fold the displacement partials (rebuild request) and
+// advance the step counter; after phase 1, sum the kinetic-energy partials of each
+// system in a fixed order.
+template <int PHASE>
+__global__ void __launch_bounds__(kVvBlock) k_vv_finalize(VvArgs A, int nblocks)
+{
+    __shared__ double s_red[kVvBlock / 64];
     if (PHASE == 0) {
+        double m = 0.0;
+        for (int k = threadIdx.x; k < nblocks; k += kVvBlock) m = fmax(m, A.disp_partial[k]);
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
+        __syncthreads();
         if (threadIdx.x == 0) {
+            for (int k = 1; k < kVvBlock / 64; ++k) m = fmax(m, s_red[k]);
+            m = fmax(m, s_red[0]);
+            const double prev = __longlong_as_double((long long)A.dsc->disp2_bits);
+            A.dsc->disp2_bits = (unsigned long long)__double_as_longlong(fmax(prev, m));
+            if (m > A.thr2) A.dsc->need_rebuild = 1;
             A.dsc->step += 1;
-            A.dsc->ticket_vv = 0;
         }
         return;
     }
-    if (EKIN) {
-        for (int b = 0; b < A.B; ++b) {
-            const int64_t s0 = A.sys_off[b], s1 = A.sys_off[b + 1];
-            double t = 0.0;
-            if (s1 > s0) {
-                const int64_t k0 = s0 / kVvBlock, k1 = (s1 - 1) / kVvBlock;
-                for (int64_t k = k0 + threadIdx.x; k <= k1; k += kVvBlock)
-                    t += __hip_atomic_load(&A.partial[k + b], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-            }
-            t = block_sum_d(t, s_red);
-            if (threadIdx.x == 0) A.ekin[b] = t;
+    for (int b = 0; b < A.B; ++b) {
+        const int64_t s0 = A.sys_off[b], s1 = A.sys_off[b + 1];
+        double t = 0.0;
+        if (s1 > s0) {
+            const int64_t k0 = s0 / kVvBlock, k1 = (s1 - 1) / kVvBlock;
+            for (int64_t k = k0 + threadIdx.x; k <= k1; k += kVvBlock) t += A.partial[k + b];
         }
+        t = block_sum_d(t, s_red);
+        if (threadIdx.x == 0) A.ekin[b] = t;
     }
-    if (threadIdx.x == 0) A.dsc->ticket_vv = 0;
 }
 
 void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const double* fx,
                const double* fy, const double* fz, double* x, double* y, double* z, double* vx,
                double* vy, double* vz, double* ekin, hipStream_t st)
 {
-    if (c->N == 0) return;
     VvArgs A;
     A.N = c->N; A.dt = dt; A.hdt = 0.5 * dt;
     const double half_skin = 0.5 * c->cfg.skin;
@@ -310,17 +316,21 @@ void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const doubl
     A.inv_mass = inv_mass; A.fx = fx; A.fy = fy; A.fz = fz;
     A.x = x; A.y = y; A.z = z; A.vx = vx; A.vy = vy; A.vz = vz;
     A.xref = c->d_xref; A.partial = c->d_partial; A.ekin = ekin;
-    A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
     const int nb = (int)div_up(c->N, kVvBlock);
-    if (phase == 0)
-        hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A);
-    else if (ekin)
-        hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A);
-    else
+    A.disp_partial = c->d_partial + nb + c->B + 1;
+    A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
+    if (phase == 0) {
+        if (nb > 0) hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A);
+        hipLaunchKernelGGL((k_vv_finalize<0>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
+    } else if (ekin) {
+        if (nb > 0) hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A);
+        hipLaunchKernelGGL((k_vv_finalize<1>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
+    } else if (nb > 0) {
         hipLaunchKernelGGL((k_vv<1, false>), dim3(nb), dim3(kVvBlock), 0, st, A);
+    }
 }
 
-int64_t vv_partials_needed(int64_t N, int B) { return div_up(N, kVvBlock) + B + 1; }
+int64_t vv_partials_needed(int64_t N, int B) { return 2 * (div_up(N, kVvBlock) + B + 1); }
 
 // ------------------------------------------------------------------ device scalars
 

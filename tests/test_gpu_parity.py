@@ -426,10 +426,13 @@ def test_device_flags_are_reported():
     eng.build()
     assert eng.sync_check(raise_on_flags=False) & md.MD_FLAG_BAD_INPUT
     eng.close()
-    # neighbour list too small
-    say("flag: list overflow")
-    s2 = synth.water_small()
-    e2 = make_engine(s2, 1, max_neighbors=16)
-    e2.build()
-    assert e2.sync_check(raise_on_flags=False) & md.MD_FLAG_LIST_OVERFLOW
-    e2.close()
+    # neighbour list too small: the per-atom lists are written by the first force
+    # call after a rebuild, which reports the overflow
+    for prec in (0, 1):
+        say("flag: list overflow, precision %d" % prec)
+        s2 = synth.water_small()
+        e2 = make_engine(s2, prec, max_neighbors=16)
+        e2.build()
+        e2.forces()
+        assert e2.sync_check(raise_on_flags=False) & md.MD_FLAG_LIST_OVERFLOW
+        e2.close()
