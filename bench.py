@@ -49,7 +49,17 @@ def make_system(name, n_steps):
     raise SystemExit("unknown config " + name)
 
 
-def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, time_force=True):
+STATE = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q")
+
+
+def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5):
+    """Timed region: `steps` replays of the captured step graph, inputs resident.
+    Then the same steps are replayed eagerly from a snapshot of the state at the
+    start of the timed region, with the force-kernel timer on: the trajectory is
+    deterministic, so the eager replay launches exactly the kernels of the timed
+    region (checked: identical final state and rebuild count) and gives the
+    duration of every force-kernel launch.  Pair counts are sampled between steps
+    of the replay (where no list rebuild is pending)."""
     import torch
     from paper_2401_03180_amd import md
     eng = md.Engine(sys_, prec, cluster_group=cluster_group, skin=skin)
@@ -61,9 +71,12 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, time_force=True):
         graph = eng.graph(md.MD_BUILD_AUTO, stream, energy=True, ekin=True)
         for _ in range(warmup):
             md.md_graph_launch(graph, stream)
+        # the timed trajectory starts from a fresh build of the current positions
+        eng.build(md.MD_BUILD_FORCE, stream)
         stream.synchronize()
+        snap = {n: getattr(eng, n).clone() for n in STATE}
+        k0 = eng.get_step(stream)
         st0 = eng.stats(stream)
-        pairs0 = eng.debug_pairs(prec=prec).shape[0]
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -77,13 +90,40 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, time_force=True):
         ms = ev0.elapsed_time(ev1)
         flags = eng.sync_check(stream, raise_on_flags=False)
         st1 = eng.stats(stream)
-        pairs1 = eng.debug_pairs(prec=prec).shape[0]
-        kernel_ms = eng.time_forces(reps=20, energy=True, stream=stream) if time_force else None
-        step_k = eng.get_step(stream)
+        final = {n: getattr(eng, n).clone() for n in STATE}
+        step_end = eng.get_step(stream)
+
+        # eager replay of the same steps with the force-kernel timer
+        for n in STATE:
+            getattr(eng, n).copy_(snap[n])
+        eng.set_step(k0, stream)
+        eng.build(md.MD_BUILD_FORCE, stream)
+        stream.synchronize()
+        st2 = eng.stats(stream)
+        eng.timer_start(steps)
+        sample_at = set(int(v) for v in np.linspace(1, steps, pair_samples))
+        pairs = []
+        for i in range(1, steps + 1):
+            eng.step(md.MD_BUILD_AUTO, energy=True, ekin=True, stream=stream)
+            if i in sample_at:
+                stream.synchronize()
+                pairs.append(eng.debug_pairs(prec=prec, stream=stream).shape[0])
+        durations = eng.timer_read()
+        stream.synchronize()
+        st3 = eng.stats(stream)
+        same = all(torch.equal(getattr(eng, n), final[n]) for n in STATE)
+        eng.timer_start(0)
     eng.close()
-    return {"ms": ms, "wall_s": wall, "flags": flags, "pairs": 0.5 * (pairs0 + pairs1),
-            "pairs0": pairs0, "pairs1": pairs1, "kernel_ms": kernel_ms,
-            "builds": st1["n_builds"] - st0["n_builds"], "stats": st1, "step": step_k}
+    builds = st1["n_builds"] - st0["n_builds"]
+    builds_replay = st3["n_builds"] - st2["n_builds"]
+    d = np.asarray(durations, dtype=np.float64)
+    return {"ms": ms, "wall_s": wall, "flags": flags, "pairs": float(np.mean(pairs)),
+            "pairs_min": int(min(pairs)), "pairs_max": int(max(pairs)),
+            "kernel_ms": float(d.mean()), "kernel_ms_median": float(np.median(d)),
+            "kernel_ms_p90": float(np.percentile(d, 90)), "kernel_launches": int(d.size),
+            "builds": builds, "builds_replay": builds_replay,
+            "replay_identical": bool(same and builds == builds_replay), "stats": st1,
+            "step": step_end}
 
 
 def cpu_baseline(sys_, target_s=12.0, threads=None):
@@ -157,9 +197,11 @@ def main():
     md.lib()
 
     if a.calib_copy:
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        # streaming kernel of known traffic (reads 1 GiB, writes 1 GiB): the scale
+        # of the HBM byte counters
+        src = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
@@ -171,7 +213,12 @@ def main():
     n = sys32.n_atoms
     value = n * a.steps / (r32["ms"] * 1e-3)
     extra = {"flags": r32["flags"], "rebuilds_timed": r32["builds"],
-             "pairs_in_cutoff": r32["pairs"], "list_codes": r32["stats"]["n_list_codes"],
+             "replay_identical": r32["replay_identical"],
+             "pairs_in_cutoff_mean": r32["pairs"], "pairs_min": r32["pairs_min"],
+             "pairs_max": r32["pairs_max"], "force_launches_timed": r32["kernel_launches"],
+             "force_kernel_ms_median": r32["kernel_ms_median"],
+             "force_kernel_ms_p90": r32["kernel_ms_p90"],
+             "list_codes": r32["stats"]["n_list_codes"],
              "groups": r32["stats"]["n_groups"], "cluster_group": r32["stats"]["cluster_group"],
              "max_group_entries": r32["stats"]["max_group_entries"],
              "group_entry_capacity": r32["stats"]["group_entry_capacity"],
@@ -179,13 +226,13 @@ def main():
              "list_capacity": r32["stats"]["list_capacity"]}
     if not a.no_fp64:
         sys64 = make_system(a.config, S)
-        r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, a.cluster_group, a.skin,
-                      time_force=True)
+        r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, a.cluster_group, a.skin)
         log("fp64", {k: v for k, v in r64.items() if k != "stats"})
         v64 = n * a.steps / (r64["ms"] * 1e-3)
         extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
                       "fp32_vs_fp64_speedup": value / v64,
-                      "fp64_force_kernel_ms": r64["kernel_ms"], "fp64_flags": r64["flags"]})
+                      "fp64_force_kernel_ms": r64["kernel_ms"], "fp64_flags": r64["flags"],
+                      "fp64_replay_identical": r64["replay_identical"]})
 
     kernel_ms = r32["kernel_ms"]
     achieved = FLOP_PER_PAIR * r32["pairs"] / (kernel_ms * 1e-3) / 1e12

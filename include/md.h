@@ -235,14 +235,19 @@ md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t build_m
 md_status md_graph_launch(md_graph* graph, md_stream stream);
 md_status md_graph_destroy(md_graph* graph);
 
-/* Benchmark helper: runs the force evaluation of md_screened_forces `reps` times
- * on `stream` and times the force kernel alone with HIP events recorded on that
- * stream around each launch (the slot repack that precedes every launch is outside
- * the timed intervals).  *avg_ms receives the mean kernel time.  Synchronous. */
-md_status md_time_forces(md_ctx* ctx, md_precision prec, const double* x, const double* y,
-                         const double* z, const int8_t* q, const uint8_t* type, double* fx,
-                         double* fy, double* fz, double* epot, int32_t reps, float* avg_ms,
-                         md_stream stream);
+/* Measurement helper: time the main force kernel of each of the next `capacity`
+ * force evaluations issued by md_screened_forces or md_step outside graph capture.
+ * Two HIP events are recorded on the launch stream, immediately before and after
+ * that kernel (the slot repack before it and the energy reduction after it fall
+ * outside the interval).  A new call discards earlier records (it synchronizes the
+ * device first); capacity 0 stops recording and frees the events.  Launches beyond
+ * the capacity are not timed. */
+md_status md_force_timer_start(md_ctx* ctx, int32_t capacity);
+
+/* Number of timed launches so far in *n, and the first min(*n, max) kernel
+ * durations, in milliseconds and launch order, in the host array ms.  Waits for
+ * those launches to finish. */
+md_status md_force_timer_read(md_ctx* ctx, float* ms, int32_t max, int32_t* n);
 
 typedef struct md_stats {
     int64_t n_atoms, n_clusters, n_groups, n_entries;   /* from the last build */

@@ -69,6 +69,27 @@ bool null_any(std::initializer_list<const void*> ps)
 
 hipStream_t S(md_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
+void free_timer(Ctx* c)
+{
+    for (hipEvent_t e : c->t_ev)
+        if (e) (void)hipEventDestroy(e);
+    c->t_ev.clear();
+    c->t_cap = c->t_n = 0;
+}
+
+// Events for the next timed force launch, if the timer has room and the stream is
+// not being captured into a graph.
+void next_timer_events(Ctx* c, hipStream_t st, hipEvent_t* e0, hipEvent_t* e1)
+{
+    *e0 = *e1 = nullptr;
+    if (c->t_n >= c->t_cap) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    *e0 = c->t_ev[2 * c->t_n];
+    *e1 = c->t_ev[2 * c->t_n + 1];
+    ++c->t_n;
+}
+
 }  // namespace
 
 extern "C" {
@@ -138,6 +159,7 @@ md_status md_destroy(md_ctx* ctx)
 {
     if (!ctx) return MD_OK;
     (void)hipDeviceSynchronize();
+    free_timer(&ctx->c);
     free_all(&ctx->c);
     delete ctx;
     return MD_OK;
@@ -439,41 +461,45 @@ md_status md_screened_forces(md_ctx* ctx, md_precision prec, const double* x, co
     if (prec != MD_FP64 && prec != MD_FP32_KAHAN) return fail(c, MD_ERR_ARG, "unknown precision");
     if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
     if (!c->built) return fail(c, MD_ERR_STATE, "md_build_cells has not run");
+    hipEvent_t e0, e1;
+    next_timer_events(c, S(stream), &e0, &e1);
     launch_repack(c, x, y, z, q, S(stream));
-    HIP_TRY(c, launch_forces(c, prec, fx, fy, fz, epot, nullptr, 0, S(stream)));
+    HIP_TRY(c, launch_forces(c, prec, fx, fy, fz, epot, nullptr, 0, S(stream), e0, e1));
     return MD_OK;
 }
 
-md_status md_time_forces(md_ctx* ctx, md_precision prec, const double* x, const double* y,
-                         const double* z, const int8_t* q, const uint8_t* type, double* fx,
-                         double* fy, double* fz, double* epot, int32_t reps, float* avg_ms,
-                         md_stream stream)
+md_status md_force_timer_start(md_ctx* ctx, int32_t capacity)
 {
-    if (!ctx || !avg_ms || reps < 1) return MD_ERR_ARG;
+    if (!ctx) return MD_ERR_ARG;
     Ctx* c = &ctx->c;
-    if (null_any({x, y, z, q, type, fx, fy, fz}) && c->N > 0)
-        return fail(c, MD_ERR_ARG, "NULL array");
-    if (!c->tables_bound || !c->built) return fail(c, MD_ERR_STATE, "no build");
-    hipStream_t st = S(stream);
-    std::vector<hipEvent_t> ev(2 * reps, nullptr);
-    for (auto& e : ev) HIP_TRY(c, hipEventCreate(&e));
-    hipError_t err = hipSuccess;
-    for (int r = 0; r < reps && err == hipSuccess; ++r) {
-        launch_repack(c, x, y, z, q, st);
-        err = hipEventRecord(ev[2 * r], st);
-        if (err == hipSuccess) err = launch_forces(c, prec, fx, fy, fz, epot, nullptr, 0, st);
-        if (err == hipSuccess) err = hipEventRecord(ev[2 * r + 1], st);
+    if (capacity < 0) return fail(c, MD_ERR_ARG, "capacity must be >= 0");
+    (void)hipDeviceSynchronize();      // no recorded event may still be pending
+    free_timer(c);
+    if (capacity == 0) return MD_OK;
+    c->t_ev.assign(2 * (size_t)capacity, nullptr);
+    for (auto& e : c->t_ev) {
+        const hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) {
+            free_timer(c);
+            return fail(c, MD_ERR_HIP, "event creation failed: %s", hipGetErrorString(err));
+        }
     }
-    if (err == hipSuccess) err = hipStreamSynchronize(st);
-    double total = 0.0;
-    for (int r = 0; r < reps && err == hipSuccess; ++r) {
-        float ms = 0.f;
-        err = hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
-        total += ms;
+    c->t_cap = capacity;
+    return MD_OK;
+}
+
+md_status md_force_timer_read(md_ctx* ctx, float* ms, int32_t max, int32_t* n)
+{
+    if (!ctx || !n || (max > 0 && !ms) || max < 0) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    *n = c->t_n;
+    for (int i = 0; i < c->t_n && i < max; ++i) {
+        hipError_t err = hipEventSynchronize(c->t_ev[2 * i + 1]);
+        float v = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&v, c->t_ev[2 * i], c->t_ev[2 * i + 1]);
+        if (err != hipSuccess) return fail(c, MD_ERR_HIP, "timer read: %s", hipGetErrorString(err));
+        ms[i] = v;
     }
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    if (err != hipSuccess) return fail(c, MD_ERR_HIP, "timing failed: %s", hipGetErrorString(err));
-    *avg_ms = (float)(total / reps);
     return MD_OK;
 }
 

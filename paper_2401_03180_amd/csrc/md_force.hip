@@ -200,37 +200,37 @@ __device__ inline double reduce8(double v)
     return v;
 }
 
-// Rebuild the half-list `half` of cluster I from the staged candidates: the codes
-// (staged index | type << 13) of partners within rc + skin, compacted per atom in
-// entry order; rows of 32 codes per atom padded with the sentinel.
-__device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int il, int k,
-                                int ai, float xi, float yi, float zi, int nent,
-                                const float4* s_j, const uint8_t* s_mask,
-                                const __attribute__((address_space(1))) uint32_t* ent_gl,
-                                int sentinel)
+// Rebuild the half-list `half` of cluster I from the candidates staged in LDS
+// (during a rebuild their .w holds the type): the codes (staged index | type << 13)
+// of partners within rc + skin, compacted per atom in entry order; rows of 32
+// codes per atom padded with the sentinel.  s_mask[e] holds the clusters of the
+// group entry e can reach (low byte) and the cluster whose own unshifted entry it
+// is (high byte).  Returns the row count.
+__device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int il, int k, int ai,
+                               float xi, float yi, float zi, int nent, const float4* s_j,
+                               const uint16_t* s_mask, int sentinel)
 {
     const int lane = threadIdx.x & 63;
     int cnt = 0;
     uint16_t* out = A.nb + ((int64_t)I * 2 + half) * A.nb_Th * 64;
+    const bool live = ai >= 0;
     for (int e = half; e < nent; e += 2) {
-        if (((s_mask[e] >> cw) & 1u) == 0u) continue;   // out of this cluster's reach
-        const uint32_t en = ent_gl[e];
+        const uint32_t mk = s_mask[e];
+        if (((mk >> cw) & 1u) == 0u) continue;          // out of this cluster's reach
         const int j = e * kCluster + k;
         const float4 pj = s_j[j];
         const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const bool self = ((en & kEntClusterMask) == (uint32_t)I) && ((en >> 26) == 0x15u) &&
-                          (k == il);
-        const bool pass = (ai >= 0) && (r2 < A.thr2) && !self;
+        const bool self = ((mk >> (8 + cw)) & 1u) && (k == il);
+        const bool pass = live && (r2 < A.thr2) && !self;
         const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
         const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
         if (pass) {
             const int pos = cnt + __popc(mine & ((1u << k) - 1u));
             if (pos < A.nb_cap_h) {
-                const int tj = A.ts[(int64_t)(en & kEntClusterMask) * kCluster + k];
                 const int t = pos >> 3;
                 out[((t >> 2) * 64 + il * 8 + (pos & 7)) * 4 + (t & 3)] =
-                    (uint16_t)(j | (tj << kCodeIdxBits));
+                    (uint16_t)(j | (__float_as_int(pj.w) << kCodeIdxBits));
             }
         }
         cnt += __popc(mine);
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
     for (int i = tid; i < A.T * A.T; i += blockDim.x)
         s_lj[i] = make_float2(A.lj32[2 * i], A.lj32[2 * i + 1]);
     const int sentinel = A.E_cap * kCluster;
-    uint8_t* s_mask = reinterpret_cast<uint8_t*>(s_j + sentinel + 1);
+    uint16_t* s_mask = reinterpret_cast<uint16_t*>(s_j + sentinel + 1);
     if (tid == 0) s_j[sentinel] = make_float4(kFarF, kFarF, kFarF, 0.0f);
     const float rc2f = (float)A.rc2;
     const int64_t cs = A.cap_slots;
@@ -309,7 +309,10 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 const bool ok = idx < nst;
                 for (int d = 0; d < 3; ++d) p[u][d] = ok ? (double)xs_g[d * cs + slot[u]] : 0.0;
                 im[u] = ok ? A.slot_img[slot[u]] : 0;
-                qv[u] = ok ? (float)A.qs[slot[u]] : 0.0f;
+                // while the lists are rebuilt .w carries the type (the charges are
+                // put back before the pair loop)
+                qv[u] = !ok ? 0.0f
+                            : rebuild ? __int_as_float((int)A.ts[slot[u]]) : (float)A.qs[slot[u]];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -328,7 +331,13 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                     if (!pad) m = fmaxf(m, fabsf(r[d]));
                 }
                 s_j[idx] = make_float4(r[0], r[1], r[2], pad ? 0.0f : qv[u]);
-                if (rebuild && (idx & 7) == 0) s_mask[idx >> 3] = A.ent_mask[(int64_t)g * A.E_cap + (idx >> 3)];
+                if (rebuild && (idx & 7) == 0) {
+                    const int e = idx >> 3;
+                    const int c = (int)(en[u] & kEntClusterMask) - gr.cl0;
+                    const uint32_t own = ((en[u] >> 26) == 0x15u && c >= 0 && c < gr.ncl)
+                                             ? (1u << (8 + c)) : 0u;
+                    s_mask[e] = (uint16_t)(A.ent_mask[(int64_t)g * A.E_cap + e] | own);
+                }
             }
         }
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
@@ -347,12 +356,13 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 
         double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ea = 0.0;
         int ai = -1;
-        if (cw < gr.ncl) {
-            const int I = gr.cl0 + cw;
-            const int64_t slot_i = (int64_t)I * kCluster + il;
+        const bool act = cw < gr.ncl;              // wave-uniform
+        const int I = gr.cl0 + cw;
+        const int64_t slot_i = (int64_t)I * kCluster + il;
+        float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f;
+        int tb = 0;
+        if (act) {
             ai = A.perm[slot_i];
-            float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f;
-            int tb = 0;
             if (ai >= 0) {
                 const int32_t im = A.slot_img[slot_i];
                 float r[3];
@@ -365,18 +375,30 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 qike = (float)(kKe * (double)A.qs[slot_i]);
                 tb = A.ts[slot_i] * A.T;
             }
+        }
+        int nr = 0;
+        if (rebuild) {
+            if (act)
+                nr = build_half_list(A, I, half, cw, il, k8, ai, xi, yi, zi, gr.nent, s_j, s_mask,
+                                     sentinel);
+            // the lists are read back only inside this work-group: the barrier's
+            // work-group-scope ordering suffices (an agent-scope fence would write
+            // back the L2)
+            __syncthreads();
+            for (int idx = tid; idx < nst; idx += blockDim.x) {      // charges back in .w
+                const uint32_t en = ent_gl[idx >> 3];
+                const float qv = (float)A.qs[(int64_t)(en & kEntClusterMask) * kCluster + (idx & 7)];
+                reinterpret_cast<float*>(s_j + idx)[3] = qv;
+            }
+            __syncthreads();
+        } else if (act) {
+            nr = A.cl_nt[(int64_t)I * 2 + half];
+        }
+        if (act) {
             const float kapf = (float)kap;
             const float nkl2 = (float)(-kap * 1.4426950408889634);   // -kappa log2(e)
             // wave-uniform row count and list base (scalar loop control / addressing);
             // each lane reads its next 4 codes with one 8-byte load, two rows ahead
-            int nr;
-            if (rebuild) {
-                nr = build_half_list(A, I, half, cw, il, k8, ai, xi, yi, zi, gr.nent, s_j,
-                                     s_mask, ent_gl, sentinel);
-                __threadfence();      // the wave reads back codes other lanes wrote
-            } else {
-                nr = A.cl_nt[(int64_t)I * 2 + half];
-            }
             nr = __builtin_amdgcn_readfirstlane(nr);
             const auto cp = gbl(reinterpret_cast<const uint64_t*>(
                                 A.nb + ((int64_t)I * 2 + half) * A.nb_Th * 64)) + lane;
@@ -591,8 +613,9 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
 
 size_t force32_lds_bytes(int E_cap)
 {
-    // staged candidates (+ the far sentinel) and the per-entry reach masks
-    return (size_t)(E_cap * kCluster + 1) * sizeof(float4) + (size_t)((E_cap + 15) & ~15);
+    // staged candidates (+ the far sentinel) and the per-entry reach / self masks
+    return (size_t)(E_cap * kCluster + 1) * sizeof(float4) +
+           (size_t)((E_cap * sizeof(uint16_t) + 15) & ~(size_t)15);
 }
 
 template <bool E, bool M, bool S>
@@ -626,7 +649,8 @@ static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks
 }
 
 hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, double* fz,
-                         double* epot, int2* emit, int64_t emit_max, hipStream_t st)
+                         double* epot, int2* emit, int64_t emit_max, hipStream_t st,
+                         hipEvent_t ev0, hipEvent_t ev1)
 {
     ForceArgs A;
     A.groups = c->d_groups; A.ent = c->d_ent; A.nb = c->d_nb; A.cl_nt = c->d_cl_nt;
@@ -657,12 +681,20 @@ hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, doub
     const int blocks = (int)std::max<int64_t>(
         1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu));
     const bool E = epot != nullptr, M = emit != nullptr, S = c->cfg.screen_lj != 0;
+    if (ev0) {
+        const hipError_t e = hipEventRecord(ev0, st);
+        if (e != hipSuccess) return e;
+    }
     if (E) {
         if (M) { if (S) launch_one<true, true, true>(c, prec, A, blocks, st); else launch_one<true, true, false>(c, prec, A, blocks, st); }
         else   { if (S) launch_one<true, false, true>(c, prec, A, blocks, st); else launch_one<true, false, false>(c, prec, A, blocks, st); }
     } else {
         if (M) { if (S) launch_one<false, true, true>(c, prec, A, blocks, st); else launch_one<false, true, false>(c, prec, A, blocks, st); }
         else   { if (S) launch_one<false, false, true>(c, prec, A, blocks, st); else launch_one<false, false, false>(c, prec, A, blocks, st); }
+    }
+    if (ev1) {
+        const hipError_t e = hipEventRecord(ev1, st);
+        if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_force_finalize, dim3(1), dim3(256), 0, st, c->d_grp_epot, epot,
                        c->d_sys_grp0, c->B, c->dsc);

@@ -76,6 +76,9 @@ struct Ctx {
     size_t max_lds = 65536;        // per work-group
     size_t lds_per_cu = 65536;
     size_t force32_static_lds = 8192;
+    // force-kernel launch timer: event pairs recorded around the next t_cap launches
+    std::vector<hipEvent_t> t_ev;
+    int t_cap = 0, t_n = 0;
 
     // host copies
     std::vector<int64_t> sys_off;

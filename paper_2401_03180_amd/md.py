@@ -28,7 +28,7 @@ EXPORTED = (
     "md_create", "md_destroy", "md_last_error", "md_bind_tables", "md_set_step", "md_get_step",
     "md_build_cells", "md_ionize_step", "md_screened_forces",
     "md_integrate_vv", "md_sync_check", "md_clear_flags", "md_debug_pairs", "md_get_stats",
-    "md_time_forces", "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
+    "md_force_timer_start", "md_force_timer_read", "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
     "md_rates_from_fractions",
 )
 
@@ -90,7 +90,7 @@ def lib():
             "md_sync_check": [P, P, P], "md_clear_flags": [P, P],
             "md_debug_pairs": [P, ctypes.c_int, P, P, P, P, P, P, i64, P],
             "md_get_stats": [P, P, P], "md_step": [P, P, i32, P],
-            "md_time_forces": [P, ctypes.c_int, P, P, P, P, P, P, P, P, P, i32, P, P],
+            "md_force_timer_start": [P, i32], "md_force_timer_read": [P, P, i32, P],
             "md_graph_create": [P, P, i32, P, P], "md_graph_launch": [P, P],
             "md_graph_destroy": [P], "md_debye_length_nm": [f64, f64],
             "md_rates_from_fractions": [i64, i32, P, P],
@@ -206,12 +206,17 @@ def md_debug_pairs(ctx, prec, x, y, z, q, max_pairs, stream=None) -> np.ndarray:
     return buf[:n.value]
 
 
-def md_time_forces(ctx, prec, x, y, z, q, type_, fx, fy, fz, epot, reps, stream=None) -> float:
-    ms = ctypes.c_float()
-    _check(ctx, lib().md_time_forces(ctx, int(prec), _ptr(x), _ptr(y), _ptr(z), _ptr(q),
-                                     _ptr(type_), _ptr(fx), _ptr(fy), _ptr(fz), _ptr(epot),
-                                     int(reps), ctypes.byref(ms), _stream(stream)))
-    return ms.value
+def md_force_timer_start(ctx, capacity):
+    _check(ctx, lib().md_force_timer_start(ctx, int(capacity)))
+
+
+def md_force_timer_read(ctx) -> np.ndarray:
+    """Kernel durations (ms) of the force launches timed since md_force_timer_start."""
+    n = ctypes.c_int32()
+    _check(ctx, lib().md_force_timer_read(ctx, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(n.value, 1), dtype=np.float32)
+    _check(ctx, lib().md_force_timer_read(ctx, out.ctypes.data, n.value, ctypes.byref(n)))
+    return out[:n.value]
 
 
 def md_get_stats(ctx, stream=None) -> dict:
@@ -347,10 +352,11 @@ class Engine:
     def step(self, build_mode=MD_BUILD_AUTO, energy=True, ekin=True, stream=None):
         md_step(self.ctx, self.step_args(energy, ekin), build_mode, stream)
 
-    def time_forces(self, reps=20, prec=None, energy=True, stream=None):
-        return md_time_forces(self.ctx, self.prec if prec is None else prec, self.x, self.y,
-                              self.z, self.q, self.type, self.fx, self.fy, self.fz,
-                              self.epot if energy else None, reps, stream)
+    def timer_start(self, capacity):
+        md_force_timer_start(self.ctx, capacity)
+
+    def timer_read(self):
+        return md_force_timer_read(self.ctx)
 
     def set_step(self, k, stream=None):
         md_set_step(self.ctx, k, stream)
@@ -364,12 +370,11 @@ class Engine:
     def stats(self, stream=None):
         return md_get_stats(self.ctx, stream)
 
-    def debug_pairs(self, prec=None, max_pairs=None):
+    def debug_pairs(self, prec=None, max_pairs=None, stream=None):
         if max_pairs is None:
             max_pairs = int(self.sys.n_atoms * 400 * (self.sys.rc + 0.2) ** 3) + 1024
-        p = md_debug_pairs(self.ctx, self.prec if prec is None else prec, self.x, self.y, self.z,
-                           self.q, max_pairs)
-        return p
+        return md_debug_pairs(self.ctx, self.prec if prec is None else prec, self.x, self.y,
+                              self.z, self.q, max_pairs, stream)
 
     def graph(self, build_mode, stream, energy=False, ekin=False):
         """Executable graph of one full step (captured once per argument set)."""
