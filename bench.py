@@ -52,8 +52,9 @@ def make_system(name, n_steps):
 STATE = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q")
 
 
-def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5):
-    """Timed region: `steps` replays of the captured step graph, inputs resident.
+def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_graph=True):
+    """Timed region: `steps` replays of the captured step graph (or, with use_graph
+    False, `steps` eager md_step calls), inputs resident.
     Then the same steps are replayed eagerly from a snapshot of the state at the
     start of the timed region, with the force-kernel timer on: the trajectory is
     deterministic, so the eager replay launches exactly the kernels of the timed
@@ -68,9 +69,13 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5):
         eng.set_step(0, stream)
         eng.build(md.MD_BUILD_FORCE, stream)
         eng.forces(energy=True, stream=stream)
-        graph = eng.graph(md.MD_BUILD_AUTO, stream, energy=True, ekin=True)
+        if use_graph:
+            graph = eng.graph(md.MD_BUILD_AUTO, stream, energy=True, ekin=True)
+            one_step = lambda: md.md_graph_launch(graph, stream)
+        else:
+            one_step = lambda: eng.step(md.MD_BUILD_AUTO, energy=True, ekin=True, stream=stream)
         for _ in range(warmup):
-            md.md_graph_launch(graph, stream)
+            one_step()
         # the timed trajectory starts from a fresh build of the current positions
         eng.build(md.MD_BUILD_FORCE, stream)
         stream.synchronize()
@@ -83,7 +88,7 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5):
         t0 = time.perf_counter()
         ev0.record(stream)
         for _ in range(steps):
-            md.md_graph_launch(graph, stream)
+            one_step()
         ev1.record(stream)
         stream.synchronize()
         wall = time.perf_counter() - t0
@@ -127,27 +132,47 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5):
 
 
 def cpu_baseline(sys_, target_s=12.0, threads=None):
-    """The oracle, as it stands, on a bounded sample of one step: full-j force rows for a
-    random subset of atoms plus ionization and velocity Verlet over all atoms; the
-    per-step time is extrapolated from the rows to all atoms."""
+    """The oracle, as it stands: whole steps (all-pairs FP64 force rows of every atom,
+    ionization and both velocity-Verlet half steps) repeated until about target_s
+    seconds of work; when one step alone would exceed that, the force rows of a random
+    subset of atoms are timed and scaled to all atoms."""
     import oracle
     threads = threads or min(os.cpu_count() or 1, 16)
     n = sys_.n_atoms
     rng = np.random.default_rng(0)
     kap = oracle.kappa_from_lambda(sys_.lambda_d[:, 1])
-    probe = np.sort(rng.choice(n, 256, replace=False))
+    probe = np.sort(rng.choice(n, min(n, 256), replace=False))
     t = time.perf_counter()
     oracle.forces_rows(sys_, probe, kappa=kap, n_threads=threads)
     per_row = (time.perf_counter() - t) / probe.size
+    q = sys_.q.copy()
+    pos = [sys_.x.copy(), sys_.y.copy(), sys_.z.copy()]
+    vel = [sys_.vx.copy(), sys_.vy.copy(), sys_.vz.copy()]
+    F = (np.zeros(n), np.zeros(n), np.zeros(n))
+    if per_row * n <= target_s:
+        rows = np.arange(n)
+        t = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t < target_s and steps < sys_.n_steps:
+            steps += 1
+            s = steps
+            oracle.vv(0, sys_.dt, sys_.inv_mass, F, pos, vel)
+            oracle.ionize(sys_, q, s)
+            out = oracle.forces_rows(sys_, rows, q=q, x=pos[0], y=pos[1], z=pos[2],
+                                     kappa=oracle.kappa_from_lambda(sys_.lambda_d[:, s]),
+                                     n_threads=threads)
+            F = (out["fx"], out["fy"], out["fz"])
+            oracle.vv(1, sys_.dt, sys_.inv_mass, F, pos, vel)
+        t_all = time.perf_counter() - t
+        return {"value": n * steps / t_all, "unit": "atom-steps/s", "cores": threads,
+                "kind": "oracle",
+                "sample": "O(N^2) FP64 oracle, %d whole steps of all %d atoms (all-pairs force "
+                          "rows, ionize, velocity Verlet) in %.1f s" % (steps, n, t_all)}
     rows_n = int(min(n, max(256, target_s / max(per_row, 1e-9))))
     rows = np.sort(rng.choice(n, rows_n, replace=False))
     t = time.perf_counter()
     oracle.forces_rows(sys_, rows, kappa=kap, n_threads=threads)
     t_rows = time.perf_counter() - t
-    q = sys_.q.copy()
-    pos = [sys_.x.copy(), sys_.y.copy(), sys_.z.copy()]
-    vel = [sys_.vx.copy(), sys_.vy.copy(), sys_.vz.copy()]
-    F = (np.zeros(n), np.zeros(n), np.zeros(n))
     t = time.perf_counter()
     oracle.vv(0, sys_.dt, sys_.inv_mass, F, pos, vel)
     oracle.ionize(sys_, q, 1)
@@ -155,21 +180,31 @@ def cpu_baseline(sys_, target_s=12.0, threads=None):
     t_elem = time.perf_counter() - t
     t_step = t_rows * n / rows_n + t_elem
     return {"value": n / t_step, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "O(N^2) FP64 oracle: full-j force rows of %d of %d atoms (%.1f s) plus "
-                      "ionize and velocity Verlet over all atoms, extrapolated to one full "
-                      "step (%.1f s)" % (rows_n, n, t_rows, t_step)}
+            "sample": "O(N^2) FP64 oracle: all-pairs force rows of %d of %d atoms (%.1f s) plus "
+                      "ionize and velocity Verlet over all atoms, scaled to one whole step "
+                      "(%.1f s)" % (rows_n, n, t_rows, t_step)}
 
 
-def traffic_from_profile(kernel_src_hash):
-    """HBM bytes per force launch from committed rocprofv3 counter runs, if they were
-    taken on the current force-kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "force32_water_98304_counters.json")
+def kernel_source_sha1():
+    d = os.path.join(ROOT, "paper_2401_03180_amd", "csrc")
+    src = b"".join(open(os.path.join(d, f), "rb").read() for f in ("md_force.hip", "md_internal.h"))
+    return hashlib.sha1(src).hexdigest()
+
+
+def traffic_from_profile():
+    """HBM bytes per force launch from the committed rocprofv3 counter summary, if it
+    was taken on the current force-kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "force32_water_98304_counters.txt")
     if not os.path.exists(path):
         return None
-    d = json.load(open(path))
-    if d.get("kernel_source_sha1") != kernel_src_hash:
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "|", "#")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha1") != kernel_source_sha1():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def main():
@@ -182,6 +217,8 @@ def main():
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch the step kernels one by one instead of replaying a graph")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -208,7 +245,8 @@ def main():
     S = a.warmup + a.steps
     sys32 = make_system(a.config, S)
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup)
-    r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, a.cluster_group, a.skin)
+    r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, a.cluster_group, a.skin,
+                  use_graph=not a.eager)
     log("fp32", {k: v for k, v in r32.items() if k != "stats"})
     n = sys32.n_atoms
     value = n * a.steps / (r32["ms"] * 1e-3)
@@ -226,7 +264,8 @@ def main():
              "list_capacity": r32["stats"]["list_capacity"]}
     if not a.no_fp64:
         sys64 = make_system(a.config, S)
-        r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, a.cluster_group, a.skin)
+        r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, a.cluster_group, a.skin,
+                      use_graph=not a.eager)
         log("fp64", {k: v for k, v in r64.items() if k != "stats"})
         v64 = n * a.steps / (r64["ms"] * 1e-3)
         extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
@@ -236,10 +275,9 @@ def main():
 
     kernel_ms = r32["kernel_ms"]
     achieved = FLOP_PER_PAIR * r32["pairs"] / (kernel_ms * 1e-3) / 1e12
-    src = open(os.path.join(ROOT, "paper_2401_03180_amd", "csrc", "md_force.hip"), "rb").read()
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": traffic_from_profile(hashlib.sha1(src).hexdigest()),
+                "traffic": traffic_from_profile(),
                 "kernel": "k_force32", "kernel_ms": kernel_ms,
                 "flop_per_pair": FLOP_PER_PAIR,
                 "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS}
@@ -251,7 +289,7 @@ def main():
            "config": {"workload": a.config, "atoms": n, "precision": "fp32 forces + kahan, "
                       "fp64 positions/integration/energies", "rc_nm": sys32.rc,
                       "skin_nm": a.skin if a.skin is not None else sys32.skin,
-                      "parallelism": "single-gpu"},
+                      "launch": "eager" if a.eager else "graph", "parallelism": "single-gpu"},
            "roofline": roofline, "extra": extra}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sys32)

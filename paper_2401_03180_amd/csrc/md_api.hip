@@ -237,8 +237,7 @@ static md_status size_and_allocate(Ctx* c)
                          M_PI * rl * rl * (X + Y + Z) + 4.0 / 3.0 * M_PI * rl * rl * rl;
         const int est = (int)(V * rho / kCluster * 1.35) + 16;
         E_cap = std::min(est, kMaxGroupEntries);
-        while (E_cap > 32 && (atom_lists_lds_bytes(E_cap, 2 * G) + 1024 > c->max_lds ||
-                              force32_lds_bytes(E_cap) + 8192 > c->max_lds))
+        while (E_cap > 32 && force32_lds_bytes(E_cap) + 8192 > c->max_lds)
             E_cap -= 8;
         if (E_cap >= est || G == 1) break;
         G /= 2;

@@ -19,7 +19,6 @@
 
 namespace md {
 
-constexpr float kFar = 1.0e4f;   // staged coordinate of padding slots
 
 __device__ inline int find_sys_by_col(const GridSys* grid, int B, int c)
 {
@@ -548,204 +547,7 @@ __global__ void __launch_bounds__(64 * kEntryWaves) k_group_entries(EntryArgs A)
     }
 }
 
-// ---------------------------------------------------------------- per-atom codes
-
-__host__ __device__ inline int wl_capacity(int E_cap) { return E_cap / 2 + 8; }
-
-// Byte offsets of the list kernel's LDS pieces, each 16-byte aligned.
-struct LdsLayout {
-    int ent, mask, wl, ring, total;
-};
-__host__ __device__ inline LdsLayout lists_lds_layout(int E_cap, int waves)
-{
-    auto up = [](int v) { return (v + 15) & ~15; };
-    LdsLayout L;
-    L.ent = up((E_cap * kCluster + 1) * 16);
-    L.mask = L.ent + up(E_cap * 4);
-    L.wl = L.mask + up(E_cap);
-    L.ring = L.wl + up(waves * wl_capacity(E_cap) * 2);
-    L.total = L.ring + waves * kCluster * 64 * 2;
-    return L;
-}
-
-struct ListArgs {
-    const double* xs;            // slot-order positions at build time (SoA, stride cap_slots)
-    int64_t cap_slots;
-    const GridSys* grid;
-    const Group* groups;
-    const uint32_t* ent;
-    const uint8_t* ent_mask;
-    const int32_t* slot_img;
-    const uint8_t* ts;
-    uint16_t* nb;
-    int32_t* cl_nt;
-    int32_t* cl_len;
-    int E_cap, nb_cap_h, nb_Th;  // per-half list capacity per atom, and its /8
-    int wl_cap;                  // per-wave entry-list capacity
-    float thr2;                  // (rc + skin)^2 with a relative margin
-    DevScalars* dsc;
-    const int32_t* gate;
-};
-
-// FP32 coordinates of slot `slot` in the group frame, shifted by the entry's image;
-// padding slots (NaN positions) are placed far away and flagged with valid = false.
-__device__ inline float3 staged_coords(const double* xs, int64_t cs, int64_t slot, int32_t img,
-                                       uint32_t en, const GridSys& gs, const double* c,
-                                       bool* valid)
-{
-    const double p0 = xs[slot];
-    *valid = p0 == p0;
-    float r[3];
-    for (int d = 0; d < 3; ++d) {
-        double v = xs[d * cs + slot];
-        if (gs.periodic) {
-            const int sh = (int)((en >> (26 + 2 * d)) & 3u) - 1;
-            v = v - (double)(unpack_img(img, d) - sh) * gs.L[d];
-        }
-        r[d] = *valid ? (float)(v - c[d]) : kFar;
-    }
-    return make_float3(r[0], r[1], r[2]);
-}
-
-// One work-group per group, two waves per cluster: wave (c, h) scans the entries
-// e = h, h + 2, ... that can reach cluster c and writes, for each of its 8 atoms, the
-// compacted codes of partners within rc + skin into that atom's half-list h.  The
-// force kernel's wave (c, h) consumes half-list h.
-__global__ void __launch_bounds__(1024) k_atom_lists(ListArgs A)
-{
-    if (gated_off(A.gate)) return;
-    extern __shared__ float4 s_dyn[];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int cw = w >> 1, h = w & 1;
-    // LDS carve-out (16-byte aligned pieces, sizes as in atom_lists_lds_bytes)
-    char* lds = reinterpret_cast<char*>(s_dyn);
-    const LdsLayout L = lists_lds_layout(A.E_cap, (int)(blockDim.x >> 6));
-    float4* s_pos = reinterpret_cast<float4*>(lds);
-    uint32_t* s_ent = reinterpret_cast<uint32_t*>(lds + L.ent);
-    uint8_t* s_mask = reinterpret_cast<uint8_t*>(lds + L.mask);
-    uint16_t* s_wl = reinterpret_cast<uint16_t*>(lds + L.wl);
-    uint16_t* s_ring = reinterpret_cast<uint16_t*>(lds + L.ring);
-    const int ngroups = A.dsc->n_groups;
-    const uint16_t sentinel = (uint16_t)(A.E_cap * kCluster);
-    const int64_t cs = A.cap_slots;
-    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
-        const Group gr = A.groups[g];
-        const GridSys gs = A.grid[gr.sys];
-        const int nst = gr.nent * kCluster;
-        for (int idx = tid; idx < nst; idx += blockDim.x) {
-            const int e = idx >> 3, jl = idx & 7;
-            const uint32_t en = A.ent[(int64_t)g * A.E_cap + e];
-            if (jl == 0) {
-                s_ent[e] = en;
-                s_mask[e] = A.ent_mask[(int64_t)g * A.E_cap + e];
-            }
-            const int64_t slot = (int64_t)(en & kEntClusterMask) * kCluster + jl;
-            bool ok;
-            const float3 f = staged_coords(A.xs, cs, slot, A.slot_img[slot], en, gs, gr.c, &ok);
-            s_pos[idx] = make_float4(f.x, f.y, f.z, ok ? (float)A.ts[slot] : -1.0f);
-        }
-        __syncthreads();
-        if (cw < gr.ncl) {
-            const int I = gr.cl0 + cw;
-            const int il = lane >> 3, k = lane & 7;
-            // this wave's entries: parity h and reachable from cluster cw, in order;
-            // e_self is the cluster's own unshifted entry (its diagonal is excluded)
-            uint16_t* wl = s_wl + w * A.wl_cap;
-            int ne = 0, e_self = -1;
-            for (int base = 0; base < gr.nent; base += 64) {
-                const int e = base + lane;
-                bool take = false;
-                if (e < gr.nent && (e & 1) == h) {
-                    take = ((s_mask[e] >> cw) & 1u) != 0u;
-                    const uint32_t en = s_ent[e];
-                    if ((en & kEntClusterMask) == (uint32_t)I && (en >> 26) == 0x15u) e_self = e;
-                }
-                const unsigned long long bal = __ballot(take);
-                if (take) {
-                    const int pos = ne + __popcll(bal & ((1ull << lane) - 1ull));
-                    if (pos < A.wl_cap) wl[pos] = (uint16_t)e;
-                }
-                ne += __popcll(bal);
-            }
-            for (int off = 32; off > 0; off >>= 1) e_self = max(e_self, __shfl_xor(e_self, off, 64));
-            ne = min(ne, A.wl_cap);
-            const int64_t slot_i = (int64_t)I * kCluster + il;
-            bool ok_i;
-            const float3 xi = staged_coords(A.xs, cs, slot_i, A.slot_img[slot_i], 0x54000000u, gs,
-                                            gr.c, &ok_i);
-            int cnt = 0;
-            uint16_t* out = A.nb + ((int64_t)I * 2 + h) * A.nb_Th * 64;
-            // Codes pass through a 2-row ring in LDS, ordered by their owner lane, so
-            // every completed row (32 codes of one atom = 64 contiguous bytes of the
-            // list) is written with one 8-byte store per lane.
-            uint16_t* ring = s_ring + w * (kCluster * 64);
-            auto ring_at = [&](int atom, int pos) -> uint16_t& {
-                // owner lane pos % 8, iteration t = pos / 8 -> (row parity, lane, t % 4)
-                return ring[atom * 64 + ((pos >> 5) & 1) * 32 + (pos & 7) * 4 + ((pos >> 3) & 3)];
-            };
-            auto flush_row = [&](int row) {
-                // lane (il, k) writes codes of iterations 4 row .. 4 row + 3
-                const uint64_t v = *reinterpret_cast<const uint64_t*>(
-                    &ring[il * 64 + (row & 1) * 32 + k * 4]);
-                if ((row + 1) * 32 <= A.nb_cap_h)
-                    *reinterpret_cast<uint64_t*>(&out[((int64_t)row * 64 + il * 8 + k) * 4]) = v;
-            };
-            auto test = [&](int e) {
-                const int j = e * kCluster + k;
-                const float4 pj = s_pos[j];
-                const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
-                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                const bool pass = ok_i && (pj.w >= 0.0f) && (r2 < A.thr2) &&
-                                  !(e == e_self && k == il);
-                const unsigned long long bal = __ballot(pass);
-                const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
-                if (pass) {
-                    const int pos = cnt + __popc(mine & ((1u << k) - 1u));
-                    ring_at(il, pos) = (uint16_t)(j | ((int)pj.w << kCodeIdxBits));
-                }
-                const int before = cnt;
-                cnt += __popc(mine);
-                __builtin_amdgcn_wave_barrier();
-                if ((cnt >> 5) != (before >> 5)) flush_row(before >> 5);   // a row completed
-                __builtin_amdgcn_wave_barrier();
-            };
-            int i = 0;
-            for (; i + 1 < ne; i += 2) {
-                const int e0 = wl[i], e1 = wl[i + 1];
-                test(e0);
-                test(e1);
-            }
-            if (i < ne) test(wl[i]);
-            int mx = cnt;
-            for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
-            // rows of 4 iterations (32 codes per atom); pad and write the open rows
-            const int nrow = min((mx + 31) >> 5, A.nb_Th >> 2);
-            for (int row = cnt >> 5; row < nrow; ++row) {
-                for (int p = 0; p < 4; ++p) {
-                    const int pos = row * 32 + p * 8 + k;
-                    if (pos >= cnt) ring_at(il, pos) = sentinel;
-                }
-                __builtin_amdgcn_wave_barrier();
-                flush_row(row);
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (lane == 0) {
-                A.cl_nt[(int64_t)I * 2 + h] = nrow;
-                A.cl_len[(int64_t)I * 2 + h] = mx;
-                if (mx > A.nb_cap_h || ne >= A.wl_cap) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------- orchestration
-
-size_t atom_lists_lds_bytes(int E_cap, int waves)
-{
-    return lists_lds_layout(E_cap, waves).total;
-}
 
 void launch_build(Ctx* c, const double* x, const double* y, const double* z,
                   const uint8_t* type, bool force, hipStream_t st)
@@ -798,24 +600,6 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
                            st, A);
     }
     hipLaunchKernelGGL(k_build_done, dim3(1), dim3(1), 0, st, c->dsc, gate);
-}
-
-// Per-atom lists for the FP64 path (the FP32 force kernel builds them itself):
-// runs only while lists are pending after a candidate-table build.
-__global__ void k_lists_done(DevScalars* d) { d->lists_pending = 0; }
-
-void launch_lists(Ctx* c, hipStream_t st)
-{
-    const int32_t* gate = &c->dsc->lists_pending;
-    const double m = c->rlist * (1.0 + 1e-5);
-    ListArgs A{c->d_xs, c->cap_slots, c->d_grid, c->d_groups, c->d_ent, c->d_ent_mask,
-               c->d_slot_img, c->d_ts, c->d_nb, c->d_cl_nt, c->d_cl_len, c->E_cap, c->nb_cap_h,
-               c->nb_Th, wl_capacity(c->E_cap), (float)(m * m), c->dsc, gate};
-    const size_t lds = atom_lists_lds_bytes(c->E_cap, 2 * c->G);
-    const int per_cu = (int)std::max<size_t>(1, c->lds_per_cu / (lds + 1024));
-    const int nb = (int)std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu);
-    hipLaunchKernelGGL(k_atom_lists, dim3(std::max(nb, 1)), dim3(128 * c->G), lds, st, A);
-    hipLaunchKernelGGL(k_lists_done, dim3(1), dim3(1), 0, st, c->dsc);
 }
 
 __global__ void k_skin_check(DevScalars* d)

@@ -252,7 +252,9 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
 
 // ------------------------------------------------------------------ FP32 kernel
 
-template <bool ENERGY, bool EMIT, bool SCREEN_LJ>
+// LISTS: only (re)build the per-atom lists, for the FP64 kernel; does nothing
+// unless a rebuild is pending.
+template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool LISTS = false>
 __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 {
     extern __shared__ float4 s_j[];
@@ -269,6 +271,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
     const int ngroups = A.dsc->n_groups;
     // candidate tables were rebuilt: (re)build the per-atom half-lists first
     const bool rebuild = __builtin_amdgcn_readfirstlane(A.dsc->lists_pending) != 0;
+    if (LISTS && !rebuild) return;
     for (int i = tid; i < A.T * A.T; i += blockDim.x)
         s_lj[i] = make_float2(A.lj32[2 * i], A.lj32[2 * i + 1]);
     const int sentinel = A.E_cap * kCluster;
@@ -381,6 +384,11 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             if (act)
                 nr = build_half_list(A, I, half, cw, il, k8, ai, xi, yi, zi, gr.nent, s_j, s_mask,
                                      sentinel);
+            if (LISTS) {              // static group order (the force queue is not used)
+                __syncthreads();
+                g += gridDim.x;
+                continue;
+            }
             // the lists are read back only inside this work-group: the barrier's
             // work-group-scope ordering suffices (an agent-scope fence would write
             // back the L2)
@@ -635,6 +643,8 @@ hipError_t force_kernel_setup(Ctx* c)
     set_lds_attr<true, false, false>(lds);  set_lds_attr<true, false, true>(lds);
     set_lds_attr<false, true, false>(lds);  set_lds_attr<false, true, true>(lds);
     set_lds_attr<true, true, false>(lds);   set_lds_attr<true, true, true>(lds);
+    (void)hipFuncSetAttribute((const void*)k_force32<false, false, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return hipGetLastError();
 }
 
@@ -668,18 +678,23 @@ hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, doub
         const double m = c->rlist * (1.0 + 1e-5);
         A.thr2 = (float)(m * m);
     }
-    if (prec == MD_FP64) launch_lists(c, st);     // the FP32 kernel builds its own lists
     // persistent grid: as many work-groups as fit on every CU at once (LDS, waves)
-    int per_cu;
-    if (prec == MD_FP32_KAHAN) {
+    int per_cu32;
+    {
         const size_t lds = force32_lds_bytes(c->E_cap) + c->force32_static_lds;
-        per_cu = (int)std::max<size_t>(1, c->lds_per_cu / lds);
-        per_cu = std::min(per_cu, std::max(1, 32 / (c->G * A.wpc)));
-    } else {
-        per_cu = std::max(1, 16 / c->G);
+        per_cu32 = (int)std::max<size_t>(1, c->lds_per_cu / lds);
+        per_cu32 = std::min(per_cu32, std::max(1, 32 / (c->G * A.wpc)));
     }
+    const int per_cu = prec == MD_FP32_KAHAN ? per_cu32 : std::max(1, 16 / c->G);
     const int blocks = (int)std::max<int64_t>(
         1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu));
+    if (prec == MD_FP64) {
+        // the FP32 kernel's list builder, alone (the FP32 force kernel builds its own)
+        const int lb = (int)std::max<int64_t>(
+            1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu32));
+        hipLaunchKernelGGL((k_force32<false, false, false, true>), dim3(lb),
+                           dim3(64 * c->G * A.wpc), force32_lds_bytes(c->E_cap), st, A);
+    }
     const bool E = epot != nullptr, M = emit != nullptr, S = c->cfg.screen_lj != 0;
     if (ev0) {
         const hipError_t e = hipEventRecord(ev0, st);

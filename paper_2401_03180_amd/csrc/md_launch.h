@@ -24,8 +24,6 @@ void launch_clear_flags(Ctx* c, hipStream_t st);
 void launch_build(Ctx* c, const double* x, const double* y, const double* z, const uint8_t* type,
                   bool force, hipStream_t st);
 void launch_skin_check(Ctx* c, hipStream_t st);
-size_t atom_lists_lds_bytes(int E_cap, int waves);
-void launch_lists(Ctx* c, hipStream_t st);
 
 // md_force.hip
 void launch_repack(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
