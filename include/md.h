@@ -89,13 +89,19 @@ typedef struct md_config {
     int32_t cluster_group;      /* i-clusters per force work-group: 1, 2, 4 or 8 (0 = 4) */
     int32_t max_neighbors;      /* per-atom neighbour-list capacity (0 = derived) */
     double density_hint;        /* upper bound on atoms per nm^3 used for sizing (0 = 130) */
+    int32_t fast_capacity;      /* atoms allowed beyond skin/2 of their build position before a
+                                   rebuild is due; their pairs are evaluated separately, exactly
+                                   (0 = min(1024, max(64, N/96)); -1 = none: rebuild as soon as
+                                   one atom is that far; at most 65536) */
+    int32_t reserved;           /* 0 */
 } md_config;
 
 /* Build modes of md_build_cells. */
 #define MD_BUILD_AUTO 0         /* device-decided: the build kernels are enqueued but do their
-                                   work only if phase 0 of md_integrate_vv found an atom that
-                                   moved more than skin/2 since the last build (no host
-                                   round trip, graph-capturable); the first build always runs */
+                                   work only if phase 0 of md_integrate_vv found more than
+                                   fast_capacity atoms that moved more than skin/2 since the
+                                   last build (no host round trip, graph-capturable); the
+                                   first build always runs */
 #define MD_BUILD_FORCE 1        /* rebuild now */
 #define MD_BUILD_CHECK 2        /* never rebuild; latch MD_FLAG_SKIN if a rebuild was due */
 
@@ -255,6 +261,7 @@ typedef struct md_stats {
     int64_t max_list_len, list_capacity;                /* per atom */
     int64_t max_group_entries, group_entry_capacity;
     int64_t n_builds;                                   /* builds executed on the device */
+    int64_t n_fast, n_fast_raw;                         /* fast atoms now (capped, found) */
     int32_t cluster_group;
     uint32_t flags;
 } md_stats;

@@ -55,7 +55,8 @@ void free_all(Ctx* c)
                     c->d_col_pre, c->d_cl_lo, c->d_cl_hi,
                     c->d_cl_nt, c->d_cl_len, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_qs,
                     c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
-                    c->d_partial};
+                    c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
+                    c->d_fast_list, c->d_fast_e, c->d_atype};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -117,6 +118,8 @@ md_status md_create(const md_config* cfg, const int64_t* sys_offsets, md_ctx** o
     const int G = cfg->cluster_group ? cfg->cluster_group : 4;
     if (G != 1 && G != 2 && G != 4 && G != 8)
         return fail(nullptr, MD_ERR_ARG, "cluster_group must be 1, 2, 4 or 8");
+    if (cfg->fast_capacity < -1 || cfg->fast_capacity > 65536)
+        return fail(nullptr, MD_ERR_ARG, "fast_capacity must be in [-1, 65536]");
     if (sys_offsets[0] != 0) return fail(nullptr, MD_ERR_ARG, "sys_offsets[0] must be 0");
     for (int b = 0; b < cfg->n_systems; ++b)
         if (sys_offsets[b + 1] < sys_offsets[b])
@@ -251,8 +254,11 @@ static md_status size_and_allocate(Ctx* c)
     c->nb_cap = nb_cap;
     // two half-lists per atom (entries of even / odd index), each with some slack
     c->nb_cap_h = ((nb_cap / 2 + nb_cap / 16 + 8) + 31) & ~31;     // rows of 32 codes
-    c->nb_Th = c->nb_cap_h / 8;
     c->cap_partials = vv_partials_needed(N, B);
+    // fast-atom capacity: beyond it a rebuild is due (-1: rebuild on the first fast atom)
+    if (cfg.fast_capacity < 0) c->fast_cap = 0;
+    else if (cfg.fast_capacity > 0) c->fast_cap = cfg.fast_capacity;
+    else c->fast_cap = (int)std::min<int64_t>(1024, std::max<int64_t>(64, N / 96));
 
     // allocation
     HIP_TRY(c, dalloc(&c->dsc, 1));
@@ -284,10 +290,19 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, dalloc(&c->d_groups, c->cap_groups));
     HIP_TRY(c, dalloc(&c->d_ent, c->cap_groups * (int64_t)E_cap));
     HIP_TRY(c, dalloc(&c->d_ent_mask, c->cap_groups * (int64_t)E_cap));
-    HIP_TRY(c, dalloc(&c->d_nb, c->cap_clusters * 2 * (int64_t)c->nb_Th * 64));
+    HIP_TRY(c, dalloc(&c->d_nb, c->cap_clusters * 2 * kCluster * (int64_t)c->nb_cap_h));
     HIP_TRY(c, dalloc(&c->d_grp_epot, c->cap_groups));
     HIP_TRY(c, dalloc(&c->d_xref, 3 * N));
     HIP_TRY(c, dalloc(&c->d_partial, c->cap_partials));
+    {
+        const int64_t nvb = div_up(std::max<int64_t>(N, 1), 256);
+        HIP_TRY(c, dalloc(&c->d_fast_flag, std::max<int64_t>(N, 1)));
+        HIP_TRY(c, dalloc(&c->d_fast_loc, nvb * 256));
+        HIP_TRY(c, dalloc(&c->d_fast_cnt, nvb));
+        HIP_TRY(c, dalloc(&c->d_fast_list, std::max(c->fast_cap, 1)));
+        HIP_TRY(c, dalloc(&c->d_fast_e, std::max(c->fast_cap, 1)));
+        HIP_TRY(c, dalloc(&c->d_atype, std::max<int64_t>(N, 1)));
+    }
 
     // initial contents
     DevScalars h{};
@@ -314,6 +329,9 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, hipMemset(c->d_xref, 0, sizeof(double) * 3 * std::max<int64_t>(N, 1)));
     HIP_TRY(c, hipMemset(c->d_sys_grp0, 0, sizeof(int32_t) * (B + 1)));
     HIP_TRY(c, hipMemset(c->d_grp_epot, 0, sizeof(double) * c->cap_groups));
+    HIP_TRY(c, hipMemset(c->d_fast_flag, 0, std::max<int64_t>(N, 1)));
+    HIP_TRY(c, hipMemset(c->d_atype, 0, std::max<int64_t>(N, 1)));
+    HIP_TRY(c, hipMemset(c->d_fast_cnt, 0, sizeof(int32_t) * div_up(std::max<int64_t>(N, 1), 256)));
     HIP_TRY(c, force_kernel_setup(c));
     return MD_OK;
 }
@@ -349,11 +367,13 @@ md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const
         if (qmax[e] < 0) return fail(c, MD_ERR_ARG, "qmax must be >= 0");
     if (c->tables_bound) {
         (void)hipDeviceSynchronize();
+        free_timer(c);
         free_all(c);
         Ctx fresh;
         fresh.cfg = c->cfg; fresh.B = c->B; fresh.N = c->N; fresh.G = c->cfg.cluster_group ? c->cfg.cluster_group : 4;
         fresh.sys_off = c->sys_off; fresh.rlist = c->rlist; fresh.device = c->device;
-        fresh.n_cu = c->n_cu; fresh.max_lds = c->max_lds;
+        fresh.n_cu = c->n_cu; fresh.max_lds = c->max_lds; fresh.lds_per_cu = c->lds_per_cu;
+        fresh.force32_static_lds = c->force32_static_lds;
         *c = fresh;
     }
     c->box.assign(c->cfg.periodic ? box : nullptr, c->cfg.periodic ? box + 3 * B : nullptr);
@@ -463,7 +483,8 @@ md_status md_screened_forces(md_ctx* ctx, md_precision prec, const double* x, co
     hipEvent_t e0, e1;
     next_timer_events(c, S(stream), &e0, &e1);
     launch_repack(c, x, y, z, q, S(stream));
-    HIP_TRY(c, launch_forces(c, prec, fx, fy, fz, epot, nullptr, 0, S(stream), e0, e1));
+    HIP_TRY(c, launch_forces(c, prec, x, y, z, q, fx, fy, fz, epot, nullptr, 0, S(stream), e0,
+                             e1));
     return MD_OK;
 }
 
@@ -564,7 +585,7 @@ md_status md_debug_pairs(md_ctx* ctx, md_precision prec, const double* x, const 
     e = hipMemsetAsync(&c->dsc->pair_count, 0, sizeof(unsigned long long), st);
     if (e == hipSuccess) {
         launch_repack(c, x, y, z, q, st);
-        e = launch_forces(c, prec, f, f + c->N, f + 2 * c->N, nullptr, buf, max, st);
+        e = launch_forces(c, prec, x, y, z, q, f, f + c->N, f + 2 * c->N, nullptr, buf, max, st);
     }
     unsigned long long cnt = 0;
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -596,6 +617,8 @@ md_status md_get_stats(md_ctx* ctx, md_stats* out, md_stream stream)
     out->n_clusters = h.n_clusters;
     out->n_groups = h.n_groups;
     out->n_builds = h.n_builds;
+    out->n_fast = h.n_fast;
+    out->n_fast_raw = h.n_fast_raw;
     out->flags = h.flags;
     int64_t ne = 0, max_e = 0, codes = 0, max_l = 0;
     if (h.n_groups > 0) {

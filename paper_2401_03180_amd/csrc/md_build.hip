@@ -49,6 +49,8 @@ __global__ void k_build_done(DevScalars* d, const int32_t* gate)
     d->need_rebuild = 0;
     d->lists_pending = 1;
     d->disp2_bits = 0ull;
+    d->n_fast = 0;
+    d->n_fast_raw = 0;
     d->n_builds += 1;
 }
 
@@ -173,6 +175,7 @@ struct BinArgs {
     int32_t* rank;
     int32_t* img;
     double* xref;
+    uint8_t* fast_flag;
     int64_t cap_bins;
     DevScalars* dsc;
     const int32_t* gate;
@@ -208,6 +211,7 @@ __device__ inline void bin_one(const BinArgs& A, int64_t a)
     A.xref[a] = p[0];
     A.xref[A.N + a] = p[1];
     A.xref[2 * A.N + a] = p[2];
+    A.fast_flag[a] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_bin(BinArgs A)
@@ -295,6 +299,7 @@ struct ClusterArgs {
     int32_t* inv_perm;
     int32_t* slot_img;
     uint8_t* ts;
+    uint8_t* atype;
     double* xs;
     int64_t cap_slots;
     double* cl_lo;
@@ -359,6 +364,7 @@ __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
                 int ty = A.type[a];
                 if (ty >= A.T) { set_flag(A.dsc, MD_FLAG_BAD_INPUT); ty = A.T - 1; }
                 A.ts[slot] = (uint8_t)ty;
+                A.atype[a] = (uint8_t)ty;
                 const double p[3] = {A.x[a], A.y[a], A.z[a]};
                 for (int d = 0; d < 3; ++d) A.xs[d * A.cap_slots + slot] = p[d];
                 for (int d = 0; d < 3; ++d) {
@@ -563,7 +569,7 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
     }
     {
         BinArgs A{N, x, y, z, c->d_sys_of_atom, c->d_grid, c->d_bin_cnt, c->d_key, c->d_rank,
-                  c->d_img, c->d_xref, c->cap_bins, c->dsc, gate};
+                  c->d_img, c->d_xref, c->d_fast_flag, c->cap_bins, c->dsc, gate};
         const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(N, 256), wide));
         hipLaunchKernelGGL(k_bin, dim3(nb), dim3(256), 0, st, A);
     }
@@ -584,7 +590,8 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
     launch_scan64(c->d_col_cnt, c->d_col_pre, c->cap_cols + 1, c->d_scan_tmp, gate, st);
     {
         ClusterArgs A{x, y, z, type, c->d_grid, c->B, c->d_bin_start, c->d_sorted, c->d_col_pre,
-                      c->d_img, c->d_perm, c->d_inv_perm, c->d_slot_img, c->d_ts, c->d_xs,
+                      c->d_img, c->d_perm, c->d_inv_perm, c->d_slot_img, c->d_ts, c->d_atype,
+                      c->d_xs,
                       c->cap_slots, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_sys_grp0,
                       c->cap_clusters, c->G, c->T, c->dsc, gate};
         const int nb = (int)std::max<int64_t>(
@@ -594,8 +601,8 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
     {
         EntryArgs A{c->d_grid, c->d_col_pre, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
                     c->d_ent_mask, c->E_cap, c->rlist, c->dsc, gate};
-        const int nb = (int)std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * 4);
         const size_t lds = (size_t)kEntryWaves * c->E_cap * (sizeof(uint32_t) + 1);
+        const int nb = (int)std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * 4);
         hipLaunchKernelGGL(k_group_entries, dim3(std::max(nb, 1)), dim3(64 * kEntryWaves), lds,
                            st, A);
     }

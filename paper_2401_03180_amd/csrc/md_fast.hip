@@ -1,0 +1,344 @@
+// md_fast.hip -- pairs of "fast" atoms between neighbour builds (arXiv 2401.03180,
+// section II.A Eq. 2 and Eq. 8, section II.B cutoff; same pair predicate and
+// potential as the list kernels).
+//
+// The per-atom lists hold every partner within rc + skin at the last build, so a pair
+// whose two atoms have each moved at most skin/2 since then is in them.  An atom that
+// has moved farther ("fast": flagged by the first velocity-Verlet half step) is staged
+// like a padding slot by the list kernels, and every pair it takes part in is
+// evaluated here, in FP64 with the exact predicate:
+//   * k_fast_self: one work-group per fast atom f scans the columns within
+//     rc + skin/2 of f (every other atom sits in the column of its build position,
+//     which is within skin/2 of where it is now) and then every other fast atom;
+//     it writes F_f and the energy of f's pairs (pairs with another fast atom count
+//     one half from each side);
+//   * k_fast_nbr: one work-group per column adds, to each non-fast atom of the
+//     column, the forces of the fast atoms within reach, in fast-list order.
+// No atomics on forces: every result is written by one thread in a fixed order.
+#include "md_internal.h"
+#include "md_launch.h"
+
+namespace md {
+
+constexpr int kFastBlock = 256;
+
+struct FastArgs {
+    const double *x, *y, *z;       // caller positions (current)
+    const int8_t* q;               // caller charges (current)
+    const uint8_t* atype;          // types in caller order (build time)
+    const int32_t* sys_of_atom;
+    const int64_t* sys_off;
+    const GridSys* grid;
+    int B;
+    const int64_t* col_pre;
+    const int32_t* perm;
+    const double* kappa;
+    int64_t S1;
+    const double *c6, *c12;
+    int T;
+    double rc2, reach;             // rc^2; column search radius rc + skin/2
+    int screen_lj;
+    const uint8_t* fast_flag;
+    const int32_t* fast_list;
+    double* fast_e;
+    DevScalars* dsc;
+    double *fx, *fy, *fz;
+    int2* emit;
+    int64_t emit_max;
+};
+
+__device__ inline int col_first_cluster(const int64_t* pre, int c)
+{
+    return (int)(pre[c] & 0xFFFFFFFFll);
+}
+
+// Exact membership and FP64 pair terms for d = p_a - p_b (minimum image); returns
+// false when the pair is outside the cutoff.  f multiplies d for the force on a.
+__device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double kap, double xa,
+                                 double ya, double za, int qa, int ta, double xb, double yb,
+                                 double zb, int qb, int tb, double* dx, double* dy, double* dz,
+                                 double* f, double* e)
+{
+    double r2;
+    {
+#pragma clang fp contract(off)
+        double ex = xa - xb, ey = ya - yb, ez = za - zb;
+        if (gs.periodic) {
+            ex = ex - gs.L[0] * rint(ex * gs.invL[0]);
+            ey = ey - gs.L[1] * rint(ey * gs.invL[1]);
+            ez = ez - gs.L[2] * rint(ez * gs.invL[2]);
+        }
+        r2 = ex * ex + ey * ey;
+        r2 = r2 + ez * ez;
+        *dx = ex; *dy = ey; *dz = ez;
+    }
+    if (!(r2 < A.rc2)) return false;
+    const double c6 = A.c6[ta * A.T + tb], c12 = A.c12[ta * A.T + tb];
+    const double r = sqrt(r2);
+    const double rinv2 = 1.0 / r2;
+    const double rinv6 = rinv2 * rinv2 * rinv2;
+    const double s = exp(-kap * r);
+    const double uc = kKe * (double)qa * (double)qb / r;
+    const double l12 = c12 * rinv6 * rinv6, l6 = c6 * rinv6;
+    if (A.screen_lj) {
+        const double uu = uc + (l12 - l6);
+        *f = ((uc + 12.0 * l12 - 6.0 * l6) + uu * (kap * r)) * s * rinv2;
+        *e = uu * s;
+    } else {
+        *f = (uc + uc * (kap * r)) * s * rinv2 + (12.0 * l12 - 6.0 * l6) * rinv2;
+        *e = uc * s + (l12 - l6);
+    }
+    return true;
+}
+
+__device__ inline void emit_one(const FastArgs& A, int a, int b)
+{
+    const unsigned long long p = atomicAdd(&A.dsc->pair_count, 1ull);
+    if ((int64_t)p < A.emit_max) A.emit[p] = make_int2(min(a, b), max(a, b));
+}
+
+// Distance from the point p to the interval [lo, hi] along one axis; periodic axes
+// take the nearest image of p.
+__device__ inline double axis_gap(double p, double lo, double hi, bool periodic, double L)
+{
+    double g = fmax(0.0, fmax(lo - p, p - hi));
+    if (periodic) {
+        g = fmin(g, fmax(0.0, fmax(lo - (p + L), (p + L) - hi)));
+        g = fmin(g, fmax(0.0, fmax(lo - (p - L), (p - L) - hi)));
+    }
+    return g;
+}
+
+// Column index range along axis d (x or y) within `reach` of coordinate p.  Periodic
+// ranges are in unwrapped column numbers (callers wrap them) and become every column
+// when they would cover the axis (also for a non-finite p); vacuum ranges are clamped
+// to the grid.  The range length never exceeds the column count.
+__device__ inline void col_range(const GridSys& g, int d, double p, double reach, int* c0, int* c1)
+{
+    if (g.periodic) {
+        const double w = p - g.L[d] * floor(p * g.invL[d]);
+        const double a = floor((w - reach) * g.inv_w[d]);
+        const double b = floor((w + reach) * g.inv_w[d]);
+        if (!(b - a + 1.0 < (double)g.n[d]) || !(fabs(a) < 1e6) || !(fabs(b) < 1e6)) {
+            *c0 = 0; *c1 = g.n[d] - 1;
+        } else {
+            *c0 = (int)a; *c1 = (int)b;
+        }
+    } else {
+        const double w = p - g.origin[d];
+        const double a = fmin(fmax(floor((w - reach) * g.inv_w[d]), 0.0), (double)(g.n[d] - 1));
+        const double b = fmin(fmax(floor((w + reach) * g.inv_w[d]), 0.0), (double)(g.n[d] - 1));
+        *c0 = (int)a; *c1 = (int)b;
+    }
+}
+
+__device__ inline double block_sum(double v, double* s)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += s[k];
+    return t;
+}
+
+__device__ inline int64_t clamp_step_fast(const FastArgs& A)
+{
+    int64_t s = A.dsc->step;
+    return s < 0 ? 0 : (s >= A.S1 ? A.S1 - 1 : s);
+}
+
+template <bool ENERGY, bool EMIT>
+__global__ void __launch_bounds__(kFastBlock) k_fast_self(FastArgs A)
+{
+    __shared__ double s_red[kFastBlock / 64];
+    const int nf = A.dsc->n_fast;
+    const int fi = blockIdx.x;
+    if (fi >= nf) return;
+    const int f = A.fast_list[fi];
+    const int b = A.sys_of_atom[f];
+    const GridSys gs = A.grid[b];
+    const double kap = A.kappa[(int64_t)b * A.S1 + clamp_step_fast(A)];
+    const double xf = A.x[f], yf = A.y[f], zf = A.z[f];
+    const int qf = A.q[f], tf = A.atype[f];
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, E = 0.0;
+    int cx0, cx1, cy0, cy1;
+    col_range(gs, 0, xf, A.reach, &cx0, &cx1);
+    col_range(gs, 1, yf, A.reach, &cy0, &cy1);
+    for (int cx = cx0; cx <= cx1; ++cx) {
+        const int wx = gs.periodic ? ((cx % gs.n[0]) + gs.n[0]) % gs.n[0] : cx;
+        for (int cy = cy0; cy <= cy1; ++cy) {
+            const int wy = gs.periodic ? ((cy % gs.n[1]) + gs.n[1]) % gs.n[1] : cy;
+            const int col = gs.col_off + wx * gs.n[1] + wy;
+            const int64_t s0 = (int64_t)col_first_cluster(A.col_pre, col) * kCluster;
+            const int64_t s1 = min((int64_t)col_first_cluster(A.col_pre, col + 1) * kCluster,
+                                   (int64_t)A.dsc->n_slots);
+            for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+                const int a = A.perm[s];
+                if (a < 0 || a == f || A.fast_flag[a]) continue;
+                double dx, dy, dz, fp, e;
+                if (pair_fp64(A, gs, kap, xf, yf, zf, qf, tf, A.x[a], A.y[a], A.z[a], A.q[a],
+                              A.atype[a], &dx, &dy, &dz, &fp, &e)) {
+                    Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
+                    if (ENERGY) E += e;
+                    if (EMIT) emit_one(A, f, a);
+                }
+            }
+        }
+    }
+    // other fast atoms of the same system, by their current positions
+    const int64_t a0 = A.sys_off[b], a1 = A.sys_off[b + 1];
+    for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+        const int g = A.fast_list[k];
+        if (g == f || g < a0 || g >= a1) continue;
+        double dx, dy, dz, fp, e;
+        if (pair_fp64(A, gs, kap, xf, yf, zf, qf, tf, A.x[g], A.y[g], A.z[g], A.q[g],
+                      A.atype[g], &dx, &dy, &dz, &fp, &e)) {
+            Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
+            if (ENERGY) E += 0.5 * e;
+            if (EMIT && f < g) emit_one(A, f, g);
+        }
+    }
+    Fx = block_sum(Fx, s_red);
+    Fy = block_sum(Fy, s_red);
+    Fz = block_sum(Fz, s_red);
+    if (ENERGY) E = block_sum(E, s_red);
+    if (threadIdx.x == 0) {
+        A.fx[f] = Fx;
+        A.fy[f] = Fy;
+        A.fz[f] = Fz;
+        if (ENERGY) A.fast_e[fi] = E;
+    }
+}
+
+// System of a global column: the last system whose first column is <= c.
+__device__ inline int sys_of_col(const GridSys* grid, int B, int c)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (grid[mid].col_off <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int kFastLocal = 1024;     // fast atoms near one column held in LDS
+
+__global__ void __launch_bounds__(kFastBlock) k_fast_nbr(FastArgs A)
+{
+    __shared__ int s_loc[kFastLocal];
+    __shared__ int s_cnt[kFastBlock / 64];
+    const int nf = A.dsc->n_fast;
+    const int col = blockIdx.x;
+    if (nf == 0 || col >= A.dsc->n_cols) return;
+    const int b = sys_of_col(A.grid, A.B, col);
+    const GridSys gs = A.grid[b];
+    const int lc = col - gs.col_off;
+    const int cx = lc / gs.n[1], cy = lc % gs.n[1];
+    // column rectangle (edge columns of a vacuum grid extend outward: binning clamps)
+    double lo[2], hi[2];
+    const int cc[2] = {cx, cy};
+    for (int d = 0; d < 2; ++d) {
+        const double o = gs.periodic ? 0.0 : gs.origin[d];
+        lo[d] = o + cc[d] * gs.w[d];
+        hi[d] = o + (cc[d] + 1) * gs.w[d];
+        if (!gs.periodic && cc[d] == 0) lo[d] = -INFINITY;
+        if (!gs.periodic && cc[d] == gs.n[d] - 1) hi[d] = INFINITY;
+    }
+    const int64_t a0 = A.sys_off[b], a1 = A.sys_off[b + 1];
+    const double R2 = A.reach * A.reach;
+    // fast atoms of this system within reach of the column, in fast-list order
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int total = 0;
+    for (int base = 0; base < nf; base += blockDim.x) {
+        const int k = base + threadIdx.x;
+        bool take = false;
+        if (k < nf) {
+            const int g = A.fast_list[k];
+            if (g >= a0 && g < a1) {
+                double px = A.x[g], py = A.y[g];
+                if (gs.periodic) {
+                    px -= gs.L[0] * floor(px * gs.invL[0]);
+                    py -= gs.L[1] * floor(py * gs.invL[1]);
+                }
+                const double gx = axis_gap(px, lo[0], hi[0], gs.periodic, gs.L[0]);
+                const double gy = axis_gap(py, lo[1], hi[1], gs.periodic, gs.L[1]);
+                take = gx * gx + gy * gy < R2;
+            }
+        }
+        const unsigned long long bal = __ballot(take);
+        if (lane == 0) s_cnt[w] = __popcll(bal);
+        __syncthreads();
+        int off = total;
+        for (int v = 0; v < w; ++v) off += s_cnt[v];
+        int add = 0;
+        for (int v = 0; v < (int)(blockDim.x >> 6); ++v) add += s_cnt[v];
+        if (take) {
+            const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
+            if (pos < kFastLocal) s_loc[pos] = A.fast_list[k];
+        }
+        total += add;
+        __syncthreads();
+    }
+    if (total == 0) return;
+    if (total > kFastLocal) {
+        if (threadIdx.x == 0) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
+        total = kFastLocal;
+    }
+    const double kap = A.kappa[(int64_t)b * A.S1 + clamp_step_fast(A)];
+    const int64_t s0 = (int64_t)col_first_cluster(A.col_pre, col) * kCluster;
+    const int64_t s1 = min((int64_t)col_first_cluster(A.col_pre, col + 1) * kCluster,
+                           (int64_t)A.dsc->n_slots);
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+        const int a = A.perm[s];
+        if (a < 0 || A.fast_flag[a]) continue;
+        const double xa = A.x[a], ya = A.y[a], za = A.z[a];
+        const int qa = A.q[a], ta = A.atype[a];
+        double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+        bool any = false;
+        for (int k = 0; k < total; ++k) {
+            const int g = s_loc[k];
+            double dx, dy, dz, fp, e;
+            if (pair_fp64(A, gs, kap, xa, ya, za, qa, ta, A.x[g], A.y[g], A.z[g], A.q[g],
+                          A.atype[g], &dx, &dy, &dz, &fp, &e)) {
+                Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
+                any = true;
+            }
+        }
+        if (any) {
+            A.fx[a] += Fx;
+            A.fy[a] += Fy;
+            A.fz[a] += Fz;
+        }
+    }
+}
+
+void launch_fast(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
+                 double* fx, double* fy, double* fz, bool energy, int2* emit, int64_t emit_max,
+                 hipStream_t st)
+{
+    FastArgs A;
+    A.x = x; A.y = y; A.z = z; A.q = q; A.atype = c->d_atype;
+    A.sys_of_atom = c->d_sys_of_atom; A.sys_off = c->d_sys_off; A.grid = c->d_grid; A.B = c->B;
+    A.col_pre = c->d_col_pre; A.perm = c->d_perm;
+    A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
+    A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T;
+    A.rc2 = c->cfg.rc * c->cfg.rc;
+    A.reach = c->cfg.rc + 0.5 * c->cfg.skin;
+    A.screen_lj = c->cfg.screen_lj;
+    A.fast_flag = c->d_fast_flag; A.fast_list = c->d_fast_list; A.fast_e = c->d_fast_e;
+    A.dsc = c->dsc; A.fx = fx; A.fy = fy; A.fz = fz; A.emit = emit; A.emit_max = emit_max;
+    const dim3 gs((unsigned)std::max(c->fast_cap, 1)), bs(kFastBlock);
+    if (emit) {
+        if (energy) hipLaunchKernelGGL((k_fast_self<true, true>), gs, bs, 0, st, A);
+        else hipLaunchKernelGGL((k_fast_self<false, true>), gs, bs, 0, st, A);
+    } else {
+        if (energy) hipLaunchKernelGGL((k_fast_self<true, false>), gs, bs, 0, st, A);
+        else hipLaunchKernelGGL((k_fast_self<false, false>), gs, bs, 0, st, A);
+    }
+    hipLaunchKernelGGL(k_fast_nbr, dim3((unsigned)std::max<int64_t>(c->cap_cols, 1)), bs, 0, st,
+                       A);
+}
+
+}  // namespace md

@@ -29,11 +29,14 @@ constexpr int kForceBlockMax = 64 * kMaxGroup * kMaxWpc;
 // ------------------------------------------------------------------ repack (per step)
 
 // Gather positions and charges into slot order; reset the force work queue;
-// latch MD_FLAG_SKIN if the lists are stale.
+// latch MD_FLAG_SKIN if the lists are stale.  Fast atoms (moved more than skin/2
+// since the build) get NaN positions like padding slots: the list kernels skip
+// them and their pairs are evaluated by the fast-atom kernels.
 __global__ void __launch_bounds__(256) k_repack(const double* x, const double* y,
                                                 const double* z, const int8_t* q,
-                                                const int32_t* perm, double* xs, int8_t* qs,
-                                                int64_t cap_slots, DevScalars* dsc)
+                                                const int32_t* perm, const uint8_t* fast_flag,
+                                                double* xs, int8_t* qs, int64_t cap_slots,
+                                                DevScalars* dsc)
 {
     const int64_t n = dsc->n_slots;
     const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -43,7 +46,7 @@ __global__ void __launch_bounds__(256) k_repack(const double* x, const double* y
     }
     for (int64_t s = i0; s < n; s += (int64_t)gridDim.x * blockDim.x) {
         const int a = perm[s];
-        if (a >= 0) {
+        if (a >= 0 && !fast_flag[a]) {
             xs[s] = x[a];
             xs[cap_slots + s] = y[a];
             xs[2 * cap_slots + s] = z[a];
@@ -52,7 +55,7 @@ __global__ void __launch_bounds__(256) k_repack(const double* x, const double* y
             xs[s] = NAN;
             xs[cap_slots + s] = NAN;
             xs[2 * cap_slots + s] = NAN;
-            qs[s] = 0;
+            qs[s] = a >= 0 ? q[a] : 0;
         }
     }
 }
@@ -62,7 +65,7 @@ void launch_repack(Ctx* c, const double* x, const double* y, const double* z, co
 {
     const int nb = (int)std::min<int64_t>(div_up(c->cap_slots, 256), (int64_t)c->n_cu * 8);
     hipLaunchKernelGGL(k_repack, dim3(std::max(nb, 1)), dim3(256), 0, st, x, y, z, q, c->d_perm,
-                       c->d_xs, c->d_qs, c->cap_slots, c->dsc);
+                       c->d_fast_flag, c->d_xs, c->d_qs, c->cap_slots, c->dsc);
 }
 
 // ------------------------------------------------------------------ shared pieces
@@ -85,7 +88,7 @@ struct ForceArgs {
     const double* c12;
     int T;
     double rc2;                  // rc * rc (FP64, rounded once)
-    int E_cap, nb_Th;
+    int E_cap;
     int64_t cap_slots;
     double *fx, *fy, *fz;
     double* grp_epot;
@@ -104,18 +107,26 @@ struct ForceArgs {
 };
 
 // One block after every force launch: the per-system energy as the sum of the
-// group energies in a fixed order (deterministic), and the end of a pending list
-// rebuild.
+// group energies and of the fast atoms' pair energies in a fixed order
+// (deterministic), and the end of a pending list rebuild.
 __global__ void __launch_bounds__(256) k_force_finalize(const double* grp_epot, double* epot,
                                                         const int32_t* sys_grp0, int B,
-                                                        DevScalars* dsc)
+                                                        const int32_t* fast_list,
+                                                        const double* fast_e,
+                                                        const int64_t* sys_off, DevScalars* dsc)
 {
     __shared__ double s_red[4];
     if (epot) {
+        const int nf = dsc->n_fast;
         for (int b = 0; b < B; ++b) {
             const int g0 = sys_grp0[b], g1 = sys_grp0[b + 1];
             double t = 0.0;
             for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) t += grp_epot[g];
+            const int64_t a0 = sys_off[b], a1 = sys_off[b + 1];
+            for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+                const int f = fast_list[k];
+                if (f >= a0 && f < a1) t += fast_e[k];
+            }
             for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
             __syncthreads();
             if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;
@@ -202,50 +213,45 @@ __device__ inline double reduce8(double v)
 
 // Rebuild the half-list `half` of cluster I from the candidates staged in LDS
 // (during a rebuild their .w holds the type): the codes (staged index | type << 13)
-// of partners within rc + skin, compacted per atom in entry order; rows of 32
-// codes per atom padded with the sentinel.  s_mask[e] holds the clusters of the
-// group entry e can reach (low byte) and the cluster whose own unshifted entry it
-// is (high byte).  Returns the row count.
+// of partners within rc + skin, compacted per atom in entry order.  Each atom's
+// half-list is contiguous (nb_cap_h codes), padded with the sentinel to whole rows
+// of 32 codes.  s_mask[e] holds the clusters of the group entry e can reach (low
+// byte) and the cluster whose own unshifted entry it is (high byte).  Returns the
+// row count.
 __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int il, int k, int ai,
                                float xi, float yi, float zi, int nent, const float4* s_j,
                                const uint16_t* s_mask, int sentinel)
 {
     const int lane = threadIdx.x & 63;
-    int cnt = 0;
-    uint16_t* out = A.nb + ((int64_t)I * 2 + half) * A.nb_Th * 64;
+    uint16_t* out = A.nb + (((int64_t)I * 2 + half) * kCluster + il) * A.nb_cap_h;
     const bool live = ai >= 0;
+    const uint32_t below = (1u << k) - 1u;      // lanes of this atom before this one
+    const float thr2 = A.thr2;
+    const int cap = A.nb_cap_h;
+    int cnt = 0;
     for (int e = half; e < nent; e += 2) {
-        const uint32_t mk = s_mask[e];
+        const uint32_t mk = __builtin_amdgcn_readfirstlane(s_mask[e]);
         if (((mk >> cw) & 1u) == 0u) continue;          // out of this cluster's reach
         const int j = e * kCluster + k;
         const float4 pj = s_j[j];
         const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const bool self = ((mk >> (8 + cw)) & 1u) && (k == il);
-        const bool pass = live && (r2 < A.thr2) && !self;
+        const bool own = ((mk >> (8 + cw)) & 1u) != 0u;
+        const bool pass = live && (r2 < thr2) && !(own && k == il);
         const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
         const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
-        if (pass) {
-            const int pos = cnt + __popc(mine & ((1u << k) - 1u));
-            if (pos < A.nb_cap_h) {
-                const int t = pos >> 3;
-                out[((t >> 2) * 64 + il * 8 + (pos & 7)) * 4 + (t & 3)] =
-                    (uint16_t)(j | (__float_as_int(pj.w) << kCodeIdxBits));
-            }
-        }
+        const int pos = cnt + __popc(mine & below);
+        if (pass && pos < cap) out[pos] = (uint16_t)(j | (__float_as_int(pj.w) << kCodeIdxBits));
         cnt += __popc(mine);
     }
     int mx = cnt;
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
-    const int nrow = min((mx + 31) >> 5, A.nb_Th >> 2);
-    for (int pos = (cnt + 7 - k) / 8 * 8 + k; pos < nrow * 32; pos += 8) {
-        const int t = pos >> 3;
-        out[((t >> 2) * 64 + il * 8 + k) * 4 + (t & 3)] = (uint16_t)sentinel;
-    }
+    const int nrow = min((mx + 31) >> 5, cap >> 5);
+    for (int pos = cnt + k; pos < nrow * 32; pos += 8) out[pos] = (uint16_t)sentinel;
     if (lane == 0) {
         A.cl_nt[(int64_t)I * 2 + half] = nrow;
         A.cl_len[(int64_t)I * 2 + half] = mx;
-        if (mx > A.nb_cap_h) atomicOr(&A.dsc->flags, MD_FLAG_LIST_OVERFLOW);
+        if (mx > cap) atomicOr(&A.dsc->flags, MD_FLAG_LIST_OVERFLOW);
     }
     return nrow;
 }
@@ -366,7 +372,9 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         int tb = 0;
         if (act) {
             ai = A.perm[slot_i];
-            if (ai >= 0) {
+            // a fast atom (NaN position) takes no part, like padding: its pairs and
+            // its force come from the fast-atom kernels
+            if (ai >= 0 && A.xs[slot_i] == A.xs[slot_i]) {
                 const int32_t im = A.slot_img[slot_i];
                 float r[3];
                 for (int d = 0; d < 3; ++d) {
@@ -408,8 +416,10 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             // wave-uniform row count and list base (scalar loop control / addressing);
             // each lane reads its next 4 codes with one 8-byte load, two rows ahead
             nr = __builtin_amdgcn_readfirstlane(nr);
+            // lane (i, k) takes codes 4k .. 4k + 3 of every 32-code row of atom i
             const auto cp = gbl(reinterpret_cast<const uint64_t*>(
-                                A.nb + ((int64_t)I * 2 + half) * A.nb_Th * 64)) + lane;
+                                A.nb + (((int64_t)I * 2 + half) * kCluster + il) * A.nb_cap_h)) +
+                            k8;
             const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
             const GridSys* gsp = A.grid + gr.sys;
             float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
@@ -456,11 +466,11 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             };
             const uint64_t sent4 = 0x0001000100010001ull * (uint64_t)sentinel;
             uint64_t v0 = nr > 0 ? (uint64_t)cp[0] : sent4;
-            uint64_t v1 = nr > 1 ? (uint64_t)cp[64] : sent4;
+            uint64_t v1 = nr > 1 ? (uint64_t)cp[8] : sent4;
             for (int r = 0; r < nr; ++r) {
                 const uint64_t cur = v0;
                 v0 = v1;
-                if (r + 2 < nr) v1 = cp[(r + 2) * 64];
+                if (r + 2 < nr) v1 = cp[(r + 2) * 8];
                 const uint32_t lo = (uint32_t)cur, hi = (uint32_t)(cur >> 32);
                 pair(lo & 0xFFFFu);
                 pair(lo >> 16);
@@ -540,10 +550,12 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
             }
             const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
             double Fx = 0.0, Fy = 0.0, Fz = 0.0, eacc = 0.0;
+            const int k = lane & 7;
             for (int hh = 0; hh < 2; ++hh)
             for (int t = 0, nt = 4 * A.cl_nt[(int64_t)I * 2 + hh]; t < nt; ++t) {
-                const uint32_t code = gbl(A.nb + ((int64_t)I * 2 + hh) * A.nb_Th * 64)
-                                         [((t >> 2) * 64 + lane) * 4 + (t & 3)];
+                const uint32_t code =
+                    gbl(A.nb + (((int64_t)I * 2 + hh) * kCluster + il) * A.nb_cap_h)
+                        [(t >> 2) * 32 + k * 4 + (t & 3)];
                 const uint32_t idx = code & kCodeIdxMask;
                 if (idx == sentinel || ai < 0) continue;
                 const int64_t slot_j = slot_of_code(ent_g, idx);
@@ -658,7 +670,8 @@ static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks
         hipLaunchKernelGGL((k_force64<E, M, S>), dim3(blocks), dim3(64 * c->G), 0, st, A);
 }
 
-hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, double* fz,
+hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const double* y,
+                         const double* z, const int8_t* q, double* fx, double* fy, double* fz,
                          double* epot, int2* emit, int64_t emit_max, hipStream_t st,
                          hipEvent_t ev0, hipEvent_t ev1)
 {
@@ -668,7 +681,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, doub
     A.grid = c->d_grid; A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
     A.lj32 = c->d_lj32; A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T;
     A.rc2 = c->cfg.rc * c->cfg.rc;
-    A.E_cap = c->E_cap; A.nb_Th = c->nb_Th; A.cap_slots = c->cap_slots;
+    A.E_cap = c->E_cap; A.cap_slots = c->cap_slots;
     A.fx = fx; A.fy = fy; A.fz = fz;
     A.grp_epot = c->d_grp_epot; A.epot = epot; A.sys_grp0 = c->d_sys_grp0; A.B = c->B;
     A.dsc = c->dsc; A.emit = emit; A.emit_max = emit_max;
@@ -711,8 +724,9 @@ hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, doub
         const hipError_t e = hipEventRecord(ev1, st);
         if (e != hipSuccess) return e;
     }
+    if (c->fast_cap > 0) launch_fast(c, x, y, z, q, fx, fy, fz, E, emit, emit_max, st);
     hipLaunchKernelGGL(k_force_finalize, dim3(1), dim3(256), 0, st, c->d_grp_epot, epot,
-                       c->d_sys_grp0, c->B, c->dsc);
+                       c->d_sys_grp0, c->B, c->d_fast_list, c->d_fast_e, c->d_sys_off, c->dsc);
     return hipGetLastError();
 }
 

@@ -62,6 +62,8 @@ struct DevScalars {
     int64_t n_builds;
     uint32_t work_force;        // work-queue counter of the force kernel
     unsigned long long pair_count;  // debug pair export counter
+    int32_t n_fast;             // atoms beyond skin/2 of their build position (<= capacity)
+    int32_t n_fast_raw;         // the same, uncapped (above the capacity a rebuild is due)
 };
 
 struct Ctx {
@@ -88,8 +90,7 @@ struct Ctx {
     int32_t G = 4;                 // i-clusters per group
     int32_t E_cap = 0;             // entries per group
     int32_t nb_cap = 0;            // per-atom list capacity (both halves)
-    int32_t nb_cap_h = 0;          // per-atom capacity of one half-list (multiple of 8)
-    int32_t nb_Th = 0;             // nb_cap_h / 8
+    int32_t nb_cap_h = 0;          // per-atom capacity of one half-list (multiple of 32)
     double rlist = 0.0;            // rc + skin
 
     // capacities
@@ -136,11 +137,19 @@ struct Ctx {
     Group* d_groups = nullptr;     // cap_groups
     uint32_t* d_ent = nullptr;     // cap_groups * E_cap
     uint8_t* d_ent_mask = nullptr; // cap_groups * E_cap: group clusters each entry can reach
-    uint16_t* d_nb = nullptr;      // cap_clusters * 2 * nb_Th * 64
+    uint16_t* d_nb = nullptr;      // cap_clusters * 2 * 8 * nb_cap_h: (cluster, half, atom) lists
     double* d_grp_epot = nullptr;  // cap_groups
     // integrator
     double* d_xref = nullptr;      // N*3 build positions
     double* d_partial = nullptr;   // cap_partials (kinetic-energy block partials)
+    // atoms that moved more than skin/2 since the last build
+    int32_t fast_cap = 0;
+    uint8_t* d_fast_flag = nullptr;   // N
+    int32_t* d_fast_loc = nullptr;    // vv blocks * block size: per-block lists
+    int32_t* d_fast_cnt = nullptr;    // vv blocks
+    int32_t* d_fast_list = nullptr;   // fast_cap, ascending atom index
+    double* d_fast_e = nullptr;       // fast_cap: energy of each fast atom's pairs
+    uint8_t* d_atype = nullptr;       // N: types in caller order (build time)
 };
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }

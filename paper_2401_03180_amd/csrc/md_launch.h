@@ -30,10 +30,16 @@ void launch_repack(Ctx* c, const double* x, const double* y, const double* z, co
                    hipStream_t st);
 // ev0 / ev1 (optional) are recorded on st immediately before / after the main force
 // kernel, so their interval times that kernel alone
-hipError_t launch_forces(Ctx* c, md_precision prec, double* fx, double* fy, double* fz,
+hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const double* y,
+                         const double* z, const int8_t* q, double* fx, double* fy, double* fz,
                          double* epot, int2* emit, int64_t emit_max, hipStream_t st,
                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t force32_lds_bytes(int E_cap);
+
+// md_fast.hip
+void launch_fast(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
+                 double* fx, double* fy, double* fz, bool energy, int2* emit, int64_t emit_max,
+                 hipStream_t st);
 hipError_t force_kernel_setup(Ctx* c);
 
 }  // namespace md

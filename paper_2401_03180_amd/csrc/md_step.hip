@@ -205,6 +205,11 @@ struct VvArgs {
     const int32_t* sys_of_atom;
     int B;
     DevScalars* dsc;
+    uint8_t* fast_flag;          // N
+    int32_t* fast_loc;           // nblocks * kVvBlock
+    int32_t* fast_cnt;           // nblocks
+    int32_t* fast_list;          // fast_cap
+    int fast_cap;
 };
 
 __device__ double block_sum_d(double v, double* s)
@@ -240,6 +245,7 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A)
             A.x[a] = x; A.y[a] = y; A.z[a] = z;
             const double ex = x - A.xref[a], ey = y - A.xref[A.N + a], ez = z - A.xref[2 * A.N + a];
             d2 = ex * ex + ey * ey + ez * ez;
+            A.fast_flag[a] = d2 > A.thr2 ? 1 : 0;
         } else if (EKIN) {
             double v2 = vx * vx + vy * vy;
             v2 = v2 + vz * vz;
@@ -247,14 +253,25 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A)
         }
     }
     if (PHASE == 0) {
-        // block maximum of the squared displacement since the last build
+        // this block's fast atoms in atom order, and the block maximum of the squared
+        // displacement since the last build
+        __shared__ int s_n[kVvBlock / 64];
+        const bool fast = a < A.N && d2 > A.thr2;
+        const unsigned long long bal = __ballot(fast);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (lane == 0) s_n[wv] = __popcll(bal);
         for (int off = 32; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, 64));
-        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = d2;
+        if (lane == 0) s_red[wv] = d2;
         __syncthreads();
+        int pos = __popcll(bal & ((1ull << lane) - 1ull));
+        for (int k = 0; k < wv; ++k) pos += s_n[k];
+        if (fast) A.fast_loc[(int64_t)blockIdx.x * kVvBlock + pos] = (int32_t)a;
         if (threadIdx.x == 0) {
             double m = s_red[0];
-            for (int k = 1; k < kVvBlock / 64; ++k) m = fmax(m, s_red[k]);
+            int n = s_n[0];
+            for (int k = 1; k < kVvBlock / 64; ++k) { m = fmax(m, s_red[k]); n += s_n[k]; }
             A.disp_partial[blockIdx.x] = m;
+            A.fast_cnt[blockIdx.x] = n;
         }
     }
     if (PHASE == 1 && EKIN) {
@@ -278,17 +295,39 @@ __global__ void __launch_bounds__(kVvBlock) k_vv_finalize(VvArgs A, int nblocks)
 {
     __shared__ double s_red[kVvBlock / 64];
     if (PHASE == 0) {
+        // fast list: the blocks' lists concatenated in block order (ascending atom
+        // index), up to the capacity; a rebuild is due when more atoms are fast
+        __shared__ int s_sum[kVvBlock];
+        const int chunk = (nblocks + kVvBlock - 1) / kVvBlock;
+        const int k0 = threadIdx.x * chunk, k1 = min(nblocks, k0 + chunk);
         double m = 0.0;
-        for (int k = threadIdx.x; k < nblocks; k += kVvBlock) m = fmax(m, A.disp_partial[k]);
+        int n = 0;
+        for (int k = k0; k < k1; ++k) {
+            m = fmax(m, A.disp_partial[k]);
+            n += A.fast_cnt[k];
+        }
+        s_sum[threadIdx.x] = n;
         for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
         if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
         __syncthreads();
+        int off = 0, total = 0;
+        for (int t = 0; t < kVvBlock; ++t) {
+            if (t < (int)threadIdx.x) off += s_sum[t];
+            total += s_sum[t];
+        }
+        for (int k = k0; k < k1 && off < A.fast_cap; ++k) {
+            const int cnt = A.fast_cnt[k];
+            for (int i = 0; i < cnt && off < A.fast_cap; ++i, ++off)
+                A.fast_list[off] = A.fast_loc[(int64_t)k * kVvBlock + i];
+        }
         if (threadIdx.x == 0) {
             for (int k = 1; k < kVvBlock / 64; ++k) m = fmax(m, s_red[k]);
             m = fmax(m, s_red[0]);
             const double prev = __longlong_as_double((long long)A.dsc->disp2_bits);
             A.dsc->disp2_bits = (unsigned long long)__double_as_longlong(fmax(prev, m));
-            if (m > A.thr2) A.dsc->need_rebuild = 1;
+            A.dsc->n_fast_raw = total;
+            A.dsc->n_fast = min(total, A.fast_cap);
+            if (total > A.fast_cap) A.dsc->need_rebuild = 1;
             A.dsc->step += 1;
         }
         return;
@@ -319,6 +358,8 @@ void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const doubl
     const int nb = (int)div_up(c->N, kVvBlock);
     A.disp_partial = c->d_partial + nb + c->B + 1;
     A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
+    A.fast_flag = c->d_fast_flag; A.fast_loc = c->d_fast_loc; A.fast_cnt = c->d_fast_cnt;
+    A.fast_list = c->d_fast_list; A.fast_cap = c->fast_cap;
     if (phase == 0) {
         if (nb > 0) hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A);
         hipLaunchKernelGGL((k_vv_finalize<0>), dim3(1), dim3(kVvBlock), 0, st, A, nb);

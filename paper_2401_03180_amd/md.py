@@ -39,7 +39,8 @@ class md_config(ctypes.Structure):
                 ("periodic", ctypes.c_int32), ("screen_lj", ctypes.c_int32),
                 ("rc", ctypes.c_double), ("skin", ctypes.c_double),
                 ("capacity_atoms", ctypes.c_int64), ("cluster_group", ctypes.c_int32),
-                ("max_neighbors", ctypes.c_int32), ("density_hint", ctypes.c_double)]
+                ("max_neighbors", ctypes.c_int32), ("density_hint", ctypes.c_double),
+                ("fast_capacity", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class md_stats(ctypes.Structure):
@@ -48,6 +49,7 @@ class md_stats(ctypes.Structure):
                 ("n_list_codes", ctypes.c_int64), ("max_list_len", ctypes.c_int64),
                 ("list_capacity", ctypes.c_int64), ("max_group_entries", ctypes.c_int64),
                 ("group_entry_capacity", ctypes.c_int64), ("n_builds", ctypes.c_int64),
+                ("n_fast", ctypes.c_int64), ("n_fast_raw", ctypes.c_int64),
                 ("cluster_group", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
     def as_dict(self):
@@ -268,7 +270,7 @@ class Engine:
     """
 
     def __init__(self, sys, precision=MD_FP32_KAHAN, cluster_group=0, skin=None,
-                 density_hint=0.0, max_neighbors=0, device="cuda"):
+                 density_hint=0.0, max_neighbors=0, fast_capacity=0, device="cuda"):
         import torch
         self.torch = torch
         self.sys = sys
@@ -300,6 +302,7 @@ class Engine:
         cfg.cluster_group = cluster_group
         cfg.max_neighbors = max_neighbors
         cfg.density_hint = density_hint
+        cfg.fast_capacity = fast_capacity
         self.cfg = cfg
         self.ctx = md_create(cfg, sys.sys_offsets)
         md_bind_tables(self.ctx, sys.box, sys.c6, sys.c12, sys.qmax, sys.lambda_d, sys.base,

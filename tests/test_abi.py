@@ -53,9 +53,9 @@ def test_rates_helper_matches_oracle():
 
 
 def test_struct_layout_matches_header():
-    # md_config: 6 int32, 2 double, int64, 2 int32, double
-    assert ctypes.sizeof(md.md_config) == 6 * 4 + 2 * 8 + 8 + 2 * 4 + 8
-    assert ctypes.sizeof(md.md_stats) == 10 * 8 + 2 * 4
+    # md_config: 6 int32, 2 double, int64, 2 int32, double, 2 int32
+    assert ctypes.sizeof(md.md_config) == 6 * 4 + 2 * 8 + 8 + 2 * 4 + 8 + 2 * 4
+    assert ctypes.sizeof(md.md_stats) == 12 * 8 + 2 * 4
 
 
 def test_create_validates_arguments_without_gpu():

@@ -392,7 +392,8 @@ def test_device_flags_are_reported():
     import torch
     from paper_2401_03180_amd import md
     s = _tiny_system(64, True)
-    eng = make_engine(s, 1)
+    # no fast-atom capacity: one atom beyond skin/2 already makes a rebuild due
+    eng = make_engine(s, 1, fast_capacity=-1)
     eng.build()
     # step counter beyond the bound tables
     say("flag: step")
@@ -436,3 +437,96 @@ def test_device_flags_are_reported():
         e2.forces()
         assert e2.sync_check(raise_on_flags=False) & md.MD_FLAG_LIST_OVERFLOW
         e2.close()
+
+
+# ------------------------------------------------------------------ fast atoms
+
+def _fast_case(periodic, n_fast, seed):
+    """A system, per-atom displacements (most below skin/2 = 0.05 nm, `n_fast` of them
+    beyond it, among them both atoms of some bonded pairs) and charges."""
+    rng = np.random.default_rng(seed)
+    if periodic:
+        s = synth.water_small(n_steps=5)
+    else:
+        s = synth.methane_clusters(n_clusters=3, lo=300, hi=2000, n_steps=5)
+    s.q = random_charges(s, seed)
+    n = s.n_atoms
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    disp = u * rng.uniform(0.0, 0.045, n)[:, None]
+    half = n_fast // 2
+    lead = rng.choice(n - 1, half, replace=False)
+    fast = np.unique(np.concatenate([lead, lead + 1]))[:n_fast]
+    disp[fast] = u[fast] * rng.uniform(0.06, 0.3, fast.size)[:, None]
+    return s, disp, fast
+
+
+def _displace(eng, s, disp):
+    """Move every atom by `disp` through phase 0 of velocity Verlet with zero force,
+    which also flags the atoms beyond skin/2 of the build positions."""
+    import torch
+    for c, name in enumerate(("vx", "vy", "vz")):
+        getattr(eng, name).copy_(torch.as_tensor(disp[:, c] / s.dt))
+    for name in ("fx", "fy", "fz"):
+        getattr(eng, name).zero_()
+    eng.vv(0, ekin=False)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("periodic", [True, False])
+def test_fast_atoms_exact_without_rebuild(prec, periodic):
+    """Atoms beyond skin/2 of their build positions (no rebuild): the fast-atom
+    kernels supply their pairs; pair set, forces and energies match the oracle at the
+    new positions."""
+    from paper_2401_03180_amd import md
+    s, disp, fast = _fast_case(periodic, 24, 21 + periodic)
+    say("fast atoms", "periodic" if periodic else "vacuum", "prec", prec)
+    eng = make_engine(s, prec, fast_capacity=64, density_hint=0.0 if periodic else 100.0)
+    set_q(eng, s.q)
+    eng.set_step(0)
+    eng.build()
+    _displace(eng, s, disp)
+    eng.build(md.MD_BUILD_AUTO)
+    st = eng.stats()
+    assert st["n_builds"] == 1 and st["n_fast"] == fast.size and st["n_fast_raw"] == fast.size
+    F, epot = gpu_forces(eng, prec)
+    x, y, z = eng.host("x"), eng.host("y"), eng.host("z")
+    ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 1), x=x, y=y, z=z)
+    assert force_error(F, ref) <= TOL[prec]
+    for b in range(s.n_systems):
+        a0, a1 = s.sys_offsets[b], s.sys_offsets[b + 1]
+        esc = 2 * np.abs(ref["e_atom"][a0:a1]).sum()
+        assert abs(epot[b] - ref["epot"][b]) <= TOL[prec] * esc
+    gp = sorted_pairs(eng.debug_pairs(prec=prec))
+    assert np.array_equal(gp, oracle.pairs(s, x=x, y=y, z=z))
+    assert eng.stats()["flags"] == 0
+    eng.close()
+
+
+def test_fast_capacity_overflow_rebuilds():
+    """More fast atoms than the capacity: the device requests a rebuild, MD_BUILD_AUTO
+    performs it, and the forces are exact again; MD_BUILD_CHECK instead latches
+    MD_FLAG_SKIN."""
+    from paper_2401_03180_amd import md
+    s, disp, fast = _fast_case(True, 24, 5)
+    for mode in (md.MD_BUILD_AUTO, md.MD_BUILD_CHECK):
+        say("fast capacity overflow, build mode", mode)
+        eng = make_engine(s, 1, fast_capacity=4)
+        set_q(eng, s.q)
+        eng.set_step(0)
+        eng.build()
+        _displace(eng, s, disp)
+        st = eng.stats()
+        assert st["n_fast_raw"] == fast.size and st["n_fast"] == 4
+        eng.build(mode)
+        eng.forces()
+        flags = eng.sync_check(raise_on_flags=False)
+        if mode == md.MD_BUILD_AUTO:
+            assert flags == 0 and eng.stats()["n_builds"] == 2
+            F = (eng.host("fx"), eng.host("fy"), eng.host("fz"))
+            ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 1), x=eng.host("x"),
+                                y=eng.host("y"), z=eng.host("z"))
+            assert force_error(F, ref) <= TOL[1]
+        else:
+            assert flags & md.MD_FLAG_SKIN and eng.stats()["n_builds"] == 1
+        eng.close()
