@@ -52,7 +52,8 @@ def make_system(name, n_steps):
 STATE = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q")
 
 
-def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_graph=True):
+def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_graph=True,
+            fast_capacity=0):
     """Timed region: `steps` replays of the captured step graph (or, with use_graph
     False, `steps` eager md_step calls), inputs resident.
     Then the same steps are replayed eagerly from a snapshot of the state at the
@@ -63,7 +64,8 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
     of the replay (where no list rebuild is pending)."""
     import torch
     from paper_2401_03180_amd import md
-    eng = md.Engine(sys_, prec, cluster_group=cluster_group, skin=skin)
+    eng = md.Engine(sys_, prec, cluster_group=cluster_group, skin=skin,
+                    fast_capacity=fast_capacity)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         eng.set_step(0, stream)
@@ -129,6 +131,43 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
             "builds": builds, "builds_replay": builds_replay,
             "replay_identical": bool(same and builds == builds_replay), "stats": st1,
             "step": step_end}
+
+
+def run_gpu_per_system(sys_, prec, steps, warmup):
+    """The plain form for batched workloads: every system in a context of its own,
+    its step replayed as its own graph, systems one after another on one stream."""
+    import torch
+    from paper_2401_03180_amd import md
+    engines, graphs = [], []
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for b in range(sys_.n_systems):
+            sb = sys_.subsystem(b)
+            e = md.Engine(sb, prec)
+            e.set_step(0, stream)
+            e.build(md.MD_BUILD_FORCE, stream)
+            e.forces(energy=True, stream=stream)
+            engines.append(e)
+            graphs.append(e.graph(md.MD_BUILD_AUTO, stream, energy=True, ekin=True))
+        for _ in range(warmup):
+            for g in graphs:
+                md.md_graph_launch(g, stream)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            for g in graphs:
+                md.md_graph_launch(g, stream)
+        ev1.record(stream)
+        stream.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        flags = 0
+        for e in engines:
+            flags |= e.sync_check(stream, raise_on_flags=False)
+    for e in engines:
+        e.close()
+    return {"ms": ms, "flags": flags}
 
 
 def cpu_baseline(sys_, target_s=12.0, threads=None):
@@ -217,6 +256,11 @@ def main():
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--fast-capacity", type=int, default=None)
+    ap.add_argument("--tune", action="store_true",
+                    help="search cluster group, skin and fast-atom capacity first and cache "
+                         "the best (paper_2401_03180_amd/tuned.json)")
+    ap.add_argument("--no-tuned", action="store_true", help="ignore the cached configuration")
     ap.add_argument("--eager", action="store_true",
                     help="launch the step kernels one by one instead of replaying a graph")
     ap.add_argument("--calib-copy", action="store_true",
@@ -243,10 +287,31 @@ def main():
         del src, dst
 
     S = a.warmup + a.steps
+    from paper_2401_03180_amd import autotune
+
+    def knobs(prec):
+        """Launch configuration: command line, else the cached tuning, else defaults."""
+        if a.tune:
+            autotune.tune(a.config, lambda: make_system(a.config, S), prec, a.steps, a.warmup,
+                          log=log)
+        t = None if a.no_tuned else autotune.load(a.config, prec)
+        k = {"cluster_group": 0, "skin": None, "fast_capacity": 0, "tuned": t is not None}
+        if t is not None:
+            k.update(cluster_group=t["cluster_group"], skin=t["skin"],
+                     fast_capacity=t["fast_capacity"])
+        if a.cluster_group:
+            k["cluster_group"] = a.cluster_group
+        if a.skin is not None:
+            k["skin"] = a.skin
+        if a.fast_capacity is not None:
+            k["fast_capacity"] = a.fast_capacity
+        return k
+
     sys32 = make_system(a.config, S)
-    log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup)
-    r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, a.cluster_group, a.skin,
-                  use_graph=not a.eager)
+    k32 = knobs(md.MD_FP32_KAHAN)
+    log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
+    r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
+                  use_graph=not a.eager, fast_capacity=k32["fast_capacity"])
     log("fp32", {k: v for k, v in r32.items() if k != "stats"})
     n = sys32.n_atoms
     value = n * a.steps / (r32["ms"] * 1e-3)
@@ -264,14 +329,25 @@ def main():
              "list_capacity": r32["stats"]["list_capacity"]}
     if not a.no_fp64:
         sys64 = make_system(a.config, S)
-        r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, a.cluster_group, a.skin,
-                      use_graph=not a.eager)
-        log("fp64", {k: v for k, v in r64.items() if k != "stats"})
-        v64 = n * a.steps / (r64["ms"] * 1e-3)
-        extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
-                      "fp32_vs_fp64_speedup": value / v64,
-                      "fp64_force_kernel_ms": r64["kernel_ms"], "fp64_flags": r64["flags"],
-                      "fp64_replay_identical": r64["replay_identical"]})
+        if sys64.n_systems > 1:
+            # batched workloads: the plain FP64 form runs one system per context and launch
+            r64 = run_gpu_per_system(sys64, md.MD_FP64, a.steps, a.warmup)
+            v64 = n * a.steps / (r64["ms"] * 1e-3)
+            extra.update({"fp64_per_system_value": v64,
+                          "fp64_per_system_ms_per_step": r64["ms"] / a.steps,
+                          "batched_fp32_vs_per_system_fp64_speedup": value / v64,
+                          "fp64_flags": r64["flags"]})
+            log("fp64 per system", r64)
+        else:
+            k64 = knobs(md.MD_FP64)
+            r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, k64["cluster_group"], k64["skin"],
+                          use_graph=not a.eager, fast_capacity=k64["fast_capacity"])
+            log("fp64", {k: v for k, v in r64.items() if k != "stats"})
+            v64 = n * a.steps / (r64["ms"] * 1e-3)
+            extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
+                          "fp32_vs_fp64_speedup": value / v64,
+                          "fp64_force_kernel_ms": r64["kernel_ms"], "fp64_flags": r64["flags"],
+                          "fp64_replay_identical": r64["replay_identical"], "fp64_launch": k64})
 
     kernel_ms = r32["kernel_ms"]
     achieved = FLOP_PER_PAIR * r32["pairs"] / (kernel_ms * 1e-3) / 1e12
@@ -288,7 +364,10 @@ def main():
            "data": "synthetic",
            "config": {"workload": a.config, "atoms": n, "precision": "fp32 forces + kahan, "
                       "fp64 positions/integration/energies", "rc_nm": sys32.rc,
-                      "skin_nm": a.skin if a.skin is not None else sys32.skin,
+                      "skin_nm": k32["skin"] if k32["skin"] is not None else sys32.skin,
+                      "cluster_group": r32["stats"]["cluster_group"],
+                      "fast_capacity": k32["fast_capacity"], "tuned": k32["tuned"],
+                      "systems": sys32.n_systems,
                       "launch": "eager" if a.eager else "graph", "parallelism": "single-gpu"},
            "roofline": roofline, "extra": extra}
     if not a.no_cpu:

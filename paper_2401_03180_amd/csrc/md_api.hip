@@ -238,7 +238,10 @@ static md_status size_and_allocate(Ctx* c)
         const double X = 2.0 * a, Y = 2.0 * a, Z = (G + 1) * a;
         const double V = X * Y * Z + 2.0 * rl * (X * Y + X * Z + Y * Z) +
                          M_PI * rl * rl * (X + Y + Z) + 4.0 / 3.0 * M_PI * rl * rl * rl;
-        const int est = (int)(V * rho / kCluster * 1.35) + 16;
+        // vacuum grids follow each system's bounding box, whose columns widen as a
+        // cluster expands (ions leaving it stretch the box): more headroom there
+        const double safety = cfg.periodic ? 1.35 : 2.4;
+        const int est = (int)(V * rho / kCluster * safety) + 16;
         E_cap = std::min(est, kMaxGroupEntries);
         while (E_cap > 32 && force32_lds_bytes(E_cap) + 8192 > c->max_lds)
             E_cap -= 8;

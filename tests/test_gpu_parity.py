@@ -268,13 +268,7 @@ def test_vacuum_batched_clusters(prec):
     # every system alone gives the same pair set and forces within tolerance
     for b in (0, 3):
         a0, a1 = int(s.sys_offsets[b]), int(s.sys_offsets[b + 1])
-        sb = s.copy()
-        for name in ("x", "y", "z", "vx", "vy", "vz", "elem", "type", "atom_id", "inv_mass", "q"):
-            setattr(sb, name, getattr(s, name)[a0:a1].copy())
-        sb.sys_offsets = np.array([0, a1 - a0], np.int64)
-        sb.lambda_d = s.lambda_d[b:b + 1].copy()
-        sb.g = s.g[b:b + 1].copy()
-        sb.seeds = s.seeds[b:b + 1].copy()
+        sb = s.subsystem(b)
         say("methane single system", b, "prec", prec)
         e1 = make_engine(sb, prec, density_hint=100.0)
         set_q(e1, sb.q)
@@ -530,3 +524,65 @@ def test_fast_capacity_overflow_rebuilds():
         else:
             assert flags & md.MD_FLAG_SKIN and eng.stats()["n_builds"] == 1
         eng.close()
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def _graph_steps_then_sample(s, prec, steps, n_rows, seed, **kw):
+    """Run `steps` graph replays of the full step (automatic rebuilds, fast atoms),
+    then compare the forces of `n_rows` sampled atoms with the oracle's all-pairs rows
+    at the positions and charges the GPU reached."""
+    import torch
+    from paper_2401_03180_amd import md
+    eng = make_engine(s, prec, **kw)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        eng.set_step(0, st)
+        eng.build(md.MD_BUILD_FORCE, st)
+        eng.forces(energy=True, stream=st)
+        g = eng.graph(md.MD_BUILD_AUTO, st, energy=True, ekin=True)
+        for _ in range(steps):
+            md.md_graph_launch(g, st)
+        st.synchronize()
+    assert eng.sync_check(raise_on_flags=False) == 0
+    assert eng.get_step() == steps
+    F = (eng.host("fx"), eng.host("fy"), eng.host("fz"))
+    x, y, z, q = eng.host("x"), eng.host("y"), eng.host("z"), eng.host("q")
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(s.n_atoms, n_rows, replace=False))
+    ref = oracle.forces_rows(s, rows, q=q, x=x, y=y, z=z, kappa=oracle_kappa(s, steps))
+    assert force_error(tuple(f[rows] for f in F), ref) <= TOL[prec]
+    stats = eng.stats()
+    eng.close()
+    return stats
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_protein_crystal_full_size_sampled(prec):
+    """524,288-atom protein-crystal-like box (rc 1.2 nm, charges up to Z): sampled
+    forces after graph-replayed steps."""
+    s = synth.protein_crystal(n_steps=6)
+    s.base[:] = np.where(s.base > 0, 0.05, 0.0)      # charges on many atoms within 6 steps
+    say("protein_524288 sampled rows prec", prec)
+    st = _graph_steps_then_sample(s, prec, 6, 300, 31)
+    assert st["n_atoms"] == 524288
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_methane_batched_full_size_sampled(prec):
+    """256 vacuum methane clusters (1.73 M atoms) in one batched context: sampled forces
+    after graph-replayed steps with per-cluster pulses."""
+    s = synth.methane_clusters(n_steps=2000)
+    s.base[:] = np.where(s.base > 0, 1.0, 0.0)
+    say("methane_256 sampled rows prec", prec)
+    st = _graph_steps_then_sample(s, prec, 700, 400, 41, density_hint=100.0)
+    assert st["n_atoms"] == s.n_atoms
+
+
+def test_water_large_full_size_sampled():
+    """4,194,304-atom water box: sampled FP32 forces after graph-replayed steps."""
+    s = synth.water_large(n_steps=4)
+    s.base[:] = np.where(s.base > 0, 0.05, 0.0)
+    say("water_4194304 sampled rows")
+    st = _graph_steps_then_sample(s, 1, 4, 200, 51)
+    assert st["n_atoms"] == 4194304

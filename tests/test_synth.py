@@ -45,6 +45,9 @@ def test_methane_clusters():
     assert len(set(s.seeds.tolist())) == 256
     # per-system atom ids restart at zero
     assert s.atom_id[s.sys_offsets[1]] == 0
+    # Lennard-Jones between C atoms only (no bonded terms or exclusions on this path)
+    assert s.c6[0, 0] > 0 and s.c12[0, 0] > 0
+    assert not s.c6[1].any() and not s.c12[1].any() and not s.c6[:, 1].any()
 
 
 def test_water_large_counts():
@@ -52,3 +55,13 @@ def test_water_large_counts():
     assert s.n_atoms % 3 == 1
     full = synth.water_large()
     assert full.n_atoms == 4194304
+
+
+def test_subsystem_is_the_system_alone():
+    s = synth.methane_clusters(n_clusters=4, lo=100, hi=400, n_steps=3)
+    b = 2
+    sb = s.subsystem(b)
+    a0, a1 = s.sys_offsets[b], s.sys_offsets[b + 1]
+    assert sb.n_systems == 1 and sb.n_atoms == a1 - a0
+    assert np.array_equal(sb.x, s.x[a0:a1]) and np.array_equal(sb.atom_id, s.atom_id[a0:a1])
+    assert np.array_equal(sb.g[0], s.g[b]) and sb.seeds[0] == s.seeds[b]
