@@ -71,6 +71,8 @@ typedef enum md_precision {
 #define MD_FLAG_STEP 0x10u           /* step counter outside the bound schedule tables */
 #define MD_FLAG_BAD_INPUT 0x20u      /* a type, element or charge outside its table (the entry
                                         was clamped or skipped) */
+#define MD_FLAG_BARRIER 0x40u        /* a grid-wide wait of the fused step kernel timed out: the
+                                        step's results are invalid (md_clear_flags resets it) */
 
 #define MD_MAX_TYPES 8
 #define MD_MAX_ELEMENTS 8

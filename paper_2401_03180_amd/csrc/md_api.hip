@@ -56,7 +56,7 @@ void free_all(Ctx* c)
                     c->d_cl_nt, c->d_cl_len, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_qs,
                     c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
                     c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
-                    c->d_fast_list, c->d_fast_e, c->d_atype};
+                    c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -305,6 +305,8 @@ static md_status size_and_allocate(Ctx* c)
         HIP_TRY(c, dalloc(&c->d_fast_list, std::max(c->fast_cap, 1)));
         HIP_TRY(c, dalloc(&c->d_fast_e, std::max(c->fast_cap, 1)));
         HIP_TRY(c, dalloc(&c->d_atype, std::max<int64_t>(N, 1)));
+        c->cap_bar = 8 * std::max(c->n_cu, 1);
+        HIP_TRY(c, dalloc(&c->d_bar_arrive, c->cap_bar));
     }
 
     // initial contents
@@ -334,8 +336,10 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, hipMemset(c->d_grp_epot, 0, sizeof(double) * c->cap_groups));
     HIP_TRY(c, hipMemset(c->d_fast_flag, 0, std::max<int64_t>(N, 1)));
     HIP_TRY(c, hipMemset(c->d_atype, 0, std::max<int64_t>(N, 1)));
+    HIP_TRY(c, hipMemset(c->d_bar_arrive, 0, sizeof(uint32_t) * c->cap_bar));
     HIP_TRY(c, hipMemset(c->d_fast_cnt, 0, sizeof(int32_t) * div_up(std::max<int64_t>(N, 1), 256)));
     HIP_TRY(c, force_kernel_setup(c));
+    HIP_TRY(c, build_step_setup(c));
     return MD_OK;
 }
 
@@ -695,6 +699,29 @@ extern "C" {
 
 static md_status step_impl(md_ctx* ctx, const md_step_args* a, int32_t build_mode, md_stream st)
 {
+    Ctx* c = &ctx->c;
+    const bool fused = (build_mode == MD_BUILD_AUTO || build_mode == MD_BUILD_FORCE) &&
+                       c->bs_blocks > 0 && c->tables_bound && c->built && c->N > 0;
+    if (fused) {
+        // the same sequence in four launches: phase 0 + ionization; fast-list join,
+        // step counter, rebuild when due and slot repack; forces; phase 1
+        if (!(a->dt > 0.0) || !isfinite(a->dt)) return fail(c, MD_ERR_ARG, "dt must be > 0");
+        if (null_any({a->x, a->y, a->z, a->vx, a->vy, a->vz, a->fx, a->fy, a->fz, a->inv_mass,
+                      a->elem, a->type, a->atom_id, a->q}))
+            return fail(c, MD_ERR_ARG, "NULL array");
+        if (a->prec != MD_FP64 && a->prec != MD_FP32_KAHAN)
+            return fail(c, MD_ERR_ARG, "unknown precision");
+        hipStream_t hs = S(st);
+        launch_vv0_ionize(c, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y, a->z, a->vx,
+                          a->vy, a->vz, a->elem, a->atom_id, a->q, hs);
+        launch_build_step(c, a->x, a->y, a->z, a->type, a->q, build_mode == MD_BUILD_FORCE, hs);
+        hipEvent_t e0, e1;
+        next_timer_events(c, hs, &e0, &e1);
+        HIP_TRY(c, launch_forces(c, a->prec, a->x, a->y, a->z, a->q, a->fx, a->fy, a->fz,
+                                 a->epot, nullptr, 0, hs, e0, e1));
+        return md_integrate_vv(ctx, 1, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y, a->z,
+                               a->vx, a->vy, a->vz, a->ekin, st);
+    }
     md_status s = md_integrate_vv(ctx, 0, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y,
                                   a->z, a->vx, a->vy, a->vz, nullptr, st);
     if (s == MD_OK) s = md_ionize_step(ctx, a->elem, a->atom_id, a->q, st);

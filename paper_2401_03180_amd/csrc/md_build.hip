@@ -14,6 +14,7 @@
 //      candidate atoms within rc + skin (entry * 8 + lane | type << 13).
 // The lists stay valid while no atom moves more than skin/2 from its build
 // position.
+#include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
 
@@ -43,15 +44,20 @@ __device__ inline int upper_index(const int32_t* arr, int n, int v)
 
 // End of a candidate-table build: the per-atom lists are now pending (the next
 // force evaluation rebuilds them), the displacement reference is the new one.
-__global__ void k_build_done(DevScalars* d, const int32_t* gate)
+__device__ inline void ph_build_done(DevScalars* d)
 {
-    if (gate && *gate == 0) return;
     d->need_rebuild = 0;
     d->lists_pending = 1;
     d->disp2_bits = 0ull;
     d->n_fast = 0;
     d->n_fast_raw = 0;
     d->n_builds += 1;
+}
+
+__global__ void k_build_done(DevScalars* d, const int32_t* gate)
+{
+    if (gate && *gate == 0) return;
+    ph_build_done(d);
 }
 
 // Every build kernel takes `gate`: NULL runs it unconditionally (forced build);
@@ -63,14 +69,13 @@ __device__ inline int col_grp0(const int64_t* pre, int c) { return (int)(pre[c] 
 
 // ---------------------------------------------------------------- vacuum grids
 
-__global__ void __launch_bounds__(256) k_sys_bbox(const double* x, const double* y,
-                                                  const double* z, const int64_t* sys_off,
-                                                  double* lo, double* hi, DevScalars* dsc,
-                                                  const int32_t* gate)
+// Bounding box of every vacuum system b = bid, bid + nblk, ... (one block each, 256 threads).
+__device__ void ph_sys_bbox(const double* x, const double* y, const double* z,
+                            const int64_t* sys_off, int B, double* lo, double* hi,
+                            DevScalars* dsc, int bid, int nblk)
 {
-    if (gated_off(gate)) return;
     __shared__ double s_v[6][4];
-    const int b = blockIdx.x;
+    for (int b = bid; b < B; b += nblk) {
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
     for (int64_t a = sys_off[b] + threadIdx.x; a < sys_off[b + 1]; a += blockDim.x) {
@@ -103,17 +108,25 @@ __global__ void __launch_bounds__(256) k_sys_bbox(const double* x, const double*
             hi[b * 3 + k] = c;
         }
     }
+    __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sys_bbox(const double* x, const double* y,
+                                                  const double* z, const int64_t* sys_off, int B,
+                                                  double* lo, double* hi, DevScalars* dsc,
+                                                  const int32_t* gate)
+{
+    if (gated_off(gate)) return;
+    ph_sys_bbox(x, y, z, sys_off, B, lo, hi, dsc, blockIdx.x, gridDim.x);
 }
 
 // One block: grid dimensions of every vacuum system (columns of about 8 atoms'
 // cross-section, z bins a quarter of that), bounded by per-system budgets so the
 // totals never exceed the capacities; then the global column / bin offsets.
-__global__ void __launch_bounds__(256) k_grid_vacuum(const double* lo, const double* hi,
-                                                     const int64_t* sys_off, int B,
-                                                     GridSys* grid, DevScalars* dsc,
-                                                     const int32_t* gate)
+__device__ void ph_grid_vacuum(const double* lo, const double* hi, const int64_t* sys_off, int B,
+                               GridSys* grid, DevScalars* dsc)
 {
-    if (gated_off(gate)) return;
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
         const int64_t nb = sys_off[b + 1] - sys_off[b];
         GridSys g;
@@ -161,6 +174,15 @@ __global__ void __launch_bounds__(256) k_grid_vacuum(const double* lo, const dou
         dsc->n_cols = cols;
         dsc->n_bins = bins;
     }
+}
+
+__global__ void __launch_bounds__(256) k_grid_vacuum(const double* lo, const double* hi,
+                                                     const int64_t* sys_off, int B,
+                                                     GridSys* grid, DevScalars* dsc,
+                                                     const int32_t* gate)
+{
+    if (gated_off(gate)) return;
+    ph_grid_vacuum(lo, hi, sys_off, B, grid, dsc);
 }
 
 // ---------------------------------------------------------------- binning + sort
@@ -214,12 +236,15 @@ __device__ inline void bin_one(const BinArgs& A, int64_t a)
     A.fast_flag[a] = 0;
 }
 
+__device__ inline void ph_bin(const BinArgs& A, int64_t gid, int64_t stride)
+{
+    for (int64_t a = gid; a < A.N; a += stride) bin_one(A, a);
+}
+
 __global__ void __launch_bounds__(256) k_bin(BinArgs A)
 {
     if (gated_off(A.gate)) return;
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (int64_t a = gid; a < A.N; a += (int64_t)gridDim.x * blockDim.x)
-        bin_one(A, a);
+    ph_bin(A, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 
@@ -240,12 +265,9 @@ struct ScatterArgs {
     const int32_t* gate;
 };
 
-__global__ void __launch_bounds__(256) k_scatter_cols(ScatterArgs A)
+__device__ void ph_scatter_cols(const ScatterArgs& A, int64_t gid, int64_t stride)
 {
-    if (gated_off(A.gate)) return;
     const int ncols = A.dsc->n_cols;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     for (int64_t a = gid; a < A.N; a += stride)
         A.sorted[A.bin_start[A.key[a]] + A.rank[a]] = (int32_t)a;
     for (int64_t c = gid; c <= A.cap_cols; c += stride) {
@@ -263,16 +285,20 @@ __global__ void __launch_bounds__(256) k_scatter_cols(ScatterArgs A)
     }
 }
 
+__global__ void __launch_bounds__(256) k_scatter_cols(ScatterArgs A)
+{
+    if (gated_off(A.gate)) return;
+    ph_scatter_cols(A, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+                    (int64_t)gridDim.x * blockDim.x);
+}
+
 // Order the atoms of each bin by caller index (bins hold a few atoms), and clear
 // the bin counters for the next build.
-__global__ void __launch_bounds__(256) k_bin_sort(const int32_t* bin_start, int32_t* sorted,
-                                                  int32_t* bin_cnt, int64_t cap_bins,
-                                                  const DevScalars* dsc, const int32_t* gate)
+__device__ void ph_bin_sort(const int32_t* bin_start, int32_t* sorted, int32_t* bin_cnt,
+                            int64_t cap_bins, const DevScalars* dsc, int64_t gid, int64_t stride)
 {
-    if (gated_off(gate)) return;
     const int nbins = dsc->n_bins;
-    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < cap_bins;
-         b += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t b = gid; b < cap_bins; b += stride) {
         bin_cnt[b] = 0;
         if (b >= nbins) continue;
         const int s = bin_start[b], e = bin_start[b + 1];
@@ -284,6 +310,15 @@ __global__ void __launch_bounds__(256) k_bin_sort(const int32_t* bin_start, int3
             sorted[j + 1] = v;
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_bin_sort(const int32_t* bin_start, int32_t* sorted,
+                                                  int32_t* bin_cnt, int64_t cap_bins,
+                                                  const DevScalars* dsc, const int32_t* gate)
+{
+    if (gated_off(gate)) return;
+    ph_bin_sort(bin_start, sorted, bin_cnt, cap_bins, dsc,
+                blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 struct ClusterArgs {
@@ -324,14 +359,11 @@ __device__ inline int column_of_cluster(const int64_t* pre, int n, int v)
     return lo;
 }
 
-__global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
+__device__ void ph_clusters(const ClusterArgs& A, int64_t gid0, int64_t stride)
 {
-    if (gated_off(A.gate)) return;
     const int ncols = A.dsc->n_cols;
     int total = col_cl0(A.col_pre, ncols);
     const int ngroups = col_grp0(A.col_pre, ncols);
-    const int64_t gid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (gid0 == 0) {
         if (total > A.cap_clusters) set_flag(A.dsc, MD_FLAG_CELL_OVERFLOW);
         A.dsc->n_clusters = min((int64_t)total, A.cap_clusters);
@@ -396,6 +428,13 @@ __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
     }
 }
 
+__global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
+{
+    if (gated_off(A.gate)) return;
+    ph_clusters(A, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+                (int64_t)gridDim.x * blockDim.x);
+}
+
 // ---------------------------------------------------------------- group candidate tables
 
 struct EntryArgs {
@@ -418,10 +457,9 @@ struct EntryArgs {
 // wave order, so the table is deterministic.
 constexpr int kEntryWaves = 4;
 
-__global__ void __launch_bounds__(64 * kEntryWaves) k_group_entries(EntryArgs A)
+// s_eb: dynamic LDS of kEntryWaves * E_cap * 5 bytes.
+__device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, int nblk)
 {
-    if (gated_off(A.gate)) return;
-    extern __shared__ uint32_t s_eb[];                     // [waves][E_cap] entries
     uint8_t* s_mb = reinterpret_cast<uint8_t*>(s_eb + kEntryWaves * A.E_cap);  // masks
     __shared__ int s_cnt[kEntryWaves];
     __shared__ double s_cb[kMaxGroup][6];
@@ -429,7 +467,7 @@ __global__ void __launch_bounds__(64 * kEntryWaves) k_group_entries(EntryArgs A)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ngroups = A.dsc->n_groups;
     const double rl = A.rlist, rl2 = rl * rl;
-    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    for (int g = bid; g < ngroups; g += nblk) {
         const Group gr = A.groups[g];
         const GridSys gs = A.grid[gr.sys];
         double lo[3], hi[3];
@@ -553,6 +591,13 @@ __global__ void __launch_bounds__(64 * kEntryWaves) k_group_entries(EntryArgs A)
     }
 }
 
+__global__ void __launch_bounds__(64 * kEntryWaves) k_group_entries(EntryArgs A)
+{
+    if (gated_off(A.gate)) return;
+    extern __shared__ uint32_t s_eb[];                     // [waves][E_cap] entries
+    ph_group_entries(A, s_eb, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------- orchestration
 
 void launch_build(Ctx* c, const double* x, const double* y, const double* z,
@@ -563,7 +608,7 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
     const int wide = std::max(1, c->n_cu * 8);
     if (!c->cfg.periodic) {
         hipLaunchKernelGGL(k_sys_bbox, dim3(c->B), dim3(256), 0, st, x, y, z, c->d_sys_off,
-                           c->d_sys_lo, c->d_sys_hi, c->dsc, gate);
+                           c->B, c->d_sys_lo, c->d_sys_hi, c->dsc, gate);
         hipLaunchKernelGGL(k_grid_vacuum, dim3(1), dim3(256), 0, st, c->d_sys_lo, c->d_sys_hi,
                            c->d_sys_off, c->B, c->d_grid, c->dsc, gate);
     }
@@ -607,6 +652,181 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
                            st, A);
     }
     hipLaunchKernelGGL(k_build_done, dim3(1), dim3(1), 0, st, c->dsc, gate);
+}
+
+// ---------------------------------------------------------------- fused per-step build
+
+// Exclusive scan of in[0..n) into out[0..n) by all blocks of a persistent grid:
+// each block sums a contiguous chunk, waits for the others, offsets its chunk by
+// the totals of the chunks before it and scans it in tiles.  tot holds nblk values.
+template <class T>
+__device__ bool ph_scan(const T* in, T* out, int64_t n, T* tot, int bid, int nblk,
+                        GridBarrier& gb, DevScalars* d)
+{
+    __shared__ T s_w[16];
+    const int64_t chunk = (n + nblk - 1) / nblk;
+    const int64_t c0 = min(n, (int64_t)bid * chunk), c1 = min(n, c0 + chunk);
+    T t = 0;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) t += in[i];
+    t = block_sum_all(t, s_w);
+    if (threadIdx.x == 0) tot[bid] = t;
+    if (!grid_barrier(gb, d)) return false;
+    T off = 0;
+    for (int k = threadIdx.x; k < bid; k += blockDim.x) off += tot[k];
+    off = block_sum_all(off, s_w);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t base = c0; base < c1; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const T v = i < c1 ? in[i] : (T)0;
+        T inc = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const T y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        __syncthreads();
+        if (lane == 63) s_w[wv] = inc;
+        __syncthreads();
+        T wofs = 0, ttot = 0;
+        for (int k = 0; k < nw; ++k) {
+            if (k < wv) wofs += s_w[k];
+            ttot += s_w[k];
+        }
+        if (i < c1) out[i] = off + wofs + inc - v;
+        off += ttot;
+    }
+    return grid_barrier(gb, d);
+}
+
+struct StepBuildArgs {
+    FastJoinArgs join;
+    int force;                   // rebuild whatever the displacements
+    int periodic;
+    const double *x, *y, *z;
+    const int64_t* sys_off;
+    int B;
+    double *sys_lo, *sys_hi;
+    GridSys* grid;
+    BinArgs bin;
+    ScatterArgs sc;
+    ClusterArgs cl;
+    EntryArgs en;
+    int32_t* bin_cnt;
+    int32_t* bin_start;
+    int64_t n_bin_scan;          // cap_bins + 1
+    int64_t* col_cnt;
+    int64_t* col_pre;
+    int64_t n_col_scan;          // cap_cols + 1
+    int64_t* scan_tmp;           // >= grid blocks
+    int32_t* sorted;
+    int64_t cap_bins;
+    RepackArgs rp;
+    uint32_t* bar_arrive;        // >= grid blocks
+    DevScalars* dsc;
+};
+
+// The build half of one step in one persistent launch (all blocks resident): join
+// the fast-atom lists of phase 0 of the integrator and advance the step counter;
+// when a rebuild is due (more fast atoms than the capacity, a pending request, or
+// `force`), run the whole build with grid barriers between its phases; finally
+// gather positions and charges into slot order for the force kernels.  On a step
+// without rebuild this replaces a dozen launches by one.
+__global__ void __launch_bounds__(256) k_build_step(StepBuildArgs S)
+{
+    extern __shared__ uint32_t s_dyn[];
+    __shared__ int s_i[16];
+    DevScalars* d = S.dsc;
+    const int bid = blockIdx.x, nblk = gridDim.x;
+    const int64_t gid = bid * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t gstride = (int64_t)nblk * blockDim.x;
+    // every block takes the decision from the same inputs (no one writes them here)
+    const int pending = d->need_rebuild;
+    int cnt = 0;
+    for (int k = threadIdx.x; k < S.join.nblocks; k += blockDim.x) cnt += S.join.fast_cnt[k];
+    const int total = block_sum_all(cnt, s_i);
+    const bool rebuild = S.force || pending || total > S.join.fast_cap;
+    // the generation word cannot move before every block has arrived at the first
+    // barrier, so all blocks read the same starting value here
+    GridBarrier gb{S.bar_arrive, &d->bar_gen, (unsigned)nblk,
+                   __hip_atomic_load(&d->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+    if (bid == 0) fast_join_block(S.join);
+    if (!rebuild) {
+        repack_range(S.rp, gid, gstride, true);
+        return;
+    }
+    if (!S.periodic) {
+        ph_sys_bbox(S.x, S.y, S.z, S.sys_off, S.B, S.sys_lo, S.sys_hi, d, bid, nblk);
+        if (!grid_barrier(gb, d)) return;
+        if (bid == 0) ph_grid_vacuum(S.sys_lo, S.sys_hi, S.sys_off, S.B, S.grid, d);
+        if (!grid_barrier(gb, d)) return;
+    }
+    ph_bin(S.bin, gid, gstride);
+    if (!grid_barrier(gb, d)) return;
+    if (!ph_scan<int32_t>(S.bin_cnt, S.bin_start, S.n_bin_scan,
+                          reinterpret_cast<int32_t*>(S.scan_tmp), bid, nblk, gb, d))
+        return;
+    ph_scatter_cols(S.sc, gid, gstride);
+    if (!grid_barrier(gb, d)) return;
+    ph_bin_sort(S.bin_start, S.sorted, S.bin_cnt, S.cap_bins, d, gid, gstride);
+    if (!grid_barrier(gb, d)) return;
+    if (!ph_scan<int64_t>(S.col_cnt, S.col_pre, S.n_col_scan, S.scan_tmp, bid, nblk, gb, d))
+        return;
+    ph_clusters(S.cl, gid, gstride);
+    if (!grid_barrier(gb, d)) return;
+    // candidate tables and the slot repack read disjoint data: no barrier between
+    ph_group_entries(S.en, s_dyn, bid, nblk);
+    repack_range(S.rp, gid, gstride, false);
+    if (bid == 0 && threadIdx.x == 0) ph_build_done(d);
+}
+
+size_t build_step_lds_bytes(int E_cap)
+{
+    return (size_t)kEntryWaves * E_cap * (sizeof(uint32_t) + 1);
+}
+
+hipError_t build_step_setup(Ctx* c)
+{
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, (const void*)k_build_step, 256, build_step_lds_bytes(c->E_cap));
+    if (e != hipSuccess) {
+        c->bs_blocks = 0;
+        return e;
+    }
+    c->bs_blocks = occ > 0 ? std::min(c->n_cu * std::min(occ, 4), c->cap_bar) : 0;
+    return hipSuccess;
+}
+
+void launch_build_step(Ctx* c, const double* x, const double* y, const double* z,
+                       const uint8_t* type, const int8_t* q, bool force, hipStream_t st)
+{
+    StepBuildArgs S;
+    const int nvb = vv_blocks(c->N);
+    S.join = FastJoinArgs{c->d_partial + nvb + c->B + 1, c->d_fast_cnt, c->d_fast_loc,
+                          c->d_fast_list, c->fast_cap, nvb, vv_block_size(), c->dsc};
+    S.force = force ? 1 : 0;
+    S.periodic = c->cfg.periodic;
+    S.x = x; S.y = y; S.z = z;
+    S.sys_off = c->d_sys_off; S.B = c->B; S.sys_lo = c->d_sys_lo; S.sys_hi = c->d_sys_hi;
+    S.grid = c->d_grid;
+    S.bin = BinArgs{c->N, x, y, z, c->d_sys_of_atom, c->d_grid, c->d_bin_cnt, c->d_key,
+                    c->d_rank, c->d_img, c->d_xref, c->d_fast_flag, c->cap_bins, c->dsc, nullptr};
+    S.sc = ScatterArgs{c->N, c->d_key, c->d_rank, c->d_bin_start, c->d_sorted, c->d_grid, c->B,
+                       c->d_col_cnt, c->cap_cols, c->G, c->dsc, nullptr};
+    S.cl = ClusterArgs{x, y, z, type, c->d_grid, c->B, c->d_bin_start, c->d_sorted,
+                       c->d_col_pre, c->d_img, c->d_perm, c->d_inv_perm, c->d_slot_img, c->d_ts,
+                       c->d_atype, c->d_xs, c->cap_slots, c->d_cl_lo, c->d_cl_hi, c->d_groups,
+                       c->d_sys_grp0, c->cap_clusters, c->G, c->T, c->dsc, nullptr};
+    S.en = EntryArgs{c->d_grid, c->d_col_pre, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
+                     c->d_ent_mask, c->E_cap, c->rlist, c->dsc, nullptr};
+    S.bin_cnt = c->d_bin_cnt; S.bin_start = c->d_bin_start; S.n_bin_scan = c->cap_bins + 1;
+    S.col_cnt = c->d_col_cnt; S.col_pre = c->d_col_pre; S.n_col_scan = c->cap_cols + 1;
+    S.scan_tmp = c->d_scan_tmp; S.sorted = c->d_sorted; S.cap_bins = c->cap_bins;
+    S.rp = RepackArgs{x, y, z, q, c->d_perm, c->d_fast_flag, c->d_xs, c->d_qs, c->cap_slots,
+                      c->dsc};
+    S.bar_arrive = c->d_bar_arrive;
+    S.dsc = c->dsc;
+    hipLaunchKernelGGL(k_build_step, dim3(c->bs_blocks), dim3(256),
+                       build_step_lds_bytes(c->E_cap), st, S);
 }
 
 __global__ void k_skin_check(DevScalars* d)

@@ -1,0 +1,176 @@
+// md_device.h -- device routines shared by the stand-alone kernels and the fused
+// per-step build kernel (inline, so every translation unit has its own copy).
+#pragma once
+
+#include "md_internal.h"
+
+namespace md {
+
+// Grid-wide barrier for a persistent launch whose blocks are all resident at once.
+// Every block publishes its writes (agent-scope release) and stores the barrier's
+// epoch into its own arrival word (no contended atomics); the threads of block 0
+// watch all arrival words, then store the epoch into the generation word, which
+// the other blocks watch.  Epochs are gen0 + 1, gen0 + 2, ... where gen0 is the
+// generation read at kernel start.  Waits are bounded (about half a second): a
+// block that gives up latches MD_FLAG_BARRIER and the caller leaves the kernel,
+// so no launch can hang; later barriers time out the same way.
+struct GridBarrier {
+    uint32_t* arrive;              // one word per block
+    uint32_t* gen;
+    unsigned nblk;
+    unsigned epoch;                // epoch of the last barrier passed
+};
+
+__device__ inline bool bar_wait_ok(unsigned spins) { return spins <= (1u << 22); }
+
+__device__ inline bool grid_barrier(GridBarrier& B, DevScalars* d)
+{
+    __shared__ int s_ok;
+    const unsigned ep = B.epoch + 1u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();                          // release this block's writes
+        __hip_atomic_store(&B.arrive[blockIdx.x], ep, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    if (blockIdx.x == 0) {
+        // every thread watches a share of the arrival words
+        unsigned spins = 0;
+        for (unsigned k = threadIdx.x; k < B.nblk; k += blockDim.x) {
+            while (__hip_atomic_load(&B.arrive[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+                   ep) {
+                __builtin_amdgcn_s_sleep(2);
+                if (!bar_wait_ok(++spins)) { ok = 0; break; }
+            }
+            if (!ok) break;
+        }
+        ok = __syncthreads_and(ok);
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (ok) __hip_atomic_store(B.gen, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(B.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ep) {
+            __builtin_amdgcn_s_sleep(4);
+            if (!bar_wait_ok(++spins)) { ok = 0; break; }
+        }
+        __threadfence();                          // acquire the others' writes
+    }
+    if (threadIdx.x == 0) {
+        if (!ok) atomicOr(&d->flags, MD_FLAG_BARRIER);
+        s_ok = ok;
+    }
+    __syncthreads();
+    B.epoch = ep;
+    return s_ok != 0;
+}
+
+// Sum of v over the block (every thread receives it); s holds one value per wave.
+template <class T>
+__device__ inline T block_sum_all(T v, T* s)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += s[k];
+    return t;
+}
+
+// After phase 0 of velocity Verlet: join the per-block fast-atom lists (block
+// order = ascending atom index) into the capped dense list, record the counts and
+// the largest displacement, and advance the step counter.  One block (any size that
+// is a multiple of 64, at most 1024).  Returns the uncapped fast count.
+struct FastJoinArgs {
+    const double* disp_partial;
+    const int32_t* fast_cnt;
+    const int32_t* fast_loc;       // per-block lists, stride loc_stride
+    int32_t* fast_list;
+    int fast_cap;
+    int nblocks;
+    int loc_stride;
+    DevScalars* dsc;
+};
+
+__device__ inline int fast_join_block(const FastJoinArgs& A)
+{
+    __shared__ int s_sum[1024];
+    __shared__ double s_m[16];
+    const int nt = blockDim.x;
+    const int chunk = (A.nblocks + nt - 1) / nt;
+    const int k0 = threadIdx.x * chunk, k1 = min(A.nblocks, k0 + chunk);
+    double m = 0.0;
+    int n = 0;
+    for (int k = k0; k < k1; ++k) {
+        m = fmax(m, A.disp_partial[k]);
+        n += A.fast_cnt[k];
+    }
+    s_sum[threadIdx.x] = n;
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int t = 0; t < nt; ++t) {
+        if (t < (int)threadIdx.x) off += s_sum[t];
+        total += s_sum[t];
+    }
+    for (int k = k0; k < k1 && off < A.fast_cap; ++k) {
+        const int cnt = A.fast_cnt[k];
+        for (int i = 0; i < cnt && off < A.fast_cap; ++i, ++off)
+            A.fast_list[off] = A.fast_loc[(int64_t)k * A.loc_stride + i];
+    }
+    if (threadIdx.x == 0) {
+        double mm = s_m[0];
+        for (int k = 1; k < nt / 64; ++k) mm = fmax(mm, s_m[k]);
+        const double prev = __longlong_as_double((long long)A.dsc->disp2_bits);
+        A.dsc->disp2_bits = (unsigned long long)__double_as_longlong(fmax(prev, mm));
+        A.dsc->n_fast_raw = total;
+        A.dsc->n_fast = min(total, A.fast_cap);
+        A.dsc->step += 1;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Gather positions and charges into slot order for the force kernels; fast atoms
+// (moved more than skin/2 since the build) and padding slots get NaN positions.
+struct RepackArgs {
+    const double *x, *y, *z;
+    const int8_t* q;
+    const int32_t* perm;
+    const uint8_t* fast_flag;
+    double* xs;
+    int8_t* qs;
+    int64_t cap_slots;
+    DevScalars* dsc;
+};
+
+// check_skin: latch MD_FLAG_SKIN when a rebuild is still pending (stale lists).
+__device__ inline void repack_range(const RepackArgs& A, int64_t gtid, int64_t gstride,
+                                    bool check_skin)
+{
+    const int64_t n = A.dsc->n_slots;
+    if (gtid == 0) {
+        A.dsc->work_force = 0u;
+        if (check_skin && A.dsc->need_rebuild) atomicOr(&A.dsc->flags, MD_FLAG_SKIN);
+    }
+    for (int64_t s = gtid; s < n; s += gstride) {
+        const int a = A.perm[s];
+        if (a >= 0 && !A.fast_flag[a]) {
+            A.xs[s] = A.x[a];
+            A.xs[A.cap_slots + s] = A.y[a];
+            A.xs[2 * A.cap_slots + s] = A.z[a];
+            A.qs[s] = A.q[a];
+        } else {
+            A.xs[s] = NAN;
+            A.xs[A.cap_slots + s] = NAN;
+            A.xs[2 * A.cap_slots + s] = NAN;
+            A.qs[s] = a >= 0 ? A.q[a] : 0;
+        }
+    }
+}
+
+}  // namespace md

@@ -7,11 +7,12 @@
 // has moved farther ("fast": flagged by the first velocity-Verlet half step) is staged
 // like a padding slot by the list kernels, and every pair it takes part in is
 // evaluated here, in FP64 with the exact predicate:
-//   * k_fast_self: one work-group per fast atom f scans the columns within
-//     rc + skin/2 of f (every other atom sits in the column of its build position,
-//     which is within skin/2 of where it is now) and then every other fast atom;
-//     it writes F_f and the energy of f's pairs (pairs with another fast atom count
-//     one half from each side);
+//   * k_fast_self: one work-group per fast atom f scans, in the columns within
+//     rc + skin/2 of f, the z bins within that distance (every other atom sits in
+//     the bin of its build position, which is within skin/2 of where it is now),
+//     reading the slot-ordered positions (NaN for fast atoms and padding), and then
+//     every other fast atom; it writes F_f and the energy of f's pairs (pairs with
+//     another fast atom count one half from each side);
 //   * k_fast_nbr: one work-group per column adds, to each non-fast atom of the
 //     column, the forces of the fast atoms within reach, in fast-list order.
 // No atomics on forces: every result is written by one thread in a fixed order.
@@ -21,6 +22,7 @@
 namespace md {
 
 constexpr int kFastBlock = 256;
+constexpr int kFastRanges = 256;     // (column, z range) pairs per sweep of k_fast_self
 
 struct FastArgs {
     const double *x, *y, *z;       // caller positions (current)
@@ -31,7 +33,12 @@ struct FastArgs {
     const GridSys* grid;
     int B;
     const int64_t* col_pre;
+    const int32_t* bin_start;
     const int32_t* perm;
+    const double* xs;              // slot-order positions (SoA, stride cap_slots)
+    const int8_t* qs;
+    const uint8_t* ts;
+    int64_t cap_slots;
     const double* kappa;
     int64_t S1;
     const double *c6, *c12;
@@ -132,6 +139,39 @@ __device__ inline void col_range(const GridSys& g, int d, double p, double reach
     }
 }
 
+// z-bin ranges (up to two, for a periodic wrap) of column-local bins within
+// `reach` of coordinate p; returns the number of ranges.
+__device__ inline int zbin_ranges(const GridSys& g, double p, double reach, int r0[2], int r1[2])
+{
+    const int nz = g.n[2];
+    if (g.periodic) {
+        const double w = p - g.L[2] * floor(p * g.invL[2]);
+        const double a = floor((w - reach) * g.inv_w[2]);
+        const double b = floor((w + reach) * g.inv_w[2]);
+        if (!(b - a + 1.0 < (double)nz) || !(fabs(a) < 1e6) || !(fabs(b) < 1e6)) {
+            r0[0] = 0; r1[0] = nz - 1;
+            return 1;
+        }
+        int lo = (int)a, hi = (int)b;
+        if (lo < 0) {
+            r0[0] = 0; r1[0] = hi;
+            r0[1] = lo + nz; r1[1] = nz - 1;
+            return 2;
+        }
+        if (hi >= nz) {
+            r0[0] = lo; r1[0] = nz - 1;
+            r0[1] = 0; r1[1] = hi - nz;
+            return 2;
+        }
+        r0[0] = lo; r1[0] = hi;
+        return 1;
+    }
+    const double w = p - g.origin[2];
+    r0[0] = (int)fmin(fmax(floor((w - reach) * g.inv_w[2]), 0.0), (double)(nz - 1));
+    r1[0] = (int)fmin(fmax(floor((w + reach) * g.inv_w[2]), 0.0), (double)(nz - 1));
+    return 1;
+}
+
 __device__ inline double block_sum(double v, double* s)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -166,24 +206,58 @@ __global__ void __launch_bounds__(kFastBlock) k_fast_self(FastArgs A)
     int cx0, cx1, cy0, cy1;
     col_range(gs, 0, xf, A.reach, &cx0, &cx1);
     col_range(gs, 1, yf, A.reach, &cy0, &cy1);
-    for (int cx = cx0; cx <= cx1; ++cx) {
-        const int wx = gs.periodic ? ((cx % gs.n[0]) + gs.n[0]) % gs.n[0] : cx;
-        for (int cy = cy0; cy <= cy1; ++cy) {
+    int zr0[2], zr1[2];
+    const int nzr = zbin_ranges(gs, zf, A.reach, zr0, zr1);
+    const int64_t cs = A.cap_slots;
+    const int64_t n_slots = A.dsc->n_slots;
+    // slot ranges of every (column, z range) pair within reach, computed by one
+    // thread each, then swept by the whole work-group as one flattened list
+    __shared__ int64_t s_r0[kFastRanges];
+    __shared__ int s_len[kFastRanges], s_pre[kFastRanges + 1];
+    const int ncy = cy1 - cy0 + 1;
+    const int npairs = (cx1 - cx0 + 1) * ncy * nzr;
+    for (int p0 = 0; p0 < npairs; p0 += kFastRanges) {
+        const int np = min(kFastRanges, npairs - p0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < np; t += blockDim.x) {
+            const int p = p0 + t;
+            const int r = p % nzr, cc = p / nzr;
+            const int cx = cx0 + cc / ncy, cy = cy0 + cc % ncy;
+            const int wx = gs.periodic ? ((cx % gs.n[0]) + gs.n[0]) % gs.n[0] : cx;
             const int wy = gs.periodic ? ((cy % gs.n[1]) + gs.n[1]) % gs.n[1] : cy;
             const int col = gs.col_off + wx * gs.n[1] + wy;
-            const int64_t s0 = (int64_t)col_first_cluster(A.col_pre, col) * kCluster;
-            const int64_t s1 = min((int64_t)col_first_cluster(A.col_pre, col + 1) * kCluster,
-                                   (int64_t)A.dsc->n_slots);
-            for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-                const int a = A.perm[s];
-                if (a < 0 || a == f || A.fast_flag[a]) continue;
-                double dx, dy, dz, fp, e;
-                if (pair_fp64(A, gs, kap, xf, yf, zf, qf, tf, A.x[a], A.y[a], A.z[a], A.q[a],
-                              A.atype[a], &dx, &dy, &dz, &fp, &e)) {
-                    Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
-                    if (ENERGY) E += e;
-                    if (EMIT) emit_one(A, f, a);
-                }
+            const int64_t slot0 = (int64_t)col_first_cluster(A.col_pre, col) * kCluster;
+            const int bin0 = gs.bin_off + (col - gs.col_off) * gs.n[2];
+            const int a_col = A.bin_start[bin0];
+            // the column's atoms are in bin order from slot0 on
+            const int64_t s0 = slot0 + (A.bin_start[bin0 + zr0[r]] - a_col);
+            const int64_t s1 = min(slot0 + (A.bin_start[bin0 + zr1[r] + 1] - a_col), n_slots);
+            s_r0[t] = s0;
+            s_len[t] = (int)max((int64_t)0, s1 - s0);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int t = 0; t < np; ++t) { s_pre[t] = acc; acc += s_len[t]; }
+            s_pre[np] = acc;
+        }
+        __syncthreads();
+        const int total = s_pre[np];
+        for (int k = threadIdx.x; k < total; k += blockDim.x) {
+            int lo = 0, hi = np - 1;                // last range with s_pre <= k
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pre[mid] <= k) lo = mid; else hi = mid - 1;
+            }
+            const int64_t s = s_r0[lo] + (k - s_pre[lo]);
+            const double xa = A.xs[s];
+            if (xa != xa) continue;                // fast atom or padding
+            double dx, dy, dz, fp, e;
+            if (pair_fp64(A, gs, kap, xf, yf, zf, qf, tf, xa, A.xs[cs + s], A.xs[2 * cs + s],
+                          A.qs[s], A.ts[s], &dx, &dy, &dz, &fp, &e)) {
+                Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
+                if (ENERGY) E += e;
+                if (EMIT) emit_one(A, f, A.perm[s]);
             }
         }
     }
@@ -290,11 +364,12 @@ __global__ void __launch_bounds__(kFastBlock) k_fast_nbr(FastArgs A)
     const int64_t s0 = (int64_t)col_first_cluster(A.col_pre, col) * kCluster;
     const int64_t s1 = min((int64_t)col_first_cluster(A.col_pre, col + 1) * kCluster,
                            (int64_t)A.dsc->n_slots);
+    const int64_t cs = A.cap_slots;
     for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-        const int a = A.perm[s];
-        if (a < 0 || A.fast_flag[a]) continue;
-        const double xa = A.x[a], ya = A.y[a], za = A.z[a];
-        const int qa = A.q[a], ta = A.atype[a];
+        const double xa = A.xs[s];
+        if (xa != xa) continue;                    // fast atom or padding
+        const double ya = A.xs[cs + s], za = A.xs[2 * cs + s];
+        const int qa = A.qs[s], ta = A.ts[s];
         double Fx = 0.0, Fy = 0.0, Fz = 0.0;
         bool any = false;
         for (int k = 0; k < total; ++k) {
@@ -307,6 +382,7 @@ __global__ void __launch_bounds__(kFastBlock) k_fast_nbr(FastArgs A)
             }
         }
         if (any) {
+            const int a = A.perm[s];
             A.fx[a] += Fx;
             A.fy[a] += Fy;
             A.fz[a] += Fz;
@@ -321,7 +397,8 @@ void launch_fast(Ctx* c, const double* x, const double* y, const double* z, cons
     FastArgs A;
     A.x = x; A.y = y; A.z = z; A.q = q; A.atype = c->d_atype;
     A.sys_of_atom = c->d_sys_of_atom; A.sys_off = c->d_sys_off; A.grid = c->d_grid; A.B = c->B;
-    A.col_pre = c->d_col_pre; A.perm = c->d_perm;
+    A.col_pre = c->d_col_pre; A.bin_start = c->d_bin_start; A.perm = c->d_perm;
+    A.xs = c->d_xs; A.qs = c->d_qs; A.ts = c->d_ts; A.cap_slots = c->cap_slots;
     A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
     A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T;
     A.rc2 = c->cfg.rc * c->cfg.rc;

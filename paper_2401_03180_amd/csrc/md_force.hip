@@ -17,6 +17,7 @@
 // so the pair set equals the FP64 definition.
 // FP64 path: the plain comparison form, every pair in FP64 from the caller's
 // positions with the exact membership expression.
+#include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
 
@@ -32,40 +33,19 @@ constexpr int kForceBlockMax = 64 * kMaxGroup * kMaxWpc;
 // latch MD_FLAG_SKIN if the lists are stale.  Fast atoms (moved more than skin/2
 // since the build) get NaN positions like padding slots: the list kernels skip
 // them and their pairs are evaluated by the fast-atom kernels.
-__global__ void __launch_bounds__(256) k_repack(const double* x, const double* y,
-                                                const double* z, const int8_t* q,
-                                                const int32_t* perm, const uint8_t* fast_flag,
-                                                double* xs, int8_t* qs, int64_t cap_slots,
-                                                DevScalars* dsc)
+__global__ void __launch_bounds__(256) k_repack(RepackArgs A)
 {
-    const int64_t n = dsc->n_slots;
-    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i0 == 0) {
-        dsc->work_force = 0u;
-        if (dsc->need_rebuild) atomicOr(&dsc->flags, MD_FLAG_SKIN);
-    }
-    for (int64_t s = i0; s < n; s += (int64_t)gridDim.x * blockDim.x) {
-        const int a = perm[s];
-        if (a >= 0 && !fast_flag[a]) {
-            xs[s] = x[a];
-            xs[cap_slots + s] = y[a];
-            xs[2 * cap_slots + s] = z[a];
-            qs[s] = q[a];
-        } else {
-            xs[s] = NAN;
-            xs[cap_slots + s] = NAN;
-            xs[2 * cap_slots + s] = NAN;
-            qs[s] = a >= 0 ? q[a] : 0;
-        }
-    }
+    repack_range(A, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+                 (int64_t)gridDim.x * blockDim.x, true);
 }
 
 void launch_repack(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
                    hipStream_t st)
 {
     const int nb = (int)std::min<int64_t>(div_up(c->cap_slots, 256), (int64_t)c->n_cu * 8);
-    hipLaunchKernelGGL(k_repack, dim3(std::max(nb, 1)), dim3(256), 0, st, x, y, z, q, c->d_perm,
-                       c->d_fast_flag, c->d_xs, c->d_qs, c->cap_slots, c->dsc);
+    const RepackArgs A{x, y, z, q, c->d_perm, c->d_fast_flag, c->d_xs, c->d_qs, c->cap_slots,
+                       c->dsc};
+    hipLaunchKernelGGL(k_repack, dim3(std::max(nb, 1)), dim3(256), 0, st, A);
 }
 
 // ------------------------------------------------------------------ shared pieces
@@ -425,44 +405,75 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
             float ax = 0.f, ay = 0.f, az = 0.f, ea = 0.f;
             double eacc = 0.0;
-            auto pair = [&](uint32_t code) {
-                const uint32_t idx = code & kCodeIdxMask;
-                const int tj = (int)(code >> kCodeIdxBits);
-                const float4 pj = s_j[idx];
-                const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
-                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                bool in = r2 < lo2;
-                const bool amb = fabsf(r2 - rc2f) <= band;
-                if (__builtin_expect(__builtin_amdgcn_ballot_w64(amb) != 0ull, 0)) {
-                    if (amb) in = recheck_pair(ent_g, A.xs, cs, slot_i, idx, gsp, A.rc2) != 0;
+            // one row = 4 codes per lane: the 4 candidate reads are issued together,
+            // then the 4 distances, one ballot for the rare FP64 re-decisions, and the
+            // 4 pair terms, summed in code order
+            auto row = [&](uint64_t codes) {
+                uint32_t idx[4];
+                int tj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t code = (uint32_t)(codes >> (16 * u)) & 0xFFFFu;
+                    idx[u] = code & kCodeIdxMask;
+                    tj[u] = (int)(code >> kCodeIdxBits);
                 }
-                if (EMIT) emit_pairs(in, ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit,
-                                     A.emit_max);
-                const float rinv = in ? __builtin_amdgcn_rsqf(r2) : 0.0f;
-                const float r = r2 * rinv;
-                const float s = __builtin_amdgcn_exp2f(r * nkl2);
-                const float rinv2 = rinv * rinv;
-                const float rinv6 = rinv2 * rinv2 * rinv2;
-                const float uc = qike * pj.w * rinv;
-                const float2 lj = s_lj[tb + tj];
-                const float l6 = lj.x * rinv6;
-                const float l12 = lj.y * rinv6 * rinv6;
-                const float kr = r * kapf;
-                float f, e;
-                if (SCREEN_LJ) {
-                    const float uu = uc + (l12 - l6);
-                    const float wv = fmaf(-6.0f, l6, fmaf(12.0f, l12, uc));
-                    f = fmaf(uu, kr, wv) * s * rinv2;
-                    e = uu * s;
-                } else {
-                    const float wl = fmaf(-6.0f, l6, 12.0f * l12);
-                    f = fmaf(uc * s, 1.0f + kr, wl) * rinv2;
-                    e = fmaf(uc, s, l12 - l6);
+                float4 pj[4];
+                float2 lj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pj[u] = s_j[idx[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) lj[u] = s_lj[tb + tj[u]];
+                float dx[4], dy[4], dz[4], r2[4];
+                bool in[4], amb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    dx[u] = xi - pj[u].x;
+                    dy[u] = yi - pj[u].y;
+                    dz[u] = zi - pj[u].z;
+                    r2[u] = fmaf(dz[u], dz[u], fmaf(dy[u], dy[u], dx[u] * dx[u]));
+                    in[u] = r2[u] < lo2;
+                    amb[u] = fabsf(r2[u] - rc2f) <= band;
                 }
-                ax = fmaf(f, dx, ax);
-                ay = fmaf(f, dy, ay);
-                az = fmaf(f, dz, az);
-                if (ENERGY) ea += e;
+                if (__builtin_expect(
+                        __builtin_amdgcn_ballot_w64(amb[0] | amb[1] | amb[2] | amb[3]) != 0ull, 0)) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (amb[u])
+                            in[u] = recheck_pair(ent_g, A.xs, cs, slot_i, idx[u], gsp, A.rc2) != 0;
+                }
+                if (EMIT) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        emit_pairs(in[u], ent_g, A.perm, ai, idx[u], &A.dsc->pair_count, A.emit,
+                                   A.emit_max);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float rinv = in[u] ? __builtin_amdgcn_rsqf(r2[u]) : 0.0f;
+                    const float r = r2[u] * rinv;
+                    const float s = __builtin_amdgcn_exp2f(r * nkl2);
+                    const float rinv2 = rinv * rinv;
+                    const float rinv6 = rinv2 * rinv2 * rinv2;
+                    const float uc = qike * pj[u].w * rinv;
+                    const float l6 = lj[u].x * rinv6;
+                    const float l12 = lj[u].y * rinv6 * rinv6;
+                    const float kr = r * kapf;
+                    float f, e;
+                    if (SCREEN_LJ) {
+                        const float uu = uc + (l12 - l6);
+                        const float wv = fmaf(-6.0f, l6, fmaf(12.0f, l12, uc));
+                        f = fmaf(uu, kr, wv) * s * rinv2;
+                        e = uu * s;
+                    } else {
+                        const float wl = fmaf(-6.0f, l6, 12.0f * l12);
+                        f = fmaf(uc * s, 1.0f + kr, wl) * rinv2;
+                        e = fmaf(uc, s, l12 - l6);
+                    }
+                    ax = fmaf(f, dx[u], ax);
+                    ay = fmaf(f, dy[u], ay);
+                    az = fmaf(f, dz[u], az);
+                    if (ENERGY) ea += e;
+                }
             };
             const uint64_t sent4 = 0x0001000100010001ull * (uint64_t)sentinel;
             uint64_t v0 = nr > 0 ? (uint64_t)cp[0] : sent4;
@@ -471,11 +482,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 const uint64_t cur = v0;
                 v0 = v1;
                 if (r + 2 < nr) v1 = cp[(r + 2) * 8];
-                const uint32_t lo = (uint32_t)cur, hi = (uint32_t)(cur >> 32);
-                pair(lo & 0xFFFFu);
-                pair(lo >> 16);
-                pair(hi & 0xFFFFu);
-                pair(hi >> 16);
+                row(cur);
                 if (r & 1) {      // fold every 8 terms into the compensated sums
                     kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
                     if (ENERGY) eacc += (double)ea;

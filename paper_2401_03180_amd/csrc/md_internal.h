@@ -64,6 +64,7 @@ struct DevScalars {
     unsigned long long pair_count;  // debug pair export counter
     int32_t n_fast;             // atoms beyond skin/2 of their build position (<= capacity)
     int32_t n_fast_raw;         // the same, uncapped (above the capacity a rebuild is due)
+    uint32_t bar_gen, bar_pad_;     // grid barrier generation of the fused build kernel
 };
 
 struct Ctx {
@@ -78,6 +79,9 @@ struct Ctx {
     size_t max_lds = 65536;        // per work-group
     size_t lds_per_cu = 65536;
     size_t force32_static_lds = 8192;
+    int bs_blocks = 0;             // grid of the fused build kernel (0: not usable)
+    int cap_bar = 0;               // arrival words of its barrier
+    uint32_t* d_bar_arrive = nullptr;
     // force-kernel launch timer: event pairs recorded around the next t_cap launches
     std::vector<hipEvent_t> t_ev;
     int t_cap = 0, t_n = 0;

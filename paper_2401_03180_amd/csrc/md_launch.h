@@ -17,10 +17,21 @@ void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const doubl
                const double* fy, const double* fz, double* x, double* y, double* z, double* vx,
                double* vy, double* vz, double* ekin, hipStream_t st);
 int64_t vv_partials_needed(int64_t N, int B);
+// phase 0 of velocity Verlet with the ionization of the step it starts (md_step)
+void launch_vv0_ionize(Ctx* c, double dt, const double* inv_mass, const double* fx,
+                       const double* fy, const double* fz, double* x, double* y, double* z,
+                       double* vx, double* vy, double* vz, const uint8_t* elem,
+                       const uint32_t* atom_id, int8_t* q, hipStream_t st);
+int vv_blocks(int64_t N);
+int vv_block_size();
 void launch_set_step(Ctx* c, int64_t step, hipStream_t st);
 void launch_clear_flags(Ctx* c, hipStream_t st);
 
 // md_build.hip
+// md_step's fused build: fast-list join, step counter, rebuild when due, slot repack
+void launch_build_step(Ctx* c, const double* x, const double* y, const double* z,
+                       const uint8_t* type, const int8_t* q, bool force, hipStream_t st);
+hipError_t build_step_setup(Ctx* c);
 void launch_build(Ctx* c, const double* x, const double* y, const double* z, const uint8_t* type,
                   bool force, hipStream_t st);
 void launch_skin_check(Ctx* c, hipStream_t st);

@@ -1,5 +1,6 @@
 // md_step.hip -- element-wise per-step kernels: ionization, velocity Verlet,
 // slot repacking, and the generic scan / fill utilities used by the build.
+#include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
 
@@ -148,43 +149,65 @@ __device__ inline uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, u
 
 // ------------------------------------------------------------------ ionization
 
-__global__ void __launch_bounds__(256) k_ionize(int64_t N, const int32_t* sys_of_atom,
-                                                const uint8_t* elem, const uint32_t* atom_id,
-                                                int8_t* q, const int8_t* qmax, const double* base,
-                                                int32_t E, int32_t Q, const double* g, int64_t S1,
-                                                const uint64_t* seeds, DevScalars* dsc)
+struct IonArgs {
+    int64_t N;
+    const int32_t* sys_of_atom;
+    const uint8_t* elem;
+    const uint32_t* atom_id;
+    int8_t* q;
+    const int8_t* qmax;
+    const double* base;
+    int32_t E, Q;
+    const double* g;
+    int64_t S1;
+    const uint64_t* seeds;
+    DevScalars* dsc;
+};
+
+// Ionization of atom a at step s (1 <= s < S1).
+__device__ inline void ionize_one(const IonArgs& A, int64_t a, int64_t s)
 {
-    const int64_t s = dsc->step;
-    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (a >= N) return;
-    if (s < 1 || s >= S1) {
-        if (a == 0) set_flag(dsc, MD_FLAG_STEP);
+    const int e = A.elem[a];
+    const int qa = A.q[a];
+    if (e >= A.E || qa < 0 || qa >= A.Q) {
+        set_flag(A.dsc, MD_FLAG_BAD_INPUT);
         return;
     }
-    const int e = elem[a];
-    const int qa = q[a];
-    if (e >= E || qa < 0 || qa >= Q) {
-        set_flag(dsc, MD_FLAG_BAD_INPUT);
-        return;
-    }
-    if (qa >= qmax[e]) return;
-    const int b = sys_of_atom[a];
-    double p = base[e * Q + qa] * g[b * S1 + s];
+    if (qa >= A.qmax[e]) return;
+    const int b = A.sys_of_atom[a];
+    double p = A.base[e * A.Q + qa] * A.g[b * A.S1 + s];
     p = p > 1.0 ? 1.0 : p;
     const uint64_t thresh = (uint64_t)floor(p * 4294967296.0);
-    const uint64_t seed = seeds[b];
-    const uint32_t u = philox_word0(atom_id[a], (uint32_t)s, (uint32_t)b, 0u, (uint32_t)seed,
+    const uint64_t seed = A.seeds[b];
+    const uint32_t u = philox_word0(A.atom_id[a], (uint32_t)s, (uint32_t)b, 0u, (uint32_t)seed,
                                     (uint32_t)(seed >> 32));
-    if ((uint64_t)u < thresh) q[a] = (int8_t)(qa + 1);
+    if ((uint64_t)u < thresh) A.q[a] = (int8_t)(qa + 1);
+}
+
+__global__ void __launch_bounds__(256) k_ionize(IonArgs A)
+{
+    const int64_t s = A.dsc->step;
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= A.N) return;
+    if (s < 1 || s >= A.S1) {
+        if (a == 0) set_flag(A.dsc, MD_FLAG_STEP);
+        return;
+    }
+    ionize_one(A, a, s);
+}
+
+static IonArgs ion_args(Ctx* c, const uint8_t* elem, const uint32_t* atom_id, int8_t* q)
+{
+    return IonArgs{c->N, c->d_sys_of_atom, elem, atom_id, q, c->d_qmax, c->d_base, c->E, c->Q,
+                   c->d_g, c->n_steps + 1, c->d_seeds, c->dsc};
 }
 
 void launch_ionize(Ctx* c, const uint8_t* elem, const uint32_t* atom_id, int8_t* q,
                    hipStream_t st)
 {
     if (c->N == 0) return;
-    hipLaunchKernelGGL(k_ionize, dim3(div_up(c->N, 256)), dim3(256), 0, st, c->N,
-                       c->d_sys_of_atom, elem, atom_id, q, c->d_qmax, c->d_base, c->E, c->Q, c->d_g,
-                       c->n_steps + 1, c->d_seeds, c->dsc);
+    hipLaunchKernelGGL(k_ionize, dim3(div_up(c->N, 256)), dim3(256), 0, st,
+                       ion_args(c, elem, atom_id, q));
 }
 
 // ------------------------------------------------------------------ velocity Verlet
@@ -225,13 +248,20 @@ __device__ double block_sum_d(double v, double* s)
     return t;   // valid in thread 0
 }
 
-template <int PHASE, bool EKIN>
-__global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A)
+// IONIZE (phase 0 only): also the ionization of the step this phase starts (the
+// step counter is advanced after this kernel), as md_step issues it.
+template <int PHASE, bool EKIN, bool IONIZE = false>
+__global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I)
 {
 #pragma clang fp contract(off)
     __shared__ double s_red[kVvBlock / 64];
     const int64_t a = blockIdx.x * (int64_t)kVvBlock + threadIdx.x;
     double d2 = 0.0, ke = 0.0;
+    if (IONIZE && a < A.N) {
+        const int64_t s = A.dsc->step + 1;
+        if (s >= 1 && s < I.S1) ionize_one(I, a, s);
+        else if (a == 0) set_flag(A.dsc, MD_FLAG_STEP);
+    }
     if (a < A.N) {
         const double h = A.hdt * A.inv_mass[a];
         double vx = A.vx[a] + h * A.fx[a];
@@ -297,39 +327,10 @@ __global__ void __launch_bounds__(kVvBlock) k_vv_finalize(VvArgs A, int nblocks)
     if (PHASE == 0) {
         // fast list: the blocks' lists concatenated in block order (ascending atom
         // index), up to the capacity; a rebuild is due when more atoms are fast
-        __shared__ int s_sum[kVvBlock];
-        const int chunk = (nblocks + kVvBlock - 1) / kVvBlock;
-        const int k0 = threadIdx.x * chunk, k1 = min(nblocks, k0 + chunk);
-        double m = 0.0;
-        int n = 0;
-        for (int k = k0; k < k1; ++k) {
-            m = fmax(m, A.disp_partial[k]);
-            n += A.fast_cnt[k];
-        }
-        s_sum[threadIdx.x] = n;
-        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
-        __syncthreads();
-        int off = 0, total = 0;
-        for (int t = 0; t < kVvBlock; ++t) {
-            if (t < (int)threadIdx.x) off += s_sum[t];
-            total += s_sum[t];
-        }
-        for (int k = k0; k < k1 && off < A.fast_cap; ++k) {
-            const int cnt = A.fast_cnt[k];
-            for (int i = 0; i < cnt && off < A.fast_cap; ++i, ++off)
-                A.fast_list[off] = A.fast_loc[(int64_t)k * kVvBlock + i];
-        }
-        if (threadIdx.x == 0) {
-            for (int k = 1; k < kVvBlock / 64; ++k) m = fmax(m, s_red[k]);
-            m = fmax(m, s_red[0]);
-            const double prev = __longlong_as_double((long long)A.dsc->disp2_bits);
-            A.dsc->disp2_bits = (unsigned long long)__double_as_longlong(fmax(prev, m));
-            A.dsc->n_fast_raw = total;
-            A.dsc->n_fast = min(total, A.fast_cap);
-            if (total > A.fast_cap) A.dsc->need_rebuild = 1;
-            A.dsc->step += 1;
-        }
+        FastJoinArgs J{A.disp_partial, A.fast_cnt, A.fast_loc, A.fast_list, A.fast_cap, nblocks,
+                       kVvBlock, A.dsc};
+        const int total = fast_join_block(J);
+        if (threadIdx.x == 0 && total > A.fast_cap) A.dsc->need_rebuild = 1;
         return;
     }
     for (int b = 0; b < A.B; ++b) {
@@ -360,23 +361,58 @@ void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const doubl
     A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
     A.fast_flag = c->d_fast_flag; A.fast_loc = c->d_fast_loc; A.fast_cnt = c->d_fast_cnt;
     A.fast_list = c->d_fast_list; A.fast_cap = c->fast_cap;
+    const IonArgs I{};
     if (phase == 0) {
-        if (nb > 0) hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A);
+        if (nb > 0) hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I);
         hipLaunchKernelGGL((k_vv_finalize<0>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
     } else if (ekin) {
-        if (nb > 0) hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A);
+        if (nb > 0) hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A, I);
         hipLaunchKernelGGL((k_vv_finalize<1>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
     } else if (nb > 0) {
-        hipLaunchKernelGGL((k_vv<1, false>), dim3(nb), dim3(kVvBlock), 0, st, A);
+        hipLaunchKernelGGL((k_vv<1, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I);
     }
 }
+
+void launch_vv0_ionize(Ctx* c, double dt, const double* inv_mass, const double* fx,
+                       const double* fy, const double* fz, double* x, double* y, double* z,
+                       double* vx, double* vy, double* vz, const uint8_t* elem,
+                       const uint32_t* atom_id, int8_t* q, hipStream_t st)
+{
+    VvArgs A;
+    A.N = c->N; A.dt = dt; A.hdt = 0.5 * dt;
+    const double half_skin = 0.5 * c->cfg.skin;
+    A.thr2 = half_skin * half_skin;
+    A.inv_mass = inv_mass; A.fx = fx; A.fy = fy; A.fz = fz;
+    A.x = x; A.y = y; A.z = z; A.vx = vx; A.vy = vy; A.vz = vz;
+    A.xref = c->d_xref; A.partial = c->d_partial; A.ekin = nullptr;
+    const int nb = (int)div_up(c->N, kVvBlock);
+    A.disp_partial = c->d_partial + nb + c->B + 1;
+    A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
+    A.fast_flag = c->d_fast_flag; A.fast_loc = c->d_fast_loc; A.fast_cnt = c->d_fast_cnt;
+    A.fast_list = c->d_fast_list; A.fast_cap = c->fast_cap;
+    if (nb > 0)
+        hipLaunchKernelGGL((k_vv<0, false, true>), dim3(nb), dim3(kVvBlock), 0, st, A,
+                           ion_args(c, elem, atom_id, q));
+}
+
+int vv_blocks(int64_t N) { return (int)div_up(N, kVvBlock); }
+int vv_block_size() { return kVvBlock; }
 
 int64_t vv_partials_needed(int64_t N, int B) { return 2 * (div_up(N, kVvBlock) + B + 1); }
 
 // ------------------------------------------------------------------ device scalars
 
 __global__ void k_set_step(DevScalars* d, int64_t step) { d->step = step; }
-__global__ void k_clear_flags(DevScalars* d) { d->flags = 0u; }
+// Clear the error word and re-arm the fused build kernel's barrier (a timed-out
+// barrier can leave arrival words ahead of the generation).
+__global__ void k_clear_flags(DevScalars* d, uint32_t* bar_arrive, int n)
+{
+    for (int k = threadIdx.x; k < n; k += blockDim.x) bar_arrive[k] = 0u;
+    if (threadIdx.x == 0) {
+        d->flags = 0u;
+        d->bar_gen = 0u;
+    }
+}
 
 void launch_set_step(Ctx* c, int64_t step, hipStream_t st)
 {
@@ -385,7 +421,8 @@ void launch_set_step(Ctx* c, int64_t step, hipStream_t st)
 
 void launch_clear_flags(Ctx* c, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(1), 0, st, c->dsc);
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(256), 0, st, c->dsc, c->d_bar_arrive,
+                       c->cap_bar);
 }
 
 }  // namespace md

@@ -22,6 +22,7 @@ MD_FP64, MD_FP32_KAHAN = 0, 1
 MD_BUILD_AUTO, MD_BUILD_FORCE, MD_BUILD_CHECK = 0, 1, 2
 MD_FLAG_CELL_OVERFLOW, MD_FLAG_LIST_OVERFLOW, MD_FLAG_SKIN = 0x1, 0x2, 0x4
 MD_FLAG_NONFINITE, MD_FLAG_STEP, MD_FLAG_BAD_INPUT = 0x8, 0x10, 0x20
+MD_FLAG_BARRIER = 0x40
 MD_MAX_TYPES, MD_MAX_ELEMENTS, MD_MAX_CHARGE_STATES = 8, 8, 128
 
 EXPORTED = (
