@@ -718,9 +718,11 @@ static md_status step_impl(md_ctx* ctx, const md_step_args* a, int32_t build_mod
         hipEvent_t e0, e1;
         next_timer_events(c, hs, &e0, &e1);
         HIP_TRY(c, launch_forces(c, a->prec, a->x, a->y, a->z, a->q, a->fx, a->fy, a->fz,
-                                 a->epot, nullptr, 0, hs, e0, e1));
-        return md_integrate_vv(ctx, 1, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y, a->z,
-                               a->vx, a->vy, a->vz, a->ekin, st);
+                                 a->epot, nullptr, 0, hs, e0, e1, false));
+        launch_vv1_finalize(c, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->vx, a->vy, a->vz,
+                            a->ekin, a->epot, hs);
+        HIP_TRY(c, hipGetLastError());
+        return MD_OK;
     }
     md_status s = md_integrate_vv(ctx, 0, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y,
                                   a->z, a->vx, a->vy, a->vz, nullptr, st);

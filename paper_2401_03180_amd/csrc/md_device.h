@@ -173,4 +173,47 @@ __device__ inline void repack_range(const RepackArgs& A, int64_t gtid, int64_t g
     }
 }
 
+// One block after the force kernels: the per-system energy as the sum of the group
+// energies and of the fast atoms' pair energies in a fixed order (deterministic),
+// and the end of a pending list rebuild.
+struct ForceFinalizeArgs {
+    const double* grp_epot;
+    double* epot;                  // NULL: no energy requested
+    const int32_t* sys_grp0;
+    int B;
+    const int32_t* fast_list;
+    const double* fast_e;
+    const int64_t* sys_off;
+    DevScalars* dsc;
+};
+
+__device__ inline void force_finalize_block(const ForceFinalizeArgs& F)
+{
+    __shared__ double s_red[16];
+    if (F.epot) {
+        const int nf = F.dsc->n_fast;
+        const int nw = blockDim.x >> 6;
+        for (int b = 0; b < F.B; ++b) {
+            const int g0 = F.sys_grp0[b], g1 = F.sys_grp0[b + 1];
+            double t = 0.0;
+            for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) t += F.grp_epot[g];
+            const int64_t a0 = F.sys_off[b], a1 = F.sys_off[b + 1];
+            for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+                const int f = F.fast_list[k];
+                if (f >= a0 && f < a1) t += F.fast_e[k];
+            }
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double e = 0.0;
+                for (int w = 0; w < nw; ++w) e += s_red[w];
+                F.epot[b] = e;
+            }
+        }
+    }
+    if (threadIdx.x == 0) F.dsc->lists_pending = 0;
+}
+
 }  // namespace md

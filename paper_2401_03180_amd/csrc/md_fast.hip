@@ -7,13 +7,13 @@
 // has moved farther ("fast": flagged by the first velocity-Verlet half step) is staged
 // like a padding slot by the list kernels, and every pair it takes part in is
 // evaluated here, in FP64 with the exact predicate:
-//   * k_fast_self: one work-group per fast atom f scans, in the columns within
+//   * fast_self: one work-group per fast atom f scans, in the columns within
 //     rc + skin/2 of f, the z bins within that distance (every other atom sits in
 //     the bin of its build position, which is within skin/2 of where it is now),
 //     reading the slot-ordered positions (NaN for fast atoms and padding), and then
 //     every other fast atom; it writes F_f and the energy of f's pairs (pairs with
 //     another fast atom count one half from each side);
-//   * k_fast_nbr: one work-group per column adds, to each non-fast atom of the
+//   * fast_nbr: one work-group per column adds, to each non-fast atom of the
 //     column, the forces of the fast atoms within reach, in fast-list order.
 // No atomics on forces: every result is written by one thread in a fixed order.
 #include "md_internal.h"
@@ -22,7 +22,7 @@
 namespace md {
 
 constexpr int kFastBlock = 256;
-constexpr int kFastRanges = 256;     // (column, z range) pairs per sweep of k_fast_self
+constexpr int kFastRanges = 256;     // (column, z range) pairs per sweep of fast_self
 
 struct FastArgs {
     const double *x, *y, *z;       // caller positions (current)
@@ -189,12 +189,12 @@ __device__ inline int64_t clamp_step_fast(const FastArgs& A)
     return s < 0 ? 0 : (s >= A.S1 ? A.S1 - 1 : s);
 }
 
+// Work-group fi of the fast-atom pass: all pairs of fast atom fi.
 template <bool ENERGY, bool EMIT>
-__global__ void __launch_bounds__(kFastBlock) k_fast_self(FastArgs A)
+__device__ void fast_self(const FastArgs& A, int fi)
 {
     __shared__ double s_red[kFastBlock / 64];
     const int nf = A.dsc->n_fast;
-    const int fi = blockIdx.x;
     if (fi >= nf) return;
     const int f = A.fast_list[fi];
     const int b = A.sys_of_atom[f];
@@ -299,12 +299,12 @@ __device__ inline int sys_of_col(const GridSys* grid, int B, int c)
 
 constexpr int kFastLocal = 1024;     // fast atoms near one column held in LDS
 
-__global__ void __launch_bounds__(kFastBlock) k_fast_nbr(FastArgs A)
+// Column `col` of the fast-atom pass: forces of nearby fast atoms on its other atoms.
+__device__ void fast_nbr(const FastArgs& A, int col)
 {
     __shared__ int s_loc[kFastLocal];
     __shared__ int s_cnt[kFastBlock / 64];
     const int nf = A.dsc->n_fast;
-    const int col = blockIdx.x;
     if (nf == 0 || col >= A.dsc->n_cols) return;
     const int b = sys_of_col(A.grid, A.B, col);
     const GridSys gs = A.grid[b];
@@ -390,6 +390,16 @@ __global__ void __launch_bounds__(kFastBlock) k_fast_nbr(FastArgs A)
     }
 }
 
+// One launch: work-groups [0, fast_cap) take one fast atom each (its own pairs),
+// the following ones one column each (the fast atoms' forces on the column's other
+// atoms); the two halves write disjoint atoms, so they need no ordering.
+template <bool ENERGY, bool EMIT>
+__global__ void __launch_bounds__(kFastBlock) k_fast(FastArgs A, int fast_cap)
+{
+    if ((int)blockIdx.x < fast_cap) fast_self<ENERGY, EMIT>(A, blockIdx.x);
+    else fast_nbr(A, blockIdx.x - fast_cap);
+}
+
 void launch_fast(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
                  double* fx, double* fy, double* fz, bool energy, int2* emit, int64_t emit_max,
                  hipStream_t st)
@@ -406,16 +416,15 @@ void launch_fast(Ctx* c, const double* x, const double* y, const double* z, cons
     A.screen_lj = c->cfg.screen_lj;
     A.fast_flag = c->d_fast_flag; A.fast_list = c->d_fast_list; A.fast_e = c->d_fast_e;
     A.dsc = c->dsc; A.fx = fx; A.fy = fy; A.fz = fz; A.emit = emit; A.emit_max = emit_max;
-    const dim3 gs((unsigned)std::max(c->fast_cap, 1)), bs(kFastBlock);
+    const int fc = std::max(c->fast_cap, 1);
+    const dim3 gs((unsigned)(fc + std::max<int64_t>(c->cap_cols, 1))), bs(kFastBlock);
     if (emit) {
-        if (energy) hipLaunchKernelGGL((k_fast_self<true, true>), gs, bs, 0, st, A);
-        else hipLaunchKernelGGL((k_fast_self<false, true>), gs, bs, 0, st, A);
+        if (energy) hipLaunchKernelGGL((k_fast<true, true>), gs, bs, 0, st, A, fc);
+        else hipLaunchKernelGGL((k_fast<false, true>), gs, bs, 0, st, A, fc);
     } else {
-        if (energy) hipLaunchKernelGGL((k_fast_self<true, false>), gs, bs, 0, st, A);
-        else hipLaunchKernelGGL((k_fast_self<false, false>), gs, bs, 0, st, A);
+        if (energy) hipLaunchKernelGGL((k_fast<true, false>), gs, bs, 0, st, A, fc);
+        else hipLaunchKernelGGL((k_fast<false, false>), gs, bs, 0, st, A, fc);
     }
-    hipLaunchKernelGGL(k_fast_nbr, dim3((unsigned)std::max<int64_t>(c->cap_cols, 1)), bs, 0, st,
-                       A);
 }
 
 }  // namespace md

@@ -86,35 +86,9 @@ struct ForceArgs {
     float thr2;                  // ((rc + skin)(1 + 1e-5))^2
 };
 
-// One block after every force launch: the per-system energy as the sum of the
-// group energies and of the fast atoms' pair energies in a fixed order
-// (deterministic), and the end of a pending list rebuild.
-__global__ void __launch_bounds__(256) k_force_finalize(const double* grp_epot, double* epot,
-                                                        const int32_t* sys_grp0, int B,
-                                                        const int32_t* fast_list,
-                                                        const double* fast_e,
-                                                        const int64_t* sys_off, DevScalars* dsc)
+__global__ void __launch_bounds__(256) k_force_finalize(ForceFinalizeArgs F)
 {
-    __shared__ double s_red[4];
-    if (epot) {
-        const int nf = dsc->n_fast;
-        for (int b = 0; b < B; ++b) {
-            const int g0 = sys_grp0[b], g1 = sys_grp0[b + 1];
-            double t = 0.0;
-            for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) t += grp_epot[g];
-            const int64_t a0 = sys_off[b], a1 = sys_off[b + 1];
-            for (int k = threadIdx.x; k < nf; k += blockDim.x) {
-                const int f = fast_list[k];
-                if (f >= a0 && f < a1) t += fast_e[k];
-            }
-            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-            __syncthreads();
-            if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;
-            __syncthreads();
-            if (threadIdx.x == 0) epot[b] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
-        }
-    }
-    if (threadIdx.x == 0) dsc->lists_pending = 0;
+    force_finalize_block(F);
 }
 
 template <class T>
@@ -677,10 +651,16 @@ static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks
         hipLaunchKernelGGL((k_force64<E, M, S>), dim3(blocks), dim3(64 * c->G), 0, st, A);
 }
 
+ForceFinalizeArgs force_finalize_args(Ctx* c, double* epot)
+{
+    return ForceFinalizeArgs{c->d_grp_epot, epot, c->d_sys_grp0, c->B, c->d_fast_list,
+                             c->d_fast_e, c->d_sys_off, c->dsc};
+}
+
 hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const double* y,
                          const double* z, const int8_t* q, double* fx, double* fy, double* fz,
                          double* epot, int2* emit, int64_t emit_max, hipStream_t st,
-                         hipEvent_t ev0, hipEvent_t ev1)
+                         hipEvent_t ev0, hipEvent_t ev1, bool finalize)
 {
     ForceArgs A;
     A.groups = c->d_groups; A.ent = c->d_ent; A.nb = c->d_nb; A.cl_nt = c->d_cl_nt;
@@ -732,8 +712,9 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
         if (e != hipSuccess) return e;
     }
     if (c->fast_cap > 0) launch_fast(c, x, y, z, q, fx, fy, fz, E, emit, emit_max, st);
-    hipLaunchKernelGGL(k_force_finalize, dim3(1), dim3(256), 0, st, c->d_grp_epot, epot,
-                       c->d_sys_grp0, c->B, c->d_fast_list, c->d_fast_e, c->d_sys_off, c->dsc);
+    if (finalize)
+        hipLaunchKernelGGL(k_force_finalize, dim3(1), dim3(256), 0, st,
+                           force_finalize_args(c, epot));
     return hipGetLastError();
 }
 

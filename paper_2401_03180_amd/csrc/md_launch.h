@@ -22,6 +22,10 @@ void launch_vv0_ionize(Ctx* c, double dt, const double* inv_mass, const double* 
                        const double* fy, const double* fz, double* x, double* y, double* z,
                        double* vx, double* vy, double* vz, const uint8_t* elem,
                        const uint32_t* atom_id, int8_t* q, hipStream_t st);
+// phase 1 of velocity Verlet with the force finalize of the step (md_step)
+void launch_vv1_finalize(Ctx* c, double dt, const double* inv_mass, const double* fx,
+                         const double* fy, const double* fz, double* vx, double* vy, double* vz,
+                         double* ekin, double* epot, hipStream_t st);
 int vv_blocks(int64_t N);
 int vv_block_size();
 void launch_set_step(Ctx* c, int64_t step, hipStream_t st);
@@ -41,10 +45,14 @@ void launch_repack(Ctx* c, const double* x, const double* y, const double* z, co
                    hipStream_t st);
 // ev0 / ev1 (optional) are recorded on st immediately before / after the main force
 // kernel, so their interval times that kernel alone
+// finalize = false leaves the energy reduction and the end of a pending list
+// rebuild to the caller (md_step folds them into phase 1 of the integrator).
 hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const double* y,
                          const double* z, const int8_t* q, double* fx, double* fy, double* fz,
                          double* epot, int2* emit, int64_t emit_max, hipStream_t st,
-                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool finalize = true);
+struct ForceFinalizeArgs;
+ForceFinalizeArgs force_finalize_args(Ctx* c, double* epot);
 size_t force32_lds_bytes(int E_cap);
 
 // md_fast.hip

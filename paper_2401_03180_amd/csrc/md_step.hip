@@ -249,12 +249,17 @@ __device__ double block_sum_d(double v, double* s)
 }
 
 // IONIZE (phase 0 only): also the ionization of the step this phase starts (the
-// step counter is advanced after this kernel), as md_step issues it.
-template <int PHASE, bool EKIN, bool IONIZE = false>
-__global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I)
+// step counter is advanced after this kernel), as md_step issues it.  FIN (phase 1
+// only): one extra work-group runs the force finalize of the step.
+template <int PHASE, bool EKIN, bool IONIZE = false, bool FIN = false>
+__global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinalizeArgs F)
 {
 #pragma clang fp contract(off)
     __shared__ double s_red[kVvBlock / 64];
+    if (FIN && blockIdx.x == gridDim.x - 1) {
+        force_finalize_block(F);
+        return;
+    }
     const int64_t a = blockIdx.x * (int64_t)kVvBlock + threadIdx.x;
     double d2 = 0.0, ke = 0.0;
     if (IONIZE && a < A.N) {
@@ -345,10 +350,11 @@ __global__ void __launch_bounds__(kVvBlock) k_vv_finalize(VvArgs A, int nblocks)
     }
 }
 
-void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const double* fx,
-               const double* fy, const double* fz, double* x, double* y, double* z, double* vx,
-               double* vy, double* vz, double* ekin, hipStream_t st)
+static VvArgs vv_args(Ctx* c, int phase, double dt, const double* inv_mass, const double* fx,
+                      const double* fy, const double* fz, double* x, double* y, double* z,
+                      double* vx, double* vy, double* vz, double* ekin)
 {
+    (void)phase;
     VvArgs A;
     A.N = c->N; A.dt = dt; A.hdt = 0.5 * dt;
     const double half_skin = 0.5 * c->cfg.skin;
@@ -361,15 +367,46 @@ void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const doubl
     A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
     A.fast_flag = c->d_fast_flag; A.fast_loc = c->d_fast_loc; A.fast_cnt = c->d_fast_cnt;
     A.fast_list = c->d_fast_list; A.fast_cap = c->fast_cap;
+    return A;
+}
+
+void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const double* fx,
+               const double* fy, const double* fz, double* x, double* y, double* z, double* vx,
+               double* vy, double* vz, double* ekin, hipStream_t st)
+{
+    const VvArgs A = vv_args(c, phase, dt, inv_mass, fx, fy, fz, x, y, z, vx, vy, vz, ekin);
+    const int nb = (int)div_up(c->N, kVvBlock);
     const IonArgs I{};
+    const ForceFinalizeArgs F{};
     if (phase == 0) {
-        if (nb > 0) hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I);
+        if (nb > 0)
+            hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F);
         hipLaunchKernelGGL((k_vv_finalize<0>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
     } else if (ekin) {
-        if (nb > 0) hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A, I);
+        if (nb > 0)
+            hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F);
         hipLaunchKernelGGL((k_vv_finalize<1>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
     } else if (nb > 0) {
-        hipLaunchKernelGGL((k_vv<1, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I);
+        hipLaunchKernelGGL((k_vv<1, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F);
+    }
+}
+
+void launch_vv1_finalize(Ctx* c, double dt, const double* inv_mass, const double* fx,
+                         const double* fy, const double* fz, double* vx, double* vy, double* vz,
+                         double* ekin, double* epot, hipStream_t st)
+{
+    VvArgs A = vv_args(c, 1, dt, inv_mass, fx, fy, fz, nullptr, nullptr, nullptr, vx, vy, vz,
+                       ekin);
+    const int nb = (int)div_up(c->N, kVvBlock);
+    const IonArgs I{};
+    const ForceFinalizeArgs F = force_finalize_args(c, epot);
+    if (ekin) {
+        hipLaunchKernelGGL((k_vv<1, true, false, true>), dim3(nb + 1), dim3(kVvBlock), 0, st, A,
+                           I, F);
+        hipLaunchKernelGGL((k_vv_finalize<1>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
+    } else {
+        hipLaunchKernelGGL((k_vv<1, false, false, true>), dim3(nb + 1), dim3(kVvBlock), 0, st, A,
+                           I, F);
     }
 }
 
@@ -378,21 +415,11 @@ void launch_vv0_ionize(Ctx* c, double dt, const double* inv_mass, const double* 
                        double* vx, double* vy, double* vz, const uint8_t* elem,
                        const uint32_t* atom_id, int8_t* q, hipStream_t st)
 {
-    VvArgs A;
-    A.N = c->N; A.dt = dt; A.hdt = 0.5 * dt;
-    const double half_skin = 0.5 * c->cfg.skin;
-    A.thr2 = half_skin * half_skin;
-    A.inv_mass = inv_mass; A.fx = fx; A.fy = fy; A.fz = fz;
-    A.x = x; A.y = y; A.z = z; A.vx = vx; A.vy = vy; A.vz = vz;
-    A.xref = c->d_xref; A.partial = c->d_partial; A.ekin = nullptr;
+    const VvArgs A = vv_args(c, 0, dt, inv_mass, fx, fy, fz, x, y, z, vx, vy, vz, nullptr);
     const int nb = (int)div_up(c->N, kVvBlock);
-    A.disp_partial = c->d_partial + nb + c->B + 1;
-    A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
-    A.fast_flag = c->d_fast_flag; A.fast_loc = c->d_fast_loc; A.fast_cnt = c->d_fast_cnt;
-    A.fast_list = c->d_fast_list; A.fast_cap = c->fast_cap;
     if (nb > 0)
         hipLaunchKernelGGL((k_vv<0, false, true>), dim3(nb), dim3(kVvBlock), 0, st, A,
-                           ion_args(c, elem, atom_id, q));
+                           ion_args(c, elem, atom_id, q), ForceFinalizeArgs{});
 }
 
 int vv_blocks(int64_t N) { return (int)div_up(N, kVvBlock); }
