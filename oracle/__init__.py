@@ -63,6 +63,9 @@ def lib():
             L.orc_ionize.argtypes = [i64, P, P, P, P, P, i32, P, P, P, i64]
             L.orc_ionize.restype = i64
             L.orc_vv.argtypes = [i64, i32, f64, P, P, P, P, P, P, P, P, P, P]
+            L.orc_langevin_normals.argtypes = [ctypes.c_uint32, i64, i64, ctypes.c_uint64, P]
+            L.orc_vv_langevin.argtypes = [i64, P, P, i32, P, P, P, i64, i64, P, f64, P, P, P, P,
+                                          P, P, P, P, P, P]
             L.orc_ekin.argtypes = [i64, P, P, P, P, P, P]
             _lib = L
     return _lib
@@ -213,6 +216,32 @@ def vv(phase, dt, inv_mass, f, pos, vel):
     lib().orc_vv(pos[0].shape[0], int(phase), float(dt), _p(_c(inv_mass, np.float64)),
                  _p(fx), _p(fy), _p(fz), _p(pos[0]), _p(pos[1]), _p(pos[2]), _p(vel[0]),
                  _p(vel[1]), _p(vel[2]))
+
+
+def langevin_normals(atom_id, step, system, seed) -> np.ndarray:
+    out = np.empty(3)
+    lib().orc_langevin_normals(int(atom_id), int(step), int(system), int(seed), _p(out))
+    return out
+
+
+def langevin_c1(gamma, dt) -> np.ndarray:
+    """c1 = exp(-gamma dt) per (system, element): the table the library computes too."""
+    return np.exp(-np.asarray(gamma, dtype=np.float64) * dt)
+
+
+def vv_langevin(sys, step, c1, kt, f, pos, vel):
+    """Phase 0 with the Langevin coupling (in place); c1 [B, E], kt [B, S+1] in kJ/mol."""
+    fx, fy, fz = (_c(a, np.float64) for a in f)
+    for a in (*pos, *vel):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    c1 = _c(c1, np.float64)
+    kt = _c(kt, np.float64)
+    lib().orc_vv_langevin(sys.n_systems, _p(_c(sys.sys_offsets, np.int64)),
+                          _p(_c(sys.elem, np.uint8)), int(c1.shape[1]),
+                          _p(_c(sys.atom_id, np.uint32)), _p(c1), _p(kt), int(kt.shape[1]),
+                          int(step), _p(_c(sys.seeds, np.uint64)), float(sys.dt),
+                          _p(_c(sys.inv_mass, np.float64)), _p(fx), _p(fy), _p(fz), _p(pos[0]),
+                          _p(pos[1]), _p(pos[2]), _p(vel[0]), _p(vel[1]), _p(vel[2]))
 
 
 def ekin(sys, vx, vy, vz) -> np.ndarray:

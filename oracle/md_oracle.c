@@ -31,6 +31,9 @@
  *    stochastic charges average to the CR fractions).
  *  - Velocity-Verlet integration of Newton's equation (section II.B, Eq. 12;
  *    the paper uses leap-frog, which yields the same positions).
+ *  - Langevin coupling of the ions to the free electrons (section II.B, Eq. 13-14):
+ *    friction and a random force of matching variance, integrated exactly over a
+ *    step between two half drifts (a reading: the paper gives no discretization).
  *
  * Philox4x32-10 follows its published definition (Salmon, Moraes, Dror, Shaw,
  * "Parallel random numbers: as easy as 1, 2, 3", SC'11).
@@ -358,6 +361,68 @@ void orc_vv(int64_t n, int32_t phase, double dt, const double* inv_mass, const d
             x[a] = x[a] + dt * vx[a];
             y[a] = y[a] + dt * vy[a];
             z[a] = z[a] + dt * vz[a];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Langevin electron-ion coupling (section II.B, Eq. 13 and Eq. 14)          */
+/* ------------------------------------------------------------------------ */
+
+/* Three standard normals for atom `atom_id` of system b at step s: Philox4x32-10
+ * with counter (atom_id, s, b, 1) and key (seed low, seed high), Box-Muller in FP64
+ * on output words (0, 1) and (2, 3) with u = (w + 1/2) 2^-32:
+ * z = sqrt(-2 ln u_a) cos(2 pi u_b), sqrt(-2 ln u_a) sin(2 pi u_b), and the cosine
+ * of the second pair. */
+void orc_langevin_normals(uint32_t atom_id, int64_t s, int64_t b, uint64_t seed, double z[3])
+{
+    const uint32_t ctr[4] = {atom_id, (uint32_t)s, (uint32_t)b, 1u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    const double two_pi = 6.283185307179586;
+    double u0 = ((double)w[0] + 0.5) * 2.3283064365386963e-10;
+    double u1 = ((double)w[1] + 0.5) * 2.3283064365386963e-10;
+    double u2 = ((double)w[2] + 0.5) * 2.3283064365386963e-10;
+    double u3 = ((double)w[3] + 0.5) * 2.3283064365386963e-10;
+    double r0 = sqrt(-2.0 * log(u0));
+    double r1 = sqrt(-2.0 * log(u2));
+    z[0] = r0 * cos(two_pi * u1);
+    z[1] = r0 * sin(two_pi * u1);
+    z[2] = r1 * cos(two_pi * u3);
+}
+
+/* Phase 0 of the integrator with the coupling, for step s (the step this phase
+ * starts): the friction -m gamma v and the random force of variance 2 m gamma kT
+ * integrated exactly over dt between two half drifts:
+ *   v += h F;  x += (dt/2) v;  v = c1 v + sqrt(kT (1 - c1^2) / m) z;  x += (dt/2) v,
+ * with h = (dt/2)/m, c1 = c1_tab[b * E + e] (= exp(-gamma dt), tabulated by the caller)
+ * and kT = kt[b * S1 + s] (k_B T_e in kJ/mol).  Phase 1 is the plain kick. */
+void orc_vv_langevin(int64_t n_sys, const int64_t* sys_off, const uint8_t* elem, int32_t E,
+                     const uint32_t* atom_id, const double* c1_tab, const double* kt, int64_t S1,
+                     int64_t s, const uint64_t* seeds, double dt, const double* inv_mass,
+                     const double* fx, const double* fy, const double* fz, double* x, double* y,
+                     double* z, double* vx, double* vy, double* vz)
+{
+    double hdt = 0.5 * dt;
+    for (int64_t b = 0; b < n_sys; ++b) {
+        double kT = kt[b * S1 + s];
+        for (int64_t a = sys_off[b]; a < sys_off[b + 1]; ++a) {
+            double h = hdt * inv_mass[a];
+            double c1 = c1_tab[b * E + elem[a]];
+            double sig = sqrt(kT * (1.0 - c1 * c1) * inv_mass[a]);
+            double g[3];
+            orc_langevin_normals(atom_id[a], s, b, seeds[b], g);
+            double v[3] = {vx[a] + h * fx[a], vy[a] + h * fy[a], vz[a] + h * fz[a]};
+            double* p[3] = {&x[a], &y[a], &z[a]};
+            for (int d = 0; d < 3; ++d) {
+                *p[d] = *p[d] + hdt * v[d];
+                v[d] = c1 * v[d] + sig * g[d];
+                *p[d] = *p[d] + hdt * v[d];
+            }
+            vx[a] = v[0];
+            vy[a] = v[1];
+            vz[a] = v[2];
         }
     }
 }
