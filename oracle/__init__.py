@@ -12,6 +12,7 @@ paper's order (ionize, screened forces, integrate).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 import threading
@@ -225,8 +226,9 @@ def langevin_normals(atom_id, step, system, seed) -> np.ndarray:
 
 
 def langevin_c1(gamma, dt) -> np.ndarray:
-    """c1 = exp(-gamma dt) per (system, element): the table the library computes too."""
-    return np.exp(-np.asarray(gamma, dtype=np.float64) * dt)
+    """c1 = exp(-gamma dt) per (system, element), with the C library's exp."""
+    g = np.asarray(gamma, dtype=np.float64)
+    return np.array([math.exp(-v * dt) for v in g.reshape(-1)]).reshape(g.shape)
 
 
 def vv_langevin(sys, step, c1, kt, f, pos, vel):
