@@ -227,7 +227,9 @@ typedef struct md_step_args {
 
 /* One full step in the order of the method: md_integrate_vv phase 0 (kick + drift,
  * step counter s = k + 1), md_ionize_step (step s), md_build_cells(build_mode),
- * md_screened_forces (kappa of step s), md_integrate_vv phase 1 (kick).  The forces
+ * md_screened_forces (kappa of step s), md_integrate_vv phase 1 (kick); while the
+ * Langevin coupling is bound, md_integrate_langevin replaces phase 0 (args->dt must
+ * then equal the bound dt, else MD_ERR_ARG).  The forces
  * in fx, fy, fz must be those of the current positions on entry (call
  * md_screened_forces once before the first step).  Asynchronous. */
 md_status md_step(md_ctx* ctx, const md_step_args* args, int32_t build_mode, md_stream stream);
@@ -236,7 +238,8 @@ md_status md_step(md_ctx* ctx, const md_step_args* args, int32_t build_mode, md_
  * `stream` (not the null stream) into an executable graph, without executing it.
  * Replaying it runs the step with no host work; the step counter, schedules,
  * random streams and (with MD_BUILD_AUTO) list rebuilds advance on the device.
- * The pointers in args are baked into the graph. */
+ * The pointers in args, and whether the Langevin coupling is bound, are baked into
+ * the graph (the coupling's tables are read at replay time). */
 typedef struct md_graph md_graph;
 md_status md_graph_create(md_ctx* ctx, const md_step_args* args, int32_t build_mode,
                           md_stream stream, md_graph** out);
@@ -270,6 +273,31 @@ typedef struct md_stats {
 
 /* Synchronize `stream` and report build statistics. */
 md_status md_get_stats(md_ctx* ctx, md_stats* out, md_stream stream);
+
+/* Langevin electron-ion coupling (section II.B, Eq. 13 and Eq. 14): friction
+ * -m gamma v and a Gaussian random force with <f(t) f(t')> = 2 m gamma k_B T_e delta(t - t')
+ * on every atom.  Binds HOST tables: gamma [B*E] (ps^-1, per system and element; the
+ * paper's gamma = rho_N g_e-ion, constant over a run), kt [B*(S+1)] (k_B T_e in kJ/mol per
+ * system and step, read every step), and the time step dt they will be used with (the
+ * library tabulates c1 = exp(-gamma dt)).  gamma NULL unbinds; md_bind_tables unbinds
+ * too (the step count may change).  Errors: MD_ERR_STATE before md_bind_tables,
+ * MD_ERR_ARG for kt NULL, dt not finite and > 0, or a gamma or kt entry negative or
+ * not finite.  Synchronous. */
+md_status md_bind_langevin(md_ctx* ctx, const double* gamma, const double* kt, double dt);
+
+/* Phase 0 of the integrator with the coupling bound by md_bind_langevin (a reading:
+ * the paper gives no discretization): for the step s = k + 1 this phase starts,
+ *   v += h F;  x += (dt/2) v;  v = c1 v + sqrt(kT (1 - c1^2) / m) z;  x += (dt/2) v,
+ * then the step counter advances as in md_integrate_vv phase 0 (displacement
+ * tracking included).  z: three normals from Philox4x32-10 with counter
+ * (atom_id, s, b, 1) and key (seed low, high), Box-Muller in FP64 on words (0, 1) and
+ * (2, 3) with u = (w + 1/2) 2^-32.  elem: uint8 [N]; atom_id: uint32 [N]; the other
+ * arrays as in md_integrate_vv.  dt must equal the bound one.  md_step uses this phase
+ * automatically while the coupling is bound.  Asynchronous. */
+md_status md_integrate_langevin(md_ctx* ctx, double dt, const double* inv_mass,
+                                const uint8_t* elem, const uint32_t* atom_id, const double* fx,
+                                const double* fy, const double* fz, double* x, double* y,
+                                double* z, double* vx, double* vy, double* vz, md_stream stream);
 
 /* Host helpers for the per-step schedules (FP64, no device work). */
 

@@ -56,7 +56,8 @@ void free_all(Ctx* c)
                     c->d_cl_nt, c->d_cl_len, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_qs,
                     c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
                     c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
-                    c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive};
+                    c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
+                    c->d_lg_c1, c->d_lg_kt};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -547,6 +548,57 @@ md_status md_integrate_vv(md_ctx* ctx, int32_t phase, double dt, const double* i
     return MD_OK;
 }
 
+md_status md_bind_langevin(md_ctx* ctx, const double* gamma, const double* kt, double dt)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    if (!gamma) {
+        c->langevin = false;
+        return MD_OK;
+    }
+    if (!kt) return fail(c, MD_ERR_ARG, "kt is NULL");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, MD_ERR_ARG, "dt must be finite and > 0");
+    const int64_t BE = (int64_t)c->B * c->E, BS = (int64_t)c->B * (c->n_steps + 1);
+    std::vector<double> c1((size_t)std::max<int64_t>(BE, 1));
+    for (int64_t i = 0; i < BE; ++i) {
+        if (!(gamma[i] >= 0.0) || !isfinite(gamma[i]))
+            return fail(c, MD_ERR_ARG, "gamma[%lld] must be finite and >= 0", (long long)i);
+        c1[i] = exp(-gamma[i] * dt);
+    }
+    for (int64_t i = 0; i < BS; ++i)
+        if (!(kt[i] >= 0.0) || !isfinite(kt[i]))
+            return fail(c, MD_ERR_ARG, "kt[%lld] must be finite and >= 0", (long long)i);
+    if (!c->d_lg_c1) {
+        HIP_TRY(c, dalloc(&c->d_lg_c1, BE));
+        HIP_TRY(c, dalloc(&c->d_lg_kt, BS));
+    }
+    HIP_TRY(c, hipDeviceSynchronize());      // no step may still read the old tables
+    HIP_TRY(c, hipMemcpy(c->d_lg_c1, c1.data(), sizeof(double) * c1.size(), hipMemcpyHostToDevice));
+    if (BS > 0)
+        HIP_TRY(c, hipMemcpy(c->d_lg_kt, kt, sizeof(double) * BS, hipMemcpyHostToDevice));
+    c->lg_dt = dt;
+    c->langevin = true;
+    return MD_OK;
+}
+
+md_status md_integrate_langevin(md_ctx* ctx, double dt, const double* inv_mass,
+                                const uint8_t* elem, const uint32_t* atom_id, const double* fx,
+                                const double* fy, const double* fz, double* x, double* y,
+                                double* z, double* vx, double* vy, double* vz, md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    if (!c->langevin) return fail(c, MD_ERR_STATE, "Langevin coupling not bound");
+    if (dt != c->lg_dt) return fail(c, MD_ERR_ARG, "dt differs from the bound one");
+    if (null_any({inv_mass, elem, atom_id, fx, fy, fz, x, y, z, vx, vy, vz}) && c->N > 0)
+        return fail(c, MD_ERR_ARG, "NULL array");
+    launch_vv0_langevin(c, dt, inv_mass, elem, atom_id, fx, fy, fz, x, y, z, vx, vy, vz, S(stream));
+    HIP_TRY(c, hipGetLastError());
+    return MD_OK;
+}
+
 md_status md_sync_check(md_ctx* ctx, md_stream stream, uint32_t* flags)
 {
     if (!ctx) return MD_ERR_ARG;
@@ -711,6 +763,8 @@ static md_status step_impl(md_ctx* ctx, const md_step_args* a, int32_t build_mod
             return fail(c, MD_ERR_ARG, "NULL array");
         if (a->prec != MD_FP64 && a->prec != MD_FP32_KAHAN)
             return fail(c, MD_ERR_ARG, "unknown precision");
+        if (c->langevin && a->dt != c->lg_dt)
+            return fail(c, MD_ERR_ARG, "dt differs from the one the coupling was bound with");
         hipStream_t hs = S(st);
         launch_vv0_ionize(c, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y, a->z, a->vx,
                           a->vy, a->vz, a->elem, a->atom_id, a->q, hs);
@@ -724,8 +778,12 @@ static md_status step_impl(md_ctx* ctx, const md_step_args* a, int32_t build_mod
         HIP_TRY(c, hipGetLastError());
         return MD_OK;
     }
-    md_status s = md_integrate_vv(ctx, 0, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x, a->y,
-                                  a->z, a->vx, a->vy, a->vz, nullptr, st);
+    md_status s = c->langevin
+                      ? md_integrate_langevin(ctx, a->dt, a->inv_mass, a->elem, a->atom_id, a->fx,
+                                              a->fy, a->fz, a->x, a->y, a->z, a->vx, a->vy, a->vz,
+                                              st)
+                      : md_integrate_vv(ctx, 0, a->dt, a->inv_mass, a->fx, a->fy, a->fz, a->x,
+                                        a->y, a->z, a->vx, a->vy, a->vz, nullptr, st);
     if (s == MD_OK) s = md_ionize_step(ctx, a->elem, a->atom_id, a->q, st);
     if (s == MD_OK) s = md_build_cells(ctx, a->x, a->y, a->z, a->type, build_mode, st);
     if (s == MD_OK)

@@ -80,6 +80,11 @@ struct Ctx {
     size_t lds_per_cu = 65536;
     size_t force32_static_lds = 8192;
     int bs_blocks = 0;             // grid of the fused build kernel (0: not usable)
+    // Langevin coupling (bound by md_bind_langevin)
+    bool langevin = false;
+    double lg_dt = 0.0;
+    double* d_lg_c1 = nullptr;     // B*E: exp(-gamma dt)
+    double* d_lg_kt = nullptr;     // B*(S+1): k_B T_e, kJ/mol
     int cap_bar = 0;               // arrival words of its barrier
     uint32_t* d_bar_arrive = nullptr;
     // force-kernel launch timer: event pairs recorded around the next t_cap launches

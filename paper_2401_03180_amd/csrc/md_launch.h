@@ -26,6 +26,11 @@ void launch_vv0_ionize(Ctx* c, double dt, const double* inv_mass, const double* 
 void launch_vv1_finalize(Ctx* c, double dt, const double* inv_mass, const double* fx,
                          const double* fy, const double* fz, double* vx, double* vy, double* vz,
                          double* ekin, double* epot, hipStream_t st);
+// phase 0 with the Langevin coupling (md_integrate_langevin)
+void launch_vv0_langevin(Ctx* c, double dt, const double* inv_mass, const uint8_t* elem,
+                         const uint32_t* atom_id, const double* fx, const double* fy,
+                         const double* fz, double* x, double* y, double* z, double* vx,
+                         double* vy, double* vz, hipStream_t st);
 int vv_blocks(int64_t N);
 int vv_block_size();
 void launch_set_step(Ctx* c, int64_t step, hipStream_t st);

@@ -248,11 +248,54 @@ __device__ double block_sum_d(double v, double* s)
     return t;   // valid in thread 0
 }
 
+// Langevin coupling tables and per-atom inputs (phase 0 only).
+struct LgArgs {
+    const double* c1;              // B*E
+    const double* kt;              // B*S1
+    int E;
+    int64_t S1;
+    const uint8_t* elem;
+    const uint32_t* atom_id;
+    const uint64_t* seeds;
+    const int32_t* sys_of_atom;
+};
+
+// Three standard normals for (atom_id, step s, system b): Philox4x32-10 with counter
+// (atom_id, s, b, 1), Box-Muller in FP64 on words (0, 1) and (2, 3).
+__device__ inline void langevin_normals(uint32_t id, uint32_t s, uint32_t b, uint64_t seed,
+                                        double z[3])
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+    uint32_t c0 = id, c1 = s, c2 = b, c3 = 1u;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
+        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
+        const uint32_t n0 = hiB ^ c1 ^ k0;
+        const uint32_t n2 = hiA ^ c3 ^ k1;
+        c0 = n0; c1 = loB; c2 = n2; c3 = loA;
+        k0 += kWeylA; k1 += kWeylB;
+    }
+    const double two_pi = 6.283185307179586;
+    const double scale = 2.3283064365386963e-10;
+    const double u0 = ((double)c0 + 0.5) * scale, u1 = ((double)c1 + 0.5) * scale;
+    const double u2 = ((double)c2 + 0.5) * scale, u3 = ((double)c3 + 0.5) * scale;
+    const double r0 = sqrt(-2.0 * log(u0));
+    const double r1 = sqrt(-2.0 * log(u2));
+    z[0] = r0 * cos(two_pi * u1);
+    z[1] = r0 * sin(two_pi * u1);
+    z[2] = r1 * cos(two_pi * u3);
+}
+
 // IONIZE (phase 0 only): also the ionization of the step this phase starts (the
 // step counter is advanced after this kernel), as md_step issues it.  FIN (phase 1
-// only): one extra work-group runs the force finalize of the step.
-template <int PHASE, bool EKIN, bool IONIZE = false, bool FIN = false>
-__global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinalizeArgs F)
+// only): one extra work-group runs the force finalize of the step.  LANGEVIN (phase
+// 0 only): the drift is split around the exact friction + noise velocity update.
+template <int PHASE, bool EKIN, bool IONIZE = false, bool FIN = false, bool LANGEVIN = false>
+__global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinalizeArgs F,
+                                                 LgArgs L)
 {
 #pragma clang fp contract(off)
     __shared__ double s_red[kVvBlock / 64];
@@ -272,12 +315,35 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinal
         double vx = A.vx[a] + h * A.fx[a];
         double vy = A.vy[a] + h * A.fy[a];
         double vz = A.vz[a] + h * A.fz[a];
+        if (PHASE == 0 && LANGEVIN) {
+            const int b = L.sys_of_atom[a];
+            const int64_t s = A.dsc->step + 1;
+            const int64_t sk = s < 0 ? 0 : (s >= L.S1 ? L.S1 - 1 : s);
+            const double c1 = L.c1[b * L.E + L.elem[a]];
+            const double sig = sqrt(L.kt[b * L.S1 + sk] * (1.0 - c1 * c1) * A.inv_mass[a]);
+            double g[3];
+            langevin_normals(L.atom_id[a], (uint32_t)s, (uint32_t)b, L.seeds[b], g);
+            double p[3] = {A.x[a], A.y[a], A.z[a]};
+            double v[3] = {vx, vy, vz};
+            for (int d = 0; d < 3; ++d) {
+                p[d] = p[d] + A.hdt * v[d];
+                v[d] = c1 * v[d] + sig * g[d];
+                p[d] = p[d] + A.hdt * v[d];
+            }
+            vx = v[0]; vy = v[1]; vz = v[2];
+            A.x[a] = p[0]; A.y[a] = p[1]; A.z[a] = p[2];
+        }
         A.vx[a] = vx; A.vy[a] = vy; A.vz[a] = vz;
         if (PHASE == 0) {
-            const double x = A.x[a] + A.dt * vx;
-            const double y = A.y[a] + A.dt * vy;
-            const double z = A.z[a] + A.dt * vz;
-            A.x[a] = x; A.y[a] = y; A.z[a] = z;
+            double x, y, z;
+            if (LANGEVIN) {
+                x = A.x[a]; y = A.y[a]; z = A.z[a];
+            } else {
+                x = A.x[a] + A.dt * vx;
+                y = A.y[a] + A.dt * vy;
+                z = A.z[a] + A.dt * vz;
+                A.x[a] = x; A.y[a] = y; A.z[a] = z;
+            }
             const double ex = x - A.xref[a], ey = y - A.xref[A.N + a], ez = z - A.xref[2 * A.N + a];
             d2 = ex * ex + ey * ey + ez * ez;
             A.fast_flag[a] = d2 > A.thr2 ? 1 : 0;
@@ -350,6 +416,12 @@ __global__ void __launch_bounds__(kVvBlock) k_vv_finalize(VvArgs A, int nblocks)
     }
 }
 
+static LgArgs lg_args(Ctx* c, const uint8_t* elem, const uint32_t* atom_id)
+{
+    return LgArgs{c->d_lg_c1, c->d_lg_kt, c->E, c->n_steps + 1, elem, atom_id, c->d_seeds,
+                  c->d_sys_of_atom};
+}
+
 static VvArgs vv_args(Ctx* c, int phase, double dt, const double* inv_mass, const double* fx,
                       const double* fy, const double* fz, double* x, double* y, double* z,
                       double* vx, double* vy, double* vz, double* ekin)
@@ -378,16 +450,17 @@ void launch_vv(Ctx* c, int phase, double dt, const double* inv_mass, const doubl
     const int nb = (int)div_up(c->N, kVvBlock);
     const IonArgs I{};
     const ForceFinalizeArgs F{};
+    const LgArgs L{};
     if (phase == 0) {
         if (nb > 0)
-            hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F);
+            hipLaunchKernelGGL((k_vv<0, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F, L);
         hipLaunchKernelGGL((k_vv_finalize<0>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
     } else if (ekin) {
         if (nb > 0)
-            hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F);
+            hipLaunchKernelGGL((k_vv<1, true>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F, L);
         hipLaunchKernelGGL((k_vv_finalize<1>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
     } else if (nb > 0) {
-        hipLaunchKernelGGL((k_vv<1, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F);
+        hipLaunchKernelGGL((k_vv<1, false>), dim3(nb), dim3(kVvBlock), 0, st, A, I, F, L);
     }
 }
 
@@ -400,13 +473,14 @@ void launch_vv1_finalize(Ctx* c, double dt, const double* inv_mass, const double
     const int nb = (int)div_up(c->N, kVvBlock);
     const IonArgs I{};
     const ForceFinalizeArgs F = force_finalize_args(c, epot);
+    const LgArgs L{};
     if (ekin) {
         hipLaunchKernelGGL((k_vv<1, true, false, true>), dim3(nb + 1), dim3(kVvBlock), 0, st, A,
-                           I, F);
+                           I, F, L);
         hipLaunchKernelGGL((k_vv_finalize<1>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
     } else {
         hipLaunchKernelGGL((k_vv<1, false, false, true>), dim3(nb + 1), dim3(kVvBlock), 0, st, A,
-                           I, F);
+                           I, F, L);
     }
 }
 
@@ -417,9 +491,27 @@ void launch_vv0_ionize(Ctx* c, double dt, const double* inv_mass, const double* 
 {
     const VvArgs A = vv_args(c, 0, dt, inv_mass, fx, fy, fz, x, y, z, vx, vy, vz, nullptr);
     const int nb = (int)div_up(c->N, kVvBlock);
-    if (nb > 0)
+    if (nb <= 0) return;
+    if (c->langevin)
+        hipLaunchKernelGGL((k_vv<0, false, true, false, true>), dim3(nb), dim3(kVvBlock), 0, st, A,
+                           ion_args(c, elem, atom_id, q), ForceFinalizeArgs{},
+                           lg_args(c, elem, atom_id));
+    else
         hipLaunchKernelGGL((k_vv<0, false, true>), dim3(nb), dim3(kVvBlock), 0, st, A,
-                           ion_args(c, elem, atom_id, q), ForceFinalizeArgs{});
+                           ion_args(c, elem, atom_id, q), ForceFinalizeArgs{}, LgArgs{});
+}
+
+void launch_vv0_langevin(Ctx* c, double dt, const double* inv_mass, const uint8_t* elem,
+                         const uint32_t* atom_id, const double* fx, const double* fy,
+                         const double* fz, double* x, double* y, double* z, double* vx,
+                         double* vy, double* vz, hipStream_t st)
+{
+    const VvArgs A = vv_args(c, 0, dt, inv_mass, fx, fy, fz, x, y, z, vx, vy, vz, nullptr);
+    const int nb = (int)div_up(c->N, kVvBlock);
+    if (nb > 0)
+        hipLaunchKernelGGL((k_vv<0, false, false, false, true>), dim3(nb), dim3(kVvBlock), 0, st,
+                           A, IonArgs{}, ForceFinalizeArgs{}, lg_args(c, elem, atom_id));
+    hipLaunchKernelGGL((k_vv_finalize<0>), dim3(1), dim3(kVvBlock), 0, st, A, nb);
 }
 
 int vv_blocks(int64_t N) { return (int)div_up(N, kVvBlock); }

@@ -30,7 +30,7 @@ EXPORTED = (
     "md_build_cells", "md_ionize_step", "md_screened_forces",
     "md_integrate_vv", "md_sync_check", "md_clear_flags", "md_debug_pairs", "md_get_stats",
     "md_force_timer_start", "md_force_timer_read", "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
-    "md_rates_from_fractions",
+    "md_rates_from_fractions", "md_bind_langevin", "md_integrate_langevin",
 )
 
 
@@ -97,6 +97,8 @@ def lib():
             "md_graph_create": [P, P, i32, P, P], "md_graph_launch": [P, P],
             "md_graph_destroy": [P], "md_debye_length_nm": [f64, f64],
             "md_rates_from_fractions": [i64, i32, P, P],
+            "md_bind_langevin": [P, P, P, f64],
+            "md_integrate_langevin": [P, f64, P, P, P, P, P, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -184,6 +186,24 @@ def md_integrate_vv(ctx, phase, dt, inv_mass, fx, fy, fz, x, y, z, vx, vy, vz, e
     _check(ctx, lib().md_integrate_vv(ctx, int(phase), float(dt), _ptr(inv_mass), _ptr(fx),
                                       _ptr(fy), _ptr(fz), _ptr(x), _ptr(y), _ptr(z), _ptr(vx),
                                       _ptr(vy), _ptr(vz), _ptr(ekin), _stream(stream)))
+
+
+def md_bind_langevin(ctx, gamma, kt, dt):
+    """gamma: host [B, E] ps^-1 (None unbinds); kt: host [B, S+1] kJ/mol."""
+    if gamma is None:
+        _check(ctx, lib().md_bind_langevin(ctx, None, None, float(dt)))
+        return
+    g = np.ascontiguousarray(gamma, dtype=np.float64)
+    k = np.ascontiguousarray(kt, dtype=np.float64)
+    _check(ctx, lib().md_bind_langevin(ctx, g.ctypes.data, k.ctypes.data, float(dt)))
+
+
+def md_integrate_langevin(ctx, dt, inv_mass, elem, atom_id, fx, fy, fz, x, y, z, vx, vy, vz,
+                          stream=None):
+    _check(ctx, lib().md_integrate_langevin(ctx, float(dt), _ptr(inv_mass), _ptr(elem),
+                                            _ptr(atom_id), _ptr(fx), _ptr(fy), _ptr(fz), _ptr(x),
+                                            _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz),
+                                            _stream(stream)))
 
 
 def md_sync_check(ctx, stream=None, raise_on_flags=True) -> int:
@@ -340,6 +360,19 @@ class Engine:
         md_integrate_vv(self.ctx, phase, self.sys.dt, self.inv_mass, self.fx, self.fy, self.fz,
                         self.x, self.y, self.z, self.vx, self.vy, self.vz,
                         self.ekin if ekin else None, stream)
+
+    def bind_langevin(self, gamma, kt):
+        """Bind (or, with gamma None, unbind) the electron-ion coupling; graphs captured
+        before run the previous integrator and are dropped."""
+        for g in self.graphs.values():
+            md_graph_destroy(g)
+        self.graphs = {}
+        md_bind_langevin(self.ctx, gamma, kt, self.sys.dt)
+
+    def langevin(self, stream=None):
+        md_integrate_langevin(self.ctx, self.sys.dt, self.inv_mass, self.elem, self.atom_id,
+                              self.fx, self.fy, self.fz, self.x, self.y, self.z, self.vx,
+                              self.vy, self.vz, stream)
 
     def step_args(self, energy=True, ekin=True):
         a = md_step_args()

@@ -457,6 +457,26 @@ def methane_clusters(n_clusters: int = 256, n_steps: int = 2000, lo: int = 1000,
                    "%d vacuum CH4 clusters, %d atoms" % (n_clusters, pos.shape[0]))
 
 
+EV_KJ_PER_MOL = 96.48533212      # 1 eV per particle in kJ/mol
+
+
+def langevin_inputs(sys: System, gamma_ps=None, te0_ev: float = 0.0259,
+                    te_peak_ev: float = 30.0):
+    """Synthetic electron-ion coupling inputs (the paper takes them from the CR code):
+    gamma [B, E] in ps^-1, one constant value per element (default 2 ps^-1 for the
+    heaviest element, 5 ps^-1 for the rest: equilibration over hundreds of fs), and
+    k_B T_e [B, S+1] in kJ/mol, rising from te0 to te_peak with the running integral of
+    each system's pulse envelope g."""
+    E = sys.n_elements
+    if gamma_ps is None:
+        gamma_ps = [2.0 if e == 0 else 5.0 for e in range(E)]
+    gamma = np.tile(np.asarray(gamma_ps, dtype=np.float64)[None, :E], (sys.n_systems, 1))
+    cum = np.cumsum(sys.g, axis=1)
+    frac = cum / np.maximum(cum[:, -1:], 1e-300)
+    te = te0_ev + (te_peak_ev - te0_ev) * frac
+    return np.ascontiguousarray(gamma), np.ascontiguousarray(te * EV_KJ_PER_MOL)
+
+
 CONFIGS = {
     "water_1536": water_small,
     "water_98304": water_pulse,
