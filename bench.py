@@ -53,7 +53,7 @@ STATE = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q")
 
 
 def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_graph=True,
-            fast_capacity=0):
+            fast_capacity=0, langevin=None):
     """Timed region: `steps` replays of the captured step graph (or, with use_graph
     False, `steps` eager md_step calls), inputs resident.
     Then the same steps are replayed eagerly from a snapshot of the state at the
@@ -61,11 +61,14 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
     deterministic, so the eager replay launches exactly the kernels of the timed
     region (checked: identical final state and rebuild count) and gives the
     duration of every force-kernel launch.  Pair counts are sampled between steps
-    of the replay (where no list rebuild is pending)."""
+    of the replay (where no list rebuild is pending).  langevin: (gamma, kt) tables
+    of the electron-ion coupling, bound for the whole run, or None."""
     import torch
     from paper_2401_03180_amd import md
     eng = md.Engine(sys_, prec, cluster_group=cluster_group, skin=skin,
                     fast_capacity=fast_capacity)
+    if langevin is not None:
+        eng.bind_langevin(*langevin)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         eng.set_step(0, stream)
@@ -133,7 +136,7 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
             "step": step_end}
 
 
-def run_gpu_per_system(sys_, prec, steps, warmup):
+def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None):
     """The plain form for batched workloads: every system in a context of its own,
     its step replayed as its own graph, systems one after another on one stream."""
     import torch
@@ -144,6 +147,8 @@ def run_gpu_per_system(sys_, prec, steps, warmup):
         for b in range(sys_.n_systems):
             sb = sys_.subsystem(b)
             e = md.Engine(sb, prec)
+            if langevin is not None:
+                e.bind_langevin(langevin[0][b:b + 1], langevin[1][b:b + 1])
             e.set_step(0, stream)
             e.build(md.MD_BUILD_FORCE, stream)
             e.forces(energy=True, stream=stream)
@@ -170,12 +175,22 @@ def run_gpu_per_system(sys_, prec, steps, warmup):
     return {"ms": ms, "flags": flags}
 
 
-def cpu_baseline(sys_, target_s=12.0, threads=None):
+def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None):
     """The oracle, as it stands: whole steps (all-pairs FP64 force rows of every atom,
-    ionization and both velocity-Verlet half steps) repeated until about target_s
+    ionization and both velocity-Verlet half steps, phase 0 with the electron-ion
+    coupling when langevin = (gamma, kt) is given) repeated until about target_s
     seconds of work; when one step alone would exceed that, the force rows of a random
     subset of atoms are timed and scaled to all atoms."""
     import oracle
+    if langevin is not None:
+        c1 = oracle.langevin_c1(langevin[0], sys_.dt)
+
+    def phase0(s, F, pos, vel):
+        if langevin is None:
+            oracle.vv(0, sys_.dt, sys_.inv_mass, F, pos, vel)
+        else:
+            oracle.vv_langevin(sys_, s, c1, langevin[1], F, pos, vel)
+
     threads = threads or min(os.cpu_count() or 1, 16)
     n = sys_.n_atoms
     rng = np.random.default_rng(0)
@@ -195,7 +210,7 @@ def cpu_baseline(sys_, target_s=12.0, threads=None):
         while time.perf_counter() - t < target_s and steps < sys_.n_steps:
             steps += 1
             s = steps
-            oracle.vv(0, sys_.dt, sys_.inv_mass, F, pos, vel)
+            phase0(s, F, pos, vel)
             oracle.ionize(sys_, q, s)
             out = oracle.forces_rows(sys_, rows, q=q, x=pos[0], y=pos[1], z=pos[2],
                                      kappa=oracle.kappa_from_lambda(sys_.lambda_d[:, s]),
@@ -213,7 +228,7 @@ def cpu_baseline(sys_, target_s=12.0, threads=None):
     oracle.forces_rows(sys_, rows, kappa=kap, n_threads=threads)
     t_rows = time.perf_counter() - t
     t = time.perf_counter()
-    oracle.vv(0, sys_.dt, sys_.inv_mass, F, pos, vel)
+    phase0(1, F, pos, vel)
     oracle.ionize(sys_, q, 1)
     oracle.vv(1, sys_.dt, sys_.inv_mass, F, pos, vel)
     t_elem = time.perf_counter() - t
@@ -263,6 +278,9 @@ def main():
     ap.add_argument("--no-tuned", action="store_true", help="ignore the cached configuration")
     ap.add_argument("--eager", action="store_true",
                     help="launch the step kernels one by one instead of replaying a graph")
+    ap.add_argument("--langevin", action="store_true",
+                    help="bind the electron-ion coupling (synthetic gamma per element and "
+                         "electron-temperature schedule) for every run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -308,10 +326,14 @@ def main():
         return k
 
     sys32 = make_system(a.config, S)
+    lg = None
+    if a.langevin:
+        from paper_2401_03180_amd import synth
+        lg = synth.langevin_inputs(sys32)
     k32 = knobs(md.MD_FP32_KAHAN)
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
     r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
-                  use_graph=not a.eager, fast_capacity=k32["fast_capacity"])
+                  use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg)
     log("fp32", {k: v for k, v in r32.items() if k != "stats"})
     n = sys32.n_atoms
     value = n * a.steps / (r32["ms"] * 1e-3)
@@ -331,7 +353,7 @@ def main():
         sys64 = make_system(a.config, S)
         if sys64.n_systems > 1:
             # batched workloads: the plain FP64 form runs one system per context and launch
-            r64 = run_gpu_per_system(sys64, md.MD_FP64, a.steps, a.warmup)
+            r64 = run_gpu_per_system(sys64, md.MD_FP64, a.steps, a.warmup, langevin=lg)
             v64 = n * a.steps / (r64["ms"] * 1e-3)
             extra.update({"fp64_per_system_value": v64,
                           "fp64_per_system_ms_per_step": r64["ms"] / a.steps,
@@ -341,7 +363,7 @@ def main():
         else:
             k64 = knobs(md.MD_FP64)
             r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, k64["cluster_group"], k64["skin"],
-                          use_graph=not a.eager, fast_capacity=k64["fast_capacity"])
+                          use_graph=not a.eager, fast_capacity=k64["fast_capacity"], langevin=lg)
             log("fp64", {k: v for k, v in r64.items() if k != "stats"})
             v64 = n * a.steps / (r64["ms"] * 1e-3)
             extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
@@ -367,11 +389,11 @@ def main():
                       "skin_nm": k32["skin"] if k32["skin"] is not None else sys32.skin,
                       "cluster_group": r32["stats"]["cluster_group"],
                       "fast_capacity": k32["fast_capacity"], "tuned": k32["tuned"],
-                      "systems": sys32.n_systems,
+                      "systems": sys32.n_systems, "langevin": lg is not None,
                       "launch": "eager" if a.eager else "graph", "parallelism": "single-gpu"},
            "roofline": roofline, "extra": extra}
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sys32)
+        out["cpu_baseline"] = cpu_baseline(sys32, langevin=lg)
     print(json.dumps(out), flush=True)
 
 
