@@ -51,10 +51,10 @@ def lib():
             L.orc_debye_length_nm.restype = f64
             L.orc_rates_from_fractions.argtypes = [i64, i32, P, P]
             L.orc_forces.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i32, P, P, P, i32,
-                                     P, P, P, P, P, P]
+                                     P, P, P, P, P, P, P, i32]
             L.orc_forces.restype = i64
             L.orc_forces_rows.argtypes = [i64, P, P, P, i32, P, f64, P, P, P, P, P, i32, P, P,
-                                          P, i32, P, P, P, P, P, P, i32]
+                                          P, i32, P, P, P, P, P, P, i32, P, i32]
             L.orc_forces_rows.restype = i64
             L.orc_pairs.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i64]
             L.orc_pairs.restype = i64
@@ -68,6 +68,8 @@ def lib():
             L.orc_vv_langevin.argtypes = [i64, P, P, i32, P, P, P, i64, i64, P, f64, P, P, P, P,
                                           P, P, P, P, P, P]
             L.orc_ekin.argtypes = [i64, P, P, P, P, P, P]
+            L.orc_hybrid_coeffs.argtypes = [f64, f64, f64, P]
+            L.orc_hybrid_phi.argtypes = [f64, P, f64, f64, P, P]
             _lib = L
     return _lib
 
@@ -102,11 +104,42 @@ def rates_from_fractions(P) -> np.ndarray:
     return out
 
 
+# ------------------------------------------------------------------ hybrid screening
+
+def hybrid_coeffs(Q, lambda_d, ne) -> np.ndarray:
+    """(r', c1, c2, c3) of the hybrid potential of a charge-Q ion (Eq. 4-7 reading)."""
+    out = np.empty(4)
+    lib().orc_hybrid_coeffs(float(Q), float(lambda_d), float(ne), _p(out))
+    return out
+
+
+def hybrid_phi(Q, h, kappa, r):
+    """(phi, -r dphi/dr) of the hybrid potential with coefficients h at distance r."""
+    h = _c(h, np.float64)
+    phi, w = ctypes.c_double(), ctypes.c_double()
+    lib().orc_hybrid_phi(float(Q), _p(h), float(kappa), float(r), ctypes.byref(phi),
+                         ctypes.byref(w))
+    return phi.value, w.value
+
+
+def hybrid_table(lambda_d, ne, n_q) -> np.ndarray:
+    """[B, n_q, 4] coefficients for charges 0 .. n_q - 1 of every system, from the
+    per-system Debye length and electron density of one force evaluation."""
+    lam = np.atleast_1d(np.asarray(lambda_d, dtype=np.float64))
+    n_e = np.atleast_1d(np.asarray(ne, dtype=np.float64))
+    out = np.zeros((lam.size, n_q, 4))
+    for b in range(lam.size):
+        for Q in range(1, n_q):
+            out[b, Q] = hybrid_coeffs(Q, lam[b], n_e[b])
+    return out
+
+
 # ------------------------------------------------------------------ forces
 
-def forces(sys, q=None, kappa=None, x=None, y=None, z=None, per_atom=True):
+def forces(sys, q=None, kappa=None, x=None, y=None, z=None, per_atom=True, hybrid=None):
     """Brute-force FP64 forces for all systems of ``sys`` at positions (x, y, z)
-    (default: the system's own), charges q and per-system kappa.
+    (default: the system's own), charges q and per-system kappa; ``hybrid`` (a
+    ``hybrid_table``) switches the Coulomb term to the hybrid potential.
     Returns dict(fx, fy, fz, e_atom, a_atom, epot, npairs)."""
     x = _c(sys.x if x is None else x, np.float64)
     y = _c(sys.y if y is None else y, np.float64)
@@ -120,18 +153,30 @@ def forces(sys, q=None, kappa=None, x=None, y=None, z=None, per_atom=True):
     out = {k: np.empty(n) for k in ("fx", "fy", "fz", "e_atom", "a_atom")}
     epot = np.empty(B)
     box = None if sys.box is None else _c(sys.box, np.float64)
+    hyb, n_q = _hyb(hybrid, B, q)
     npairs = lib().orc_forces(B, _p(_c(sys.sys_offsets, np.int64)), int(sys.periodic), _p(box),
                               sys.rc, _p(x), _p(y), _p(z), _p(q),
                               _p(_c(sys.type, np.uint8)), sys.n_types,
                               _p(_c(sys.c6, np.float64)), _p(_c(sys.c12, np.float64)),
                               _p(kappa), int(sys.screen_lj), _p(out["fx"]), _p(out["fy"]),
-                              _p(out["fz"]), _p(out["e_atom"]), _p(out["a_atom"]), _p(epot))
+                              _p(out["fz"]), _p(out["e_atom"]), _p(out["a_atom"]), _p(epot),
+                              _p(hyb), n_q)
     out["epot"] = epot
     out["npairs"] = int(npairs)
     return out
 
 
-def forces_rows(sys, rows, q=None, kappa=None, x=None, y=None, z=None, n_threads=0):
+def _hyb(hybrid, B, q):
+    if hybrid is None:
+        return None, 0
+    h = _c(hybrid, np.float64)
+    assert h.ndim == 3 and h.shape[0] == B and h.shape[2] == 4
+    assert q.size == 0 or (q.min() >= 0 and q.max() < h.shape[1])
+    return h, int(h.shape[1])
+
+
+def forces_rows(sys, rows, q=None, kappa=None, x=None, y=None, z=None, n_threads=0,
+                hybrid=None):
     """F_i, e_i, A_i of the listed atoms against every atom of their system
     (OpenMP over rows)."""
     x = _c(sys.x if x is None else x, np.float64)
@@ -149,13 +194,14 @@ def forces_rows(sys, rows, q=None, kappa=None, x=None, y=None, z=None, n_threads
     out = {k: np.empty(m) for k in ("fx", "fy", "fz", "e_atom", "a_atom")}
     out["row_hits"] = np.empty(m, dtype=np.int64)
     box = None if sys.box is None else _c(sys.box, np.float64)
+    hyb, n_q = _hyb(hybrid, B, q)
     hits = lib().orc_forces_rows(m, _p(rows), _p(sys_of_row), _p(offs), int(sys.periodic),
                                  _p(box), sys.rc, _p(x), _p(y), _p(z), _p(q),
                                  _p(_c(sys.type, np.uint8)), sys.n_types,
                                  _p(_c(sys.c6, np.float64)), _p(_c(sys.c12, np.float64)),
                                  _p(kappa), int(sys.screen_lj), _p(out["fx"]), _p(out["fy"]),
                                  _p(out["fz"]), _p(out["e_atom"]), _p(out["a_atom"]),
-                                 _p(out["row_hits"]), int(n_threads))
+                                 _p(out["row_hits"]), int(n_threads), _p(hyb), n_q)
     out["hits"] = int(hits)
     return out
 

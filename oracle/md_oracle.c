@@ -34,6 +34,11 @@
  *  - Langevin coupling of the ions to the free electrons (section II.B, Eq. 13-14):
  *    friction and a random force of matching variance, integrated exactly over a
  *    step between two half drifts (a reading: the paper gives no discretization).
+ *  - Hybrid ion-sphere / Debye potential (section II.A, Eq. 4-7), a reading: the
+ *    ion-sphere form Q/r + c1 - c2 r^2 inside r', Debye form c3 exp(-r/lambda)/r
+ *    outside, r' from Eq. 7, c1..c3 from matching value, slope and curvature at r';
+ *    the energy of a pair is the mean of (charge j in the potential of ion i) and
+ *    (charge i in the potential of ion j).
  *
  * Philox4x32-10 follows its published definition (Salmon, Moraes, Dror, Shaw,
  * "Parallel random numbers: as easy as 1, 2, 3", SC'11).
@@ -129,6 +134,115 @@ static inline double pair_r2(const orc_geom* g, const double* x, const double* y
     return r2;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Hybrid ion-sphere / Debye potential (section II.A, Eq. 4-7)               */
+/* ------------------------------------------------------------------------ */
+
+/* Coefficients of the potential of one ion of charge Q in an electron gas of
+ * density ne (nm^-3) with Debye length lambda (nm):
+ *   phi(r) = Q/r + c1 - c2 r^2          for r <  r'   (ion sphere, Eq. 5 form)
+ *   phi(r) = c3 exp(-r/lambda) / r      for r >= r'   (Debye, Eq. 2 form)
+ * with the ion-sphere radius R = (3Q / (4 pi ne))^(1/3) (Eq. 4), the transition
+ * radius r' = lambda (((R/lambda)^3 + 1)^(1/3) - 1) (Eq. 7), and c1, c2, c3 the
+ * solution of the three linear conditions that phi, phi' and phi'' agree at r'.
+ * out = {r', c1, c2, c3}.  Q <= 0: no potential (all zero).  lambda = +inf (no
+ * screening): r' = 0 and c3 = Q, the bare Coulomb potential. */
+void orc_hybrid_coeffs(double Q, double lambda, double ne, double out[4])
+{
+    if (!(Q > 0.0)) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        return;
+    }
+    if (isinf(lambda)) {
+        out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; out[3] = Q;
+        return;
+    }
+    const double pi = 3.14159265358979323846;
+    double R = cbrt(3.0 * Q / (4.0 * pi * ne));
+    double a = R / lambda;
+    double rp = lambda * (cbrt(a * a * a + 1.0) - 1.0);
+    double kap = 1.0 / lambda;
+    /* u(r) = exp(-kap r)/r and its first two derivatives at r' */
+    double u0 = exp(-kap * rp) / rp;
+    double t = kap + 1.0 / rp;
+    double u1 = -u0 * t;
+    double u2 = u0 * (t * t + 1.0 / (rp * rp));
+    /* unknowns (c1, c2, c3):
+     *   value:      c1 - rp^2 c2 - u0 c3 = -Q/rp
+     *   slope:         -2 rp c2  - u1 c3 =  Q/rp^2
+     *   curvature:     -2 c2     - u2 c3 = -2Q/rp^3
+     * solved by Gaussian elimination with partial pivoting */
+    double M[3][4] = {{1.0, -rp * rp, -u0, -Q / rp},
+                      {0.0, -2.0 * rp, -u1, Q / (rp * rp)},
+                      {0.0, -2.0, -u2, -2.0 * Q / (rp * rp * rp)}};
+    for (int c = 0; c < 3; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
+        for (int k = 0; k < 4; ++k) {
+            double tmp = M[c][k];
+            M[c][k] = M[p][k];
+            M[p][k] = tmp;
+        }
+        for (int r = c + 1; r < 3; ++r) {
+            double m = M[r][c] / M[c][c];
+            for (int k = c; k < 4; ++k) M[r][k] = M[r][k] - m * M[c][k];
+        }
+    }
+    double x[3];
+    for (int c = 2; c >= 0; --c) {
+        double s = M[c][3];
+        for (int k = c + 1; k < 3; ++k) s = s - M[c][k] * x[k];
+        x[c] = s / M[c][c];
+    }
+    out[0] = rp;
+    out[1] = x[0];
+    out[2] = x[1];
+    out[3] = x[2];
+}
+
+/* The potential phi of an ion of charge Q with coefficients h = {r', c1, c2, c3}
+ * (orc_hybrid_coeffs) at distance r, and w = -r dphi/dr. */
+void orc_hybrid_phi(double Q, const double h[4], double kappa, double r, double* phi, double* w)
+{
+    if (r < h[0]) {
+        *phi = Q / r + h[1] - h[2] * r * r;
+        *w = Q / r + 2.0 * h[2] * r * r;
+    } else {
+        double e = exp(-kappa * r) / r;
+        *phi = h[3] * e;
+        *w = h[3] * e * (1.0 + kappa * r);
+    }
+}
+
+/* Pair energy and scalar force with the hybrid Coulomb term:
+ * phi = k_e (q_j phi_i(r) + q_i phi_j(r)) / 2 + LJ (screened as in Eq. 8). */
+static void pair_phi_f_hybrid(double r2, int qi, int qj, const double* hi, const double* hj,
+                              double c6, double c12, double kappa, int screen_lj, double* phi,
+                              double* f)
+{
+    double r = sqrt(r2);
+    double rinv2 = 1.0 / r2;
+    double rinv6 = rinv2 * rinv2 * rinv2;
+    double s = exp(-kappa * r);
+    double pi_ = 0.0, wi = 0.0, pj = 0.0, wj = 0.0;
+    if (qi > 0) orc_hybrid_phi((double)qi, hi, kappa, r, &pi_, &wi);
+    if (qj > 0) orc_hybrid_phi((double)qj, hj, kappa, r, &pj, &wj);
+    double uc = 0.5 * ORC_KE * ((double)qj * pi_ + (double)qi * pj);
+    double wc = 0.5 * ORC_KE * ((double)qj * wi + (double)qi * wj);
+    double lj12 = c12 * rinv6 * rinv6;
+    double lj6 = c6 * rinv6;
+    double ulj = lj12 - lj6;
+    double wlj = 12.0 * lj12 - 6.0 * lj6;
+    if (screen_lj) {
+        *phi = uc + ulj * s;
+        *f = (wc + (wlj + ulj * (kappa * r)) * s) * rinv2;
+    } else {
+        *phi = uc + ulj;
+        *f = (wc + wlj) * rinv2;
+    }
+}
+
 /* Screened pair energy phi and scalar force f (F_i = f * d, F_j = -f * d). */
 static inline void pair_phi_f(double r2, double qiqj_ke, double c6, double c12,
                               double kappa, int screen_lj, double* phi, double* f)
@@ -161,7 +275,8 @@ int64_t orc_forces(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
                    const double* z, const int8_t* q, const uint8_t* type, int32_t n_types,
                    const double* c6, const double* c12, const double* kappa,
                    int32_t screen_lj, double* fx, double* fy, double* fz,
-                   double* e_atom, double* a_atom, double* epot)
+                   double* e_atom, double* a_atom, double* epot, const double* hyb,
+                   int32_t n_q)
 {
     int64_t npairs = 0;
     int64_t n = sys_off[n_sys];
@@ -183,7 +298,12 @@ int64_t orc_forces(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
                 int tt = type[i] * n_types + type[j];
                 double qq = ORC_KE * ((double)q[i] * (double)q[j]);
                 double phi, f;
-                pair_phi_f(r2, qq, c6[tt], c12[tt], kappa[b], screen_lj, &phi, &f);
+                if (hyb)
+                    pair_phi_f_hybrid(r2, q[i], q[j], hyb + 4 * (b * n_q + q[i]),
+                                      hyb + 4 * (b * n_q + q[j]), c6[tt], c12[tt], kappa[b],
+                                      screen_lj, &phi, &f);
+                else
+                    pair_phi_f(r2, qq, c6[tt], c12[tt], kappa[b], screen_lj, &phi, &f);
                 fx[i] += f * d[0]; fy[i] += f * d[1]; fz[i] += f * d[2];
                 fx[j] -= f * d[0]; fy[j] -= f * d[1]; fz[j] -= f * d[2];
                 if (e_atom) { e_atom[i] += 0.5 * phi; e_atom[j] += 0.5 * phi; }
@@ -211,7 +331,7 @@ int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_
                         const uint8_t* type, int32_t n_types, const double* c6,
                         const double* c12, const double* kappa, int32_t screen_lj,
                         double* fx, double* fy, double* fz, double* e_atom, double* a_atom,
-                        int64_t* row_hits, int32_t n_threads)
+                        int64_t* row_hits, int32_t n_threads, const double* hyb, int32_t n_q)
 {
     int64_t hits = 0;
 #ifdef _OPENMP
@@ -233,7 +353,12 @@ int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_
             int tt = type[i] * n_types + type[j];
             double qq = ORC_KE * ((double)q[i] * (double)q[j]);
             double phi, f;
-            pair_phi_f(r2, qq, c6[tt], c12[tt], kappa[b], screen_lj, &phi, &f);
+            if (hyb)
+                pair_phi_f_hybrid(r2, q[i], q[j], hyb + 4 * (b * n_q + q[i]),
+                                  hyb + 4 * (b * n_q + q[j]), c6[tt], c12[tt], kappa[b], screen_lj,
+                                  &phi, &f);
+            else
+                pair_phi_f(r2, qq, c6[tt], c12[tt], kappa[b], screen_lj, &phi, &f);
             F[0] += f * d[0]; F[1] += f * d[1]; F[2] += f * d[2];
             e += 0.5 * phi;
             a += fabs(f) * sqrt(r2);
