@@ -299,6 +299,25 @@ md_status md_integrate_langevin(md_ctx* ctx, double dt, const double* inv_mass,
                                 const double* fy, const double* fz, double* x, double* y,
                                 double* z, double* vx, double* vy, double* vz, md_stream stream);
 
+/* Hybrid ion-sphere / Debye screening (section II.A, Eq. 4-7; a reading: the paper
+ * gives the form but not the pair rule).  Binds the free-electron density ne
+ * [B*(S+1)] (HOST array, nm^-3, per system and step, > 0) to go with the Debye
+ * lengths of md_bind_tables.  From then on the Coulomb term of every pair is
+ *   k_e (q_j phi_{q_i}(r) + q_i phi_{q_j}(r)) / 2,
+ * where phi_Q is the potential of a charge-Q ion: Q/r + c1 - c2 r^2 inside r' (the
+ * ion-sphere form of Eq. 5), c3 exp(-r/lambda_D)/r outside (the Debye form of
+ * Eq. 2), with R = (3Q / (4 pi ne))^(1/3) (Eq. 4), r' from Eq. 7 and c1, c2, c3
+ * matching value, slope and curvature at r'.  An infinite Debye length leaves the
+ * bare Coulomb term.  The Lennard-Jones term, the cutoff and the pair set are
+ * unchanged.  The library tabulates the coefficients for every (system, step,
+ * charge < n_charge_states) on the host (FP64, and FP32 for the FP32 path).  ne
+ * NULL unbinds; md_bind_tables unbinds too.  Applies to md_screened_forces,
+ * md_step and graphs captured after the call.  Errors: MD_ERR_STATE before
+ * md_bind_tables; MD_ERR_ARG for an ne entry not finite and > 0, or coefficients
+ * that overflow (an ion sphere so large against lambda_D that exp(-r'/lambda_D)
+ * underflows).  Synchronous. */
+md_status md_bind_hybrid(md_ctx* ctx, const double* ne);
+
 /* Host helpers for the per-step schedules (FP64, no device work). */
 
 /* Debye length (section II.A, Eq. 3) in nm for electron temperature te_ev (eV) and

@@ -57,7 +57,7 @@ void free_all(Ctx* c)
                     c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
                     c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
                     c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
-                    c->d_lg_c1, c->d_lg_kt};
+                    c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -382,6 +382,7 @@ md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const
         fresh.sys_off = c->sys_off; fresh.rlist = c->rlist; fresh.device = c->device;
         fresh.n_cu = c->n_cu; fresh.max_lds = c->max_lds; fresh.lds_per_cu = c->lds_per_cu;
         fresh.force32_static_lds = c->force32_static_lds;
+        fresh.force32_static_lds_h = c->force32_static_lds_h;
         *c = fresh;
     }
     c->box.assign(c->cfg.periodic ? box : nullptr, c->cfg.periodic ? box + 3 * B : nullptr);
@@ -390,6 +391,7 @@ md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const
     md_status s = size_and_allocate(c);
     if (s != MD_OK) return s;
     const int64_t S1 = n_steps + 1;
+    c->lambda_d.assign(lambda_d, lambda_d + (size_t)B * S1);
     std::vector<double> kappa((size_t)B * S1);
     for (size_t i = 0; i < kappa.size(); ++i) {
         const double lam = lambda_d[i];
@@ -579,6 +581,72 @@ md_status md_bind_langevin(md_ctx* ctx, const double* gamma, const double* kt, d
         HIP_TRY(c, hipMemcpy(c->d_lg_kt, kt, sizeof(double) * BS, hipMemcpyHostToDevice));
     c->lg_dt = dt;
     c->langevin = true;
+    return MD_OK;
+}
+
+// Coefficients {r', c1, c2, c3} of the hybrid potential of a charge-Q ion (Q >= 1):
+// R from Eq. 4, r' from Eq. 7; eliminating c2 between the slope and curvature
+// conditions at r' gives c3 = 3Q / (r'^3 u0 (t^2 + t/r' + 1/r'^2)) with
+// u0 = exp(-r'/lambda)/r' and t = 1/lambda + 1/r'; the slope condition gives c2 and
+// the value condition c1.  An infinite Debye length leaves the bare charge.
+static void hybrid_coeffs(double Q, double lambda, double ne, double h[4])
+{
+    if (isinf(lambda)) {
+        h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; h[3] = Q;
+        return;
+    }
+    const double R = cbrt(3.0 * Q / (4.0 * M_PI * ne));
+    const double a = R / lambda;
+    const double rp = lambda * (cbrt(a * a * a + 1.0) - 1.0);
+    const double u0 = exp(-rp / lambda) / rp;
+    const double t = 1.0 / lambda + 1.0 / rp;
+    const double c3 = 3.0 * Q / (rp * rp * rp * u0 * (t * t + t / rp + 1.0 / (rp * rp)));
+    const double c2 = (c3 * u0 * t - Q / (rp * rp)) / (2.0 * rp);
+    const double c1 = c3 * u0 - Q / rp + c2 * rp * rp;
+    h[0] = rp; h[1] = c1; h[2] = c2; h[3] = c3;
+}
+
+md_status md_bind_hybrid(md_ctx* ctx, const double* ne)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    if (!ne) {
+        c->hybrid = false;
+        return MD_OK;
+    }
+    const int64_t S1 = c->n_steps + 1, BS = (int64_t)c->B * S1;
+    const int nq = std::max(c->Q, 1);
+    std::vector<double> h64((size_t)std::max<int64_t>(BS * nq * 4, 4), 0.0);
+    std::vector<float4> h32((size_t)std::max<int64_t>(BS * nq, 1));
+    for (int64_t i = 0; i < BS; ++i) {
+        if (!(ne[i] > 0.0) || !isfinite(ne[i]))
+            return fail(c, MD_ERR_ARG, "ne[%lld] must be finite and > 0", (long long)i);
+        for (int q = 1; q < nq; ++q) {
+            double* h = &h64[(size_t)(i * nq + q) * 4];
+            hybrid_coeffs((double)q, c->lambda_d[i], ne[i], h);
+            for (int k = 0; k < 4; ++k)
+                if (!isfinite(h[k]))
+                    return fail(c, MD_ERR_ARG,
+                                "hybrid coefficients not finite at entry %lld, charge %d "
+                                "(lambda_d %.6g nm, ne %.6g nm^-3)",
+                                (long long)i, q, c->lambda_d[i], ne[i]);
+        }
+    }
+    for (size_t k = 0; k < h32.size(); ++k)
+        h32[k] = make_float4((float)h64[4 * k], (float)h64[4 * k + 1], (float)h64[4 * k + 2],
+                             (float)h64[4 * k + 3]);
+    if (!c->d_hyb64) {
+        HIP_TRY(c, dalloc(&c->d_hyb64, (int64_t)h64.size()));
+        HIP_TRY(c, dalloc(&c->d_hyb32, (int64_t)h32.size()));
+    }
+    HIP_TRY(c, hipDeviceSynchronize());      // no step may still read the old tables
+    HIP_TRY(c, hipMemcpy(c->d_hyb64, h64.data(), sizeof(double) * h64.size(),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_hyb32, h32.data(), sizeof(float4) * h32.size(),
+                         hipMemcpyHostToDevice));
+    c->hyb_q = nq;
+    c->hybrid = true;
     return MD_OK;
 }
 

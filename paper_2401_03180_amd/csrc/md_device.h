@@ -67,6 +67,53 @@ __device__ inline bool grid_barrier(GridBarrier& B, DevScalars* d)
     return s_ok != 0;
 }
 
+// Hybrid ion-sphere / Debye potential of an ion of charge Q (section II.A, Eq. 4-7):
+// h = {r', c1, c2, c3}; inside r' the ion-sphere form Q/r + c1 - c2 r^2, outside the
+// Debye form c3 exp(-kappa r)/r (s = exp(-kappa r) is passed in).  Returns phi and
+// w = -r dphi/dr.
+__device__ inline void hyb_phi_w(double Q, const double* h, double kap, double r, double s,
+                                 double& phi, double& w)
+{
+#pragma clang fp contract(off)
+    if (r < h[0]) {
+        phi = Q / r + h[1] - h[2] * r * r;
+        w = Q / r + 2.0 * h[2] * r * r;
+    } else {
+        const double e = s / r;
+        phi = h[3] * e;
+        w = h[3] * e * (1.0 + kap * r);
+    }
+}
+
+// FP64 pair terms with the hybrid Coulomb term k_e (q_b phi_a + q_a phi_b) / 2 and the
+// Lennard-Jones term (screened by exp(-kappa r) when screen_lj): f multiplies
+// d = p_a - p_b for the force on a; e is the pair energy.  hrow: the coefficient rows
+// of charges 0 .. qn - 1 for this system and step.
+__device__ inline void pair_terms_hybrid64(double r2, double kap, int qa, int qb, double c6,
+                                           double c12, bool screen_lj, const double* hrow,
+                                           int qn, double* f, double* e)
+{
+#pragma clang fp contract(off)
+    const double r = sqrt(r2);
+    const double rinv2 = 1.0 / r2;
+    const double rinv6 = rinv2 * rinv2 * rinv2;
+    const double s = exp(-kap * r);
+    double pa = 0.0, wa = 0.0, pb = 0.0, wb = 0.0;
+    if (qa > 0) hyb_phi_w((double)qa, hrow + 4 * min(qa, qn - 1), kap, r, s, pa, wa);
+    if (qb > 0) hyb_phi_w((double)qb, hrow + 4 * min(qb, qn - 1), kap, r, s, pb, wb);
+    const double uc = 0.5 * kKe * ((double)qb * pa + (double)qa * pb);
+    const double wc = 0.5 * kKe * ((double)qb * wa + (double)qa * wb);
+    const double l12 = c12 * rinv6 * rinv6, l6 = c6 * rinv6;
+    const double ulj = l12 - l6, wlj = 12.0 * l12 - 6.0 * l6;
+    if (screen_lj) {
+        *e = uc + ulj * s;
+        *f = (wc + (wlj + ulj * (kap * r)) * s) * rinv2;
+    } else {
+        *e = uc + ulj;
+        *f = (wc + wlj) * rinv2;
+    }
+}
+
 // Sum of v over the block (every thread receives it); s holds one value per wave.
 template <class T>
 __device__ inline T block_sum_all(T v, T* s)

@@ -16,6 +16,7 @@
 //   * fast_nbr: one work-group per column adds, to each non-fast atom of the
 //     column, the forces of the fast atoms within reach, in fast-list order.
 // No atomics on forces: every result is written by one thread in a fixed order.
+#include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
 
@@ -45,6 +46,8 @@ struct FastArgs {
     int T;
     double rc2, reach;             // rc^2; column search radius rc + skin/2
     int screen_lj;
+    const double* hyb64;           // hybrid screening rows (NULL: Debye)
+    int hyb_q;
     const uint8_t* fast_flag;
     const int32_t* fast_list;
     double* fast_e;
@@ -61,10 +64,11 @@ __device__ inline int col_first_cluster(const int64_t* pre, int c)
 
 // Exact membership and FP64 pair terms for d = p_a - p_b (minimum image); returns
 // false when the pair is outside the cutoff.  f multiplies d for the force on a.
-__device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double kap, double xa,
-                                 double ya, double za, int qa, int ta, double xb, double yb,
-                                 double zb, int qb, int tb, double* dx, double* dy, double* dz,
-                                 double* f, double* e)
+// hrow: hybrid-screening coefficient rows of the system and step (NULL: Debye).
+__device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double kap,
+                                 const double* hrow, double xa, double ya, double za, int qa,
+                                 int ta, double xb, double yb, double zb, int qb, int tb,
+                                 double* dx, double* dy, double* dz, double* f, double* e)
 {
     double r2;
     {
@@ -81,6 +85,10 @@ __device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double ka
     }
     if (!(r2 < A.rc2)) return false;
     const double c6 = A.c6[ta * A.T + tb], c12 = A.c12[ta * A.T + tb];
+    if (hrow) {
+        pair_terms_hybrid64(r2, kap, qa, qb, c6, c12, A.screen_lj != 0, hrow, A.hyb_q, f, e);
+        return true;
+    }
     const double r = sqrt(r2);
     const double rinv2 = 1.0 / r2;
     const double rinv6 = rinv2 * rinv2 * rinv2;
@@ -199,7 +207,9 @@ __device__ void fast_self(const FastArgs& A, int fi)
     const int f = A.fast_list[fi];
     const int b = A.sys_of_atom[f];
     const GridSys gs = A.grid[b];
-    const double kap = A.kappa[(int64_t)b * A.S1 + clamp_step_fast(A)];
+    const int64_t step = clamp_step_fast(A);
+    const double kap = A.kappa[(int64_t)b * A.S1 + step];
+    const double* hrow = A.hyb64 ? A.hyb64 + ((int64_t)b * A.S1 + step) * A.hyb_q * 4 : nullptr;
     const double xf = A.x[f], yf = A.y[f], zf = A.z[f];
     const int qf = A.q[f], tf = A.atype[f];
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, E = 0.0;
@@ -253,7 +263,7 @@ __device__ void fast_self(const FastArgs& A, int fi)
             const double xa = A.xs[s];
             if (xa != xa) continue;                // fast atom or padding
             double dx, dy, dz, fp, e;
-            if (pair_fp64(A, gs, kap, xf, yf, zf, qf, tf, xa, A.xs[cs + s], A.xs[2 * cs + s],
+            if (pair_fp64(A, gs, kap, hrow, xf, yf, zf, qf, tf, xa, A.xs[cs + s], A.xs[2 * cs + s],
                           A.qs[s], A.ts[s], &dx, &dy, &dz, &fp, &e)) {
                 Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
                 if (ENERGY) E += e;
@@ -267,7 +277,7 @@ __device__ void fast_self(const FastArgs& A, int fi)
         const int g = A.fast_list[k];
         if (g == f || g < a0 || g >= a1) continue;
         double dx, dy, dz, fp, e;
-        if (pair_fp64(A, gs, kap, xf, yf, zf, qf, tf, A.x[g], A.y[g], A.z[g], A.q[g],
+        if (pair_fp64(A, gs, kap, hrow, xf, yf, zf, qf, tf, A.x[g], A.y[g], A.z[g], A.q[g],
                       A.atype[g], &dx, &dy, &dz, &fp, &e)) {
             Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
             if (ENERGY) E += 0.5 * e;
@@ -360,7 +370,9 @@ __device__ void fast_nbr(const FastArgs& A, int col)
         if (threadIdx.x == 0) set_flag(A.dsc, MD_FLAG_LIST_OVERFLOW);
         total = kFastLocal;
     }
-    const double kap = A.kappa[(int64_t)b * A.S1 + clamp_step_fast(A)];
+    const int64_t step = clamp_step_fast(A);
+    const double kap = A.kappa[(int64_t)b * A.S1 + step];
+    const double* hrow = A.hyb64 ? A.hyb64 + ((int64_t)b * A.S1 + step) * A.hyb_q * 4 : nullptr;
     const int64_t s0 = (int64_t)col_first_cluster(A.col_pre, col) * kCluster;
     const int64_t s1 = min((int64_t)col_first_cluster(A.col_pre, col + 1) * kCluster,
                            (int64_t)A.dsc->n_slots);
@@ -375,7 +387,7 @@ __device__ void fast_nbr(const FastArgs& A, int col)
         for (int k = 0; k < total; ++k) {
             const int g = s_loc[k];
             double dx, dy, dz, fp, e;
-            if (pair_fp64(A, gs, kap, xa, ya, za, qa, ta, A.x[g], A.y[g], A.z[g], A.q[g],
+            if (pair_fp64(A, gs, kap, hrow, xa, ya, za, qa, ta, A.x[g], A.y[g], A.z[g], A.q[g],
                           A.atype[g], &dx, &dy, &dz, &fp, &e)) {
                 Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
                 any = true;
@@ -414,6 +426,8 @@ void launch_fast(Ctx* c, const double* x, const double* y, const double* z, cons
     A.rc2 = c->cfg.rc * c->cfg.rc;
     A.reach = c->cfg.rc + 0.5 * c->cfg.skin;
     A.screen_lj = c->cfg.screen_lj;
+    A.hyb64 = c->hybrid ? c->d_hyb64 : nullptr;
+    A.hyb_q = c->hyb_q;
     A.fast_flag = c->d_fast_flag; A.fast_list = c->d_fast_list; A.fast_e = c->d_fast_e;
     A.dsc = c->dsc; A.fx = fx; A.fy = fy; A.fz = fz; A.emit = emit; A.emit_max = emit_max;
     const int fc = std::max(c->fast_cap, 1);

@@ -17,6 +17,10 @@
 // so the pair set equals the FP64 definition.
 // FP64 path: the plain comparison form, every pair in FP64 from the caller's
 // positions with the exact membership expression.
+// HYBRID: the Coulomb term of a pair is k_e (q_j phi_i + q_i phi_j) / 2 with phi_Q the
+// hybrid ion-sphere / Debye potential of a charge-Q ion (section II.A, Eq. 4-7),
+// whose coefficients {r', c1, c2, c3} per (system, step, charge) are tabulated on the
+// host; the Lennard-Jones term is unchanged.
 #include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
@@ -84,6 +88,10 @@ struct ForceArgs {
     const uint8_t* ent_mask;
     int nb_cap_h;
     float thr2;                  // ((rc + skin)(1 + 1e-5))^2
+    // hybrid screening rows, [(b * S1 + step) * hyb_q + q]
+    const float4* hyb32;
+    const double* hyb64;
+    int hyb_q;
 };
 
 __global__ void __launch_bounds__(256) k_force_finalize(ForceFinalizeArgs F)
@@ -213,12 +221,13 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
 // ------------------------------------------------------------------ FP32 kernel
 
 // LISTS: only (re)build the per-atom lists, for the FP64 kernel; does nothing
-// unless a rebuild is pending.
-template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool LISTS = false>
+// unless a rebuild is pending.  HYBRID: hybrid screening of the Coulomb term.
+template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool LISTS = false, bool HYBRID = false>
 __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 {
     extern __shared__ float4 s_j[];
     __shared__ float2 s_lj[MD_MAX_TYPES * MD_MAX_TYPES];
+    __shared__ float4 s_hyb[HYBRID ? MD_MAX_CHARGE_STATES : 1];   // {r', c1, c2, c3} per charge
     __shared__ float s_m[kForceBlockMax / 64];
     __shared__ double s_part[kForceBlockMax / 64][kCluster][4];
     __shared__ int s_g;
@@ -248,6 +257,10 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         const GridSys gs = A.grid[gr.sys];
         const double kap = A.kappa[(int64_t)gr.sys * A.S1 + step];
         const auto ent_gl = gbl(A.ent + (int64_t)g * A.E_cap);
+        if (HYBRID) {
+            const float4* hr = A.hyb32 + ((int64_t)gr.sys * A.S1 + step) * A.hyb_q;
+            for (int q = tid; q < A.hyb_q; q += blockDim.x) s_hyb[q] = hr[q];
+        }
 
         // ---- stage the candidate atoms in the group frame (padding slots hold NaN
         //      positions and are never inside the cutoff)
@@ -322,7 +335,8 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         const bool act = cw < gr.ncl;              // wave-uniform
         const int I = gr.cl0 + cw;
         const int64_t slot_i = (int64_t)I * kCluster + il;
-        float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f;
+        float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f, qif = 0.0f;
+        float4 hi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         int tb = 0;
         if (act) {
             ai = A.perm[slot_i];
@@ -339,6 +353,11 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 xi = r[0]; yi = r[1]; zi = r[2];
                 qike = (float)(kKe * (double)A.qs[slot_i]);
                 tb = A.ts[slot_i] * A.T;
+                if (HYBRID) {
+                    const int qv = A.qs[slot_i];
+                    qif = (float)qv;
+                    hi = s_hyb[min(max(qv, 0), A.hyb_q - 1)];
+                }
             }
         }
         int nr = 0;
@@ -367,6 +386,8 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         if (act) {
             const float kapf = (float)kap;
             const float nkl2 = (float)(-kap * 1.4426950408889634);   // -kappa log2(e)
+            const float hke = (float)(0.5 * kKe);
+            const int qn1 = A.hyb_q - 1;
             // wave-uniform row count and list base (scalar loop control / addressing);
             // each lane reads its next 4 codes with one 8-byte load, two rows ahead
             nr = __builtin_amdgcn_readfirstlane(nr);
@@ -433,7 +454,29 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                     const float l12 = lj[u].y * rinv6 * rinv6;
                     const float kr = r * kapf;
                     float f, e;
-                    if (SCREEN_LJ) {
+                    if (HYBRID) {
+                        // potentials of ions i and j at r (ion-sphere form inside r',
+                        // Debye form outside) and w = -r dphi/dr
+                        const float qj = pj[u].w;
+                        const float4 hj = s_hyb[min(max((int)qj, 0), qn1)];
+                        const float so = s * rinv, kr1 = 1.0f + kr;
+                        const bool ii = r < hi.x, jj = r < hj.x;
+                        const float pI = ii ? fmaf(qif, rinv, fmaf(-hi.z, r2[u], hi.y)) : hi.w * so;
+                        const float wI = ii ? fmaf(2.0f * hi.z, r2[u], qif * rinv) : hi.w * so * kr1;
+                        const float pJ = jj ? fmaf(qj, rinv, fmaf(-hj.z, r2[u], hj.y)) : hj.w * so;
+                        const float wJ = jj ? fmaf(2.0f * hj.z, r2[u], qj * rinv) : hj.w * so * kr1;
+                        const float uC = in[u] ? hke * fmaf(qj, pI, qif * pJ) : 0.0f;
+                        const float wC = in[u] ? hke * fmaf(qj, wI, qif * wJ) : 0.0f;
+                        const float ulj = l12 - l6, wlj = fmaf(-6.0f, l6, 12.0f * l12);
+                        if (SCREEN_LJ) {
+                            f = fmaf(fmaf(ulj, kr, wlj), s, wC) * rinv2;
+                            e = fmaf(ulj, s, uC);
+                        } else {
+                            f = (wC + wlj) * rinv2;
+                            e = uC + ulj;
+                        }
+                        (void)uc;
+                    } else if (SCREEN_LJ) {
                         const float uu = uc + (l12 - l6);
                         const float wv = fmaf(-6.0f, l6, fmaf(12.0f, l12, uc));
                         f = fmaf(uu, kr, wv) * s * rinv2;
@@ -502,7 +545,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 
 // ------------------------------------------------------------------ FP64 kernel
 
-template <bool ENERGY, bool EMIT, bool SCREEN_LJ>
+template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool HYBRID = false>
 __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
 {
     __shared__ double s_e[kMaxGroup];
@@ -516,6 +559,8 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
         const Group gr = A.groups[g];
         const GridSys gs = A.grid[gr.sys];
         const double kap = A.kappa[(int64_t)gr.sys * A.S1 + step];
+        const double* hrow = HYBRID ? A.hyb64 + ((int64_t)gr.sys * A.S1 + step) * A.hyb_q * 4
+                                    : nullptr;
         double e_w = 0.0;
         if (w < gr.ncl) {
             const int I = gr.cl0 + w;
@@ -523,10 +568,11 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
             const int64_t slot_i = (int64_t)I * kCluster + il;
             const int ai = A.perm[slot_i];
             double xi = 0.0, yi = 0.0, zi = 0.0, qi = 0.0;
-            int ti = 0;
+            int ti = 0, qi_n = 0;
             if (ai >= 0) {
                 xi = A.xs[slot_i]; yi = A.xs[cs + slot_i]; zi = A.xs[2 * cs + slot_i];
-                qi = kKe * (double)A.qs[slot_i];
+                qi_n = A.qs[slot_i];
+                qi = kKe * (double)qi_n;
                 ti = A.ts[slot_i];
             }
             const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
@@ -561,13 +607,22 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
                                A.emit_max);
                 const int tj = (int)(code >> kCodeIdxBits);
                 const double c6 = A.c6[ti * A.T + tj], c12 = A.c12[ti * A.T + tj];
+                double f, e;
+                if (HYBRID) {
+                    pair_terms_hybrid64(r2, kap, qi_n, A.qs[slot_j], c6, c12, SCREEN_LJ, hrow,
+                                        A.hyb_q, &f, &e);
+                    Fx += f * dx;
+                    Fy += f * dy;
+                    Fz += f * dz;
+                    if (ENERGY) eacc += e;
+                    continue;
+                }
                 const double r = sqrt(r2);
                 const double rinv2 = 1.0 / r2;
                 const double rinv6 = rinv2 * rinv2 * rinv2;
                 const double s = exp(-kap * r);
                 const double uc = qi * (double)A.qs[slot_j] / r;
                 const double l12 = c12 * rinv6 * rinv6, l6 = c6 * rinv6;
-                double f, e;
                 if (SCREEN_LJ) {
                     const double uu = uc + (l12 - l6);
                     f = ((uc + 12.0 * l12 - 6.0 * l6) + uu * (kap * r)) * s * rinv2;
@@ -624,6 +679,8 @@ static void set_lds_attr(size_t lds)
 {
     (void)hipFuncSetAttribute((const void*)k_force32<E, M, S>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_force32<E, M, S, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t force_kernel_setup(Ctx* c)
@@ -631,6 +688,9 @@ hipError_t force_kernel_setup(Ctx* c)
     hipFuncAttributes fa;
     if (hipFuncGetAttributes(&fa, (const void*)k_force32<true, false, true>) == hipSuccess)
         c->force32_static_lds = fa.sharedSizeBytes;
+    if (hipFuncGetAttributes(&fa, (const void*)k_force32<true, false, true, false, true>) ==
+        hipSuccess)
+        c->force32_static_lds_h = fa.sharedSizeBytes;
     const size_t lds = force32_lds_bytes(c->E_cap);
     set_lds_attr<false, false, false>(lds); set_lds_attr<false, false, true>(lds);
     set_lds_attr<true, false, false>(lds);  set_lds_attr<true, false, true>(lds);
@@ -641,14 +701,21 @@ hipError_t force_kernel_setup(Ctx* c)
     return hipGetLastError();
 }
 
-template <bool E, bool M, bool S>
+template <bool E, bool M, bool S, bool H>
 static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks, hipStream_t st)
 {
     if (prec == MD_FP32_KAHAN)
-        hipLaunchKernelGGL((k_force32<E, M, S>), dim3(blocks), dim3(64 * c->G * A.wpc),
+        hipLaunchKernelGGL((k_force32<E, M, S, false, H>), dim3(blocks), dim3(64 * c->G * A.wpc),
                            force32_lds_bytes(c->E_cap), st, A);
     else
-        hipLaunchKernelGGL((k_force64<E, M, S>), dim3(blocks), dim3(64 * c->G), 0, st, A);
+        hipLaunchKernelGGL((k_force64<E, M, S, H>), dim3(blocks), dim3(64 * c->G), 0, st, A);
+}
+
+template <bool E, bool M, bool S>
+static void launch_sh(Ctx* c, md_precision prec, const ForceArgs& A, int blocks, hipStream_t st)
+{
+    if (c->hybrid) launch_one<E, M, S, true>(c, prec, A, blocks, st);
+    else launch_one<E, M, S, false>(c, prec, A, blocks, st);
 }
 
 ForceFinalizeArgs force_finalize_args(Ctx* c, double* epot)
@@ -674,6 +741,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     A.dsc = c->dsc; A.emit = emit; A.emit_max = emit_max;
     A.wpc = kMaxWpc;
     A.cl_len = c->d_cl_len; A.ent_mask = c->d_ent_mask; A.nb_cap_h = c->nb_cap_h;
+    A.hyb32 = c->d_hyb32; A.hyb64 = c->d_hyb64; A.hyb_q = c->hyb_q;
     {
         const double m = c->rlist * (1.0 + 1e-5);
         A.thr2 = (float)(m * m);
@@ -681,7 +749,8 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     // persistent grid: as many work-groups as fit on every CU at once (LDS, waves)
     int per_cu32;
     {
-        const size_t lds = force32_lds_bytes(c->E_cap) + c->force32_static_lds;
+        const size_t lds = force32_lds_bytes(c->E_cap) +
+                           (c->hybrid ? c->force32_static_lds_h : c->force32_static_lds);
         per_cu32 = (int)std::max<size_t>(1, c->lds_per_cu / lds);
         per_cu32 = std::min(per_cu32, std::max(1, 32 / (c->G * A.wpc)));
     }
@@ -701,11 +770,11 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
         if (e != hipSuccess) return e;
     }
     if (E) {
-        if (M) { if (S) launch_one<true, true, true>(c, prec, A, blocks, st); else launch_one<true, true, false>(c, prec, A, blocks, st); }
-        else   { if (S) launch_one<true, false, true>(c, prec, A, blocks, st); else launch_one<true, false, false>(c, prec, A, blocks, st); }
+        if (M) { if (S) launch_sh<true, true, true>(c, prec, A, blocks, st); else launch_sh<true, true, false>(c, prec, A, blocks, st); }
+        else   { if (S) launch_sh<true, false, true>(c, prec, A, blocks, st); else launch_sh<true, false, false>(c, prec, A, blocks, st); }
     } else {
-        if (M) { if (S) launch_one<false, true, true>(c, prec, A, blocks, st); else launch_one<false, true, false>(c, prec, A, blocks, st); }
-        else   { if (S) launch_one<false, false, true>(c, prec, A, blocks, st); else launch_one<false, false, false>(c, prec, A, blocks, st); }
+        if (M) { if (S) launch_sh<false, true, true>(c, prec, A, blocks, st); else launch_sh<false, true, false>(c, prec, A, blocks, st); }
+        else   { if (S) launch_sh<false, false, true>(c, prec, A, blocks, st); else launch_sh<false, false, false>(c, prec, A, blocks, st); }
     }
     if (ev1) {
         const hipError_t e = hipEventRecord(ev1, st);

@@ -85,6 +85,13 @@ struct Ctx {
     double lg_dt = 0.0;
     double* d_lg_c1 = nullptr;     // B*E: exp(-gamma dt)
     double* d_lg_kt = nullptr;     // B*(S+1): k_B T_e, kJ/mol
+    // hybrid ion-sphere / Debye screening (bound by md_bind_hybrid): per (system,
+    // step, charge) the coefficients {r', c1, c2, c3}
+    bool hybrid = false;
+    size_t force32_static_lds_h = 0;   // static LDS of the hybrid FP32 force kernel
+    int32_t hyb_q = 0;             // charges tabulated (0 .. hyb_q - 1)
+    double* d_hyb64 = nullptr;     // B*(S+1)*hyb_q*4
+    float4* d_hyb32 = nullptr;     // B*(S+1)*hyb_q
     int cap_bar = 0;               // arrival words of its barrier
     uint32_t* d_bar_arrive = nullptr;
     // force-kernel launch timer: event pairs recorded around the next t_cap launches
@@ -94,6 +101,7 @@ struct Ctx {
     // host copies
     std::vector<int64_t> sys_off;
     std::vector<double> box;       // B*3 (periodic)
+    std::vector<double> lambda_d;  // B*(S+1) Debye lengths as bound (nm; +inf: unscreened)
     int64_t n_steps = 0;
     int32_t T = 0, E = 0, Q = 0;
     int32_t G = 4;                 // i-clusters per group

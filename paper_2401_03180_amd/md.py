@@ -30,7 +30,7 @@ EXPORTED = (
     "md_build_cells", "md_ionize_step", "md_screened_forces",
     "md_integrate_vv", "md_sync_check", "md_clear_flags", "md_debug_pairs", "md_get_stats",
     "md_force_timer_start", "md_force_timer_read", "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
-    "md_rates_from_fractions", "md_bind_langevin", "md_integrate_langevin",
+    "md_rates_from_fractions", "md_bind_langevin", "md_integrate_langevin", "md_bind_hybrid",
 )
 
 
@@ -98,6 +98,7 @@ def lib():
             "md_graph_destroy": [P], "md_debye_length_nm": [f64, f64],
             "md_rates_from_fractions": [i64, i32, P, P],
             "md_bind_langevin": [P, P, P, f64],
+            "md_bind_hybrid": [P, P],
             "md_integrate_langevin": [P, f64, P, P, P, P, P, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
@@ -196,6 +197,15 @@ def md_bind_langevin(ctx, gamma, kt, dt):
     g = np.ascontiguousarray(gamma, dtype=np.float64)
     k = np.ascontiguousarray(kt, dtype=np.float64)
     _check(ctx, lib().md_bind_langevin(ctx, g.ctypes.data, k.ctypes.data, float(dt)))
+
+
+def md_bind_hybrid(ctx, ne):
+    """ne: host [B, S+1] free-electron density in nm^-3 (None unbinds)."""
+    if ne is None:
+        _check(ctx, lib().md_bind_hybrid(ctx, None))
+        return
+    n = np.ascontiguousarray(ne, dtype=np.float64)
+    _check(ctx, lib().md_bind_hybrid(ctx, n.ctypes.data))
 
 
 def md_integrate_langevin(ctx, dt, inv_mass, elem, atom_id, fx, fy, fz, x, y, z, vx, vy, vz,
@@ -368,6 +378,14 @@ class Engine:
             md_graph_destroy(g)
         self.graphs = {}
         md_bind_langevin(self.ctx, gamma, kt, self.sys.dt)
+
+    def bind_hybrid(self, ne):
+        """Bind (or, with None, unbind) hybrid ion-sphere / Debye screening; graphs
+        captured before use the previous force kernel and are dropped."""
+        for g in self.graphs.values():
+            md_graph_destroy(g)
+        self.graphs = {}
+        md_bind_hybrid(self.ctx, ne)
 
     def langevin(self, stream=None):
         md_integrate_langevin(self.ctx, self.sys.dt, self.inv_mass, self.elem, self.atom_id,

@@ -460,21 +460,44 @@ def methane_clusters(n_clusters: int = 256, n_steps: int = 2000, lo: int = 1000,
 EV_KJ_PER_MOL = 96.48533212      # 1 eV per particle in kJ/mol
 
 
+def electron_temperature_ev(sys: System, te0_ev: float = 0.0259,
+                            te_peak_ev: float = 30.0) -> np.ndarray:
+    """Synthetic T_e [B, S+1] in eV (the paper takes it from the CR code): rising from
+    te0 (300 K) to te_peak with the running integral of each system's pulse envelope."""
+    cum = np.cumsum(sys.g, axis=1)
+    frac = cum / np.maximum(cum[:, -1:], 1e-300)
+    return te0_ev + (te_peak_ev - te0_ev) * frac
+
+
 def langevin_inputs(sys: System, gamma_ps=None, te0_ev: float = 0.0259,
                     te_peak_ev: float = 30.0):
-    """Synthetic electron-ion coupling inputs (the paper takes them from the CR code):
-    gamma [B, E] in ps^-1, one constant value per element (default 2 ps^-1 for the
-    heaviest element, 5 ps^-1 for the rest: equilibration over hundreds of fs), and
-    k_B T_e [B, S+1] in kJ/mol, rising from te0 to te_peak with the running integral of
-    each system's pulse envelope g."""
+    """Synthetic electron-ion coupling inputs: gamma [B, E] in ps^-1, one constant
+    value per element (default 2 ps^-1 for the first element, 5 ps^-1 for the rest:
+    equilibration over hundreds of fs), and k_B T_e [B, S+1] in kJ/mol from
+    electron_temperature_ev."""
     E = sys.n_elements
     if gamma_ps is None:
         gamma_ps = [2.0 if e == 0 else 5.0 for e in range(E)]
     gamma = np.tile(np.asarray(gamma_ps, dtype=np.float64)[None, :E], (sys.n_systems, 1))
-    cum = np.cumsum(sys.g, axis=1)
-    frac = cum / np.maximum(cum[:, -1:], 1e-300)
-    te = te0_ev + (te_peak_ev - te0_ev) * frac
+    te = electron_temperature_ev(sys, te0_ev, te_peak_ev)
     return np.ascontiguousarray(gamma), np.ascontiguousarray(te * EV_KJ_PER_MOL)
+
+
+EPS0_SI = 8.8541878128e-12        # F/m
+E_CHARGE_SI = 1.602176634e-19     # C
+
+
+def hybrid_inputs(sys: System, te0_ev: float = 0.0259, te_peak_ev: float = 30.0) -> np.ndarray:
+    """Synthetic free-electron density n_e [B, S+1] in nm^-3, consistent with the
+    system's Debye-length schedule through Eq. 3 at the temperature of
+    electron_temperature_ev: n_e = eps0 k_B T_e / (e^2 lambda_D^2).  Unscreened steps
+    (lambda_D = inf) get n_e = 1 nm^-3 (unused there)."""
+    te = electron_temperature_ev(sys, te0_ev, te_peak_ev)
+    lam_m = sys.lambda_d * 1e-9
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ne_m3 = EPS0_SI * te / (E_CHARGE_SI * lam_m ** 2)
+    ne = np.where(np.isfinite(sys.lambda_d), ne_m3 * 1e-27, 1.0)
+    return np.ascontiguousarray(ne)
 
 
 CONFIGS = {
