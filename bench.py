@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 FLOP_PER_PAIR = 44                # forces 42 + energy 2, per pair inside the cutoff
+FLOP_PER_PAIR_HYBRID = 57         # hybrid screening (Debye branch on both ions): 55 + 2
 METRIC = "atom-steps/s for screened-force+ionize step; % FP32 VALU peak; FP32-vs-FP64 speedup"
 
 
@@ -53,7 +54,7 @@ STATE = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q")
 
 
 def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_graph=True,
-            fast_capacity=0, langevin=None):
+            fast_capacity=0, langevin=None, hybrid=None):
     """Timed region: `steps` replays of the captured step graph (or, with use_graph
     False, `steps` eager md_step calls), inputs resident.
     Then the same steps are replayed eagerly from a snapshot of the state at the
@@ -62,13 +63,16 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
     region (checked: identical final state and rebuild count) and gives the
     duration of every force-kernel launch.  Pair counts are sampled between steps
     of the replay (where no list rebuild is pending).  langevin: (gamma, kt) tables
-    of the electron-ion coupling, bound for the whole run, or None."""
+    of the electron-ion coupling, bound for the whole run, or None; hybrid: the
+    free-electron density table of hybrid screening, or None."""
     import torch
     from paper_2401_03180_amd import md
     eng = md.Engine(sys_, prec, cluster_group=cluster_group, skin=skin,
                     fast_capacity=fast_capacity)
     if langevin is not None:
         eng.bind_langevin(*langevin)
+    if hybrid is not None:
+        eng.bind_hybrid(hybrid)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         eng.set_step(0, stream)
@@ -136,7 +140,7 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
             "step": step_end}
 
 
-def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None):
+def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None, hybrid=None):
     """The plain form for batched workloads: every system in a context of its own,
     its step replayed as its own graph, systems one after another on one stream."""
     import torch
@@ -149,6 +153,8 @@ def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None):
             e = md.Engine(sb, prec)
             if langevin is not None:
                 e.bind_langevin(langevin[0][b:b + 1], langevin[1][b:b + 1])
+            if hybrid is not None:
+                e.bind_hybrid(hybrid[b:b + 1])
             e.set_step(0, stream)
             e.build(md.MD_BUILD_FORCE, stream)
             e.forces(energy=True, stream=stream)
@@ -175,15 +181,21 @@ def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None):
     return {"ms": ms, "flags": flags}
 
 
-def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None):
+def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None):
     """The oracle, as it stands: whole steps (all-pairs FP64 force rows of every atom,
     ionization and both velocity-Verlet half steps, phase 0 with the electron-ion
-    coupling when langevin = (gamma, kt) is given) repeated until about target_s
+    coupling when langevin = (gamma, kt) is given, hybrid screening when the density
+    table hybrid is given) repeated until about target_s
     seconds of work; when one step alone would exceed that, the force rows of a random
     subset of atoms are timed and scaled to all atoms."""
     import oracle
     if langevin is not None:
         c1 = oracle.langevin_c1(langevin[0], sys_.dt)
+
+    def htab(s):
+        if hybrid is None:
+            return None
+        return oracle.hybrid_table(sys_.lambda_d[:, s], hybrid[:, s], sys_.base.shape[1])
 
     def phase0(s, F, pos, vel):
         if langevin is None:
@@ -197,7 +209,7 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None):
     kap = oracle.kappa_from_lambda(sys_.lambda_d[:, 1])
     probe = np.sort(rng.choice(n, min(n, 256), replace=False))
     t = time.perf_counter()
-    oracle.forces_rows(sys_, probe, kappa=kap, n_threads=threads)
+    oracle.forces_rows(sys_, probe, kappa=kap, n_threads=threads, hybrid=htab(1))
     per_row = (time.perf_counter() - t) / probe.size
     q = sys_.q.copy()
     pos = [sys_.x.copy(), sys_.y.copy(), sys_.z.copy()]
@@ -214,7 +226,7 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None):
             oracle.ionize(sys_, q, s)
             out = oracle.forces_rows(sys_, rows, q=q, x=pos[0], y=pos[1], z=pos[2],
                                      kappa=oracle.kappa_from_lambda(sys_.lambda_d[:, s]),
-                                     n_threads=threads)
+                                     n_threads=threads, hybrid=htab(s))
             F = (out["fx"], out["fy"], out["fz"])
             oracle.vv(1, sys_.dt, sys_.inv_mass, F, pos, vel)
         t_all = time.perf_counter() - t
@@ -225,7 +237,7 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None):
     rows_n = int(min(n, max(256, target_s / max(per_row, 1e-9))))
     rows = np.sort(rng.choice(n, rows_n, replace=False))
     t = time.perf_counter()
-    oracle.forces_rows(sys_, rows, kappa=kap, n_threads=threads)
+    oracle.forces_rows(sys_, rows, kappa=kap, n_threads=threads, hybrid=htab(1))
     t_rows = time.perf_counter() - t
     t = time.perf_counter()
     phase0(1, F, pos, vel)
@@ -281,6 +293,9 @@ def main():
     ap.add_argument("--langevin", action="store_true",
                     help="bind the electron-ion coupling (synthetic gamma per element and "
                          "electron-temperature schedule) for every run")
+    ap.add_argument("--hybrid", action="store_true",
+                    help="bind hybrid ion-sphere / Debye screening (synthetic electron "
+                         "density consistent with the Debye-length schedule)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -330,10 +345,15 @@ def main():
     if a.langevin:
         from paper_2401_03180_amd import synth
         lg = synth.langevin_inputs(sys32)
+    hy = None
+    if a.hybrid:
+        from paper_2401_03180_amd import synth
+        hy = synth.hybrid_inputs(sys32)
     k32 = knobs(md.MD_FP32_KAHAN)
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
     r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
-                  use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg)
+                  use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg,
+                  hybrid=hy)
     log("fp32", {k: v for k, v in r32.items() if k != "stats"})
     n = sys32.n_atoms
     value = n * a.steps / (r32["ms"] * 1e-3)
@@ -353,7 +373,7 @@ def main():
         sys64 = make_system(a.config, S)
         if sys64.n_systems > 1:
             # batched workloads: the plain FP64 form runs one system per context and launch
-            r64 = run_gpu_per_system(sys64, md.MD_FP64, a.steps, a.warmup, langevin=lg)
+            r64 = run_gpu_per_system(sys64, md.MD_FP64, a.steps, a.warmup, langevin=lg, hybrid=hy)
             v64 = n * a.steps / (r64["ms"] * 1e-3)
             extra.update({"fp64_per_system_value": v64,
                           "fp64_per_system_ms_per_step": r64["ms"] / a.steps,
@@ -363,7 +383,8 @@ def main():
         else:
             k64 = knobs(md.MD_FP64)
             r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, k64["cluster_group"], k64["skin"],
-                          use_graph=not a.eager, fast_capacity=k64["fast_capacity"], langevin=lg)
+                          use_graph=not a.eager, fast_capacity=k64["fast_capacity"], langevin=lg,
+                          hybrid=hy)
             log("fp64", {k: v for k, v in r64.items() if k != "stats"})
             v64 = n * a.steps / (r64["ms"] * 1e-3)
             extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
@@ -372,12 +393,15 @@ def main():
                           "fp64_replay_identical": r64["replay_identical"], "fp64_launch": k64})
 
     kernel_ms = r32["kernel_ms"]
-    achieved = FLOP_PER_PAIR * r32["pairs"] / (kernel_ms * 1e-3) / 1e12
+    fpp = FLOP_PER_PAIR_HYBRID if hy is not None else FLOP_PER_PAIR
+    achieved = fpp * r32["pairs"] / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": traffic_from_profile(),
-                "kernel": "k_force32", "kernel_ms": kernel_ms,
-                "flop_per_pair": FLOP_PER_PAIR,
+                # the counter summary covers the Debye kernel only
+                "traffic": traffic_from_profile() if hy is None else None,
+                "kernel": "k_force32" + ("<HYBRID>" if hy is not None else ""),
+                "kernel_ms": kernel_ms,
+                "flop_per_pair": fpp,
                 "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS}
 
     out = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1,
@@ -390,10 +414,11 @@ def main():
                       "cluster_group": r32["stats"]["cluster_group"],
                       "fast_capacity": k32["fast_capacity"], "tuned": k32["tuned"],
                       "systems": sys32.n_systems, "langevin": lg is not None,
+                      "hybrid_screening": hy is not None,
                       "launch": "eager" if a.eager else "graph", "parallelism": "single-gpu"},
            "roofline": roofline, "extra": extra}
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sys32, langevin=lg)
+        out["cpu_baseline"] = cpu_baseline(sys32, langevin=lg, hybrid=hy)
     print(json.dumps(out), flush=True)
 
 
