@@ -69,6 +69,9 @@ def lib():
                                           P, P, P, P, P, P]
             L.orc_ekin.argtypes = [i64, P, P, P, P, P, P]
             L.orc_hybrid_coeffs.argtypes = [f64, f64, f64, P]
+            L.orc_rdf_histogram.argtypes = [i64, P, i32, P, P, P, P, P, i32, f64, i32, P]
+            L.orc_rdf_normalize.argtypes = [i32, f64, P, i64, i64, i32, f64, P]
+            L.orc_structure_factor.argtypes = [i32, f64, P, f64, i32, P, P]
             L.orc_hybrid_phi.argtypes = [f64, P, f64, f64, P, P]
             _lib = L
     return _lib
@@ -228,6 +231,38 @@ def pair_r2(periodic, box, x, y, z, i, j) -> float:
     box = None if box is None else _c(box, np.float64)
     return float(lib().orc_pair_r2(int(periodic), _p(box), _p(_c(x, np.float64)),
                                    _p(_c(y, np.float64)), _p(_c(z, np.float64)), i, j))
+
+
+# ------------------------------------------------------------------ RDF / S(q)
+
+def rdf_histogram(sys, r_max, n_bins, x=None, y=None, z=None) -> np.ndarray:
+    """uint64 [B, E, E, n_bins] pair-distance counts (upper triangle e_a <= e_b)."""
+    x = _c(sys.x if x is None else x, np.float64)
+    y = _c(sys.y if y is None else y, np.float64)
+    z = _c(sys.z if z is None else z, np.float64)
+    E = sys.n_elements
+    hist = np.zeros((sys.n_systems, E, E, n_bins), dtype=np.uint64)
+    box = None if sys.box is None else _c(sys.box, np.float64)
+    lib().orc_rdf_histogram(sys.n_systems, _p(_c(sys.sys_offsets, np.int64)), int(sys.periodic),
+                            _p(box), _p(x), _p(y), _p(z), _p(_c(sys.elem, np.uint8)), E,
+                            float(r_max), int(n_bins), _p(hist))
+    return hist
+
+
+def rdf_normalize(counts, r_max, n_a, n_b, same, volume) -> np.ndarray:
+    c = _c(counts, np.uint64)
+    g = np.empty(c.size)
+    lib().orc_rdf_normalize(c.size, float(r_max), _p(c), int(n_a), int(n_b), int(bool(same)),
+                            float(volume), _p(g))
+    return g
+
+
+def structure_factor(g, r_max, rho0, q) -> np.ndarray:
+    g = _c(g, np.float64)
+    q = _c(np.atleast_1d(q), np.float64)
+    S = np.empty(q.size)
+    lib().orc_structure_factor(g.size, float(r_max), _p(g), float(rho0), q.size, _p(q), _p(S))
+    return S
 
 
 # ------------------------------------------------------------------ random numbers / charges

@@ -39,6 +39,9 @@
  *    outside, r' from Eq. 7, c1..c3 from matching value, slope and curvature at r';
  *    the energy of a pair is the mean of (charge j in the potential of ion i) and
  *    (charge i in the potential of ion j).
+ *  - Radial distribution functions and partial structure factors (section II.C,
+ *    Eq. 18): brute-force pair-distance histograms per element pair, their
+ *    normalization against the ideal gas, and the sine transform of Eq. 18.
  *
  * Philox4x32-10 follows its published definition (Salmon, Moraes, Dror, Shaw,
  * "Parallel random numbers: as easy as 1, 2, 3", SC'11).
@@ -394,6 +397,80 @@ int64_t orc_pairs(int64_t n_sys, const int64_t* sys_off, int32_t periodic, const
             }
     }
     return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Radial distribution functions and structure factors (section II.C, Eq. 18) */
+/* ------------------------------------------------------------------------ */
+
+/* Histogram of the minimum-image distances of all unordered pairs of each system
+ * below r_max: pair {i, j} goes to hist[b][min(e_i,e_j)][max(e_i,e_j)][k] (added to)
+ * with k such that (k dr)^2 <= r^2 < ((k+1) dr)^2, dr = r_max / n_bins, and r^2 the
+ * expression of the cutoff predicate.  Brute force over all pairs. */
+void orc_rdf_histogram(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
+                       const double* box, const double* x, const double* y, const double* z,
+                       const uint8_t* elem, int32_t E, double r_max, int32_t n_bins,
+                       uint64_t* hist)
+{
+    double dr = r_max / (double)n_bins;
+    double* e2 = (double*)malloc(sizeof(double) * (size_t)(n_bins + 1));
+    for (int32_t k = 0; k <= n_bins; ++k) {
+        double e = (double)k * dr;
+        e2[k] = e * e;
+    }
+    for (int64_t b = 0; b < n_sys; ++b) {
+        orc_geom g;
+        geom_init(&g, periodic, periodic ? box + 3 * b : NULL, r_max);
+        for (int64_t i = sys_off[b]; i < sys_off[b + 1]; ++i)
+            for (int64_t j = i + 1; j < sys_off[b + 1]; ++j) {
+                double d[3];
+                double r2 = pair_r2(&g, x, y, z, i, j, d);
+                if (!(r2 < e2[n_bins])) continue;
+                /* largest k with e2[k] <= r2 (binary search; e2[0] = 0 <= r2) */
+                int32_t lo = 0, hi = n_bins - 1;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi + 1) / 2;
+                    if (e2[mid] <= r2) lo = mid; else hi = mid - 1;
+                }
+                int ea = elem[i] < elem[j] ? elem[i] : elem[j];
+                int eb = elem[i] < elem[j] ? elem[j] : elem[i];
+                hist[((b * E + ea) * E + eb) * n_bins + lo] += 1;
+            }
+    }
+    free(e2);
+}
+
+/* g(r) of one element pair: counts over the ideal-gas expectation, P / V times the
+ * shell volume 4/3 pi (r_{k+1}^3 - r_k^3), with P = n_a n_b pairs of distinct
+ * elements or n_a (n_a - 1) / 2 pairs of one element. */
+void orc_rdf_normalize(int32_t n_bins, double r_max, const uint64_t* counts, int64_t n_a,
+                       int64_t n_b, int32_t same, double volume, double* g)
+{
+    const double pi = 3.14159265358979323846;
+    double P = same ? (double)n_a * (double)(n_a - 1) / 2.0 : (double)n_a * (double)n_b;
+    double dr = r_max / (double)n_bins;
+    for (int32_t k = 0; k < n_bins; ++k) {
+        double r0 = k * dr, r1 = (k + 1) * dr;
+        double expect = P / volume * (4.0 * pi / 3.0) * (r1 * r1 * r1 - r0 * r0 * r0);
+        g[k] = expect > 0.0 ? (double)counts[k] / expect : 0.0;
+    }
+}
+
+/* Eq. 18 with the integral over [0, r_max] by the midpoint rule on the bins:
+ * S(q) = 1 + (4 pi rho0 / q) sum_k r_k (g_k - 1) sin(q r_k) dr, r_k = (k + 1/2) dr. */
+void orc_structure_factor(int32_t n_bins, double r_max, const double* g, double rho0,
+                          int32_t n_q, const double* q, double* S)
+{
+    const double pi = 3.14159265358979323846;
+    double dr = r_max / (double)n_bins;
+    for (int32_t m = 0; m < n_q; ++m) {
+        double integral = 0.0;
+        for (int32_t k = 0; k < n_bins; ++k) {
+            double r = (k + 0.5) * dr;
+            integral += r * (g[k] - 1.0) * sin(q[m] * r) * dr;
+        }
+        S[m] = 1.0 + 4.0 * pi * rho0 / q[m] * integral;
+    }
 }
 
 /* Squared minimum-image distance of one pair (for adversarial predicate tests). */
