@@ -406,12 +406,15 @@ int64_t orc_pairs(int64_t n_sys, const int64_t* sys_off, int32_t periodic, const
 /* Histogram of the minimum-image distances of all unordered pairs of each system
  * below r_max: pair {i, j} goes to hist[b][min(e_i,e_j)][max(e_i,e_j)][k] (added to)
  * with k such that (k dr)^2 <= r^2 < ((k+1) dr)^2, dr = r_max / n_bins, and r^2 the
- * expression of the cutoff predicate.  Brute force over all pairs. */
+ * expression of the cutoff predicate.  Brute force over all pairs (OpenMP over i,
+ * with per-thread histograms summed at the end: integer counts, so the result does
+ * not depend on the thread count). */
 void orc_rdf_histogram(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
                        const double* box, const double* x, const double* y, const double* z,
                        const uint8_t* elem, int32_t E, double r_max, int32_t n_bins,
                        uint64_t* hist)
 {
+    size_t per_sys = (size_t)E * (size_t)E * (size_t)n_bins;
     double dr = r_max / (double)n_bins;
     double* e2 = (double*)malloc(sizeof(double) * (size_t)(n_bins + 1));
     for (int32_t k = 0; k <= n_bins; ++k) {
@@ -421,21 +424,36 @@ void orc_rdf_histogram(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
     for (int64_t b = 0; b < n_sys; ++b) {
         orc_geom g;
         geom_init(&g, periodic, periodic ? box + 3 * b : NULL, r_max);
-        for (int64_t i = sys_off[b]; i < sys_off[b + 1]; ++i)
-            for (int64_t j = i + 1; j < sys_off[b + 1]; ++j) {
-                double d[3];
-                double r2 = pair_r2(&g, x, y, z, i, j, d);
-                if (!(r2 < e2[n_bins])) continue;
-                /* largest k with e2[k] <= r2 (binary search; e2[0] = 0 <= r2) */
-                int32_t lo = 0, hi = n_bins - 1;
-                while (lo < hi) {
-                    int32_t mid = (lo + hi + 1) / 2;
-                    if (e2[mid] <= r2) lo = mid; else hi = mid - 1;
+        uint64_t* hb = hist + (size_t)b * per_sys;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+        {
+            uint64_t* mine = (uint64_t*)calloc(per_sys, sizeof(uint64_t));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+            for (int64_t i = sys_off[b]; i < sys_off[b + 1]; ++i)
+                for (int64_t j = i + 1; j < sys_off[b + 1]; ++j) {
+                    double d[3];
+                    double r2 = pair_r2(&g, x, y, z, i, j, d);
+                    if (!(r2 < e2[n_bins])) continue;
+                    /* largest k with e2[k] <= r2 (binary search; e2[0] = 0 <= r2) */
+                    int32_t lo = 0, hi = n_bins - 1;
+                    while (lo < hi) {
+                        int32_t mid = (lo + hi + 1) / 2;
+                        if (e2[mid] <= r2) lo = mid; else hi = mid - 1;
+                    }
+                    int ea = elem[i] < elem[j] ? elem[i] : elem[j];
+                    int eb = elem[i] < elem[j] ? elem[j] : elem[i];
+                    mine[((size_t)ea * E + eb) * n_bins + lo] += 1;
                 }
-                int ea = elem[i] < elem[j] ? elem[i] : elem[j];
-                int eb = elem[i] < elem[j] ? elem[j] : elem[i];
-                hist[((b * E + ea) * E + eb) * n_bins + lo] += 1;
-            }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+            for (size_t k = 0; k < per_sys; ++k) hb[k] += mine[k];
+            free(mine);
+        }
     }
     free(e2);
 }
