@@ -318,6 +318,37 @@ md_status md_integrate_langevin(md_ctx* ctx, double dt, const double* inv_mass,
  * underflows).  Synchronous. */
 md_status md_bind_hybrid(md_ctx* ctx, const double* ne);
 
+/* Pair-distance histogram for the radial distribution functions g_ab(r) behind the
+ * partial structure factors of section II.C (Eq. 18).  Adds to hist (DEVICE uint64
+ * [B][E][E][n_bins], not cleared: the caller zeroes it, or accumulates frames)
+ * the count of every unordered pair {i, j} of one system whose minimum-image
+ * distance r (the FP64 r^2 of the cutoff predicate) is below r_max, under
+ * [b][min(e_i, e_j)][max(e_i, e_j)][k] with k such that (k dr)^2 <= r^2 < ((k+1) dr)^2,
+ * dr = r_max / n_bins (squared edges evaluated as (k * dr) * (k * dr) in FP64).
+ * Counts are exact.  Uses the last md_build_cells for the search (any positions
+ * are accepted; atoms farther than skin/2 from their build position are handled by
+ * a brute-force pass over their system, so many of them make the call slow).
+ * Errors: MD_ERR_STATE before a build; MD_ERR_ARG for r_max outside (0, rc],
+ * n_bins outside [1, 2048] or a NULL array.  The first call allocates N bytes of
+ * workspace (do not capture it into a graph).  Asynchronous. */
+md_status md_rdf_histogram(md_ctx* ctx, const double* x, const double* y, const double* z,
+                           const uint8_t* elem, double r_max, int32_t n_bins, uint64_t* hist,
+                           md_stream stream);
+
+/* g_ab for one element pair from its n_bins counts (HOST arrays, FP64, no device
+ * work): g[k] = counts[k] / (P / volume * 4/3 pi (r_{k+1}^3 - r_k^3)) with r_k = k dr
+ * and P = n_a n_b pairs (same = 0) or n_a (n_a - 1) / 2 (same = 1: a = b).  The ideal
+ * gas gives g = 1.  MD_ERR_ARG for bad sizes or volume <= 0. */
+md_status md_rdf_normalize(int32_t n_bins, double r_max, const uint64_t* counts, int64_t n_a,
+                           int64_t n_b, int32_t same, double volume, double* g);
+
+/* Partial structure factor of section II.C, Eq. 18, from a binned g (HOST arrays):
+ * S(q) = 1 + 4 pi rho0 / q * sum_k r_k (g_k - 1) sin(q r_k) dr with bin centres
+ * r_k = (k + 1/2) dr, i.e. the midpoint rule of the integral truncated at r_max
+ * (rho0 in nm^-3, q in nm^-1, q > 0).  MD_ERR_ARG for bad sizes or q <= 0. */
+md_status md_structure_factor(int32_t n_bins, double r_max, const double* g, double rho0,
+                              int32_t n_q, const double* q, double* S);
+
 /* Host helpers for the per-step schedules (FP64, no device work). */
 
 /* Debye length (section II.A, Eq. 3) in nm for electron temperature te_ev (eV) and

@@ -57,7 +57,7 @@ void free_all(Ctx* c)
                     c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
                     c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
                     c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
-                    c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32};
+                    c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32, c->d_rdf_moved};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -647,6 +647,60 @@ md_status md_bind_hybrid(md_ctx* ctx, const double* ne)
                          hipMemcpyHostToDevice));
     c->hyb_q = nq;
     c->hybrid = true;
+    return MD_OK;
+}
+
+md_status md_rdf_histogram(md_ctx* ctx, const double* x, const double* y, const double* z,
+                           const uint8_t* elem, double r_max, int32_t n_bins, uint64_t* hist,
+                           md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound || !c->built)
+        return fail(c, MD_ERR_STATE, "build cells before the histogram");
+    if (!(r_max > 0.0) || !(r_max <= c->cfg.rc))
+        return fail(c, MD_ERR_ARG, "r_max must be in (0, rc]");
+    if (n_bins < 1 || n_bins > kRdfMaxBins)
+        return fail(c, MD_ERR_ARG, "n_bins must be in [1, %d]", kRdfMaxBins);
+    if (null_any({x, y, z, elem, hist}) && c->N > 0) return fail(c, MD_ERR_ARG, "NULL array");
+    if (!c->d_rdf_moved) HIP_TRY(c, dalloc(&c->d_rdf_moved, c->N));
+    launch_rdf(c, x, y, z, elem, r_max, n_bins, reinterpret_cast<unsigned long long*>(hist),
+               S(stream));
+    HIP_TRY(c, hipGetLastError());
+    return MD_OK;
+}
+
+md_status md_rdf_normalize(int32_t n_bins, double r_max, const uint64_t* counts, int64_t n_a,
+                           int64_t n_b, int32_t same, double volume, double* g)
+{
+    if (n_bins < 1 || !(r_max > 0.0) || !counts || !g || !(volume > 0.0) || n_a < 0 || n_b < 0)
+        return MD_ERR_ARG;
+    const double pairs = same ? 0.5 * (double)n_a * (double)(n_a - 1) : (double)n_a * (double)n_b;
+    const double dr = r_max / (double)n_bins;
+    for (int k = 0; k < n_bins; ++k) {
+        const double r0 = (double)k * dr, r1 = (double)(k + 1) * dr;
+        const double shell = 4.0 / 3.0 * M_PI * (r1 * r1 * r1 - r0 * r0 * r0);
+        const double ideal = pairs / volume * shell;
+        g[k] = ideal > 0.0 ? (double)counts[k] / ideal : 0.0;
+    }
+    return MD_OK;
+}
+
+md_status md_structure_factor(int32_t n_bins, double r_max, const double* g, double rho0,
+                              int32_t n_q, const double* q, double* S)
+{
+    if (n_bins < 1 || !(r_max > 0.0) || !g || n_q < 0 || (n_q > 0 && (!q || !S)))
+        return MD_ERR_ARG;
+    const double dr = r_max / (double)n_bins;
+    for (int m = 0; m < n_q; ++m) {
+        if (!(q[m] > 0.0)) return MD_ERR_ARG;
+        double acc = 0.0;
+        for (int k = 0; k < n_bins; ++k) {
+            const double r = ((double)k + 0.5) * dr;
+            acc += r * (g[k] - 1.0) * sin(q[m] * r);
+        }
+        S[m] = 1.0 + 4.0 * M_PI * rho0 / q[m] * acc * dr;
+    }
     return MD_OK;
 }
 

@@ -114,6 +114,81 @@ __device__ inline void pair_terms_hybrid64(double r2, double kap, int qa, int qb
     }
 }
 
+// ---- the build grid: columns (x, y) with z bins, per system
+
+__device__ inline int col_first_cluster(const int64_t* pre, int c)
+{
+    return (int)(pre[c] & 0xFFFFFFFFll);
+}
+
+// Distance from the point p to the interval [lo, hi] along one axis; periodic axes
+// take the nearest image of p.
+__device__ inline double axis_gap(double p, double lo, double hi, bool periodic, double L)
+{
+    double g = fmax(0.0, fmax(lo - p, p - hi));
+    if (periodic) {
+        g = fmin(g, fmax(0.0, fmax(lo - (p + L), (p + L) - hi)));
+        g = fmin(g, fmax(0.0, fmax(lo - (p - L), (p - L) - hi)));
+    }
+    return g;
+}
+
+// Column index range along axis d (x or y) within `reach` of coordinate p.  Periodic
+// ranges are in unwrapped column numbers (callers wrap them) and become every column
+// when they would cover the axis (also for a non-finite p); vacuum ranges are clamped
+// to the grid.  The range length never exceeds the column count.
+__device__ inline void col_range(const GridSys& g, int d, double p, double reach, int* c0, int* c1)
+{
+    if (g.periodic) {
+        const double w = p - g.L[d] * floor(p * g.invL[d]);
+        const double a = floor((w - reach) * g.inv_w[d]);
+        const double b = floor((w + reach) * g.inv_w[d]);
+        if (!(b - a + 1.0 < (double)g.n[d]) || !(fabs(a) < 1e6) || !(fabs(b) < 1e6)) {
+            *c0 = 0; *c1 = g.n[d] - 1;
+        } else {
+            *c0 = (int)a; *c1 = (int)b;
+        }
+    } else {
+        const double w = p - g.origin[d];
+        const double a = fmin(fmax(floor((w - reach) * g.inv_w[d]), 0.0), (double)(g.n[d] - 1));
+        const double b = fmin(fmax(floor((w + reach) * g.inv_w[d]), 0.0), (double)(g.n[d] - 1));
+        *c0 = (int)a; *c1 = (int)b;
+    }
+}
+
+// z-bin ranges (up to two, for a periodic wrap) of column-local bins within
+// `reach` of coordinate p; returns the number of ranges.
+__device__ inline int zbin_ranges(const GridSys& g, double p, double reach, int r0[2], int r1[2])
+{
+    const int nz = g.n[2];
+    if (g.periodic) {
+        const double w = p - g.L[2] * floor(p * g.invL[2]);
+        const double a = floor((w - reach) * g.inv_w[2]);
+        const double b = floor((w + reach) * g.inv_w[2]);
+        if (!(b - a + 1.0 < (double)nz) || !(fabs(a) < 1e6) || !(fabs(b) < 1e6)) {
+            r0[0] = 0; r1[0] = nz - 1;
+            return 1;
+        }
+        int lo = (int)a, hi = (int)b;
+        if (lo < 0) {
+            r0[0] = 0; r1[0] = hi;
+            r0[1] = lo + nz; r1[1] = nz - 1;
+            return 2;
+        }
+        if (hi >= nz) {
+            r0[0] = lo; r1[0] = nz - 1;
+            r0[1] = 0; r1[1] = hi - nz;
+            return 2;
+        }
+        r0[0] = lo; r1[0] = hi;
+        return 1;
+    }
+    const double w = p - g.origin[2];
+    r0[0] = (int)fmin(fmax(floor((w - reach) * g.inv_w[2]), 0.0), (double)(nz - 1));
+    r1[0] = (int)fmin(fmax(floor((w + reach) * g.inv_w[2]), 0.0), (double)(nz - 1));
+    return 1;
+}
+
 // Sum of v over the block (every thread receives it); s holds one value per wave.
 template <class T>
 __device__ inline T block_sum_all(T v, T* s)

@@ -32,6 +32,11 @@ void launch_vv0_langevin(Ctx* c, double dt, const double* inv_mass, const uint8_
                          const double* fz, double* x, double* y, double* z, double* vx,
                          double* vy, double* vz, hipStream_t st);
 int vv_blocks(int64_t N);
+// pair-distance histograms (md_rdf.hip)
+constexpr size_t kRdfLdsMax = 48 * 1024;
+constexpr int kRdfMaxBins = 2048;
+void launch_rdf(Ctx* c, const double* x, const double* y, const double* z, const uint8_t* elem,
+                double r_max, int n_bins, unsigned long long* hist, hipStream_t st);
 int vv_block_size();
 void launch_set_step(Ctx* c, int64_t step, hipStream_t st);
 void launch_clear_flags(Ctx* c, hipStream_t st);

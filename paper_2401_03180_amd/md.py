@@ -31,6 +31,7 @@ EXPORTED = (
     "md_integrate_vv", "md_sync_check", "md_clear_flags", "md_debug_pairs", "md_get_stats",
     "md_force_timer_start", "md_force_timer_read", "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
     "md_rates_from_fractions", "md_bind_langevin", "md_integrate_langevin", "md_bind_hybrid",
+    "md_rdf_histogram", "md_rdf_normalize", "md_structure_factor",
 )
 
 
@@ -99,6 +100,9 @@ def lib():
             "md_rates_from_fractions": [i64, i32, P, P],
             "md_bind_langevin": [P, P, P, f64],
             "md_bind_hybrid": [P, P],
+            "md_rdf_histogram": [P, P, P, P, P, f64, i32, P, P],
+            "md_rdf_normalize": [i32, f64, P, i64, i64, i32, f64, P],
+            "md_structure_factor": [i32, f64, P, f64, i32, P, P],
             "md_integrate_langevin": [P, f64, P, P, P, P, P, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
@@ -206,6 +210,29 @@ def md_bind_hybrid(ctx, ne):
         return
     n = np.ascontiguousarray(ne, dtype=np.float64)
     _check(ctx, lib().md_bind_hybrid(ctx, n.ctypes.data))
+
+
+def md_rdf_histogram(ctx, x, y, z, elem, r_max, n_bins, hist, stream=None):
+    """hist: device int64/uint64 tensor [B, E, E, n_bins] (added to)."""
+    _check(ctx, lib().md_rdf_histogram(ctx, _ptr(x), _ptr(y), _ptr(z), _ptr(elem), float(r_max),
+                                       int(n_bins), _ptr(hist), _stream(stream)))
+
+
+def md_rdf_normalize(counts, r_max, n_a, n_b, same, volume) -> np.ndarray:
+    c = np.ascontiguousarray(counts, dtype=np.uint64)
+    g = np.zeros(c.size)
+    _check(None, lib().md_rdf_normalize(c.size, float(r_max), c.ctypes.data, int(n_a), int(n_b),
+                                        int(bool(same)), float(volume), g.ctypes.data))
+    return g
+
+
+def md_structure_factor(g, r_max, rho0, q) -> np.ndarray:
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    S = np.zeros(q.size)
+    _check(None, lib().md_structure_factor(g.size, float(r_max), g.ctypes.data, float(rho0),
+                                           q.size, q.ctypes.data, S.ctypes.data))
+    return S
 
 
 def md_integrate_langevin(ctx, dt, inv_mass, elem, atom_id, fx, fy, fz, x, y, z, vx, vy, vz,
@@ -386,6 +413,18 @@ class Engine:
             md_graph_destroy(g)
         self.graphs = {}
         md_bind_hybrid(self.ctx, ne)
+
+    def rdf(self, r_max, n_bins, hist=None, stream=None):
+        """Pair-distance histogram [B, E, E, n_bins] (int64 tensor; added to `hist`
+        when given)."""
+        torch = self.torch
+        if hist is None:
+            E = self.sys.n_elements
+            hist = torch.zeros((self.sys.n_systems, E, E, n_bins), dtype=torch.int64,
+                               device=self.dev)
+        md_rdf_histogram(self.ctx, self.x, self.y, self.z, self.elem, r_max, n_bins, hist,
+                         stream)
+        return hist
 
     def langevin(self, stream=None):
         md_integrate_langevin(self.ctx, self.sys.dt, self.inv_mass, self.elem, self.atom_id,
