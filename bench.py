@@ -181,6 +181,42 @@ def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None, hybrid=None):
     return {"ms": ms, "flags": flags}
 
 
+def run_rdf(sys_, r_max=1.0, n_bins=250, calls=20, warmup=3, steps=50):
+    """Pair-distance histogram of the workload after `steps` graph-replayed steps
+    (moved atoms included), timed with HIP events over `calls` calls on one stream;
+    returns ms per call and the pairs counted per call."""
+    import torch
+    from paper_2401_03180_amd import md
+    eng = md.Engine(sys_, md.MD_FP32_KAHAN)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        eng.set_step(0, stream)
+        eng.build(md.MD_BUILD_FORCE, stream)
+        eng.forces(energy=True, stream=stream)
+        g = eng.graph(md.MD_BUILD_AUTO, stream, energy=True, ekin=True)
+        for _ in range(steps):
+            md.md_graph_launch(g, stream)
+        E = sys_.n_elements
+        h = torch.zeros((sys_.n_systems, E, E, n_bins), dtype=torch.int64, device="cuda")
+        for _ in range(warmup):
+            eng.rdf(r_max, n_bins, hist=h, stream=stream)
+        h.zero_()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(calls):
+            eng.rdf(r_max, n_bins, hist=h, stream=stream)
+        ev1.record(stream)
+        stream.synchronize()
+        flags = eng.sync_check(stream, raise_on_flags=False)
+    eng.close()
+    ms = ev0.elapsed_time(ev1) / calls
+    pairs = int(h.sum().item()) // calls
+    return {"rdf_ms_per_call": ms, "rdf_pairs_per_call": pairs,
+            "rdf_pairs_per_s": pairs / (ms * 1e-3), "rdf_r_max": r_max, "rdf_bins": n_bins,
+            "rdf_flags": flags}
+
+
 def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None):
     """The oracle, as it stands: whole steps (all-pairs FP64 force rows of every atom,
     ionization and both velocity-Verlet half steps, phase 0 with the electron-ion
@@ -296,6 +332,9 @@ def main():
     ap.add_argument("--hybrid", action="store_true",
                     help="bind hybrid ion-sphere / Debye screening (synthetic electron "
                          "density consistent with the Debye-length schedule)")
+    ap.add_argument("--rdf", action="store_true",
+                    help="also time the pair-distance histogram (1 nm, 250 bins) after the "
+                         "timed steps' workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -391,6 +430,11 @@ def main():
                           "fp32_vs_fp64_speedup": value / v64,
                           "fp64_force_kernel_ms": r64["kernel_ms"], "fp64_flags": r64["flags"],
                           "fp64_replay_identical": r64["replay_identical"], "fp64_launch": k64})
+
+    if a.rdf:
+        rr = run_rdf(make_system(a.config, S))
+        log("rdf", rr)
+        extra.update(rr)
 
     kernel_ms = r32["kernel_ms"]
     fpp = FLOP_PER_PAIR_HYBRID if hy is not None else FLOP_PER_PAIR

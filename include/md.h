@@ -329,8 +329,8 @@ md_status md_bind_hybrid(md_ctx* ctx, const double* ne);
  * are accepted; atoms farther than skin/2 from their build position are handled by
  * a brute-force pass over their system, so many of them make the call slow).
  * Errors: MD_ERR_STATE before a build; MD_ERR_ARG for r_max outside (0, rc],
- * n_bins outside [1, 2048] or a NULL array.  The first call allocates N bytes of
- * workspace (do not capture it into a graph).  Asynchronous. */
+ * n_bins outside [1, 2048] or a NULL array.  The first call allocates about
+ * 26 bytes per slot of workspace (do not capture it into a graph).  Asynchronous. */
 md_status md_rdf_histogram(md_ctx* ctx, const double* x, const double* y, const double* z,
                            const uint8_t* elem, double r_max, int32_t n_bins, uint64_t* hist,
                            md_stream stream);

@@ -57,7 +57,8 @@ void free_all(Ctx* c)
                     c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
                     c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
                     c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
-                    c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32, c->d_rdf_moved};
+                    c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32, c->d_rdf_moved,
+                    c->d_rdf_xr, c->d_rdf_er};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -663,7 +664,11 @@ md_status md_rdf_histogram(md_ctx* ctx, const double* x, const double* y, const 
     if (n_bins < 1 || n_bins > kRdfMaxBins)
         return fail(c, MD_ERR_ARG, "n_bins must be in [1, %d]", kRdfMaxBins);
     if (null_any({x, y, z, elem, hist}) && c->N > 0) return fail(c, MD_ERR_ARG, "NULL array");
-    if (!c->d_rdf_moved) HIP_TRY(c, dalloc(&c->d_rdf_moved, c->N));
+    if (!c->d_rdf_moved) {
+        HIP_TRY(c, dalloc(&c->d_rdf_moved, c->N));
+        HIP_TRY(c, dalloc(&c->d_rdf_xr, 3 * c->cap_slots));
+        HIP_TRY(c, dalloc(&c->d_rdf_er, c->cap_slots));
+    }
     launch_rdf(c, x, y, z, elem, r_max, n_bins, reinterpret_cast<unsigned long long*>(hist),
                S(stream));
     HIP_TRY(c, hipGetLastError());

@@ -93,6 +93,8 @@ struct Ctx {
     double* d_hyb64 = nullptr;     // B*(S+1)*hyb_q*4
     float4* d_hyb32 = nullptr;     // B*(S+1)*hyb_q
     uint8_t* d_rdf_moved = nullptr;   // N: atoms beyond skin/2 of the build (histogram pass)
+    double* d_rdf_xr = nullptr;       // cap_slots*3: slot-order current positions
+    uint8_t* d_rdf_er = nullptr;      // cap_slots: slot-order elements
     int cap_bar = 0;               // arrival words of its barrier
     uint32_t* d_bar_arrive = nullptr;
     // force-kernel launch timer: event pairs recorded around the next t_cap launches

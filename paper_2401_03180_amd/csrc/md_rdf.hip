@@ -12,6 +12,8 @@
 // by scanning, around the other atom's current position, the bins within
 // r_max + skin/2; pairs with an atom that has moved farther ("moved" here, judged
 // from the positions passed in) are counted by a brute-force pass over its system.
+// The current positions are first gathered into slot order (NaN for moved atoms and
+// padding), so that the scans of neighbouring slots read the same cache lines.
 #include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
@@ -37,7 +39,10 @@ struct RdfArgs {
     double dr;                     // r_max / n_bins
     double reach;                  // r_max + skin/2
     double thr2;                   // (skin/2)^2
-    uint8_t* moved;
+    uint8_t* moved;                // per atom
+    double* xr;                    // slot-order current positions (SoA, stride cap_slots)
+    uint8_t* er;                   // slot-order elements
+    int64_t cap_slots;
     unsigned long long* hist;      // [B][E][E][n_bins]
     int lds_hist;                  // per-block LDS histogram when the block is one system
 };
@@ -68,33 +73,54 @@ __device__ inline int64_t hist_index(const RdfArgs& A, int b, int ea, int eb, in
     return (((int64_t)b * A.E + lo) * A.E + hi) * A.n_bins + k;
 }
 
-// An atom is "moved" when it is farther than skin/2 from its build position (or its
-// position is not finite).
-__global__ void __launch_bounds__(kRdfBlock) k_rdf_flag(RdfArgs A)
+// Per slot: the atom's "moved" flag (farther than skin/2 from its build position,
+// or a position that is not finite) and its current position in slot order (NaN
+// when moved, and for padding slots).
+__global__ void __launch_bounds__(kRdfBlock) k_rdf_gather(RdfArgs A)
 {
 #pragma clang fp contract(off)
-    const int64_t a = blockIdx.x * (int64_t)kRdfBlock + threadIdx.x;
-    if (a >= A.N) return;
-    const double ex = A.x[a] - A.xref[a];
-    const double ey = A.y[a] - A.xref[A.N + a];
-    const double ez = A.z[a] - A.xref[2 * A.N + a];
-    double d2 = ex * ex + ey * ey;
-    d2 = d2 + ez * ez;
-    A.moved[a] = (d2 <= A.thr2) ? 0 : 1;
+    const int64_t s = blockIdx.x * (int64_t)kRdfBlock + threadIdx.x;
+    if (s >= A.cap_slots) return;
+    const int a = s < A.dsc->n_slots ? A.perm[s] : -1;
+    double p[3] = {NAN, NAN, NAN};
+    uint8_t e = 0;
+    if (a >= 0) {
+        p[0] = A.x[a]; p[1] = A.y[a]; p[2] = A.z[a];
+        const double ex = p[0] - A.xref[a];
+        const double ey = p[1] - A.xref[A.N + a];
+        const double ez = p[2] - A.xref[2 * A.N + a];
+        double d2 = ex * ex + ey * ey;
+        d2 = d2 + ez * ez;
+        const uint8_t mv = (d2 <= A.thr2) ? 0 : 1;
+        A.moved[a] = mv;
+        if (mv) p[0] = p[1] = p[2] = NAN;
+        e = A.elem[a];
+    }
+    A.xr[s] = p[0];
+    A.xr[A.cap_slots + s] = p[1];
+    A.xr[2 * A.cap_slots + s] = p[2];
+    A.er[s] = e;
 }
 
-// Pairs of two atoms that have not moved: thread per atom i, partners j > i found
-// in the bins within reach of i.
+// Pairs of two atoms that have not moved: thread per slot i, partners in slots
+// j > i among the bins within reach of i (a moved or padding slot has a NaN
+// position, so its distances fail the range test).
 __global__ void __launch_bounds__(kRdfBlock) k_rdf_grid(RdfArgs A)
 {
     extern __shared__ double s_dyn[];
     double* e2 = s_dyn;                                              // n_bins + 1
     unsigned* s_h = reinterpret_cast<unsigned*>(s_dyn + A.n_bins + 1); // E*E*n_bins
     const int n = A.n_bins;
-    const int64_t a0 = blockIdx.x * (int64_t)kRdfBlock;
-    const int64_t i = a0 + threadIdx.x;
-    const int64_t last = min(a0 + kRdfBlock, A.N) - 1;
-    const int bfirst = A.sys_of_atom[a0], blast = A.sys_of_atom[last];
+    const int64_t n_slots = A.dsc->n_slots;
+    const int64_t s0b = blockIdx.x * (int64_t)kRdfBlock;
+    if (s0b >= n_slots) return;                                      // block-uniform
+    const int64_t i = s0b + threadIdx.x;
+    // the block's system when all its slots belong to one (slots are system-major)
+    const int64_t last = min(s0b + kRdfBlock, n_slots) - 1;
+    int pf = -1, pl = -1;
+    for (int64_t t = s0b; t <= last && pf < 0; ++t) pf = A.perm[t];
+    for (int64_t t = last; t >= s0b && pl < 0; --t) pl = A.perm[t];
+    const int bfirst = pf >= 0 ? A.sys_of_atom[pf] : 0, blast = pl >= 0 ? A.sys_of_atom[pl] : 0;
     const bool lds = A.lds_hist && bfirst == blast;                  // block-uniform
     const int nh = A.E * A.E * n;
     fill_edges(e2, n, A.dr);
@@ -103,22 +129,23 @@ __global__ void __launch_bounds__(kRdfBlock) k_rdf_grid(RdfArgs A)
     __syncthreads();
     const double inv_dr = 1.0 / A.dr;
     const double r2max = e2[n];
-    const bool live = i < A.N && !A.moved[i];
+    const int64_t cs = A.cap_slots;
+    const double xi = i < n_slots ? A.xr[i] : NAN;
+    const bool live = xi == xi;
     int b = 0, ei = 0;
-    double xi = 0.0, yi = 0.0, zi = 0.0;
+    double yi = 0.0, zi = 0.0;
     GridSys gs{};
     int cx0 = 0, cx1 = -1, cy0 = 0, cy1 = -1, nzr = 0;
     int zr0[2] = {0, 0}, zr1[2] = {-1, -1};
     if (live) {
-        b = A.sys_of_atom[i];
+        b = A.sys_of_atom[A.perm[i]];
         gs = A.grid[b];
-        ei = A.elem[i];
-        xi = A.x[i]; yi = A.y[i]; zi = A.z[i];
+        ei = A.er[i];
+        yi = A.xr[cs + i]; zi = A.xr[2 * cs + i];
         col_range(gs, 0, xi, A.reach, &cx0, &cx1);
         col_range(gs, 1, yi, A.reach, &cy0, &cy1);
         nzr = zbin_ranges(gs, zi, A.reach, zr0, zr1);
     }
-    const int64_t n_slots = A.dsc->n_slots;
     const int ncy = cy1 - cy0 + 1;
     const int npairs = live ? (cx1 - cx0 + 1) * ncy * nzr : 0;
     for (int p = 0; p < npairs; ++p) {
@@ -130,15 +157,13 @@ __global__ void __launch_bounds__(kRdfBlock) k_rdf_grid(RdfArgs A)
         const int64_t slot0 = (int64_t)col_first_cluster(A.col_pre, col) * kCluster;
         const int bin0 = gs.bin_off + (col - gs.col_off) * gs.n[2];
         const int a_col = A.bin_start[bin0];
-        const int64_t s0 = slot0 + (A.bin_start[bin0 + zr0[r]] - a_col);
+        const int64_t s0 = max(slot0 + (A.bin_start[bin0 + zr0[r]] - a_col), i + 1);
         const int64_t s1 = min(slot0 + (A.bin_start[bin0 + zr1[r] + 1] - a_col), n_slots);
-        for (int64_t s = s0; s < s1; ++s) {
-            const int j = A.perm[s];
-            if (j <= i || A.moved[j]) continue;          // padding (-1), counted once
-            const double r2 = pair_r2_exact(xi, yi, zi, A.x[j], A.y[j], A.z[j], gs);
-            if (!(r2 < r2max)) continue;
+        for (int64_t s = s0; s < s1; ++s) {          // each pair once: slot j > slot i
+            const double r2 = pair_r2_exact(xi, yi, zi, A.xr[s], A.xr[cs + s], A.xr[2 * cs + s], gs);
+            if (!(r2 < r2max)) continue;                 // also NaN: moved or padding
             const int k = rdf_bin(r2, e2, n, inv_dr);
-            const int ej = A.elem[j];
+            const int ej = A.er[s];
             if (lds)
                 atomicAdd(&s_h[(min(ei, ej) * A.E + max(ei, ej)) * n + k], 1u);
             else
@@ -214,13 +239,17 @@ void launch_rdf(Ctx* c, const double* x, const double* y, const double* z, const
     A.reach = r_max + 0.5 * c->cfg.skin;
     A.thr2 = 0.25 * c->cfg.skin * c->cfg.skin;
     A.moved = c->d_rdf_moved;
+    A.xr = c->d_rdf_xr;
+    A.er = c->d_rdf_er;
+    A.cap_slots = c->cap_slots;
     A.hist = hist;
     const size_t with = rdf_lds_bytes(c->E, n_bins, true);
     A.lds_hist = with <= kRdfLdsMax ? 1 : 0;
     const int nb = (int)div_up(c->N, kRdfBlock);
+    const int ns = (int)div_up(c->cap_slots, kRdfBlock);
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_rdf_flag, dim3(nb), dim3(kRdfBlock), 0, st, A);
-    hipLaunchKernelGGL(k_rdf_grid, dim3(nb), dim3(kRdfBlock),
+    hipLaunchKernelGGL(k_rdf_gather, dim3(ns), dim3(kRdfBlock), 0, st, A);
+    hipLaunchKernelGGL(k_rdf_grid, dim3(ns), dim3(kRdfBlock),
                        A.lds_hist ? with : rdf_lds_bytes(c->E, n_bins, false), st, A);
     hipLaunchKernelGGL(k_rdf_moved, dim3(nb), dim3(kRdfBlock), rdf_lds_bytes(c->E, n_bins, false),
                        st, A);
