@@ -51,10 +51,10 @@ def lib():
             L.orc_debye_length_nm.restype = f64
             L.orc_rates_from_fractions.argtypes = [i64, i32, P, P]
             L.orc_forces.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i32, P, P, P, i32,
-                                     P, P, P, P, P, P, P, i32]
+                                     P, P, P, P, P, P, P, i32, P, P, P]
             L.orc_forces.restype = i64
             L.orc_forces_rows.argtypes = [i64, P, P, P, i32, P, f64, P, P, P, P, P, i32, P, P,
-                                          P, i32, P, P, P, P, P, P, i32, P, i32]
+                                          P, i32, P, P, P, P, P, P, i32, P, i32, P, P, P]
             L.orc_forces_rows.restype = i64
             L.orc_pairs.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i64]
             L.orc_pairs.restype = i64
@@ -69,6 +69,8 @@ def lib():
                                           P, P, P, P, P, P]
             L.orc_ekin.argtypes = [i64, P, P, P, P, P, P]
             L.orc_hybrid_coeffs.argtypes = [f64, f64, f64, P]
+            L.orc_bonded.argtypes = [i64, P, i32, P, P, P, P, P, i64, P, P, i64, P, P, P, P, P,
+                                     P]
             L.orc_rdf_histogram.argtypes = [i64, P, i32, P, P, P, P, P, i32, f64, i32, P]
             L.orc_rdf_normalize.argtypes = [i32, f64, P, i64, i64, i32, f64, P]
             L.orc_structure_factor.argtypes = [i32, f64, P, f64, i32, P, P]
@@ -137,12 +139,68 @@ def hybrid_table(lambda_d, ne, n_q) -> np.ndarray:
     return out
 
 
+# ------------------------------------------------------------------ force-field terms
+
+class ForceField:
+    """Optional terms of section II.B (readings): ``inv_z`` [T] = 1/Z per type scales
+    the LJ radius of a pair by (c_i + c_j)/2, c = 1 - q/Z (Eq. 11); ``excl`` lists
+    the pairs (global atom indices) whose LJ term is omitted; ``bonds`` [n, 2] with
+    ``bond_par`` [n, 3] = (D_e, beta, b_e) and ``angles`` [n, 3] (middle atom second)
+    with ``angle_par`` [n, 2] = (k, theta0) are the Morse and harmonic-angle terms
+    (Eq. 9, Eq. 10)."""
+
+    def __init__(self, n_atoms, inv_z=None, excl=None, bonds=None, bond_par=None,
+                 angles=None, angle_par=None):
+        self.inv_z = None if inv_z is None else _c(inv_z, np.float64)
+        self.excl_off = self.excl = None
+        if excl is not None:
+            e = np.asarray(excl, dtype=np.int64).reshape(-1, 2)
+            both = np.concatenate([e, e[:, ::-1]])
+            both = both[np.lexsort((both[:, 1], both[:, 0]))]
+            both = np.unique(both, axis=0)
+            self.excl_off = _c(np.searchsorted(both[:, 0], np.arange(n_atoms + 1)), np.int64)
+            self.excl = _c(both[:, 1], np.int64)
+        z2 = np.zeros((0, 2), np.int32)
+        self.bonds = _c(z2 if bonds is None else bonds, np.int32)
+        self.bond_par = _c(np.zeros((0, 3)) if bond_par is None else bond_par, np.float64)
+        self.angles = _c(np.zeros((0, 3), np.int32) if angles is None else angles, np.int32)
+        self.angle_par = _c(np.zeros((0, 2)) if angle_par is None else angle_par, np.float64)
+
+    def args(self):
+        return _p(self.inv_z), _p(self.excl_off), _p(self.excl)
+
+
+def _ff_args(ff):
+    return (None, None, None) if ff is None else ff.args()
+
+
+def bonded(sys, ff, q=None, x=None, y=None, z=None):
+    """Forces and per-system energies of the bonded terms alone."""
+    x = _c(sys.x if x is None else x, np.float64)
+    y = _c(sys.y if y is None else y, np.float64)
+    z = _c(sys.z if z is None else z, np.float64)
+    q = _c(sys.q if q is None else q, np.int8)
+    n = x.shape[0]
+    out = {k: np.zeros(n) for k in ("fx", "fy", "fz")}
+    epot = np.zeros(sys.n_systems)
+    box = None if sys.box is None else _c(sys.box, np.float64)
+    lib().orc_bonded(sys.n_systems, _p(_c(sys.sys_offsets, np.int64)), int(sys.periodic), _p(box),
+                     _p(x), _p(y), _p(z), _p(q), ff.bonds.shape[0], _p(ff.bonds),
+                     _p(ff.bond_par), ff.angles.shape[0], _p(ff.angles), _p(ff.angle_par),
+                     _p(out["fx"]), _p(out["fy"]), _p(out["fz"]), _p(epot))
+    out["epot"] = epot
+    return out
+
+
 # ------------------------------------------------------------------ forces
 
-def forces(sys, q=None, kappa=None, x=None, y=None, z=None, per_atom=True, hybrid=None):
+def forces(sys, q=None, kappa=None, x=None, y=None, z=None, per_atom=True, hybrid=None,
+           ff=None):
     """Brute-force FP64 forces for all systems of ``sys`` at positions (x, y, z)
     (default: the system's own), charges q and per-system kappa; ``hybrid`` (a
-    ``hybrid_table``) switches the Coulomb term to the hybrid potential.
+    ``hybrid_table``) switches the Coulomb term to the hybrid potential; ``ff`` (a
+    ForceField) adds its LJ scaling and exclusions to the pair loop (its bonded terms
+    are separate: ``bonded``).
     Returns dict(fx, fy, fz, e_atom, a_atom, epot, npairs)."""
     x = _c(sys.x if x is None else x, np.float64)
     y = _c(sys.y if y is None else y, np.float64)
@@ -163,7 +221,7 @@ def forces(sys, q=None, kappa=None, x=None, y=None, z=None, per_atom=True, hybri
                               _p(_c(sys.c6, np.float64)), _p(_c(sys.c12, np.float64)),
                               _p(kappa), int(sys.screen_lj), _p(out["fx"]), _p(out["fy"]),
                               _p(out["fz"]), _p(out["e_atom"]), _p(out["a_atom"]), _p(epot),
-                              _p(hyb), n_q)
+                              _p(hyb), n_q, *_ff_args(ff))
     out["epot"] = epot
     out["npairs"] = int(npairs)
     return out
@@ -179,7 +237,7 @@ def _hyb(hybrid, B, q):
 
 
 def forces_rows(sys, rows, q=None, kappa=None, x=None, y=None, z=None, n_threads=0,
-                hybrid=None):
+                hybrid=None, ff=None):
     """F_i, e_i, A_i of the listed atoms against every atom of their system
     (OpenMP over rows)."""
     x = _c(sys.x if x is None else x, np.float64)
@@ -204,7 +262,8 @@ def forces_rows(sys, rows, q=None, kappa=None, x=None, y=None, z=None, n_threads
                                  _p(_c(sys.c6, np.float64)), _p(_c(sys.c12, np.float64)),
                                  _p(kappa), int(sys.screen_lj), _p(out["fx"]), _p(out["fy"]),
                                  _p(out["fz"]), _p(out["e_atom"]), _p(out["a_atom"]),
-                                 _p(out["row_hits"]), int(n_threads), _p(hyb), n_q)
+                                 _p(out["row_hits"]), int(n_threads), _p(hyb), n_q,
+                                 *_ff_args(ff))
     out["hits"] = int(hits)
     return out
 

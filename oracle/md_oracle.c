@@ -39,6 +39,10 @@
  *    outside, r' from Eq. 7, c1..c3 from matching value, slope and curvature at r';
  *    the energy of a pair is the mean of (charge j in the potential of ion i) and
  *    (charge i in the potential of ion j).
+ *  - Force-field terms of section II.B (readings): Lennard-Jones radii scaled with
+ *    the charge (Eq. 11), LJ omitted between atoms joined by a bond or an angle
+ *    (screened Coulomb kept), Morse bonds and harmonic angles scaled by the mean
+ *    charge of their atoms (Eq. 9, Eq. 10).
  *  - Radial distribution functions and partial structure factors (section II.C,
  *    Eq. 18): brute-force pair-distance histograms per element pair, their
  *    normalization against the ideal gas, and the sine transform of Eq. 18.
@@ -268,6 +272,47 @@ static inline void pair_phi_f(double r2, double qiqj_ke, double c6, double c12,
     }
 }
 
+/* Optional force-field terms of the pair loop (NULL members: off).
+ *   inv_z[t]   1/Z of type t: the LJ radius of a pair is scaled by s = (c_i + c_j)/2
+ *              with c = 1 - q / Z (Eq. 11), i.e. c6 -> c6 s^6, c12 -> c12 s^12;
+ *   excl_off, excl  per-atom sorted lists (CSR over global atom indices) of the
+ *              partners whose LJ term is omitted (bonded 1-2 and 1-3 pairs). */
+typedef struct {
+    const double* inv_z;
+    const int64_t* excl_off;
+    const int64_t* excl;
+} orc_ff;
+
+static int excluded(const orc_ff* ff, int64_t i, int64_t j)
+{
+    if (!ff || !ff->excl_off) return 0;
+    for (int64_t k = ff->excl_off[i]; k < ff->excl_off[i + 1]; ++k)
+        if (ff->excl[k] == j) return 1;
+    return 0;
+}
+
+/* c6, c12 of pair (i, j) after exclusion and charge scaling. */
+static void pair_lj(const orc_ff* ff, int64_t i, int64_t j, const int8_t* q, const uint8_t* type,
+                    int32_t n_types, const double* c6, const double* c12, double* a6, double* a12)
+{
+    int tt = type[i] * n_types + type[j];
+    *a6 = c6[tt];
+    *a12 = c12[tt];
+    if (excluded(ff, i, j)) {
+        *a6 = 0.0;
+        *a12 = 0.0;
+        return;
+    }
+    if (ff && ff->inv_z) {
+        double ci = 1.0 - (double)q[i] * ff->inv_z[type[i]];
+        double cj = 1.0 - (double)q[j] * ff->inv_z[type[j]];
+        double s = 0.5 * (ci + cj);
+        double s6 = s * s * s * s * s * s;
+        *a6 = *a6 * s6;
+        *a12 = *a12 * s6 * s6;
+    }
+}
+
 /* Brute-force forces and energies over all i<j pairs of every system.
  *   kappa[b]  screening constant of system b for this force evaluation.
  *   e_atom[i] = 1/2 sum_j phi_ij ;  a_atom[i] = sum_j |f_ij| r_ij ;
@@ -279,8 +324,11 @@ int64_t orc_forces(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
                    const double* c6, const double* c12, const double* kappa,
                    int32_t screen_lj, double* fx, double* fy, double* fz,
                    double* e_atom, double* a_atom, double* epot, const double* hyb,
-                   int32_t n_q)
+                   int32_t n_q, const double* inv_z, const int64_t* excl_off,
+                   const int64_t* excl)
 {
+    orc_ff ffv = {inv_z, excl_off, excl};
+    const orc_ff* ff = &ffv;
     int64_t npairs = 0;
     int64_t n = sys_off[n_sys];
     for (int64_t i = 0; i < n; ++i) {
@@ -298,15 +346,16 @@ int64_t orc_forces(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
                 double r2 = pair_r2(&g, x, y, z, i, j, d);
                 if (!(r2 < g.rc2)) continue;
                 if (r2 <= 0.0) abort();   /* coincident atoms: undefined */
-                int tt = type[i] * n_types + type[j];
+                double a6, a12;
+                pair_lj(ff, i, j, q, type, n_types, c6, c12, &a6, &a12);
                 double qq = ORC_KE * ((double)q[i] * (double)q[j]);
                 double phi, f;
                 if (hyb)
                     pair_phi_f_hybrid(r2, q[i], q[j], hyb + 4 * (b * n_q + q[i]),
-                                      hyb + 4 * (b * n_q + q[j]), c6[tt], c12[tt], kappa[b],
+                                      hyb + 4 * (b * n_q + q[j]), a6, a12, kappa[b],
                                       screen_lj, &phi, &f);
                 else
-                    pair_phi_f(r2, qq, c6[tt], c12[tt], kappa[b], screen_lj, &phi, &f);
+                    pair_phi_f(r2, qq, a6, a12, kappa[b], screen_lj, &phi, &f);
                 fx[i] += f * d[0]; fy[i] += f * d[1]; fz[i] += f * d[2];
                 fx[j] -= f * d[0]; fy[j] -= f * d[1]; fz[j] -= f * d[2];
                 if (e_atom) { e_atom[i] += 0.5 * phi; e_atom[j] += 0.5 * phi; }
@@ -334,8 +383,11 @@ int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_
                         const uint8_t* type, int32_t n_types, const double* c6,
                         const double* c12, const double* kappa, int32_t screen_lj,
                         double* fx, double* fy, double* fz, double* e_atom, double* a_atom,
-                        int64_t* row_hits, int32_t n_threads, const double* hyb, int32_t n_q)
+                        int64_t* row_hits, int32_t n_threads, const double* hyb, int32_t n_q,
+                        const double* inv_z, const int64_t* excl_off, const int64_t* excl)
 {
+    orc_ff ffv = {inv_z, excl_off, excl};
+    const orc_ff* ff = &ffv;
     int64_t hits = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -353,15 +405,16 @@ int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_
             double d[3];
             double r2 = pair_r2(&g, x, y, z, i, j, d);
             if (!(r2 < g.rc2)) continue;
-            int tt = type[i] * n_types + type[j];
+            double a6, a12;
+            pair_lj(ff, i, j, q, type, n_types, c6, c12, &a6, &a12);
             double qq = ORC_KE * ((double)q[i] * (double)q[j]);
             double phi, f;
             if (hyb)
                 pair_phi_f_hybrid(r2, q[i], q[j], hyb + 4 * (b * n_q + q[i]),
-                                  hyb + 4 * (b * n_q + q[j]), c6[tt], c12[tt], kappa[b], screen_lj,
+                                  hyb + 4 * (b * n_q + q[j]), a6, a12, kappa[b], screen_lj,
                                   &phi, &f);
             else
-                pair_phi_f(r2, qq, c6[tt], c12[tt], kappa[b], screen_lj, &phi, &f);
+                pair_phi_f(r2, qq, a6, a12, kappa[b], screen_lj, &phi, &f);
             F[0] += f * d[0]; F[1] += f * d[1]; F[2] += f * d[2];
             e += 0.5 * phi;
             a += fabs(f) * sqrt(r2);
@@ -397,6 +450,104 @@ int64_t orc_pairs(int64_t n_sys, const int64_t* sys_off, int32_t periodic, const
             }
     }
     return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bonded terms (section II.B, Eq. 9 and Eq. 10; readings)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Minimum-image separation a - b of two atoms of system geometry g. */
+static void bond_vec(const orc_geom* g, const double* x, const double* y, const double* z,
+                     int64_t a, int64_t b, double d[3])
+{
+    d[0] = x[a] - x[b];
+    d[1] = y[a] - y[b];
+    d[2] = z[a] - z[b];
+    if (g->periodic)
+        for (int k = 0; k < 3; ++k) d[k] = d[k] - g->L[k] * rint(d[k] * g->invL[k]);
+}
+
+/* Scale of a bonded term over n atoms: c = 1 - (sum of their charges)/n, clamped to
+ * [0, 1] (Eq. 9: 1 for neutral atoms, 0 once the mean charge reaches 1). */
+static double bonded_scale(const int8_t* q, const int32_t* atoms, int n)
+{
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += (double)q[atoms[k]];
+    double c = 1.0 - s / (double)n;
+    return c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
+}
+
+/* Morse bonds V = c D_e (1 - exp(-beta (r - b_e)))^2 (Eq. 10 read as the standard
+ * Morse form) and harmonic angles V = c k/2 (theta - theta0)^2 with theta the angle
+ * at the middle atom.  Forces are ADDED to fx, fy, fz; the energy of every term is
+ * added to epot of the system of its first atom (epot may be NULL). */
+void orc_bonded(int64_t n_sys, const int64_t* sys_off, int32_t periodic, const double* box,
+                const double* x, const double* y, const double* z, const int8_t* q,
+                int64_t n_bonds, const int32_t* bonds, const double* bond_par,
+                int64_t n_angles, const int32_t* angles, const double* angle_par,
+                double* fx, double* fy, double* fz, double* epot)
+{
+    for (int64_t t = 0; t < n_bonds; ++t) {
+        const int32_t* at = bonds + 2 * t;
+        int64_t i = at[0], j = at[1];
+        int64_t b = 0;
+        while (b + 1 < n_sys && sys_off[b + 1] <= i) ++b;
+        orc_geom g;
+        geom_init(&g, periodic, periodic ? box + 3 * b : NULL, 0.0);
+        double d[3];
+        bond_vec(&g, x, y, z, i, j, d);
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double De = bond_par[3 * t], beta = bond_par[3 * t + 1], be = bond_par[3 * t + 2];
+        double c = bonded_scale(q, at, 2);
+        double ex = exp(-beta * (r - be));
+        double u = 1.0 - ex;
+        double V = c * De * u * u;
+        double dVdr = c * 2.0 * De * u * beta * ex;
+        /* F_i = -dV/dr * d/r, F_j = -F_i */
+        for (int k = 0; k < 3; ++k) {
+            double fk = -dVdr * d[k] / r;
+            double* F = k == 0 ? fx : (k == 1 ? fy : fz);
+            F[i] += fk;
+            F[j] -= fk;
+        }
+        if (epot) epot[b] += V;
+    }
+    for (int64_t t = 0; t < n_angles; ++t) {
+        const int32_t* at = angles + 3 * t;
+        int64_t i = at[0], j = at[1], k = at[2];
+        int64_t b = 0;
+        while (b + 1 < n_sys && sys_off[b + 1] <= i) ++b;
+        orc_geom g;
+        geom_init(&g, periodic, periodic ? box + 3 * b : NULL, 0.0);
+        double a[3], e[3];
+        bond_vec(&g, x, y, z, i, j, a);
+        bond_vec(&g, x, y, z, k, j, e);
+        double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        double le = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        double cs = (a[0] * e[0] + a[1] * e[1] + a[2] * e[2]) / (la * le);
+        if (cs > 1.0) cs = 1.0;
+        if (cs < -1.0) cs = -1.0;
+        double th = acos(cs);
+        double kth = angle_par[2 * t], th0 = angle_par[2 * t + 1];
+        double c = bonded_scale(q, at, 3);
+        double V = 0.5 * c * kth * (th - th0) * (th - th0);
+        double dVdth = c * kth * (th - th0);
+        double sn = sqrt(1.0 - cs * cs);
+        if (epot) epot[b] += V;
+        if (sn < 1e-12) continue;          /* collinear: the gradient is undefined */
+        /* d(theta)/d(a) = -(e/(|a||e|) - cos a/|a|^2) / sin, likewise for e */
+        double Fi[3], Fk[3];
+        for (int m = 0; m < 3; ++m) {
+            Fi[m] = dVdth / sn * (e[m] / (la * le) - cs * a[m] / (la * la));
+            Fk[m] = dVdth / sn * (a[m] / (la * le) - cs * e[m] / (le * le));
+        }
+        double* F[3] = {fx, fy, fz};
+        for (int m = 0; m < 3; ++m) {
+            F[m][i] += Fi[m];
+            F[m][k] += Fk[m];
+            F[m][j] -= Fi[m] + Fk[m];
+        }
+    }
 }
 
 /* ------------------------------------------------------------------------ */

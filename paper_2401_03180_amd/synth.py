@@ -457,6 +457,42 @@ def methane_clusters(n_clusters: int = 256, n_steps: int = 2000, lo: int = 1000,
                    "%d vacuum CH4 clusters, %d atoms" % (n_clusters, pos.shape[0]))
 
 
+def molecular_force_field(sys: System, kind: str):
+    """Synthetic bonded topology and parameters for the molecules of a water or
+    methane workload (atoms of one molecule are consecutive: O H H or C H H H H):
+    Morse bonds to the heavy atom, harmonic H-X-H angles, LJ exclusions for the 1-2
+    and 1-3 pairs they define, Lennard-Jones tables for every element pair
+    (Lorentz-Berthelot), and Z per type for the charge scaling of the LJ radius.
+    Returns a dict of numpy arrays (global atom indices)."""
+    if kind == "water":
+        per, nh, Z = 3, 2, (8, 1)
+        sig, eps = (0.3166, 0.10), (0.65, 0.02)
+        bond = (450.0, 22.0, 0.1)                         # D_e kJ/mol, beta 1/nm, b_e nm
+        ang = (380.0, math.radians(109.47))               # k kJ/mol/rad^2, theta0
+    elif kind == "methane":
+        per, nh, Z = 5, 4, (6, 1)
+        sig, eps = (0.34, 0.25), (0.40, 0.10)
+        bond = (430.0, 18.0, 0.109)
+        ang = (330.0, math.acos(-1.0 / 3.0))
+    else:
+        raise ValueError(kind)
+    n = sys.n_atoms
+    assert n % per == 0
+    heavy = np.arange(0, n, per)
+    bonds = np.stack([np.repeat(heavy, nh),
+                      (heavy[:, None] + 1 + np.arange(nh)[None, :]).ravel()], 1)
+    pairs = [(a, b) for a in range(nh) for b in range(a + 1, nh)]
+    angles = np.array([(h + 1 + a, h, h + 1 + b) for h in heavy for a, b in pairs])
+    c6, c12 = lj_tables_lorentz_berthelot(sig, eps)
+    excl = np.concatenate([bonds, angles[:, [0, 2]]])
+    return {"bonds": bonds.astype(np.int32),
+            "bond_par": np.tile(np.array(bond), (bonds.shape[0], 1)),
+            "angles": angles.astype(np.int32),
+            "angle_par": np.tile(np.array(ang), (angles.shape[0], 1)),
+            "excl": excl.astype(np.int64), "c6": c6, "c12": c12,
+            "z": np.array(Z, dtype=np.int8)}
+
+
 EV_KJ_PER_MOL = 96.48533212      # 1 eV per particle in kJ/mol
 
 
