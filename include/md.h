@@ -318,6 +318,32 @@ md_status md_integrate_langevin(md_ctx* ctx, double dt, const double* inv_mass,
  * underflows).  Synchronous. */
 md_status md_bind_hybrid(md_ctx* ctx, const double* ne);
 
+/* Force-field terms of section II.B (readings: the paper names the terms; the forms
+ * of Eq. 9 and Eq. 10 are garbled).  Binds, replacing what was bound before (HOST
+ * arrays, global atom indices of the batch):
+ *   z_type [n_types]   atomic number per type, or NULL: the LJ radius of a pair is
+ *                      scaled by s = (c_i + c_j)/2 with c = 1 - q/Z (Eq. 11), i.e.
+ *                      c6 -> c6 s^6 and c12 -> c12 s^12 at the current charges;
+ *   excl [n_excl][2]   pairs whose LJ term is omitted (the bonded 1-2 and 1-3
+ *                      partners); their screened Coulomb term stays; needs
+ *                      n_types <= 7 (excluded pairs carry type n_types in the
+ *                      neighbour lists, which are rebuilt at the next build);
+ *   bonds [n_bonds][2] with bond_par [n_bonds][3] = (D_e kJ/mol, beta nm^-1, b_e nm):
+ *                      Morse bonds c D_e (1 - exp(-beta (r - b_e)))^2;
+ *   angles [n_angles][3] (middle atom second) with angle_par [n_angles][2] =
+ *                      (k kJ/mol/rad^2, theta0 rad): c k/2 (theta - theta0)^2;
+ * where c = max(0, 1 - (sum of the term's charges)/(its atom count)) (Eq. 9).
+ * md_screened_forces and md_step then add the bonded forces (FP64, one thread per
+ * atom over its terms: no atomics) and their energies to epot.  Every count may be
+ * 0 (that part is off).  Errors: MD_ERR_STATE before md_bind_tables; MD_ERR_ARG for
+ * an atom index out of range, a term whose atoms are in different systems or repeat,
+ * a parameter that is not finite, Z < 1, or exclusions with n_types > 7.  Graphs
+ * captured before the call hold the previous arrays: capture again.  Synchronous. */
+md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const int32_t* excl,
+                             int64_t n_excl, const int32_t* bonds, const double* bond_par,
+                             int64_t n_bonds, const int32_t* angles, const double* angle_par,
+                             int64_t n_angles);
+
 /* Pair-distance histogram for the radial distribution functions g_ab(r) behind the
  * partial structure factors of section II.C (Eq. 18).  Adds to hist (DEVICE uint64
  * [B][E][E][n_bins], not cleared: the caller zeroes it, or accumulates frames)

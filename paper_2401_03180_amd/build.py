@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["md_api.hip", "md_build.hip", "md_fast.hip", "md_rdf.hip", "md_force.hip", "md_step.hip"]
+SOURCES = ["md_api.hip", "md_build.hip", "md_fast.hip", "md_rdf.hip", "md_bonded.hip", "md_force.hip", "md_step.hip"]
 HEADERS = ["md_internal.h", "md_launch.h", "md_device.h"]
 LIB = os.path.join(HERE, "libmd_hip.so")
 ARCH = os.environ.get("MD_OFFLOAD_ARCH", "gfx950")

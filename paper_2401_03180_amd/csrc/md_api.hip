@@ -5,6 +5,8 @@
 #include <stdarg.h>
 
 #include <algorithm>
+#include <utility>
+#include <vector>
 #include <cstdio>
 #include <new>
 
@@ -58,7 +60,9 @@ void free_all(Ctx* c)
                     c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
                     c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
                     c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32, c->d_rdf_moved,
-                    c->d_rdf_xr, c->d_rdf_er};
+                    c->d_rdf_xr, c->d_rdf_er, c->d_invz32, c->d_invz64, c->d_excl_off,
+                    c->d_excl, c->d_bonds, c->d_bond_par, c->d_angles, c->d_angle_par,
+                    c->d_bt_off, c->d_bt, c->d_bond_e};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -169,6 +173,8 @@ md_status md_destroy(md_ctx* ctx)
     delete ctx;
     return MD_OK;
 }
+
+static md_status upload_lj(Ctx* c, int stride);
 
 static md_status size_and_allocate(Ctx* c)
 {
@@ -399,22 +405,21 @@ md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const
         if (!(lam > 0.0)) return fail(c, MD_ERR_ARG, "lambda_d must be > 0 (+inf: unscreened)");
         kappa[i] = isinf(lam) ? 0.0 : 1.0 / lam;
     }
-    std::vector<float> lj32(2 * T * T);
-    for (int i = 0; i < T * T; ++i) {
-        lj32[2 * i] = (float)c6[i];
-        lj32[2 * i + 1] = (float)c12[i];
-    }
-    HIP_TRY(c, dalloc(&c->d_c6, T * T));
-    HIP_TRY(c, dalloc(&c->d_c12, T * T));
-    HIP_TRY(c, dalloc(&c->d_lj32, 2 * T * T));
+    c->h_c6.assign(c6, c6 + T * T);
+    c->h_c12.assign(c12, c12 + T * T);
+    constexpr int TT = MD_MAX_TYPES * MD_MAX_TYPES;     // room for the padded layout
+    HIP_TRY(c, dalloc(&c->d_c6, TT));
+    HIP_TRY(c, dalloc(&c->d_c12, TT));
+    HIP_TRY(c, dalloc(&c->d_lj32, 2 * TT));
     HIP_TRY(c, dalloc(&c->d_qmax, E));
     HIP_TRY(c, dalloc(&c->d_kappa, B * S1));
     HIP_TRY(c, dalloc(&c->d_base, (int64_t)E * Q));
     HIP_TRY(c, dalloc(&c->d_g, B * S1));
     HIP_TRY(c, dalloc(&c->d_seeds, B));
-    HIP_TRY(c, hipMemcpy(c->d_c6, c6, sizeof(double) * T * T, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_c12, c12, sizeof(double) * T * T, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_lj32, lj32.data(), sizeof(float) * 2 * T * T, hipMemcpyHostToDevice));
+    {
+        const md_status ls = upload_lj(c, T);
+        if (ls != MD_OK) return ls;
+    }
     HIP_TRY(c, hipMemcpy(c->d_qmax, qmax, E, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_kappa, kappa.data(), sizeof(double) * B * S1, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_base, base, sizeof(double) * E * Q, hipMemcpyHostToDevice));
@@ -582,6 +587,176 @@ md_status md_bind_langevin(md_ctx* ctx, const double* gamma, const double* kt, d
         HIP_TRY(c, hipMemcpy(c->d_lg_kt, kt, sizeof(double) * BS, hipMemcpyHostToDevice));
     c->lg_dt = dt;
     c->langevin = true;
+    return MD_OK;
+}
+
+// Device LJ tables with row stride `stride` (T, or T + 1 with the all-zero
+// pseudo-type T that marks LJ-excluded pairs in the neighbour lists).
+static md_status upload_lj(Ctx* c, int stride)
+{
+    const int T = c->T;
+    std::vector<double> a6((size_t)stride * stride, 0.0), a12((size_t)stride * stride, 0.0);
+    std::vector<float> lj32(2 * (size_t)stride * stride, 0.0f);
+    for (int i = 0; i < T; ++i)
+        for (int j = 0; j < T; ++j) {
+            const size_t d = (size_t)i * stride + j;
+            a6[d] = c->h_c6[(size_t)i * T + j];
+            a12[d] = c->h_c12[(size_t)i * T + j];
+            lj32[2 * d] = (float)a6[d];
+            lj32[2 * d + 1] = (float)a12[d];
+        }
+    HIP_TRY(c, hipMemcpy(c->d_c6, a6.data(), sizeof(double) * a6.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_c12, a12.data(), sizeof(double) * a12.size(),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_lj32, lj32.data(), sizeof(float) * lj32.size(),
+                         hipMemcpyHostToDevice));
+    c->T_lj = stride;
+    return MD_OK;
+}
+
+md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const int32_t* excl,
+                             int64_t n_excl, const int32_t* bonds, const double* bond_par,
+                             int64_t n_bonds, const int32_t* angles, const double* angle_par,
+                             int64_t n_angles)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound) return fail(c, MD_ERR_STATE, "tables not bound");
+    if (n_excl < 0 || n_bonds < 0 || n_angles < 0) return fail(c, MD_ERR_ARG, "negative count");
+    if ((n_excl && !excl) || (n_bonds && (!bonds || !bond_par)) ||
+        (n_angles && (!angles || !angle_par)))
+        return fail(c, MD_ERR_ARG, "NULL array");
+    const int64_t N = c->N;
+    const int T = c->T;
+    if (n_excl > 0 && T >= MD_MAX_TYPES)
+        return fail(c, MD_ERR_ARG, "LJ exclusions need n_types <= %d", MD_MAX_TYPES - 1);
+    std::vector<int32_t> soa(N);
+    for (int b = 0; b < c->B; ++b)
+        for (int64_t a = c->sys_off[b]; a < c->sys_off[b + 1]; ++a) soa[a] = b;
+    auto check_term = [&](const int32_t* at, int n, const char* what, int64_t t) -> md_status {
+        for (int k = 0; k < n; ++k) {
+            if (at[k] < 0 || at[k] >= N)
+                return fail(c, MD_ERR_ARG, "%s %lld: atom %d out of range", what, (long long)t,
+                            at[k]);
+            if (soa[at[k]] != soa[at[0]])
+                return fail(c, MD_ERR_ARG, "%s %lld spans two systems", what, (long long)t);
+            for (int l = 0; l < k; ++l)
+                if (at[l] == at[k])
+                    return fail(c, MD_ERR_ARG, "%s %lld repeats atom %d", what, (long long)t,
+                                at[k]);
+        }
+        return MD_OK;
+    };
+    for (int64_t t = 0; t < n_excl; ++t) {
+        const md_status s = check_term(excl + 2 * t, 2, "exclusion", t);
+        if (s != MD_OK) return s;
+    }
+    for (int64_t t = 0; t < n_bonds; ++t) {
+        const md_status s = check_term(bonds + 2 * t, 2, "bond", t);
+        if (s != MD_OK) return s;
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(bond_par[3 * t + k]))
+                return fail(c, MD_ERR_ARG, "bond %lld: parameter not finite", (long long)t);
+    }
+    for (int64_t t = 0; t < n_angles; ++t) {
+        const md_status s = check_term(angles + 3 * t, 3, "angle", t);
+        if (s != MD_OK) return s;
+        for (int k = 0; k < 2; ++k)
+            if (!isfinite(angle_par[2 * t + k]))
+                return fail(c, MD_ERR_ARG, "angle %lld: parameter not finite", (long long)t);
+    }
+    if (z_type)
+        for (int t = 0; t < T; ++t)
+            if (z_type[t] < 1) return fail(c, MD_ERR_ARG, "Z of type %d must be >= 1", t);
+    HIP_TRY(c, hipDeviceSynchronize());          // no launch may still read the old data
+    auto csr = [&](std::vector<std::pair<int32_t, int32_t>>& e, int32_t** off, int32_t** lst)
+        -> md_status {
+        std::sort(e.begin(), e.end());
+        e.erase(std::unique(e.begin(), e.end()), e.end());
+        std::vector<int32_t> o(N + 1, 0), l(std::max<size_t>(e.size(), 1));
+        for (auto& p : e) ++o[p.first + 1];
+        for (int64_t a = 0; a < N; ++a) o[a + 1] += o[a];
+        for (size_t k = 0; k < e.size(); ++k) l[k] = e[k].second;
+        if (*off) { (void)hipFree(*off); *off = nullptr; }
+        if (*lst) { (void)hipFree(*lst); *lst = nullptr; }
+        HIP_TRY(c, dalloc(off, N + 1));
+        HIP_TRY(c, dalloc(lst, (int64_t)l.size()));
+        HIP_TRY(c, hipMemcpy(*off, o.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(*lst, l.data(), sizeof(int32_t) * l.size(), hipMemcpyHostToDevice));
+        return MD_OK;
+    };
+    // LJ exclusions: both directions, sorted, in the list build's pseudo-type
+    const bool had_excl = c->ff_excl;
+    c->ff_excl = n_excl > 0;
+    if (c->ff_excl) {
+        std::vector<std::pair<int32_t, int32_t>> e;
+        e.reserve(2 * n_excl);
+        for (int64_t t = 0; t < n_excl; ++t) {
+            e.emplace_back(excl[2 * t], excl[2 * t + 1]);
+            e.emplace_back(excl[2 * t + 1], excl[2 * t]);
+        }
+        const md_status s = csr(e, &c->d_excl_off, &c->d_excl);
+        if (s != MD_OK) return s;
+    }
+    {
+        const md_status s = upload_lj(c, c->ff_excl ? T + 1 : T);
+        if (s != MD_OK) return s;
+    }
+    if (had_excl || c->ff_excl) {
+        // the neighbour lists carry the exclusions: rebuild them at the next build
+        const int32_t one = 1;
+        HIP_TRY(c, hipMemcpy(&c->dsc->need_rebuild, &one, sizeof one, hipMemcpyHostToDevice));
+    }
+    // charge scaling of the LJ radius
+    c->ff_qlj = z_type != nullptr;
+    if (c->ff_qlj) {
+        float iz32[MD_MAX_TYPES] = {};
+        double iz64[MD_MAX_TYPES] = {};
+        for (int t = 0; t < T; ++t) {
+            iz64[t] = 1.0 / (double)z_type[t];
+            iz32[t] = (float)iz64[t];
+        }
+        if (!c->d_invz32) {
+            HIP_TRY(c, dalloc(&c->d_invz32, MD_MAX_TYPES));
+            HIP_TRY(c, dalloc(&c->d_invz64, MD_MAX_TYPES));
+        }
+        HIP_TRY(c, hipMemcpy(c->d_invz32, iz32, sizeof iz32, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_invz64, iz64, sizeof iz64, hipMemcpyHostToDevice));
+    }
+    // bonded terms and, per atom, the terms it takes part in
+    for (void* p : {(void*)c->d_bonds, (void*)c->d_bond_par, (void*)c->d_angles,
+                    (void*)c->d_angle_par})
+        if (p) (void)hipFree(p);
+    c->d_bonds = nullptr; c->d_bond_par = nullptr; c->d_angles = nullptr; c->d_angle_par = nullptr;
+    c->n_bonds = n_bonds;
+    c->n_angles = n_angles;
+    if (n_bonds + n_angles > 0) {
+        HIP_TRY(c, dalloc(&c->d_bonds, 2 * n_bonds));
+        HIP_TRY(c, dalloc(&c->d_bond_par, 3 * n_bonds));
+        HIP_TRY(c, dalloc(&c->d_angles, 3 * n_angles));
+        HIP_TRY(c, dalloc(&c->d_angle_par, 2 * n_angles));
+        if (n_bonds) {
+            HIP_TRY(c, hipMemcpy(c->d_bonds, bonds, sizeof(int32_t) * 2 * n_bonds,
+                                 hipMemcpyHostToDevice));
+            HIP_TRY(c, hipMemcpy(c->d_bond_par, bond_par, sizeof(double) * 3 * n_bonds,
+                                 hipMemcpyHostToDevice));
+        }
+        if (n_angles) {
+            HIP_TRY(c, hipMemcpy(c->d_angles, angles, sizeof(int32_t) * 3 * n_angles,
+                                 hipMemcpyHostToDevice));
+            HIP_TRY(c, hipMemcpy(c->d_angle_par, angle_par, sizeof(double) * 2 * n_angles,
+                                 hipMemcpyHostToDevice));
+        }
+        std::vector<std::pair<int32_t, int32_t>> inc;
+        inc.reserve(2 * n_bonds + 3 * n_angles);
+        for (int64_t t = 0; t < n_bonds; ++t)
+            for (int k = 0; k < 2; ++k) inc.emplace_back(bonds[2 * t + k], (int32_t)(t * 2));
+        for (int64_t t = 0; t < n_angles; ++t)
+            for (int k = 0; k < 3; ++k) inc.emplace_back(angles[3 * t + k], (int32_t)(t * 2 + 1));
+        const md_status s = csr(inc, &c->d_bt_off, &c->d_bt);
+        if (s != MD_OK) return s;
+        if (!c->d_bond_e) HIP_TRY(c, dalloc(&c->d_bond_e, N));
+    }
     return MD_OK;
 }
 

@@ -307,6 +307,7 @@ struct ForceFinalizeArgs {
     const double* fast_e;
     const int64_t* sys_off;
     DevScalars* dsc;
+    const double* bond_e;          // per-atom bonded energies (NULL: no bonded terms)
 };
 
 __device__ inline void force_finalize_block(const ForceFinalizeArgs& F)
@@ -324,6 +325,8 @@ __device__ inline void force_finalize_block(const ForceFinalizeArgs& F)
                 const int f = F.fast_list[k];
                 if (f >= a0 && f < a1) t += F.fast_e[k];
             }
+            if (F.bond_e)
+                for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) t += F.bond_e[a];
             for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
             __syncthreads();
             if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;

@@ -48,6 +48,9 @@ struct FastArgs {
     int screen_lj;
     const double* hyb64;           // hybrid screening rows (NULL: Debye)
     int hyb_q;
+    const double* invz64;          // 1/Z per type when the LJ radius scales with charge
+    const int32_t* excl_off;       // LJ exclusions per caller atom (NULL: none)
+    const int32_t* excl;
     const uint8_t* fast_flag;
     const int32_t* fast_list;
     double* fast_e;
@@ -60,10 +63,12 @@ struct FastArgs {
 // Exact membership and FP64 pair terms for d = p_a - p_b (minimum image); returns
 // false when the pair is outside the cutoff.  f multiplies d for the force on a.
 // hrow: hybrid-screening coefficient rows of the system and step (NULL: Debye).
+// ia, ib: caller indices of the two atoms (for the LJ exclusions).
 __device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double kap,
-                                 const double* hrow, double xa, double ya, double za, int qa,
-                                 int ta, double xb, double yb, double zb, int qb, int tb,
-                                 double* dx, double* dy, double* dz, double* f, double* e)
+                                 const double* hrow, int ia, int ib, double xa, double ya,
+                                 double za, int qa, int ta, double xb, double yb, double zb,
+                                 int qb, int tb, double* dx, double* dy, double* dz, double* f,
+                                 double* e)
 {
     double r2;
     {
@@ -79,7 +84,20 @@ __device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double ka
         *dx = ex; *dy = ey; *dz = ez;
     }
     if (!(r2 < A.rc2)) return false;
-    const double c6 = A.c6[ta * A.T + tb], c12 = A.c12[ta * A.T + tb];
+    double c6 = A.c6[ta * A.T + tb], c12 = A.c12[ta * A.T + tb];
+    if (A.excl_off) {
+        for (int x = A.excl_off[ia]; x < A.excl_off[ia + 1]; ++x)
+            if (A.excl[x] == ib) { c6 = 0.0; c12 = 0.0; break; }
+    }
+    if (A.invz64) {
+#pragma clang fp contract(off)
+        const double ca = 1.0 - (double)qa * A.invz64[ta];
+        const double cb = 1.0 - (double)qb * A.invz64[tb];
+        const double sc = 0.5 * (ca + cb);
+        const double s6 = sc * sc * sc * sc * sc * sc;
+        c6 = c6 * s6;
+        c12 = c12 * s6 * s6;
+    }
     if (hrow) {
         pair_terms_hybrid64(r2, kap, qa, qb, c6, c12, A.screen_lj != 0, hrow, A.hyb_q, f, e);
         return true;
@@ -190,7 +208,8 @@ __device__ void fast_self(const FastArgs& A, int fi)
             const double xa = A.xs[s];
             if (xa != xa) continue;                // fast atom or padding
             double dx, dy, dz, fp, e;
-            if (pair_fp64(A, gs, kap, hrow, xf, yf, zf, qf, tf, xa, A.xs[cs + s], A.xs[2 * cs + s],
+            if (pair_fp64(A, gs, kap, hrow, f, A.perm[s], xf, yf, zf, qf, tf, xa, A.xs[cs + s],
+                          A.xs[2 * cs + s],
                           A.qs[s], A.ts[s], &dx, &dy, &dz, &fp, &e)) {
                 Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
                 if (ENERGY) E += e;
@@ -204,7 +223,7 @@ __device__ void fast_self(const FastArgs& A, int fi)
         const int g = A.fast_list[k];
         if (g == f || g < a0 || g >= a1) continue;
         double dx, dy, dz, fp, e;
-        if (pair_fp64(A, gs, kap, hrow, xf, yf, zf, qf, tf, A.x[g], A.y[g], A.z[g], A.q[g],
+        if (pair_fp64(A, gs, kap, hrow, f, g, xf, yf, zf, qf, tf, A.x[g], A.y[g], A.z[g], A.q[g],
                       A.atype[g], &dx, &dy, &dz, &fp, &e)) {
             Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
             if (ENERGY) E += 0.5 * e;
@@ -309,12 +328,14 @@ __device__ void fast_nbr(const FastArgs& A, int col)
         if (xa != xa) continue;                    // fast atom or padding
         const double ya = A.xs[cs + s], za = A.xs[2 * cs + s];
         const int qa = A.qs[s], ta = A.ts[s];
+        const int ia = A.perm[s];
         double Fx = 0.0, Fy = 0.0, Fz = 0.0;
         bool any = false;
         for (int k = 0; k < total; ++k) {
             const int g = s_loc[k];
             double dx, dy, dz, fp, e;
-            if (pair_fp64(A, gs, kap, hrow, xa, ya, za, qa, ta, A.x[g], A.y[g], A.z[g], A.q[g],
+            if (pair_fp64(A, gs, kap, hrow, ia, g, xa, ya, za, qa, ta, A.x[g], A.y[g], A.z[g],
+                          A.q[g],
                           A.atype[g], &dx, &dy, &dz, &fp, &e)) {
                 Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
                 any = true;
@@ -349,7 +370,9 @@ void launch_fast(Ctx* c, const double* x, const double* y, const double* z, cons
     A.col_pre = c->d_col_pre; A.bin_start = c->d_bin_start; A.perm = c->d_perm;
     A.xs = c->d_xs; A.qs = c->d_qs; A.ts = c->d_ts; A.cap_slots = c->cap_slots;
     A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
-    A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T;
+    A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T_lj;
+    A.invz64 = c->ff_qlj ? c->d_invz64 : nullptr;
+    A.excl_off = c->ff_excl ? c->d_excl_off : nullptr; A.excl = c->d_excl;
     A.rc2 = c->cfg.rc * c->cfg.rc;
     A.reach = c->cfg.rc + 0.5 * c->cfg.skin;
     A.screen_lj = c->cfg.screen_lj;

@@ -21,6 +21,9 @@
 // hybrid ion-sphere / Debye potential of a charge-Q ion (section II.A, Eq. 4-7),
 // whose coefficients {r', c1, c2, c3} per (system, step, charge) are tabulated on the
 // host; the Lennard-Jones term is unchanged.
+// QLJ: the LJ radius of a pair is scaled by s = (c_i + c_j)/2 with c = 1 - q/Z per
+// atom (section II.B, Eq. 11): c6 -> c6 s^6, c12 -> c12 s^12.  LJ-excluded pairs
+// (bonded 1-2 and 1-3 partners) carry the all-zero pseudo-type in their list codes.
 #include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
@@ -92,6 +95,12 @@ struct ForceArgs {
     const float4* hyb32;
     const double* hyb64;
     int hyb_q;
+    // force-field terms
+    const float* invz32;         // 1/Z per type (QLJ)
+    const double* invz64;
+    const int32_t* excl_off;     // LJ exclusions per caller atom (NULL: none)
+    const int32_t* excl;
+    int t_excl;                  // pseudo-type of excluded pairs
 };
 
 __global__ void __launch_bounds__(256) k_force_finalize(ForceFinalizeArgs F)
@@ -182,7 +191,7 @@ __device__ inline double reduce8(double v)
 // row count.
 __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int il, int k, int ai,
                                float xi, float yi, float zi, int nent, const float4* s_j,
-                               const uint16_t* s_mask, int sentinel)
+                               const uint16_t* s_mask, int sentinel, const uint32_t* ent_g)
 {
     const int lane = threadIdx.x & 63;
     uint16_t* out = A.nb + (((int64_t)I * 2 + half) * kCluster + il) * A.nb_cap_h;
@@ -203,7 +212,13 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
         const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
         const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
         const int pos = cnt + __popc(mine & below);
-        if (pass && pos < cap) out[pos] = (uint16_t)(j | (__float_as_int(pj.w) << kCodeIdxBits));
+        int tcode = __float_as_int(pj.w);
+        if (A.excl_off && pass) {             // LJ-excluded partner: the pseudo-type
+            const int aj = A.perm[slot_of_code(ent_g, (uint32_t)j)];
+            for (int x = A.excl_off[ai]; x < A.excl_off[ai + 1]; ++x)
+                if (A.excl[x] == aj) { tcode = A.t_excl; break; }
+        }
+        if (pass && pos < cap) out[pos] = (uint16_t)(j | (tcode << kCodeIdxBits));
         cnt += __popc(mine);
     }
     int mx = cnt;
@@ -222,7 +237,8 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
 
 // LISTS: only (re)build the per-atom lists, for the FP64 kernel; does nothing
 // unless a rebuild is pending.  HYBRID: hybrid screening of the Coulomb term.
-template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool LISTS = false, bool HYBRID = false>
+template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool LISTS = false, bool HYBRID = false,
+          bool QLJ = false>
 __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 {
     extern __shared__ float4 s_j[];
@@ -243,6 +259,9 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
     if (LISTS && !rebuild) return;
     for (int i = tid; i < A.T * A.T; i += blockDim.x)
         s_lj[i] = make_float2(A.lj32[2 * i], A.lj32[2 * i + 1]);
+    __shared__ float s_invz[QLJ ? MD_MAX_TYPES : 1];
+    if (QLJ)
+        for (int i = tid; i < MD_MAX_TYPES; i += blockDim.x) s_invz[i] = A.invz32[i];
     const int sentinel = A.E_cap * kCluster;
     uint16_t* s_mask = reinterpret_cast<uint16_t*>(s_j + sentinel + 1);
     if (tid == 0) s_j[sentinel] = make_float4(kFarF, kFarF, kFarF, 0.0f);
@@ -337,6 +356,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         const int64_t slot_i = (int64_t)I * kCluster + il;
         float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f, qif = 0.0f;
         float4 hi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float ci = 1.0f;                       // QLJ: 1 - q_i / Z_i
         int tb = 0;
         if (act) {
             ai = A.perm[slot_i];
@@ -353,6 +373,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 xi = r[0]; yi = r[1]; zi = r[2];
                 qike = (float)(kKe * (double)A.qs[slot_i]);
                 tb = A.ts[slot_i] * A.T;
+                if (QLJ) ci = fmaf(-(float)A.qs[slot_i], s_invz[A.ts[slot_i]], 1.0f);
                 if (HYBRID) {
                     const int qv = A.qs[slot_i];
                     qif = (float)qv;
@@ -364,7 +385,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         if (rebuild) {
             if (act)
                 nr = build_half_list(A, I, half, cw, il, k8, ai, xi, yi, zi, gr.nent, s_j, s_mask,
-                                     sentinel);
+                                     sentinel, A.ent + (int64_t)g * A.E_cap);
             if (LISTS) {              // static group order (the force queue is not used)
                 __syncthreads();
                 g += gridDim.x;
@@ -418,6 +439,16 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 for (int u = 0; u < 4; ++u) pj[u] = s_j[idx[u]];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) lj[u] = s_lj[tb + tj[u]];
+                if (QLJ) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float cj = fmaf(-pj[u].w, s_invz[tj[u]], 1.0f);
+                        const float sc = 0.5f * (ci + cj);
+                        const float s2 = sc * sc, s6 = s2 * s2 * s2;
+                        lj[u].x *= s6;
+                        lj[u].y *= s6 * s6;
+                    }
+                }
                 float dx[4], dy[4], dz[4], r2[4];
                 bool in[4], amb[4];
 #pragma unroll
@@ -545,7 +576,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 
 // ------------------------------------------------------------------ FP64 kernel
 
-template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool HYBRID = false>
+template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool HYBRID = false, bool QLJ = false>
 __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
 {
     __shared__ double s_e[kMaxGroup];
@@ -606,7 +637,16 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
                     emit_pairs(true, ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit,
                                A.emit_max);
                 const int tj = (int)(code >> kCodeIdxBits);
-                const double c6 = A.c6[ti * A.T + tj], c12 = A.c12[ti * A.T + tj];
+                double c6 = A.c6[ti * A.T + tj], c12 = A.c12[ti * A.T + tj];
+                if (QLJ) {
+#pragma clang fp contract(off)
+                    const double ci = 1.0 - (double)qi_n * A.invz64[ti];
+                    const double cj = 1.0 - (double)A.qs[slot_j] * A.invz64[tj];
+                    const double sc = 0.5 * (ci + cj);
+                    const double s6 = sc * sc * sc * sc * sc * sc;
+                    c6 = c6 * s6;
+                    c12 = c12 * s6 * s6;
+                }
                 double f, e;
                 if (HYBRID) {
                     pair_terms_hybrid64(r2, kap, qi_n, A.qs[slot_j], c6, c12, SCREEN_LJ, hrow,
@@ -681,6 +721,10 @@ static void set_lds_attr(size_t lds)
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute((const void*)k_force32<E, M, S, false, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_force32<E, M, S, false, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_force32<E, M, S, false, true, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t force_kernel_setup(Ctx* c)
@@ -688,9 +732,9 @@ hipError_t force_kernel_setup(Ctx* c)
     hipFuncAttributes fa;
     if (hipFuncGetAttributes(&fa, (const void*)k_force32<true, false, true>) == hipSuccess)
         c->force32_static_lds = fa.sharedSizeBytes;
-    if (hipFuncGetAttributes(&fa, (const void*)k_force32<true, false, true, false, true>) ==
+    if (hipFuncGetAttributes(&fa, (const void*)k_force32<true, false, true, false, true, true>) ==
         hipSuccess)
-        c->force32_static_lds_h = fa.sharedSizeBytes;
+        c->force32_static_lds_h = fa.sharedSizeBytes;      // the largest variant
     const size_t lds = force32_lds_bytes(c->E_cap);
     set_lds_attr<false, false, false>(lds); set_lds_attr<false, false, true>(lds);
     set_lds_attr<true, false, false>(lds);  set_lds_attr<true, false, true>(lds);
@@ -701,27 +745,33 @@ hipError_t force_kernel_setup(Ctx* c)
     return hipGetLastError();
 }
 
-template <bool E, bool M, bool S, bool H>
+template <bool E, bool M, bool S, bool H, bool Q>
 static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks, hipStream_t st)
 {
     if (prec == MD_FP32_KAHAN)
-        hipLaunchKernelGGL((k_force32<E, M, S, false, H>), dim3(blocks), dim3(64 * c->G * A.wpc),
-                           force32_lds_bytes(c->E_cap), st, A);
+        hipLaunchKernelGGL((k_force32<E, M, S, false, H, Q>), dim3(blocks),
+                           dim3(64 * c->G * A.wpc), force32_lds_bytes(c->E_cap), st, A);
     else
-        hipLaunchKernelGGL((k_force64<E, M, S, H>), dim3(blocks), dim3(64 * c->G), 0, st, A);
+        hipLaunchKernelGGL((k_force64<E, M, S, H, Q>), dim3(blocks), dim3(64 * c->G), 0, st, A);
 }
 
 template <bool E, bool M, bool S>
 static void launch_sh(Ctx* c, md_precision prec, const ForceArgs& A, int blocks, hipStream_t st)
 {
-    if (c->hybrid) launch_one<E, M, S, true>(c, prec, A, blocks, st);
-    else launch_one<E, M, S, false>(c, prec, A, blocks, st);
+    if (c->hybrid) {
+        if (c->ff_qlj) launch_one<E, M, S, true, true>(c, prec, A, blocks, st);
+        else launch_one<E, M, S, true, false>(c, prec, A, blocks, st);
+    } else {
+        if (c->ff_qlj) launch_one<E, M, S, false, true>(c, prec, A, blocks, st);
+        else launch_one<E, M, S, false, false>(c, prec, A, blocks, st);
+    }
 }
 
 ForceFinalizeArgs force_finalize_args(Ctx* c, double* epot)
 {
     return ForceFinalizeArgs{c->d_grp_epot, epot, c->d_sys_grp0, c->B, c->d_fast_list,
-                             c->d_fast_e, c->d_sys_off, c->dsc};
+                             c->d_fast_e, c->d_sys_off, c->dsc,
+                             c->n_bonds + c->n_angles > 0 ? c->d_bond_e : nullptr};
 }
 
 hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const double* y,
@@ -733,7 +783,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     A.groups = c->d_groups; A.ent = c->d_ent; A.nb = c->d_nb; A.cl_nt = c->d_cl_nt;
     A.perm = c->d_perm; A.slot_img = c->d_slot_img; A.xs = c->d_xs; A.qs = c->d_qs; A.ts = c->d_ts;
     A.grid = c->d_grid; A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
-    A.lj32 = c->d_lj32; A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T;
+    A.lj32 = c->d_lj32; A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T_lj;
     A.rc2 = c->cfg.rc * c->cfg.rc;
     A.E_cap = c->E_cap; A.cap_slots = c->cap_slots;
     A.fx = fx; A.fy = fy; A.fz = fz;
@@ -742,6 +792,8 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     A.wpc = kMaxWpc;
     A.cl_len = c->d_cl_len; A.ent_mask = c->d_ent_mask; A.nb_cap_h = c->nb_cap_h;
     A.hyb32 = c->d_hyb32; A.hyb64 = c->d_hyb64; A.hyb_q = c->hyb_q;
+    A.invz32 = c->d_invz32; A.invz64 = c->d_invz64;
+    A.excl_off = c->ff_excl ? c->d_excl_off : nullptr; A.excl = c->d_excl; A.t_excl = c->T;
     {
         const double m = c->rlist * (1.0 + 1e-5);
         A.thr2 = (float)(m * m);
@@ -781,6 +833,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
         if (e != hipSuccess) return e;
     }
     if (c->fast_cap > 0) launch_fast(c, x, y, z, q, fx, fy, fz, E, emit, emit_max, st);
+    if (c->n_bonds + c->n_angles > 0) launch_bonded(c, x, y, z, q, fx, fy, fz, st);
     if (finalize)
         hipLaunchKernelGGL(k_force_finalize, dim3(1), dim3(256), 0, st,
                            force_finalize_args(c, epot));

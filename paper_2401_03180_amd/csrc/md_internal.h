@@ -93,6 +93,21 @@ struct Ctx {
     double* d_hyb64 = nullptr;     // B*(S+1)*hyb_q*4
     float4* d_hyb32 = nullptr;     // B*(S+1)*hyb_q
     uint8_t* d_rdf_moved = nullptr;   // N: atoms beyond skin/2 of the build (histogram pass)
+    // force-field terms (bound by md_bind_forcefield)
+    int32_t T_lj = 0;              // stride of the LJ tables: T, or T + 1 with exclusions
+                                   // (type T is the "LJ excluded" pseudo-type, all zero)
+    bool ff_qlj = false;           // LJ radius scaled with the charge
+    float* d_invz32 = nullptr;     // MD_MAX_TYPES: 1/Z per type (0 for the pseudo-type)
+    double* d_invz64 = nullptr;
+    bool ff_excl = false;
+    int32_t* d_excl_off = nullptr; // N+1: per-atom LJ-excluded partners (CSR, sorted)
+    int32_t* d_excl = nullptr;
+    int64_t n_bonds = 0, n_angles = 0;
+    int32_t* d_bonds = nullptr;    double* d_bond_par = nullptr;      // [n][2], [n][3]
+    int32_t* d_angles = nullptr;   double* d_angle_par = nullptr;     // [n][3], [n][2]
+    int32_t* d_bt_off = nullptr;   // N+1: per-atom incident bonded terms (CSR)
+    int32_t* d_bt = nullptr;       // term id * 2 + kind (0 bond, 1 angle)
+    double* d_bond_e = nullptr;    // N: energy of the bonded terms whose first atom is a
     double* d_rdf_xr = nullptr;       // cap_slots*3: slot-order current positions
     uint8_t* d_rdf_er = nullptr;      // cap_slots: slot-order elements
     int cap_bar = 0;               // arrival words of its barrier
@@ -105,6 +120,7 @@ struct Ctx {
     std::vector<int64_t> sys_off;
     std::vector<double> box;       // B*3 (periodic)
     std::vector<double> lambda_d;  // B*(S+1) Debye lengths as bound (nm; +inf: unscreened)
+    std::vector<double> h_c6, h_c12;   // T*T as bound
     int64_t n_steps = 0;
     int32_t T = 0, E = 0, Q = 0;
     int32_t G = 4;                 // i-clusters per group

@@ -31,7 +31,7 @@ EXPORTED = (
     "md_integrate_vv", "md_sync_check", "md_clear_flags", "md_debug_pairs", "md_get_stats",
     "md_force_timer_start", "md_force_timer_read", "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
     "md_rates_from_fractions", "md_bind_langevin", "md_integrate_langevin", "md_bind_hybrid",
-    "md_rdf_histogram", "md_rdf_normalize", "md_structure_factor",
+    "md_rdf_histogram", "md_rdf_normalize", "md_structure_factor", "md_bind_forcefield",
 )
 
 
@@ -101,6 +101,7 @@ def lib():
             "md_bind_langevin": [P, P, P, f64],
             "md_bind_hybrid": [P, P],
             "md_rdf_histogram": [P, P, P, P, P, f64, i32, P, P],
+            "md_bind_forcefield": [P, P, P, i64, P, P, i64, P, P, i64],
             "md_rdf_normalize": [i32, f64, P, i64, i64, i32, f64, P],
             "md_structure_factor": [i32, f64, P, f64, i32, P, P],
             "md_integrate_langevin": [P, f64, P, P, P, P, P, P, P, P, P, P, P, P, P],
@@ -210,6 +211,25 @@ def md_bind_hybrid(ctx, ne):
         return
     n = np.ascontiguousarray(ne, dtype=np.float64)
     _check(ctx, lib().md_bind_hybrid(ctx, n.ctypes.data))
+
+
+def md_bind_forcefield(ctx, z_type=None, excl=None, bonds=None, bond_par=None, angles=None,
+                       angle_par=None):
+    """Host arrays (see include/md.h); None disables a part."""
+    def arr(a, dt, cols):
+        if a is None:
+            return None, 0
+        v = np.ascontiguousarray(np.asarray(a, dtype=dt).reshape(-1, cols))
+        return v, v.shape[0]
+    z = None if z_type is None else np.ascontiguousarray(z_type, dtype=np.int8)
+    ex, nex = arr(excl, np.int32, 2)
+    bo, nbo = arr(bonds, np.int32, 2)
+    bp, _ = arr(bond_par, np.float64, 3)
+    an, nan_ = arr(angles, np.int32, 3)
+    ap, _ = arr(angle_par, np.float64, 2)
+    ptr = lambda v: None if v is None else v.ctypes.data
+    _check(ctx, lib().md_bind_forcefield(ctx, ptr(z), ptr(ex), nex, ptr(bo), ptr(bp), nbo,
+                                         ptr(an), ptr(ap), nan_))
 
 
 def md_rdf_histogram(ctx, x, y, z, elem, r_max, n_bins, hist, stream=None):
@@ -413,6 +433,14 @@ class Engine:
             md_graph_destroy(g)
         self.graphs = {}
         md_bind_hybrid(self.ctx, ne)
+
+    def bind_forcefield(self, **kw):
+        """md_bind_forcefield with keyword arrays (z_type, excl, bonds, bond_par,
+        angles, angle_par); graphs captured before are dropped."""
+        for g in self.graphs.values():
+            md_graph_destroy(g)
+        self.graphs = {}
+        md_bind_forcefield(self.ctx, **kw)
 
     def rdf(self, r_max, n_bins, hist=None, stream=None):
         """Pair-distance histogram [B, E, E, n_bins] (int64 tensor; added to `hist`

@@ -1,0 +1,276 @@
+"""GPU parity of the force-field terms of section II.B (readings): charge-scaled LJ
+radii (Eq. 11), LJ exclusions of bonded 1-2 and 1-3 partners, Morse bonds and
+harmonic angles scaled by the mean charge (Eq. 9, Eq. 10), through the C ABI against
+the oracle on the same seeded inputs.  Per-atom error of the total force relative to
+A_i + |F_bonded,i| <= 1e-10 (FP64 path) / 1e-5 (FP32 path); energies to the same bar;
+pair sets unchanged."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_03180_amd import synth
+from gpu_util import oracle_kappa, random_charges, require_gpu, say, sorted_pairs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-5}
+PRECS = [0, 1]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def with_ff(s, kind, parts=("z", "excl", "bonds", "angles")):
+    """The system with its full LJ tables, the oracle's ForceField and the binding
+    arguments for the chosen parts."""
+    d = synth.molecular_force_field(s, kind)
+    s.c6, s.c12 = d["c6"], d["c12"]
+    kw = {}
+    if "z" in parts:
+        kw["z_type"] = d["z"]
+    if "excl" in parts:
+        kw["excl"] = d["excl"]
+    if "bonds" in parts:
+        kw["bonds"], kw["bond_par"] = d["bonds"], d["bond_par"]
+    if "angles" in parts:
+        kw["angles"], kw["angle_par"] = d["angles"], d["angle_par"]
+    ff = oracle.ForceField(s.n_atoms, inv_z=1.0 / d["z"] if "z" in parts else None,
+                           excl=kw.get("excl"), bonds=kw.get("bonds"),
+                           bond_par=kw.get("bond_par"), angles=kw.get("angles"),
+                           angle_par=kw.get("angle_par"))
+    return ff, kw
+
+
+def make_engine(sys, prec, **kw):
+    from paper_2401_03180_amd.md import Engine
+    return Engine(sys, prec, **kw)
+
+
+def set_q(eng, q):
+    import torch
+    eng.q.copy_(torch.as_tensor(q, dtype=torch.int8))
+
+
+def reference(s, ff, k, q=None, x=None, y=None, z=None):
+    nb = oracle.forces(s, q=q, kappa=oracle_kappa(s, k), x=x, y=y, z=z, ff=ff)
+    bo = oracle.bonded(s, ff, q=q, x=x, y=y, z=z)
+    F = [nb[c] + bo[c] for c in ("fx", "fy", "fz")]
+    scale = nb["a_atom"] + np.sqrt(bo["fx"] ** 2 + bo["fy"] ** 2 + bo["fz"] ** 2)
+    return F, nb["epot"] + bo["epot"], scale, nb
+
+
+def check(eng, s, prec, ff, k, x=None, y=None, z=None):
+    eng.forces(prec=prec, energy=True)
+    eng.sync_check()
+    F = [eng.host(c) for c in ("fx", "fy", "fz")]
+    ref, epot, scale, nb = reference(s, ff, k, q=eng.host("q"), x=x, y=y, z=z)
+    d = np.sqrt(sum((a - b) ** 2 for a, b in zip(F, ref)))
+    assert np.all(d[scale == 0] == 0.0)
+    err = np.max(d[scale > 0] / scale[scale > 0])
+    assert err <= TOL[prec], err
+    got = eng.host("epot")
+    for b in range(s.n_systems):
+        a0, a1 = s.sys_offsets[b], s.sys_offsets[b + 1]
+        esc = 2 * np.abs(nb["e_atom"][a0:a1]).sum() + abs(epot[b])
+        assert abs(got[b] - epot[b]) <= TOL[prec] * esc, b
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_methane_clusters_forcefield(prec):
+    s = synth.methane_clusters(n_clusters=5, lo=300, hi=4000, n_steps=4)
+    s.q = random_charges(s, 6, hi=4)
+    ff, kw = with_ff(s, "methane")
+    say("forcefield methane prec", prec)
+    eng = make_engine(s, prec, density_hint=100.0)
+    eng.bind_forcefield(**kw)
+    set_q(eng, s.q)
+    eng.set_step(2)
+    eng.build()
+    check(eng, s, prec, ff, 2)
+    assert np.array_equal(sorted_pairs(eng.debug_pairs(prec=prec)), oracle.pairs(s))
+    eng.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_water_box_forcefield(prec):
+    """Periodic water: bonds and angles that cross the box boundary."""
+    s = synth.water_small(n_steps=4)
+    s.q = random_charges(s, 7, hi=5)
+    ff, kw = with_ff(s, "water")
+    say("forcefield water prec", prec)
+    eng = make_engine(s, prec)
+    eng.bind_forcefield(**kw)
+    set_q(eng, s.q)
+    eng.set_step(1)
+    eng.build()
+    check(eng, s, prec, ff, 1)
+    eng.close()
+
+
+@pytest.mark.parametrize("parts", [("z",), ("excl",), ("bonds", "angles")])
+def test_forcefield_parts_alone(parts):
+    s = synth.water_small(n_steps=4)
+    s.q = random_charges(s, 9, hi=5)
+    ff, kw = with_ff(s, "water", parts)
+    say("forcefield parts", parts)
+    eng = make_engine(s, 0)
+    eng.bind_forcefield(**kw)
+    set_q(eng, s.q)
+    eng.set_step(1)
+    eng.build()
+    check(eng, s, 0, ff, 1)
+    eng.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_forcefield_fast_atoms(prec):
+    """Displaced atoms beyond skin/2 go through the fast-atom kernels, which apply
+    the exclusions and the charge scaling themselves."""
+    from paper_2401_03180_amd import md
+    from test_gpu_parity import _displace, _fast_case
+    s, disp, fast = _fast_case(True, 30, 131)
+    s.q = random_charges(s, 132, hi=5)
+    ff, kw = with_ff(s, "water")
+    say("forcefield fast atoms prec", prec)
+    eng = make_engine(s, prec, fast_capacity=64)
+    eng.bind_forcefield(**kw)
+    set_q(eng, s.q)
+    eng.set_step(0)
+    eng.build()
+    _displace(eng, s, disp)
+    eng.build(md.MD_BUILD_AUTO)
+    assert eng.stats()["n_fast"] == fast.size
+    x, y, z = eng.host("x"), eng.host("y"), eng.host("z")
+    check(eng, s, prec, ff, 1, x=x, y=y, z=z)
+    eng.close()
+
+
+def test_forcefield_trajectory_against_oracle():
+    """Twelve fused FP64 steps of bonded methane clusters with ionization: charges
+    bit-exact, positions within 1e-9 nm."""
+    s = synth.methane_clusters(n_clusters=3, lo=300, hi=1500, n_steps=12)
+    s.base[:] = np.where(s.base > 0, 0.3, 0.0)
+    ff, kw = with_ff(s, "methane")
+    say("forcefield trajectory")
+    eng = make_engine(s, 0, density_hint=100.0)
+    eng.bind_forcefield(**kw)
+    eng.set_step(0)
+    eng.build()
+    eng.forces(energy=True)
+    x, y, z = s.x.copy(), s.y.copy(), s.z.copy()
+    vx, vy, vz = s.vx.copy(), s.vy.copy(), s.vz.copy()
+    q = s.q.copy()
+    kap = oracle.kappa_from_lambda(s.lambda_d)
+
+    def total(step):
+        nb = oracle.forces(s, q=q, kappa=kap[:, step], x=x, y=y, z=z, ff=ff)
+        bo = oracle.bonded(s, ff, q=q, x=x, y=y, z=z)
+        return tuple(nb[c] + bo[c] for c in ("fx", "fy", "fz")), nb["epot"] + bo["epot"]
+
+    F, _ = total(0)
+    for step in range(1, 13):
+        eng.step(build_mode=0)
+        oracle.vv(0, s.dt, s.inv_mass, F, (x, y, z), (vx, vy, vz))
+        oracle.ionize(s, q, step)
+        F, ep = total(step)
+        oracle.vv(1, s.dt, s.inv_mass, F, (x, y, z), (vx, vy, vz))
+        assert np.array_equal(eng.host("q"), q), step
+        assert np.allclose(eng.host("epot"), ep, rtol=1e-9, atol=1e-6), step
+    for n, ref in zip(("x", "y", "z"), (x, y, z)):
+        assert np.max(np.abs(eng.host(n) - ref)) < 1e-9, n
+    eng.sync_check()
+    eng.close()
+
+
+def test_forcefield_graph_replay_and_unbind():
+    import torch
+    from paper_2401_03180_amd.md import md_graph_launch
+    s = synth.water_small(n_steps=8)
+    s.q = random_charges(s, 12, hi=5)
+    ff, kw = with_ff(s, "water")
+    say("forcefield graph vs eager")
+    ea, eb = make_engine(s, 1), make_engine(s, 1)
+    for e in (ea, eb):
+        e.bind_forcefield(**kw)
+        set_q(e, s.q)
+        e.set_step(0)
+        e.build()
+        e.forces(energy=False)
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        g = eb.graph(0, st, energy=True)
+    for step in range(5):
+        ea.step(build_mode=0, energy=True, ekin=False)
+        torch.cuda.synchronize()
+        md_graph_launch(g, st)
+        st.synchronize()
+        for n in ("x", "vx", "q", "fx", "epot"):
+            assert np.array_equal(ea.host(n), eb.host(n)), (step, n)
+    # unbinding everything returns to the plain pair terms (lists rebuilt first)
+    ea.bind_forcefield()
+    ea.build()
+    ea.forces(energy=True)
+    x, y, z, q = ea.host("x"), ea.host("y"), ea.host("z"), ea.host("q")
+    ref = oracle.forces(s, q=q, x=x, y=y, z=z, kappa=oracle_kappa(s, 5))
+    F = [ea.host(c) for c in ("fx", "fy", "fz")]
+    d = np.sqrt(sum((a - ref[c]) ** 2 for a, c in zip(F, ("fx", "fy", "fz"))))
+    assert np.max(d / ref["a_atom"]) <= TOL[1]
+    for e in (ea, eb):
+        e.sync_check()
+        e.close()
+
+
+def test_forcefield_argument_errors():
+    from paper_2401_03180_amd import md
+    s = synth.methane_clusters(n_clusters=2, lo=300, hi=400, n_steps=2)
+    say("forcefield argument errors")
+    eng = make_engine(s, 1, density_hint=100.0)
+    n0 = int(s.sys_offsets[1])
+    bad = [dict(bonds=[[0, s.n_atoms]], bond_par=[[1.0, 1.0, 0.1]]),
+           dict(bonds=[[0, n0]], bond_par=[[1.0, 1.0, 0.1]]),               # two systems
+           dict(angles=[[1, 0, 1]], angle_par=[[1.0, 1.9]]),                # repeated atom
+           dict(bonds=[[0, 1]], bond_par=[[np.nan, 1.0, 0.1]]),
+           dict(z_type=[6, 0])]
+    for kw in bad:
+        with pytest.raises(md.MDError) as e:
+            eng.bind_forcefield(**kw)
+        assert e.value.status == md.MD_ERR_ARG, kw
+    eng.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_methane_full_size_forcefield_sampled(prec):
+    """256 bonded methane clusters (1.73 M atoms): 300 graph-replayed steps with
+    ionization, then sampled rows of the total force against the oracle."""
+    import torch
+    from paper_2401_03180_amd import md
+    s = synth.methane_clusters(n_steps=400)
+    ff, kw = with_ff(s, "methane")
+    say("forcefield methane_256 sampled rows prec", prec)
+    eng = make_engine(s, prec, density_hint=100.0)
+    eng.bind_forcefield(**kw)
+    st = torch.cuda.Stream()
+    steps = 300
+    with torch.cuda.stream(st):
+        eng.set_step(0, st)
+        eng.build(md.MD_BUILD_FORCE, st)
+        eng.forces(energy=True, stream=st)
+        g = eng.graph(md.MD_BUILD_AUTO, st, energy=True, ekin=True)
+        for _ in range(steps):
+            md.md_graph_launch(g, st)
+        st.synchronize()
+    assert eng.sync_check(raise_on_flags=False) == 0
+    F = [eng.host(c) for c in ("fx", "fy", "fz")]
+    x, y, z, q = eng.host("x"), eng.host("y"), eng.host("z"), eng.host("q")
+    rows = np.sort(np.random.default_rng(77).choice(s.n_atoms, 400, replace=False))
+    nb = oracle.forces_rows(s, rows, q=q, x=x, y=y, z=z, kappa=oracle_kappa(s, steps), ff=ff)
+    bo = oracle.bonded(s, ff, q=q, x=x, y=y, z=z)
+    d = np.sqrt(sum((F[k][rows] - (nb[c] + bo[c][rows])) ** 2
+                    for k, c in enumerate(("fx", "fy", "fz"))))
+    scale = nb["a_atom"] + np.sqrt(bo["fx"][rows] ** 2 + bo["fy"][rows] ** 2 +
+                                   bo["fz"][rows] ** 2)
+    assert np.max(d / scale) <= TOL[prec]
+    eng.close()
