@@ -28,6 +28,7 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector (256 CU x 2.4 GHz x 256 F
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 FLOP_PER_PAIR = 44                # forces 42 + energy 2, per pair inside the cutoff
 FLOP_PER_PAIR_HYBRID = 57         # hybrid screening (Debye branch on both ions): 55 + 2
+FLOP_QLJ_EXTRA = 10               # charge-scaled LJ radius: c_j 2, s 2, s^6 3, c6/c12 3
 METRIC = "atom-steps/s for screened-force+ionize step; % FP32 VALU peak; FP32-vs-FP64 speedup"
 
 
@@ -54,7 +55,7 @@ STATE = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q")
 
 
 def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_graph=True,
-            fast_capacity=0, langevin=None, hybrid=None):
+            fast_capacity=0, langevin=None, hybrid=None, ff=None):
     """Timed region: `steps` replays of the captured step graph (or, with use_graph
     False, `steps` eager md_step calls), inputs resident.
     Then the same steps are replayed eagerly from a snapshot of the state at the
@@ -64,7 +65,8 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
     duration of every force-kernel launch.  Pair counts are sampled between steps
     of the replay (where no list rebuild is pending).  langevin: (gamma, kt) tables
     of the electron-ion coupling, bound for the whole run, or None; hybrid: the
-    free-electron density table of hybrid screening, or None."""
+    free-electron density table of hybrid screening, or None; ff: md_bind_forcefield
+    keyword arrays, or None."""
     import torch
     from paper_2401_03180_amd import md
     eng = md.Engine(sys_, prec, cluster_group=cluster_group, skin=skin,
@@ -73,6 +75,8 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
         eng.bind_langevin(*langevin)
     if hybrid is not None:
         eng.bind_hybrid(hybrid)
+    if ff is not None:
+        eng.bind_forcefield(**ff)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         eng.set_step(0, stream)
@@ -140,7 +144,7 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
             "step": step_end}
 
 
-def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None, hybrid=None):
+def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None, hybrid=None, ff_kind=None):
     """The plain form for batched workloads: every system in a context of its own,
     its step replayed as its own graph, systems one after another on one stream."""
     import torch
@@ -155,6 +159,8 @@ def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None, hybrid=None):
                 e.bind_langevin(langevin[0][b:b + 1], langevin[1][b:b + 1])
             if hybrid is not None:
                 e.bind_hybrid(hybrid[b:b + 1])
+            if ff_kind is not None:
+                e.bind_forcefield(**ff_binding(sb, ff_kind))
             e.set_step(0, stream)
             e.build(md.MD_BUILD_FORCE, stream)
             e.forces(energy=True, stream=stream)
@@ -179,6 +185,16 @@ def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None, hybrid=None):
     for e in engines:
         e.close()
     return {"ms": ms, "flags": flags}
+
+
+def ff_binding(sys_, kind):
+    """Synthetic molecular force field of the workload: full LJ tables into sys_ and
+    the md_bind_forcefield keyword arrays."""
+    from paper_2401_03180_amd import synth
+    d = synth.molecular_force_field(sys_, kind)
+    sys_.c6, sys_.c12 = d["c6"], d["c12"]
+    return {"z_type": d["z"], "excl": d["excl"], "bonds": d["bonds"],
+            "bond_par": d["bond_par"], "angles": d["angles"], "angle_par": d["angle_par"]}
 
 
 def run_rdf(sys_, r_max=1.0, n_bins=250, calls=20, warmup=3, steps=50):
@@ -217,11 +233,12 @@ def run_rdf(sys_, r_max=1.0, n_bins=250, calls=20, warmup=3, steps=50):
             "rdf_flags": flags}
 
 
-def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None):
+def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None, ff=None):
     """The oracle, as it stands: whole steps (all-pairs FP64 force rows of every atom,
     ionization and both velocity-Verlet half steps, phase 0 with the electron-ion
     coupling when langevin = (gamma, kt) is given, hybrid screening when the density
-    table hybrid is given) repeated until about target_s
+    table hybrid is given, the force-field terms of the oracle ForceField ff)
+    repeated until about target_s
     seconds of work; when one step alone would exceed that, the force rows of a random
     subset of atoms are timed and scaled to all atoms."""
     import oracle
@@ -245,7 +262,7 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None):
     kap = oracle.kappa_from_lambda(sys_.lambda_d[:, 1])
     probe = np.sort(rng.choice(n, min(n, 256), replace=False))
     t = time.perf_counter()
-    oracle.forces_rows(sys_, probe, kappa=kap, n_threads=threads, hybrid=htab(1))
+    oracle.forces_rows(sys_, probe, kappa=kap, n_threads=threads, hybrid=htab(1), ff=ff)
     per_row = (time.perf_counter() - t) / probe.size
     q = sys_.q.copy()
     pos = [sys_.x.copy(), sys_.y.copy(), sys_.z.copy()]
@@ -262,8 +279,11 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None):
             oracle.ionize(sys_, q, s)
             out = oracle.forces_rows(sys_, rows, q=q, x=pos[0], y=pos[1], z=pos[2],
                                      kappa=oracle.kappa_from_lambda(sys_.lambda_d[:, s]),
-                                     n_threads=threads, hybrid=htab(s))
+                                     n_threads=threads, hybrid=htab(s), ff=ff)
             F = (out["fx"], out["fy"], out["fz"])
+            if ff is not None:
+                bo = oracle.bonded(sys_, ff, q=q, x=pos[0], y=pos[1], z=pos[2])
+                F = tuple(f + bo[c] for f, c in zip(F, ("fx", "fy", "fz")))
             oracle.vv(1, sys_.dt, sys_.inv_mass, F, pos, vel)
         t_all = time.perf_counter() - t
         return {"value": n * steps / t_all, "unit": "atom-steps/s", "cores": threads,
@@ -273,11 +293,13 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None):
     rows_n = int(min(n, max(256, target_s / max(per_row, 1e-9))))
     rows = np.sort(rng.choice(n, rows_n, replace=False))
     t = time.perf_counter()
-    oracle.forces_rows(sys_, rows, kappa=kap, n_threads=threads, hybrid=htab(1))
+    oracle.forces_rows(sys_, rows, kappa=kap, n_threads=threads, hybrid=htab(1), ff=ff)
     t_rows = time.perf_counter() - t
     t = time.perf_counter()
     phase0(1, F, pos, vel)
     oracle.ionize(sys_, q, 1)
+    if ff is not None:
+        oracle.bonded(sys_, ff, q=q, x=pos[0], y=pos[1], z=pos[2])
     oracle.vv(1, sys_.dt, sys_.inv_mass, F, pos, vel)
     t_elem = time.perf_counter() - t
     t_step = t_rows * n / rows_n + t_elem
@@ -332,6 +354,9 @@ def main():
     ap.add_argument("--hybrid", action="store_true",
                     help="bind hybrid ion-sphere / Debye screening (synthetic electron "
                          "density consistent with the Debye-length schedule)")
+    ap.add_argument("--forcefield", action="store_true",
+                    help="bind the synthetic molecular force field (Morse bonds, angles, "
+                         "LJ exclusions, charge-scaled LJ radii, LJ on every element pair)")
     ap.add_argument("--rdf", action="store_true",
                     help="also time the pair-distance histogram (1 nm, 250 bins) after the "
                          "timed steps' workload")
@@ -380,6 +405,8 @@ def main():
         return k
 
     sys32 = make_system(a.config, S)
+    ff_kind = ("methane" if a.config.startswith("methane") else "water") if a.forcefield else None
+    ffb = ff_binding(sys32, ff_kind) if ff_kind else None
     lg = None
     if a.langevin:
         from paper_2401_03180_amd import synth
@@ -392,7 +419,7 @@ def main():
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
     r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
                   use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg,
-                  hybrid=hy)
+                  hybrid=hy, ff=ffb)
     log("fp32", {k: v for k, v in r32.items() if k != "stats"})
     n = sys32.n_atoms
     value = n * a.steps / (r32["ms"] * 1e-3)
@@ -410,9 +437,11 @@ def main():
              "list_capacity": r32["stats"]["list_capacity"]}
     if not a.no_fp64:
         sys64 = make_system(a.config, S)
+        ffb64 = ff_binding(sys64, ff_kind) if ff_kind else None
         if sys64.n_systems > 1:
             # batched workloads: the plain FP64 form runs one system per context and launch
-            r64 = run_gpu_per_system(sys64, md.MD_FP64, a.steps, a.warmup, langevin=lg, hybrid=hy)
+            r64 = run_gpu_per_system(sys64, md.MD_FP64, a.steps, a.warmup, langevin=lg, hybrid=hy,
+                                     ff_kind=ff_kind)
             v64 = n * a.steps / (r64["ms"] * 1e-3)
             extra.update({"fp64_per_system_value": v64,
                           "fp64_per_system_ms_per_step": r64["ms"] / a.steps,
@@ -423,7 +452,7 @@ def main():
             k64 = knobs(md.MD_FP64)
             r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, k64["cluster_group"], k64["skin"],
                           use_graph=not a.eager, fast_capacity=k64["fast_capacity"], langevin=lg,
-                          hybrid=hy)
+                          hybrid=hy, ff=ffb64)
             log("fp64", {k: v for k, v in r64.items() if k != "stats"})
             v64 = n * a.steps / (r64["ms"] * 1e-3)
             extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
@@ -437,13 +466,15 @@ def main():
         extra.update(rr)
 
     kernel_ms = r32["kernel_ms"]
-    fpp = FLOP_PER_PAIR_HYBRID if hy is not None else FLOP_PER_PAIR
+    fpp = (FLOP_PER_PAIR_HYBRID if hy is not None else FLOP_PER_PAIR) + \
+        (FLOP_QLJ_EXTRA if ffb is not None else 0)
     achieved = fpp * r32["pairs"] / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                 # the counter summary covers the Debye kernel only
-                "traffic": traffic_from_profile() if hy is None else None,
-                "kernel": "k_force32" + ("<HYBRID>" if hy is not None else ""),
+                "traffic": traffic_from_profile() if hy is None and ffb is None else None,
+                "kernel": "k_force32" + ("<HYBRID>" if hy is not None else "") +
+                          ("<QLJ>" if ffb is not None else ""),
                 "kernel_ms": kernel_ms,
                 "flop_per_pair": fpp,
                 "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS}
@@ -459,10 +490,17 @@ def main():
                       "fast_capacity": k32["fast_capacity"], "tuned": k32["tuned"],
                       "systems": sys32.n_systems, "langevin": lg is not None,
                       "hybrid_screening": hy is not None,
+                      "forcefield": ff_kind,
                       "launch": "eager" if a.eager else "graph", "parallelism": "single-gpu"},
            "roofline": roofline, "extra": extra}
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sys32, langevin=lg, hybrid=hy)
+        off = None
+        if ffb is not None:
+            import oracle
+            off = oracle.ForceField(sys32.n_atoms, inv_z=1.0 / ffb["z_type"], excl=ffb["excl"],
+                                    bonds=ffb["bonds"], bond_par=ffb["bond_par"],
+                                    angles=ffb["angles"], angle_par=ffb["angle_par"])
+        out["cpu_baseline"] = cpu_baseline(sys32, langevin=lg, hybrid=hy, ff=off)
     print(json.dumps(out), flush=True)
 
 

@@ -62,7 +62,7 @@ void free_all(Ctx* c)
                     c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32, c->d_rdf_moved,
                     c->d_rdf_xr, c->d_rdf_er, c->d_invz32, c->d_invz64, c->d_excl_off,
                     c->d_excl, c->d_bonds, c->d_bond_par, c->d_angles, c->d_angle_par,
-                    c->d_bt_off, c->d_bt, c->d_bond_e};
+                    c->d_bt_off, c->d_bt, c->d_bond_e, c->d_bond_blk};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -755,7 +755,10 @@ md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const int32_t* e
             for (int k = 0; k < 3; ++k) inc.emplace_back(angles[3 * t + k], (int32_t)(t * 2 + 1));
         const md_status s = csr(inc, &c->d_bt_off, &c->d_bt);
         if (s != MD_OK) return s;
-        if (!c->d_bond_e) HIP_TRY(c, dalloc(&c->d_bond_e, N));
+        if (!c->d_bond_e) {
+            HIP_TRY(c, dalloc(&c->d_bond_e, N));
+            HIP_TRY(c, dalloc(&c->d_bond_blk, div_up(N, kBondedBlock)));
+        }
     }
     return MD_OK;
 }

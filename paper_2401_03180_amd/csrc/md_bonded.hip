@@ -13,8 +13,6 @@
 
 namespace md {
 
-constexpr int kBondedBlock = 256;
-
 struct BondedArgs {
     const double *x, *y, *z;
     const int8_t* q;
@@ -29,6 +27,7 @@ struct BondedArgs {
     const double* angle_par;
     double *fx, *fy, *fz;
     double* bond_e;
+    double* bond_blk;
 };
 
 __device__ inline void min_image(const GridSys& g, const double* x, const double* y,
@@ -50,11 +49,11 @@ __device__ inline double term_scale(const int8_t* q, const int32_t* at, int n)
     return c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
 }
 
-__global__ void __launch_bounds__(kBondedBlock) k_bonded(BondedArgs A)
+// The forces on atom a from every bonded term it takes part in (added to fx, fy,
+// fz) and the energy of the terms it is the first atom of (returned, and stored).
+__device__ inline double bonded_atom(const BondedArgs& A, int64_t a)
 {
 #pragma clang fp contract(off)
-    const int64_t a = blockIdx.x * (int64_t)kBondedBlock + threadIdx.x;
-    if (a >= A.N) return;
     const GridSys g = A.grid[A.sys_of_atom[a]];
     double F[3] = {0.0, 0.0, 0.0}, e = 0.0;
     for (int t = A.bt_off[a]; t < A.bt_off[a + 1]; ++t) {
@@ -103,6 +102,24 @@ __global__ void __launch_bounds__(kBondedBlock) k_bonded(BondedArgs A)
     A.fy[a] += F[1];
     A.fz[a] += F[2];
     A.bond_e[a] = e;
+    return e;
+}
+
+__global__ void __launch_bounds__(kBondedBlock) k_bonded(BondedArgs A)
+{
+    __shared__ double s_e[kBondedBlock / 64];
+    const int64_t a = blockIdx.x * (int64_t)kBondedBlock + threadIdx.x;
+    double e = a < A.N ? bonded_atom(A, a) : 0.0;
+    // the work-group's energy, in a fixed order (the finalize uses it for work-groups
+    // that lie inside one system)
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+    if ((threadIdx.x & 63) == 0) s_e[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBondedBlock / 64; ++w) t += s_e[w];
+        A.bond_blk[blockIdx.x] = t;
+    }
 }
 
 void launch_bonded(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
@@ -110,7 +127,7 @@ void launch_bonded(Ctx* c, const double* x, const double* y, const double* z, co
 {
     const BondedArgs A{x, y, z, q, c->d_sys_of_atom, c->d_grid, c->N, c->d_bt_off, c->d_bt,
                        c->d_bonds, c->d_bond_par, c->d_angles, c->d_angle_par, fx, fy, fz,
-                       c->d_bond_e};
+                       c->d_bond_e, c->d_bond_blk};
     const int nb = (int)div_up(c->N, kBondedBlock);
     if (nb > 0) hipLaunchKernelGGL(k_bonded, dim3(nb), dim3(kBondedBlock), 0, st, A);
 }

@@ -308,6 +308,9 @@ struct ForceFinalizeArgs {
     const int64_t* sys_off;
     DevScalars* dsc;
     const double* bond_e;          // per-atom bonded energies (NULL: no bonded terms)
+    const double* bond_blk;        // their sums per work-group of bonded_block atoms
+    int bonded_block;
+    int64_t N;
 };
 
 __device__ inline void force_finalize_block(const ForceFinalizeArgs& F)
@@ -325,8 +328,19 @@ __device__ inline void force_finalize_block(const ForceFinalizeArgs& F)
                 const int f = F.fast_list[k];
                 if (f >= a0 && f < a1) t += F.fast_e[k];
             }
-            if (F.bond_e)
-                for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) t += F.bond_e[a];
+            if (F.bond_e && a1 > a0) {
+                // whole bonded work-groups inside the system by their sums, the (at
+                // most two) that straddle its ends atom by atom
+                const int64_t bb = F.bonded_block;
+                for (int64_t k = a0 / bb + threadIdx.x; k <= (a1 - 1) / bb; k += blockDim.x) {
+                    const int64_t lo = k * bb, hi = min(lo + bb, F.N);
+                    if (lo >= a0 && hi <= a1) {
+                        t += F.bond_blk[k];
+                    } else {
+                        for (int64_t a = max(lo, a0); a < min(hi, a1); ++a) t += F.bond_e[a];
+                    }
+                }
+            }
             for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
             __syncthreads();
             if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;

@@ -101,7 +101,10 @@ struct ForceArgs {
     const int32_t* excl_off;     // LJ exclusions per caller atom (NULL: none)
     const int32_t* excl;
     int t_excl;                  // pseudo-type of excluded pairs
+    const int32_t* inv_perm;     // slot of each caller atom (current build)
 };
+
+constexpr int kExclRegs = 8;     // excluded partners per atom held in registers
 
 __global__ void __launch_bounds__(256) k_force_finalize(ForceFinalizeArgs F)
 {
@@ -200,6 +203,16 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
     const float thr2 = A.thr2;
     const int cap = A.nb_cap_h;
     int cnt = 0;
+    // the LJ-excluded partners of this lane's atom as slots of the current build (the
+    // first kExclRegs in registers; any others are looked up by atom below)
+    int exs[kExclRegs];
+    int x0 = 0, x1 = 0;
+    if (A.excl_off && live) {
+        x0 = A.excl_off[ai];
+        x1 = A.excl_off[ai + 1];
+    }
+#pragma unroll
+    for (int x = 0; x < kExclRegs; ++x) exs[x] = x0 + x < x1 ? A.inv_perm[A.excl[x0 + x]] : -1;
     for (int e = half; e < nent; e += 2) {
         const uint32_t mk = __builtin_amdgcn_readfirstlane(s_mask[e]);
         if (((mk >> cw) & 1u) == 0u) continue;          // out of this cluster's reach
@@ -214,9 +227,16 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
         const int pos = cnt + __popc(mine & below);
         int tcode = __float_as_int(pj.w);
         if (A.excl_off && pass) {             // LJ-excluded partner: the pseudo-type
-            const int aj = A.perm[slot_of_code(ent_g, (uint32_t)j)];
-            for (int x = A.excl_off[ai]; x < A.excl_off[ai + 1]; ++x)
-                if (A.excl[x] == aj) { tcode = A.t_excl; break; }
+            const int slot_j =
+                (int)((__builtin_amdgcn_readfirstlane(ent_g[e]) & kEntClusterMask) * kCluster) + k;
+            bool exc = false;
+#pragma unroll
+            for (int x = 0; x < kExclRegs; ++x) exc |= exs[x] == slot_j;
+            if (!exc && x1 - x0 > kExclRegs) {
+                const int aj = A.perm[slot_j];
+                for (int x = x0 + kExclRegs; x < x1; ++x) exc |= A.excl[x] == aj;
+            }
+            if (exc) tcode = A.t_excl;
         }
         if (pass && pos < cap) out[pos] = (uint16_t)(j | (tcode << kCodeIdxBits));
         cnt += __popc(mine);
@@ -771,7 +791,8 @@ ForceFinalizeArgs force_finalize_args(Ctx* c, double* epot)
 {
     return ForceFinalizeArgs{c->d_grp_epot, epot, c->d_sys_grp0, c->B, c->d_fast_list,
                              c->d_fast_e, c->d_sys_off, c->dsc,
-                             c->n_bonds + c->n_angles > 0 ? c->d_bond_e : nullptr};
+                             c->n_bonds + c->n_angles > 0 ? c->d_bond_e : nullptr,
+                             c->d_bond_blk, kBondedBlock, c->N};
 }
 
 hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const double* y,
@@ -794,6 +815,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     A.hyb32 = c->d_hyb32; A.hyb64 = c->d_hyb64; A.hyb_q = c->hyb_q;
     A.invz32 = c->d_invz32; A.invz64 = c->d_invz64;
     A.excl_off = c->ff_excl ? c->d_excl_off : nullptr; A.excl = c->d_excl; A.t_excl = c->T;
+    A.inv_perm = c->d_inv_perm;
     {
         const double m = c->rlist * (1.0 + 1e-5);
         A.thr2 = (float)(m * m);

@@ -108,6 +108,7 @@ struct Ctx {
     int32_t* d_bt_off = nullptr;   // N+1: per-atom incident bonded terms (CSR)
     int32_t* d_bt = nullptr;       // term id * 2 + kind (0 bond, 1 angle)
     double* d_bond_e = nullptr;    // N: energy of the bonded terms whose first atom is a
+    double* d_bond_blk = nullptr;  // per bonded work-group: the sum of its atoms' d_bond_e
     double* d_rdf_xr = nullptr;       // cap_slots*3: slot-order current positions
     uint8_t* d_rdf_er = nullptr;      // cap_slots: slot-order elements
     int cap_bar = 0;               // arrival words of its barrier

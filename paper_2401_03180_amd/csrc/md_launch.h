@@ -32,7 +32,9 @@ void launch_vv0_langevin(Ctx* c, double dt, const double* inv_mass, const uint8_
                          const double* fz, double* x, double* y, double* z, double* vx,
                          double* vy, double* vz, hipStream_t st);
 int vv_blocks(int64_t N);
-// bonded terms (md_bonded.hip): forces added to fx, fy, fz; energies per atom
+// bonded terms (md_bonded.hip): forces added to fx, fy, fz; energies per atom and
+// per work-group of kBondedBlock atoms
+constexpr int kBondedBlock = 256;
 void launch_bonded(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
                    double* fx, double* fy, double* fz, hipStream_t st);
 // pair-distance histograms (md_rdf.hip)
