@@ -778,6 +778,8 @@ __global__ void __launch_bounds__(256) k_build_step(StepBuildArgs S)
     if (bid == 0 && threadIdx.x == 0) ph_build_done(d);
 }
 
+constexpr int kBuildStepPerCu = 2;
+
 size_t build_step_lds_bytes(int E_cap)
 {
     return (size_t)kEntryWaves * E_cap * (sizeof(uint32_t) + 1);
@@ -792,7 +794,11 @@ hipError_t build_step_setup(Ctx* c)
         c->bs_blocks = 0;
         return e;
     }
-    c->bs_blocks = occ > 0 ? std::min(c->n_cu * std::min(occ, 4), c->cap_bar) : 0;
+    // two resident work-groups per CU: every grid barrier costs one release (an L2
+    // write-back) per work-group, and the phases have little work per work-group
+    // (measured on water_98304: forced-rebuild step 0.70 ms with 2 per CU, 0.79 ms
+    // with 4, 0.75 ms with 1)
+    c->bs_blocks = occ > 0 ? std::min(c->n_cu * std::min(occ, kBuildStepPerCu), c->cap_bar) : 0;
     return hipSuccess;
 }
 
