@@ -21,6 +21,7 @@
 namespace md {
 
 constexpr int kRdfBlock = 256;
+constexpr int kRdfSplit = 8;         // threads sharing one slot's scan (latency hiding)
 
 struct RdfArgs {
     const double *x, *y, *z;       // current positions (caller order)
@@ -102,9 +103,10 @@ __global__ void __launch_bounds__(kRdfBlock) k_rdf_gather(RdfArgs A)
     A.er[s] = e;
 }
 
-// Pairs of two atoms that have not moved: thread per slot i, partners in slots
-// j > i among the bins within reach of i (a moved or padding slot has a NaN
-// position, so its distances fail the range test).
+// Pairs of two atoms that have not moved: kRdfSplit threads per slot i share the
+// scan of the bins within reach of i (each takes every kRdfSplit-th candidate) and
+// count partners in slots j > i (a moved or padding slot has a NaN position, so its
+// distances fail the range test).
 __global__ void __launch_bounds__(kRdfBlock) k_rdf_grid(RdfArgs A)
 {
     extern __shared__ double s_dyn[];
@@ -112,11 +114,13 @@ __global__ void __launch_bounds__(kRdfBlock) k_rdf_grid(RdfArgs A)
     unsigned* s_h = reinterpret_cast<unsigned*>(s_dyn + A.n_bins + 1); // E*E*n_bins
     const int n = A.n_bins;
     const int64_t n_slots = A.dsc->n_slots;
-    const int64_t s0b = blockIdx.x * (int64_t)kRdfBlock;
+    constexpr int kSlotsPerBlock = kRdfBlock / kRdfSplit;
+    const int64_t s0b = blockIdx.x * (int64_t)kSlotsPerBlock;
     if (s0b >= n_slots) return;                                      // block-uniform
-    const int64_t i = s0b + threadIdx.x;
+    const int64_t i = s0b + threadIdx.x / kRdfSplit;
+    const int sub = threadIdx.x % kRdfSplit;
     // the block's system when all its slots belong to one (slots are system-major)
-    const int64_t last = min(s0b + kRdfBlock, n_slots) - 1;
+    const int64_t last = min(s0b + kSlotsPerBlock, n_slots) - 1;
     int pf = -1, pl = -1;
     for (int64_t t = s0b; t <= last && pf < 0; ++t) pf = A.perm[t];
     for (int64_t t = last; t >= s0b && pl < 0; --t) pl = A.perm[t];
@@ -159,7 +163,7 @@ __global__ void __launch_bounds__(kRdfBlock) k_rdf_grid(RdfArgs A)
         const int a_col = A.bin_start[bin0];
         const int64_t s0 = max(slot0 + (A.bin_start[bin0 + zr0[r]] - a_col), i + 1);
         const int64_t s1 = min(slot0 + (A.bin_start[bin0 + zr1[r] + 1] - a_col), n_slots);
-        for (int64_t s = s0; s < s1; ++s) {          // each pair once: slot j > slot i
+        for (int64_t s = s0 + sub; s < s1; s += kRdfSplit) {   // each pair once: slot j > slot i
             const double r2 = pair_r2_exact(xi, yi, zi, A.xr[s], A.xr[cs + s], A.xr[2 * cs + s], gs);
             if (!(r2 < r2max)) continue;                 // also NaN: moved or padding
             const int k = rdf_bin(r2, e2, n, inv_dr);
@@ -247,9 +251,10 @@ void launch_rdf(Ctx* c, const double* x, const double* y, const double* z, const
     A.lds_hist = with <= kRdfLdsMax ? 1 : 0;
     const int nb = (int)div_up(c->N, kRdfBlock);
     const int ns = (int)div_up(c->cap_slots, kRdfBlock);
+    const int ng = (int)div_up(c->cap_slots, kRdfBlock / kRdfSplit);
     if (nb <= 0) return;
     hipLaunchKernelGGL(k_rdf_gather, dim3(ns), dim3(kRdfBlock), 0, st, A);
-    hipLaunchKernelGGL(k_rdf_grid, dim3(ns), dim3(kRdfBlock),
+    hipLaunchKernelGGL(k_rdf_grid, dim3(ng), dim3(kRdfBlock),
                        A.lds_hist ? with : rdf_lds_bytes(c->E, n_bins, false), st, A);
     hipLaunchKernelGGL(k_rdf_moved, dim3(nb), dim3(kRdfBlock), rdf_lds_bytes(c->E, n_bins, false),
                        st, A);
