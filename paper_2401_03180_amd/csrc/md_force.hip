@@ -192,9 +192,12 @@ __device__ inline double reduce8(double v)
 // of 32 codes.  s_mask[e] holds the clusters of the group entry e can reach (low
 // byte) and the cluster whose own unshifted entry it is (high byte).  Returns the
 // row count.
-__device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int il, int k, int ai,
-                               float xi, float yi, float zi, int nent, const float4* s_j,
-                               const uint16_t* s_mask, int sentinel, const uint32_t* ent_g)
+// EXCL: LJ exclusions are bound (a separate instantiation keeps their per-candidate
+// test out of the plain builder's loop).
+template <bool EXCL>
+__device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, int il, int k,
+                                 int ai, float xi, float yi, float zi, int nent, const float4* s_j,
+                                 const uint16_t* s_mask, int sentinel, const uint32_t* ent_g)
 {
     const int lane = threadIdx.x & 63;
     uint16_t* out = A.nb + (((int64_t)I * 2 + half) * kCluster + il) * A.nb_cap_h;
@@ -207,7 +210,7 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
     // first kExclRegs in registers; any others are looked up by atom below)
     int exs[kExclRegs];
     int x0 = 0, x1 = 0;
-    if (A.excl_off && live) {
+    if (EXCL && live) {
         x0 = A.excl_off[ai];
         x1 = A.excl_off[ai + 1];
     }
@@ -226,7 +229,7 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
         const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
         const int pos = cnt + __popc(mine & below);
         int tcode = __float_as_int(pj.w);
-        if (A.excl_off && pass) {             // LJ-excluded partner: the pseudo-type
+        if (EXCL && pass) {                   // LJ-excluded partner: the pseudo-type
             const int slot_j =
                 (int)((__builtin_amdgcn_readfirstlane(ent_g[e]) & kEntClusterMask) * kCluster) + k;
             bool exc = false;
@@ -251,6 +254,18 @@ __device__ int build_half_list(const ForceArgs& A, int I, int half, int cw, int 
         if (mx > cap) atomicOr(&A.dsc->flags, MD_FLAG_LIST_OVERFLOW);
     }
     return nrow;
+}
+
+__device__ inline int build_half_list(const ForceArgs& A, int I, int half, int cw, int il, int k,
+                                      int ai, float xi, float yi, float zi, int nent,
+                                      const float4* s_j, const uint16_t* s_mask, int sentinel,
+                                      const uint32_t* ent_g)
+{
+    if (A.excl_off)
+        return build_half_list_t<true>(A, I, half, cw, il, k, ai, xi, yi, zi, nent, s_j, s_mask,
+                                       sentinel, ent_g);
+    return build_half_list_t<false>(A, I, half, cw, il, k, ai, xi, yi, zi, nent, s_j, s_mask,
+                                    sentinel, ent_g);
 }
 
 // ------------------------------------------------------------------ FP32 kernel
