@@ -69,12 +69,13 @@ __device__ inline int col_grp0(const int64_t* pre, int c) { return (int)(pre[c] 
 
 // ---------------------------------------------------------------- vacuum grids
 
-// Bounding box of every vacuum system b = bid, bid + nblk, ... (one block each, 256 threads).
+// Bounding box of every vacuum system b = bid, bid + nblk, ... (one block each, up
+// to 1024 threads).
 __device__ void ph_sys_bbox(const double* x, const double* y, const double* z,
                             const int64_t* sys_off, int B, double* lo, double* hi,
                             DevScalars* dsc, int bid, int nblk)
 {
-    __shared__ double s_v[6][4];
+    __shared__ double s_v[6][16];
     for (int b = bid; b < B; b += nblk) {
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
@@ -451,24 +452,37 @@ struct EntryArgs {
     const int32_t* gate;
 };
 
-// One work-group (4 waves) per group.  The candidate columns are dealt round-robin
-// to the waves; each wave appends its passing (cluster, shift) candidates in a
-// fixed order with a ballot prefix, and the four wave lists are concatenated in
-// wave order, so the table is deterministic.
+// Four waves per group; a work-group of 256 k threads works on k groups at once
+// (this latency-bound phase needs many waves in flight).  The candidate columns are
+// dealt round-robin to a group's waves; each wave appends its passing (cluster,
+// shift) candidates in a fixed order with a ballot prefix, and the four wave lists
+// are concatenated in wave order, so the table is deterministic.
 constexpr int kEntryWaves = 4;
+constexpr int kEntryMaxSub = 4;           // groups at once per work-group (1024 threads)
 
-// s_eb: dynamic LDS of kEntryWaves * E_cap * 5 bytes.
+// s_eb: dynamic LDS of (blockDim / 256) * kEntryWaves * E_cap * 5 bytes.
 __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, int nblk)
 {
-    uint8_t* s_mb = reinterpret_cast<uint8_t*>(s_eb + kEntryWaves * A.E_cap);  // masks
-    __shared__ int s_cnt[kEntryWaves];
-    __shared__ double s_cb[kMaxGroup][6];
+    const int nsub = blockDim.x / (64 * kEntryWaves);
+    const int sub = threadIdx.x / (64 * kEntryWaves);
+    const int ltid = threadIdx.x % (64 * kEntryWaves);
+    uint8_t* s_mb = reinterpret_cast<uint8_t*>(s_eb + nsub * kEntryWaves * A.E_cap) +
+                    sub * kEntryWaves * A.E_cap;                       // masks
+    s_eb += sub * kEntryWaves * A.E_cap;
+    __shared__ int s_cnt_all[kEntryMaxSub][kEntryWaves];
+    __shared__ double s_cb_all[kEntryMaxSub][kMaxGroup][6];
+    int* s_cnt = s_cnt_all[sub];
+    double (*s_cb)[6] = s_cb_all[sub];
     const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(ltid >> 6);
     const int ngroups = A.dsc->n_groups;
     const double rl = A.rlist, rl2 = rl * rl;
-    for (int g = bid; g < ngroups; g += nblk) {
-        const Group gr = A.groups[g];
+    // every sub-group of the work-group takes the same number of trips (the
+    // work-group barriers below are shared); idle ones skip the work
+    for (int k = 0; (k * nblk + bid) * nsub < ngroups; ++k) {
+        const int g = (k * nblk + bid) * nsub + sub;
+        const bool active = g < ngroups;
+        const Group gr = active ? A.groups[g] : Group{};
         const GridSys gs = A.grid[gr.sys];
         double lo[3], hi[3];
         for (int d = 0; d < 3; ++d) {
@@ -501,8 +515,8 @@ __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, in
         uint32_t* my_e = s_eb + w * A.E_cap;
         uint8_t* my_m = s_mb + w * A.E_cap;
         // bounding boxes of the group's own clusters (for the reach masks)
-        if (threadIdx.x < gr.ncl * 6) {
-            const int c = threadIdx.x / 6, d = threadIdx.x % 6;
+        if (active && ltid < gr.ncl * 6) {
+            const int c = ltid / 6, d = ltid % 6;
             s_cb[c][d] = d < 3 ? A.cl_lo[(gr.cl0 + c) * 3 + d] : A.cl_hi[(gr.cl0 + c) * 3 + d - 3];
         }
         __syncthreads();
@@ -576,7 +590,7 @@ __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, in
                 A.ent_mask[(int64_t)g * A.E_cap + pos] = my_m[i];
             }
         }
-        if (threadIdx.x == 0) {
+        if (active && ltid == 0) {
             for (int d = 0; d < 3; ++d) {
                 if (!finite_box) { lo[d] = 0.0; hi[d] = 0.0; }
                 A.groups[g].lo[d] = lo[d];
@@ -697,6 +711,43 @@ __device__ bool ph_scan(const T* in, T* out, int64_t n, T* tot, int bid, int nbl
     return grid_barrier(gb, d);
 }
 
+// Exclusive scan of a short array computed by every block on its own (no grid
+// barrier): each block writes the same values, so every block can read the result
+// right away (its own writes are visible to it).  n must be small (the column
+// counts), since every block reads and writes all of it.
+template <class T>
+__device__ void ph_scan_local(const T* in, T* out, int64_t n)
+{
+    __shared__ T s_w[16];
+    __shared__ T s_carry;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    for (int64_t base = 0; base < n; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const T v = i < n ? in[i] : (T)0;
+        T inc = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const T y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        __syncthreads();
+        if (lane == 63) s_w[wv] = inc;
+        __syncthreads();
+        T wofs = 0, ttot = 0;
+        for (int k = 0; k < nw; ++k) {
+            if (k < wv) wofs += s_w[k];
+            ttot += s_w[k];
+        }
+        const T carry = s_carry;
+        if (i < n) out[i] = carry + wofs + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + ttot;
+    }
+    __syncthreads();
+}
+
+constexpr int64_t kLocalScanMax = 4096;   // column counts up to this are scanned per block
+
 struct StepBuildArgs {
     FastJoinArgs join;
     int force;                   // rebuild whatever the displacements
@@ -730,7 +781,11 @@ struct StepBuildArgs {
 // `force`), run the whole build with grid barriers between its phases; finally
 // gather positions and charges into slot order for the force kernels.  On a step
 // without rebuild this replaces a dozen launches by one.
-__global__ void __launch_bounds__(256) k_build_step(StepBuildArgs S)
+// 1024 threads per work-group: one work-group per CU fits (registers), which gives
+// the latency-bound phases 16 waves per CU and each grid barrier one release per CU.
+constexpr int kBuildStepThreads = 1024;
+
+__global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs S)
 {
     extern __shared__ uint32_t s_dyn[];
     __shared__ int s_i[16];
@@ -768,8 +823,12 @@ __global__ void __launch_bounds__(256) k_build_step(StepBuildArgs S)
     if (!grid_barrier(gb, d)) return;
     ph_bin_sort(S.bin_start, S.sorted, S.bin_cnt, S.cap_bins, d, gid, gstride);
     if (!grid_barrier(gb, d)) return;
-    if (!ph_scan<int64_t>(S.col_cnt, S.col_pre, S.n_col_scan, S.scan_tmp, bid, nblk, gb, d))
+    if (S.n_col_scan <= kLocalScanMax) {
+        ph_scan_local<int64_t>(S.col_cnt, S.col_pre, S.n_col_scan);
+    } else if (!ph_scan<int64_t>(S.col_cnt, S.col_pre, S.n_col_scan, S.scan_tmp, bid, nblk, gb,
+                                 d)) {
         return;
+    }
     ph_clusters(S.cl, gid, gstride);
     if (!grid_barrier(gb, d)) return;
     // candidate tables and the slot repack read disjoint data: no barrier between
@@ -778,26 +837,29 @@ __global__ void __launch_bounds__(256) k_build_step(StepBuildArgs S)
     if (bid == 0 && threadIdx.x == 0) ph_build_done(d);
 }
 
-constexpr int kBuildStepPerCu = 2;
+constexpr int kBuildStepPerCu = 1;
 
 size_t build_step_lds_bytes(int E_cap)
 {
-    return (size_t)kEntryWaves * E_cap * (sizeof(uint32_t) + 1);
+    return (size_t)(kBuildStepThreads / (64 * kEntryWaves)) * kEntryWaves * E_cap *
+           (sizeof(uint32_t) + 1);
 }
 
 hipError_t build_step_setup(Ctx* c)
 {
     int occ = 0;
+    (void)hipFuncSetAttribute((const void*)k_build_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)build_step_lds_bytes(c->E_cap));
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, (const void*)k_build_step, 256, build_step_lds_bytes(c->E_cap));
+        &occ, (const void*)k_build_step, kBuildStepThreads, build_step_lds_bytes(c->E_cap));
     if (e != hipSuccess) {
         c->bs_blocks = 0;
         return e;
     }
-    // two resident work-groups per CU: every grid barrier costs one release (an L2
-    // write-back) per work-group, and the phases have little work per work-group
-    // (measured on water_98304: forced-rebuild step 0.70 ms with 2 per CU, 0.79 ms
-    // with 4, 0.75 ms with 1)
+    // one resident work-group of 1024 threads per CU: every grid barrier costs one
+    // release (an L2 write-back) per work-group, while the latency-bound phases want
+    // many waves (with 256-thread work-groups a forced-rebuild step took 0.70 ms at two
+    // per CU, 0.79 ms at four, 0.75 ms at one)
     c->bs_blocks = occ > 0 ? std::min(c->n_cu * std::min(occ, kBuildStepPerCu), c->cap_bar) : 0;
     return hipSuccess;
 }
@@ -831,7 +893,7 @@ void launch_build_step(Ctx* c, const double* x, const double* y, const double* z
                       c->dsc};
     S.bar_arrive = c->d_bar_arrive;
     S.dsc = c->dsc;
-    hipLaunchKernelGGL(k_build_step, dim3(c->bs_blocks), dim3(256),
+    hipLaunchKernelGGL(k_build_step, dim3(c->bs_blocks), dim3(kBuildStepThreads),
                        build_step_lds_bytes(c->E_cap), st, S);
 }
 

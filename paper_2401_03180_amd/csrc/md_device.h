@@ -219,9 +219,10 @@ struct FastJoinArgs {
 
 __device__ inline int fast_join_block(const FastJoinArgs& A)
 {
-    __shared__ int s_sum[1024];
+    __shared__ int s_w[16];
     __shared__ double s_m[16];
     const int nt = blockDim.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = nt >> 6;
     const int chunk = (A.nblocks + nt - 1) / nt;
     const int k0 = threadIdx.x * chunk, k1 = min(A.nblocks, k0 + chunk);
     double m = 0.0;
@@ -230,14 +231,20 @@ __device__ inline int fast_join_block(const FastJoinArgs& A)
         m = fmax(m, A.disp_partial[k]);
         n += A.fast_cnt[k];
     }
-    s_sum[threadIdx.x] = n;
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    // exclusive prefix of the per-thread counts in thread order (= atom order)
+    int inc = n;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_w[wv] = inc;
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) s_m[wv] = m;
     __syncthreads();
-    int off = 0, total = 0;
-    for (int t = 0; t < nt; ++t) {
-        if (t < (int)threadIdx.x) off += s_sum[t];
-        total += s_sum[t];
+    int off = inc - n, total = 0;
+    for (int k = 0; k < nw; ++k) {
+        if (k < wv) off += s_w[k];
+        total += s_w[k];
     }
     for (int k = k0; k < k1 && off < A.fast_cap; ++k) {
         const int cnt = A.fast_cnt[k];
