@@ -375,7 +375,11 @@ __device__ void ph_clusters(const ClusterArgs& A, int64_t gid0, int64_t stride)
     for (int64_t b = gid0; b < A.B; b += stride)
         A.sys_grp0[b] = min(col_grp0(A.col_pre, A.grid[b].col_off), (int)A.cap_clusters);
     total = (int)min((int64_t)total, A.cap_clusters);
-    for (int64_t cl = gid0; cl < total; cl += stride) {
+    // one thread per slot; the kCluster threads of a cluster are adjacent lanes (the
+    // stride is a multiple of 64), which reduce the cluster's bounding box by shuffles
+    for (int64_t slot = gid0; slot < (int64_t)total * kCluster; slot += stride) {
+        const int64_t cl = slot / kCluster;
+        const int l = (int)(slot % kCluster);
         const int c = column_of_cluster(A.col_pre, ncols, (int)cl);
         const int b = find_sys_by_col(A.grid, A.B, c);
         const GridSys& g = A.grid[b];
@@ -385,8 +389,7 @@ __device__ void ph_clusters(const ClusterArgs& A, int64_t gid0, int64_t stride)
         const int abeg = A.bin_start[bin0] + kCluster * k;
         const int aend = A.bin_start[bin0 + nz];
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int l = 0; l < kCluster; ++l) {
-            const int64_t slot = cl * kCluster + l;
+        {
             const int src = abeg + l;
             if (src < aend) {
                 const int a = A.sorted[src];
@@ -412,6 +415,12 @@ __device__ void ph_clusters(const ClusterArgs& A, int64_t gid0, int64_t stride)
                 for (int d = 0; d < 3; ++d) A.xs[d * A.cap_slots + slot] = NAN;
             }
         }
+        for (int d = 0; d < 3; ++d)
+            for (int o = 1; o < kCluster; o <<= 1) {
+                lo[d] = fmin(lo[d], __shfl_xor(lo[d], o, 64));
+                hi[d] = fmax(hi[d], __shfl_xor(hi[d], o, 64));
+            }
+        if (l != 0) continue;
         for (int d = 0; d < 3; ++d) {
             A.cl_lo[cl * 3 + d] = lo[d];
             A.cl_hi[cl * 3 + d] = hi[d];
@@ -453,12 +462,15 @@ struct EntryArgs {
 };
 
 // Four waves per group; a work-group of 256 k threads works on k groups at once
-// (this latency-bound phase needs many waves in flight).  The candidate columns are
-// dealt round-robin to a group's waves; each wave appends its passing (cluster,
-// shift) candidates in a fixed order with a ballot prefix, and the four wave lists
-// are concatenated in wave order, so the table is deterministic.
+// (this latency-bound phase needs many waves in flight).  The candidate columns of a
+// group and their cluster ranges are listed in LDS, and the clusters of all of them
+// are dealt to the group's lanes as one flat sequence (so every lane has work and the
+// loads of many clusters are in flight together); each wave appends its passing
+// (cluster, shift) candidates in a fixed order with a ballot prefix, and the four
+// wave lists are concatenated in wave order, so the table is deterministic.
 constexpr int kEntryWaves = 4;
 constexpr int kEntryMaxSub = 4;           // groups at once per work-group (1024 threads)
+constexpr int kEntryMaxCols = 128;        // candidate columns listed per group (else per column)
 
 // s_eb: dynamic LDS of (blockDim / 256) * kEntryWaves * E_cap * 5 bytes.
 __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, int nblk)
@@ -471,8 +483,14 @@ __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, in
     s_eb += sub * kEntryWaves * A.E_cap;
     __shared__ int s_cnt_all[kEntryMaxSub][kEntryWaves];
     __shared__ double s_cb_all[kEntryMaxSub][kMaxGroup][6];
+    __shared__ int s_cj0_all[kEntryMaxSub][kEntryMaxCols];       // first cluster of a column
+    __shared__ int s_cpre_all[kEntryMaxSub][kEntryMaxCols + 1];  // prefix of cluster counts
+    __shared__ uint8_t s_csh_all[kEntryMaxSub][kEntryMaxCols];   // (sx + 1) | (sy + 1) << 2
     int* s_cnt = s_cnt_all[sub];
     double (*s_cb)[6] = s_cb_all[sub];
+    int* s_cj0 = s_cj0_all[sub];
+    int* s_cpre = s_cpre_all[sub];
+    uint8_t* s_csh = s_csh_all[sub];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(ltid >> 6);
     const int ngroups = A.dsc->n_groups;
@@ -512,67 +530,116 @@ __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, in
         }
         const int ncy = cr[1][1] - cr[1][0] + 1;
         const int ncol = (cr[0][1] - cr[0][0] + 1) * max(ncy, 0);
+        const bool flat = ncol <= kEntryMaxCols;          // the same for the whole group
         uint32_t* my_e = s_eb + w * A.E_cap;
         uint8_t* my_m = s_mb + w * A.E_cap;
-        // bounding boxes of the group's own clusters (for the reach masks)
+        // candidate column ci: global column and periodic shifts (valid: images -1..1)
+        auto column = [&](int ci, int* col, int* sx, int* sy) -> bool {
+            const int cx = cr[0][0] + ci / ncy, cy = cr[1][0] + ci % ncy;
+            const int cxw = ((cx % gs.n[0]) + gs.n[0]) % gs.n[0];
+            const int cyw = ((cy % gs.n[1]) + gs.n[1]) % gs.n[1];
+            *sx = (cx - cxw) / gs.n[0];
+            *sy = (cy - cyw) / gs.n[1];
+            *col = gs.col_off + cxw * gs.n[1] + cyw;
+            return *sx >= -1 && *sx <= 1 && *sy >= -1 && *sy <= 1;
+        };
+        // bounding boxes of the group's own clusters (for the reach masks) and the
+        // list of candidate columns with their cluster counts
         if (active && ltid < gr.ncl * 6) {
             const int c = ltid / 6, d = ltid % 6;
             s_cb[c][d] = d < 3 ? A.cl_lo[(gr.cl0 + c) * 3 + d] : A.cl_hi[(gr.cl0 + c) * 3 + d - 3];
         }
+        if (flat && ltid < ncol) {
+            int col, sx, sy;
+            const bool ok = column(ltid, &col, &sx, &sy);
+            const int j0 = ok ? col_cl0(A.col_pre, col) : 0;
+            s_cj0[ltid] = j0;
+            s_cpre[ltid + 1] = ok ? col_cl0(A.col_pre, col + 1) - j0 : 0;
+            s_csh[ltid] = (uint8_t)((sx + 1) | ((sy + 1) << 2));
+        }
+        __syncthreads();
+        if (flat && ltid < 64) {                 // prefix of the counts (one wave)
+            int carry = 0;
+            for (int base = 0; base < ncol; base += 64) {
+                const int i = base + lane;
+                const int v = i < ncol ? s_cpre[i + 1] : 0;
+                int inc = v;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(inc, o, 64);
+                    if (lane >= o) inc += y;
+                }
+                if (i < ncol) s_cpre[i + 1] = carry + inc;
+                carry += __shfl(inc, 63, 64);
+            }
+            if (lane == 0) s_cpre[0] = 0;
+        }
         __syncthreads();
         int count = 0;
-        for (int ci = w; ci < ncol; ci += kEntryWaves) {
-            const int cx = cr[0][0] + ci / ncy, cy = cr[1][0] + ci % ncy;
-            const int cxw = ((cx % gs.n[0]) + gs.n[0]) % gs.n[0];
-            const int sx = (cx - cxw) / gs.n[0];
-            const int cyw = ((cy % gs.n[1]) + gs.n[1]) % gs.n[1];
-            const int sy = (cy - cyw) / gs.n[1];
-            if (sx < -1 || sx > 1 || sy < -1 || sy > 1) continue;
-            const int col = gs.col_off + cxw * gs.n[1] + cyw;
-            const int j0 = col_cl0(A.col_pre, col), j1 = col_cl0(A.col_pre, col + 1);
+        // test cluster J (this lane's, when `has`) under the column shifts and every z
+        // image; append the passing ones in (image, lane) order
+        auto test_append = [&](bool has, int J, int sx, int sy) {
             const double shx = gs.periodic ? sx * gs.L[0] : 0.0;
             const double shy = gs.periodic ? sy * gs.L[1] : 0.0;
-            for (int base = j0; base < j1; base += 64) {
-                // each lane tests one cluster J of the column for every z image
-                const int J = base + lane;
-                double jlo[3] = {0, 0, 0}, jhi[3] = {0, 0, 0};
-                double dxy2 = INFINITY;
-                if (J < j1) {
-                    for (int d = 0; d < 3; ++d) {
-                        jlo[d] = A.cl_lo[(int64_t)J * 3 + d];
-                        jhi[d] = A.cl_hi[(int64_t)J * 3 + d];
-                    }
-                    jlo[0] += shx; jhi[0] += shx;
-                    jlo[1] += shy; jhi[1] += shy;
-                    const double gx = fmax(0.0, fmax(jlo[0] - hi[0], lo[0] - jhi[0]));
-                    const double gy = fmax(0.0, fmax(jlo[1] - hi[1], lo[1] - jhi[1]));
-                    dxy2 = gx * gx + gy * gy;
+            double jlo[3] = {0, 0, 0}, jhi[3] = {0, 0, 0};
+            double dxy2 = INFINITY;
+            if (has) {
+                for (int d = 0; d < 3; ++d) {
+                    jlo[d] = A.cl_lo[(int64_t)J * 3 + d];
+                    jhi[d] = A.cl_hi[(int64_t)J * 3 + d];
                 }
-                for (int sz = gs.periodic ? -1 : 0; sz <= (gs.periodic ? 1 : 0); ++sz) {
-                    const double shz = gs.periodic ? sz * gs.L[2] : 0.0;
-                    const double zl = jlo[2] + shz, zh = jhi[2] + shz;
-                    const double gz = fmax(0.0, fmax(zl - hi[2], lo[2] - zh));
-                    const bool pass = dxy2 + gz * gz < rl2;
-                    const unsigned long long bal = __ballot(pass);
-                    if (bal == 0ull) continue;
-                    uint32_t cmask = 0u;
-                    if (pass) {
-                        // which clusters of the group this candidate can reach
-                        for (int c = 0; c < gr.ncl; ++c) {
-                            const double ax = fmax(0.0, fmax(jlo[0] - s_cb[c][3], s_cb[c][0] - jhi[0]));
-                            const double ay = fmax(0.0, fmax(jlo[1] - s_cb[c][4], s_cb[c][1] - jhi[1]));
-                            const double az = fmax(0.0, fmax(zl - s_cb[c][5], s_cb[c][2] - zh));
-                            if (ax * ax + ay * ay + az * az < rl2) cmask |= 1u << c;
-                        }
-                        const int pos = count + __popcll(bal & ((1ull << lane) - 1ull));
-                        if (pos < A.E_cap) {
-                            my_e[pos] = (uint32_t)J | ((uint32_t)(sx + 1) << 26) |
-                                        ((uint32_t)(sy + 1) << 28) | ((uint32_t)(sz + 1) << 30);
-                            my_m[pos] = (uint8_t)cmask;
-                        }
+                jlo[0] += shx; jhi[0] += shx;
+                jlo[1] += shy; jhi[1] += shy;
+                const double gx = fmax(0.0, fmax(jlo[0] - hi[0], lo[0] - jhi[0]));
+                const double gy = fmax(0.0, fmax(jlo[1] - hi[1], lo[1] - jhi[1]));
+                dxy2 = gx * gx + gy * gy;
+            }
+            for (int sz = gs.periodic ? -1 : 0; sz <= (gs.periodic ? 1 : 0); ++sz) {
+                const double shz = gs.periodic ? sz * gs.L[2] : 0.0;
+                const double zl = jlo[2] + shz, zh = jhi[2] + shz;
+                const double gz = fmax(0.0, fmax(zl - hi[2], lo[2] - zh));
+                const bool pass = dxy2 + gz * gz < rl2;
+                const unsigned long long bal = __ballot(pass);
+                if (bal == 0ull) continue;
+                uint32_t cmask = 0u;
+                if (pass) {
+                    // which clusters of the group this candidate can reach
+                    for (int c = 0; c < gr.ncl; ++c) {
+                        const double ax = fmax(0.0, fmax(jlo[0] - s_cb[c][3], s_cb[c][0] - jhi[0]));
+                        const double ay = fmax(0.0, fmax(jlo[1] - s_cb[c][4], s_cb[c][1] - jhi[1]));
+                        const double az = fmax(0.0, fmax(zl - s_cb[c][5], s_cb[c][2] - zh));
+                        if (ax * ax + ay * ay + az * az < rl2) cmask |= 1u << c;
                     }
-                    count += __popcll(bal);
+                    const int pos = count + __popcll(bal & ((1ull << lane) - 1ull));
+                    if (pos < A.E_cap) {
+                        my_e[pos] = (uint32_t)J | ((uint32_t)(sx + 1) << 26) |
+                                    ((uint32_t)(sy + 1) << 28) | ((uint32_t)(sz + 1) << 30);
+                        my_m[pos] = (uint8_t)cmask;
+                    }
                 }
+                count += __popcll(bal);
+            }
+        };
+        if (flat) {
+            const int ntot = s_cpre[ncol];
+            for (int t0 = w * 64; t0 < ntot; t0 += kEntryWaves * 64) {
+                const int t = t0 + lane;
+                const bool has = t < ntot;
+                // the candidate column of item t: the last ci with s_cpre[ci] <= t
+                int a = 0, b = ncol - 1;
+                while (a < b) {
+                    const int m = (a + b + 1) >> 1;
+                    if (s_cpre[m] <= t) a = m; else b = m - 1;
+                }
+                const int sh = s_csh[a];
+                test_append(has, s_cj0[a] + (t - s_cpre[a]), (sh & 3) - 1, (sh >> 2) - 1);
+            }
+        } else {
+            for (int ci = w; ci < ncol; ci += kEntryWaves) {
+                int col, sx, sy;
+                if (!column(ci, &col, &sx, &sy)) continue;
+                const int j0 = col_cl0(A.col_pre, col), j1 = col_cl0(A.col_pre, col + 1);
+                for (int base = j0; base < j1; base += 64)
+                    test_append(base + lane < j1, base + lane, sx, sy);
             }
         }
         if (lane == 0) s_cnt[w] = count;
@@ -654,7 +721,7 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
                       c->cap_slots, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_sys_grp0,
                       c->cap_clusters, c->G, c->T, c->dsc, gate};
         const int nb = (int)std::max<int64_t>(
-            1, std::min<int64_t>(div_up(std::max<int64_t>(c->cap_clusters, c->B), 256), wide));
+            1, std::min<int64_t>(div_up(std::max<int64_t>(c->cap_slots, c->B), 256), wide));
         hipLaunchKernelGGL(k_clusters, dim3(nb), dim3(256), 0, st, A);
     }
     {
