@@ -24,6 +24,7 @@ namespace md {
 
 constexpr int kFastBlock = 256;
 constexpr int kFastRanges = 256;     // (column, z range) pairs per sweep of fast_self
+constexpr int kFastU = 4;            // items per thread whose loads are issued together
 
 struct FastArgs {
     const double *x, *y, *z;       // caller positions (current)
@@ -60,36 +61,46 @@ struct FastArgs {
     int64_t emit_max;
 };
 
+// d = p_a - p_b (minimum image) and its squared length, in FP64 in a fixed order:
+// the exact membership test of the pair.
+__device__ inline double pair_r2_fp64(const GridSys& gs, double xa, double ya, double za,
+                                      double xb, double yb, double zb, double* dx, double* dy,
+                                      double* dz)
+{
+#pragma clang fp contract(off)
+    double ex = xa - xb, ey = ya - yb, ez = za - zb;
+    if (gs.periodic) {
+        ex = ex - gs.L[0] * rint(ex * gs.invL[0]);
+        ey = ey - gs.L[1] * rint(ey * gs.invL[1]);
+        ez = ez - gs.L[2] * rint(ez * gs.invL[2]);
+    }
+    double r2 = ex * ex + ey * ey;
+    r2 = r2 + ez * ez;
+    *dx = ex; *dy = ey; *dz = ez;
+    return r2;
+}
+
 // Exact membership and FP64 pair terms for d = p_a - p_b (minimum image); returns
 // false when the pair is outside the cutoff.  f multiplies d for the force on a.
 // hrow: hybrid-screening coefficient rows of the system and step (NULL: Debye).
 // ia, ib: caller indices of the two atoms (for the LJ exclusions).
+// FULL: hybrid screening, charge-scaled LJ or LJ exclusions may be bound (the plain
+// instantiation leaves their code, and its registers, out).
+template <bool FULL>
 __device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double kap,
                                  const double* hrow, int ia, int ib, double xa, double ya,
                                  double za, int qa, int ta, double xb, double yb, double zb,
                                  int qb, int tb, double* dx, double* dy, double* dz, double* f,
                                  double* e)
 {
-    double r2;
-    {
-#pragma clang fp contract(off)
-        double ex = xa - xb, ey = ya - yb, ez = za - zb;
-        if (gs.periodic) {
-            ex = ex - gs.L[0] * rint(ex * gs.invL[0]);
-            ey = ey - gs.L[1] * rint(ey * gs.invL[1]);
-            ez = ez - gs.L[2] * rint(ez * gs.invL[2]);
-        }
-        r2 = ex * ex + ey * ey;
-        r2 = r2 + ez * ez;
-        *dx = ex; *dy = ey; *dz = ez;
-    }
+    const double r2 = pair_r2_fp64(gs, xa, ya, za, xb, yb, zb, dx, dy, dz);
     if (!(r2 < A.rc2)) return false;
     double c6 = A.c6[ta * A.T + tb], c12 = A.c12[ta * A.T + tb];
-    if (A.excl_off) {
+    if (FULL && A.excl_off) {
         for (int x = A.excl_off[ia]; x < A.excl_off[ia + 1]; ++x)
             if (A.excl[x] == ib) { c6 = 0.0; c12 = 0.0; break; }
     }
-    if (A.invz64) {
+    if (FULL && A.invz64) {
 #pragma clang fp contract(off)
         const double ca = 1.0 - (double)qa * A.invz64[ta];
         const double cb = 1.0 - (double)qb * A.invz64[tb];
@@ -98,7 +109,7 @@ __device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double ka
         c6 = c6 * s6;
         c12 = c12 * s6 * s6;
     }
-    if (hrow) {
+    if (FULL && hrow) {
         pair_terms_hybrid64(r2, kap, qa, qb, c6, c12, A.screen_lj != 0, hrow, A.hyb_q, f, e);
         return true;
     }
@@ -125,15 +136,27 @@ __device__ inline void emit_one(const FastArgs& A, int a, int b)
     if ((int64_t)p < A.emit_max) A.emit[p] = make_int2(min(a, b), max(a, b));
 }
 
-__device__ inline double block_sum(double v, double* s)
+// The four sums over the work-group in one pass (each in a fixed order); the
+// results are valid in every thread.
+__device__ inline void block_sum4(double& a, double& b, double& c, double& d,
+                                  double (*s)[kFastBlock / 64])
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+        d += __shfl_xor(d, off, 64);
+    }
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        s[0][w] = a; s[1][w] = b; s[2][w] = c; s[3][w] = d;
+    }
     __syncthreads();
-    double t = 0.0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += s[k];
-    return t;
+    a = b = c = d = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+        a += s[0][k]; b += s[1][k]; c += s[2][k]; d += s[3][k];
+    }
 }
 
 __device__ inline int64_t clamp_step_fast(const FastArgs& A)
@@ -142,11 +165,40 @@ __device__ inline int64_t clamp_step_fast(const FastArgs& A)
     return s < 0 ? 0 : (s >= A.S1 ? A.S1 - 1 : s);
 }
 
-// Work-group fi of the fast-atom pass: all pairs of fast atom fi.
-template <bool ENERGY, bool EMIT>
+// Exclusive prefix of one int per thread over the work-group, in thread order; the
+// block sum goes to *total.  s holds one int per wave.  Starts with a barrier, so
+// LDS read before the call may be overwritten after it.
+__device__ inline int block_excl_scan(int v, int* s, int* total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    __syncthreads();
+    if (lane == 63) s[wv] = inc;
+    __syncthreads();
+    int off = inc - v, t = 0;
+    for (int k = 0; k < nw; ++k) {
+        if (k < wv) off += s[k];
+        t += s[k];
+    }
+    *total = t;
+    return off;
+}
+
+// Work-group fi of the fast-atom pass: all pairs of fast atom fi.  Each thread takes
+// kFastU items per trip and issues their loads together (the pass is latency-bound);
+// its items keep the order k, k + blockDim, ... of a plain strided loop.
+template <bool ENERGY, bool EMIT, bool FULL>
 __device__ void fast_self(const FastArgs& A, int fi)
 {
-    __shared__ double s_red[kFastBlock / 64];
+    static_assert(kFastRanges == kFastBlock, "one (column, z range) pair per thread");
+    __shared__ double s_red4[4][kFastBlock / 64];
+    __shared__ int s_ws[kFastBlock / 64];
+    __shared__ int64_t s_r0[kFastRanges];
+    __shared__ int s_pre[kFastRanges + 1];
     const int nf = A.dsc->n_fast;
     if (fi >= nf) return;
     const int f = A.fast_list[fi];
@@ -165,16 +217,16 @@ __device__ void fast_self(const FastArgs& A, int fi)
     const int nzr = zbin_ranges(gs, zf, A.reach, zr0, zr1);
     const int64_t cs = A.cap_slots;
     const int64_t n_slots = A.dsc->n_slots;
-    // slot ranges of every (column, z range) pair within reach, computed by one
-    // thread each, then swept by the whole work-group as one flattened list
-    __shared__ int64_t s_r0[kFastRanges];
-    __shared__ int s_len[kFastRanges], s_pre[kFastRanges + 1];
+    // slot ranges of every (column, z range) pair within reach, one per thread, then
+    // swept by the whole work-group as one flattened list
     const int ncy = cy1 - cy0 + 1;
     const int npairs = (cx1 - cx0 + 1) * ncy * nzr;
     for (int p0 = 0; p0 < npairs; p0 += kFastRanges) {
         const int np = min(kFastRanges, npairs - p0);
-        __syncthreads();
-        for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        const int t = threadIdx.x;
+        int64_t r0 = 0;
+        int len = 0;
+        if (t < np) {
             const int p = p0 + t;
             const int r = p % nzr, cc = p / nzr;
             const int cx = cx0 + cc / ncy, cy = cy0 + cc % ncy;
@@ -187,53 +239,93 @@ __device__ void fast_self(const FastArgs& A, int fi)
             // the column's atoms are in bin order from slot0 on
             const int64_t s0 = slot0 + (A.bin_start[bin0 + zr0[r]] - a_col);
             const int64_t s1 = min(slot0 + (A.bin_start[bin0 + zr1[r] + 1] - a_col), n_slots);
-            s_r0[t] = s0;
-            s_len[t] = (int)max((int64_t)0, s1 - s0);
+            r0 = s0;
+            len = (int)max((int64_t)0, s1 - s0);
+        }
+        int total;
+        const int off = block_excl_scan(len, s_ws, &total);   // the previous sweep is done
+        if (t < np) {
+            s_r0[t] = r0;
+            s_pre[t] = off;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int t = 0; t < np; ++t) { s_pre[t] = acc; acc += s_len[t]; }
-            s_pre[np] = acc;
-        }
-        __syncthreads();
-        const int total = s_pre[np];
-        for (int k = threadIdx.x; k < total; k += blockDim.x) {
-            int lo = 0, hi = np - 1;                // last range with s_pre <= k
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_pre[mid] <= k) lo = mid; else hi = mid - 1;
+        for (int k0 = t; k0 < total; k0 += kFastU * kFastBlock) {
+            int64_t sl[kFastU];
+#pragma unroll
+            for (int u = 0; u < kFastU; ++u) {
+                const int k = k0 + u * kFastBlock;
+                sl[u] = -1;
+                if (k < total) {
+                    int lo = 0, hi = np - 1;            // last range with s_pre <= k
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= k) lo = mid; else hi = mid - 1;
+                    }
+                    sl[u] = s_r0[lo] + (k - s_pre[lo]);
+                }
             }
-            const int64_t s = s_r0[lo] + (k - s_pre[lo]);
-            const double xa = A.xs[s];
-            if (xa != xa) continue;                // fast atom or padding
-            double dx, dy, dz, fp, e;
-            if (pair_fp64(A, gs, kap, hrow, f, A.perm[s], xf, yf, zf, qf, tf, xa, A.xs[cs + s],
-                          A.xs[2 * cs + s],
-                          A.qs[s], A.ts[s], &dx, &dy, &dz, &fp, &e)) {
-                Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
-                if (ENERGY) E += e;
-                if (EMIT) emit_one(A, f, A.perm[s]);
+            double px[kFastU], py[kFastU], pz[kFastU];
+            int pq[kFastU], pt[kFastU], pa[kFastU];
+#pragma unroll
+            for (int u = 0; u < kFastU; ++u) {
+                const int64_t s = sl[u];
+                px[u] = NAN; py[u] = 0.0; pz[u] = 0.0; pq[u] = 0; pt[u] = 0; pa[u] = -1;
+                if (s >= 0) {
+                    px[u] = A.xs[s];
+                    py[u] = A.xs[cs + s];
+                    pz[u] = A.xs[2 * cs + s];
+                    pq[u] = A.qs[s];
+                    pt[u] = A.ts[s];
+                    pa[u] = A.perm[s];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kFastU; ++u) {
+                if (px[u] != px[u]) continue;          // fast atom, padding or no item
+                double dx, dy, dz, fp, e;
+                if (pair_fp64<FULL>(A, gs, kap, hrow, f, pa[u], xf, yf, zf, qf, tf, px[u], py[u], pz[u],
+                              pq[u], pt[u], &dx, &dy, &dz, &fp, &e)) {
+                    Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
+                    if (ENERGY) E += e;
+                    if (EMIT) emit_one(A, f, pa[u]);
+                }
             }
         }
     }
     // other fast atoms of the same system, by their current positions
     const int64_t a0 = A.sys_off[b], a1 = A.sys_off[b + 1];
-    for (int k = threadIdx.x; k < nf; k += blockDim.x) {
-        const int g = A.fast_list[k];
-        if (g == f || g < a0 || g >= a1) continue;
-        double dx, dy, dz, fp, e;
-        if (pair_fp64(A, gs, kap, hrow, f, g, xf, yf, zf, qf, tf, A.x[g], A.y[g], A.z[g], A.q[g],
-                      A.atype[g], &dx, &dy, &dz, &fp, &e)) {
-            Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
-            if (ENERGY) E += 0.5 * e;
-            if (EMIT && f < g) emit_one(A, f, g);
+    for (int k0 = threadIdx.x; k0 < nf; k0 += kFastU * kFastBlock) {
+        int gg[kFastU];
+#pragma unroll
+        for (int u = 0; u < kFastU; ++u) {
+            const int k = k0 + u * kFastBlock;
+            gg[u] = k < nf ? A.fast_list[k] : -1;
+        }
+        double px[kFastU], py[kFastU], pz[kFastU];
+        int pq[kFastU], pt[kFastU];
+#pragma unroll
+        for (int u = 0; u < kFastU; ++u) {
+            const int g = gg[u];
+            px[u] = 0.0; py[u] = 0.0; pz[u] = 0.0; pq[u] = 0; pt[u] = 0;
+            if (g != f && g >= a0 && g < a1) {
+                px[u] = A.x[g]; py[u] = A.y[g]; pz[u] = A.z[g];
+                pq[u] = A.q[g]; pt[u] = A.atype[g];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFastU; ++u) {
+            const int g = gg[u];
+            if (g == f || g < a0 || g >= a1) continue;
+            double dx, dy, dz, fp, e;
+            if (pair_fp64<FULL>(A, gs, kap, hrow, f, g, xf, yf, zf, qf, tf, px[u], py[u], pz[u], pq[u],
+                          pt[u], &dx, &dy, &dz, &fp, &e)) {
+                Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
+                if (ENERGY) E += 0.5 * e;
+                if (EMIT && f < g) emit_one(A, f, g);
+            }
         }
     }
-    Fx = block_sum(Fx, s_red);
-    Fy = block_sum(Fy, s_red);
-    Fz = block_sum(Fz, s_red);
-    if (ENERGY) E = block_sum(E, s_red);
+    block_sum4(Fx, Fy, Fz, E, s_red4);
     if (threadIdx.x == 0) {
         A.fx[f] = Fx;
         A.fy[f] = Fy;
@@ -253,13 +345,31 @@ __device__ inline int sys_of_col(const GridSys* grid, int B, int c)
     return lo;
 }
 
-constexpr int kFastLocal = 1024;     // fast atoms near one column held in LDS
+// Distance along z from coordinate z to the interval [lo, hi] (all wrapped into
+// [0, L) for a periodic system, where the nearer image counts); +inf for an empty
+// interval.
+__device__ inline double wave_z_gap(double z, double lo, double hi, const GridSys& gs)
+{
+    if (!(lo <= hi)) return INFINITY;
+    const double g0 = fmax(0.0, fmax(lo - z, z - hi));
+    if (!gs.periodic) return g0;
+    const double g1 = fmax(0.0, fmax(lo - (z + gs.L[2]), (z + gs.L[2]) - hi));
+    const double g2 = fmax(0.0, fmax(lo - (z - gs.L[2]), (z - gs.L[2]) - hi));
+    return fmin(g0, fmin(g1, g2));
+}
+
+constexpr int kFastLocal = 1024;     // fast atoms near one column (indices in LDS)
+constexpr int kFastChunk = kFastBlock;   // their positions staged in LDS per chunk
 
 // Column `col` of the fast-atom pass: forces of nearby fast atoms on its other atoms.
+template <bool FULL>
 __device__ void fast_nbr(const FastArgs& A, int col)
 {
     __shared__ int s_loc[kFastLocal];
-    __shared__ int s_cnt[kFastBlock / 64];
+    __shared__ int s_ws[kFastBlock / 64];
+    __shared__ double s_px[kFastChunk], s_py[kFastChunk], s_pz[kFastChunk];
+    __shared__ int s_pg[kFastChunk], s_pq[kFastChunk], s_pt[kFastChunk];
+    __shared__ double s_pzw[kFastChunk];
     const int nf = A.dsc->n_fast;
     if (nf == 0 || col >= A.dsc->n_cols) return;
     const int b = sys_of_col(A.grid, A.B, col);
@@ -278,38 +388,43 @@ __device__ void fast_nbr(const FastArgs& A, int col)
     }
     const int64_t a0 = A.sys_off[b], a1 = A.sys_off[b + 1];
     const double R2 = A.reach * A.reach;
-    // fast atoms of this system within reach of the column, in fast-list order
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // fast atoms of this system within reach of the column, in fast-list order: each
+    // thread tests kFastU consecutive list entries (loads issued together)
     int total = 0;
-    for (int base = 0; base < nf; base += blockDim.x) {
-        const int k = base + threadIdx.x;
-        bool take = false;
-        if (k < nf) {
-            const int g = A.fast_list[k];
-            if (g >= a0 && g < a1) {
-                double px = A.x[g], py = A.y[g];
-                if (gs.periodic) {
-                    px -= gs.L[0] * floor(px * gs.invL[0]);
-                    py -= gs.L[1] * floor(py * gs.invL[1]);
-                }
-                const double gx = axis_gap(px, lo[0], hi[0], gs.periodic, gs.L[0]);
-                const double gy = axis_gap(py, lo[1], hi[1], gs.periodic, gs.L[1]);
-                take = gx * gx + gy * gy < R2;
-            }
+    for (int base = 0; base < nf; base += kFastU * kFastBlock) {
+        const int kb = base + threadIdx.x * kFastU;
+        int gg[kFastU];
+#pragma unroll
+        for (int u = 0; u < kFastU; ++u) gg[u] = kb + u < nf ? A.fast_list[kb + u] : -1;
+        double px[kFastU], py[kFastU];
+#pragma unroll
+        for (int u = 0; u < kFastU; ++u) {
+            px[u] = 0.0; py[u] = 0.0;
+            if (gg[u] >= a0 && gg[u] < a1) { px[u] = A.x[gg[u]]; py[u] = A.y[gg[u]]; }
         }
-        const unsigned long long bal = __ballot(take);
-        if (lane == 0) s_cnt[w] = __popcll(bal);
-        __syncthreads();
-        int off = total;
-        for (int v = 0; v < w; ++v) off += s_cnt[v];
-        int add = 0;
-        for (int v = 0; v < (int)(blockDim.x >> 6); ++v) add += s_cnt[v];
-        if (take) {
-            const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
-            if (pos < kFastLocal) s_loc[pos] = A.fast_list[k];
+        unsigned takes = 0u;
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < kFastU; ++u) {
+            if (!(gg[u] >= a0 && gg[u] < a1)) continue;
+            double qx = px[u], qy = py[u];
+            if (gs.periodic) {
+                qx -= gs.L[0] * floor(qx * gs.invL[0]);
+                qy -= gs.L[1] * floor(qy * gs.invL[1]);
+            }
+            const double gx = axis_gap(qx, lo[0], hi[0], gs.periodic, gs.L[0]);
+            const double gy = axis_gap(qy, lo[1], hi[1], gs.periodic, gs.L[1]);
+            if (gx * gx + gy * gy < R2) { takes |= 1u << u; ++c; }
+        }
+        int add;
+        int pos = total + block_excl_scan(c, s_ws, &add);
+#pragma unroll
+        for (int u = 0; u < kFastU; ++u) {
+            if (((takes >> u) & 1u) == 0u) continue;
+            if (pos < kFastLocal) s_loc[pos] = gg[u];
+            ++pos;
         }
         total += add;
-        __syncthreads();
     }
     if (total == 0) return;
     if (total > kFastLocal) {
@@ -323,29 +438,80 @@ __device__ void fast_nbr(const FastArgs& A, int col)
     const int64_t s1 = min((int64_t)col_first_cluster(A.col_pre, col + 1) * kCluster,
                            (int64_t)A.dsc->n_slots);
     const int64_t cs = A.cap_slots;
-    for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-        const double xa = A.xs[s];
-        if (xa != xa) continue;                    // fast atom or padding
-        const double ya = A.xs[cs + s], za = A.xs[2 * cs + s];
-        const int qa = A.qs[s], ta = A.ts[s];
-        const int ia = A.perm[s];
+    // a wave skips a fast atom only when its z gap exceeds rc by a margin far above
+    // the rounding of the wrapped coordinates
+    const double zskip = sqrt(A.rc2) * (1.0 + 1e-9) + 1e-9;
+    for (int64_t sb = s0; sb < s1; sb += kFastBlock) {
+        const int64_t s = sb + threadIdx.x;
+        double xa = NAN, ya = 0.0, za = 0.0;
+        int qa = 0, ta = 0, ia = -1;
+        if (s < s1) {
+            xa = A.xs[s]; ya = A.xs[cs + s]; za = A.xs[2 * cs + s];
+            qa = A.qs[s]; ta = A.ts[s]; ia = A.perm[s];
+        }
+        const bool live = xa == xa;                    // not fast, padding or past the end
+        // z extent of the wave's live atoms (a column's slots are in z-bin order, so
+        // a wave covers a short stretch of it): fast atoms farther than rc from it in
+        // z are skipped by the whole wave
+        double zl = INFINITY, zh = -INFINITY;
+        if (live) {
+            const double zw = gs.periodic ? za - gs.L[2] * floor(za * gs.invL[2]) : za;
+            zl = zw;
+            zh = zw;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            zl = fmin(zl, __shfl_xor(zl, off, 64));
+            zh = fmax(zh, __shfl_xor(zh, off, 64));
+        }
         double Fx = 0.0, Fy = 0.0, Fz = 0.0;
         bool any = false;
-        for (int k = 0; k < total; ++k) {
-            const int g = s_loc[k];
-            double dx, dy, dz, fp, e;
-            if (pair_fp64(A, gs, kap, hrow, ia, g, xa, ya, za, qa, ta, A.x[g], A.y[g], A.z[g],
-                          A.q[g],
-                          A.atype[g], &dx, &dy, &dz, &fp, &e)) {
-                Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
-                any = true;
+        for (int c0 = 0; c0 < total; c0 += kFastChunk) {
+            const int nc = min(kFastChunk, total - c0);
+            __syncthreads();                           // the previous chunk is consumed
+            if ((int)threadIdx.x < nc) {
+                const int g = s_loc[c0 + threadIdx.x];
+                s_pg[threadIdx.x] = g;
+                s_px[threadIdx.x] = A.x[g];
+                s_py[threadIdx.x] = A.y[g];
+                s_pz[threadIdx.x] = A.z[g];
+                s_pq[threadIdx.x] = A.q[g];
+                s_pt[threadIdx.x] = A.atype[g];
+                const double zg = s_pz[threadIdx.x];
+                s_pzw[threadIdx.x] = gs.periodic ? zg - gs.L[2] * floor(zg * gs.invL[2]) : zg;
+            }
+            __syncthreads();
+            if (!live) continue;
+            // membership first (cheap), then the pair terms of this lane's partners
+            // only, in ascending k: a wave no longer runs the terms for every k that
+            // one of its lanes needs
+            for (int k0 = 0; k0 < nc; k0 += 64) {
+                const int kn = min(64, nc - k0);
+                unsigned long long hit = 0ull;
+                for (int kk = 0; kk < kn; ++kk) {
+                    const int k = k0 + kk;
+                    if (wave_z_gap(s_pzw[k], zl, zh, gs) > zskip) continue;    // wave-uniform
+                    double dx, dy, dz;
+                    const double r2 = pair_r2_fp64(gs, xa, ya, za, s_px[k], s_py[k], s_pz[k], &dx,
+                                                   &dy, &dz);
+                    if (r2 < A.rc2) hit |= 1ull << kk;
+                }
+                while (hit != 0ull) {
+                    const int k = k0 + __builtin_ctzll(hit);
+                    hit &= hit - 1ull;
+                    double dx, dy, dz, fp, e;
+                    if (pair_fp64<FULL>(A, gs, kap, hrow, ia, s_pg[k], xa, ya, za, qa, ta, s_px[k],
+                                        s_py[k], s_pz[k], s_pq[k], s_pt[k], &dx, &dy, &dz, &fp,
+                                        &e)) {
+                        Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
+                        any = true;
+                    }
+                }
             }
         }
         if (any) {
-            const int a = A.perm[s];
-            A.fx[a] += Fx;
-            A.fy[a] += Fy;
-            A.fz[a] += Fz;
+            A.fx[ia] += Fx;
+            A.fy[ia] += Fy;
+            A.fz[ia] += Fz;
         }
     }
 }
@@ -353,11 +519,11 @@ __device__ void fast_nbr(const FastArgs& A, int col)
 // One launch: work-groups [0, fast_cap) take one fast atom each (its own pairs),
 // the following ones one column each (the fast atoms' forces on the column's other
 // atoms); the two halves write disjoint atoms, so they need no ordering.
-template <bool ENERGY, bool EMIT>
+template <bool ENERGY, bool EMIT, bool FULL>
 __global__ void __launch_bounds__(kFastBlock) k_fast(FastArgs A, int fast_cap)
 {
-    if ((int)blockIdx.x < fast_cap) fast_self<ENERGY, EMIT>(A, blockIdx.x);
-    else fast_nbr(A, blockIdx.x - fast_cap);
+    if ((int)blockIdx.x < fast_cap) fast_self<ENERGY, EMIT, FULL>(A, blockIdx.x);
+    else fast_nbr<FULL>(A, blockIdx.x - fast_cap);
 }
 
 void launch_fast(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
@@ -382,12 +548,21 @@ void launch_fast(Ctx* c, const double* x, const double* y, const double* z, cons
     A.dsc = c->dsc; A.fx = fx; A.fy = fy; A.fz = fz; A.emit = emit; A.emit_max = emit_max;
     const int fc = std::max(c->fast_cap, 1);
     const dim3 gs((unsigned)(fc + std::max<int64_t>(c->cap_cols, 1))), bs(kFastBlock);
-    if (emit) {
-        if (energy) hipLaunchKernelGGL((k_fast<true, true>), gs, bs, 0, st, A, fc);
-        else hipLaunchKernelGGL((k_fast<false, true>), gs, bs, 0, st, A, fc);
+    const bool full = A.hyb64 || A.invz64 || A.excl_off;
+    if (full) {
+        if (emit) {
+            if (energy) hipLaunchKernelGGL((k_fast<true, true, true>), gs, bs, 0, st, A, fc);
+            else hipLaunchKernelGGL((k_fast<false, true, true>), gs, bs, 0, st, A, fc);
+        } else {
+            if (energy) hipLaunchKernelGGL((k_fast<true, false, true>), gs, bs, 0, st, A, fc);
+            else hipLaunchKernelGGL((k_fast<false, false, true>), gs, bs, 0, st, A, fc);
+        }
+    } else if (emit) {
+        if (energy) hipLaunchKernelGGL((k_fast<true, true, false>), gs, bs, 0, st, A, fc);
+        else hipLaunchKernelGGL((k_fast<false, true, false>), gs, bs, 0, st, A, fc);
     } else {
-        if (energy) hipLaunchKernelGGL((k_fast<true, false>), gs, bs, 0, st, A, fc);
-        else hipLaunchKernelGGL((k_fast<false, false>), gs, bs, 0, st, A, fc);
+        if (energy) hipLaunchKernelGGL((k_fast<true, false, false>), gs, bs, 0, st, A, fc);
+        else hipLaunchKernelGGL((k_fast<false, false, false>), gs, bs, 0, st, A, fc);
     }
 }
 
