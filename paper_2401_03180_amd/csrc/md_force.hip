@@ -216,14 +216,11 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
     }
 #pragma unroll
     for (int x = 0; x < kExclRegs; ++x) exs[x] = x0 + x < x1 ? A.inv_perm[A.excl[x0 + x]] : -1;
-    for (int e = half; e < nent; e += 2) {
-        const uint32_t mk = __builtin_amdgcn_readfirstlane(s_mask[e]);
-        if (((mk >> cw) & 1u) == 0u) continue;          // out of this cluster's reach
+    // candidate entry e (its atom k staged as pj): test, compact in entry order, store
+    auto emit = [&](int e, bool own, const float4& pj) {
         const int j = e * kCluster + k;
-        const float4 pj = s_j[j];
         const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const bool own = ((mk >> (8 + cw)) & 1u) != 0u;
         const bool pass = live && (r2 < thr2) && !(own && k == il);
         const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
         const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
@@ -243,6 +240,31 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
         }
         if (pass && pos < cap) out[pos] = (uint16_t)(j | (tcode << kCodeIdxBits));
         cnt += __popc(mine);
+    };
+    // the entries of this half (e = half, half + 2, ...) that reach this cluster, 64
+    // at a time: one lane reads each mask, a ballot lists the reaching ones, and the
+    // wave walks them two at a time (both candidate reads in flight together)
+    for (int eb = half; eb < nent; eb += 128) {
+        const int el = eb + 2 * lane;
+        const uint32_t mk = el < nent ? (uint32_t)s_mask[el] : 0u;
+        uint64_t todo = __builtin_amdgcn_ballot_w64(((mk >> cw) & 1u) != 0u);
+        const uint64_t ownb = __builtin_amdgcn_ballot_w64(((mk >> (8 + cw)) & 1u) != 0u);
+        while (todo != 0ull) {
+            const int l0 = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            const int e0 = eb + 2 * l0;
+            const float4 p0 = s_j[e0 * kCluster + k];
+            if (todo != 0ull) {
+                const int l1 = __builtin_ctzll(todo);
+                todo &= todo - 1ull;
+                const int e1 = eb + 2 * l1;
+                const float4 p1 = s_j[e1 * kCluster + k];
+                emit(e0, ((ownb >> l0) & 1ull) != 0ull, p0);
+                emit(e1, ((ownb >> l1) & 1ull) != 0ull, p1);
+            } else {
+                emit(e0, ((ownb >> l0) & 1ull) != 0ull, p0);
+            }
+        }
     }
     int mx = cnt;
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
@@ -382,7 +404,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         const float rcf = sqrtf(rc2f);
         const float band = 2.0f * (3.4641016f * rcf * u * (2.0f * m + rcf) + 3.0f * u * rc2f) +
                            1e-12f;
-        const float lo2 = rc2f - band;
+        const float lo2 = rc2f - band, hi2 = rc2f + band;
 
         double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ea = 0.0;
         int ai = -1;
@@ -459,21 +481,24 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             // one row = 4 codes per lane: the 4 candidate reads are issued together,
             // then the 4 distances, one ballot for the rare FP64 re-decisions, and the
             // 4 pair terms, summed in code order
+            const float2* lj_row = s_lj + tb;           // this atom's row of the LJ table
             auto row = [&](uint64_t codes) {
                 uint32_t idx[4];
                 int tj[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const uint32_t code = (uint32_t)(codes >> (16 * u)) & 0xFFFFu;
-                    idx[u] = code & kCodeIdxMask;
-                    tj[u] = (int)(code >> kCodeIdxBits);
+                    // one bit-field extract per field from the 32-bit half
+                    const uint32_t wd = (uint32_t)(codes >> (32 * (u >> 1)));
+                    const uint32_t sh = 16u * (uint32_t)(u & 1);
+                    idx[u] = __builtin_amdgcn_ubfe(wd, sh, kCodeIdxBits);
+                    tj[u] = (int)__builtin_amdgcn_ubfe(wd, sh + kCodeIdxBits, 16 - kCodeIdxBits);
                 }
                 float4 pj[4];
                 float2 lj[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) pj[u] = s_j[idx[u]];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) lj[u] = s_lj[tb + tj[u]];
+                for (int u = 0; u < 4; ++u) lj[u] = lj_row[tj[u]];
                 if (QLJ) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -492,14 +517,20 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                     dy[u] = yi - pj[u].y;
                     dz[u] = zi - pj[u].z;
                     r2[u] = fmaf(dz[u], dz[u], fmaf(dy[u], dy[u], dx[u] * dx[u]));
+                    // in: surely inside; below hi2 but not in: within the band, where
+                    // the FP64 test decides (two compares, combined on the scalar unit)
                     in[u] = r2[u] < lo2;
-                    amb[u] = fabsf(r2[u] - rc2f) <= band;
+                    amb[u] = r2[u] <= hi2;
                 }
-                if (__builtin_expect(
-                        __builtin_amdgcn_ballot_w64(amb[0] | amb[1] | amb[2] | amb[3]) != 0ull, 0)) {
+                uint64_t band_any = 0ull;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    band_any |= __builtin_amdgcn_ballot_w64(amb[u]) &
+                                ~__builtin_amdgcn_ballot_w64(in[u]);
+                if (__builtin_expect(band_any != 0ull, 0)) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        if (amb[u])
+                        if (amb[u] && !in[u])
                             in[u] = recheck_pair(ent_g, A.xs, cs, slot_i, idx[u], gsp, A.rc2) != 0;
                 }
                 if (EMIT) {
