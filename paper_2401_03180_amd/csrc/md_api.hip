@@ -55,7 +55,7 @@ void free_all(Ctx* c)
                     c->d_base, c->d_g, c->d_seeds, c->d_key, c->d_rank, c->d_img,
                     c->d_bin_cnt, c->d_bin_start, c->d_sorted, c->d_scan_tmp, c->d_col_cnt,
                     c->d_col_pre, c->d_cl_lo, c->d_cl_hi,
-                    c->d_cl_nt, c->d_cl_len, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_qs,
+                    c->d_cl_nt, c->d_cl_len, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_xo, c->d_qs,
                     c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
                     c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
                     c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
@@ -296,6 +296,7 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, dalloc(&c->d_slot_img, c->cap_slots));
     HIP_TRY(c, dalloc(&c->d_inv_perm, N));
     HIP_TRY(c, dalloc(&c->d_xs, 3 * c->cap_slots));
+    HIP_TRY(c, dalloc(&c->d_xo, c->cap_slots));
     HIP_TRY(c, dalloc(&c->d_qs, c->cap_slots));
     HIP_TRY(c, dalloc(&c->d_ts, c->cap_slots));
     HIP_TRY(c, dalloc(&c->d_groups, c->cap_groups));

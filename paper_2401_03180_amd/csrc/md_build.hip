@@ -957,7 +957,7 @@ void launch_build_step(Ctx* c, const double* x, const double* y, const double* z
     S.col_cnt = c->d_col_cnt; S.col_pre = c->d_col_pre; S.n_col_scan = c->cap_cols + 1;
     S.scan_tmp = c->d_scan_tmp; S.sorted = c->d_sorted; S.cap_bins = c->cap_bins;
     S.rp = RepackArgs{x, y, z, q, c->d_perm, c->d_fast_flag, c->d_xs, c->d_qs, c->cap_slots,
-                      c->dsc};
+                      c->dsc, c->d_slot_img, c->d_cl_lo, c->d_grid, c->d_sys_of_atom, c->d_xo};
     S.bar_arrive = c->d_bar_arrive;
     S.dsc = c->dsc;
     hipLaunchKernelGGL(k_build_step, dim3(c->bs_blocks), dim3(kBuildStepThreads),

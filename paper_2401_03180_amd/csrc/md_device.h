@@ -275,6 +275,13 @@ struct RepackArgs {
     int8_t* qs;
     int64_t cap_slots;
     DevScalars* dsc;
+    // FP32 staging copy: the position in the frame of the build (image removed) less
+    // the low corner of the slot's cluster box, and the charge
+    const int32_t* slot_img;
+    const double* cl_lo;
+    const GridSys* grid;
+    const int32_t* sys_of_atom;
+    float4* xo;
 };
 
 // check_skin: latch MD_FLAG_SKIN when a rebuild is still pending (stale lists).
@@ -289,15 +296,27 @@ __device__ inline void repack_range(const RepackArgs& A, int64_t gtid, int64_t g
     for (int64_t s = gtid; s < n; s += gstride) {
         const int a = A.perm[s];
         if (a >= 0 && !A.fast_flag[a]) {
-            A.xs[s] = A.x[a];
-            A.xs[A.cap_slots + s] = A.y[a];
-            A.xs[2 * A.cap_slots + s] = A.z[a];
-            A.qs[s] = A.q[a];
+            const double p[3] = {A.x[a], A.y[a], A.z[a]};
+            const int8_t qa = A.q[a];
+            A.xs[s] = p[0];
+            A.xs[A.cap_slots + s] = p[1];
+            A.xs[2 * A.cap_slots + s] = p[2];
+            A.qs[s] = qa;
+            const GridSys& g = A.grid[A.sys_of_atom[a]];
+            const int32_t im = A.slot_img[s];
+            const double* lo = A.cl_lo + (s / kCluster) * 3;
+            float o[3];
+            for (int d = 0; d < 3; ++d) {
+                const double w = g.periodic ? p[d] - (double)unpack_img(im, d) * g.L[d] : p[d];
+                o[d] = (float)(w - lo[d]);
+            }
+            A.xo[s] = make_float4(o[0], o[1], o[2], (float)qa);
         } else {
             A.xs[s] = NAN;
             A.xs[A.cap_slots + s] = NAN;
             A.xs[2 * A.cap_slots + s] = NAN;
             A.qs[s] = a >= 0 ? A.q[a] : 0;
+            A.xo[s] = make_float4(NAN, NAN, NAN, a >= 0 ? (float)A.q[a] : 0.0f);
         }
     }
 }

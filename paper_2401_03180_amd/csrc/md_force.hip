@@ -51,7 +51,7 @@ void launch_repack(Ctx* c, const double* x, const double* y, const double* z, co
 {
     const int nb = (int)std::min<int64_t>(div_up(c->cap_slots, 256), (int64_t)c->n_cu * 8);
     const RepackArgs A{x, y, z, q, c->d_perm, c->d_fast_flag, c->d_xs, c->d_qs, c->cap_slots,
-                       c->dsc};
+                       c->dsc, c->d_slot_img, c->d_cl_lo, c->d_grid, c->d_sys_of_atom, c->d_xo};
     hipLaunchKernelGGL(k_repack, dim3(std::max(nb, 1)), dim3(256), 0, st, A);
 }
 
@@ -65,6 +65,8 @@ struct ForceArgs {
     const int32_t* perm;
     const int32_t* slot_img;
     const double* xs;            // slot-order FP64 positions (SoA, stride cap_slots)
+    const float4* xo;            // slot-order FP32 offsets from the cluster box corner, charge
+    const double* cl_lo;         // cluster box corners (the offsets' origins)
     const int8_t* qs;
     const uint8_t* ts;
     const GridSys* grid;
@@ -115,6 +117,13 @@ template <class T>
 __device__ inline const __attribute__((address_space(1))) T* gbl(const T* p)
 {
     return (const __attribute__((address_space(1))) T*)p;
+}
+
+// Global load at a 32-bit byte offset from a base pointer (the base stays scalar).
+template <class T>
+__device__ inline T ld_off(const T* p, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
 }
 
 __device__ inline int64_t slot_of_code(const uint32_t* ent_g, uint32_t idx)
@@ -324,11 +333,13 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
     if (tid == 0) s_j[sentinel] = make_float4(kFarF, kFarF, kFarF, 0.0f);
     const float rc2f = (float)A.rc2;
     const int64_t cs = A.cap_slots;
-    const auto xs_g = gbl(A.xs);
 
     // the first group of every work-group is its own index; later ones come from a
     // shared counter (no burst of same-address atomics at launch)
     for (int g = blockIdx.x; g < ngroups;) {
+        // the next group is claimed now (its atomic's latency overlaps this group)
+        unsigned claim = 0u;
+        if (!LISTS && tid == 0) claim = atomicAdd(&A.dsc->work_force, 1u);
         const Group gr = A.groups[g];
         const GridSys gs = A.grid[gr.sys];
         const double kap = A.kappa[(int64_t)gr.sys * A.S1 + step];
@@ -339,51 +350,60 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         }
 
         // ---- stage the candidate atoms in the group frame (padding slots hold NaN
-        //      positions and are never inside the cutoff)
-        float m = 0.0f;
+        //      positions and are never inside the cutoff): per entry the FP64 offset of
+        //      the cluster's box corner from the group centre (with the entry's
+        //      periodic shift), rounded once, plus each atom's FP32 offset from that
+        //      corner (written by the repack)
+        float m = 0.0f;                        // largest |staged coordinate| or |offset|
         const int nst = gr.nent * kCluster;
         constexpr int U = 4;
         for (int base = tid; base < nst; base += U * blockDim.x) {
-            uint32_t en[U];
-            int64_t slot[U];
+            // an item past the end repeats the last one (its loads and m stay valid)
+            // and is not stored; 32-bit byte offsets keep the load bases scalar
+            uint32_t en[U], slot[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = base + u * blockDim.x;
-                en[u] = idx < nst ? (uint32_t)ent_gl[idx >> 3] : 0x54000000u;
-                slot[u] = (int64_t)(en[u] & kEntClusterMask) * kCluster + (idx & 7);
+                const uint32_t ic = (uint32_t)min(base + u * (int)blockDim.x, nst - 1);
+                en[u] = ld_off(A.ent, ((uint32_t)g * (uint32_t)A.E_cap + (ic >> 3)) * 4u);
+                slot[u] = (en[u] & kEntClusterMask) * kCluster + (ic & 7u);
             }
-            double p[U][3];
-            int32_t im[U];
-            float qv[U];
+            float4 o[U];
+            double an[U][3];
+            float tv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = base + u * blockDim.x;
-                const bool ok = idx < nst;
-                for (int d = 0; d < 3; ++d) p[u][d] = ok ? (double)xs_g[d * cs + slot[u]] : 0.0;
-                im[u] = ok ? A.slot_img[slot[u]] : 0;
+                const uint32_t cl = en[u] & kEntClusterMask;
+                const uint32_t cb = (cl << 4) + (cl << 3);      // 24 bytes per corner
+                o[u] = ld_off(A.xo, slot[u] * (uint32_t)sizeof(float4));
+                for (int d = 0; d < 3; ++d)
+                    an[u][d] = ld_off(A.cl_lo, cb + 8u * (uint32_t)d);
                 // while the lists are rebuilt .w carries the type (the charges are
                 // put back before the pair loop)
-                qv[u] = !ok ? 0.0f
-                            : rebuild ? __int_as_float((int)A.ts[slot[u]]) : (float)A.qs[slot[u]];
+                tv[u] = rebuild ? __int_as_float((int)ld_off(A.ts, slot[u])) : 0.0f;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int idx = base + u * blockDim.x;
-                if (idx >= nst) continue;
-                // padding slots (NaN positions) go far away, outside every cutoff
-                const bool pad = p[u][0] != p[u][0];
+                // padding and fast atoms (NaN offsets) go far away, outside every
+                // cutoff; their NaNs do not enter m (max ignores a NaN operand)
+                const bool pad = o[u].x != o[u].x;
+                const float od[3] = {o[u].x, o[u].y, o[u].z};
                 float r[3];
+#pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    double v = p[u][d];
+                    double bd = an[u][d] - gr.c[d];
                     if (gs.periodic) {
                         const int sh = (int)((en[u] >> (26 + 2 * d)) & 3u) - 1;
-                        v = v - (double)(unpack_img(im[u], d) - sh) * gs.L[d];
+                        bd = fma((double)sh, gs.L[d], bd);
                     }
-                    r[d] = pad ? kFarF : (float)(v - gr.c[d]);
-                    if (!pad) m = fmaxf(m, fabsf(r[d]));
+                    const float rv = (float)bd + od[d];
+                    m = fmaxf(m, fmaxf(fabsf(rv), fabsf(od[d])));
+                    r[d] = pad ? kFarF : rv;
                 }
-                s_j[idx] = make_float4(r[0], r[1], r[2], pad ? 0.0f : qv[u]);
-                if (rebuild && (idx & 7) == 0) {
+                if (idx < nst)
+                    s_j[idx] = make_float4(r[0], r[1], r[2],
+                                           pad ? 0.0f : (rebuild ? tv[u] : o[u].w));
+                if (rebuild && idx < nst && (idx & 7) == 0) {
                     const int e = idx >> 3;
                     const int c = (int)(en[u] & kEntClusterMask) - gr.cl0;
                     const uint32_t own = ((en[u] >> 26) == 0x15u && c >= 0 && c < gr.ncl)
@@ -392,53 +412,60 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 }
             }
         }
+        // this wave's i-atoms (slot-indexed): the loads are issued before the barrier,
+        // so their latency overlaps the wait
+        const bool act = cw < gr.ncl;              // wave-uniform
+        const int I = gr.cl0 + cw;
+        const int64_t slot_i = (int64_t)I * kCluster + il;
+        int ai = -1, im_i = 0, q_i = 0, t_i = 0, nr = 0;
+        double pxi[3] = {0.0, 0.0, 0.0};
+        if (act) {
+            ai = A.perm[slot_i];
+            for (int d = 0; d < 3; ++d) pxi[d] = A.xs[d * cs + slot_i];
+            im_i = A.slot_img[slot_i];
+            q_i = A.qs[slot_i];
+            t_i = A.ts[slot_i];
+            if (!rebuild) nr = A.cl_nt[(int64_t)I * 2 + half];
+        }
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
         if (lane == 0) s_m[w] = m;
         __syncthreads();
         m = s_m[0];
         for (int k = 1; k < nw; ++k) m = fmaxf(m, s_m[k]);
-        // Rounding bound of the FP32 r^2 near the cutoff: each staged coordinate
-        // carries <= u|x| error (u = 2^-24), so |d32 - d| <= u (2m + |d|) per axis and
-        // |r2_32 - r2| <= 2 sqrt(3) rc u (2m + rc) + 3 u rc^2; doubled for margin.
+        // Rounding bound of the FP32 r^2 near the cutoff (u = 2^-24, m as above): a
+        // staged candidate coordinate fl(fl(b) + fl(o)) carries <= u (|b| + |o| + |x|)
+        // <= 4 u m error (|b| <= |x| + |o|), the i-atom coordinate <= u m, so
+        // |d32 - d| <= u (5m + |d|) per axis and |r2_32 - r2| <= 2 sqrt(3) rc u (5m + rc)
+        // + 3 u rc^2; doubled for margin.
         const float u = 5.9604645e-8f;
         const float rcf = sqrtf(rc2f);
-        const float band = 2.0f * (3.4641016f * rcf * u * (2.0f * m + rcf) + 3.0f * u * rc2f) +
+        const float band = 2.0f * (3.4641016f * rcf * u * (5.0f * m + rcf) + 3.0f * u * rc2f) +
                            1e-12f;
         const float lo2 = rc2f - band, hi2 = rc2f + band;
 
         double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ea = 0.0;
-        int ai = -1;
-        const bool act = cw < gr.ncl;              // wave-uniform
-        const int I = gr.cl0 + cw;
-        const int64_t slot_i = (int64_t)I * kCluster + il;
         float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f, qif = 0.0f;
         float4 hi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float ci = 1.0f;                       // QLJ: 1 - q_i / Z_i
         int tb = 0;
-        if (act) {
-            ai = A.perm[slot_i];
-            // a fast atom (NaN position) takes no part, like padding: its pairs and
-            // its force come from the fast-atom kernels
-            if (ai >= 0 && A.xs[slot_i] == A.xs[slot_i]) {
-                const int32_t im = A.slot_img[slot_i];
-                float r[3];
-                for (int d = 0; d < 3; ++d) {
-                    double v = A.xs[d * cs + slot_i];
-                    if (gs.periodic) v = v - (double)unpack_img(im, d) * gs.L[d];
-                    r[d] = (float)(v - gr.c[d]);
-                }
-                xi = r[0]; yi = r[1]; zi = r[2];
-                qike = (float)(kKe * (double)A.qs[slot_i]);
-                tb = A.ts[slot_i] * A.T;
-                if (QLJ) ci = fmaf(-(float)A.qs[slot_i], s_invz[A.ts[slot_i]], 1.0f);
-                if (HYBRID) {
-                    const int qv = A.qs[slot_i];
-                    qif = (float)qv;
-                    hi = s_hyb[min(max(qv, 0), A.hyb_q - 1)];
-                }
+        // a fast atom (NaN position) takes no part, like padding: its pairs and its
+        // force come from the fast-atom kernels
+        if (act && ai >= 0 && pxi[0] == pxi[0]) {
+            float r[3];
+            for (int d = 0; d < 3; ++d) {
+                double v = pxi[d];
+                if (gs.periodic) v = v - (double)unpack_img(im_i, d) * gs.L[d];
+                r[d] = (float)(v - gr.c[d]);
+            }
+            xi = r[0]; yi = r[1]; zi = r[2];
+            qike = (float)(kKe * (double)q_i);
+            tb = t_i * A.T;
+            if (QLJ) ci = fmaf(-(float)q_i, s_invz[t_i], 1.0f);
+            if (HYBRID) {
+                qif = (float)q_i;
+                hi = s_hyb[min(max(q_i, 0), A.hyb_q - 1)];
             }
         }
-        int nr = 0;
         if (rebuild) {
             if (act)
                 nr = build_half_list(A, I, half, cw, il, k8, ai, xi, yi, zi, gr.nent, s_j, s_mask,
@@ -458,8 +485,6 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 reinterpret_cast<float*>(s_j + idx)[3] = qv;
             }
             __syncthreads();
-        } else if (act) {
-            nr = A.cl_nt[(int64_t)I * 2 + half];
         }
         if (act) {
             const float kapf = (float)kap;
@@ -633,8 +658,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 for (int i = 0; i < kCluster; ++i) t += s_part[k][i][3];
             A.grp_epot[g] = 0.5 * t;       // each pair is visited from both atoms
         }
-        __syncthreads();
-        if (tid == 0) s_g = (int)(gridDim.x + atomicAdd(&A.dsc->work_force, 1u));
+        if (tid == 0) s_g = (int)(gridDim.x + claim);
         __syncthreads();
         g = s_g;
     }
@@ -849,6 +873,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     ForceArgs A;
     A.groups = c->d_groups; A.ent = c->d_ent; A.nb = c->d_nb; A.cl_nt = c->d_cl_nt;
     A.perm = c->d_perm; A.slot_img = c->d_slot_img; A.xs = c->d_xs; A.qs = c->d_qs; A.ts = c->d_ts;
+    A.xo = c->d_xo; A.cl_lo = c->d_cl_lo;
     A.grid = c->d_grid; A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
     A.lj32 = c->d_lj32; A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T_lj;
     A.rc2 = c->cfg.rc * c->cfg.rc;

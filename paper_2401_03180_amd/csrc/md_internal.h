@@ -168,6 +168,7 @@ struct Ctx {
     int32_t* d_slot_img = nullptr; // cap_slots: packed image of the slot's atom
     int32_t* d_inv_perm = nullptr; // N
     double* d_xs = nullptr;        // cap_slots*3 positions in slot order (SoA x|y|z)
+    float4* d_xo = nullptr;        // cap_slots: offsets from the cluster's box corner, charge
     int8_t* d_qs = nullptr;        // cap_slots charges in slot order
     uint8_t* d_ts = nullptr;       // cap_slots types in slot order (build time)
     // groups and lists
