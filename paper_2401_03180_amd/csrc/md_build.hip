@@ -842,12 +842,12 @@ struct StepBuildArgs {
     DevScalars* dsc;
 };
 
-// The build half of one step in one persistent launch (all blocks resident): join
-// the fast-atom lists of phase 0 of the integrator and advance the step counter;
-// when a rebuild is due (more fast atoms than the capacity, a pending request, or
-// `force`), run the whole build with grid barriers between its phases; finally
-// gather positions and charges into slot order for the force kernels.  On a step
-// without rebuild this replaces a dozen launches by one.
+// The build half of one step in one persistent launch (all blocks resident): gather
+// positions and charges into the current slot order for the force kernels, join the
+// fast-atom lists of phase 0 of the integrator and advance the step counter; when a
+// rebuild is due (more fast atoms than the capacity, a pending request, or `force`),
+// run the whole build with grid barriers between its phases and gather again into
+// the new slot order.  On a step without rebuild this replaces a dozen launches by one.
 // 1024 threads per work-group: one work-group per CU fits (registers), which gives
 // the latency-bound phases 16 waves per CU and each grid barrier one release per CU.
 constexpr int kBuildStepThreads = 1024;
@@ -862,6 +862,10 @@ __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs 
     const int64_t gstride = (int64_t)nblk * blockDim.x;
     // every block takes the decision from the same inputs (no one writes them here)
     const int pending = d->need_rebuild;
+    // unless a rebuild is already requested, the slot repack for the current lists
+    // runs first, before the decision is known (a rebuild rewrites everything it
+    // writes, after several grid barriers)
+    if (!S.force && !pending) repack_range(S.rp, gid, gstride, false);
     int cnt = 0;
     for (int k = threadIdx.x; k < S.join.nblocks; k += blockDim.x) cnt += S.join.fast_cnt[k];
     const int total = block_sum_all(cnt, s_i);
@@ -870,11 +874,10 @@ __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs 
     // barrier, so all blocks read the same starting value here
     GridBarrier gb{S.bar_arrive, &d->bar_gen, (unsigned)nblk,
                    __hip_atomic_load(&d->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
-    if (bid == 0) fast_join_block(S.join);
-    if (!rebuild) {
-        repack_range(S.rp, gid, gstride, true);
-        return;
-    }
+    // the last block (which holds no repack slots unless the slots outnumber the
+    // grid's threads) joins the fast-atom lists
+    if (bid == nblk - 1) fast_join_block(S.join);
+    if (!rebuild) return;
     if (!S.periodic) {
         ph_sys_bbox(S.x, S.y, S.z, S.sys_off, S.B, S.sys_lo, S.sys_hi, d, bid, nblk);
         if (!grid_barrier(gb, d)) return;
@@ -957,7 +960,8 @@ void launch_build_step(Ctx* c, const double* x, const double* y, const double* z
     S.col_cnt = c->d_col_cnt; S.col_pre = c->d_col_pre; S.n_col_scan = c->cap_cols + 1;
     S.scan_tmp = c->d_scan_tmp; S.sorted = c->d_sorted; S.cap_bins = c->cap_bins;
     S.rp = RepackArgs{x, y, z, q, c->d_perm, c->d_fast_flag, c->d_xs, c->d_qs, c->cap_slots,
-                      c->dsc, c->d_slot_img, c->d_cl_lo, c->d_grid, c->d_sys_of_atom, c->d_xo};
+                      c->dsc, c->d_slot_img, c->d_cl_lo, c->d_grid, c->d_sys_of_atom, c->B,
+                      c->d_xo};
     S.bar_arrive = c->d_bar_arrive;
     S.dsc = c->dsc;
     hipLaunchKernelGGL(k_build_step, dim3(c->bs_blocks), dim3(kBuildStepThreads),

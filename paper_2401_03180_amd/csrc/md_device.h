@@ -280,7 +280,8 @@ struct RepackArgs {
     const int32_t* slot_img;
     const double* cl_lo;
     const GridSys* grid;
-    const int32_t* sys_of_atom;
+    const int32_t* sys_of_atom;    // (not read for a single system)
+    int B;
     float4* xo;
 };
 
@@ -302,7 +303,7 @@ __device__ inline void repack_range(const RepackArgs& A, int64_t gtid, int64_t g
             A.xs[A.cap_slots + s] = p[1];
             A.xs[2 * A.cap_slots + s] = p[2];
             A.qs[s] = qa;
-            const GridSys& g = A.grid[A.sys_of_atom[a]];
+            const GridSys& g = A.grid[A.B == 1 ? 0 : A.sys_of_atom[a]];
             const int32_t im = A.slot_img[s];
             const double* lo = A.cl_lo + (s / kCluster) * 3;
             float o[3];

@@ -51,7 +51,8 @@ void launch_repack(Ctx* c, const double* x, const double* y, const double* z, co
 {
     const int nb = (int)std::min<int64_t>(div_up(c->cap_slots, 256), (int64_t)c->n_cu * 8);
     const RepackArgs A{x, y, z, q, c->d_perm, c->d_fast_flag, c->d_xs, c->d_qs, c->cap_slots,
-                       c->dsc, c->d_slot_img, c->d_cl_lo, c->d_grid, c->d_sys_of_atom, c->d_xo};
+                       c->dsc, c->d_slot_img, c->d_cl_lo, c->d_grid, c->d_sys_of_atom, c->B,
+                       c->d_xo};
     hipLaunchKernelGGL(k_repack, dim3(std::max(nb, 1)), dim3(256), 0, st, A);
 }
 
