@@ -461,18 +461,20 @@ struct EntryArgs {
     const int32_t* gate;
 };
 
-// Four waves per group; a work-group of 256 k threads works on k groups at once
-// (this latency-bound phase needs many waves in flight).  The candidate columns of a
+// kEntryWaves waves per group (one: measured fastest, since this latency-bound phase
+// gains more from groups in flight than from lanes per group); a work-group of
+// 64 kEntryWaves k threads works on k groups at once.  The candidate columns of a
 // group and their cluster ranges are listed in LDS, and the clusters of all of them
 // are dealt to the group's lanes as one flat sequence (so every lane has work and the
 // loads of many clusters are in flight together); each wave appends its passing
-// (cluster, shift) candidates in a fixed order with a ballot prefix, and the four
-// wave lists are concatenated in wave order, so the table is deterministic.
-constexpr int kEntryWaves = 4;
-constexpr int kEntryMaxSub = 4;           // groups at once per work-group (1024 threads)
-constexpr int kEntryMaxCols = 128;        // candidate columns listed per group (else per column)
+// (cluster, shift) candidates in a fixed order with a ballot prefix, and the wave
+// lists are concatenated in wave order, so the table is deterministic.
+constexpr int kEntryWaves = 1;
+constexpr int kEntryMaxSub = 16;          // groups at once per work-group (1024 threads)
+constexpr int kEntryMaxCols = 64;         // candidate columns listed per group (else per column)
+static_assert(kEntryMaxCols <= 64 * kEntryWaves, "one thread per listed column");
 
-// s_eb: dynamic LDS of (blockDim / 256) * kEntryWaves * E_cap * 5 bytes.
+// s_eb: dynamic LDS of blockDim / 64 * E_cap * 5 bytes.
 __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, int nblk)
 {
     const int nsub = blockDim.x / (64 * kEntryWaves);
