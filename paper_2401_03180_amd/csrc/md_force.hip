@@ -351,66 +351,59 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         }
 
         // ---- stage the candidate atoms in the group frame (padding slots hold NaN
-        //      positions and are never inside the cutoff): per entry the FP64 offset of
-        //      the cluster's box corner from the group centre (with the entry's
-        //      periodic shift), rounded once, plus each atom's FP32 offset from that
-        //      corner (written by the repack)
+        //      positions and are never inside the cutoff): one thread per entry adds
+        //      the FP64 offset of the cluster's box corner from the group centre (with
+        //      the entry's periodic shift), rounded once, to the FP32 offsets of its 8
+        //      atoms from that corner (written by the repack).  Each thread walks its
+        //      atoms in an order rotated by its lane, which spreads the LDS writes over
+        //      the banks.
         float m = 0.0f;                        // largest |staged coordinate| or |offset|
-        const int nst = gr.nent * kCluster;
-        constexpr int U = 4;
-        for (int base = tid; base < nst; base += U * blockDim.x) {
-            // an item past the end repeats the last one (its loads and m stay valid)
-            // and is not stored; 32-bit byte offsets keep the load bases scalar
-            uint32_t en[U], slot[U];
+        const int nent = gr.nent;
+        for (int e = tid; e < nent; e += blockDim.x) {
+            // 32-bit byte offsets keep the load bases scalar
+            const uint32_t en =
+                ld_off(A.ent, ((uint32_t)g * (uint32_t)A.E_cap + (uint32_t)e) * 4u);
+            const uint32_t cl = en & kEntClusterMask;
+            const uint32_t cb = (cl << 4) + (cl << 3);          // 24 bytes per corner
+            const uint32_t s0 = cl * kCluster;
+            float4 o[kCluster];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t ic = (uint32_t)min(base + u * (int)blockDim.x, nst - 1);
-                en[u] = ld_off(A.ent, ((uint32_t)g * (uint32_t)A.E_cap + (ic >> 3)) * 4u);
-                slot[u] = (en[u] & kEntClusterMask) * kCluster + (ic & 7u);
+            for (int j = 0; j < kCluster; ++j)
+                o[j] = ld_off(A.xo, (s0 + (uint32_t)((j + lane) & 7)) * (uint32_t)sizeof(float4));
+            // while the lists are rebuilt .w carries the type (the charges are put back
+            // before the pair loop); the 8 types of a cluster are one aligned word
+            const uint64_t types =
+                rebuild ? ld_off(reinterpret_cast<const uint64_t*>(A.ts), s0) : 0ull;
+            float b[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double bd = ld_off(A.cl_lo, cb + 8u * (uint32_t)d) - gr.c[d];
+                if (gs.periodic) {
+                    const int sh = (int)((en >> (26 + 2 * d)) & 3u) - 1;
+                    bd = fma((double)sh, gs.L[d], bd);
+                }
+                b[d] = (float)bd;
             }
-            float4 o[U];
-            double an[U][3];
-            float tv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t cl = en[u] & kEntClusterMask;
-                const uint32_t cb = (cl << 4) + (cl << 3);      // 24 bytes per corner
-                o[u] = ld_off(A.xo, slot[u] * (uint32_t)sizeof(float4));
-                for (int d = 0; d < 3; ++d)
-                    an[u][d] = ld_off(A.cl_lo, cb + 8u * (uint32_t)d);
-                // while the lists are rebuilt .w carries the type (the charges are
-                // put back before the pair loop)
-                tv[u] = rebuild ? __int_as_float((int)ld_off(A.ts, slot[u])) : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int idx = base + u * blockDim.x;
+            for (int j = 0; j < kCluster; ++j) {
+                const int k = (j + lane) & 7;
                 // padding and fast atoms (NaN offsets) go far away, outside every
                 // cutoff; their NaNs do not enter m (max ignores a NaN operand)
-                const bool pad = o[u].x != o[u].x;
-                const float od[3] = {o[u].x, o[u].y, o[u].z};
-                float r[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    double bd = an[u][d] - gr.c[d];
-                    if (gs.periodic) {
-                        const int sh = (int)((en[u] >> (26 + 2 * d)) & 3u) - 1;
-                        bd = fma((double)sh, gs.L[d], bd);
-                    }
-                    const float rv = (float)bd + od[d];
-                    m = fmaxf(m, fmaxf(fabsf(rv), fabsf(od[d])));
-                    r[d] = pad ? kFarF : rv;
-                }
-                if (idx < nst)
-                    s_j[idx] = make_float4(r[0], r[1], r[2],
-                                           pad ? 0.0f : (rebuild ? tv[u] : o[u].w));
-                if (rebuild && idx < nst && (idx & 7) == 0) {
-                    const int e = idx >> 3;
-                    const int c = (int)(en[u] & kEntClusterMask) - gr.cl0;
-                    const uint32_t own = ((en[u] >> 26) == 0x15u && c >= 0 && c < gr.ncl)
-                                             ? (1u << (8 + c)) : 0u;
-                    s_mask[e] = (uint16_t)(A.ent_mask[(int64_t)g * A.E_cap + e] | own);
-                }
+                const bool pad = o[j].x != o[j].x;
+                const float r0 = b[0] + o[j].x, r1 = b[1] + o[j].y, r2 = b[2] + o[j].z;
+                m = fmaxf(m, fmaxf(fabsf(r0), fabsf(o[j].x)));
+                m = fmaxf(m, fmaxf(fabsf(r1), fabsf(o[j].y)));
+                m = fmaxf(m, fmaxf(fabsf(r2), fabsf(o[j].z)));
+                const float wv =
+                    rebuild ? __int_as_float((int)((types >> (8 * k)) & 0xFFull)) : o[j].w;
+                s_j[e * kCluster + k] = pad ? make_float4(kFarF, kFarF, kFarF, 0.0f)
+                                            : make_float4(r0, r1, r2, wv);
+            }
+            if (rebuild) {
+                const int c = (int)cl - gr.cl0;
+                const uint32_t own = ((en >> 26) == 0x15u && c >= 0 && c < gr.ncl)
+                                         ? (1u << (8 + c)) : 0u;
+                s_mask[e] = (uint16_t)(A.ent_mask[(int64_t)g * A.E_cap + e] | own);
             }
         }
         // this wave's i-atoms (slot-indexed): the loads are issued before the barrier,
@@ -480,7 +473,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             // work-group-scope ordering suffices (an agent-scope fence would write
             // back the L2)
             __syncthreads();
-            for (int idx = tid; idx < nst; idx += blockDim.x) {      // charges back in .w
+            for (int idx = tid; idx < nent * kCluster; idx += blockDim.x) {   // charges back
                 const uint32_t en = ent_gl[idx >> 3];
                 const float qv = (float)A.qs[(int64_t)(en & kEntClusterMask) * kCluster + (idx & 7)];
                 reinterpret_cast<float*>(s_j + idx)[3] = qv;
