@@ -359,6 +359,10 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         //      the banks.
         float m = 0.0f;                        // largest |staged coordinate| or |offset|
         const int nent = gr.nent;
+        // the lane index through an opaque move, so the rotated offsets below are
+        // recomputed per group instead of being held (and spilled) across the loop
+        int lrot;
+        __asm__ volatile("v_mov_b32 %0, %1" : "=v"(lrot) : "v"(lane));
         for (int e = tid; e < nent; e += blockDim.x) {
             // 32-bit byte offsets keep the load bases scalar
             const uint32_t en =
@@ -369,7 +373,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             float4 o[kCluster];
 #pragma unroll
             for (int j = 0; j < kCluster; ++j)
-                o[j] = ld_off(A.xo, (s0 + (uint32_t)((j + lane) & 7)) * (uint32_t)sizeof(float4));
+                o[j] = ld_off(A.xo, (s0 + (uint32_t)((j + lrot) & 7)) * (uint32_t)sizeof(float4));
             // while the lists are rebuilt .w carries the type (the charges are put back
             // before the pair loop); the 8 types of a cluster are one aligned word
             const uint64_t types =
@@ -386,7 +390,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             }
 #pragma unroll
             for (int j = 0; j < kCluster; ++j) {
-                const int k = (j + lane) & 7;
+                const int k = (j + lrot) & 7;
                 // padding and fast atoms (NaN offsets) go far away, outside every
                 // cutoff; their NaNs do not enter m (max ignores a NaN operand)
                 const bool pad = o[j].x != o[j].x;
