@@ -24,9 +24,9 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 
-SKINS = (0.05, 0.075, 0.1, 0.15)
+SKINS = (0.06, 0.075, 0.09, 0.1, 0.12)
 GROUPS = (2, 4, 8)
-FAST_SCALE = (0.5, 1.0, 2.0)      # multiples of the automatic capacity
+FAST_SCALE = (0.25, 0.5, 1.0, 2.0)      # multiples of the automatic capacity
 
 
 def device_arch() -> str:
