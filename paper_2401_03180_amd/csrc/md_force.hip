@@ -195,6 +195,15 @@ __device__ inline double reduce8(double v)
     return v;
 }
 
+// Place of list position p in its row of 32 codes: p = 32 r + 8 a + k is stored at
+// 32 r + 4 k + a, so lane k of an atom reads positions k, k + 8, k + 16, k + 24 with
+// one 8-byte load, and at each step the atom's 8 lanes read 8 consecutive positions
+// (mostly neighbouring candidates of one entry: fewer LDS bank conflicts).
+__device__ inline int row_place(int p)
+{
+    return (p & ~31) | ((p & 7) << 2) | ((p >> 3) & 3);
+}
+
 // Rebuild the half-list `half` of cluster I from the candidates staged in LDS
 // (during a rebuild their .w holds the type): the codes (staged index | type << 13)
 // of partners within rc + skin, compacted per atom in entry order.  Each atom's
@@ -248,7 +257,7 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
             }
             if (exc) tcode = A.t_excl;
         }
-        if (pass && pos < cap) out[pos] = (uint16_t)(j | (tcode << kCodeIdxBits));
+        if (pass && pos < cap) out[row_place(pos)] = (uint16_t)(j | (tcode << kCodeIdxBits));
         cnt += __popc(mine);
     };
     // the entries of this half (e = half, half + 2, ...) that reach this cluster, 64
@@ -279,7 +288,7 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
     int mx = cnt;
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
     const int nrow = min((mx + 31) >> 5, cap >> 5);
-    for (int pos = cnt + k; pos < nrow * 32; pos += 8) out[pos] = (uint16_t)sentinel;
+    for (int pos = cnt + k; pos < nrow * 32; pos += 8) out[row_place(pos)] = (uint16_t)sentinel;
     if (lane == 0) {
         A.cl_nt[(int64_t)I * 2 + half] = nrow;
         A.cl_len[(int64_t)I * 2 + half] = mx;
