@@ -4,15 +4,15 @@
 //
 // Work decomposition (full neighbour lists, no atomics, deterministic):
 //   * a persistent work-group pulls cluster groups from a queue;
-//   * it stages every candidate atom of the group's table in LDS, converted once to
-//     FP32 coordinates relative to the group's frame origin (FP64 subtraction, one
-//     rounding), with the charge in .w;
+//   * it stages every candidate atom of the group's table in LDS as FP32 coordinates
+//     relative to the group's centre: per table entry the FP64 offset of the
+//     cluster's box corner (with the entry's periodic shift), rounded once, plus the
+//     atom's FP32 offset from that corner (written by the repack), charge in .w;
 //   * each 64-lane wave owns one 8-atom i-cluster: lane = 8 * i + k walks codes
 //     k, k+8, ... of atom i's compacted list, so all 64 lanes evaluate distinct
 //     pairs; the 8 partial sums of an atom are combined at the end.
 // FP32 path: pair arithmetic in FP32; per-lane sums in FP32 over chunks of 8 terms,
-// folded into a Kahan (sum, compensation) pair; cross-lane combination and the
-// output in FP64.  Membership uses an FP32 distance whose rounding error is
+// accumulated in FP64; cross-lane combination and the output in FP64.  Membership uses an FP32 distance whose rounding error is
 // bounded; pairs inside the error band are re-decided with the FP64 expression,
 // so the pair set equals the FP64 definition.
 // FP64 path: the plain comparison form, every pair in FP64 from the caller's
@@ -176,14 +176,6 @@ __device__ inline int64_t clamp_step(const ForceArgs& A)
         s = s < 0 ? 0 : A.S1 - 1;
     }
     return s;
-}
-
-__device__ inline void kahan_add(float& s, float& c, float x)
-{
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
 }
 
 // Combine the 8 lanes of one atom (lanes 8i .. 8i+7) in FP64.
@@ -507,7 +499,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                             k8;
             const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
             const GridSys* gsp = A.grid + gr.sys;
-            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+            double sx = 0.0, sy = 0.0, sz = 0.0;
             float ax = 0.f, ay = 0.f, az = 0.f, ea = 0.f;
             double eacc = 0.0;
             // one row = 4 codes per lane: the 4 candidate reads are issued together,
@@ -629,18 +621,18 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 v0 = v1;
                 if (r + 2 < nr) v1 = cp[(r + 2) * 8];
                 row(cur);
-                if (r & 1) {      // fold every 8 terms into the compensated sums
-                    kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
+                if (r & 1) {      // fold every 8 terms into the FP64 sums
+                    sx += (double)ax; sy += (double)ay; sz += (double)az;
                     if (ENERGY) eacc += (double)ea;
                     ax = ay = az = ea = 0.0f;
                 }
             }
             if (ENERGY) eacc += (double)ea;
-            kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
-            // true per-lane sum = s - c; combine the atom's 8 lanes in FP64
-            Fx = reduce8((double)sx - (double)cx);
-            Fy = reduce8((double)sy - (double)cy);
-            Fz = reduce8((double)sz - (double)cz);
+            sx += (double)ax; sy += (double)ay; sz += (double)az;
+            // combine the atom's 8 lanes in FP64
+            Fx = reduce8(sx);
+            Fy = reduce8(sy);
+            Fz = reduce8(sz);
             if (ENERGY) Ea = reduce8(eacc);
         }
         // combine the waves of each cluster in a fixed order (deterministic)
