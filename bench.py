@@ -471,8 +471,9 @@ def main():
     achieved = fpp * r32["pairs"] / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                # the counter summary covers the Debye kernel only
-                "traffic": traffic_from_profile() if hy is None and ffb is None else None,
+                # the counter summary covers the Debye kernel on the plain water_98304 run
+                "traffic": (traffic_from_profile() if a.config == "water_98304" and hy is None
+                            and ffb is None and lg is None else None),
                 "kernel": "k_force32" + ("<HYBRID>" if hy is not None else "") +
                           ("<QLJ>" if ffb is not None else ""),
                 "kernel_ms": kernel_ms,
