@@ -137,7 +137,10 @@ const char* md_last_error(const md_ctx* ctx);
  *   seeds     uint64 [B] per-system random seeds;
  *   n_steps   S >= 0.
  * Synchronous.  Resets the step counter to 0 and the error word to 0.  Fails with
- * MD_ERR_GEOMETRY when a periodic box edge is below 2 (rc + skin). */
+ * MD_ERR_GEOMETRY when a periodic box edge is below 2 (rc + skin), and with
+ * MD_ERR_CAPACITY when the workspace would exceed a kernel's limits (the candidate
+ * tables and slot arrays are addressed with 32-bit byte offsets: tens of millions of
+ * atoms per context). */
 md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const double* c12,
                          const int8_t* qmax, const double* lambda_d, const double* base,
                          const double* g, const uint64_t* seeds, int64_t n_steps);

@@ -257,6 +257,12 @@ static md_status size_and_allocate(Ctx* c)
         G /= 2;
     }
     if (E_cap < 32) return fail(c, MD_ERR_CAPACITY, "LDS too small for the candidate table");
+    // the force kernel addresses the candidate tables and the slot arrays with 32-bit
+    // byte offsets
+    if ((uint64_t)c->cap_groups * (uint64_t)E_cap * 4u >= ((uint64_t)1 << 32) ||
+        (uint64_t)c->cap_slots * 16u >= ((uint64_t)1 << 32))
+        return fail(c, MD_ERR_CAPACITY, "system too large for the force kernel's 32-bit offsets "
+                    "(%lld groups x %d entries)", (long long)c->cap_groups, E_cap);
     c->G = G;
     c->E_cap = E_cap;
     int nb_cap = cfg.max_neighbors;
