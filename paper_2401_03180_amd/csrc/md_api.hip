@@ -57,7 +57,7 @@ void free_all(Ctx* c)
                     c->d_col_pre, c->d_cl_lo, c->d_cl_hi,
                     c->d_cl_nt, c->d_cl_len, c->d_perm, c->d_slot_img, c->d_inv_perm, c->d_xs, c->d_xo, c->d_qs,
                     c->d_ts, c->d_groups, c->d_ent, c->d_ent_mask, c->d_nb, c->d_grp_epot, c->d_xref,
-                    c->d_partial, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
+                    c->d_partial, c->d_ek_slots, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
                     c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
                     c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32, c->d_rdf_moved,
                     c->d_rdf_xr, c->d_rdf_er, c->d_invz32, c->d_invz64, c->d_excl_off,
@@ -312,6 +312,8 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, dalloc(&c->d_grp_epot, c->cap_groups));
     HIP_TRY(c, dalloc(&c->d_xref, 3 * N));
     HIP_TRY(c, dalloc(&c->d_partial, c->cap_partials));
+    HIP_TRY(c, dalloc(&c->d_ek_slots, c->cap_partials));
+    HIP_TRY(c, hipMemset(c->d_ek_slots, 0xFF, sizeof(unsigned long long) * c->cap_partials));
     {
         const int64_t nvb = div_up(std::max<int64_t>(N, 1), 256);
         HIP_TRY(c, dalloc(&c->d_fast_flag, std::max<int64_t>(N, 1)));

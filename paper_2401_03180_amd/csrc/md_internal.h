@@ -180,6 +180,9 @@ struct Ctx {
     // integrator
     double* d_xref = nullptr;      // N*3 build positions
     double* d_partial = nullptr;   // cap_partials (kinetic-energy block partials)
+    // the same partials for the fused step, each published as one device-scope atomic
+    // word (kEkSlotEmpty when not yet written; the reader empties them again)
+    unsigned long long* d_ek_slots = nullptr;   // cap_partials
     // atoms that moved more than skin/2 since the last build
     int32_t fast_cap = 0;
     uint8_t* d_fast_flag = nullptr;   // N

@@ -222,6 +222,7 @@ struct VvArgs {
     double *x, *y, *z, *vx, *vy, *vz;
     const double* xref;          // N*3 build positions
     double* partial;             // nblocks + B (kinetic-energy partials)
+    unsigned long long* ek_slots;   // the same as atomic words (fused phase 1), or NULL
     double* disp_partial;        // nblocks (displacement maxima)
     double* ekin;
     const int64_t* sys_off;
@@ -289,6 +290,41 @@ __device__ inline void langevin_normals(uint32_t id, uint32_t s, uint32_t b, uin
     z[2] = r1 * cos(two_pi * u3);
 }
 
+constexpr unsigned long long kEkSlotEmpty = ~0ull;   // a NaN no arithmetic produces
+
+// Phase 1 of the fused step: the extra work-group sums the kinetic-energy partials of
+// every system in the order of the finalize kernel (so the result is the same), waiting
+// for each block's word, and empties the words for the next launch.  A wait that does
+// not end latches MD_FLAG_BARRIER.
+__device__ void ekin_from_slots(const VvArgs& A, double* s_red)
+{
+    for (int b = 0; b < A.B; ++b) {
+        const int64_t s0 = A.sys_off[b], s1 = A.sys_off[b + 1];
+        double t = 0.0;
+        if (s1 > s0) {
+            const int64_t k0 = s0 / kVvBlock, k1 = (s1 - 1) / kVvBlock;
+            for (int64_t k = k0 + threadIdx.x; k <= k1; k += kVvBlock) {
+                unsigned long long* w = A.ek_slots + k + b;
+                unsigned long long v;
+                unsigned spins = 0;
+                while ((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ==
+                       kEkSlotEmpty) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > (1u << 22)) {
+                        atomicOr(&A.dsc->flags, MD_FLAG_BARRIER);
+                        v = 0ull;
+                        break;
+                    }
+                }
+                t += __longlong_as_double((long long)v);
+                __hip_atomic_store(w, kEkSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        t = block_sum_d(t, s_red);
+        if (threadIdx.x == 0) A.ekin[b] = t;
+    }
+}
+
 // IONIZE (phase 0 only): also the ionization of the step this phase starts (the
 // step counter is advanced after this kernel), as md_step issues it.  FIN (phase 1
 // only): one extra work-group runs the force finalize of the step.  LANGEVIN (phase
@@ -301,6 +337,7 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinal
     __shared__ double s_red[kVvBlock / 64];
     if (FIN && blockIdx.x == gridDim.x - 1) {
         force_finalize_block(F);
+        if (EKIN && A.ek_slots) ekin_from_slots(A, s_red);
         return;
     }
     const int64_t a = blockIdx.x * (int64_t)kVvBlock + threadIdx.x;
@@ -383,7 +420,18 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinal
         const int myb = a < A.N ? A.sys_of_atom[a] : -1;
         for (int b = b0; b <= b1; ++b) {
             double t = block_sum_d(myb == b ? ke : 0.0, s_red);
-            if (threadIdx.x == 0) A.partial[blockIdx.x + b] = t;
+            if (threadIdx.x == 0) {
+                if (A.ek_slots) {
+                    // the partial travels as one atomic word: no separate ready flag,
+                    // hence no release fence (an L2 write-back) per work-group
+                    unsigned long long v = (unsigned long long)__double_as_longlong(t);
+                    if (v == kEkSlotEmpty) v = 0x7FF8000000000000ull;
+                    __hip_atomic_store(A.ek_slots + blockIdx.x + b, v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    A.partial[blockIdx.x + b] = t;
+                }
+            }
         }
     }
 }
@@ -433,7 +481,7 @@ static VvArgs vv_args(Ctx* c, int phase, double dt, const double* inv_mass, cons
     A.thr2 = half_skin * half_skin;
     A.inv_mass = inv_mass; A.fx = fx; A.fy = fy; A.fz = fz;
     A.x = x; A.y = y; A.z = z; A.vx = vx; A.vy = vy; A.vz = vz;
-    A.xref = c->d_xref; A.partial = c->d_partial; A.ekin = ekin;
+    A.xref = c->d_xref; A.partial = c->d_partial; A.ek_slots = nullptr; A.ekin = ekin;
     const int nb = (int)div_up(c->N, kVvBlock);
     A.disp_partial = c->d_partial + nb + c->B + 1;
     A.sys_off = c->d_sys_off; A.sys_of_atom = c->d_sys_of_atom; A.B = c->B; A.dsc = c->dsc;
@@ -474,7 +522,12 @@ void launch_vv1_finalize(Ctx* c, double dt, const double* inv_mass, const double
     const IonArgs I{};
     const ForceFinalizeArgs F = force_finalize_args(c, epot);
     const LgArgs L{};
-    if (ekin) {
+    if (ekin && nb > 0) {
+        // the extra work-group also sums the kinetic energies (no separate launch)
+        A.ek_slots = c->d_ek_slots;
+        hipLaunchKernelGGL((k_vv<1, true, false, true>), dim3(nb + 1), dim3(kVvBlock), 0, st, A,
+                           I, F, L);
+    } else if (ekin) {
         hipLaunchKernelGGL((k_vv<1, true, false, true>), dim3(nb + 1), dim3(kVvBlock), 0, st, A,
                            I, F, L);
         hipLaunchKernelGGL((k_vv_finalize<1>), dim3(1), dim3(kVvBlock), 0, st, A, nb);

@@ -552,6 +552,9 @@ def _graph_steps_then_sample(s, prec, steps, n_rows, seed, **kw):
     rows = np.sort(rng.choice(s.n_atoms, n_rows, replace=False))
     ref = oracle.forces_rows(s, rows, q=q, x=x, y=y, z=z, kappa=oracle_kappa(s, steps))
     assert force_error(tuple(f[rows] for f in F), ref) <= TOL[prec]
+    # kinetic energy per system of the last replay (summed inside the fused phase 1)
+    ek = oracle.ekin(s, eng.host("vx"), eng.host("vy"), eng.host("vz"))
+    assert np.allclose(eng.host("ekin"), ek, rtol=1e-12, atol=0.0)
     stats = eng.stats()
     eng.close()
     return stats
@@ -586,3 +589,28 @@ def test_water_large_full_size_sampled():
     say("water_4194304 sampled rows")
     st = _graph_steps_then_sample(s, 1, 4, 200, 51)
     assert st["n_atoms"] == 4194304
+
+
+@pytest.mark.gpu
+def test_graph_step_kinetic_energy_every_replay():
+    """The fused step sums the kinetic energy inside phase 1 (per-block partials as atomic
+    words, emptied after use): every replay's value equals the oracle's sum over the
+    velocities it produced, on a single system and on a batch of systems."""
+    import torch
+    from paper_2401_03180_amd import md
+    for s in (synth.water_small(), synth.methane_clusters(n_clusters=6, n_steps=40)):
+        say("fused kinetic energy", s.n_systems, "systems")
+        eng = make_engine(s, 1)
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            eng.set_step(0, st)
+            eng.build(md.MD_BUILD_FORCE, st)
+            eng.forces(energy=True, stream=st)
+            g = eng.graph(md.MD_BUILD_AUTO, st, energy=True, ekin=True)
+            for rep in range(12):
+                md.md_graph_launch(g, st)
+                st.synchronize()
+                ek = oracle.ekin(s, eng.host("vx"), eng.host("vy"), eng.host("vz"))
+                assert np.allclose(eng.host("ekin"), ek, rtol=1e-12, atol=0.0), rep
+        assert eng.sync_check(raise_on_flags=False) == 0
+        eng.close()
