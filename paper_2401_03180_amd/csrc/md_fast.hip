@@ -220,9 +220,13 @@ __device__ void fast_self(const FastArgs& A, int fi)
     // slot ranges of every (column, z range) pair within reach, one per thread, then
     // swept by the whole work-group as one flattened list
     const int ncy = cy1 - cy0 + 1;
-    const int npairs = (cx1 - cx0 + 1) * ncy * nzr;
-    for (int p0 = 0; p0 < npairs; p0 += kFastRanges) {
-        const int np = min(kFastRanges, npairs - p0);
+    const int npairs = max(0, (cx1 - cx0 + 1) * ncy * nzr);
+    // the other fast atoms of the same system (by their current positions) are items of
+    // the last sweep after its slots, so their loads overlap the slots'
+    const int64_t a0 = A.sys_off[b], a1 = A.sys_off[b + 1];
+    for (int p0 = 0; p0 == 0 || p0 < npairs; p0 += kFastRanges) {
+        const int np = max(0, min(kFastRanges, npairs - p0));
+        const int nextra = p0 + kFastRanges >= npairs ? nf : 0;
         const int t = threadIdx.x;
         int64_t r0 = 0;
         int len = 0;
@@ -249,12 +253,15 @@ __device__ void fast_self(const FastArgs& A, int fi)
             s_pre[t] = off;
         }
         __syncthreads();
-        for (int k0 = t; k0 < total; k0 += kFastU * kFastBlock) {
+        const int nitems = total + nextra;
+        for (int k0 = t; k0 < nitems; k0 += kFastU * kFastBlock) {
             int64_t sl[kFastU];
+            int gg[kFastU];
 #pragma unroll
             for (int u = 0; u < kFastU; ++u) {
                 const int k = k0 + u * kFastBlock;
                 sl[u] = -1;
+                gg[u] = -1;
                 if (k < total) {
                     int lo = 0, hi = np - 1;            // last range with s_pre <= k
                     while (lo < hi) {
@@ -262,6 +269,8 @@ __device__ void fast_self(const FastArgs& A, int fi)
                         if (s_pre[mid] <= k) lo = mid; else hi = mid - 1;
                     }
                     sl[u] = s_r0[lo] + (k - s_pre[lo]);
+                } else if (k < nitems) {
+                    gg[u] = A.fast_list[k - total];
                 }
             }
             double px[kFastU], py[kFastU], pz[kFastU];
@@ -269,6 +278,7 @@ __device__ void fast_self(const FastArgs& A, int fi)
 #pragma unroll
             for (int u = 0; u < kFastU; ++u) {
                 const int64_t s = sl[u];
+                const int g = gg[u];
                 px[u] = NAN; py[u] = 0.0; pz[u] = 0.0; pq[u] = 0; pt[u] = 0; pa[u] = -1;
                 if (s >= 0) {
                     px[u] = A.xs[s];
@@ -277,51 +287,26 @@ __device__ void fast_self(const FastArgs& A, int fi)
                     pq[u] = A.qs[s];
                     pt[u] = A.ts[s];
                     pa[u] = A.perm[s];
+                } else if (g >= 0 && g != f && g >= a0 && g < a1) {
+                    px[u] = A.x[g]; py[u] = A.y[g]; pz[u] = A.z[g];
+                    pq[u] = A.q[g]; pt[u] = A.atype[g];
+                    pa[u] = g;
                 }
             }
 #pragma unroll
             for (int u = 0; u < kFastU; ++u) {
-                if (px[u] != px[u]) continue;          // fast atom, padding or no item
+                // a fast atom or padding slot (NaN), no item, or a fast atom that is f
+                // itself or in another system
+                if (px[u] != px[u] || pa[u] < 0) continue;
+                const bool other_fast = gg[u] >= 0;
                 double dx, dy, dz, fp, e;
-                if (pair_fp64<FULL>(A, gs, kap, hrow, f, pa[u], xf, yf, zf, qf, tf, px[u], py[u], pz[u],
-                              pq[u], pt[u], &dx, &dy, &dz, &fp, &e)) {
+                if (pair_fp64<FULL>(A, gs, kap, hrow, f, pa[u], xf, yf, zf, qf, tf, px[u], py[u],
+                                    pz[u], pq[u], pt[u], &dx, &dy, &dz, &fp, &e)) {
                     Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
-                    if (ENERGY) E += e;
-                    if (EMIT) emit_one(A, f, pa[u]);
+                    // a pair of two fast atoms counts one half from each side
+                    if (ENERGY) E += other_fast ? 0.5 * e : e;
+                    if (EMIT && (!other_fast || f < pa[u])) emit_one(A, f, pa[u]);
                 }
-            }
-        }
-    }
-    // other fast atoms of the same system, by their current positions
-    const int64_t a0 = A.sys_off[b], a1 = A.sys_off[b + 1];
-    for (int k0 = threadIdx.x; k0 < nf; k0 += kFastU * kFastBlock) {
-        int gg[kFastU];
-#pragma unroll
-        for (int u = 0; u < kFastU; ++u) {
-            const int k = k0 + u * kFastBlock;
-            gg[u] = k < nf ? A.fast_list[k] : -1;
-        }
-        double px[kFastU], py[kFastU], pz[kFastU];
-        int pq[kFastU], pt[kFastU];
-#pragma unroll
-        for (int u = 0; u < kFastU; ++u) {
-            const int g = gg[u];
-            px[u] = 0.0; py[u] = 0.0; pz[u] = 0.0; pq[u] = 0; pt[u] = 0;
-            if (g != f && g >= a0 && g < a1) {
-                px[u] = A.x[g]; py[u] = A.y[g]; pz[u] = A.z[g];
-                pq[u] = A.q[g]; pt[u] = A.atype[g];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kFastU; ++u) {
-            const int g = gg[u];
-            if (g == f || g < a0 || g >= a1) continue;
-            double dx, dy, dz, fp, e;
-            if (pair_fp64<FULL>(A, gs, kap, hrow, f, g, xf, yf, zf, qf, tf, px[u], py[u], pz[u], pq[u],
-                          pt[u], &dx, &dy, &dz, &fp, &e)) {
-                Fx += fp * dx; Fy += fp * dy; Fz += fp * dz;
-                if (ENERGY) E += 0.5 * e;
-                if (EMIT && f < g) emit_one(A, f, g);
             }
         }
     }
