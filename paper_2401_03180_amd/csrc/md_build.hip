@@ -866,7 +866,9 @@ __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs 
     const int pending = d->need_rebuild;
     // unless a rebuild is already requested, the slot repack for the current lists
     // runs first, before the decision is known (a rebuild rewrites everything it
-    // writes, after several grid barriers)
+    // writes, after several grid barriers; the binning of a rebuild may clear the fast
+    // flags while another work-group's repack still reads them, which only changes
+    // values that are rewritten)
     if (!S.force && !pending) repack_range(S.rp, gid, gstride, false);
     int cnt = 0;
     for (int k = threadIdx.x; k < S.join.nblocks; k += blockDim.x) cnt += S.join.fast_cnt[k];

@@ -295,7 +295,8 @@ constexpr unsigned long long kEkSlotEmpty = ~0ull;   // a NaN no arithmetic prod
 // Phase 1 of the fused step: the extra work-group sums the kinetic-energy partials of
 // every system in the order of the finalize kernel (so the result is the same), waiting
 // for each block's word, and empties the words for the next launch.  A wait that does
-// not end latches MD_FLAG_BARRIER.
+// not end latches MD_FLAG_BARRIER (the step's results are then not to be trusted, as
+// after any latched error).
 __device__ void ekin_from_slots(const VvArgs& A, double* s_red)
 {
     for (int b = 0; b < A.B; ++b) {
