@@ -607,9 +607,17 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                         f = fmaf(uc * s, 1.0f + kr, wl) * rinv2;
                         e = fmaf(uc, s, l12 - l6);
                     }
-                    ax = fmaf(f, dx[u], ax);
-                    ay = fmaf(f, dy[u], ay);
-                    az = fmaf(f, dz[u], az);
+                    if (HYBRID) {
+                        // recomputed here: holding the 4 separations across the pair terms
+                        // spills registers in this variant
+                        ax = fmaf(f, xi - pj[u].x, ax);
+                        ay = fmaf(f, yi - pj[u].y, ay);
+                        az = fmaf(f, zi - pj[u].z, az);
+                    } else {
+                        ax = fmaf(f, dx[u], ax);
+                        ay = fmaf(f, dy[u], ay);
+                        az = fmaf(f, dz[u], az);
+                    }
                     if (ENERGY) ea += e;
                 }
             };
