@@ -304,6 +304,27 @@ __device__ void ph_bin_sort(const int32_t* bin_start, int32_t* sorted, int32_t* 
         if (b >= nbins) continue;
         const int s = bin_start[b], e = bin_start[b + 1];
         if (e - s < 2 || e - s > 128) continue;
+        if (e - s <= 8) {
+            // the common case (a bin holds ~2 atoms): all loads at once, a sorting
+            // network in registers (Batcher's odd-even merge for 8 inputs), all stores
+            constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6},
+                                         {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
+                                         {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+            int v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = s + i < e ? sorted[s + i] : INT_MAX;
+#pragma unroll
+            for (int c = 0; c < 19; ++c) {
+                const int lo = min(v[kNet[c][0]], v[kNet[c][1]]);
+                const int hi = max(v[kNet[c][0]], v[kNet[c][1]]);
+                v[kNet[c][0]] = lo;
+                v[kNet[c][1]] = hi;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (s + i < e) sorted[s + i] = v[i];
+            continue;
+        }
         for (int i = s + 1; i < e; ++i) {
             const int v = sorted[i];
             int j = i - 1;
