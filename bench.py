@@ -484,8 +484,8 @@ def main():
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": r32["ms"] / a.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": a.config, "atoms": n, "precision": "fp32 pair forces, 8-term "
-                      "partials summed in fp64; fp64 positions/integration/energies", "rc_nm": sys32.rc,
+           "config": {"workload": a.config, "atoms": n, "precision": "fp32 forces + kahan, "
+                      "fp64 positions/integration/energies", "rc_nm": sys32.rc,
                       "skin_nm": k32["skin"] if k32["skin"] is not None else sys32.skin,
                       "cluster_group": r32["stats"]["cluster_group"],
                       "fast_capacity": k32["fast_capacity"], "tuned": k32["tuned"],

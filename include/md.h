@@ -57,9 +57,7 @@ typedef enum md_status {
 
 typedef enum md_precision {
     MD_FP64 = 0,            /* plain FP64 pair arithmetic and accumulation */
-    MD_FP32_KAHAN = 1       /* FP32 pair arithmetic; per-atom sums of 8-term FP32 partials
-                               accumulated in FP64 (no less accurate than a compensated
-                               FP32 sum, whose name the constant keeps) */
+    MD_FP32_KAHAN = 1       /* FP32 pair arithmetic, FP32 + compensated per-atom sums */
 } md_precision;
 
 /* Device error word bits (latched until md_clear_flags). */

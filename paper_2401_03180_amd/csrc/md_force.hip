@@ -12,7 +12,8 @@
 //     k, k+8, ... of atom i's compacted list, so all 64 lanes evaluate distinct
 //     pairs; the 8 partial sums of an atom are combined at the end.
 // FP32 path: pair arithmetic in FP32; per-lane sums in FP32 over chunks of 8 terms,
-// accumulated in FP64; cross-lane combination and the output in FP64.  Membership uses an FP32 distance whose rounding error is
+// folded into a Kahan (sum, compensation) pair; cross-lane combination and the
+// output in FP64.  Membership uses an FP32 distance whose rounding error is
 // bounded; pairs inside the error band are re-decided with the FP64 expression,
 // so the pair set equals the FP64 definition.
 // FP64 path: the plain comparison form, every pair in FP64 from the caller's
@@ -176,6 +177,14 @@ __device__ inline int64_t clamp_step(const ForceArgs& A)
         s = s < 0 ? 0 : A.S1 - 1;
     }
     return s;
+}
+
+__device__ inline void kahan_add(float& s, float& c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
 }
 
 // Combine the 8 lanes of one atom (lanes 8i .. 8i+7) in FP64.
@@ -499,7 +508,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                             k8;
             const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
             const GridSys* gsp = A.grid + gr.sys;
-            double sx = 0.0, sy = 0.0, sz = 0.0;
+            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
             float ax = 0.f, ay = 0.f, az = 0.f, ea = 0.f;
             double eacc = 0.0;
             // one row = 4 codes per lane: the 4 candidate reads are issued together,
@@ -629,18 +638,18 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 v0 = v1;
                 if (r + 2 < nr) v1 = cp[(r + 2) * 8];
                 row(cur);
-                if (r & 1) {      // fold every 8 terms into the FP64 sums
-                    sx += (double)ax; sy += (double)ay; sz += (double)az;
+                if (r & 1) {      // fold every 8 terms into the compensated sums
+                    kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
                     if (ENERGY) eacc += (double)ea;
                     ax = ay = az = ea = 0.0f;
                 }
             }
             if (ENERGY) eacc += (double)ea;
-            sx += (double)ax; sy += (double)ay; sz += (double)az;
-            // combine the atom's 8 lanes in FP64
-            Fx = reduce8(sx);
-            Fy = reduce8(sy);
-            Fz = reduce8(sz);
+            kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
+            // true per-lane sum = s - c; combine the atom's 8 lanes in FP64
+            Fx = reduce8((double)sx - (double)cx);
+            Fy = reduce8((double)sy - (double)cy);
+            Fz = reduce8((double)sz - (double)cz);
             if (ENERGY) Ea = reduce8(eacc);
         }
         // combine the waves of each cluster in a fixed order (deterministic)
