@@ -471,6 +471,7 @@ __global__ void __launch_bounds__(256) k_clusters(ClusterArgs A)
 struct EntryArgs {
     const GridSys* grid;
     const int64_t* col_pre;
+    const int32_t* bin_start;     // first sorted atom of each bin (columns' z bins)
     const double* cl_lo;
     const double* cl_hi;
     Group* groups;
@@ -485,14 +486,18 @@ struct EntryArgs {
 // kEntryWaves waves per group (one: measured fastest, since this latency-bound phase
 // gains more from groups in flight than from lanes per group); a work-group of
 // 64 kEntryWaves k threads works on k groups at once.  The candidate columns of a
-// group and their cluster ranges are listed in LDS, and the clusters of all of them
-// are dealt to the group's lanes as one flat sequence (so every lane has work and the
-// loads of many clusters are in flight together); each wave appends its passing
-// (cluster, shift) candidates in a fixed order with a ballot prefix, and the wave
-// lists are concatenated in wave order, so the table is deterministic.
+// group are listed in LDS with, per z image, the range of their clusters that holds
+// an atom inside the group's z window widened by rc + skin (found from the column's
+// z bins: a cluster with no atom in that window has no pair within reach), and the
+// clusters of all ranges are dealt to the group's lanes as one flat sequence (so
+// every lane has work and the loads of many clusters are in flight together); each
+// wave appends its passing (cluster, shift) candidates in a fixed order with a
+// ballot prefix, and the wave lists are concatenated in wave order, so the table is
+// deterministic.
 constexpr int kEntryWaves = 1;
 constexpr int kEntryMaxSub = 16;          // groups at once per work-group (1024 threads)
 constexpr int kEntryMaxCols = 64;         // candidate columns listed per group (else per column)
+constexpr int kEntrySeg = 3;              // cluster ranges per listed column (z images -1, 0, 1)
 static_assert(kEntryMaxCols <= 64 * kEntryWaves, "one thread per listed column");
 
 // s_eb: dynamic LDS of blockDim / 64 * E_cap * 5 bytes.
@@ -506,9 +511,11 @@ __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, in
     s_eb += sub * kEntryWaves * A.E_cap;
     __shared__ int s_cnt_all[kEntryMaxSub][kEntryWaves];
     __shared__ double s_cb_all[kEntryMaxSub][kMaxGroup][6];
-    __shared__ int s_cj0_all[kEntryMaxSub][kEntryMaxCols];       // first cluster of a column
-    __shared__ int s_cpre_all[kEntryMaxSub][kEntryMaxCols + 1];  // prefix of cluster counts
-    __shared__ uint8_t s_csh_all[kEntryMaxSub][kEntryMaxCols];   // (sx + 1) | (sy + 1) << 2
+    // per (listed column, z image) range: first cluster, prefix of the cluster counts,
+    // shifts (sx + 1) | (sy + 1) << 2 | (sz + 1) << 4
+    __shared__ int s_cj0_all[kEntryMaxSub][kEntrySeg * kEntryMaxCols];
+    __shared__ int s_cpre_all[kEntryMaxSub][kEntrySeg * kEntryMaxCols + 1];
+    __shared__ uint8_t s_csh_all[kEntryMaxSub][kEntrySeg * kEntryMaxCols];
     int* s_cnt = s_cnt_all[sub];
     double (*s_cb)[6] = s_cb_all[sub];
     int* s_cj0 = s_cj0_all[sub];
@@ -572,51 +579,76 @@ __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, in
             const int c = ltid / 6, d = ltid % 6;
             s_cb[c][d] = d < 3 ? A.cl_lo[(gr.cl0 + c) * 3 + d] : A.cl_hi[(gr.cl0 + c) * 3 + d - 3];
         }
+        const int nseg = kEntrySeg * ncol;
         if (flat && ltid < ncol) {
             int col, sx, sy;
             const bool ok = column(ltid, &col, &sx, &sy);
+            const int nz = gs.n[2];
+            const int bin0 = gs.bin_off + (col - gs.col_off) * nz;
             const int j0 = ok ? col_cl0(A.col_pre, col) : 0;
-            s_cj0[ltid] = j0;
-            s_cpre[ltid + 1] = ok ? col_cl0(A.col_pre, col + 1) - j0 : 0;
-            s_csh[ltid] = (uint8_t)((sx + 1) | ((sy + 1) << 2));
+            const int a0 = ok ? A.bin_start[bin0] : 0;
+            const double oz = gs.periodic ? 0.0 : gs.origin[2];
+            const double eps = 1e-6 * (1.0 + rl);   // beyond any rounding of the bin edges
+            for (int q = 0; q < kEntrySeg; ++q) {
+                const int sz = q - 1;
+                int k0 = 0, nk = 0;
+                if (ok && (gs.periodic || sz == 0)) {
+                    // the window in the binning coordinate of this image, then its bins
+                    // (bin index is monotone in z, clamped at the ends like the binning)
+                    const double shz = gs.periodic ? sz * gs.L[2] : 0.0;
+                    const double z0 = lo[2] - rl - eps - shz - oz;
+                    const double z1 = hi[2] + rl + eps - shz - oz;
+                    const double f0 = floor(z0 * gs.inv_w[2]), f1 = floor(z1 * gs.inv_w[2]);
+                    if (f1 >= 0.0 && f0 <= (double)(nz - 1)) {
+                        const int b0 = (int)fmax(f0, 0.0), b1 = (int)fmin(f1, (double)(nz - 1));
+                        const int s0 = A.bin_start[bin0 + b0] - a0;
+                        const int s1 = A.bin_start[bin0 + b1 + 1] - a0;
+                        if (s1 > s0) {
+                            k0 = s0 / kCluster;
+                            nk = (s1 - 1) / kCluster - k0 + 1;
+                        }
+                    }
+                }
+                const int i = kEntrySeg * ltid + q;
+                s_cj0[i] = j0 + k0;
+                s_cpre[i + 1] = nk;
+                s_csh[i] = (uint8_t)((sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4));
+            }
         }
         __syncthreads();
         if (flat && ltid < 64) {                 // prefix of the counts (one wave)
             int carry = 0;
-            for (int base = 0; base < ncol; base += 64) {
+            for (int base = 0; base < nseg; base += 64) {
                 const int i = base + lane;
-                const int v = i < ncol ? s_cpre[i + 1] : 0;
+                const int v = i < nseg ? s_cpre[i + 1] : 0;
                 int inc = v;
                 for (int o = 1; o < 64; o <<= 1) {
                     const int y = __shfl_up(inc, o, 64);
                     if (lane >= o) inc += y;
                 }
-                if (i < ncol) s_cpre[i + 1] = carry + inc;
+                if (i < nseg) s_cpre[i + 1] = carry + inc;
                 carry += __shfl(inc, 63, 64);
             }
             if (lane == 0) s_cpre[0] = 0;
         }
         __syncthreads();
         int count = 0;
-        // test cluster J (this lane's, when `has`) under the column shifts and every z
-        // image; append the passing ones in (image, lane) order
-        auto test_append = [&](bool has, int J, int sx, int sy) {
+        // test cluster J (this lane's, when `has`) under the column shifts and the z
+        // images sz0 .. sz1; append the passing ones in (image, lane) order
+        // (jlo, jhi: the box of J, read by the caller when `has`)
+        auto test_append = [&](bool has, int J, int sx, int sy, int sz0, int sz1, double* jlo,
+                               double* jhi) {
             const double shx = gs.periodic ? sx * gs.L[0] : 0.0;
             const double shy = gs.periodic ? sy * gs.L[1] : 0.0;
-            double jlo[3] = {0, 0, 0}, jhi[3] = {0, 0, 0};
             double dxy2 = INFINITY;
             if (has) {
-                for (int d = 0; d < 3; ++d) {
-                    jlo[d] = A.cl_lo[(int64_t)J * 3 + d];
-                    jhi[d] = A.cl_hi[(int64_t)J * 3 + d];
-                }
                 jlo[0] += shx; jhi[0] += shx;
                 jlo[1] += shy; jhi[1] += shy;
                 const double gx = fmax(0.0, fmax(jlo[0] - hi[0], lo[0] - jhi[0]));
                 const double gy = fmax(0.0, fmax(jlo[1] - hi[1], lo[1] - jhi[1]));
                 dxy2 = gx * gx + gy * gy;
             }
-            for (int sz = gs.periodic ? -1 : 0; sz <= (gs.periodic ? 1 : 0); ++sz) {
+            for (int sz = sz0; sz <= sz1; ++sz) {
                 const double shz = gs.periodic ? sz * gs.L[2] : 0.0;
                 const double zl = jlo[2] + shz, zh = jhi[2] + shz;
                 const double gz = fmax(0.0, fmax(zl - hi[2], lo[2] - zh));
@@ -642,27 +674,57 @@ __device__ void ph_group_entries(const EntryArgs& A, uint32_t* s_eb, int bid, in
                 count += __popcll(bal);
             }
         };
+        // the box of cluster J (when `has`)
+        auto load_box = [&](bool has, int J, double* jlo, double* jhi) {
+            for (int d = 0; d < 3; ++d) {
+                jlo[d] = has ? A.cl_lo[(int64_t)J * 3 + d] : 0.0;
+                jhi[d] = has ? A.cl_hi[(int64_t)J * 3 + d] : 0.0;
+            }
+        };
         if (flat) {
-            const int ntot = s_cpre[ncol];
-            for (int t0 = w * 64; t0 < ntot; t0 += kEntryWaves * 64) {
-                const int t = t0 + lane;
-                const bool has = t < ntot;
-                // the candidate column of item t: the last ci with s_cpre[ci] <= t
-                int a = 0, b = ncol - 1;
+            const int ntot = s_cpre[nseg];
+            // item t: its range (the last ci with s_cpre[ci] <= t), cluster and shifts;
+            // the next item's box is read before this one is tested (the loads' latency
+            // overlaps the tests)
+            auto item = [&](int t, int* J, int* sh) {
+                int a = 0, b = nseg - 1;
                 while (a < b) {
                     const int m = (a + b + 1) >> 1;
                     if (s_cpre[m] <= t) a = m; else b = m - 1;
                 }
-                const int sh = s_csh[a];
-                test_append(has, s_cj0[a] + (t - s_cpre[a]), (sh & 3) - 1, (sh >> 2) - 1);
+                *sh = s_csh[a];
+                *J = s_cj0[a] + (t - s_cpre[a]);
+            };
+            int nJ = 0, nsh = 0;
+            double nlo[3], nhi[3];
+            const int t_first = w * 64 + lane;
+            if (w * 64 < ntot) item(t_first, &nJ, &nsh);
+            load_box(t_first < ntot, nJ, nlo, nhi);
+            for (int t0 = w * 64; t0 < ntot; t0 += kEntryWaves * 64) {
+                const int t = t0 + lane;
+                const bool has = t < ntot;
+                const int J = nJ, sh = nsh;
+                double jlo[3], jhi[3];
+                for (int d = 0; d < 3; ++d) { jlo[d] = nlo[d]; jhi[d] = nhi[d]; }
+                const int tn = t + kEntryWaves * 64;
+                if (t0 + kEntryWaves * 64 < ntot) {
+                    item(tn, &nJ, &nsh);
+                    load_box(tn < ntot, nJ, nlo, nhi);
+                }
+                const int sz = ((sh >> 4) & 3) - 1;
+                test_append(has, J, (sh & 3) - 1, ((sh >> 2) & 3) - 1, sz, sz, jlo, jhi);
             }
         } else {
             for (int ci = w; ci < ncol; ci += kEntryWaves) {
                 int col, sx, sy;
                 if (!column(ci, &col, &sx, &sy)) continue;
                 const int j0 = col_cl0(A.col_pre, col), j1 = col_cl0(A.col_pre, col + 1);
-                for (int base = j0; base < j1; base += 64)
-                    test_append(base + lane < j1, base + lane, sx, sy);
+                for (int base = j0; base < j1; base += 64) {
+                    double jlo[3], jhi[3];
+                    load_box(base + lane < j1, base + lane, jlo, jhi);
+                    test_append(base + lane < j1, base + lane, sx, sy, gs.periodic ? -1 : 0,
+                                gs.periodic ? 1 : 0, jlo, jhi);
+                }
             }
         }
         if (lane == 0) s_cnt[w] = count;
@@ -748,7 +810,7 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
         hipLaunchKernelGGL(k_clusters, dim3(nb), dim3(256), 0, st, A);
     }
     {
-        EntryArgs A{c->d_grid, c->d_col_pre, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
+        EntryArgs A{c->d_grid, c->d_col_pre, c->d_bin_start, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
                     c->d_ent_mask, c->E_cap, c->rlist, c->dsc, gate};
         const size_t lds = (size_t)kEntryWaves * c->E_cap * (sizeof(uint32_t) + 1);
         const int nb = (int)std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * 4);
@@ -979,7 +1041,7 @@ void launch_build_step(Ctx* c, const double* x, const double* y, const double* z
                        c->d_col_pre, c->d_img, c->d_perm, c->d_inv_perm, c->d_slot_img, c->d_ts,
                        c->d_atype, c->d_xs, c->cap_slots, c->d_cl_lo, c->d_cl_hi, c->d_groups,
                        c->d_sys_grp0, c->cap_clusters, c->G, c->T, c->dsc, nullptr};
-    S.en = EntryArgs{c->d_grid, c->d_col_pre, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
+    S.en = EntryArgs{c->d_grid, c->d_col_pre, c->d_bin_start, c->d_cl_lo, c->d_cl_hi, c->d_groups, c->d_ent,
                      c->d_ent_mask, c->E_cap, c->rlist, c->dsc, nullptr};
     S.bin_cnt = c->d_bin_cnt; S.bin_start = c->d_bin_start; S.n_bin_scan = c->cap_bins + 1;
     S.col_cnt = c->d_col_cnt; S.col_pre = c->d_col_pre; S.n_col_scan = c->cap_cols + 1;

@@ -241,7 +241,9 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
         const int j = e * kCluster + k;
         const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const bool pass = live && (r2 < thr2) && !(own && k == il);
+        // no test of the i-atom itself: padding and fast i-atoms sit at -kFarF and
+        // padding candidates at +kFarF, far outside every cutoff
+        const bool pass = (r2 < thr2) && !(own && k == il);
         const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
         const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
         const int pos = cnt + __popc(mine & below);
