@@ -128,6 +128,13 @@ __device__ inline T ld_off(const T* p, uint32_t byte_off)
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
 }
 
+// Global store at a 32-bit byte offset from a base pointer (the base stays scalar).
+template <class T>
+__device__ inline void st_off(T* p, uint32_t byte_off, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + byte_off) = v;
+}
+
 __device__ inline int64_t slot_of_code(const uint32_t* ent_g, uint32_t idx)
 {
     const uint32_t en = ent_g[idx >> 3];
@@ -220,8 +227,14 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
                                  const uint16_t* s_mask, int sentinel, const uint32_t* ent_g)
 {
     const int lane = threadIdx.x & 63;
-    uint16_t* out = A.nb + (((int64_t)I * 2 + half) * kCluster + il) * A.nb_cap_h;
+    // this half-list block of the cluster (wave-uniform base) and the lane's atom row
+    // in it (a 32-bit byte offset, so the stores keep a scalar base)
+    uint16_t* outw = A.nb + ((int64_t)I * 2 + half) * kCluster * A.nb_cap_h;
+    const uint32_t lrow = (uint32_t)(il * A.nb_cap_h);
     const bool live = ai >= 0;
+    // on the cluster's own entry the lane whose candidate is its own atom (k == il)
+    // compares against a negative threshold: one compare decides every lane
+    const float thr_own = k == il ? -1.0f : A.thr2;
     const uint32_t below = (1u << k) - 1u;      // lanes of this atom before this one
     const float thr2 = A.thr2;
     const int cap = A.nb_cap_h;
@@ -243,8 +256,8 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         // no test of the i-atom itself: padding and fast i-atoms sit at -kFarF and
         // padding candidates at +kFarF, far outside every cutoff
-        const bool pass = (r2 < thr2) && !(own && k == il);
-        const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
+        const bool pass = r2 < (own ? thr_own : thr2);
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(pass);
         const uint32_t mine = (uint32_t)(bal >> (il * 8)) & 0xFFu;
         const int pos = cnt + __popc(mine & below);
         int tcode = __float_as_int(pj.w);
@@ -260,7 +273,9 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
             }
             if (exc) tcode = A.t_excl;
         }
-        if (pass && pos < cap) out[row_place(pos)] = (uint16_t)(j | (tcode << kCodeIdxBits));
+        if (pass && pos < cap)
+            st_off(outw, (lrow + (uint32_t)row_place(pos)) * 2u,
+                   (uint16_t)(j | (tcode << kCodeIdxBits)));
         cnt += __popc(mine);
     };
     // the entries of this half (e = half, half + 2, ...) that reach this cluster, 64
@@ -291,7 +306,8 @@ __device__ int build_half_list_t(const ForceArgs& A, int I, int half, int cw, in
     int mx = cnt;
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
     const int nrow = min((mx + 31) >> 5, cap >> 5);
-    for (int pos = cnt + k; pos < nrow * 32; pos += 8) out[row_place(pos)] = (uint16_t)sentinel;
+    for (int pos = cnt + k; pos < nrow * 32; pos += 8)
+        st_off(outw, (lrow + (uint32_t)row_place(pos)) * 2u, (uint16_t)sentinel);
     if (lane == 0) {
         A.cl_nt[(int64_t)I * 2 + half] = nrow;
         A.cl_len[(int64_t)I * 2 + half] = mx;
