@@ -251,7 +251,8 @@ static md_status size_and_allocate(Ctx* c)
         const double safety = cfg.periodic ? 1.35 : 2.4;
         const int est = (int)(V * rho / kCluster * safety) + 16;
         E_cap = std::min(est, kMaxGroupEntries);
-        while (E_cap > 32 && force32_lds_bytes(E_cap) + 8192 > c->max_lds)
+        while (E_cap > 32 &&
+               force32_lds_bytes(E_cap, MD_MAX_CHARGE_STATES) + 8192 > c->max_lds)
             E_cap -= 8;
         if (E_cap >= est || G == 1) break;
         G /= 2;

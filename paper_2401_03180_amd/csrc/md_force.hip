@@ -338,7 +338,6 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 {
     extern __shared__ float4 s_j[];
     __shared__ float2 s_lj[MD_MAX_TYPES * MD_MAX_TYPES];
-    __shared__ float4 s_hyb[HYBRID ? MD_MAX_CHARGE_STATES : 1];   // {r', c1, c2, c3} per charge
     __shared__ float s_m[kForceBlockMax / 64];
     __shared__ double s_part[kForceBlockMax / 64][kCluster][4];
     __shared__ int s_g;
@@ -359,6 +358,10 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         for (int i = tid; i < MD_MAX_TYPES; i += blockDim.x) s_invz[i] = A.invz32[i];
     const int sentinel = A.E_cap * kCluster;
     uint16_t* s_mask = reinterpret_cast<uint16_t*>(s_j + sentinel + 1);
+    // hybrid screening: {r', c1, c2, c3} per charge state, after the masks (dynamic LDS
+    // sized by the bound charge states)
+    float4* s_hyb = reinterpret_cast<float4*>(
+        reinterpret_cast<char*>(s_mask) + ((A.E_cap * sizeof(uint16_t) + 15) & ~(size_t)15));
     if (tid == 0) s_j[sentinel] = make_float4(kFarF, kFarF, kFarF, 0.0f);
     const float rc2f = (float)A.rc2;
     const int64_t cs = A.cap_slots;
@@ -831,11 +834,13 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
 
 // ------------------------------------------------------------------ launch
 
-size_t force32_lds_bytes(int E_cap)
+size_t force32_lds_bytes(int E_cap, int hyb_q)
 {
-    // staged candidates (+ the far sentinel) and the per-entry reach / self masks
+    // staged candidates (+ the far sentinel), the per-entry reach / self masks and the
+    // hybrid-screening rows of the bound charge states
     return (size_t)(E_cap * kCluster + 1) * sizeof(float4) +
-           (size_t)((E_cap * sizeof(uint16_t) + 15) & ~(size_t)15);
+           (size_t)((E_cap * sizeof(uint16_t) + 15) & ~(size_t)15) +
+           (size_t)hyb_q * sizeof(float4);
 }
 
 template <bool E, bool M, bool S>
@@ -843,12 +848,13 @@ static void set_lds_attr(size_t lds)
 {
     (void)hipFuncSetAttribute((const void*)k_force32<E, M, S>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int lds_h = (int)(lds + MD_MAX_CHARGE_STATES * sizeof(float4));
     (void)hipFuncSetAttribute((const void*)k_force32<E, M, S, false, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_h);
     (void)hipFuncSetAttribute((const void*)k_force32<E, M, S, false, false, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute((const void*)k_force32<E, M, S, false, true, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_h);
 }
 
 hipError_t force_kernel_setup(Ctx* c)
@@ -874,7 +880,8 @@ static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks
 {
     if (prec == MD_FP32_KAHAN)
         hipLaunchKernelGGL((k_force32<E, M, S, false, H, Q>), dim3(blocks),
-                           dim3(64 * c->G * A.wpc), force32_lds_bytes(c->E_cap), st, A);
+                           dim3(64 * c->G * A.wpc), force32_lds_bytes(c->E_cap, H ? c->hyb_q : 0),
+                           st, A);
     else
         hipLaunchKernelGGL((k_force64<E, M, S, H, Q>), dim3(blocks), dim3(64 * c->G), 0, st, A);
 }
@@ -928,7 +935,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     // persistent grid: as many work-groups as fit on every CU at once (LDS, waves)
     int per_cu32;
     {
-        const size_t lds = force32_lds_bytes(c->E_cap) +
+        const size_t lds = force32_lds_bytes(c->E_cap, c->hybrid ? c->hyb_q : 0) +
                            (c->hybrid ? c->force32_static_lds_h : c->force32_static_lds);
         per_cu32 = (int)std::max<size_t>(1, c->lds_per_cu / lds);
         per_cu32 = std::min(per_cu32, std::max(1, 32 / (c->G * A.wpc)));

@@ -68,7 +68,8 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool finalize = true);
 struct ForceFinalizeArgs;
 ForceFinalizeArgs force_finalize_args(Ctx* c, double* epot);
-size_t force32_lds_bytes(int E_cap);
+// dynamic LDS of the FP32 force kernel (hyb_q: bound hybrid charge states, else 0)
+size_t force32_lds_bytes(int E_cap, int hyb_q = 0);
 
 // md_fast.hip
 void launch_fast(Ctx* c, const double* x, const double* y, const double* z, const int8_t* q,
