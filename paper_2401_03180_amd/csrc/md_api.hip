@@ -316,9 +316,10 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, dalloc(&c->d_ek_slots, c->cap_partials));
     HIP_TRY(c, hipMemset(c->d_ek_slots, 0xFF, sizeof(unsigned long long) * c->cap_partials));
     {
-        const int64_t nvb = div_up(std::max<int64_t>(N, 1), 256);
+        // per integrator work-group: its fast atoms (kVvBlock slots) and their count
+        const int64_t nvb = div_up(std::max<int64_t>(N, 1), kVvBlock);
         HIP_TRY(c, dalloc(&c->d_fast_flag, std::max<int64_t>(N, 1)));
-        HIP_TRY(c, dalloc(&c->d_fast_loc, nvb * 256));
+        HIP_TRY(c, dalloc(&c->d_fast_loc, nvb * kVvBlock));
         HIP_TRY(c, dalloc(&c->d_fast_cnt, nvb));
         HIP_TRY(c, dalloc(&c->d_fast_list, std::max(c->fast_cap, 1)));
         HIP_TRY(c, dalloc(&c->d_fast_e, std::max(c->fast_cap, 1)));
@@ -355,7 +356,8 @@ static md_status size_and_allocate(Ctx* c)
     HIP_TRY(c, hipMemset(c->d_fast_flag, 0, std::max<int64_t>(N, 1)));
     HIP_TRY(c, hipMemset(c->d_atype, 0, std::max<int64_t>(N, 1)));
     HIP_TRY(c, hipMemset(c->d_bar_arrive, 0, sizeof(uint32_t) * c->cap_bar));
-    HIP_TRY(c, hipMemset(c->d_fast_cnt, 0, sizeof(int32_t) * div_up(std::max<int64_t>(N, 1), 256)));
+    HIP_TRY(c, hipMemset(c->d_fast_cnt, 0,
+                         sizeof(int32_t) * div_up(std::max<int64_t>(N, 1), kVvBlock)));
     HIP_TRY(c, force_kernel_setup(c));
     HIP_TRY(c, build_step_setup(c));
     return MD_OK;

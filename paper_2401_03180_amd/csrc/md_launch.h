@@ -5,6 +5,8 @@
 
 namespace md {
 
+constexpr int kVvBlock = 256;       // threads per work-group of the integrator kernels
+
 // md_step.hip
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 void launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, const int32_t* gate,

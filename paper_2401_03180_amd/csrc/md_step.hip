@@ -212,7 +212,6 @@ void launch_ionize(Ctx* c, const uint8_t* elem, const uint32_t* atom_id, int8_t*
 
 // ------------------------------------------------------------------ velocity Verlet
 
-constexpr int kVvBlock = 256;
 
 struct VvArgs {
     int64_t N;
