@@ -5,7 +5,7 @@
 
 namespace md {
 
-constexpr int kVvBlock = 256;       // threads per work-group of the integrator kernels
+constexpr int kVvBlock = 512;       // threads per work-group of the integrator kernels (measured: 512 beats 128, 256, 1024)
 
 // md_step.hip
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
