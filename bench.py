@@ -193,7 +193,7 @@ def ff_binding(sys_, kind):
     from paper_2401_03180_amd import synth
     d = synth.molecular_force_field(sys_, kind)
     sys_.c6, sys_.c12 = d["c6"], d["c12"]
-    return {"z_type": d["z"], "excl": d["excl"], "bonds": d["bonds"],
+    return {"z_type": d["z"], "sigma_type": d["sigma"], "excl": d["excl"], "bonds": d["bonds"],
             "bond_par": d["bond_par"], "angles": d["angles"], "angle_par": d["angle_par"]}
 
 
@@ -498,7 +498,8 @@ def main():
         off = None
         if ffb is not None:
             import oracle
-            off = oracle.ForceField(sys32.n_atoms, inv_z=1.0 / ffb["z_type"], excl=ffb["excl"],
+            off = oracle.ForceField(sys32.n_atoms, inv_z=1.0 / ffb["z_type"],
+                                    sigma=ffb["sigma_type"], excl=ffb["excl"],
                                     bonds=ffb["bonds"], bond_par=ffb["bond_par"],
                                     angles=ffb["angles"], angle_par=ffb["angle_par"])
         out["cpu_baseline"] = cpu_baseline(sys32, langevin=lg, hybrid=hy, ff=off)

@@ -324,9 +324,14 @@ md_status md_bind_hybrid(md_ctx* ctx, const double* ne);
 /* Force-field terms of section II.B (readings: the paper names the terms; the forms
  * of Eq. 9 and Eq. 10 are garbled).  Binds, replacing what was bound before (HOST
  * arrays, global atom indices of the batch):
- *   z_type [n_types]   atomic number per type, or NULL: the LJ radius of a pair is
- *                      scaled by s = (c_i + c_j)/2 with c = 1 - q/Z (Eq. 11), i.e.
- *                      c6 -> c6 s^6 and c12 -> c12 s^12 at the current charges;
+ *   z_type [n_types], sigma_type [n_types]  atomic number and neutral Lennard-Jones
+ *                      radius (nm, >= 0) per type, both or neither (NULL): the
+ *                      radius of an atom shrinks to c sigma with c = 1 - q/Z
+ *                      (Eq. 11) and a pair's radius is the mean of the two scaled
+ *                      radii (the Lorentz rule of the c6/c12 tables), so at the
+ *                      current charges c6 -> c6 s^6 and c12 -> c12 s^12 with
+ *                      s = (c_i sigma_i + c_j sigma_j)/(sigma_i + sigma_j) (no
+ *                      scaling for a pair of two zero radii);
  *   excl [n_excl][2]   pairs whose LJ term is omitted (the bonded 1-2 and 1-3
  *                      partners); their screened Coulomb term stays; needs
  *                      n_types <= 7 (excluded pairs carry type n_types in the
@@ -340,12 +345,13 @@ md_status md_bind_hybrid(md_ctx* ctx, const double* ne);
  * atom over its terms: no atomics) and their energies to epot.  Every count may be
  * 0 (that part is off).  Errors: MD_ERR_STATE before md_bind_tables; MD_ERR_ARG for
  * an atom index out of range, a term whose atoms are in different systems or repeat,
- * a parameter that is not finite, Z < 1, or exclusions with n_types > 7.  Graphs
+ * a parameter that is not finite, Z < 1, a negative radius, only one of z_type and
+ * sigma_type, or exclusions with n_types > 7.  Graphs
  * captured before the call hold the previous arrays: capture again.  Synchronous. */
-md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const int32_t* excl,
-                             int64_t n_excl, const int32_t* bonds, const double* bond_par,
-                             int64_t n_bonds, const int32_t* angles, const double* angle_par,
-                             int64_t n_angles);
+md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const double* sigma_type,
+                             const int32_t* excl, int64_t n_excl, const int32_t* bonds,
+                             const double* bond_par, int64_t n_bonds, const int32_t* angles,
+                             const double* angle_par, int64_t n_angles);
 
 /* Pair-distance histogram for the radial distribution functions g_ab(r) behind the
  * partial structure factors of section II.C (Eq. 18).  Adds to hist (DEVICE uint64

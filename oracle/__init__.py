@@ -51,10 +51,10 @@ def lib():
             L.orc_debye_length_nm.restype = f64
             L.orc_rates_from_fractions.argtypes = [i64, i32, P, P]
             L.orc_forces.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i32, P, P, P, i32,
-                                     P, P, P, P, P, P, P, i32, P, P, P]
+                                     P, P, P, P, P, P, P, i32, P, P, P, P]
             L.orc_forces.restype = i64
             L.orc_forces_rows.argtypes = [i64, P, P, P, i32, P, f64, P, P, P, P, P, i32, P, P,
-                                          P, i32, P, P, P, P, P, P, i32, P, i32, P, P, P]
+                                          P, i32, P, P, P, P, P, P, i32, P, i32, P, P, P, P]
             L.orc_forces_rows.restype = i64
             L.orc_pairs.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i64]
             L.orc_pairs.restype = i64
@@ -142,16 +142,21 @@ def hybrid_table(lambda_d, ne, n_q) -> np.ndarray:
 # ------------------------------------------------------------------ force-field terms
 
 class ForceField:
-    """Optional terms of section II.B (readings): ``inv_z`` [T] = 1/Z per type scales
-    the LJ radius of a pair by (c_i + c_j)/2, c = 1 - q/Z (Eq. 11); ``excl`` lists
-    the pairs (global atom indices) whose LJ term is omitted; ``bonds`` [n, 2] with
-    ``bond_par`` [n, 3] = (D_e, beta, b_e) and ``angles`` [n, 3] (middle atom second)
-    with ``angle_par`` [n, 2] = (k, theta0) are the Morse and harmonic-angle terms
-    (Eq. 9, Eq. 10)."""
+    """Optional terms of section II.B (readings): ``inv_z`` [T] = 1/Z per type with
+    ``sigma`` [T] the neutral LJ radius per type: the radius of an atom shrinks to
+    c sigma with c = 1 - q/Z (Eq. 11) and a pair's radius is the mean of the two
+    scaled radii, so the pair's LJ radius is scaled by (c_i sigma_i + c_j sigma_j) /
+    (sigma_i + sigma_j); ``excl`` lists the pairs (global atom indices) whose LJ
+    term is omitted; ``bonds`` [n, 2] with ``bond_par`` [n, 3] = (D_e, beta, b_e) and
+    ``angles`` [n, 3] (middle atom second) with ``angle_par`` [n, 2] = (k, theta0)
+    are the Morse and harmonic-angle terms (Eq. 9, Eq. 10)."""
 
     def __init__(self, n_atoms, inv_z=None, excl=None, bonds=None, bond_par=None,
-                 angles=None, angle_par=None):
+                 angles=None, angle_par=None, sigma=None):
+        if (inv_z is None) != (sigma is None):
+            raise ValueError("inv_z and sigma go together (Eq. 11 scales the radii)")
         self.inv_z = None if inv_z is None else _c(inv_z, np.float64)
+        self.sigma = None if sigma is None else _c(sigma, np.float64)
         self.excl_off = self.excl = None
         if excl is not None:
             e = np.asarray(excl, dtype=np.int64).reshape(-1, 2)
@@ -167,11 +172,11 @@ class ForceField:
         self.angle_par = _c(np.zeros((0, 2)) if angle_par is None else angle_par, np.float64)
 
     def args(self):
-        return _p(self.inv_z), _p(self.excl_off), _p(self.excl)
+        return _p(self.inv_z), _p(self.sigma), _p(self.excl_off), _p(self.excl)
 
 
 def _ff_args(ff):
-    return (None, None, None) if ff is None else ff.args()
+    return (None, None, None, None) if ff is None else ff.args()
 
 
 def bonded(sys, ff, q=None, x=None, y=None, z=None):

@@ -273,12 +273,18 @@ static inline void pair_phi_f(double r2, double qiqj_ke, double c6, double c12,
 }
 
 /* Optional force-field terms of the pair loop (NULL members: off).
- *   inv_z[t]   1/Z of type t: the LJ radius of a pair is scaled by s = (c_i + c_j)/2
- *              with c = 1 - q / Z (Eq. 11), i.e. c6 -> c6 s^6, c12 -> c12 s^12;
+ *   inv_z[t], sigma[t]  1/Z and the neutral Lennard-Jones radius of type t: the
+ *              radius of atom i shrinks with its charge to c_i sigma_i, c_i =
+ *              1 - q_i / Z_i (Eq. 11), and a pair's radius is the arithmetic mean of
+ *              the two scaled radii (the tables' Lorentz rule), so the pair's LJ
+ *              radius is scaled by s = (c_i sigma_i + c_j sigma_j) / (sigma_i +
+ *              sigma_j): c6 -> c6 s^6, c12 -> c12 s^12 (no scaling when both radii
+ *              are zero: such a pair has no LJ term);
  *   excl_off, excl  per-atom sorted lists (CSR over global atom indices) of the
  *              partners whose LJ term is omitted (bonded 1-2 and 1-3 pairs). */
 typedef struct {
     const double* inv_z;
+    const double* sigma;
     const int64_t* excl_off;
     const int64_t* excl;
 } orc_ff;
@@ -303,10 +309,13 @@ static void pair_lj(const orc_ff* ff, int64_t i, int64_t j, const int8_t* q, con
         *a12 = 0.0;
         return;
     }
-    if (ff && ff->inv_z) {
+    if (ff && ff->inv_z && ff->sigma) {
+        double si = ff->sigma[type[i]], sj = ff->sigma[type[j]];
         double ci = 1.0 - (double)q[i] * ff->inv_z[type[i]];
         double cj = 1.0 - (double)q[j] * ff->inv_z[type[j]];
-        double s = 0.5 * (ci + cj);
+        double sum = si + sj;
+        if (!(sum > 0.0)) return;
+        double s = (ci * si + cj * sj) / sum;
         double s6 = s * s * s * s * s * s;
         *a6 = *a6 * s6;
         *a12 = *a12 * s6 * s6;
@@ -324,10 +333,11 @@ int64_t orc_forces(int64_t n_sys, const int64_t* sys_off, int32_t periodic,
                    const double* c6, const double* c12, const double* kappa,
                    int32_t screen_lj, double* fx, double* fy, double* fz,
                    double* e_atom, double* a_atom, double* epot, const double* hyb,
-                   int32_t n_q, const double* inv_z, const int64_t* excl_off,
+                   int32_t n_q, const double* inv_z, const double* sigma,
+                   const int64_t* excl_off,
                    const int64_t* excl)
 {
-    orc_ff ffv = {inv_z, excl_off, excl};
+    orc_ff ffv = {inv_z, sigma, excl_off, excl};
     const orc_ff* ff = &ffv;
     int64_t npairs = 0;
     int64_t n = sys_off[n_sys];
@@ -384,9 +394,10 @@ int64_t orc_forces_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_
                         const double* c12, const double* kappa, int32_t screen_lj,
                         double* fx, double* fy, double* fz, double* e_atom, double* a_atom,
                         int64_t* row_hits, int32_t n_threads, const double* hyb, int32_t n_q,
-                        const double* inv_z, const int64_t* excl_off, const int64_t* excl)
+                        const double* inv_z, const double* sigma, const int64_t* excl_off,
+                        const int64_t* excl)
 {
-    orc_ff ffv = {inv_z, excl_off, excl};
+    orc_ff ffv = {inv_z, sigma, excl_off, excl};
     const orc_ff* ff = &ffv;
     int64_t hits = 0;
 #ifdef _OPENMP

@@ -60,7 +60,7 @@ void free_all(Ctx* c)
                     c->d_partial, c->d_ek_slots, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
                     c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
                     c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32, c->d_rdf_moved,
-                    c->d_rdf_xr, c->d_rdf_er, c->d_invz32, c->d_invz64, c->d_excl_off,
+                    c->d_rdf_xr, c->d_rdf_er, c->d_qlj32, c->d_qlj64, c->d_excl_off,
                     c->d_excl, c->d_bonds, c->d_bond_par, c->d_angles, c->d_angle_par,
                     c->d_bt_off, c->d_bt, c->d_bond_e, c->d_bond_blk};
     for (void* p : ptrs)
@@ -626,8 +626,9 @@ static md_status upload_lj(Ctx* c, int stride)
     return MD_OK;
 }
 
-md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const int32_t* excl,
-                             int64_t n_excl, const int32_t* bonds, const double* bond_par,
+md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const double* sigma_type,
+                             const int32_t* excl, int64_t n_excl, const int32_t* bonds,
+                             const double* bond_par,
                              int64_t n_bonds, const int32_t* angles, const double* angle_par,
                              int64_t n_angles)
 {
@@ -677,9 +678,14 @@ md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const int32_t* e
             if (!isfinite(angle_par[2 * t + k]))
                 return fail(c, MD_ERR_ARG, "angle %lld: parameter not finite", (long long)t);
     }
+    if ((z_type == nullptr) != (sigma_type == nullptr))
+        return fail(c, MD_ERR_ARG, "z_type and sigma_type go together");
     if (z_type)
-        for (int t = 0; t < T; ++t)
+        for (int t = 0; t < T; ++t) {
             if (z_type[t] < 1) return fail(c, MD_ERR_ARG, "Z of type %d must be >= 1", t);
+            if (!(sigma_type[t] >= 0.0) || !isfinite(sigma_type[t]))
+                return fail(c, MD_ERR_ARG, "sigma of type %d must be finite and >= 0", t);
+        }
     HIP_TRY(c, hipDeviceSynchronize());          // no launch may still read the old data
     auto csr = [&](std::vector<std::pair<int32_t, int32_t>>& e, int32_t** off, int32_t** lst)
         -> md_status {
@@ -719,21 +725,28 @@ md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const int32_t* e
         const int32_t one = 1;
         HIP_TRY(c, hipMemcpy(&c->dsc->need_rebuild, &one, sizeof one, hipMemcpyHostToDevice));
     }
-    // charge scaling of the LJ radius
+    // charge scaling of the LJ radii (Eq. 11)
     c->ff_qlj = z_type != nullptr;
     if (c->ff_qlj) {
-        float iz32[MD_MAX_TYPES] = {};
-        double iz64[MD_MAX_TYPES] = {};
+        float t32[kQljLen32] = {};
+        double t64[kQljLen64] = {};
         for (int t = 0; t < T; ++t) {
-            iz64[t] = 1.0 / (double)z_type[t];
-            iz32[t] = (float)iz64[t];
+            t64[t] = 1.0 / (double)z_type[t];
+            t64[MD_MAX_TYPES + t] = sigma_type[t];
+            t32[kQljSig + t] = (float)sigma_type[t];
+            t32[kQljSigZ + t] = (float)(sigma_type[t] / (double)z_type[t]);
         }
-        if (!c->d_invz32) {
-            HIP_TRY(c, dalloc(&c->d_invz32, MD_MAX_TYPES));
-            HIP_TRY(c, dalloc(&c->d_invz64, MD_MAX_TYPES));
+        for (int a = 0; a < T; ++a)
+            for (int b = 0; b < T; ++b) {
+                const double sum = sigma_type[a] + sigma_type[b];
+                t32[kQljRs + a * MD_MAX_TYPES + b] = sum > 0.0 ? (float)(1.0 / sum) : 0.0f;
+            }
+        if (!c->d_qlj32) {
+            HIP_TRY(c, dalloc(&c->d_qlj32, kQljLen32));
+            HIP_TRY(c, dalloc(&c->d_qlj64, kQljLen64));
         }
-        HIP_TRY(c, hipMemcpy(c->d_invz32, iz32, sizeof iz32, hipMemcpyHostToDevice));
-        HIP_TRY(c, hipMemcpy(c->d_invz64, iz64, sizeof iz64, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_qlj32, t32, sizeof t32, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_qlj64, t64, sizeof t64, hipMemcpyHostToDevice));
     }
     // bonded terms and, per atom, the terms it takes part in
     for (void* p : {(void*)c->d_bonds, (void*)c->d_bond_par, (void*)c->d_angles,

@@ -22,9 +22,11 @@
 // hybrid ion-sphere / Debye potential of a charge-Q ion (section II.A, Eq. 4-7),
 // whose coefficients {r', c1, c2, c3} per (system, step, charge) are tabulated on the
 // host; the Lennard-Jones term is unchanged.
-// QLJ: the LJ radius of a pair is scaled by s = (c_i + c_j)/2 with c = 1 - q/Z per
-// atom (section II.B, Eq. 11): c6 -> c6 s^6, c12 -> c12 s^12.  LJ-excluded pairs
-// (bonded 1-2 and 1-3 partners) carry the all-zero pseudo-type in their list codes.
+// QLJ: the LJ radius of each atom shrinks to c sigma with c = 1 - q/Z (section II.B,
+// Eq. 11) and a pair's radius is the mean of the two scaled radii, so the pair's
+// c6 -> c6 s^6, c12 -> c12 s^12 with s = (c_i sigma_i + c_j sigma_j)/(sigma_i +
+// sigma_j).  LJ-excluded pairs (bonded 1-2 and 1-3 partners) carry the all-zero
+// pseudo-type in their list codes.
 #include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
@@ -100,8 +102,8 @@ struct ForceArgs {
     const double* hyb64;
     int hyb_q;
     // force-field terms
-    const float* invz32;         // 1/Z per type (QLJ)
-    const double* invz64;
+    const float* qlj32;          // charge-scaled LJ radii (QLJ): kQljLen32 floats
+    const double* qlj64;         // kQljLen64 doubles
     const int32_t* excl_off;     // LJ exclusions per caller atom (NULL: none)
     const int32_t* excl;
     int t_excl;                  // pseudo-type of excluded pairs
@@ -353,9 +355,9 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
     if (LISTS && !rebuild) return;
     for (int i = tid; i < A.T * A.T; i += blockDim.x)
         s_lj[i] = make_float2(A.lj32[2 * i], A.lj32[2 * i + 1]);
-    __shared__ float s_invz[QLJ ? MD_MAX_TYPES : 1];
+    __shared__ float s_qlj[QLJ ? kQljLen32 : 1];
     if (QLJ)
-        for (int i = tid; i < MD_MAX_TYPES; i += blockDim.x) s_invz[i] = A.invz32[i];
+        for (int i = tid; i < kQljLen32; i += blockDim.x) s_qlj[i] = A.qlj32[i];
     const int sentinel = A.E_cap * kCluster;
     uint16_t* s_mask = reinterpret_cast<uint16_t*>(s_j + sentinel + 1);
     // hybrid screening: {r', c1, c2, c3} per charge state, after the masks (dynamic LDS
@@ -475,7 +477,8 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ea = 0.0;
         float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f, qif = 0.0f;
         float4 hi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float ci = 1.0f;                       // QLJ: 1 - q_i / Z_i
+        float ci = 0.0f;                       // QLJ: the scaled radius c_i sigma_i
+        const float* rs_row = s_qlj + kQljRs;  // QLJ: 1/(sigma_i + sigma_j) of this atom
         int tb = 0;
         // a fast atom (NaN position) takes no part, like padding: its pairs and its
         // force come from the fast-atom kernels
@@ -489,7 +492,10 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             xi = r[0]; yi = r[1]; zi = r[2];
             qike = (float)(kKe * (double)q_i);
             tb = t_i * A.T;
-            if (QLJ) ci = fmaf(-(float)q_i, s_invz[t_i], 1.0f);
+            if (QLJ) {
+                ci = fmaf(-(float)q_i, s_qlj[kQljSigZ + t_i], s_qlj[kQljSig + t_i]);
+                rs_row = s_qlj + kQljRs + t_i * MD_MAX_TYPES;
+            }
             if (HYBRID) {
                 qif = (float)q_i;
                 hi = s_hyb[min(max(q_i, 0), A.hyb_q - 1)];
@@ -556,8 +562,9 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 if (QLJ) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const float cj = fmaf(-pj[u].w, s_invz[tj[u]], 1.0f);
-                        const float sc = 0.5f * (ci + cj);
+                        const float cj = fmaf(-pj[u].w, s_qlj[kQljSigZ + tj[u]],
+                                              s_qlj[kQljSig + tj[u]]);
+                        const float sc = (ci + cj) * rs_row[tj[u]];
                         const float s2 = sc * sc, s6 = s2 * s2 * s2;
                         lj[u].x *= s6;
                         lj[u].y *= s6 * s6;
@@ -765,15 +772,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
                                A.emit_max);
                 const int tj = (int)(code >> kCodeIdxBits);
                 double c6 = A.c6[ti * A.T + tj], c12 = A.c12[ti * A.T + tj];
-                if (QLJ) {
-#pragma clang fp contract(off)
-                    const double ci = 1.0 - (double)qi_n * A.invz64[ti];
-                    const double cj = 1.0 - (double)A.qs[slot_j] * A.invz64[tj];
-                    const double sc = 0.5 * (ci + cj);
-                    const double s6 = sc * sc * sc * sc * sc * sc;
-                    c6 = c6 * s6;
-                    c12 = c12 * s6 * s6;
-                }
+                if (QLJ) qlj_scale64(A.qlj64, ti, tj, qi_n, A.qs[slot_j], &c6, &c12);
                 double f, e;
                 if (HYBRID) {
                     pair_terms_hybrid64(r2, kap, qi_n, A.qs[slot_j], c6, c12, SCREEN_LJ, hrow,
@@ -925,7 +924,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     A.wpc = kMaxWpc;
     A.cl_len = c->d_cl_len; A.ent_mask = c->d_ent_mask; A.nb_cap_h = c->nb_cap_h;
     A.hyb32 = c->d_hyb32; A.hyb64 = c->d_hyb64; A.hyb_q = c->hyb_q;
-    A.invz32 = c->d_invz32; A.invz64 = c->d_invz64;
+    A.qlj32 = c->d_qlj32; A.qlj64 = c->d_qlj64;
     A.excl_off = c->ff_excl ? c->d_excl_off : nullptr; A.excl = c->d_excl; A.t_excl = c->T;
     A.inv_perm = c->d_inv_perm;
     {

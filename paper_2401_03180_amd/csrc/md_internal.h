@@ -96,9 +96,9 @@ struct Ctx {
     // force-field terms (bound by md_bind_forcefield)
     int32_t T_lj = 0;              // stride of the LJ tables: T, or T + 1 with exclusions
                                    // (type T is the "LJ excluded" pseudo-type, all zero)
-    bool ff_qlj = false;           // LJ radius scaled with the charge
-    float* d_invz32 = nullptr;     // MD_MAX_TYPES: 1/Z per type (0 for the pseudo-type)
-    double* d_invz64 = nullptr;
+    bool ff_qlj = false;           // LJ radii scaled with the charge
+    float* d_qlj32 = nullptr;      // kQljLen32: sigma | sigma/Z per type | 1/(sigma_i + sigma_j)
+    double* d_qlj64 = nullptr;     // kQljLen64: 1/Z | sigma per type (0 for the pseudo-type)
     bool ff_excl = false;
     int32_t* d_excl_off = nullptr; // N+1: per-atom LJ-excluded partners (CSR, sorted)
     int32_t* d_excl = nullptr;
@@ -192,6 +192,15 @@ struct Ctx {
     double* d_fast_e = nullptr;       // fast_cap: energy of each fast atom's pairs
     uint8_t* d_atype = nullptr;       // N: types in caller order (build time)
 };
+
+// Tables of the charge-scaled LJ radii (section II.B, Eq. 11): the radius of atom i
+// shrinks to c_i sigma_i with c_i = 1 - q_i/Z_i, a pair's radius is the mean of the
+// two, so its LJ radius scales by s = (c_i sigma_i + c_j sigma_j)/(sigma_i + sigma_j).
+// FP32: [sigma_t | sigma_t/Z_t | 1/(sigma_i + sigma_j) (0 when both are 0), row
+// stride MD_MAX_TYPES]; FP64: [1/Z_t | sigma_t].
+constexpr int kQljSig = 0, kQljSigZ = MD_MAX_TYPES, kQljRs = 2 * MD_MAX_TYPES;
+constexpr int kQljLen32 = 2 * MD_MAX_TYPES + MD_MAX_TYPES * MD_MAX_TYPES;
+constexpr int kQljLen64 = 2 * MD_MAX_TYPES;
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -101,7 +101,7 @@ def lib():
             "md_bind_langevin": [P, P, P, f64],
             "md_bind_hybrid": [P, P],
             "md_rdf_histogram": [P, P, P, P, P, f64, i32, P, P],
-            "md_bind_forcefield": [P, P, P, i64, P, P, i64, P, P, i64],
+            "md_bind_forcefield": [P, P, P, P, i64, P, P, i64, P, P, i64],
             "md_rdf_normalize": [i32, f64, P, i64, i64, i32, f64, P],
             "md_structure_factor": [i32, f64, P, f64, i32, P, P],
             "md_integrate_langevin": [P, f64, P, P, P, P, P, P, P, P, P, P, P, P, P],
@@ -214,22 +214,24 @@ def md_bind_hybrid(ctx, ne):
 
 
 def md_bind_forcefield(ctx, z_type=None, excl=None, bonds=None, bond_par=None, angles=None,
-                       angle_par=None):
-    """Host arrays (see include/md.h); None disables a part."""
+                       angle_par=None, sigma_type=None):
+    """Host arrays (see include/md.h); None disables a part (z_type and sigma_type go
+    together)."""
     def arr(a, dt, cols):
         if a is None:
             return None, 0
         v = np.ascontiguousarray(np.asarray(a, dtype=dt).reshape(-1, cols))
         return v, v.shape[0]
     z = None if z_type is None else np.ascontiguousarray(z_type, dtype=np.int8)
+    sg = None if sigma_type is None else np.ascontiguousarray(sigma_type, dtype=np.float64)
     ex, nex = arr(excl, np.int32, 2)
     bo, nbo = arr(bonds, np.int32, 2)
     bp, _ = arr(bond_par, np.float64, 3)
     an, nan_ = arr(angles, np.int32, 3)
     ap, _ = arr(angle_par, np.float64, 2)
     ptr = lambda v: None if v is None else v.ctypes.data
-    _check(ctx, lib().md_bind_forcefield(ctx, ptr(z), ptr(ex), nex, ptr(bo), ptr(bp), nbo,
-                                         ptr(an), ptr(ap), nan_))
+    _check(ctx, lib().md_bind_forcefield(ctx, ptr(z), ptr(sg), ptr(ex), nex, ptr(bo), ptr(bp),
+                                         nbo, ptr(an), ptr(ap), nan_))
 
 
 def md_rdf_histogram(ctx, x, y, z, elem, r_max, n_bins, hist, stream=None):
@@ -435,8 +437,8 @@ class Engine:
         md_bind_hybrid(self.ctx, ne)
 
     def bind_forcefield(self, **kw):
-        """md_bind_forcefield with keyword arrays (z_type, excl, bonds, bond_par,
-        angles, angle_par); graphs captured before are dropped."""
+        """md_bind_forcefield with keyword arrays (z_type, sigma_type, excl, bonds,
+        bond_par, angles, angle_par); graphs captured before are dropped."""
         for g in self.graphs.values():
             md_graph_destroy(g)
         self.graphs = {}

@@ -462,8 +462,9 @@ def molecular_force_field(sys: System, kind: str):
     methane workload (atoms of one molecule are consecutive: O H H or C H H H H):
     Morse bonds to the heavy atom, harmonic H-X-H angles, LJ exclusions for the 1-2
     and 1-3 pairs they define, Lennard-Jones tables for every element pair
-    (Lorentz-Berthelot), and Z per type for the charge scaling of the LJ radius.
-    Returns a dict of numpy arrays (global atom indices)."""
+    (Lorentz-Berthelot), and Z and the neutral LJ radius sigma per type for the
+    charge scaling of the LJ radii.  Returns a dict of numpy arrays (global atom
+    indices)."""
     if kind == "water":
         per, nh, Z = 3, 2, (8, 1)
         sig, eps = (0.3166, 0.10), (0.65, 0.02)
@@ -490,7 +491,7 @@ def molecular_force_field(sys: System, kind: str):
             "angles": angles.astype(np.int32),
             "angle_par": np.tile(np.array(ang), (angles.shape[0], 1)),
             "excl": excl.astype(np.int64), "c6": c6, "c12": c12,
-            "z": np.array(Z, dtype=np.int8)}
+            "z": np.array(Z, dtype=np.int8), "sigma": np.array(sig, dtype=np.float64)}
 
 
 EV_KJ_PER_MOL = 96.48533212      # 1 eV per particle in kJ/mol

@@ -118,31 +118,65 @@ def test_exclusion_removes_only_lj():
         assert oracle.forces(a)["fx"][0] != fa["fx"][0]            # the LJ term matters
 
 
+def _lj_part(r, q, z, sig, eps):
+    """x-force on atom 1 of a two-atom pair at separation r (no screening) from the
+    Lennard-Jones term alone: the full pair with the Eq. 11 charge scaling of the
+    radii minus the Coulomb-only pair; and the same for the energy."""
+    c6, c12 = synth.lj_tables_lorentz_berthelot(sig, eps)
+    full = two_atoms([r, 0, 0], q[0], q[1], lam=math.inf)
+    full.type = np.array([0, 1], np.uint8)
+    full.c6, full.c12 = c6, c12
+    coul = two_atoms([r, 0, 0], q[0], q[1], lam=math.inf)
+    ff = oracle.ForceField(2, inv_z=1.0 / np.asarray(z, np.float64), sigma=np.asarray(sig))
+    a, b = oracle.forces(full, ff=ff), oracle.forces(coul)
+    return a["fx"][1] - b["fx"][1], a["epot"][0] - b["epot"][0]
+
+
 @pytest.mark.parametrize("q1,q2,z1,z2", [(0, 0, 6, 6), (2, 0, 6, 6), (3, 4, 8, 6), (1, 1, 1, 6)])
 def test_charge_scaled_lj_minimum(q1, q2, z1, z2):
-    """With no screening, the LJ part of the force (total minus the Coulomb-only force)
-    vanishes at 2^(1/6) sigma s with s = (1 - q1/Z1 + 1 - q2/Z2)/2 (Eq. 11)."""
+    """Equal neutral radii: with no screening the LJ part of the force vanishes at
+    2^(1/6) sigma s with s = (1 - q1/Z1 + 1 - q2/Z2)/2 (Eq. 11: each radius shrinks
+    by its own c, the pair radius is their mean)."""
     sigma, eps = 0.3, 0.5
-    c6, c12 = 4 * eps * sigma ** 6, 4 * eps * sigma ** 12
     s_fac = 0.5 * ((1 - q1 / z1) + (1 - q2 / z2))
     if s_fac == 0.0:
         pytest.skip("no LJ left")
     rstar = 2 ** (1 / 6) * sigma * s_fac
-    inv_z = np.array([1.0 / z1, 1.0 / z2])
-
-    def lj_force(r):
-        full = two_atoms([r, 0, 0], q1, q2, c6=c6, c12=c12, lam=math.inf)
-        full.type = np.array([0, 1], np.uint8)
-        full.c6 = np.full((2, 2), c6)
-        full.c12 = np.full((2, 2), c12)
-        coul = two_atoms([r, 0, 0], q1, q2, lam=math.inf)
-        ff = oracle.ForceField(2, inv_z=inv_z)
-        return oracle.forces(full, ff=ff)["fx"][1] - oracle.forces(coul)["fx"][1]
-
+    args = ((q1, q2), (z1, z2), (sigma, sigma), (eps, eps))
     scale = 24 * eps / rstar
-    assert abs(lj_force(rstar)) < 1e-9 * scale
-    assert lj_force(rstar * 0.97) > 0.0                             # repulsive inside
-    assert lj_force(rstar * 1.03) < 0.0                             # attractive outside
+    assert abs(_lj_part(rstar, *args)[0]) < 1e-9 * scale
+    assert _lj_part(rstar * 0.97, *args)[0] > 0.0                  # repulsive inside
+    assert _lj_part(rstar * 1.03, *args)[0] < 0.0                  # attractive outside
+
+
+@pytest.mark.parametrize("q1,q2", [(0, 0), (0, 1), (3, 0), (5, 1), (2, 1)])
+def test_charge_scaled_lj_unequal_radii(q1, q2):
+    """Unequal neutral radii (water O 0.3166 nm, Z 8 against H 0.10 nm, Z 1): Eq. 11
+    shrinks each radius to c sigma with c = 1 - q/Z, and the pair radius is the mean
+    of the scaled radii, so the LJ force vanishes at r* = 2^(1/6) (c1 s1 + c2 s2)/2
+    and the LJ energy there is -sqrt(e1 e2) (epsilon is not scaled).  For O-H+ this
+    is the case where scaling the pair radius by the mean of c would differ."""
+    sig, eps, z = (0.3166, 0.10), (0.65, 0.02), (8, 1)
+    c = (1 - q1 / z[0], 1 - q2 / z[1])
+    rad = 0.5 * (c[0] * sig[0] + c[1] * sig[1])
+    rstar = 2 ** (1 / 6) * rad
+    args = ((q1, q2), z, sig, eps)
+    e12 = math.sqrt(eps[0] * eps[1])
+    f, e = _lj_part(rstar, *args)
+    assert abs(f) < 1e-9 * 24 * e12 / rstar
+    assert e == pytest.approx(-e12, rel=1e-9)
+    assert _lj_part(rstar * 0.97, *args)[0] > 0.0
+    assert _lj_part(rstar * 1.03, *args)[0] < 0.0
+    # the other reading (pair radius times the mean of c) puts the minimum elsewhere
+    # whenever the charges differ in their c
+    other = 2 ** (1 / 6) * 0.5 * (sig[0] + sig[1]) * 0.5 * (c[0] + c[1])
+    if abs(c[0] - c[1]) > 1e-12:
+        assert abs(_lj_part(other, *args)[0]) > 1e-3 * 24 * e12 / rstar
+
+
+def test_charge_scaled_lj_needs_radii():
+    with pytest.raises(ValueError):
+        oracle.ForceField(2, inv_z=[1.0, 1.0])
 
 
 def test_force_field_newton_and_rows():
@@ -151,7 +185,8 @@ def test_force_field_newton_and_rows():
     s.q = np.minimum(rng.integers(0, 4, s.n_atoms), s.qmax[s.elem]).astype(np.int8)
     d = synth.molecular_force_field(s, "methane")
     s.c6, s.c12 = d["c6"], d["c12"]
-    ff = oracle.ForceField(s.n_atoms, inv_z=1.0 / d["z"], excl=d["excl"], bonds=d["bonds"],
+    ff = oracle.ForceField(s.n_atoms, inv_z=1.0 / d["z"], sigma=d["sigma"], excl=d["excl"],
+                           bonds=d["bonds"],
                            bond_par=d["bond_par"], angles=d["angles"], angle_par=d["angle_par"])
     nb = oracle.forces(s, ff=ff)
     bo = oracle.bonded(s, ff)

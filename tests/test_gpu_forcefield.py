@@ -29,7 +29,7 @@ def with_ff(s, kind, parts=("z", "excl", "bonds", "angles")):
     s.c6, s.c12 = d["c6"], d["c12"]
     kw = {}
     if "z" in parts:
-        kw["z_type"] = d["z"]
+        kw["z_type"], kw["sigma_type"] = d["z"], d["sigma"]
     if "excl" in parts:
         kw["excl"] = d["excl"]
     if "bonds" in parts:
@@ -37,6 +37,7 @@ def with_ff(s, kind, parts=("z", "excl", "bonds", "angles")):
     if "angles" in parts:
         kw["angles"], kw["angle_par"] = d["angles"], d["angle_par"]
     ff = oracle.ForceField(s.n_atoms, inv_z=1.0 / d["z"] if "z" in parts else None,
+                           sigma=d["sigma"] if "z" in parts else None,
                            excl=kw.get("excl"), bonds=kw.get("bonds"),
                            bond_par=kw.get("bond_par"), angles=kw.get("angles"),
                            angle_par=kw.get("angle_par"))
@@ -233,7 +234,9 @@ def test_forcefield_argument_errors():
            dict(bonds=[[0, n0]], bond_par=[[1.0, 1.0, 0.1]]),               # two systems
            dict(angles=[[1, 0, 1]], angle_par=[[1.0, 1.9]]),                # repeated atom
            dict(bonds=[[0, 1]], bond_par=[[np.nan, 1.0, 0.1]]),
-           dict(z_type=[6, 0])]
+           dict(z_type=[6, 0], sigma_type=[0.34, 0.25]),                   # Z < 1
+           dict(z_type=[6, 1]),                                             # no radii
+           dict(z_type=[6, 1], sigma_type=[0.34, -0.1])]                    # negative radius
     for kw in bad:
         with pytest.raises(md.MDError) as e:
             eng.bind_forcefield(**kw)
