@@ -4,9 +4,19 @@ One step = device-side rebuild check / neighbour rebuild when due, stochastic
 ionization, screened FP32 pair forces with compensated sums and the FP64 energy,
 and the FP64 velocity-Verlet half steps with the kinetic-energy reduction.  Every
 step is one replay of a captured HIP graph; inputs are resident in HBM before the
-timed region.  Workload: the 98,304-atom bulk-water pulse box (32,768 H2O in a
-9.93 nm periodic cube, lambda_D ramp 1.0 -> 0.15 nm, Gaussian pulse), synthetic
-and seeded.
+timed region.  Default workload: the 4,194,304-atom bulk-water box (1,398,101 H2O
+plus one O in a 34.8 nm periodic cube, lambda_D 0.2 nm, rc 1.0 nm, per-step
+ionization probability 1e-3), synthetic and seeded.  The schedule starts at step 0
+(neutral atoms, one build); the timed steps follow the warm-up steps with no extra
+build, so rebuilds fall where the workload puts them.
+
+Beside the timed FP32 line it reports, on the same GPU: the plain FP64 force path
+(FP32-vs-FP64 speedup); the force and per-atom energy error of both paths against
+the FP64 oracle on the 65,536-atom sub-box of the 4.19 M-atom box; the whole
+schedule (initial build included) in ms per step with its rebuild count; the
+98,304-atom pulse box over its 1,000-step schedule; the 256 batched methane
+clusters against the plain FP64 form with one system per launch; and the oracle
+timed on the host cores.
 
 Prints ONE JSON line (rank 0, N = 1).  Only one GPU is supported.
 """
@@ -36,34 +46,45 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+SCHEDULE = {"water_1536": 200, "water_98304": 1000, "protein_524288": 500,
+            "methane_256": 2000, "water_4194304": 100}
+
+
 def make_system(name, n_steps):
+    """The named workload with its own schedule length, or n_steps if longer."""
     from paper_2401_03180_amd import synth
+    if name not in SCHEDULE:
+        raise SystemExit("unknown config " + name)
+    S = max(int(n_steps), SCHEDULE[name])
     if name == "water_98304":
-        return synth.water_pulse(n_steps=n_steps)
+        return synth.water_pulse(n_steps=S)
     if name == "water_1536":
-        return synth.water_small(n_steps=n_steps)
+        return synth.water_small(n_steps=S)
     if name == "protein_524288":
-        return synth.protein_crystal(n_steps=n_steps)
+        return synth.protein_crystal(n_steps=S)
     if name == "water_4194304":
-        return synth.water_large(n_steps=n_steps)
-    if name == "methane_256":
-        return synth.methane_clusters(n_steps=n_steps)
-    raise SystemExit("unknown config " + name)
+        return synth.water_large(n_steps=S)
+    return synth.methane_clusters(n_steps=S)
 
 
 STATE = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q")
 
 
 def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_graph=True,
-            fast_capacity=0, langevin=None, hybrid=None, ff=None):
-    """Timed region: `steps` replays of the captured step graph (or, with use_graph
-    False, `steps` eager md_step calls), inputs resident.
-    Then the same steps are replayed eagerly from a snapshot of the state at the
-    start of the timed region, with the force-kernel timer on: the trajectory is
-    deterministic, so the eager replay launches exactly the kernels of the timed
+            fast_capacity=0, langevin=None, hybrid=None, ff=None, schedule_steps=0,
+            subbox=None):
+    """The workload's schedule from step 0 (initial build and forces), `warmup`
+    steps, then `steps` timed steps: replays of the captured step graph (or, with
+    use_graph False, eager md_step calls), inputs resident, no build forced in
+    between.  Then the same run is repeated from the initial state with the timed
+    steps launched eagerly and the force-kernel timer on: the trajectory is
+    deterministic, so the repetition launches exactly the kernels of the timed
     region (checked: identical final state and rebuild count) and gives the
     duration of every force-kernel launch.  Pair counts are sampled between steps
-    of the replay (where no list rebuild is pending).  langevin: (gamma, kt) tables
+    of the repetition.  schedule_steps > 0: the whole schedule (initial build,
+    forces and that many graph steps) is timed once more from the initial state.
+    subbox: the oracle rows of the error report (see subbox_errors), evaluated at
+    the final state after a build at its positions.  langevin: (gamma, kt) tables
     of the electron-ion coupling, bound for the whole run, or None; hybrid: the
     free-electron density table of hybrid screening, or None; ff: md_bind_forcefield
     keyword arrays, or None."""
@@ -77,11 +98,19 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
         eng.bind_hybrid(hybrid)
     if ff is not None:
         eng.bind_forcefield(**ff)
+    out = {}
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        eng.set_step(0, stream)
-        eng.build(md.MD_BUILD_FORCE, stream)
-        eng.forces(energy=True, stream=stream)
+        init = {n: getattr(eng, n).clone() for n in STATE}
+
+        def restart():
+            for n in STATE:
+                getattr(eng, n).copy_(init[n])
+            eng.set_step(0, stream)
+            eng.build(md.MD_BUILD_FORCE, stream)
+            eng.forces(energy=True, stream=stream)
+
+        restart()
         if use_graph:
             graph = eng.graph(md.MD_BUILD_AUTO, stream, energy=True, ekin=True)
             one_step = lambda: md.md_graph_launch(graph, stream)
@@ -89,11 +118,7 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
             one_step = lambda: eng.step(md.MD_BUILD_AUTO, energy=True, ekin=True, stream=stream)
         for _ in range(warmup):
             one_step()
-        # the timed trajectory starts from a fresh build of the current positions
-        eng.build(md.MD_BUILD_FORCE, stream)
         stream.synchronize()
-        snap = {n: getattr(eng, n).clone() for n in STATE}
-        k0 = eng.get_step(stream)
         st0 = eng.stats(stream)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -111,11 +136,10 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
         final = {n: getattr(eng, n).clone() for n in STATE}
         step_end = eng.get_step(stream)
 
-        # eager replay of the same steps with the force-kernel timer
-        for n in STATE:
-            getattr(eng, n).copy_(snap[n])
-        eng.set_step(k0, stream)
-        eng.build(md.MD_BUILD_FORCE, stream)
+        # the same run again, the timed steps eager with the force-kernel timer
+        restart()
+        for _ in range(warmup):
+            one_step()
         stream.synchronize()
         st2 = eng.stats(stream)
         eng.timer_start(steps)
@@ -125,23 +149,118 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
             eng.step(md.MD_BUILD_AUTO, energy=True, ekin=True, stream=stream)
             if i in sample_at:
                 stream.synchronize()
-                pairs.append(eng.debug_pairs(prec=prec, stream=stream).shape[0])
+                pairs.append(eng.count_pairs(prec=prec, stream=stream))
         durations = eng.timer_read()
         stream.synchronize()
         st3 = eng.stats(stream)
         same = all(torch.equal(getattr(eng, n), final[n]) for n in STATE)
         eng.timer_start(0)
+
+        if schedule_steps > 0:
+            # the whole schedule, initial build and forces included
+            torch.cuda.synchronize()
+            for n in STATE:
+                getattr(eng, n).copy_(init[n])
+            stream.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            eng.set_step(0, stream)
+            eng.build(md.MD_BUILD_FORCE, stream)
+            eng.forces(energy=True, stream=stream)
+            for _ in range(schedule_steps):
+                one_step()
+            e1.record(stream)
+            stream.synchronize()
+            st4 = eng.stats(stream)
+            out.update(schedule_steps=schedule_steps,
+                       schedule_ms_per_step=e0.elapsed_time(e1) / schedule_steps,
+                       schedule_rebuilds=int(st4["n_builds"]),
+                       schedule_flags=eng.sync_check(stream, raise_on_flags=False))
+        if subbox is not None:
+            out["subbox"] = subbox_errors(eng, subbox, stream)
     eng.close()
     builds = st1["n_builds"] - st0["n_builds"]
     builds_replay = st3["n_builds"] - st2["n_builds"]
     d = np.asarray(durations, dtype=np.float64)
-    return {"ms": ms, "wall_s": wall, "flags": flags, "pairs": float(np.mean(pairs)),
-            "pairs_min": int(min(pairs)), "pairs_max": int(max(pairs)),
-            "kernel_ms": float(d.mean()), "kernel_ms_median": float(np.median(d)),
-            "kernel_ms_p90": float(np.percentile(d, 90)), "kernel_launches": int(d.size),
-            "builds": builds, "builds_replay": builds_replay,
-            "replay_identical": bool(same and builds == builds_replay), "stats": st1,
-            "step": step_end}
+    out.update({"ms": ms, "wall_s": wall, "flags": flags, "pairs": float(np.mean(pairs)),
+                "pairs_min": int(min(pairs)), "pairs_max": int(max(pairs)),
+                "kernel_ms": float(d.mean()), "kernel_ms_median": float(np.median(d)),
+                "kernel_ms_p90": float(np.percentile(d, 90)), "kernel_launches": int(d.size),
+                "builds": builds, "builds_replay": builds_replay,
+                "replay_identical": bool(same and builds == builds_replay), "stats": st1,
+                "step": step_end, "charged_fraction": float((final["q"] > 0).float().mean())})
+    return out
+
+
+def subbox_rows(sys_, n_rows=65536, threads=16):
+    """The error-report sub-box: the n_rows atoms nearest, in the max norm under the
+    minimum image, to the centre of the [0, L/4)^3 corner sub-cube (ties by index),
+    the candidate partners (every atom within that radius plus rc of the centre: a
+    superset of the rows' partners, so restricting the oracle's all-j loop to them
+    leaves its sums unchanged) and the oracle threads."""
+    L = sys_.box[0]
+    c = L / 8.0
+    P = sys_.positions()
+    d = P - c
+    d -= L * np.rint(d / L)
+    dist = np.abs(d).max(axis=1)
+    order = np.lexsort((np.arange(dist.size), dist))
+    rows = np.sort(order[:n_rows])
+    reach = dist[order[n_rows - 1]] + sys_.rc + 1e-6
+    cand = np.flatnonzero(dist <= reach)
+    return {"rows": rows, "cand": cand, "threads": threads}
+
+
+def subbox_errors(eng, sb, stream):
+    """Force and per-atom energy error of the FP32 and FP64 paths against the oracle
+    on the sub-box rows, at the engine's current positions and charges after a build
+    there (identical input snapshot for both paths)."""
+    import oracle
+    from paper_2401_03180_amd import md
+    s = eng.sys
+    eng.build(md.MD_BUILD_FORCE, stream)
+    x, y, z, q = eng.host("x"), eng.host("y"), eng.host("z"), eng.host("q")
+    step = eng.get_step(stream)
+    got = {}
+    for prec in (md.MD_FP32_KAHAN, md.MD_FP64):
+        eng.forces(prec=prec, energy=True, stream=stream)
+        F = (eng.host("fx"), eng.host("fy"), eng.host("fz"))
+        e, _ = eng.atom_energies(prec=prec, stream=stream)
+        got[prec] = (F, e)
+    rows, cand = sb["rows"], sb["cand"]
+    sub = s.copy()
+    for n, v in (("x", x), ("y", y), ("z", z), ("q", q)):
+        setattr(sub, n, v[cand].copy())
+    for n in ("vx", "vy", "vz", "elem", "type", "inv_mass"):
+        setattr(sub, n, getattr(s, n)[cand].copy())
+    sub.atom_id = np.arange(cand.size, dtype=np.uint32)
+    sub.sys_offsets = np.array([0, cand.size], np.int64)
+    local = np.searchsorted(cand, rows)
+    t = time.perf_counter()
+    kap = oracle.kappa_from_lambda(s.lambda_d[:, step])
+    ref = oracle.forces_rows(sub, local, kappa=kap, n_threads=sb["threads"])
+    t_orc = time.perf_counter() - t
+    A = ref["a_atom"]
+    out = {"rows": int(rows.size), "candidates": int(cand.size), "step": int(step),
+           "charged_fraction": float((q[rows] > 0).mean()), "oracle_s": t_orc,
+           "pairs_per_row": float(np.mean(ref["row_hits"]))}
+    for prec, name in ((md.MD_FP32_KAHAN, "fp32"), (md.MD_FP64, "fp64")):
+        F, e = got[prec]
+        dF = np.sqrt(sum((f[rows] - ref[k]) ** 2 for f, k in zip(F, ("fx", "fy", "fz"))))
+        live = A > 0
+        eF = float(np.max(dF[live] / A[live])) if live.any() else 0.0
+        Fm = np.sqrt(ref["fx"] ** 2 + ref["fy"] ** 2 + ref["fz"] ** 2)
+        big = Fm >= 0.1 * np.sqrt(np.mean(Fm ** 2))
+        de = e[rows] - ref["e_atom"]
+        out[name] = {"e_F": eF,
+                     "rel_force_max_strong": float(np.max(dF[big] / Fm[big])),
+                     "rel_force_p99_strong": float(np.percentile(dF[big] / Fm[big], 99)),
+                     "rel_force_global": float(np.sqrt(np.sum(dF ** 2) / np.sum(Fm ** 2))),
+                     "energy_rel": float(abs(de.sum()) / np.abs(ref["e_atom"]).sum()),
+                     "atom_energy_max_rel": float(np.max(np.abs(de) /
+                                                         (np.abs(ref["e_atom"]) + A + 1e-300)))}
+    return out
 
 
 def run_gpu_per_system(sys_, prec, steps, warmup, langevin=None, hybrid=None, ff_kind=None):
@@ -256,7 +375,13 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None, 
         else:
             oracle.vv_langevin(sys_, s, c1, langevin[1], F, pos, vel)
 
-    threads = threads or min(os.cpu_count() or 1, 16)
+    n_host, n_aff = host_cores()
+    # one GPU's share of the machine's host cores is 16, whatever the host has in all
+    threads = threads or min(n_aff, 16)
+    cores_note = ("%d threads: the %d-core share of one GPU (host: %d logical CPUs, %d in "
+                  "this process's affinity mask)" % (threads, 16, n_host, n_aff)
+                  if threads < n_aff else "%d threads on all %d logical CPUs of the affinity "
+                  "mask (host: %d)" % (threads, n_aff, n_host))
     n = sys_.n_atoms
     rng = np.random.default_rng(0)
     kap = oracle.kappa_from_lambda(sys_.lambda_d[:, 1])
@@ -287,7 +412,7 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None, 
             oracle.vv(1, sys_.dt, sys_.inv_mass, F, pos, vel)
         t_all = time.perf_counter() - t
         return {"value": n * steps / t_all, "unit": "atom-steps/s", "cores": threads,
-                "kind": "oracle",
+                "cores_note": cores_note, "kind": "oracle",
                 "sample": "O(N^2) FP64 oracle, %d whole steps of all %d atoms (all-pairs force "
                           "rows, ionize, velocity Verlet) in %.1f s" % (steps, n, t_all)}
     rows_n = int(min(n, max(256, target_s / max(per_row, 1e-9))))
@@ -303,7 +428,8 @@ def cpu_baseline(sys_, target_s=12.0, threads=None, langevin=None, hybrid=None, 
     oracle.vv(1, sys_.dt, sys_.inv_mass, F, pos, vel)
     t_elem = time.perf_counter() - t
     t_step = t_rows * n / rows_n + t_elem
-    return {"value": n / t_step, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+    return {"value": n / t_step, "unit": "atom-steps/s", "cores": threads,
+            "cores_note": cores_note, "kind": "oracle",
             "sample": "O(N^2) FP64 oracle: all-pairs force rows of %d of %d atoms (%.1f s) plus "
                       "ionize and velocity Verlet over all atoms, scaled to one whole step "
                       "(%.1f s)" % (rows_n, n, t_rows, t_step)}
@@ -315,10 +441,10 @@ def kernel_source_sha1():
     return hashlib.sha1(src).hexdigest()
 
 
-def traffic_from_profile():
-    """HBM bytes per force launch from the committed rocprofv3 counter summary, if it
-    was taken on the current force-kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "force32_water_98304_counters.txt")
+def traffic_from_profile(config):
+    """HBM bytes per force launch from the committed rocprofv3 counter summary of the
+    workload, if it was taken on the current force-kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "force32_%s_counters.txt" % config)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -331,16 +457,65 @@ def traffic_from_profile():
     return float(kv["hbm_bytes_per_launch"])
 
 
+def run_schedule(sys_, prec, knobs, steps=None):
+    """The workload's whole schedule (initial build and forces, then every step as a
+    graph replay), timed with HIP events: ms per step, rebuilds, flags."""
+    import torch
+    from paper_2401_03180_amd import md
+    steps = sys_.n_steps if steps is None else steps
+    eng = md.Engine(sys_, prec, cluster_group=knobs["cluster_group"], skin=knobs["skin"],
+                    fast_capacity=knobs["fast_capacity"])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        init = {n: getattr(eng, n).clone() for n in STATE}
+        eng.set_step(0, stream)
+        eng.build(md.MD_BUILD_FORCE, stream)       # a capture needs a built context
+        g = eng.graph(md.MD_BUILD_AUTO, stream, energy=True, ekin=True)
+        for n in STATE:
+            getattr(eng, n).copy_(init[n])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        eng.set_step(0, stream)
+        eng.build(md.MD_BUILD_FORCE, stream)
+        eng.forces(energy=True, stream=stream)
+        for _ in range(steps):
+            md.md_graph_launch(g, stream)
+        e1.record(stream)
+        stream.synchronize()
+        st = eng.stats(stream)
+        flags = eng.sync_check(stream, raise_on_flags=False)
+        charged = float((eng.host("q") > 0).mean())
+    eng.close()
+    ms = e0.elapsed_time(e1) / steps
+    return {"steps": steps, "ms_per_step": ms, "value": sys_.n_atoms / (ms * 1e-3),
+            "rebuilds": int(st["n_builds"]), "flags": flags, "charged_fraction": charged}
+
+
+def host_cores():
+    n = os.cpu_count() or 1
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = n
+    return n, aff
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--config", default="water_98304")
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="water_4194304")
     ap.add_argument("--cluster-group", type=int, default=0)
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the other workloads (98,304-atom schedule, batched clusters)")
+    ap.add_argument("--no-subbox", action="store_true",
+                    help="skip the oracle error report on the 65,536-atom sub-box")
     ap.add_argument("--fast-capacity", type=int, default=None)
     ap.add_argument("--tune", action="store_true",
                     help="search cluster group, skin and fast-atom capacity first and cache "
@@ -386,25 +561,28 @@ def main():
     S = a.warmup + a.steps
     from paper_2401_03180_amd import autotune
 
-    def knobs(prec):
+    def knobs(config, prec, steps=a.steps, warmup=a.warmup, cli=True):
         """Launch configuration: command line, else the cached tuning, else defaults."""
-        if a.tune:
-            autotune.tune(a.config, lambda: make_system(a.config, S), prec, a.steps, a.warmup,
+        if a.tune and cli:
+            autotune.tune(config, lambda: make_system(config, S), prec, steps, warmup,
                           log=log)
-        t = None if a.no_tuned else autotune.load(a.config, prec)
+        t = None if a.no_tuned else autotune.load(config, prec)
         k = {"cluster_group": 0, "skin": None, "fast_capacity": 0, "tuned": t is not None}
         if t is not None:
             k.update(cluster_group=t["cluster_group"], skin=t["skin"],
                      fast_capacity=t["fast_capacity"])
-        if a.cluster_group:
+        if cli and a.cluster_group:
             k["cluster_group"] = a.cluster_group
-        if a.skin is not None:
+        if cli and a.skin is not None:
             k["skin"] = a.skin
-        if a.fast_capacity is not None:
+        if cli and a.fast_capacity is not None:
             k["fast_capacity"] = a.fast_capacity
         return k
 
-    sys32 = make_system(a.config, S)
+    t_gen = time.perf_counter()
+    base_sys = make_system(a.config, S)
+    log("generated", a.config, "in %.1f s" % (time.perf_counter() - t_gen))
+    sys32 = base_sys.copy()
     ff_kind = ("methane" if a.config.startswith("methane") else "water") if a.forcefield else None
     ffb = ff_binding(sys32, ff_kind) if ff_kind else None
     lg = None
@@ -415,31 +593,47 @@ def main():
     if a.hybrid:
         from paper_2401_03180_amd import synth
         hy = synth.hybrid_inputs(sys32)
-    k32 = knobs(md.MD_FP32_KAHAN)
+    plain = ffb is None and lg is None and hy is None
+    sb = None
+    if a.config == "water_4194304" and plain and not a.no_subbox:
+        sb = subbox_rows(sys32)
+    k32 = knobs(a.config, md.MD_FP32_KAHAN)
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
+    sched = sys32.n_steps if sys32.n_systems == 1 else 0
     r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
                   use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg,
-                  hybrid=hy, ff=ffb)
+                  hybrid=hy, ff=ffb, schedule_steps=sched, subbox=sb)
     log("fp32", {k: v for k, v in r32.items() if k != "stats"})
     n = sys32.n_atoms
     value = n * a.steps / (r32["ms"] * 1e-3)
+    st = r32["stats"]
     extra = {"flags": r32["flags"], "rebuilds_timed": r32["builds"],
              "replay_identical": r32["replay_identical"],
+             "charged_fraction_end": r32["charged_fraction"],
              "pairs_in_cutoff_mean": r32["pairs"], "pairs_min": r32["pairs_min"],
              "pairs_max": r32["pairs_max"], "force_launches_timed": r32["kernel_launches"],
              "force_kernel_ms_median": r32["kernel_ms_median"],
              "force_kernel_ms_p90": r32["kernel_ms_p90"],
-             "list_codes": r32["stats"]["n_list_codes"],
-             "groups": r32["stats"]["n_groups"], "cluster_group": r32["stats"]["cluster_group"],
-             "max_group_entries": r32["stats"]["max_group_entries"],
-             "group_entry_capacity": r32["stats"]["group_entry_capacity"],
-             "max_list_len": r32["stats"]["max_list_len"],
-             "list_capacity": r32["stats"]["list_capacity"]}
+             "list_codes": st["n_list_codes"],
+             "codes_per_pair": st["n_list_codes"] / max(r32["pairs"], 1.0),
+             "groups": st["n_groups"], "cluster_group": st["cluster_group"],
+             "max_group_entries": st["max_group_entries"],
+             "group_entry_capacity": st["group_entry_capacity"],
+             "max_list_len": st["max_list_len"], "list_capacity": st["list_capacity"]}
+    if "schedule_ms_per_step" in r32:
+        extra.update(schedule_steps=r32["schedule_steps"],
+                     schedule_ms_per_step=r32["schedule_ms_per_step"],
+                     schedule_value=n / (r32["schedule_ms_per_step"] * 1e-3),
+                     schedule_rebuilds=r32["schedule_rebuilds"],
+                     schedule_flags=r32["schedule_flags"])
+    if "subbox" in r32:
+        extra["subbox_errors"] = r32["subbox"]
+        log("subbox", r32["subbox"])
     if not a.no_fp64:
-        sys64 = make_system(a.config, S)
-        ffb64 = ff_binding(sys64, ff_kind) if ff_kind else None
-        if sys64.n_systems > 1:
+        if sys32.n_systems > 1:
             # batched workloads: the plain FP64 form runs one system per context and launch
+            sys64 = base_sys.copy()
+            ffb64 = ff_binding(sys64, ff_kind) if ff_kind else None
             r64 = run_gpu_per_system(sys64, md.MD_FP64, a.steps, a.warmup, langevin=lg, hybrid=hy,
                                      ff_kind=ff_kind)
             v64 = n * a.steps / (r64["ms"] * 1e-3)
@@ -449,7 +643,9 @@ def main():
                           "fp64_flags": r64["flags"]})
             log("fp64 per system", r64)
         else:
-            k64 = knobs(md.MD_FP64)
+            sys64 = base_sys.copy()
+            ffb64 = ff_binding(sys64, ff_kind) if ff_kind else None
+            k64 = knobs(a.config, md.MD_FP64)
             r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, k64["cluster_group"], k64["skin"],
                           use_graph=not a.eager, fast_capacity=k64["fast_capacity"], langevin=lg,
                           hybrid=hy, ff=ffb64)
@@ -457,8 +653,41 @@ def main():
             v64 = n * a.steps / (r64["ms"] * 1e-3)
             extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
                           "fp32_vs_fp64_speedup": value / v64,
-                          "fp64_force_kernel_ms": r64["kernel_ms"], "fp64_flags": r64["flags"],
+                          "fp64_force_kernel_ms": r64["kernel_ms"],
+                          "fp64_force_tflops": FLOP_PER_PAIR * r64["pairs"] /
+                          (r64["kernel_ms"] * 1e-3) / 1e12,
+                          "fp64_flags": r64["flags"], "fp64_rebuilds_timed": r64["builds"],
                           "fp64_replay_identical": r64["replay_identical"], "fp64_launch": k64})
+        del sys64
+    if not a.no_legs and plain:
+        legs = {}
+        if a.config != "water_98304":
+            # the 98,304-atom pulse box over its whole 1,000-step schedule
+            s2 = make_system("water_98304", 0)
+            r = run_schedule(s2, md.MD_FP32_KAHAN, knobs("water_98304", md.MD_FP32_KAHAN,
+                                                          cli=False))
+            log("leg water_98304", r)
+            legs["water_98304"] = r
+            del s2
+        if a.config != "methane_256":
+            # 256 batched clusters against the plain FP64 form, one system per launch
+            s4 = make_system("methane_256", 0)
+            r4 = run_gpu(s4.copy(), md.MD_FP32_KAHAN, a.steps, a.warmup, 0, None,
+                         pair_samples=2, fast_capacity=0)
+            r4p = run_gpu_per_system(s4.copy(), md.MD_FP64, a.steps, a.warmup)
+            v4 = s4.n_atoms * a.steps / (r4["ms"] * 1e-3)
+            v4p = s4.n_atoms * a.steps / (r4p["ms"] * 1e-3)
+            legs["methane_256"] = {"atoms": s4.n_atoms, "systems": s4.n_systems,
+                                   "batched_fp32_ms_per_step": r4["ms"] / a.steps,
+                                   "batched_fp32_value": v4,
+                                   "batched_force_kernel_ms": r4["kernel_ms"],
+                                   "per_system_fp64_ms_per_step": r4p["ms"] / a.steps,
+                                   "per_system_fp64_value": v4p,
+                                   "batched_fp32_vs_per_system_fp64_speedup": v4 / v4p,
+                                   "flags": r4["flags"] | r4p["flags"]}
+            log("leg methane_256", legs["methane_256"])
+            del s4
+        extra["legs"] = legs
 
     if a.rdf:
         rr = run_rdf(make_system(a.config, S))
@@ -471,13 +700,13 @@ def main():
     achieved = fpp * r32["pairs"] / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                # the counter summary covers the Debye kernel on the plain water_98304 run
-                "traffic": (traffic_from_profile() if a.config == "water_98304" and hy is None
-                            and ffb is None and lg is None else None),
+                # the counter summary covers the Debye kernel on the plain workload
+                "traffic": traffic_from_profile(a.config) if plain else None,
                 "kernel": "k_force32" + ("<HYBRID>" if hy is not None else "") +
                           ("<QLJ>" if ffb is not None else ""),
                 "kernel_ms": kernel_ms,
                 "flop_per_pair": fpp,
+                "algorithmic_flop_per_launch": fpp * r32["pairs"],
                 "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS}
 
     out = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1,
@@ -487,7 +716,7 @@ def main():
            "config": {"workload": a.config, "atoms": n, "precision": "fp32 forces + kahan, "
                       "fp64 positions/integration/energies", "rc_nm": sys32.rc,
                       "skin_nm": k32["skin"] if k32["skin"] is not None else sys32.skin,
-                      "cluster_group": r32["stats"]["cluster_group"],
+                      "cluster_group": st["cluster_group"],
                       "fast_capacity": k32["fast_capacity"], "tuned": k32["tuned"],
                       "systems": sys32.n_systems, "langevin": lg is not None,
                       "hybrid_screening": hy is not None,

@@ -162,11 +162,20 @@ md_status md_build_cells(md_ctx* ctx, const double* x, const double* y, const do
 
 
 /* Stochastic integer ionization for the current step s (>= 1, the device step
- * counter): every atom a of system b with element e = elem[a] and charge
- * q[a] < qmax[e] gains +1 iff  u < floor(min(1, base[e][q] * g[b][s]) * 2^32),
+ * counter).  Section II.A assigns every atom an integer charge, drawn at random so
+ * that averages over atoms and runs follow the collisional-radiative charge-state
+ * populations; section II.B keeps charges integer (no partial charges).  Reading
+ * (the paper gives no mechanism): a sequential +1 process, every atom a of system b
+ * with element e = elem[a] and charge q[a] < qmax[e] gains +1 iff
+ *   u < floor(min(1, base[e][q] * g[b][s]) * 2^32),
  * where u is word 0 of Philox4x32-10 with counter (atom_id[a], s, b, 0) and key
- * (low, high 32 bits of seeds[b]).  elem: uint8 [N]; atom_id: uint32 [N] (the
- * atom's index inside its system); q: int8 [N], updated in place. */
+ * (low, high 32 bits of seeds[b]) (Salmon et al., SC'11), so the charges depend
+ * only on (seeds, tables, ids), never on positions or the neighbour structure.
+ * elem: uint8 [N]; atom_id: uint32 [N] (the atom's index inside its system); q:
+ * int8 [N], updated in place (device, caller-owned).  Errors: MD_ERR_ARG for a NULL
+ * array, MD_ERR_STATE before md_bind_tables; an element or charge outside its table
+ * latches MD_FLAG_BAD_INPUT, a step outside the tables MD_FLAG_STEP.
+ * Asynchronous. */
 md_status md_ionize_step(md_ctx* ctx, const uint8_t* elem, const uint32_t* atom_id, int8_t* q,
                          md_stream stream);
 
@@ -207,11 +216,15 @@ md_status md_clear_flags(md_ctx* ctx, md_stream stream);
 /* Debug export of the interacting pair set exactly as md_screened_forces decides
  * it for `prec` at positions x, y, z with charges q (runs the same force kernel):
  * writes up to max pairs (i, j), i < j, as caller indices into ij (HOST int32
- * [2*max], unordered) and their count into *n_pairs.  Synchronous; allocates
- * temporary device buffers. */
+ * [2*max], unordered) and their count into *n_pairs (max = 0: count only).
+ * e_atom (HOST FP64 [N], or NULL) receives the per-atom energies e_i = 1/2 sum_j
+ * phi_ij (section II.A, Eq. 2 and Eq. 8) of the same evaluation; it needs lists
+ * built at the current positions (no atom beyond skin/2 of the last build, e.g.
+ * right after md_build_cells with MD_BUILD_FORCE), else MD_ERR_STATE.
+ * Synchronous; allocates temporary device buffers. */
 md_status md_debug_pairs(md_ctx* ctx, md_precision prec, const double* x, const double* y,
                          const double* z, const int8_t* q, int64_t* n_pairs, int32_t* ij,
-                         int64_t max, md_stream stream);
+                         int64_t max, double* e_atom, md_stream stream);
 
 /* Every array a full step touches (all device pointers, caller order). */
 typedef struct md_step_args {

@@ -58,6 +58,8 @@ def lib():
             L.orc_forces_rows.restype = i64
             L.orc_pairs.argtypes = [i64, P, i32, P, f64, P, P, P, P, P, i64]
             L.orc_pairs.restype = i64
+            L.orc_pairs_rows.argtypes = [i64, P, P, P, i32, P, f64, P, P, P, P, P, i64, i32]
+            L.orc_pairs_rows.restype = i64
             L.orc_pair_r2.argtypes = [i32, P, P, P, P, i64, i64]
             L.orc_pair_r2.restype = f64
             L.orc_philox4x32_10.argtypes = [P, P, P]
@@ -289,6 +291,28 @@ def pairs(sys, x=None, y=None, z=None, max_pairs=None) -> np.ndarray:
         if cnt <= cap:
             return np.stack([oi[:cnt], oj[:cnt]], axis=1)
         cap = int(cnt)
+
+
+def pairs_rows(sys, rows, x=None, y=None, z=None, n_threads=0):
+    """Partners of the listed atoms: a list with, per row, the ascending int64 array
+    of every j != i of its system inside the cutoff (brute force over the system)."""
+    x = _c(sys.x if x is None else x, np.float64)
+    y = _c(sys.y if y is None else y, np.float64)
+    z = _c(sys.z if z is None else z, np.float64)
+    rows = _c(rows, np.int64)
+    offs = _c(sys.sys_offsets, np.int64)
+    sys_of_row = _c(np.searchsorted(offs, rows, side="right") - 1, np.int64)
+    box = None if sys.box is None else _c(sys.box, np.float64)
+    off = np.zeros(rows.size + 1, dtype=np.int64)
+    cap = max(1, 512 * rows.size)
+    while True:
+        out = np.empty(cap, dtype=np.int64)
+        tot = lib().orc_pairs_rows(rows.size, _p(rows), _p(sys_of_row), _p(offs),
+                                   int(sys.periodic), _p(box), sys.rc, _p(x), _p(y), _p(z),
+                                   _p(off), _p(out), cap, n_threads)
+        if tot <= cap:
+            return [out[off[r]:off[r + 1]].copy() for r in range(rows.size)]
+        cap = int(tot)
 
 
 def pair_r2(periodic, box, x, y, z, i, j) -> float:

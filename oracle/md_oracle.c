@@ -463,6 +463,49 @@ int64_t orc_pairs(int64_t n_sys, const int64_t* sys_off, int32_t periodic, const
     return cnt;
 }
 
+/* Rows mode of the pair set: for each listed atom i (rows[r], system sys_of_row[r]),
+ * every partner j != i of its system with r2 < rc2, ascending in j.  Partners of
+ * row r go to out_j[off[r] .. off[r + 1]), where off (n_rows + 1) is computed here
+ * from the counts; at most max partners are written in total.  Returns the total. */
+int64_t orc_pairs_rows(int64_t n_rows, const int64_t* rows, const int64_t* sys_of_row,
+                       const int64_t* sys_off, int32_t periodic, const double* box, double rc,
+                       const double* x, const double* y, const double* z, int64_t* off,
+                       int64_t* out_j, int64_t max, int32_t n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t r = 0; r < n_rows; ++r) {         /* count */
+        int64_t i = rows[r], b = sys_of_row[r], h = 0;
+        orc_geom g;
+        geom_init(&g, periodic, periodic ? box + 3 * b : NULL, rc);
+        for (int64_t j = sys_off[b]; j < sys_off[b + 1]; ++j) {
+            double d[3];
+            if (j != i && pair_r2(&g, x, y, z, i, j, d) < g.rc2) ++h;
+        }
+        off[r + 1] = h;
+    }
+    off[0] = 0;
+    for (int64_t r = 0; r < n_rows; ++r) off[r + 1] += off[r];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t r = 0; r < n_rows; ++r) {         /* fill */
+        int64_t i = rows[r], b = sys_of_row[r], k = off[r];
+        orc_geom g;
+        geom_init(&g, periodic, periodic ? box + 3 * b : NULL, rc);
+        for (int64_t j = sys_off[b]; j < sys_off[b + 1]; ++j) {
+            double d[3];
+            if (j != i && pair_r2(&g, x, y, z, i, j, d) < g.rc2) {
+                if (k < max) out_j[k] = j;
+                ++k;
+            }
+        }
+    }
+    return off[n_rows];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Bonded terms (section II.B, Eq. 9 and Eq. 10; readings)                  */
 /* ------------------------------------------------------------------------ */

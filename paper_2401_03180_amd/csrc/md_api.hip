@@ -60,7 +60,7 @@ void free_all(Ctx* c)
                     c->d_partial, c->d_ek_slots, c->d_fast_flag, c->d_fast_loc, c->d_fast_cnt,
                     c->d_fast_list, c->d_fast_e, c->d_atype, c->d_bar_arrive,
                     c->d_lg_c1, c->d_lg_kt, c->d_hyb64, c->d_hyb32, c->d_rdf_moved,
-                    c->d_rdf_xr, c->d_rdf_er, c->d_qlj32, c->d_qlj64, c->d_excl_off,
+                    c->d_rdf_xr, c->d_rdf_er, c->d_qlj, c->d_excl_off,
                     c->d_excl, c->d_bonds, c->d_bond_par, c->d_angles, c->d_angle_par,
                     c->d_bt_off, c->d_bt, c->d_bond_e, c->d_bond_blk};
     for (void* p : ptrs)
@@ -728,25 +728,19 @@ md_status md_bind_forcefield(md_ctx* ctx, const int8_t* z_type, const double* si
     // charge scaling of the LJ radii (Eq. 11)
     c->ff_qlj = z_type != nullptr;
     if (c->ff_qlj) {
-        float t32[kQljLen32] = {};
-        double t64[kQljLen64] = {};
+        double tab[kQljLen] = {};
         for (int t = 0; t < T; ++t) {
-            t64[t] = 1.0 / (double)z_type[t];
-            t64[MD_MAX_TYPES + t] = sigma_type[t];
-            t32[kQljSig + t] = (float)sigma_type[t];
-            t32[kQljSigZ + t] = (float)(sigma_type[t] / (double)z_type[t]);
+            tab[kQljInvZ + t] = 1.0 / (double)z_type[t];
+            tab[kQljSig + t] = sigma_type[t];
+            tab[kQljSigZ + t] = sigma_type[t] / (double)z_type[t];
         }
         for (int a = 0; a < T; ++a)
             for (int b = 0; b < T; ++b) {
                 const double sum = sigma_type[a] + sigma_type[b];
-                t32[kQljRs + a * MD_MAX_TYPES + b] = sum > 0.0 ? (float)(1.0 / sum) : 0.0f;
+                tab[kQljRs + a * MD_MAX_TYPES + b] = sum > 0.0 ? 1.0 / sum : 0.0;
             }
-        if (!c->d_qlj32) {
-            HIP_TRY(c, dalloc(&c->d_qlj32, kQljLen32));
-            HIP_TRY(c, dalloc(&c->d_qlj64, kQljLen64));
-        }
-        HIP_TRY(c, hipMemcpy(c->d_qlj32, t32, sizeof t32, hipMemcpyHostToDevice));
-        HIP_TRY(c, hipMemcpy(c->d_qlj64, t64, sizeof t64, hipMemcpyHostToDevice));
+        if (!c->d_qlj) HIP_TRY(c, dalloc(&c->d_qlj, kQljLen));
+        HIP_TRY(c, hipMemcpy(c->d_qlj, tab, sizeof tab, hipMemcpyHostToDevice));
     }
     // bonded terms and, per atom, the terms it takes part in
     for (void* p : {(void*)c->d_bonds, (void*)c->d_bond_par, (void*)c->d_angles,
@@ -957,7 +951,7 @@ md_status md_clear_flags(md_ctx* ctx, md_stream stream)
 
 md_status md_debug_pairs(md_ctx* ctx, md_precision prec, const double* x, const double* y,
                          const double* z, const int8_t* q, int64_t* n_pairs, int32_t* ij,
-                         int64_t max, md_stream stream)
+                         int64_t max, double* e_atom, md_stream stream)
 {
     if (!ctx) return MD_ERR_ARG;
     Ctx* c = &ctx->c;
@@ -966,15 +960,31 @@ md_status md_debug_pairs(md_ctx* ctx, md_precision prec, const double* x, const 
     if (max < 0) return fail(c, MD_ERR_ARG, "max must be >= 0");
     if (!c->tables_bound || !c->built) return fail(c, MD_ERR_STATE, "no build");
     hipStream_t st = S(stream);
+    if (e_atom) {
+        // per-atom energies come from the list kernels alone: no atom may be fast
+        HIP_TRY(c, hipStreamSynchronize(st));
+        int32_t nf = 0, pend = 0;
+        HIP_TRY(c, hipMemcpy(&nf, &c->dsc->n_fast_raw, sizeof nf, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(&pend, &c->dsc->need_rebuild, sizeof pend, hipMemcpyDeviceToHost));
+        if (nf != 0 || pend != 0)
+            return fail(c, MD_ERR_STATE, "per-atom energies need a build at the current "
+                                         "positions (%d atoms beyond skin/2)", nf);
+    }
     int2* buf = nullptr;
     double* f = nullptr;
     HIP_TRY(c, dalloc(&buf, std::max<int64_t>(max, 1)));
-    hipError_t e = dalloc(&f, 3 * std::max<int64_t>(c->N, 1));
+    // forces (3N), per-atom energies (N) and per-system energies (B)
+    hipError_t e = dalloc(&f, 4 * std::max<int64_t>(c->N, 1) + c->B);
     if (e != hipSuccess) { (void)hipFree(buf); return fail(c, MD_ERR_HIP, "allocation failed"); }
     e = hipMemsetAsync(&c->dsc->pair_count, 0, sizeof(unsigned long long), st);
+    if (e == hipSuccess && e_atom)
+        e = hipMemsetAsync(f + 3 * c->N, 0, sizeof(double) * c->N, st);
     if (e == hipSuccess) {
+        c->dbg_e_atom = e_atom ? f + 3 * c->N : nullptr;
         launch_repack(c, x, y, z, q, st);
-        e = launch_forces(c, prec, x, y, z, q, f, f + c->N, f + 2 * c->N, nullptr, buf, max, st);
+        e = launch_forces(c, prec, x, y, z, q, f, f + c->N, f + 2 * c->N,
+                          e_atom ? f + 4 * c->N : nullptr, buf, max, st);
+        c->dbg_e_atom = nullptr;
     }
     unsigned long long cnt = 0;
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -983,6 +993,8 @@ md_status md_debug_pairs(md_ctx* ctx, md_precision prec, const double* x, const 
     if (e == hipSuccess && max > 0)
         e = hipMemcpy(ij, buf, sizeof(int2) * std::min<int64_t>((int64_t)cnt, max),
                       hipMemcpyDeviceToHost);
+    if (e == hipSuccess && e_atom)
+        e = hipMemcpy(e_atom, f + 3 * c->N, sizeof(double) * c->N, hipMemcpyDeviceToHost);
     (void)hipFree(buf);
     (void)hipFree(f);
     if (e != hipSuccess) return fail(c, MD_ERR_HIP, "debug pair export: %s", hipGetErrorString(e));

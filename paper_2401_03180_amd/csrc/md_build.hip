@@ -294,7 +294,10 @@ __global__ void __launch_bounds__(256) k_scatter_cols(ScatterArgs A)
 }
 
 // Order the atoms of each bin by caller index (bins hold a few atoms), and clear
-// the bin counters for the next build.
+// the bin counters for the next build.  Every bin is sorted, whatever its size (a
+// vacuum grid stretched by a few far ions can put hundreds of atoms in one bin), so
+// the slot order, and with it every summation order, never depends on the order of
+// the binning atomics.
 __device__ void ph_bin_sort(const int32_t* bin_start, int32_t* sorted, int32_t* bin_cnt,
                             int64_t cap_bins, const DevScalars* dsc, int64_t gid, int64_t stride)
 {
@@ -303,7 +306,7 @@ __device__ void ph_bin_sort(const int32_t* bin_start, int32_t* sorted, int32_t* 
         bin_cnt[b] = 0;
         if (b >= nbins) continue;
         const int s = bin_start[b], e = bin_start[b + 1];
-        if (e - s < 2 || e - s > 128) continue;
+        if (e - s < 2) continue;
         if (e - s <= 8) {
             // the common case (a bin holds ~2 atoms): all loads at once, a sorting
             // network in registers (Batcher's odd-even merge for 8 inputs), all stores

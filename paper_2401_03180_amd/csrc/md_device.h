@@ -117,16 +117,16 @@ __device__ inline void pair_terms_hybrid64(double r2, double kap, int qa, int qb
 // Charge-scaled LJ radii (section II.B, Eq. 11) in FP64: each radius shrinks to
 // c sigma with c = 1 - q/Z and the pair radius is the mean of the two, so c6 and c12
 // scale by s^6 and s^12 with s = (c_a sigma_a + c_b sigma_b)/(sigma_a + sigma_b);
-// no scaling when both radii are 0 (no LJ term).  tab: [1/Z per type | sigma per type].
+// no scaling when both radii are 0 (no LJ term).  tab: the kQljLen table.
 __device__ inline void qlj_scale64(const double* tab, int ta, int tb, int qa, int qb, double* c6,
                                    double* c12)
 {
 #pragma clang fp contract(off)
-    const double sa = tab[MD_MAX_TYPES + ta], sb = tab[MD_MAX_TYPES + tb];
+    const double sa = tab[kQljSig + ta], sb = tab[kQljSig + tb];
     const double sum = sa + sb;
     if (!(sum > 0.0)) return;
-    const double ca = 1.0 - (double)qa * tab[ta];
-    const double cb = 1.0 - (double)qb * tab[tb];
+    const double ca = 1.0 - (double)qa * tab[kQljInvZ + ta];
+    const double cb = 1.0 - (double)qb * tab[kQljInvZ + tb];
     const double sc = (ca * sa + cb * sb) / sum;
     const double s6 = sc * sc * sc * sc * sc * sc;
     *c6 = *c6 * s6;

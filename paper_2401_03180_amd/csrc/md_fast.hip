@@ -49,7 +49,7 @@ struct FastArgs {
     int screen_lj;
     const double* hyb64;           // hybrid screening rows (NULL: Debye)
     int hyb_q;
-    const double* qlj64;           // charge-scaled LJ radii (Eq. 11), kQljLen64, or NULL
+    const double* qlj;             // charge-scaled LJ radii (Eq. 11), kQljLen, or NULL
     const int32_t* excl_off;       // LJ exclusions per caller atom (NULL: none)
     const int32_t* excl;
     const uint8_t* fast_flag;
@@ -100,7 +100,7 @@ __device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double ka
         for (int x = A.excl_off[ia]; x < A.excl_off[ia + 1]; ++x)
             if (A.excl[x] == ib) { c6 = 0.0; c12 = 0.0; break; }
     }
-    if (FULL && A.qlj64) qlj_scale64(A.qlj64, ta, tb, qa, qb, &c6, &c12);
+    if (FULL && A.qlj) qlj_scale64(A.qlj, ta, tb, qa, qb, &c6, &c12);
     if (FULL && hrow) {
         pair_terms_hybrid64(r2, kap, qa, qb, c6, c12, A.screen_lj != 0, hrow, A.hyb_q, f, e);
         return true;
@@ -514,7 +514,7 @@ void launch_fast(Ctx* c, const double* x, const double* y, const double* z, cons
     A.xs = c->d_xs; A.qs = c->d_qs; A.ts = c->d_ts; A.cap_slots = c->cap_slots;
     A.kappa = c->d_kappa; A.S1 = c->n_steps + 1;
     A.c6 = c->d_c6; A.c12 = c->d_c12; A.T = c->T_lj;
-    A.qlj64 = c->ff_qlj ? c->d_qlj64 : nullptr;
+    A.qlj = c->ff_qlj ? c->d_qlj : nullptr;
     A.excl_off = c->ff_excl ? c->d_excl_off : nullptr; A.excl = c->d_excl;
     A.rc2 = c->cfg.rc * c->cfg.rc;
     A.reach = c->cfg.rc + 0.5 * c->cfg.skin;
@@ -525,7 +525,7 @@ void launch_fast(Ctx* c, const double* x, const double* y, const double* z, cons
     A.dsc = c->dsc; A.fx = fx; A.fy = fy; A.fz = fz; A.emit = emit; A.emit_max = emit_max;
     const int fc = std::max(c->fast_cap, 1);
     const dim3 gs((unsigned)(fc + std::max<int64_t>(c->cap_cols, 1))), bs(kFastBlock);
-    const bool full = A.hyb64 || A.qlj64 || A.excl_off;
+    const bool full = A.hyb64 || A.qlj || A.excl_off;
     if (full) {
         if (emit) {
             if (energy) hipLaunchKernelGGL((k_fast<true, true, true>), gs, bs, 0, st, A, fc);

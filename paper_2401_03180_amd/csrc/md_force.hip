@@ -102,12 +102,12 @@ struct ForceArgs {
     const double* hyb64;
     int hyb_q;
     // force-field terms
-    const float* qlj32;          // charge-scaled LJ radii (QLJ): kQljLen32 floats
-    const double* qlj64;         // kQljLen64 doubles
+    const double* qlj;           // charge-scaled LJ radii (QLJ): the kQljLen table
     const int32_t* excl_off;     // LJ exclusions per caller atom (NULL: none)
     const int32_t* excl;
     int t_excl;                  // pseudo-type of excluded pairs
     const int32_t* inv_perm;     // slot of each caller atom (current build)
+    double* e_atom;              // debug (EMIT) launches: per-atom energies, or NULL
 };
 
 constexpr int kExclRegs = 8;     // excluded partners per atom held in registers
@@ -355,9 +355,9 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
     if (LISTS && !rebuild) return;
     for (int i = tid; i < A.T * A.T; i += blockDim.x)
         s_lj[i] = make_float2(A.lj32[2 * i], A.lj32[2 * i + 1]);
-    __shared__ float s_qlj[QLJ ? kQljLen32 : 1];
+    __shared__ double s_qlj[QLJ ? kQljLen : 1];
     if (QLJ)
-        for (int i = tid; i < kQljLen32; i += blockDim.x) s_qlj[i] = A.qlj32[i];
+        for (int i = tid; i < kQljLen; i += blockDim.x) s_qlj[i] = A.qlj[i];
     const int sentinel = A.E_cap * kCluster;
     uint16_t* s_mask = reinterpret_cast<uint16_t*>(s_j + sentinel + 1);
     // hybrid screening: {r', c1, c2, c3} per charge state, after the masks (dynamic LDS
@@ -477,8 +477,8 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
         double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ea = 0.0;
         float xi = -kFarF, yi = -kFarF, zi = -kFarF, qike = 0.0f, qif = 0.0f;
         float4 hi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float ci = 0.0f;                       // QLJ: the scaled radius c_i sigma_i
-        const float* rs_row = s_qlj + kQljRs;  // QLJ: 1/(sigma_i + sigma_j) of this atom
+        double ci = 0.0;                       // QLJ: the scaled radius c_i sigma_i
+        const double* rs_row = s_qlj + kQljRs; // QLJ: 1/(sigma_i + sigma_j) of this atom
         int tb = 0;
         // a fast atom (NaN position) takes no part, like padding: its pairs and its
         // force come from the fast-atom kernels
@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             qike = (float)(kKe * (double)q_i);
             tb = t_i * A.T;
             if (QLJ) {
-                ci = fmaf(-(float)q_i, s_qlj[kQljSigZ + t_i], s_qlj[kQljSig + t_i]);
+                ci = fma(-(double)q_i, s_qlj[kQljSigZ + t_i], s_qlj[kQljSig + t_i]);
                 rs_row = s_qlj + kQljRs + t_i * MD_MAX_TYPES;
             }
             if (HYBRID) {
@@ -562,12 +562,14 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 if (QLJ) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const float cj = fmaf(-pj[u].w, s_qlj[kQljSigZ + tj[u]],
+                        // in FP64 (full rate here): c sigma cancels as q nears Z and
+                        // the scale enters as s^12
+                        const double cj = fma(-(double)pj[u].w, s_qlj[kQljSigZ + tj[u]],
                                               s_qlj[kQljSig + tj[u]]);
-                        const float sc = (ci + cj) * rs_row[tj[u]];
-                        const float s2 = sc * sc, s6 = s2 * s2 * s2;
-                        lj[u].x *= s6;
-                        lj[u].y *= s6 * s6;
+                        const double sc = (ci + cj) * rs_row[tj[u]];
+                        const double s2 = sc * sc, s6 = s2 * s2 * s2;
+                        lj[u].x = (float)((double)lj[u].x * s6);
+                        lj[u].y = (float)((double)lj[u].y * (s6 * s6));
                     }
                 }
                 float dx[4], dy[4], dz[4], r2[4];
@@ -695,6 +697,11 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             A.fx[ai] = F[0];
             A.fy[ai] = F[1];
             A.fz[ai] = F[2];
+            if (EMIT && ENERGY && A.e_atom) {
+                double e = 0.0;
+                for (int h = 0; h < wpc; ++h) e += s_part[w + h][il][3];
+                A.e_atom[ai] = 0.5 * e;    // each pair is visited from both atoms
+            }
         }
         if (ENERGY && tid == 0) {
             double t = 0.0;
@@ -772,7 +779,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
                                A.emit_max);
                 const int tj = (int)(code >> kCodeIdxBits);
                 double c6 = A.c6[ti * A.T + tj], c12 = A.c12[ti * A.T + tj];
-                if (QLJ) qlj_scale64(A.qlj64, ti, tj, qi_n, A.qs[slot_j], &c6, &c12);
+                if (QLJ) qlj_scale64(A.qlj, ti, tj, qi_n, A.qs[slot_j], &c6, &c12);
                 double f, e;
                 if (HYBRID) {
                     pair_terms_hybrid64(r2, kap, qi_n, A.qs[slot_j], c6, c12, SCREEN_LJ, hrow,
@@ -811,6 +818,10 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
                 A.fz[ai] = Fz;
             }
             if (ENERGY) {
+                if (EMIT && A.e_atom) {
+                    const double ea = reduce8(eacc);
+                    if ((lane & 7) == 0 && ai >= 0) A.e_atom[ai] = 0.5 * ea;
+                }
                 for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
                 e_w = 0.5 * eacc;
             }
@@ -924,9 +935,10 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     A.wpc = kMaxWpc;
     A.cl_len = c->d_cl_len; A.ent_mask = c->d_ent_mask; A.nb_cap_h = c->nb_cap_h;
     A.hyb32 = c->d_hyb32; A.hyb64 = c->d_hyb64; A.hyb_q = c->hyb_q;
-    A.qlj32 = c->d_qlj32; A.qlj64 = c->d_qlj64;
+    A.qlj = c->d_qlj;
     A.excl_off = c->ff_excl ? c->d_excl_off : nullptr; A.excl = c->d_excl; A.t_excl = c->T;
     A.inv_perm = c->d_inv_perm;
+    A.e_atom = emit ? c->dbg_e_atom : nullptr;
     {
         const double m = c->rlist * (1.0 + 1e-5);
         A.thr2 = (float)(m * m);

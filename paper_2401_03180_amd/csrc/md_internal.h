@@ -97,8 +97,7 @@ struct Ctx {
     int32_t T_lj = 0;              // stride of the LJ tables: T, or T + 1 with exclusions
                                    // (type T is the "LJ excluded" pseudo-type, all zero)
     bool ff_qlj = false;           // LJ radii scaled with the charge
-    float* d_qlj32 = nullptr;      // kQljLen32: sigma | sigma/Z per type | 1/(sigma_i + sigma_j)
-    double* d_qlj64 = nullptr;     // kQljLen64: 1/Z | sigma per type (0 for the pseudo-type)
+    double* d_qlj = nullptr;       // kQljLen (0 for the pseudo-type)
     bool ff_excl = false;
     int32_t* d_excl_off = nullptr; // N+1: per-atom LJ-excluded partners (CSR, sorted)
     int32_t* d_excl = nullptr;
@@ -113,6 +112,9 @@ struct Ctx {
     uint8_t* d_rdf_er = nullptr;      // cap_slots: slot-order elements
     int cap_bar = 0;               // arrival words of its barrier
     uint32_t* d_bar_arrive = nullptr;
+    // per-atom energies e_i = 1/2 sum_j phi_ij written by the debug force launch
+    // (md_debug_pairs), NULL otherwise
+    double* dbg_e_atom = nullptr;
     // force-kernel launch timer: event pairs recorded around the next t_cap launches
     std::vector<hipEvent_t> t_ev;
     int t_cap = 0, t_n = 0;
@@ -193,14 +195,15 @@ struct Ctx {
     uint8_t* d_atype = nullptr;       // N: types in caller order (build time)
 };
 
-// Tables of the charge-scaled LJ radii (section II.B, Eq. 11): the radius of atom i
+// Table of the charge-scaled LJ radii (section II.B, Eq. 11): the radius of atom i
 // shrinks to c_i sigma_i with c_i = 1 - q_i/Z_i, a pair's radius is the mean of the
 // two, so its LJ radius scales by s = (c_i sigma_i + c_j sigma_j)/(sigma_i + sigma_j).
-// FP32: [sigma_t | sigma_t/Z_t | 1/(sigma_i + sigma_j) (0 when both are 0), row
-// stride MD_MAX_TYPES]; FP64: [1/Z_t | sigma_t].
-constexpr int kQljSig = 0, kQljSigZ = MD_MAX_TYPES, kQljRs = 2 * MD_MAX_TYPES;
-constexpr int kQljLen32 = 2 * MD_MAX_TYPES + MD_MAX_TYPES * MD_MAX_TYPES;
-constexpr int kQljLen64 = 2 * MD_MAX_TYPES;
+// FP64 (both paths evaluate the scale in FP64: sigma - q sigma/Z cancels when q
+// approaches Z, and s enters as s^12): [1/Z_t | sigma_t | sigma_t/Z_t |
+// 1/(sigma_i + sigma_j) (0 when both are 0), row stride MD_MAX_TYPES].
+constexpr int kQljInvZ = 0, kQljSig = MD_MAX_TYPES, kQljSigZ = 2 * MD_MAX_TYPES;
+constexpr int kQljRs = 3 * MD_MAX_TYPES;
+constexpr int kQljLen = 3 * MD_MAX_TYPES + MD_MAX_TYPES * MD_MAX_TYPES;
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -92,7 +92,7 @@ def lib():
             "md_screened_forces": [P, ctypes.c_int, P, P, P, P, P, P, P, P, P, P],
             "md_integrate_vv": [P, i32, f64, P, P, P, P, P, P, P, P, P, P, P, P],
             "md_sync_check": [P, P, P], "md_clear_flags": [P, P],
-            "md_debug_pairs": [P, ctypes.c_int, P, P, P, P, P, P, i64, P],
+            "md_debug_pairs": [P, ctypes.c_int, P, P, P, P, P, P, i64, P, P],
             "md_get_stats": [P, P, P], "md_step": [P, P, i32, P],
             "md_force_timer_start": [P, i32], "md_force_timer_read": [P, P, i32, P],
             "md_graph_create": [P, P, i32, P, P], "md_graph_launch": [P, P],
@@ -277,15 +277,28 @@ def md_clear_flags(ctx, stream=None):
     _check(ctx, lib().md_clear_flags(ctx, _stream(stream)))
 
 
-def md_debug_pairs(ctx, prec, x, y, z, q, max_pairs, stream=None) -> np.ndarray:
+def md_debug_pairs(ctx, prec, x, y, z, q, max_pairs, stream=None, e_atom=None) -> np.ndarray:
+    """Pairs (i, j) of the evaluation; e_atom (host FP64 [N] numpy array, or None)
+    receives the per-atom energies."""
     buf = np.empty((max(int(max_pairs), 1), 2), dtype=np.int32)
     n = ctypes.c_int64()
     _check(ctx, lib().md_debug_pairs(ctx, int(prec), _ptr(x), _ptr(y), _ptr(z), _ptr(q),
                                      ctypes.byref(n), buf.ctypes.data, int(max_pairs),
+                                     None if e_atom is None else e_atom.ctypes.data,
                                      _stream(stream)))
     if n.value > max_pairs:
         raise MDError(MD_ERR_CAPACITY, "pair buffer too small: %d > %d" % (n.value, max_pairs))
     return buf[:n.value]
+
+
+def md_count_pairs(ctx, prec, x, y, z, q, stream=None, e_atom=None) -> int:
+    """Number of interacting pairs of the evaluation (nothing exported)."""
+    n = ctypes.c_int64()
+    _check(ctx, lib().md_debug_pairs(ctx, int(prec), _ptr(x), _ptr(y), _ptr(z), _ptr(q),
+                                     ctypes.byref(n), None, 0,
+                                     None if e_atom is None else e_atom.ctypes.data,
+                                     _stream(stream)))
+    return int(n.value)
 
 
 def md_force_timer_start(ctx, capacity):
@@ -499,6 +512,18 @@ class Engine:
             max_pairs = int(self.sys.n_atoms * 400 * (self.sys.rc + 0.2) ** 3) + 1024
         return md_debug_pairs(self.ctx, self.prec if prec is None else prec, self.x, self.y,
                               self.z, self.q, max_pairs, stream)
+
+    def count_pairs(self, prec=None, stream=None):
+        return md_count_pairs(self.ctx, self.prec if prec is None else prec, self.x, self.y,
+                              self.z, self.q, stream)
+
+    def atom_energies(self, prec=None, stream=None):
+        """Per-atom energies e_i = 1/2 sum_j phi_ij of one evaluation at the current
+        state (needs a build at the current positions) and the pair count."""
+        e = np.zeros(self.sys.n_atoms, dtype=np.float64)
+        n = md_count_pairs(self.ctx, self.prec if prec is None else prec, self.x, self.y,
+                           self.z, self.q, stream, e_atom=e)
+        return e, n
 
     def graph(self, build_mode, stream, energy=False, ekin=False):
         """Executable graph of one full step (captured once per argument set)."""

@@ -56,6 +56,12 @@ def test_water_small_pairs_forces_energy(prec):
     gp = sorted_pairs(eng.debug_pairs(prec=prec))
     op = oracle.pairs(s)
     assert gp.shape == op.shape and np.array_equal(gp, op)
+    # per-atom energies e_i = 1/2 sum_j phi_ij of the debug export
+    e_atom, n = eng.atom_energies(prec)
+    assert n == op.shape[0]
+    de = np.abs(e_atom - ref["e_atom"])
+    assert np.all(de <= TOL[prec] * (np.abs(ref["e_atom"]) + ref["a_atom"]))
+    assert abs(e_atom.sum() - epot[0]) <= 1e-12 * esc
     st = eng.stats()
     assert st["flags"] == 0 and st["n_builds"] == 1
     eng.close()
@@ -582,12 +588,14 @@ def test_methane_batched_full_size_sampled(prec):
     assert st["n_atoms"] == s.n_atoms
 
 
-def test_water_large_full_size_sampled():
-    """4,194,304-atom water box: sampled FP32 forces after graph-replayed steps."""
+@pytest.mark.parametrize("prec", PRECS)
+def test_water_large_full_size_sampled(prec):
+    """4,194,304-atom water box: sampled forces after graph-replayed steps, in both
+    precisions (the FP32-against-FP64 comparison of the benchmark runs on this machine)."""
     s = synth.water_large(n_steps=4)
     s.base[:] = np.where(s.base > 0, 0.05, 0.0)
-    say("water_4194304 sampled rows")
-    st = _graph_steps_then_sample(s, 1, 4, 200, 51)
+    say("water_4194304 sampled rows prec", prec)
+    st = _graph_steps_then_sample(s, prec, 4, 200, 51 + prec)
     assert st["n_atoms"] == 4194304
 
 

@@ -201,6 +201,37 @@ def test_pair_set_matches_kdtree():
     assert len(a) > 300000
 
 
+def test_pairs_rows_match_kdtree_and_pair_set():
+    """Rows mode of the pair set: each listed atom's partners equal an independent
+    periodic k-d tree ball query (partners within 1e-9 nm of rc excluded from the
+    comparison) and the rows' pairs of the all-pairs set, on a periodic water box and
+    on a batch of vacuum clusters."""
+    s = synth.water_small()
+    L = s.box[0, 0]
+    P = np.mod(s.positions(), L)
+    t = cKDTree(P, boxsize=L)
+    rows = np.arange(0, s.n_atoms, 7)
+    got = oracle.pairs_rows(s, rows)
+    S = oracle.pairs(s)
+    both = np.concatenate([S, S[:, ::-1]])
+    for r, i in enumerate(rows):
+        ref = np.array(sorted(j for j in t.query_ball_point(P[i], s.rc) if j != i))
+        diff = set(got[r].tolist()) ^ set(ref.tolist())
+        for j in diff:
+            dd = P[i] - P[j]
+            dd -= L * np.rint(dd / L)
+            assert abs(np.linalg.norm(dd) - s.rc) < 1e-9
+        assert np.array_equal(got[r], np.sort(both[both[:, 0] == i, 1]))
+        assert np.all(np.diff(got[r]) > 0)
+    c = synth.methane_clusters(n_clusters=3, lo=300, hi=600, n_steps=2)
+    rows = np.arange(0, c.n_atoms, 11)
+    got = oracle.pairs_rows(c, rows)
+    S = oracle.pairs(c)
+    both = np.concatenate([S, S[:, ::-1]])
+    for r, i in enumerate(rows):
+        assert np.array_equal(got[r], np.sort(both[both[:, 0] == i, 1]))
+
+
 def test_pair_set_across_periodic_seam():
     L = 3.0
     s = two_atoms([0.0, 0.0, 0.0], 1, 1, periodic=True, L=L)
