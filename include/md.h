@@ -383,6 +383,24 @@ md_status md_rdf_histogram(md_ctx* ctx, const double* x, const double* y, const 
                            const uint8_t* elem, double r_max, int32_t n_bins, uint64_t* hist,
                            md_stream stream);
 
+/* No-allocation form of md_rdf_histogram, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and the same counts, bit for bit; the search workspace
+ * (25 bytes per slot of the context plus one per atom, about 28 bytes per atom) lives
+ * in a fixed device array of MD_RDF_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends, instead of the context workspace that
+ * md_rdf_histogram allocates on its first call.  Nothing is allocated and nothing
+ * synchronizes, so the call can be captured.  Every call on one device shares that
+ * device's array and leaves its contents behind: calls that overlap on one GPU (two
+ * streams, contexts or threads) race and give wrong counts, so serialize them.
+ * Errors: as md_rdf_histogram; MD_ERR_CAPACITY when the context needs more workspace
+ * than the array holds; MD_ERR_HIP when the array's device address could not be
+ * found.  Asynchronous. */
+#define MD_RDF_SCRATCH_BYTES (32u << 20)
+md_status md_rdf_histogram_noalloc(md_ctx* ctx, const double* x, const double* y,
+                                   const double* z, const uint8_t* elem, double r_max,
+                                   int32_t n_bins, uint64_t* hist, md_stream stream);
+
 /* g_ab for one element pair from its n_bins counts (HOST arrays, FP64, no device
  * work): g[k] = counts[k] / (P / volume * 4/3 pi (r_{k+1}^3 - r_k^3)) with r_k = k dr
  * and P = n_a n_b pairs (same = 0) or n_a (n_a - 1) / 2 (same = 1: a = b).  The ideal

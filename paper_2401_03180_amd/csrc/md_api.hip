@@ -147,6 +147,9 @@ md_status md_create(const md_config* cfg, const int64_t* sys_offsets, md_ctx** o
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
                                                    c->device);
+    // the device address of the no-allocation histogram's fixed workspace, once per
+    // device (its failure only disables that entry point)
+    if (e == hipSuccess) (void)rdf_scratch_setup(c->device);
     int lds = 0;
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
@@ -867,7 +870,37 @@ md_status md_rdf_histogram(md_ctx* ctx, const double* x, const double* y, const 
         HIP_TRY(c, dalloc(&c->d_rdf_er, c->cap_slots));
     }
     launch_rdf(c, x, y, z, elem, r_max, n_bins, reinterpret_cast<unsigned long long*>(hist),
-               S(stream));
+               c->d_rdf_moved, c->d_rdf_xr, c->d_rdf_er, S(stream));
+    HIP_TRY(c, hipGetLastError());
+    return MD_OK;
+}
+
+md_status md_rdf_histogram_noalloc(md_ctx* ctx, const double* x, const double* y,
+                                   const double* z, const uint8_t* elem, double r_max,
+                                   int32_t n_bins, uint64_t* hist, md_stream stream)
+{
+    if (!ctx) return MD_ERR_ARG;
+    Ctx* c = &ctx->c;
+    if (!c->tables_bound || !c->built)
+        return fail(c, MD_ERR_STATE, "build cells before the histogram");
+    if (!(r_max > 0.0) || !(r_max <= c->cfg.rc))
+        return fail(c, MD_ERR_ARG, "r_max must be in (0, rc]");
+    if (n_bins < 1 || n_bins > kRdfMaxBins)
+        return fail(c, MD_ERR_ARG, "n_bins must be in [1, %d]", kRdfMaxBins);
+    if (null_any({x, y, z, elem, hist}) && c->N > 0) return fail(c, MD_ERR_ARG, "NULL array");
+    const size_t need = rdf_scratch_bytes(c->N, c->cap_slots);
+    if (need > kRdfScratchBytes)
+        return fail(c, MD_ERR_CAPACITY,
+                    "the no-allocation histogram needs %zu bytes of workspace (%lld atoms, "
+                    "%lld slots); its fixed device array holds %zu",
+                    need, (long long)c->N, (long long)c->cap_slots, kRdfScratchBytes);
+    unsigned char* p = static_cast<unsigned char*>(rdf_scratch(c->device));
+    if (!p) return fail(c, MD_ERR_HIP, "device address of the histogram workspace unavailable");
+    double* xr = reinterpret_cast<double*>(p);
+    uint8_t* er = p + (((size_t)c->cap_slots * 3 * sizeof(double) + 255) & ~(size_t)255);
+    uint8_t* moved = er + (((size_t)c->cap_slots + 255) & ~(size_t)255);
+    launch_rdf(c, x, y, z, elem, r_max, n_bins, reinterpret_cast<unsigned long long*>(hist),
+               moved, xr, er, S(stream));
     HIP_TRY(c, hipGetLastError());
     return MD_OK;
 }

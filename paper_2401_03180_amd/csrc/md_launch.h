@@ -42,8 +42,18 @@ void launch_bonded(Ctx* c, const double* x, const double* y, const double* z, co
 // pair-distance histograms (md_rdf.hip)
 constexpr size_t kRdfLdsMax = 48 * 1024;
 constexpr int kRdfMaxBins = 2048;
+// moved (N bytes), xr (3 * cap_slots doubles), er (cap_slots bytes): the search
+// workspace, every byte of it written before it is read
 void launch_rdf(Ctx* c, const double* x, const double* y, const double* z, const uint8_t* elem,
-                double r_max, int n_bins, unsigned long long* hist, hipStream_t st);
+                double r_max, int n_bins, unsigned long long* hist, uint8_t* moved, double* xr,
+                uint8_t* er, hipStream_t st);
+// the same workspace in the fixed per-device array of the no-allocation entry point:
+// rdf_scratch_setup looks its device address up once per device (with that device
+// current); rdf_scratch returns it (NULL if the lookup failed or never ran)
+constexpr size_t kRdfScratchBytes = MD_RDF_SCRATCH_BYTES;
+size_t rdf_scratch_bytes(int64_t N, int64_t cap_slots);
+hipError_t rdf_scratch_setup(int device);
+void* rdf_scratch(int device);
 int vv_block_size();
 void launch_set_step(Ctx* c, int64_t step, hipStream_t st);
 void launch_clear_flags(Ctx* c, hipStream_t st);

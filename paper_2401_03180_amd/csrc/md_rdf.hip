@@ -14,11 +14,56 @@
 // from the positions passed in) are counted by a brute-force pass over its system.
 // The current positions are first gathered into slot order (NaN for moved atoms and
 // padding), so that the scans of neighbouring slots read the same cache lines.
+#include <mutex>
+
 #include "md_device.h"
 #include "md_internal.h"
 #include "md_launch.h"
 
 namespace md {
+
+// Workspace of the no-allocation histogram entry point: one fixed array per device
+// (the code object's copy on that device), held until the process ends.  Host code
+// never takes this name as an address: rdf_scratch_setup asks the runtime for the
+// array's device address once per device and the launch passes that pointer.
+static __device__ __align__(256) unsigned char scratch[kRdfScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+bool g_scratch_done[kScratchDevices] = {};
+}  // namespace
+
+size_t rdf_scratch_bytes(int64_t N, int64_t cap_slots)
+{
+    const size_t xr = ((size_t)cap_slots * 3 * sizeof(double) + 255) & ~(size_t)255;
+    const size_t er = ((size_t)cap_slots + 255) & ~(size_t)255;
+    return xr + er + (size_t)N;
+}
+
+hipError_t rdf_scratch_setup(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_done[device]) return g_scratch_ptr[device] ? hipSuccess : hipErrorInvalidSymbol;
+    g_scratch_done[device] = true;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* rdf_scratch(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 constexpr int kRdfBlock = 256;
 constexpr int kRdfSplit = 8;         // threads sharing one slot's scan (latency hiding)
@@ -232,7 +277,8 @@ size_t rdf_lds_bytes(int E, int n_bins, bool with_hist)
 }
 
 void launch_rdf(Ctx* c, const double* x, const double* y, const double* z, const uint8_t* elem,
-                double r_max, int n_bins, unsigned long long* hist, hipStream_t st)
+                double r_max, int n_bins, unsigned long long* hist, uint8_t* moved, double* xr,
+                uint8_t* er, hipStream_t st)
 {
     RdfArgs A;
     A.x = x; A.y = y; A.z = z; A.elem = elem; A.xref = c->d_xref;
@@ -242,9 +288,9 @@ void launch_rdf(Ctx* c, const double* x, const double* y, const double* z, const
     A.dr = r_max / (double)n_bins;
     A.reach = r_max + 0.5 * c->cfg.skin;
     A.thr2 = 0.25 * c->cfg.skin * c->cfg.skin;
-    A.moved = c->d_rdf_moved;
-    A.xr = c->d_rdf_xr;
-    A.er = c->d_rdf_er;
+    A.moved = moved;
+    A.xr = xr;
+    A.er = er;
     A.cap_slots = c->cap_slots;
     A.hist = hist;
     const size_t with = rdf_lds_bytes(c->E, n_bins, true);

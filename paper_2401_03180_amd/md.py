@@ -24,6 +24,7 @@ MD_FLAG_CELL_OVERFLOW, MD_FLAG_LIST_OVERFLOW, MD_FLAG_SKIN = 0x1, 0x2, 0x4
 MD_FLAG_NONFINITE, MD_FLAG_STEP, MD_FLAG_BAD_INPUT = 0x8, 0x10, 0x20
 MD_FLAG_BARRIER = 0x40
 MD_MAX_TYPES, MD_MAX_ELEMENTS, MD_MAX_CHARGE_STATES = 8, 8, 128
+MD_RDF_SCRATCH_BYTES = 32 << 20
 
 EXPORTED = (
     "md_create", "md_destroy", "md_last_error", "md_bind_tables", "md_set_step", "md_get_step",
@@ -32,6 +33,7 @@ EXPORTED = (
     "md_force_timer_start", "md_force_timer_read", "md_step", "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_debye_length_nm",
     "md_rates_from_fractions", "md_bind_langevin", "md_integrate_langevin", "md_bind_hybrid",
     "md_rdf_histogram", "md_rdf_normalize", "md_structure_factor", "md_bind_forcefield",
+    "md_rdf_histogram_noalloc",
 )
 
 
@@ -101,6 +103,7 @@ def lib():
             "md_bind_langevin": [P, P, P, f64],
             "md_bind_hybrid": [P, P],
             "md_rdf_histogram": [P, P, P, P, P, f64, i32, P, P],
+            "md_rdf_histogram_noalloc": [P, P, P, P, P, f64, i32, P, P],
             "md_bind_forcefield": [P, P, P, P, i64, P, P, i64, P, P, i64],
             "md_rdf_normalize": [i32, f64, P, i64, i64, i32, f64, P],
             "md_structure_factor": [i32, f64, P, f64, i32, P, P],
@@ -238,6 +241,14 @@ def md_rdf_histogram(ctx, x, y, z, elem, r_max, n_bins, hist, stream=None):
     """hist: device int64/uint64 tensor [B, E, E, n_bins] (added to)."""
     _check(ctx, lib().md_rdf_histogram(ctx, _ptr(x), _ptr(y), _ptr(z), _ptr(elem), float(r_max),
                                        int(n_bins), _ptr(hist), _stream(stream)))
+
+
+def md_rdf_histogram_noalloc(ctx, x, y, z, elem, r_max, n_bins, hist, stream=None):
+    """md_rdf_histogram with the library's fixed per-device workspace (allocates
+    nothing)."""
+    _check(ctx, lib().md_rdf_histogram_noalloc(ctx, _ptr(x), _ptr(y), _ptr(z), _ptr(elem),
+                                               float(r_max), int(n_bins), _ptr(hist),
+                                               _stream(stream)))
 
 
 def md_rdf_normalize(counts, r_max, n_a, n_b, same, volume) -> np.ndarray:
