@@ -516,6 +516,8 @@ def main():
                     help="skip the other workloads (98,304-atom schedule, batched clusters)")
     ap.add_argument("--no-subbox", action="store_true",
                     help="skip the oracle error report on the 65,536-atom sub-box")
+    ap.add_argument("--no-schedule", action="store_true",
+                    help="skip the timing of the whole schedule (initial build included)")
     ap.add_argument("--fast-capacity", type=int, default=None)
     ap.add_argument("--tune", action="store_true",
                     help="search cluster group, skin and fast-atom capacity first and cache "
@@ -599,7 +601,7 @@ def main():
         sb = subbox_rows(sys32)
     k32 = knobs(a.config, md.MD_FP32_KAHAN)
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
-    sched = sys32.n_steps if sys32.n_systems == 1 else 0
+    sched = sys32.n_steps if sys32.n_systems == 1 and not a.no_schedule else 0
     r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
                   use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg,
                   hybrid=hy, ff=ffb, schedule_steps=sched, subbox=sb)
