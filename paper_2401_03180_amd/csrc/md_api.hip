@@ -405,6 +405,7 @@ md_status md_bind_tables(md_ctx* ctx, const double* box, const double* c6, const
         fresh.n_cu = c->n_cu; fresh.max_lds = c->max_lds; fresh.lds_per_cu = c->lds_per_cu;
         fresh.force32_static_lds = c->force32_static_lds;
         fresh.force32_static_lds_h = c->force32_static_lds_h;
+        fresh.force64_static_lds = c->force64_static_lds;
         *c = fresh;
     }
     c->box.assign(c->cfg.periodic ? box : nullptr, c->cfg.periodic ? box + 3 * B : nullptr);

@@ -336,7 +336,8 @@ __device__ inline void repack_range(const RepackArgs& A, int64_t gtid, int64_t g
             A.xs[A.cap_slots + s] = NAN;
             A.xs[2 * A.cap_slots + s] = NAN;
             A.qs[s] = a >= 0 ? A.q[a] : 0;
-            A.xo[s] = make_float4(NAN, NAN, NAN, a >= 0 ? (float)A.q[a] : 0.0f);
+            // x alone marks the slot empty (the force kernel's staging tests it)
+            A.xo[s] = make_float4(NAN, 0.0f, 0.0f, a >= 0 ? (float)A.q[a] : 0.0f);
         }
     }
 }

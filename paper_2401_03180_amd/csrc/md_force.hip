@@ -92,6 +92,7 @@ struct ForceArgs {
     int2* emit;
     int64_t emit_max;
     int wpc;
+    int stage64;                 // FP64 kernel: the group table is staged in LDS
     // list (re)build inside the FP32 kernel
     int32_t* cl_len;
     const uint8_t* ent_mask;
@@ -383,64 +384,87 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
             for (int q = tid; q < A.hyb_q; q += blockDim.x) s_hyb[q] = hr[q];
         }
 
-        // ---- stage the candidate atoms in the group frame (padding slots hold NaN
-        //      positions and are never inside the cutoff): one thread per entry adds
-        //      the FP64 offset of the cluster's box corner from the group centre (with
-        //      the entry's periodic shift), rounded once, to the FP32 offsets of its 8
-        //      atoms from that corner (written by the repack).  Each thread walks its
-        //      atoms in an order rotated by its lane, which spreads the LDS writes over
-        //      the banks.
+        // ---- stage the candidate atoms in the group frame, in batches of 64 entries
+        //      per wave: (a) one lane per entry computes the FP64 offset of the
+        //      entry's cluster box corner from the group centre (with its periodic
+        //      shift), rounded once, and parks it with the cluster index in the slot
+        //      of the entry's atom (e & 7); (b) one lane per atom (an entry's 8 atoms in
+        //      adjacent lanes of the same wave, so LDS program order makes the corner
+        //      visible) adds its FP32 offset from the corner (written by the repack)
+        //      and stores the candidate.  Padding and fast atoms (offset x NaN) go far
+        //      away, outside every cutoff; their NaNs do not enter m (max ignores a NaN
+        //      operand).
         float m = 0.0f;                        // largest |staged coordinate| or |offset|
         const int nent = gr.nent;
-        // the lane index through an opaque move, so the rotated offsets below are
-        // recomputed per group instead of being held (and spilled) across the loop
-        int lrot;
-        __asm__ volatile("v_mov_b32 %0, %1" : "=v"(lrot) : "v"(lane));
-        for (int e = tid; e < nent; e += blockDim.x) {
-            // 32-bit byte offsets keep the load bases scalar
-            const uint32_t en =
-                ld_off(A.ent, ((uint32_t)g * (uint32_t)A.E_cap + (uint32_t)e) * 4u);
-            const uint32_t cl = en & kEntClusterMask;
-            const uint32_t cb = (cl << 4) + (cl << 3);          // 24 bytes per corner
-            const uint32_t s0 = cl * kCluster;
-            float4 o[kCluster];
+        const uint32_t gbase = (uint32_t)g * (uint32_t)A.E_cap;
+        for (int eb = w * 64; eb < nent; eb += nw * 64) {
+            {
+                const int e = eb + lane;
+                if (e < nent) {
+                    // 32-bit byte offsets keep the load bases scalar
+                    const uint32_t en = ld_off(A.ent, (gbase + (uint32_t)e) * 4u);
+                    const uint32_t cl = en & kEntClusterMask;
+                    const uint32_t cb = cl * 24u;                  // 24 bytes per corner
+                    float b[3];
 #pragma unroll
-            for (int j = 0; j < kCluster; ++j)
-                o[j] = ld_off(A.xo, (s0 + (uint32_t)((j + lrot) & 7)) * (uint32_t)sizeof(float4));
-            // while the lists are rebuilt .w carries the type (the charges are put back
-            // before the pair loop); the 8 types of a cluster are one aligned word
-            const uint64_t types =
-                rebuild ? ld_off(reinterpret_cast<const uint64_t*>(A.ts), s0) : 0ull;
-            float b[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                double bd = ld_off(A.cl_lo, cb + 8u * (uint32_t)d) - gr.c[d];
-                if (gs.periodic) {
-                    const int sh = (int)((en >> (26 + 2 * d)) & 3u) - 1;
-                    bd = fma((double)sh, gs.L[d], bd);
+                    for (int d = 0; d < 3; ++d) {
+                        double bd = ld_off(A.cl_lo, cb + 8u * (uint32_t)d) - gr.c[d];
+                        if (gs.periodic) {
+                            const int sh = (int)((en >> (26 + 2 * d)) & 3u) - 1;
+                            bd = fma((double)sh, gs.L[d], bd);
+                        }
+                        b[d] = (float)bd;
+                    }
+                    s_j[e * kCluster + (e & 7)] =
+                        make_float4(b[0], b[1], b[2], __int_as_float((int)cl));
+                    if (rebuild) {
+                        const int c = (int)cl - gr.cl0;
+                        const uint32_t own = ((en >> 26) == 0x15u && c >= 0 && c < gr.ncl)
+                                                 ? (1u << (8 + c)) : 0u;
+                        s_mask[e] = (uint16_t)(A.ent_mask[(int64_t)g * A.E_cap + e] | own);
+                    }
                 }
-                b[d] = (float)bd;
             }
+            // 4 loads in flight before any use.  A lane past the last entry stores
+            // nothing and loads from cluster 0 (the corner slot it would read may
+            // already hold a staged atom: no cluster index)
+            auto atoms = [&](int a0, auto reb_c) {
+                constexpr bool REB = decltype(reb_c)::value;
+                float4 bb[4], o[4];
+                uint32_t tv[4];
 #pragma unroll
-            for (int j = 0; j < kCluster; ++j) {
-                const int k = (j + lrot) & 7;
-                // padding and fast atoms (NaN offsets) go far away, outside every
-                // cutoff; their NaNs do not enter m (max ignores a NaN operand)
-                const bool pad = o[j].x != o[j].x;
-                const float r0 = b[0] + o[j].x, r1 = b[1] + o[j].y, r2 = b[2] + o[j].z;
-                m = fmaxf(m, fmaxf(fabsf(r0), fabsf(o[j].x)));
-                m = fmaxf(m, fmaxf(fabsf(r1), fabsf(o[j].y)));
-                m = fmaxf(m, fmaxf(fabsf(r2), fabsf(o[j].z)));
-                const float wv =
-                    rebuild ? __int_as_float((int)((types >> (8 * k)) & 0xFFull)) : o[j].w;
-                s_j[e * kCluster + k] = pad ? make_float4(kFarF, kFarF, kFarF, 0.0f)
-                                            : make_float4(r0, r1, r2, wv);
-            }
-            if (rebuild) {
-                const int c = (int)cl - gr.cl0;
-                const uint32_t own = ((en >> 26) == 0x15u && c >= 0 && c < gr.ncl)
-                                         ? (1u << (8 + c)) : 0u;
-                s_mask[e] = (uint16_t)(A.ent_mask[(int64_t)g * A.E_cap + e] | own);
+                for (int a = 0; a < 4; ++a) {
+                    const int e = min(eb + (a0 + a) * 8 + (lane >> 3), nent - 1);
+                    bb[a] = s_j[e * kCluster + (e & 7)];
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const bool here = eb + (a0 + a) * 8 + (lane >> 3) < nent;
+                    const uint32_t cl = here ? (uint32_t)__float_as_int(bb[a].w) : 0u;
+                    const uint32_t slot = cl * kCluster + (lane & 7);
+                    o[a] = ld_off(A.xo, slot * (uint32_t)sizeof(float4));
+                    // while the lists are rebuilt .w carries the type (the charges are
+                    // put back before the pair loop)
+                    if (REB) tv[a] = ld_off(A.ts, slot);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int e = eb + (a0 + a) * 8 + (lane >> 3);
+                    if (e < nent) {
+                        const float r0 = bb[a].x + o[a].x, r1 = bb[a].y + o[a].y,
+                                    r2 = bb[a].z + o[a].z;
+                        m = fmaxf(m, fmaxf(fabsf(r0), fabsf(o[a].x)));
+                        m = fmaxf(m, fmaxf(fabsf(r1), fabsf(o[a].y)));
+                        m = fmaxf(m, fmaxf(fabsf(r2), fabsf(o[a].z)));
+                        const float wv = REB ? __int_as_float((int)tv[a]) : o[a].w;
+                        s_j[e * kCluster + (lane & 7)] =
+                            make_float4(o[a].x != o[a].x ? kFarF : r0, r1, r2, wv);
+                    }
+                }
+            };
+            for (int a0 = 0; a0 < 8; a0 += 4) {
+                if (rebuild) atoms(a0, std::true_type{});
+                else atoms(a0, std::false_type{});
             }
         }
         // this wave's i-atoms (slot-indexed): the loads are issued before the barrier,
@@ -717,126 +741,244 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 
 // ------------------------------------------------------------------ FP64 kernel
 
-template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool HYBRID = false, bool QLJ = false>
-__global__ void __launch_bounds__(kForceBlockMax) k_force64(ForceArgs A)
+// The FP64 kernel stages a group's candidates in LDS as the caller's FP64 positions
+// (unchanged values, so every pair's distance is the exact membership expression)
+// and their charges; a group table too large for one work-group's LDS is read from
+// global memory instead (same values, same order).  Each i-cluster takes wpc waves:
+// the two half-lists, each split by alternate rows.  Candidates without a position
+// (the sentinel, padding, fast atoms: NaN in the slot arrays) are staged at the
+// origin with the charge kAbsentQ, which no pair test accepts.
+constexpr int kForce64Block = 1024;
+constexpr int16_t kAbsentQ = 0x4000;
+
+__host__ __device__ inline int64_t force64_stage_slots(int E_cap)
 {
-    __shared__ double s_e[kMaxGroup];
+    return (int64_t)E_cap * kCluster + 1;          // + the sentinel
+}
+
+size_t force64_lds_bytes(int E_cap)
+{
+    const int64_t S = force64_stage_slots(E_cap);
+    return (size_t)S * 3 * sizeof(double) + (size_t)((S * 2 + 15) & ~(int64_t)15);
+}
+
+template <bool ENERGY, bool EMIT, bool SCREEN_LJ, bool HYBRID = false, bool QLJ = false>
+__global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
+{
+    extern __shared__ double s_x[];
+    __shared__ double2 s_c[MD_MAX_TYPES * MD_MAX_TYPES];
+    __shared__ double s_part[kForce64Block / 64][kCluster][4];
     __shared__ int s_g;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wpc = A.wpc;                          // waves per i-cluster (even)
+    const int cw = w / wpc, sub = w - cw * wpc;
+    const int half = sub & 1, rp = sub >> 1, nrp = wpc >> 1;
+    const int il = lane >> 3, k8 = lane & 7;
     const int64_t step = clamp_step(A);
     const int ngroups = A.dsc->n_groups;
     const uint32_t sentinel = (uint32_t)(A.E_cap * kCluster);
     const int64_t cs = A.cap_slots;
+    const bool staged = A.stage64 != 0;              // uniform
+    const int64_t S = force64_stage_slots(A.E_cap);
+    double* s_y = s_x + S;
+    double* s_z = s_x + 2 * S;
+    int16_t* s_q = reinterpret_cast<int16_t*>(s_x + 3 * S);
+    for (int i = tid; i < A.T * A.T; i += blockDim.x) s_c[i] = make_double2(A.c6[i], A.c12[i]);
+    if (staged && tid == 0) {                        // the sentinel: never inside
+        s_x[sentinel] = 0.0; s_y[sentinel] = 0.0; s_z[sentinel] = 0.0;
+        s_q[sentinel] = kAbsentQ;
+    }
     for (int g = blockIdx.x; g < ngroups;) {
+        unsigned claim = 0u;
+        if (tid == 0) claim = atomicAdd(&A.dsc->work_force, 1u);
         const Group gr = A.groups[g];
         const GridSys gs = A.grid[gr.sys];
         const double kap = A.kappa[(int64_t)gr.sys * A.S1 + step];
         const double* hrow = HYBRID ? A.hyb64 + ((int64_t)gr.sys * A.S1 + step) * A.hyb_q * 4
                                     : nullptr;
-        double e_w = 0.0;
-        if (w < gr.ncl) {
-            const int I = gr.cl0 + w;
-            const int il = lane >> 3;
-            const int64_t slot_i = (int64_t)I * kCluster + il;
-            const int ai = A.perm[slot_i];
-            double xi = 0.0, yi = 0.0, zi = 0.0, qi = 0.0;
-            int ti = 0, qi_n = 0;
+        const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
+        const int nent = gr.nent;
+        // ---- stage: candidate t = 8 e + k is atom k of entry e's cluster (consecutive
+        //      threads read consecutive slots)
+        if (staged) {
+            for (int t = tid; t < nent * kCluster; t += blockDim.x) {
+                const int64_t slot = (int64_t)(ent_g[t >> 3] & kEntClusterMask) * kCluster + (t & 7);
+                const double px = A.xs[slot], py = A.xs[cs + slot], pz = A.xs[2 * cs + slot];
+                const bool here = px == px;
+                s_x[t] = here ? px : 0.0;
+                s_y[t] = here ? py : 0.0;
+                s_z[t] = here ? pz : 0.0;
+                s_q[t] = here ? (int16_t)A.qs[slot] : kAbsentQ;
+            }
+        }
+        const bool act = cw < gr.ncl;                 // wave-uniform
+        const int I = gr.cl0 + cw;
+        const int64_t slot_i = (int64_t)I * kCluster + il;
+        int ai = -1, ti = 0, qi_n = 0, nr = 0;
+        double xi = 0.0, yi = 0.0, zi = 0.0;
+        if (act) {
+            ai = A.perm[slot_i];
+            nr = A.cl_nt[(int64_t)I * 2 + half];
             if (ai >= 0) {
                 xi = A.xs[slot_i]; yi = A.xs[cs + slot_i]; zi = A.xs[2 * cs + slot_i];
                 qi_n = A.qs[slot_i];
-                qi = kKe * (double)qi_n;
                 ti = A.ts[slot_i];
             }
-            const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
-            double Fx = 0.0, Fy = 0.0, Fz = 0.0, eacc = 0.0;
-            const int k = lane & 7;
-            for (int hh = 0; hh < 2; ++hh)
-            for (int t = 0, nt = 4 * A.cl_nt[(int64_t)I * 2 + hh]; t < nt; ++t) {
-                const uint32_t code =
-                    gbl(A.nb + (((int64_t)I * 2 + hh) * kCluster + il) * A.nb_cap_h)
-                        [(t >> 2) * 32 + k * 4 + (t & 3)];
-                const uint32_t idx = code & kCodeIdxMask;
-                if (idx == sentinel || ai < 0) continue;
-                const int64_t slot_j = slot_of_code(ent_g, idx);
-                const double xj = A.xs[slot_j], yj = A.xs[cs + slot_j], zj = A.xs[2 * cs + slot_j];
-                double dx, dy, dz, r2;
-                {
-#pragma clang fp contract(off)
-                    dx = xi - xj;
-                    dy = yi - yj;
-                    dz = zi - zj;
-                    if (gs.periodic) {
-                        dx = dx - gs.L[0] * rint(dx * gs.invL[0]);
-                        dy = dy - gs.L[1] * rint(dy * gs.invL[1]);
-                        dz = dz - gs.L[2] * rint(dz * gs.invL[2]);
+        }
+        // a fast i-atom (NaN position) takes no part: its force comes from the
+        // fast-atom kernels
+        const bool live = ai >= 0 && xi == xi;
+        if (!live) xi = yi = zi = 0.0;
+        __syncthreads();
+        double Fx = 0.0, Fy = 0.0, Fz = 0.0, eacc = 0.0;
+        if (act) {
+            const double qi = kKe * (double)qi_n;
+            const double2* c_row = s_c + ti * A.T;
+            // one row of 4 candidates: distances by the exact membership expression (the
+            // sentinel and padding i-atoms, at finite placeholder positions, are never
+            // inside), then the pair terms of all 4 without branches (a pair outside the
+            // cutoff is evaluated at r^2 = 1 and its terms dropped), so the 4 evaluations
+            // interleave.  ST: staged table; PER: periodic system (both uniform, fixed
+            // per loop, so no branch on them sits inside the row)
+            auto row = [&](uint64_t codes, auto st_c, auto per_c) {
+                constexpr bool ST = decltype(st_c)::value;
+                constexpr bool PER = decltype(per_c)::value;
+                uint32_t idx[4];
+                int tj[4], qj[4];
+                double dx[4], dy[4], dz[4], r2[4];
+                bool in[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t code = (uint32_t)(codes >> (16 * u)) & 0xFFFFu;
+                    idx[u] = code & kCodeIdxMask;
+                    tj[u] = (int)(code >> kCodeIdxBits);
+                    double xj, yj, zj;
+                    if constexpr (ST) {
+                        xj = s_x[idx[u]]; yj = s_y[idx[u]]; zj = s_z[idx[u]];
+                        qj[u] = s_q[idx[u]];
+                    } else {
+                        xj = yj = zj = 0.0;
+                        qj[u] = kAbsentQ;
+                        if (idx[u] != sentinel) {
+                            const int64_t slot_j = slot_of_code(ent_g, idx[u]);
+                            const double px = A.xs[slot_j];
+                            if (px == px) {
+                                xj = px; yj = A.xs[cs + slot_j]; zj = A.xs[2 * cs + slot_j];
+                                qj[u] = A.qs[slot_j];
+                            }
+                        }
                     }
-                    r2 = dx * dx + dy * dy;
-                    r2 = r2 + dz * dz;
+                    {
+#pragma clang fp contract(off)
+                        dx[u] = xi - xj;
+                        dy[u] = yi - yj;
+                        dz[u] = zi - zj;
+                        if (PER) {
+                            dx[u] = dx[u] - gs.L[0] * rint(dx[u] * gs.invL[0]);
+                            dy[u] = dy[u] - gs.L[1] * rint(dy[u] * gs.invL[1]);
+                            dz[u] = dz[u] - gs.L[2] * rint(dz[u] * gs.invL[2]);
+                        }
+                        r2[u] = dx[u] * dx[u] + dy[u] * dy[u];
+                        r2[u] = r2[u] + dz[u] * dz[u];
+                    }
+                    in[u] = live && qj[u] != kAbsentQ && r2[u] < A.rc2;
                 }
-                if (!(r2 < A.rc2)) continue;
-                if (EMIT)
-                    emit_pairs(true, ent_g, A.perm, ai, idx, &A.dsc->pair_count, A.emit,
-                               A.emit_max);
-                const int tj = (int)(code >> kCodeIdxBits);
-                double c6 = A.c6[ti * A.T + tj], c12 = A.c12[ti * A.T + tj];
-                if (QLJ) qlj_scale64(A.qlj, ti, tj, qi_n, A.qs[slot_j], &c6, &c12);
-                double f, e;
-                if (HYBRID) {
-                    pair_terms_hybrid64(r2, kap, qi_n, A.qs[slot_j], c6, c12, SCREEN_LJ, hrow,
-                                        A.hyb_q, &f, &e);
-                    Fx += f * dx;
-                    Fy += f * dy;
-                    Fz += f * dz;
-                    if (ENERGY) eacc += e;
-                    continue;
+                if (EMIT) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        emit_pairs(in[u], ent_g, A.perm, ai, in[u] ? idx[u] : 0u,
+                                   &A.dsc->pair_count, A.emit, A.emit_max);
                 }
-                const double r = sqrt(r2);
-                const double rinv2 = 1.0 / r2;
-                const double rinv6 = rinv2 * rinv2 * rinv2;
-                const double s = exp(-kap * r);
-                const double uc = qi * (double)A.qs[slot_j] / r;
-                const double l12 = c12 * rinv6 * rinv6, l6 = c6 * rinv6;
-                if (SCREEN_LJ) {
-                    const double uu = uc + (l12 - l6);
-                    f = ((uc + 12.0 * l12 - 6.0 * l6) + uu * (kap * r)) * s * rinv2;
-                    e = uu * s;
-                } else {
-                    f = (uc + uc * (kap * r)) * s * rinv2 + (12.0 * l12 - 6.0 * l6) * rinv2;
-                    e = uc * s + (l12 - l6);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double rr = in[u] ? r2[u] : 1.0;
+                    const int qq = (HYBRID || QLJ) && !in[u] ? 0 : qj[u];
+                    double c6 = c_row[tj[u]].x, c12 = c_row[tj[u]].y;
+                    if (QLJ) qlj_scale64(A.qlj, ti, tj[u], qi_n, qq, &c6, &c12);
+                    double f, e;
+                    if (HYBRID) {
+                        pair_terms_hybrid64(rr, kap, qi_n, qq, c6, c12, SCREEN_LJ, hrow,
+                                            A.hyb_q, &f, &e);
+                    } else {
+                        // 1/r from one reciprocal square root; r, 1/r^2, q_i q_j / r follow
+                        const double rinv = rsqrt(rr);
+                        const double r = rr * rinv;
+                        const double rinv2 = rinv * rinv;
+                        const double rinv6 = rinv2 * rinv2 * rinv2;
+                        const double s = exp(-kap * r);
+                        const double uc = qi * (double)qq * rinv;
+                        const double l12 = c12 * rinv6 * rinv6, l6 = c6 * rinv6;
+                        if (SCREEN_LJ) {
+                            const double uu = uc + (l12 - l6);
+                            f = ((uc + 12.0 * l12 - 6.0 * l6) + uu * (kap * r)) * s * rinv2;
+                            e = uu * s;
+                        } else {
+                            f = (uc + uc * (kap * r)) * s * rinv2 +
+                                (12.0 * l12 - 6.0 * l6) * rinv2;
+                            e = uc * s + (l12 - l6);
+                        }
+                    }
+                    // (finite separations: a dropped pair adds exact zeros)
+                    const double fi = in[u] ? f : 0.0;
+                    Fx += fi * dx[u];
+                    Fy += fi * dy[u];
+                    Fz += fi * dz[u];
+                    if (ENERGY) eacc += in[u] ? e : 0.0;
                 }
-                Fx += f * dx;
-                Fy += f * dy;
-                Fz += f * dz;
-                if (ENERGY) eacc += e;
+            };
+            // lane (i, k) takes codes 4k .. 4k + 3 of rows rp, rp + nrp, ... of atom i's
+            // half-list (one 8-byte load per row, the next one issued a row ahead)
+            nr = __builtin_amdgcn_readfirstlane(nr);
+            const auto cp = gbl(reinterpret_cast<const uint64_t*>(
+                                A.nb + (((int64_t)I * 2 + half) * kCluster + il) * A.nb_cap_h)) +
+                            k8;
+            auto rows = [&](auto st_c, auto per_c) {
+                uint64_t nxt = rp < nr ? (uint64_t)cp[rp * 8] : 0ull;
+                for (int r = rp; r < nr; r += nrp) {
+                    const uint64_t cur = nxt;
+                    if (r + nrp < nr) nxt = cp[(r + nrp) * 8];
+                    row(cur, st_c, per_c);
+                }
+            };
+            using T_ = std::true_type;
+            using F_ = std::false_type;
+            if (staged) {
+                if (gs.periodic) rows(T_{}, T_{});
+                else rows(T_{}, F_{});
+            } else {
+                if (gs.periodic) rows(F_{}, T_{});
+                else rows(F_{}, F_{});
             }
             Fx = reduce8(Fx);
             Fy = reduce8(Fy);
             Fz = reduce8(Fz);
-            if ((lane & 7) == 0 && ai >= 0) {
-                A.fx[ai] = Fx;
-                A.fy[ai] = Fy;
-                A.fz[ai] = Fz;
-            }
-            if (ENERGY) {
-                if (EMIT && A.e_atom) {
-                    const double ea = reduce8(eacc);
-                    if ((lane & 7) == 0 && ai >= 0) A.e_atom[ai] = 0.5 * ea;
-                }
-                for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
-                e_w = 0.5 * eacc;
-            }
+            if (ENERGY) eacc = reduce8(eacc);
         }
-        if (ENERGY) {
-            if (lane == 0) s_e[w] = e_w;
-            __syncthreads();
-            if (tid == 0) {
-                double t = 0.0;
-                for (int k = 0; k < nw; ++k) t += s_e[k];
-                A.grp_epot[g] = t;
-            }
+        // combine the waves of each cluster in a fixed order (deterministic)
+        if (k8 == 0) {
+            s_part[w][il][0] = Fx;
+            s_part[w][il][1] = Fy;
+            s_part[w][il][2] = Fz;
+            s_part[w][il][3] = eacc;
         }
         __syncthreads();
-        if (tid == 0) s_g = (int)(gridDim.x + atomicAdd(&A.dsc->work_force, 1u));
+        if (sub == 0 && k8 == 0 && ai >= 0) {
+            double F[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int h = 0; h < wpc; ++h)
+                for (int d = 0; d < 4; ++d) F[d] += s_part[w + h][il][d];
+            A.fx[ai] = F[0];
+            A.fy[ai] = F[1];
+            A.fz[ai] = F[2];
+            if (EMIT && ENERGY && A.e_atom) A.e_atom[ai] = 0.5 * F[3];
+        }
+        if (ENERGY && tid == 0) {
+            double t = 0.0;
+            for (int k = 0; k < nw; ++k)
+                for (int i = 0; i < kCluster; ++i) t += s_part[k][i][3];
+            A.grp_epot[g] = 0.5 * t;        // each pair is visited from both atoms
+        }
+        if (tid == 0) s_g = (int)(gridDim.x + claim);
         __syncthreads();
         g = s_g;
     }
@@ -867,6 +1009,19 @@ static void set_lds_attr(size_t lds)
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_h);
 }
 
+template <bool E, bool M, bool S>
+static void set_lds_attr64(size_t lds)
+{
+    (void)hipFuncSetAttribute((const void*)k_force64<E, M, S, false, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_force64<E, M, S, true, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_force64<E, M, S, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_force64<E, M, S, true, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 hipError_t force_kernel_setup(Ctx* c)
 {
     hipFuncAttributes fa;
@@ -882,7 +1037,32 @@ hipError_t force_kernel_setup(Ctx* c)
     set_lds_attr<true, true, false>(lds);   set_lds_attr<true, true, true>(lds);
     (void)hipFuncSetAttribute((const void*)k_force32<false, false, false, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // FP64 kernel: staged tables when they fit one work-group's LDS
+    if (hipFuncGetAttributes(&fa, (const void*)k_force64<true, true, true, true, true>) ==
+        hipSuccess)
+        c->force64_static_lds = fa.sharedSizeBytes;
+    const size_t lds64 = force64_lds_bytes(c->E_cap);
+    c->stage64 = lds64 + c->force64_static_lds <= c->max_lds;
+    if (c->stage64) {
+        set_lds_attr64<false, false, false>(lds64); set_lds_attr64<false, false, true>(lds64);
+        set_lds_attr64<true, false, false>(lds64);  set_lds_attr64<true, false, true>(lds64);
+        set_lds_attr64<false, true, false>(lds64);  set_lds_attr64<false, true, true>(lds64);
+        set_lds_attr64<true, true, false>(lds64);   set_lds_attr64<true, true, true>(lds64);
+    }
     return hipGetLastError();
+}
+
+// FP64 kernel launch shape: work-groups per CU as the LDS allows (at most 4), waves
+// per i-cluster (even, at least the two half-lists) for about 16 waves per CU, so
+// that one work-group's staging overlaps another's pair loop where two fit.
+static void force64_shape(const Ctx* c, int* per_cu, int* wpc)
+{
+    const size_t lds = (c->stage64 ? force64_lds_bytes(c->E_cap) : 0) + c->force64_static_lds;
+    const int p = (int)std::min<size_t>(4, std::max<size_t>(1, c->lds_per_cu / lds));
+    int w = std::max(2, (16 / (c->G * p)) & ~1);
+    w = std::min(w, kForce64Block / 64 / c->G);
+    *per_cu = std::max(1, std::min(p, 16 / (c->G * w)));
+    *wpc = w;
 }
 
 template <bool E, bool M, bool S, bool H, bool Q>
@@ -893,7 +1073,8 @@ static void launch_one(Ctx* c, md_precision prec, const ForceArgs& A, int blocks
                            dim3(64 * c->G * A.wpc), force32_lds_bytes(c->E_cap, H ? c->hyb_q : 0),
                            st, A);
     else
-        hipLaunchKernelGGL((k_force64<E, M, S, H, Q>), dim3(blocks), dim3(64 * c->G), 0, st, A);
+        hipLaunchKernelGGL((k_force64<E, M, S, H, Q>), dim3(blocks), dim3(64 * c->G * A.wpc),
+                           c->stage64 ? force64_lds_bytes(c->E_cap) : 0, st, A);
 }
 
 template <bool E, bool M, bool S>
@@ -932,7 +1113,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     A.fx = fx; A.fy = fy; A.fz = fz;
     A.grp_epot = c->d_grp_epot; A.epot = epot; A.sys_grp0 = c->d_sys_grp0; A.B = c->B;
     A.dsc = c->dsc; A.emit = emit; A.emit_max = emit_max;
-    A.wpc = kMaxWpc;
+    A.wpc = kMaxWpc; A.stage64 = 0;
     A.cl_len = c->d_cl_len; A.ent_mask = c->d_ent_mask; A.nb_cap_h = c->nb_cap_h;
     A.hyb32 = c->d_hyb32; A.hyb64 = c->d_hyb64; A.hyb_q = c->hyb_q;
     A.qlj = c->d_qlj;
@@ -951,16 +1132,18 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
         per_cu32 = (int)std::max<size_t>(1, c->lds_per_cu / lds);
         per_cu32 = std::min(per_cu32, std::max(1, 32 / (c->G * A.wpc)));
     }
-    const int per_cu = prec == MD_FP32_KAHAN ? per_cu32 : std::max(1, 16 / c->G);
-    const int blocks = (int)std::max<int64_t>(
-        1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu));
+    int per_cu = per_cu32;
     if (prec == MD_FP64) {
         // the FP32 kernel's list builder, alone (the FP32 force kernel builds its own)
         const int lb = (int)std::max<int64_t>(
             1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu32));
         hipLaunchKernelGGL((k_force32<false, false, false, true>), dim3(lb),
                            dim3(64 * c->G * A.wpc), force32_lds_bytes(c->E_cap), st, A);
+        force64_shape(c, &per_cu, &A.wpc);
+        A.stage64 = c->stage64 ? 1 : 0;
     }
+    const int blocks = (int)std::max<int64_t>(
+        1, std::min<int64_t>(c->cap_groups, (int64_t)c->n_cu * per_cu));
     const bool E = epot != nullptr, M = emit != nullptr, S = c->cfg.screen_lj != 0;
     if (ev0) {
         const hipError_t e = hipEventRecord(ev0, st);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "md.h"
@@ -89,6 +90,8 @@ struct Ctx {
     // step, charge) the coefficients {r', c1, c2, c3}
     bool hybrid = false;
     size_t force32_static_lds_h = 0;   // static LDS of the hybrid FP32 force kernel
+    size_t force64_static_lds = 0;     // static LDS of the FP64 force kernel
+    bool stage64 = false;              // FP64 kernel: group tables fit the LDS
     int32_t hyb_q = 0;             // charges tabulated (0 .. hyb_q - 1)
     double* d_hyb64 = nullptr;     // B*(S+1)*hyb_q*4
     float4* d_hyb32 = nullptr;     // B*(S+1)*hyb_q
