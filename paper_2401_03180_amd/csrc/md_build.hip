@@ -955,7 +955,7 @@ __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs 
     // writes, after several grid barriers; the binning of a rebuild may clear the fast
     // flags while another work-group's repack still reads them, which only changes
     // values that are rewritten)
-    if (!S.force && !pending) repack_range(S.rp, gid, gstride, false);
+    if (!S.force && !pending) repack_range<4>(S.rp, gid, gstride, false);
     int cnt = 0;
     for (int k = threadIdx.x; k < S.join.nblocks; k += blockDim.x) cnt += S.join.fast_cnt[k];
     const int total = block_sum_all(cnt, s_i);
@@ -993,7 +993,7 @@ __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs 
     if (!grid_barrier(gb, d)) return;
     // candidate tables and the slot repack read disjoint data: no barrier between
     ph_group_entries(S.en, s_dyn, bid, nblk);
-    repack_range(S.rp, gid, gstride, false);
+    repack_range<4>(S.rp, gid, gstride, false);
     if (bid == 0 && threadIdx.x == 0) ph_build_done(d);
 }
 

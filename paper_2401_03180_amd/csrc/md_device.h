@@ -305,6 +305,9 @@ struct RepackArgs {
 };
 
 // check_skin: latch MD_FLAG_SKIN when a rebuild is still pending (stale lists).
+// U slots per thread and pass, each step's loads issued for all U together (the
+// gathers through the permutation are latency-bound where few threads run).
+template <int U>
 __device__ inline void repack_range(const RepackArgs& A, int64_t gtid, int64_t gstride,
                                     bool check_skin)
 {
@@ -313,31 +316,47 @@ __device__ inline void repack_range(const RepackArgs& A, int64_t gtid, int64_t g
         A.dsc->work_force = 0u;
         if (check_skin && A.dsc->need_rebuild) atomicOr(&A.dsc->flags, MD_FLAG_SKIN);
     }
-    for (int64_t s = gtid; s < n; s += gstride) {
-        const int a = A.perm[s];
-        if (a >= 0 && !A.fast_flag[a]) {
-            const double p[3] = {A.x[a], A.y[a], A.z[a]};
-            const int8_t qa = A.q[a];
-            A.xs[s] = p[0];
-            A.xs[A.cap_slots + s] = p[1];
-            A.xs[2 * A.cap_slots + s] = p[2];
-            A.qs[s] = qa;
-            const GridSys& g = A.grid[A.B == 1 ? 0 : A.sys_of_atom[a]];
-            const int32_t im = A.slot_img[s];
-            const double* lo = A.cl_lo + (s / kCluster) * 3;
-            float o[3];
-            for (int d = 0; d < 3; ++d) {
-                const double w = g.periodic ? p[d] - (double)unpack_img(im, d) * g.L[d] : p[d];
-                o[d] = (float)(w - lo[d]);
+    for (int64_t s0 = gtid; s0 < n; s0 += U * gstride) {
+        int a[U];
+        bool live[U];
+        double p[U][3];
+        int8_t qa[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t s = s0 + u * gstride;
+            a[u] = s < n ? A.perm[s] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            live[u] = a[u] >= 0 && !A.fast_flag[a[u]];
+            qa[u] = a[u] >= 0 ? A.q[a[u]] : (int8_t)0;
+            p[u][0] = live[u] ? A.x[a[u]] : NAN;
+            p[u][1] = live[u] ? A.y[a[u]] : NAN;
+            p[u][2] = live[u] ? A.z[a[u]] : NAN;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t s = s0 + u * gstride;
+            if (s >= n) break;
+            A.xs[s] = p[u][0];
+            A.xs[A.cap_slots + s] = p[u][1];
+            A.xs[2 * A.cap_slots + s] = p[u][2];
+            A.qs[s] = qa[u];
+            if (live[u]) {
+                const GridSys& g = A.grid[A.B == 1 ? 0 : A.sys_of_atom[a[u]]];
+                const int32_t im = A.slot_img[s];
+                const double* lo = A.cl_lo + (s / kCluster) * 3;
+                float o[3];
+                for (int d = 0; d < 3; ++d) {
+                    const double w =
+                        g.periodic ? p[u][d] - (double)unpack_img(im, d) * g.L[d] : p[u][d];
+                    o[d] = (float)(w - lo[d]);
+                }
+                A.xo[s] = make_float4(o[0], o[1], o[2], (float)qa[u]);
+            } else {
+                // x alone marks the slot empty (the force kernel's staging tests it)
+                A.xo[s] = make_float4(NAN, 0.0f, 0.0f, (float)qa[u]);
             }
-            A.xo[s] = make_float4(o[0], o[1], o[2], (float)qa);
-        } else {
-            A.xs[s] = NAN;
-            A.xs[A.cap_slots + s] = NAN;
-            A.xs[2 * A.cap_slots + s] = NAN;
-            A.qs[s] = a >= 0 ? A.q[a] : 0;
-            // x alone marks the slot empty (the force kernel's staging tests it)
-            A.xo[s] = make_float4(NAN, 0.0f, 0.0f, a >= 0 ? (float)A.q[a] : 0.0f);
         }
     }
 }
@@ -368,8 +387,29 @@ __device__ inline void force_finalize_block(const ForceFinalizeArgs& F)
         const int nw = blockDim.x >> 6;
         for (int b = 0; b < F.B; ++b) {
             const int g0 = F.sys_grp0[b], g1 = F.sys_grp0[b + 1];
-            double t = 0.0;
-            for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) t += F.grp_epot[g];
+            // the group energies in passes of 16 per thread (16 loads in flight
+            // together) into 16 partial sums, then the rest one at a time; combined
+            // in a fixed order
+            constexpr int U = 16;
+            double tu[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) tu[u] = 0.0;
+            const int nt = blockDim.x;
+            int g = g0 + threadIdx.x;
+            for (; g + (U - 1) * nt < g1; g += U * nt) {
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = F.grp_epot[g + u * nt];
+#pragma unroll
+                for (int u = 0; u < U; ++u) tu[u] += v[u];
+            }
+            double rest = 0.0;
+            for (; g < g1; g += nt) rest += F.grp_epot[g];
+#pragma unroll
+            for (int w = U / 2; w > 0; w >>= 1)
+#pragma unroll
+                for (int u = 0; u < w; ++u) tu[u] += tu[u + w];
+            double t = tu[0] + rest;
             const int64_t a0 = F.sys_off[b], a1 = F.sys_off[b + 1];
             for (int k = threadIdx.x; k < nf; k += blockDim.x) {
                 const int f = F.fast_list[k];

@@ -45,7 +45,7 @@ constexpr int kForceBlockMax = 64 * kMaxGroup * kMaxWpc;
 // them and their pairs are evaluated by the fast-atom kernels.
 __global__ void __launch_bounds__(256) k_repack(RepackArgs A)
 {
-    repack_range(A, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+    repack_range<1>(A, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
                  (int64_t)gridDim.x * blockDim.x, true);
 }
 

@@ -303,21 +303,39 @@ __device__ void ekin_from_slots(const VvArgs& A, double* s_red)
         double t = 0.0;
         if (s1 > s0) {
             const int64_t k0 = s0 / kVvBlock, k1 = (s1 - 1) / kVvBlock;
-            for (int64_t k = k0 + threadIdx.x; k <= k1; k += kVvBlock) {
-                unsigned long long* w = A.ek_slots + k + b;
-                unsigned long long v;
-                unsigned spins = 0;
-                while ((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ==
-                       kEkSlotEmpty) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > (1u << 22)) {
-                        atomicOr(&A.dsc->flags, MD_FLAG_BARRIER);
-                        v = 0ull;
-                        break;
-                    }
+            // 16 words per thread read together (whole passes; the rest one at a
+            // time), then each one waited for in turn and added in the same order as
+            // one at a time
+            constexpr int U = 16;
+            for (int64_t kb = k0 + threadIdx.x; kb <= k1; kb += U * kVvBlock) {
+                const int nu = kb + (U - 1) * kVvBlock <= k1 ? U : 1;
+                unsigned long long v[U];
+                if (nu == U) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        v[u] = __hip_atomic_load(A.ek_slots + kb + u * kVvBlock + b,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                t += __longlong_as_double((long long)v);
-                __hip_atomic_store(w, kEkSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = kb + u * kVvBlock;
+                    if (k > k1) break;
+                    unsigned long long* w = A.ek_slots + k + b;
+                    if (nu != U)
+                        v[u] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    unsigned spins = 0;
+                    while (v[u] == kEkSlotEmpty) {
+                        __builtin_amdgcn_s_sleep(2);
+                        v[u] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (++spins > (1u << 22)) {
+                            atomicOr(&A.dsc->flags, MD_FLAG_BARRIER);
+                            v[u] = 0ull;
+                            break;
+                        }
+                    }
+                    t += __longlong_as_double((long long)v[u]);
+                    __hip_atomic_store(w, kEkSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
         t = block_sum_d(t, s_red);
@@ -327,7 +345,7 @@ __device__ void ekin_from_slots(const VvArgs& A, double* s_red)
 
 // IONIZE (phase 0 only): also the ionization of the step this phase starts (the
 // step counter is advanced after this kernel), as md_step issues it.  FIN (phase 1
-// only): one extra work-group runs the force finalize of the step.  LANGEVIN (phase
+// only): one extra work-group (the first) runs the force finalize of the step.  LANGEVIN (phase
 // 0 only): the drift is split around the exact friction + noise velocity update.
 template <int PHASE, bool EKIN, bool IONIZE = false, bool FIN = false, bool LANGEVIN = false>
 __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinalizeArgs F,
@@ -335,12 +353,15 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinal
 {
 #pragma clang fp contract(off)
     __shared__ double s_red[kVvBlock / 64];
-    if (FIN && blockIdx.x == gridDim.x - 1) {
+    // FIN: work-group 0 (dispatched first) sums the group energies while the others
+    // integrate, then waits for their kinetic-energy words; the others take the atoms
+    if (FIN && blockIdx.x == 0) {
         force_finalize_block(F);
         if (EKIN && A.ek_slots) ekin_from_slots(A, s_red);
         return;
     }
-    const int64_t a = blockIdx.x * (int64_t)kVvBlock + threadIdx.x;
+    const int bi = FIN ? (int)blockIdx.x - 1 : (int)blockIdx.x;   // atom block
+    const int64_t a = bi * (int64_t)kVvBlock + threadIdx.x;
     double d2 = 0.0, ke = 0.0;
     if (IONIZE && a < A.N) {
         const int64_t s = A.dsc->step + 1;
@@ -403,18 +424,18 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinal
         __syncthreads();
         int pos = __popcll(bal & ((1ull << lane) - 1ull));
         for (int k = 0; k < wv; ++k) pos += s_n[k];
-        if (fast) A.fast_loc[(int64_t)blockIdx.x * kVvBlock + pos] = (int32_t)a;
+        if (fast) A.fast_loc[(int64_t)bi * kVvBlock + pos] = (int32_t)a;
         if (threadIdx.x == 0) {
             double m = s_red[0];
             int n = s_n[0];
             for (int k = 1; k < kVvBlock / 64; ++k) { m = fmax(m, s_red[k]); n += s_n[k]; }
-            A.disp_partial[blockIdx.x] = m;
-            A.fast_cnt[blockIdx.x] = n;
+            A.disp_partial[bi] = m;
+            A.fast_cnt[bi] = n;
         }
     }
     if (PHASE == 1 && EKIN) {
         // per-system partial of this block, stored at index block + system
-        const int64_t a0 = (int64_t)blockIdx.x * kVvBlock;
+        const int64_t a0 = (int64_t)bi * kVvBlock;
         const int64_t a1 = min(A.N, a0 + kVvBlock) - 1;
         const int b0 = A.sys_of_atom[a0], b1 = A.sys_of_atom[a1];
         const int myb = a < A.N ? A.sys_of_atom[a] : -1;
@@ -426,10 +447,10 @@ __global__ void __launch_bounds__(kVvBlock) k_vv(VvArgs A, IonArgs I, ForceFinal
                     // hence no release fence (an L2 write-back) per work-group
                     unsigned long long v = (unsigned long long)__double_as_longlong(t);
                     if (v == kEkSlotEmpty) v = 0x7FF8000000000000ull;
-                    __hip_atomic_store(A.ek_slots + blockIdx.x + b, v, __ATOMIC_RELAXED,
+                    __hip_atomic_store(A.ek_slots + bi + b, v, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                 } else {
-                    A.partial[blockIdx.x + b] = t;
+                    A.partial[bi + b] = t;
                 }
             }
         }
