@@ -250,8 +250,10 @@ static md_status size_and_allocate(Ctx* c)
         const double V = X * Y * Z + 2.0 * rl * (X * Y + X * Z + Y * Z) +
                          M_PI * rl * rl * (X + Y + Z) + 4.0 / 3.0 * M_PI * rl * rl * rl;
         // vacuum grids follow each system's bounding box, whose columns widen as a
-        // cluster expands (ions leaving it stretch the box): more headroom there
-        const double safety = cfg.periodic ? 1.35 : 2.4;
+        // cluster expands (ions leaving it stretch the box): more headroom there.  A
+        // group of 8 clusters often spans two columns: on a periodic water box its
+        // table reached 1.37 times the box volume's count (groups of 4: 1.25)
+        const double safety = cfg.periodic ? (G >= 8 ? 1.75 : 1.35) : 2.4;
         const int est = (int)(V * rho / kCluster * safety) + 16;
         E_cap = std::min(est, kMaxGroupEntries);
         while (E_cap > 32 &&

@@ -954,8 +954,10 @@ __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs 
     // runs first, before the decision is known (a rebuild rewrites everything it
     // writes, after several grid barriers; the binning of a rebuild may clear the fast
     // flags while another work-group's repack still reads them, which only changes
-    // values that are rewritten)
-    if (!S.force && !pending) repack_range<4>(S.rp, gid, gstride, false);
+    // values that are rewritten).  The last work-group joins the fast-atom lists
+    // instead (when there are others).
+    if (!S.force && !pending && (nblk == 1 || bid < nblk - 1))
+        repack_range<4>(S.rp, gid, (int64_t)(nblk > 1 ? nblk - 1 : 1) * blockDim.x, false);
     int cnt = 0;
     for (int k = threadIdx.x; k < S.join.nblocks; k += blockDim.x) cnt += S.join.fast_cnt[k];
     const int total = block_sum_all(cnt, s_i);
@@ -964,8 +966,6 @@ __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs 
     // barrier, so all blocks read the same starting value here
     GridBarrier gb{S.bar_arrive, &d->bar_gen, (unsigned)nblk,
                    __hip_atomic_load(&d->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
-    // the last block (which holds no repack slots unless the slots outnumber the
-    // grid's threads) joins the fast-atom lists
     if (bid == nblk - 1) fast_join_block(S.join);
     if (!rebuild) return;
     if (!S.periodic) {
