@@ -72,8 +72,11 @@ STATE = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q")
 
 def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_graph=True,
             fast_capacity=0, langevin=None, hybrid=None, ff=None, schedule_steps=0,
-            subbox=None):
-    """The workload's schedule from step 0 (initial build and forces), `warmup`
+            subbox=None, preroll_max=0):
+    """The workload's schedule from step 0 (initial build and forces), up to its
+    first automatic list rebuild when preroll_max > 0 (at most that many steps: the
+    start from a lattice needs none for tens of steps, so a short window right after
+    step 0 would hold none of the rebuilds of the rest of the schedule), `warmup`
     steps, then `steps` timed steps: replays of the captured step graph (or, with
     use_graph False, eager md_step calls), inputs resident, no build forced in
     between.  Then the same run is repeated from the initial state with the timed
@@ -116,6 +119,15 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
             one_step = lambda: md.md_graph_launch(graph, stream)
         else:
             one_step = lambda: eng.step(md.MD_BUILD_AUTO, energy=True, ekin=True, stream=stream)
+        n_pre = 0
+        if preroll_max > 0:
+            b0 = eng.stats(stream)["n_builds"]
+            while n_pre < preroll_max:
+                one_step()
+                n_pre += 1
+                stream.synchronize()
+                if eng.stats(stream)["n_builds"] > b0:
+                    break
         for _ in range(warmup):
             one_step()
         stream.synchronize()
@@ -138,7 +150,7 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
 
         # the same run again, the timed steps eager with the force-kernel timer
         restart()
-        for _ in range(warmup):
+        for _ in range(n_pre + warmup):
             one_step()
         stream.synchronize()
         st2 = eng.stats(stream)
@@ -157,8 +169,10 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
         eng.timer_start(0)
 
         if schedule_steps > 0:
-            # the whole schedule, initial build and forces included
+            # the whole schedule, initial build and forces included (rebuilds: the
+            # automatic ones during its steps)
             torch.cuda.synchronize()
+            b0 = eng.stats(stream)["n_builds"] + 1
             for n in STATE:
                 getattr(eng, n).copy_(init[n])
             stream.synchronize()
@@ -175,7 +189,7 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
             st4 = eng.stats(stream)
             out.update(schedule_steps=schedule_steps,
                        schedule_ms_per_step=e0.elapsed_time(e1) / schedule_steps,
-                       schedule_rebuilds=int(st4["n_builds"]),
+                       schedule_rebuilds=int(st4["n_builds"] - b0),
                        schedule_flags=eng.sync_check(stream, raise_on_flags=False))
         if subbox is not None:
             out["subbox"] = subbox_errors(eng, subbox, stream)
@@ -187,7 +201,7 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
                 "pairs_min": int(min(pairs)), "pairs_max": int(max(pairs)),
                 "kernel_ms": float(d.mean()), "kernel_ms_median": float(np.median(d)),
                 "kernel_ms_p90": float(np.percentile(d, 90)), "kernel_launches": int(d.size),
-                "builds": builds, "builds_replay": builds_replay,
+                "builds": builds, "builds_replay": builds_replay, "preroll_steps": n_pre,
                 "replay_identical": bool(same and builds == builds_replay), "stats": st1,
                 "step": step_end, "charged_fraction": float((final["q"] > 0).float().mean())})
     return out
@@ -459,7 +473,7 @@ def traffic_from_profile(config):
 
 def run_schedule(sys_, prec, knobs, steps=None):
     """The workload's whole schedule (initial build and forces, then every step as a
-    graph replay), timed with HIP events: ms per step, rebuilds, flags."""
+    graph replay), timed with HIP events: ms per step, automatic rebuilds, flags."""
     import torch
     from paper_2401_03180_amd import md
     steps = sys_.n_steps if steps is None else steps
@@ -474,6 +488,7 @@ def run_schedule(sys_, prec, knobs, steps=None):
         for n in STATE:
             getattr(eng, n).copy_(init[n])
         torch.cuda.synchronize()
+        b0 = eng.stats(stream)["n_builds"] + 1     # + the forced build below
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -490,7 +505,7 @@ def run_schedule(sys_, prec, knobs, steps=None):
     eng.close()
     ms = e0.elapsed_time(e1) / steps
     return {"steps": steps, "ms_per_step": ms, "value": sys_.n_atoms / (ms * 1e-3),
-            "rebuilds": int(st["n_builds"]), "flags": flags, "charged_fraction": charged}
+            "rebuilds": int(st["n_builds"] - b0), "flags": flags, "charged_fraction": charged}
 
 
 def host_cores():
@@ -560,7 +575,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    S = a.warmup + a.steps
+    PREROLL = 64          # most steps run before the timed window (to the first rebuild)
+    S = a.warmup + a.steps + PREROLL
     from paper_2401_03180_amd import autotune
 
     def knobs(config, prec, steps=a.steps, warmup=a.warmup, cli=True):
@@ -601,15 +617,17 @@ def main():
         sb = subbox_rows(sys32)
     k32 = knobs(a.config, md.MD_FP32_KAHAN)
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
-    sched = sys32.n_steps if sys32.n_systems == 1 and not a.no_schedule else 0
+    sched = (min(sys32.n_steps, SCHEDULE[a.config])
+             if sys32.n_systems == 1 and not a.no_schedule else 0)
     r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
                   use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg,
-                  hybrid=hy, ff=ffb, schedule_steps=sched, subbox=sb)
+                  hybrid=hy, ff=ffb, schedule_steps=sched, subbox=sb, preroll_max=PREROLL)
     log("fp32", {k: v for k, v in r32.items() if k != "stats"})
     n = sys32.n_atoms
     value = n * a.steps / (r32["ms"] * 1e-3)
     st = r32["stats"]
     extra = {"flags": r32["flags"], "rebuilds_timed": r32["builds"],
+             "preroll_steps": r32["preroll_steps"],
              "replay_identical": r32["replay_identical"],
              "charged_fraction_end": r32["charged_fraction"],
              "pairs_in_cutoff_mean": r32["pairs"], "pairs_min": r32["pairs_min"],
@@ -650,7 +668,7 @@ def main():
             k64 = knobs(a.config, md.MD_FP64)
             r64 = run_gpu(sys64, md.MD_FP64, a.steps, a.warmup, k64["cluster_group"], k64["skin"],
                           use_graph=not a.eager, fast_capacity=k64["fast_capacity"], langevin=lg,
-                          hybrid=hy, ff=ffb64)
+                          hybrid=hy, ff=ffb64, preroll_max=PREROLL)
             log("fp64", {k: v for k, v in r64.items() if k != "stats"})
             v64 = n * a.steps / (r64["ms"] * 1e-3)
             extra.update({"fp64_value": v64, "fp64_ms_per_step": r64["ms"] / a.steps,
@@ -659,6 +677,7 @@ def main():
                           "fp64_force_tflops": FLOP_PER_PAIR * r64["pairs"] /
                           (r64["kernel_ms"] * 1e-3) / 1e12,
                           "fp64_flags": r64["flags"], "fp64_rebuilds_timed": r64["builds"],
+                          "fp64_preroll_steps": r64["preroll_steps"],
                           "fp64_replay_identical": r64["replay_identical"], "fp64_launch": k64})
         del sys64
     if not a.no_legs and plain:
@@ -674,12 +693,13 @@ def main():
         if a.config != "methane_256":
             # 256 batched clusters against the plain FP64 form, one system per launch
             s4 = make_system("methane_256", 0)
-            r4 = run_gpu(s4.copy(), md.MD_FP32_KAHAN, a.steps, a.warmup, 0, None,
-                         pair_samples=2, fast_capacity=0)
+            k4 = knobs("methane_256", md.MD_FP32_KAHAN, cli=False)
+            r4 = run_gpu(s4.copy(), md.MD_FP32_KAHAN, a.steps, a.warmup, k4["cluster_group"],
+                         k4["skin"], pair_samples=2, fast_capacity=k4["fast_capacity"])
             r4p = run_gpu_per_system(s4.copy(), md.MD_FP64, a.steps, a.warmup)
             v4 = s4.n_atoms * a.steps / (r4["ms"] * 1e-3)
             v4p = s4.n_atoms * a.steps / (r4p["ms"] * 1e-3)
-            legs["methane_256"] = {"atoms": s4.n_atoms, "systems": s4.n_systems,
+            legs["methane_256"] = {"atoms": s4.n_atoms, "systems": s4.n_systems, "launch": k4,
                                    "batched_fp32_ms_per_step": r4["ms"] / a.steps,
                                    "batched_fp32_value": v4,
                                    "batched_force_kernel_ms": r4["kernel_ms"],
