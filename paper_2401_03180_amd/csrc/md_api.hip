@@ -252,8 +252,9 @@ static md_status size_and_allocate(Ctx* c)
         // vacuum grids follow each system's bounding box, whose columns widen as a
         // cluster expands (ions leaving it stretch the box): more headroom there.  A
         // group of 8 clusters often spans two columns: on a periodic water box its
-        // table reached 1.37 times the box volume's count (groups of 4: 1.25)
-        const double safety = cfg.periodic ? (G >= 8 ? 1.75 : 1.35) : 2.4;
+        // table reached 1.4 times the box volume's count (groups of 4: 1.25); more
+        // headroom would pass the 1,023 entries a list code can index
+        const double safety = cfg.periodic ? (G >= 8 ? 1.6 : 1.35) : 2.4;
         const int est = (int)(V * rho / kCluster * safety) + 16;
         E_cap = std::min(est, kMaxGroupEntries);
         while (E_cap > 32 &&

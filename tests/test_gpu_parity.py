@@ -622,3 +622,19 @@ def test_graph_step_kinetic_energy_every_replay():
                 assert np.allclose(eng.host("ekin"), ek, rtol=1e-12, atol=0.0), rep
         assert eng.sync_check(raise_on_flags=False) == 0
         eng.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_water_large_groups_of_eight_no_overflow(prec):
+    """4,194,304-atom water box with 8 i-clusters per group, skin 0.09 nm: a group of 8
+    often spans two columns, and its candidate table must not fill its capacity over
+    130 graph-replayed steps (it did, latching MD_FLAG_LIST_OVERFLOW, with the headroom
+    of groups of 4); sampled forces against the oracle at the end.  In FP64 the table
+    of a group of 8 exceeds one work-group's LDS, so this is also the FP64 kernel's
+    path that reads the candidates from global memory."""
+    s = synth.water_large(n_steps=130)
+    say("water_4194304 G=8 skin 0.09 130 steps prec", prec)
+    st = _graph_steps_then_sample(s, prec, 130, 100, 61 + prec, cluster_group=8, skin=0.09,
+                                  fast_capacity=1024)
+    assert st["cluster_group"] == 8
+    assert st["max_group_entries"] < st["group_entry_capacity"]

@@ -92,3 +92,25 @@ def test_molecular_topology(kind, per, nh):
     assert np.all(s.elem[a[:, 1]] == 0) and np.all(s.elem[a[:, [0, 2]]] == 1)
     assert d["excl"].shape[0] == b.shape[0] + a.shape[0]
     assert np.all(d["c6"] > 0) and np.all(d["c6"] == d["c6"].T)
+
+
+def test_tuned_cache_covers_every_benchmark_leg():
+    """The launch-configuration cache holds an entry for each workload the benchmark
+    times (the 4.19 M-atom box in both precisions, the pulse box, the protein crystal,
+    the batched methane clusters), each within the library's accepted ranges."""
+    import json
+    from paper_2401_03180_amd import autotune
+    data = json.load(open(autotune.CACHE))
+    need = ["gfx950|water_4194304|prec0", "gfx950|water_4194304|prec1",
+            "gfx950|water_98304|prec1", "gfx950|protein_524288|prec1",
+            "gfx950|methane_256|prec1"]
+    for key in need:
+        assert key in data, key
+    for key, e in data.items():
+        assert e["cluster_group"] in (1, 2, 4, 8), key
+        assert 0.0 < e["skin"] < 0.5, key
+        assert 0 <= e["fast_capacity"] <= 65536, key
+        assert e["ms_per_step"] > 0.0, key
+        # the chosen configuration is the fastest trial of its search
+        best = min(t["ms_per_step"] for t in e.get("trials", [e]))
+        assert e["ms_per_step"] <= best + 1e-9, key
