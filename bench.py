@@ -83,8 +83,8 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
     steps launched eagerly and the force-kernel timer on: the trajectory is
     deterministic, so the repetition launches exactly the kernels of the timed
     region (checked: identical final state and rebuild count) and gives the
-    duration of every force-kernel launch.  Pair counts are sampled between steps
-    of the repetition.  schedule_steps > 0: the whole schedule (initial build,
+    duration of every force-kernel launch.  A third run samples the pair counts
+    between its steps (checked: identical final state).  schedule_steps > 0: the whole schedule (initial build,
     forces and that many graph steps) is timed once more from the initial state.
     subbox: the oracle rows of the error report (see subbox_errors), evaluated at
     the final state after a build at its positions.  langevin: (gamma, kt) tables
@@ -155,18 +155,28 @@ def run_gpu(sys_, prec, steps, warmup, cluster_group, skin, pair_samples=5, use_
         stream.synchronize()
         st2 = eng.stats(stream)
         eng.timer_start(steps)
-        sample_at = set(int(v) for v in np.linspace(1, steps, pair_samples))
-        pairs = []
         for i in range(1, steps + 1):
             eng.step(md.MD_BUILD_AUTO, energy=True, ekin=True, stream=stream)
-            if i in sample_at:
-                stream.synchronize()
-                pairs.append(eng.count_pairs(prec=prec, stream=stream))
         durations = eng.timer_read()
         stream.synchronize()
         st3 = eng.stats(stream)
         same = all(torch.equal(getattr(eng, n), final[n]) for n in STATE)
         eng.timer_start(0)
+
+        # and once more, the pair counts sampled between the steps (a count-only
+        # export takes longer than a step: kept out of both timed runs)
+        restart()
+        for _ in range(n_pre + warmup):
+            one_step()
+        sample_at = set(int(v) for v in np.linspace(1, steps, pair_samples))
+        pairs = []
+        for i in range(1, steps + 1):
+            one_step()
+            if i in sample_at:
+                stream.synchronize()
+                pairs.append(eng.count_pairs(prec=prec, stream=stream))
+        stream.synchronize()
+        same = same and all(torch.equal(getattr(eng, n), final[n]) for n in STATE)
 
         if schedule_steps > 0:
             # the whole schedule, initial build and forces included (rebuilds: the
@@ -455,20 +465,27 @@ def kernel_source_sha1():
     return hashlib.sha1(src).hexdigest()
 
 
-def traffic_from_profile(config):
-    """HBM bytes per force launch from the committed rocprofv3 counter summary of the
-    workload, if it was taken on the current force-kernel source; else None."""
+def profile_values(config):
+    """The key: value lines of the committed rocprofv3 counter summary of the FP32 force
+    kernel on the workload, if it was taken on the current force-kernel source; else
+    an empty dict."""
     path = os.path.join(ROOT, "profiles", "force32_%s_counters.txt" % config)
     if not os.path.exists(path):
-        return None
+        return {}
     kv = {}
     for line in open(path):
         if ":" in line and not line.startswith((" ", "|", "#")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha1") != kernel_source_sha1():
-        return None
-    return float(kv["hbm_bytes_per_launch"])
+        return {}
+    return kv
+
+
+def traffic_from_profile(config):
+    """HBM bytes per force launch from the committed counter summary, or None."""
+    kv = profile_values(config)
+    return float(kv["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in kv else None
 
 
 def run_schedule(sys_, prec, knobs, steps=None):
@@ -636,6 +653,8 @@ def main():
              "force_kernel_ms_p90": r32["kernel_ms_p90"],
              "list_codes": st["n_list_codes"],
              "codes_per_pair": st["n_list_codes"] / max(r32["pairs"], 1.0),
+             # in-cutoff pair visits (each pair from both atoms) per list code slot
+             "pair_efficiency": 2.0 * r32["pairs"] / max(st["n_list_codes"], 1),
              "groups": st["n_groups"], "cluster_group": st["cluster_group"],
              "max_group_entries": st["max_group_entries"],
              "group_entry_capacity": st["group_entry_capacity"],
@@ -731,6 +750,11 @@ def main():
                 "algorithmic_flop_per_launch": fpp * r32["pairs"],
                 "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS}
 
+    kv = profile_values(a.config) if plain else {}
+    if "valu_issue_per_cu_cycle" in kv:
+        # from the committed counter summary (launches with current lists)
+        extra.update(valu_issue_per_cu_cycle=float(kv["valu_issue_per_cu_cycle"]),
+                     valu_lane_instructions_per_code=float(kv["valu_lane_instructions_per_code"]))
     out = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": r32["ms"] / a.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
