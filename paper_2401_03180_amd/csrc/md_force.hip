@@ -11,7 +11,7 @@
 //   * each 64-lane wave owns one 8-atom i-cluster: lane = 8 * i + k walks codes
 //     k, k+8, ... of atom i's compacted list, so all 64 lanes evaluate distinct
 //     pairs; the 8 partial sums of an atom are combined at the end.
-// FP32 path: pair arithmetic in FP32; per-lane sums in FP32 over chunks of 8 terms,
+// FP32 path: pair arithmetic in FP32; per-lane sums in FP32 over chunks of 16 terms,
 // folded into a Kahan (sum, compensation) pair; cross-lane combination and the
 // output in FP64.  Membership uses an FP32 distance whose rounding error is
 // bounded; pairs inside the error band are re-decided with the FP64 expression,
@@ -692,7 +692,7 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
                 v0 = v1;
                 if (r + 2 < nr) v1 = cp[(r + 2) * 8];
                 row(cur);
-                if (r & 1) {      // fold every 8 terms into the compensated sums
+                if ((r & 3) == 3) {      // fold every 16 terms into the compensated sums
                     kahan_add(sx, cx, ax); kahan_add(sy, cy, ay); kahan_add(sz, cz, az);
                     if (ENERGY) eacc += (double)ea;
                     ax = ay = az = ea = 0.0f;
