@@ -800,16 +800,38 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
         const uint32_t* ent_g = A.ent + (int64_t)g * A.E_cap;
         const int nent = gr.nent;
         // ---- stage: candidate t = 8 e + k is atom k of entry e's cluster (consecutive
-        //      threads read consecutive slots)
+        //      threads read consecutive slots); four candidates per thread and pass,
+        //      each step's loads issued for all four together (candidates past the end
+        //      load the last one and store nothing)
         if (staged) {
-            for (int t = tid; t < nent * kCluster; t += blockDim.x) {
-                const int64_t slot = (int64_t)(ent_g[t >> 3] & kEntClusterMask) * kCluster + (t & 7);
-                const double px = A.xs[slot], py = A.xs[cs + slot], pz = A.xs[2 * cs + slot];
-                const bool here = px == px;
-                s_x[t] = here ? px : 0.0;
-                s_y[t] = here ? py : 0.0;
-                s_z[t] = here ? pz : 0.0;
-                s_q[t] = here ? (int16_t)A.qs[slot] : kAbsentQ;
+            const int nst = nent * kCluster;
+            for (int t0 = tid; t0 < nst; t0 += 4 * (int)blockDim.x) {
+                int64_t slot[4];
+                double px[4], py[4], pz[4];
+                int16_t qv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int t = min(t0 + u * (int)blockDim.x, nst - 1);
+                    slot[u] = (int64_t)(ent_g[t >> 3] & kEntClusterMask) * kCluster + (t & 7);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    px[u] = A.xs[slot[u]];
+                    py[u] = A.xs[cs + slot[u]];
+                    pz[u] = A.xs[2 * cs + slot[u]];
+                    qv[u] = A.qs[slot[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int t = t0 + u * (int)blockDim.x;
+                    if (t < nst) {
+                        const bool here = px[u] == px[u];
+                        s_x[t] = here ? px[u] : 0.0;
+                        s_y[t] = here ? py[u] : 0.0;
+                        s_z[t] = here ? pz[u] : 0.0;
+                        s_q[t] = here ? qv[u] : kAbsentQ;
+                    }
+                }
             }
         }
         const bool act = cw < gr.ncl;                 // wave-uniform
