@@ -745,10 +745,11 @@ __global__ void __launch_bounds__(kForceBlockMax) k_force32(ForceArgs A)
 // (unchanged values, so every pair's distance is the exact membership expression)
 // and their charges; a group table too large for one work-group's LDS is read from
 // global memory instead (same values, same order).  Each i-cluster takes wpc waves:
-// the two half-lists, each split by alternate rows.  Candidates without a position
+// the two half-lists, each split by alternate rows (one wave takes both in turn).
+// Candidates without a position
 // (the sentinel, padding, fast atoms: NaN in the slot arrays) are staged at the
 // origin with the charge kAbsentQ, which no pair test accepts.
-constexpr int kForce64Block = 1024;
+constexpr int kForce64Block = 512;
 constexpr int16_t kAbsentQ = 0x4000;
 
 __host__ __device__ inline int64_t force64_stage_slots(int E_cap)
@@ -773,7 +774,10 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wpc = A.wpc;                          // waves per i-cluster (even)
     const int cw = w / wpc, sub = w - cw * wpc;
-    const int half = sub & 1, rp = sub >> 1, nrp = wpc >> 1;
+    // two or more waves per cluster: wave sub takes half-list sub & 1, rows sub >> 1,
+    // + wpc / 2, ...; one wave per cluster (groups of 8): both half-lists in turn
+    const int half = wpc > 1 ? (sub & 1) : 0, nhalf = wpc > 1 ? 1 : 2;
+    const int rp = sub >> 1, nrp = wpc > 1 ? wpc >> 1 : 1;
     const int il = lane >> 3, k8 = lane & 7;
     const int64_t step = clamp_step(A);
     const int ngroups = A.dsc->n_groups;
@@ -841,7 +845,6 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
         double xi = 0.0, yi = 0.0, zi = 0.0;
         if (act) {
             ai = A.perm[slot_i];
-            nr = A.cl_nt[(int64_t)I * 2 + half];
             if (ai >= 0) {
                 xi = A.xs[slot_i]; yi = A.xs[cs + slot_i]; zi = A.xs[2 * cs + slot_i];
                 qi_n = A.qs[slot_i];
@@ -951,26 +954,28 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
             };
             // lane (i, k) takes codes 4k .. 4k + 3 of rows rp, rp + nrp, ... of atom i's
             // half-list (one 8-byte load per row, the next one issued a row ahead)
-            nr = __builtin_amdgcn_readfirstlane(nr);
-            const auto cp = gbl(reinterpret_cast<const uint64_t*>(
-                                A.nb + (((int64_t)I * 2 + half) * kCluster + il) * A.nb_cap_h)) +
-                            k8;
-            auto rows = [&](auto st_c, auto per_c) {
-                uint64_t nxt = rp < nr ? (uint64_t)cp[rp * 8] : 0ull;
-                for (int r = rp; r < nr; r += nrp) {
-                    const uint64_t cur = nxt;
-                    if (r + nrp < nr) nxt = cp[(r + nrp) * 8];
-                    row(cur, st_c, per_c);
+            for (int hh = half; hh < half + nhalf; ++hh) {
+                nr = __builtin_amdgcn_readfirstlane(A.cl_nt[(int64_t)I * 2 + hh]);
+                const auto cp = gbl(reinterpret_cast<const uint64_t*>(
+                                    A.nb + (((int64_t)I * 2 + hh) * kCluster + il) * A.nb_cap_h)) +
+                                k8;
+                auto rows = [&](auto st_c, auto per_c) {
+                    uint64_t nxt = rp < nr ? (uint64_t)cp[rp * 8] : 0ull;
+                    for (int r = rp; r < nr; r += nrp) {
+                        const uint64_t cur = nxt;
+                        if (r + nrp < nr) nxt = cp[(r + nrp) * 8];
+                        row(cur, st_c, per_c);
+                    }
+                };
+                using T_ = std::true_type;
+                using F_ = std::false_type;
+                if (staged) {
+                    if (gs.periodic) rows(T_{}, T_{});
+                    else rows(T_{}, F_{});
+                } else {
+                    if (gs.periodic) rows(F_{}, T_{});
+                    else rows(F_{}, F_{});
                 }
-            };
-            using T_ = std::true_type;
-            using F_ = std::false_type;
-            if (staged) {
-                if (gs.periodic) rows(T_{}, T_{});
-                else rows(T_{}, F_{});
-            } else {
-                if (gs.periodic) rows(F_{}, T_{});
-                else rows(F_{}, F_{});
             }
             Fx = reduce8(Fx);
             Fy = reduce8(Fy);
@@ -1075,14 +1080,18 @@ hipError_t force_kernel_setup(Ctx* c)
 }
 
 // FP64 kernel launch shape: work-groups per CU as the LDS allows (at most 4), waves
-// per i-cluster (even, at least the two half-lists) for about 16 waves per CU, so
-// that one work-group's staging overlaps another's pair loop where two fit.
+// per i-cluster (even: whole half-lists per pair of waves; one for groups of 8) for
+// up to 16 waves per CU within the 512-thread work-group.  Work-groups of 512
+// threads leave each wave 256 VGPRs, so the four pairs of a row overlap their FP64
+// chains: faster than 1,024 threads at 128 VGPRs (10.3 against 11.2 ms per launch
+// on the 4.19 M-atom box, one work-group per CU either way, limited by the LDS).
 static void force64_shape(const Ctx* c, int* per_cu, int* wpc)
 {
     const size_t lds = (c->stage64 ? force64_lds_bytes(c->E_cap) : 0) + c->force64_static_lds;
     const int p = (int)std::min<size_t>(4, std::max<size_t>(1, c->lds_per_cu / lds));
-    int w = std::max(2, (16 / (c->G * p)) & ~1);
-    w = std::min(w, kForce64Block / 64 / c->G);
+    const int wmax = std::max(1, kForce64Block / 64 / c->G);
+    int w = std::max(1, std::min(wmax, 16 / (c->G * p)));
+    if (w > 1) w &= ~1;
     *per_cu = std::max(1, std::min(p, 16 / (c->G * w)));
     *wpc = w;
 }
