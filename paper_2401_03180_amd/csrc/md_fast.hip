@@ -108,7 +108,7 @@ __device__ inline bool pair_fp64(const FastArgs& A, const GridSys& gs, double ka
     const double r = sqrt(r2);
     const double rinv2 = 1.0 / r2;
     const double rinv6 = rinv2 * rinv2 * rinv2;
-    const double s = exp(-kap * r);
+    const double s = exp_nonpos64(-kap * r);
     const double uc = kKe * (double)qa * (double)qb / r;
     const double l12 = c12 * rinv6 * rinv6, l6 = c6 * rinv6;
     if (A.screen_lj) {

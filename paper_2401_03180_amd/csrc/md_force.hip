@@ -215,6 +215,16 @@ __device__ inline int row_place(int p)
     return (p & ~31) | ((p & 7) << 2) | ((p >> 3) & 3);
 }
 
+// 8-code columns of a half-list's last row that hold codes (1..4; 0 without rows):
+// lane k of an atom takes positions 32 r + 8 a + k of row r, and past the longest
+// list of the cluster (len codes) every position is the sentinel, whose terms are
+// exact zeros, so the FP64 kernel skips the columns a >= tail_cols of the last row.
+// (The FP32 kernel walks whole rows: splitting off its last row measured slower.)
+__device__ inline int tail_cols(int len, int nrow)
+{
+    return nrow > 0 ? min(4, max(1, (len - 32 * (nrow - 1) + 7) >> 3)) : 0;
+}
+
 // Rebuild the half-list `half` of cluster I from the candidates staged in LDS
 // (during a rebuild their .w holds the type): the codes (staged index | type << 13)
 // of partners within rc + skin, compacted per atom in entry order.  Each atom's
@@ -860,21 +870,23 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
         if (act) {
             const double qi = kKe * (double)qi_n;
             const double2* c_row = s_c + ti * A.T;
-            // one row of 4 candidates: distances by the exact membership expression (the
-            // sentinel and padding i-atoms, at finite placeholder positions, are never
-            // inside), then the pair terms of all 4 without branches (a pair outside the
-            // cutoff is evaluated at r^2 = 1 and its terms dropped), so the 4 evaluations
-            // interleave.  ST: staged table; PER: periodic system (both uniform, fixed
-            // per loop, so no branch on them sits inside the row)
-            auto row = [&](uint64_t codes, auto st_c, auto per_c) {
+            // one row of 4 candidates (NU in the last row): distances by the exact
+            // membership expression (the sentinel and padding i-atoms, at finite
+            // placeholder positions, are never inside), then the pair terms of all 4
+            // without branches (a pair outside the cutoff is evaluated at r^2 = 1 and its
+            // terms dropped), so the 4 evaluations interleave.  ST: staged table; PER:
+            // periodic system (both uniform, fixed per loop, so no branch on them sits
+            // inside the row)
+            auto row = [&](uint64_t codes, auto st_c, auto per_c, auto nu_c) {
                 constexpr bool ST = decltype(st_c)::value;
                 constexpr bool PER = decltype(per_c)::value;
+                constexpr int NU = decltype(nu_c)::value;
                 uint32_t idx[4];
                 int tj[4], qj[4];
                 double dx[4], dy[4], dz[4], r2[4];
                 bool in[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < NU; ++u) {
                     const uint32_t code = (uint32_t)(codes >> (16 * u)) & 0xFFFFu;
                     idx[u] = code & kCodeIdxMask;
                     tj[u] = (int)(code >> kCodeIdxBits);
@@ -911,12 +923,12 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
                 }
                 if (EMIT) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < NU; ++u)
                         emit_pairs(in[u], ent_g, A.perm, ai, in[u] ? idx[u] : 0u,
                                    &A.dsc->pair_count, A.emit, A.emit_max);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < NU; ++u) {
                     const double rr = in[u] ? r2[u] : 1.0;
                     const int qq = (HYBRID || QLJ) && !in[u] ? 0 : qj[u];
                     double c6 = c_row[tj[u]].x, c12 = c_row[tj[u]].y;
@@ -931,7 +943,7 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
                         const double r = rr * rinv;
                         const double rinv2 = rinv * rinv;
                         const double rinv6 = rinv2 * rinv2 * rinv2;
-                        const double s = exp(-kap * r);
+                        const double s = exp_nonpos64(-kap * r);
                         const double uc = qi * (double)qq * rinv;
                         const double l12 = c12 * rinv6 * rinv6, l6 = c6 * rinv6;
                         if (SCREEN_LJ) {
@@ -954,17 +966,30 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
             };
             // lane (i, k) takes codes 4k .. 4k + 3 of rows rp, rp + nrp, ... of atom i's
             // half-list (one 8-byte load per row, the next one issued a row ahead)
+            using C1 = std::integral_constant<int, 1>;
+            using C2 = std::integral_constant<int, 2>;
+            using C3 = std::integral_constant<int, 3>;
+            using C4 = std::integral_constant<int, 4>;
             for (int hh = half; hh < half + nhalf; ++hh) {
                 nr = __builtin_amdgcn_readfirstlane(A.cl_nt[(int64_t)I * 2 + hh]);
+                const int nt = __builtin_amdgcn_readfirstlane(
+                    tail_cols(A.cl_len[(int64_t)I * 2 + hh], nr));
                 const auto cp = gbl(reinterpret_cast<const uint64_t*>(
                                     A.nb + (((int64_t)I * 2 + hh) * kCluster + il) * A.nb_cap_h)) +
                                 k8;
                 auto rows = [&](auto st_c, auto per_c) {
                     uint64_t nxt = rp < nr ? (uint64_t)cp[rp * 8] : 0ull;
-                    for (int r = rp; r < nr; r += nrp) {
+                    int r = rp;
+                    for (; r < nr - 1; r += nrp) {
                         const uint64_t cur = nxt;
                         if (r + nrp < nr) nxt = cp[(r + nrp) * 8];
-                        row(cur, st_c, per_c);
+                        row(cur, st_c, per_c, C4{});
+                    }
+                    if (r == nr - 1) {   // the last row (in nxt): its columns in use only
+                        if (nt >= 4) row(nxt, st_c, per_c, C4{});
+                        else if (nt == 3) row(nxt, st_c, per_c, C3{});
+                        else if (nt == 2) row(nxt, st_c, per_c, C2{});
+                        else row(nxt, st_c, per_c, C1{});
                     }
                 };
                 using T_ = std::true_type;
