@@ -418,6 +418,28 @@ __device__ void fast_nbr(const FastArgs& A, int col)
     // a wave skips a fast atom only when its z gap exceeds rc by a margin far above
     // the rounding of the wrapped coordinates
     const double zskip = sqrt(A.rc2) * (1.0 + 1e-9) + 1e-9;
+    // the nearby fast atoms c0 .. c0 + nc - 1 into LDS (positions, wrapped z, charge,
+    // type); when they fit one chunk (the common case) they are staged once for all
+    // of the column's slot passes
+    auto stage = [&](int c0, int nc) {
+        if ((int)threadIdx.x < nc) {
+            const int g = s_loc[c0 + threadIdx.x];
+            s_pg[threadIdx.x] = g;
+            s_px[threadIdx.x] = A.x[g];
+            s_py[threadIdx.x] = A.y[g];
+            s_pz[threadIdx.x] = A.z[g];
+            s_pq[threadIdx.x] = A.q[g];
+            s_pt[threadIdx.x] = A.atype[g];
+            const double zg = s_pz[threadIdx.x];
+            s_pzw[threadIdx.x] = gs.periodic ? zg - gs.L[2] * floor(zg * gs.invL[2]) : zg;
+        }
+    };
+    const bool one_chunk = total <= kFastChunk;          // uniform
+    if (one_chunk) {
+        __syncthreads();                                 // s_loc written
+        stage(0, total);
+        __syncthreads();
+    }
     for (int64_t sb = s0; sb < s1; sb += kFastBlock) {
         const int64_t s = sb + threadIdx.x;
         double xa = NAN, ya = 0.0, za = 0.0;
@@ -444,19 +466,11 @@ __device__ void fast_nbr(const FastArgs& A, int col)
         bool any = false;
         for (int c0 = 0; c0 < total; c0 += kFastChunk) {
             const int nc = min(kFastChunk, total - c0);
-            __syncthreads();                           // the previous chunk is consumed
-            if ((int)threadIdx.x < nc) {
-                const int g = s_loc[c0 + threadIdx.x];
-                s_pg[threadIdx.x] = g;
-                s_px[threadIdx.x] = A.x[g];
-                s_py[threadIdx.x] = A.y[g];
-                s_pz[threadIdx.x] = A.z[g];
-                s_pq[threadIdx.x] = A.q[g];
-                s_pt[threadIdx.x] = A.atype[g];
-                const double zg = s_pz[threadIdx.x];
-                s_pzw[threadIdx.x] = gs.periodic ? zg - gs.L[2] * floor(zg * gs.invL[2]) : zg;
+            if (!one_chunk) {
+                __syncthreads();                       // the previous chunk is consumed
+                stage(c0, nc);
+                __syncthreads();
             }
-            __syncthreads();
             if (!live) continue;
             // membership first (cheap), then the pair terms of this lane's partners
             // only, in ascending k: a wave no longer runs the terms for every k that
