@@ -877,7 +877,8 @@ __global__ void __launch_bounds__(kForce64Block) k_force64(ForceArgs A)
             // terms dropped), so the 4 evaluations interleave.  ST: staged table; PER:
             // periodic system (both uniform, fixed per loop, so no branch on them sits
             // inside the row)
-            auto row = [&](uint64_t codes, auto st_c, auto per_c, auto nu_c) {
+            auto row = [&](uint64_t codes, auto st_c, auto per_c,
+                           auto nu_c) __attribute__((always_inline)) {
                 constexpr bool ST = decltype(st_c)::value;
                 constexpr bool PER = decltype(per_c)::value;
                 constexpr int NU = decltype(nu_c)::value;
