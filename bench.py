@@ -50,14 +50,25 @@ SCHEDULE = {"water_1536": 200, "water_98304": 1000, "protein_524288": 500,
             "methane_256": 2000, "water_4194304": 100}
 
 
-def make_system(name, n_steps):
-    """The named workload with its own schedule length, or n_steps if longer."""
+def schedule_len(name, dt_fs=None):
+    """Steps of the named workload's schedule (the pulse box at another time step: the
+    same schedule in time)."""
+    if dt_fs is None:
+        return SCHEDULE[name]
+    return int(round(SCHEDULE[name] * 0.1 / dt_fs))
+
+
+def make_system(name, n_steps, dt_fs=None):
+    """The named workload with its own schedule length, or n_steps if longer; dt_fs:
+    the pulse box (water_98304) at another time step."""
     from paper_2401_03180_amd import synth
     if name not in SCHEDULE:
         raise SystemExit("unknown config " + name)
-    S = max(int(n_steps), SCHEDULE[name])
+    if dt_fs is not None and name != "water_98304":
+        raise SystemExit("--dt-fs applies to water_98304 only")
+    S = max(int(n_steps), schedule_len(name, dt_fs))
     if name == "water_98304":
-        return synth.water_pulse(n_steps=S)
+        return synth.water_pulse(n_steps=S, dt_fs=0.1 if dt_fs is None else dt_fs)
     if name == "water_1536":
         return synth.water_small(n_steps=S)
     if name == "protein_524288":
@@ -566,6 +577,9 @@ def main():
     ap.add_argument("--forcefield", action="store_true",
                     help="bind the synthetic molecular force field (Morse bonds, angles, "
                          "LJ exclusions, charge-scaled LJ radii, LJ on every element pair)")
+    ap.add_argument("--dt-fs", type=float, default=None,
+                    help="water_98304 only: another time step in fs with the same pulse and "
+                         "screening schedule in time (the force-field run needs 0.05 fs)")
     ap.add_argument("--rdf", action="store_true",
                     help="also time the pair-distance histogram (1 nm, 250 bins) after the "
                          "timed steps' workload")
@@ -599,7 +613,7 @@ def main():
     def knobs(config, prec, steps=a.steps, warmup=a.warmup, cli=True):
         """Launch configuration: command line, else the cached tuning, else defaults."""
         if a.tune and cli:
-            autotune.tune(config, lambda: make_system(config, S), prec, steps, warmup,
+            autotune.tune(config, lambda: make_system(config, S, a.dt_fs), prec, steps, warmup,
                           log=log)
         t = None if a.no_tuned else autotune.load(config, prec)
         k = {"cluster_group": 0, "skin": None, "fast_capacity": 0, "tuned": t is not None}
@@ -615,7 +629,7 @@ def main():
         return k
 
     t_gen = time.perf_counter()
-    base_sys = make_system(a.config, S)
+    base_sys = make_system(a.config, S, a.dt_fs)
     log("generated", a.config, "in %.1f s" % (time.perf_counter() - t_gen))
     sys32 = base_sys.copy()
     ff_kind = ("methane" if a.config.startswith("methane") else "water") if a.forcefield else None
@@ -634,7 +648,7 @@ def main():
         sb = subbox_rows(sys32)
     k32 = knobs(a.config, md.MD_FP32_KAHAN)
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
-    sched = (min(sys32.n_steps, SCHEDULE[a.config])
+    sched = (min(sys32.n_steps, schedule_len(a.config, a.dt_fs))
              if sys32.n_systems == 1 and not a.no_schedule else 0)
     r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
                   use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg,
@@ -731,7 +745,7 @@ def main():
         extra["legs"] = legs
 
     if a.rdf:
-        rr = run_rdf(make_system(a.config, S))
+        rr = run_rdf(make_system(a.config, S, a.dt_fs))
         log("rdf", rr)
         extra.update(rr)
 
@@ -766,7 +780,7 @@ def main():
                       "fast_capacity": k32["fast_capacity"], "tuned": k32["tuned"],
                       "systems": sys32.n_systems, "langevin": lg is not None,
                       "hybrid_screening": hy is not None,
-                      "forcefield": ff_kind,
+                      "forcefield": ff_kind, "dt_fs": sys32.dt * 1e3,
                       "launch": "eager" if a.eager else "graph", "parallelism": "single-gpu"},
            "roofline": roofline, "extra": extra}
     if not a.no_cpu:

@@ -320,24 +320,29 @@ def water_small(n_steps: int = 200) -> System:
                    "bulk water, 512 H2O, 2.48 nm periodic cube")
 
 
-def water_pulse(n_steps: int = 1000) -> System:
+def water_pulse(n_steps: int = 1000, dt_fs: float = 0.1) -> System:
     """32,768 H2O (98,304 atoms), 9.93 nm periodic cube, lambda_D linear 1.0 -> 0.15 nm over
-    1,000 steps, Gaussian pulse FWHM 10 fs centred at 50 fs with peak per-step probability 5e-3,
-    rc 1.0 nm, dt 0.1 fs."""
+    the first 100 fs, Gaussian pulse FWHM 10 fs centred at 50 fs with peak ionization
+    probability 5e-3 per 0.1 fs, rc 1.0 nm, dt 0.1 fs (1,000 steps to the end of the ramp).
+
+    dt_fs: another time step with the same schedule in time (the ramp ends after
+    round(100 / dt_fs) steps, the per-step probability scales with the step); the
+    default reproduces the 0.1 fs tables exactly."""
     seed = BASE_SEED + 1
     L = 9.93
     pos, vel, elem, masses, offs = water_box(32, L, seed)
     S = n_steps
-    dt = 1e-4
+    dt = dt_fs * 1e-3
+    k_ramp = float(round(100.0 / dt_fs))
     k = np.arange(S + 1, dtype=np.float64)
-    lam = 1.0 - 0.85 * np.minimum(k, 1000.0) / 1000.0
+    lam = 1.0 - 0.85 * np.minimum(k, k_ramp) / k_ramp
     t_fs = k * dt * 1000.0
     g = gaussian_envelope(t_fs, 50.0, 10.0)
     c6, c12 = _water_lj()
     qmax = [8, 1]
     return _finish("water_98304", pos, vel, elem, elem.copy(), masses, offs, True,
                    [[L, L, L]], 1.0, 0.1, dt, S, lam[None, :], g[None, :],
-                   _base_table(qmax, 5e-3), qmax, c6, c12, seed, ("O", "H"),
+                   _base_table(qmax, 5e-3 * (dt_fs / 0.1)), qmax, c6, c12, seed, ("O", "H"),
                    "bulk water, 32,768 H2O, 9.93 nm periodic cube, pulse-driven screening")
 
 

@@ -28,6 +28,21 @@ def test_water_pulse_schedule():
     assert s.base.max() == 5e-3
 
 
+def test_water_pulse_other_time_step():
+    # the same schedule in time at half the step: ramp end, pulse peak and the
+    # ionization probability per unit time unchanged; the default is the 0.1 fs box
+    s, h = synth.water_pulse(n_steps=1000), synth.water_pulse(n_steps=2000, dt_fs=0.05)
+    assert h.dt == pytest.approx(s.dt / 2)
+    assert np.array_equal(h.lambda_d[0, ::2], s.lambda_d[0])
+    assert h.g[0].argmax() == 1000
+    np.testing.assert_allclose(h.g[0, ::2], s.g[0], rtol=1e-12, atol=1e-300)
+    assert h.base.max() / h.dt == pytest.approx(s.base.max() / s.dt, rel=1e-12)
+    assert np.array_equal(h.x, s.x) and np.array_equal(h.vx, s.vx)
+    d = synth.water_pulse(n_steps=1000, dt_fs=0.1)
+    assert all(np.array_equal(getattr(d, n), getattr(s, n))
+               for n in ("lambda_d", "g", "base", "x", "vx"))
+
+
 def test_protein_mix():
     s = synth.protein_crystal()
     assert s.n_atoms == 524288
