@@ -633,6 +633,10 @@ def main():
     log("generated", a.config, "in %.1f s" % (time.perf_counter() - t_gen))
     sys32 = base_sys.copy()
     ff_kind = ("methane" if a.config.startswith("methane") else "water") if a.forcefield else None
+    if ff_kind and a.config == "water_98304" and sys32.dt > 0.75e-4:
+        log("warning: with the molecular force field the pulse box's dynamics run away after "
+            "the pulse at dt 0.1 fs (fast ions reach the small charge-scaled LJ cores within "
+            "one step); --dt-fs 0.05 keeps them finite")
     ffb = ff_binding(sys32, ff_kind) if ff_kind else None
     lg = None
     if a.langevin:

@@ -23,6 +23,19 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
 
 
+def test_bench_time_step_option():
+    # the pulse box at another step keeps its schedule in time (twice the steps at half
+    # the step); the option is refused for the other workloads
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.schedule_len("water_98304") == 1000
+    assert bench.schedule_len("water_98304", 0.05) == 2000
+    s = bench.make_system("water_98304", 0, 0.05)
+    assert s.n_steps == 2000 and s.dt == pytest.approx(5e-5)
+    with pytest.raises(SystemExit):
+        bench.make_system("water_1536", 0, 0.05)
+
+
 def test_host_rdf_helpers_match_oracle():
     from paper_2401_03180_amd import md
     rng = np.random.default_rng(11)
