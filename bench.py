@@ -633,10 +633,12 @@ def main():
     log("generated", a.config, "in %.1f s" % (time.perf_counter() - t_gen))
     sys32 = base_sys.copy()
     ff_kind = ("methane" if a.config.startswith("methane") else "water") if a.forcefield else None
-    if ff_kind and a.config == "water_98304" and sys32.dt > 0.75e-4:
+    ff_runaway = bool(ff_kind) and a.config == "water_98304" and sys32.dt > 0.75e-4
+    if ff_runaway:
         log("warning: with the molecular force field the pulse box's dynamics run away after "
             "the pulse at dt 0.1 fs (fast ions reach the small charge-scaled LJ cores within "
-            "one step); --dt-fs 0.05 keeps them finite")
+            "one step); --dt-fs 0.05 keeps them finite.  The FP64 leg is skipped at this step: "
+            "one such run of it stalled past the divergence, cause not established")
     ffb = ff_binding(sys32, ff_kind) if ff_kind else None
     lg = None
     if a.langevin:
@@ -686,7 +688,7 @@ def main():
     if "subbox" in r32:
         extra["subbox_errors"] = r32["subbox"]
         log("subbox", r32["subbox"])
-    if not a.no_fp64:
+    if not a.no_fp64 and not ff_runaway:
         if sys32.n_systems > 1:
             # batched workloads: the plain FP64 form runs one system per context and launch
             sys64 = base_sys.copy()
