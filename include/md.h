@@ -88,7 +88,10 @@ typedef struct md_config {
     double rc;                  /* cutoff, nm (pairs with r^2 < rc^2 interact) */
     double skin;                /* Verlet buffer, nm (> 0) */
     int64_t capacity_atoms;     /* >= sys_offsets[B]; every workspace is sized from it */
-    int32_t cluster_group;      /* i-clusters per force work-group: 1, 2, 4 or 8 (0 = 4) */
+    int32_t cluster_group;      /* i-clusters per force work-group: 1, 2, 4 or 8 (0 = 4);
+                                   halved at md_create while the group's candidate table
+                                   would not fit one work-group's LDS at density_hint
+                                   (md_stats.cluster_group is the size in use) */
     int32_t max_neighbors;      /* per-atom neighbour-list capacity (0 = derived) */
     double density_hint;        /* upper bound on atoms per nm^3 used for sizing (0 = 130) */
     int32_t fast_capacity;      /* atoms allowed beyond skin/2 of their build position before a
@@ -283,7 +286,7 @@ typedef struct md_stats {
     int64_t max_group_entries, group_entry_capacity;
     int64_t n_builds;                                   /* builds executed on the device */
     int64_t n_fast, n_fast_raw;                         /* fast atoms now (capped, found) */
-    int32_t cluster_group;
+    int32_t cluster_group;                              /* i-clusters per work-group in use */
     uint32_t flags;
 } md_stats;
 

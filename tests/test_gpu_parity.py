@@ -289,6 +289,39 @@ def test_vacuum_batched_clusters(prec):
         e1.close()
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("G", [1, 2, 4, 8])
+def test_every_cluster_group_and_skin(prec, G):
+    """Every launch configuration the autotuner can choose (i-clusters per work-group,
+    skin) gives the oracle's pair set and forces, periodic and batched vacuum.  The
+    library halves a group whose candidate table would not fit one work-group's LDS
+    (groups of 8 on the small water box): the size in use is at most the one asked."""
+    cases = [(synth.water_small(n_steps=10), 5, {}),
+             (synth.methane_clusters(n_clusters=4, lo=300, hi=3000, n_steps=10), 3,
+              {"density_hint": 100.0})]
+    for ci, (s, k, kw) in enumerate(cases):
+        s.q = random_charges(s, 7 + ci)
+        ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, k))
+        op = oracle.pairs(s)
+        for skin in (0.06, 0.12):
+            say("cluster group", G, "skin", skin, "case", s.name, "prec", prec)
+            eng = make_engine(s, prec, cluster_group=G, skin=skin, **kw)
+            set_q(eng, s.q)
+            eng.set_step(k)
+            eng.build()
+            F, epot = gpu_forces(eng, prec)
+            assert force_error(F, ref) <= TOL[prec]
+            for b in range(s.n_systems):
+                a0, a1 = s.sys_offsets[b], s.sys_offsets[b + 1]
+                esc = 2 * np.abs(ref["e_atom"][a0:a1]).sum()
+                assert abs(epot[b] - ref["epot"][b]) <= TOL[prec] * esc
+            assert np.array_equal(sorted_pairs(eng.debug_pairs(prec=prec)), op)
+            st = eng.stats()
+            assert st["cluster_group"] in (1, 2, 4, 8) and st["cluster_group"] <= G
+            assert st["flags"] == 0
+            eng.close()
+
+
 # ------------------------------------------------------------------ graphs
 
 def test_graph_replay_matches_eager():
