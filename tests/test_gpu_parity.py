@@ -507,14 +507,19 @@ def _displace(eng, s, disp):
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("periodic", [True, False])
-def test_fast_atoms_exact_without_rebuild(prec, periodic):
+@pytest.mark.parametrize("n_fast,cap", [(24, 64), (24, 8192), (400, 1024), (400, 8192)])
+def test_fast_atoms_exact_without_rebuild(prec, periodic, n_fast, cap):
     """Atoms beyond skin/2 of their build positions (no rebuild): the fast-atom
     kernels supply their pairs; pair set, forces and energies match the oracle at the
-    new positions."""
+    new positions.  A capacity of 8,192 passes 16 work-groups per CU of the one-launch
+    form, so the pass runs as two launches; 400 fast atoms within reach of one column
+    of the small water box pass one LDS chunk of 256, so they are staged chunk by chunk."""
     from paper_2401_03180_amd import md
-    s, disp, fast = _fast_case(periodic, 24, 21 + periodic)
-    say("fast atoms", "periodic" if periodic else "vacuum", "prec", prec)
-    eng = make_engine(s, prec, fast_capacity=64, density_hint=0.0 if periodic else 100.0)
+    s, disp, fast = _fast_case(periodic, n_fast, 21 + periodic)
+    assert fast.size > 256 if n_fast > 256 else fast.size == n_fast
+    say("fast atoms", "periodic" if periodic else "vacuum", "prec", prec, "n_fast", n_fast,
+        "capacity", cap)
+    eng = make_engine(s, prec, fast_capacity=cap, density_hint=0.0 if periodic else 100.0)
     set_q(eng, s.q)
     eng.set_step(0)
     eng.build()
