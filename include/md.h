@@ -67,7 +67,9 @@ typedef enum md_precision {
                                         md_screened_forces after a build, which latches it) */
 #define MD_FLAG_SKIN 0x4u            /* forces were evaluated (or MD_BUILD_CHECK ran) while some
                                         atom had moved more than skin/2 since the last build */
-#define MD_FLAG_NONFINITE 0x8u       /* non-finite position seen by a build */
+#define MD_FLAG_NONFINITE 0x8u       /* non-finite position seen by a build, or one more than
+                                        500 box lengths from a periodic box (binned at the
+                                        500th image) */
 #define MD_FLAG_STEP 0x10u           /* step counter outside the bound schedule tables */
 #define MD_FLAG_BAD_INPUT 0x20u      /* a type, element or charge outside its table (the entry
                                         was clamped or skipped) */
@@ -93,7 +95,11 @@ typedef struct md_config {
                                    would not fit one work-group's LDS at density_hint
                                    (md_stats.cluster_group is the size in use) */
     int32_t max_neighbors;      /* per-atom neighbour-list capacity (0 = derived) */
-    double density_hint;        /* upper bound on atoms per nm^3 used for sizing (0 = 130) */
+    double density_hint;        /* upper bound on atoms per nm^3 used for sizing the grid,
+                                   the group tables and the per-atom lists (0: 1.1 x the
+                                   mean density of the densest periodic box, 130 for
+                                   vacuum); a region much denser than it overflows the
+                                   lists (MD_FLAG_LIST_OVERFLOW) */
     int32_t fast_capacity;      /* atoms allowed beyond skin/2 of their build position before a
                                    rebuild is due; their pairs are evaluated separately, exactly
                                    (0 = min(1024, max(64, N/96)); -1 = none: rebuild as soon as

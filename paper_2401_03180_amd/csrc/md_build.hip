@@ -298,6 +298,42 @@ __global__ void __launch_bounds__(256) k_scatter_cols(ScatterArgs A)
 // vacuum grid stretched by a few far ions can put hundreds of atoms in one bin), so
 // the slot order, and with it every summation order, never depends on the order of
 // the binning atomics.
+// In-place heap sort of a[0 .. m), ascending, by one thread: m log m steps where an
+// insertion sort takes ~m^2 / 4, for the bins that hold many atoms (a vacuum grid whose
+// box has grown around an expanding cluster keeps its dense core in few bins; a pile-up
+// of atoms, or atoms clamped into an edge bin from far outside a periodic box, puts
+// thousands in one).
+__device__ inline void heap_sort_i32(int32_t* a, int m)
+{
+    // move a[root]'s value down the max-heap a[0 .. end) to its place
+    auto sift = [&](int root, int end) {
+        const int32_t v = a[root];
+        int i = root;
+        for (;;) {
+            int c = 2 * i + 1;
+            if (c >= end) break;
+            int32_t cv = a[c];
+            if (c + 1 < end) {
+                const int32_t c2 = a[c + 1];
+                if (c2 > cv) { ++c; cv = c2; }
+            }
+            if (cv <= v) break;
+            a[i] = cv;
+            i = c;
+        }
+        a[i] = v;
+    };
+    for (int r = m / 2 - 1; r >= 0; --r) sift(r, m);
+    for (int end = m - 1; end > 0; --end) {
+        const int32_t t = a[0];
+        a[0] = a[end];
+        a[end] = t;
+        sift(0, end);
+    }
+}
+
+constexpr int kBinInsertionMax = 32;     // above this, the heap sort
+
 __device__ void ph_bin_sort(const int32_t* bin_start, int32_t* sorted, int32_t* bin_cnt,
                             int64_t cap_bins, const DevScalars* dsc, int64_t gid, int64_t stride)
 {
@@ -307,6 +343,10 @@ __device__ void ph_bin_sort(const int32_t* bin_start, int32_t* sorted, int32_t* 
         if (b >= nbins) continue;
         const int s = bin_start[b], e = bin_start[b + 1];
         if (e - s < 2) continue;
+        if (e - s > kBinInsertionMax) {
+            heap_sort_i32(sorted + s, e - s);
+            continue;
+        }
         if (e - s <= 8) {
             // the common case (a bin holds ~2 atoms): all loads at once, a sorting
             // network in registers (Batcher's odd-even merge for 8 inputs), all stores

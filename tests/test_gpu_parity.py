@@ -413,6 +413,67 @@ def test_empty_system_in_batch():
     eng.close()
 
 
+def _pile_system(n_pile, spacing, seed):
+    """A tiny periodic system with `n_pile` atoms packed on a jittered cubic lattice of
+    the given spacing around one point (far more atoms per grid bin than the grid is
+    sized for); the background atoms near that point are dropped."""
+    s = _tiny_system(64, True, L=5.0, seed=seed)
+    c = np.array([1.2345, 3.1416, 2.7183])
+    keep = np.linalg.norm(np.stack([s.x, s.y, s.z], 1) - c, axis=1) > 0.8
+    m = int(math.ceil(n_pile ** (1.0 / 3.0)))
+    rng = np.random.default_rng(seed + 1)
+    P = (synth.lattice_sites(m, spacing)[:n_pile] - 0.5 * m * spacing + c +
+         rng.uniform(-0.1 * spacing, 0.1 * spacing, size=(n_pile, 3)))
+    B = np.stack([s.x, s.y, s.z], 1)[keep]
+    X = np.concatenate([B, P])
+    n = X.shape[0]
+    q = np.concatenate([s.q[keep], rng.integers(0, 3, n_pile).astype(np.int8)])
+    z = np.zeros(n)
+    return synth.System(
+        name="pile", x=X[:, 0].copy(), y=X[:, 1].copy(), z=X[:, 2].copy(), vx=z.copy(),
+        vy=z.copy(), vz=z.copy(), elem=np.zeros(n, np.uint8), type=np.zeros(n, np.uint8),
+        atom_id=np.arange(n, dtype=np.uint32), inv_mass=np.ones(n), q=q,
+        sys_offsets=np.array([0, n], np.int64), periodic=True, box=s.box, rc=1.0, skin=0.1,
+        dt=1e-4, n_steps=4, lambda_d=np.full((1, 5), 0.3), g=np.ones((1, 5)),
+        base=np.full((1, 3), 0.5), qmax=np.array([2], np.int8), c6=np.full((1, 1), 1e-3),
+        c12=np.full((1, 1), 1e-6), seeds=np.array([1], np.uint64))
+
+
+def test_dense_bins_are_sorted_and_exact():
+    """Grid bins holding over a hundred atoms (their slot order comes from the heap sort
+    above 32 atoms per bin): the pair set is the oracle's in both precisions and the
+    FP64 forces match it; two builds give bit-identical forces.  The grid is sized
+    from the mean density (about a hundredth of the pile's), the per-atom list
+    capacity is given for the pile."""
+    from paper_2401_03180_amd import md
+    s = _pile_system(216, 0.05, 3)
+    ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 0))
+    op = oracle.pairs(s)
+    for prec in PRECS:
+        say("dense bins: 216 atoms at 0.05 nm spacing, prec", prec)
+        eng = make_engine(s, prec, max_neighbors=512)
+        set_q(eng, s.q)
+        eng.build()
+        assert np.array_equal(sorted_pairs(eng.debug_pairs(prec=prec)), op)
+        F, _ = gpu_forces(eng, prec)
+        if prec == 0:
+            assert force_error(F, ref) <= TOL[0]
+        eng.build(md.MD_BUILD_FORCE)
+        F2, _ = gpu_forces(eng, prec)
+        assert all(np.array_equal(a, b) for a, b in zip(F, F2))
+        assert eng.sync_check(raise_on_flags=False) == 0
+        eng.close()
+    # 600 atoms within 1e-6 nm of one point: one bin of ~600, built without a flag
+    s = _pile_system(600, 1e-7, 5)
+    say("dense bins: 600 atoms in one bin")
+    eng = make_engine(s, 1)
+    eng.build()
+    flags = eng.sync_check(raise_on_flags=False)
+    assert (flags & (md.MD_FLAG_CELL_OVERFLOW | md.MD_FLAG_NONFINITE)) == 0
+    assert eng.stats()["n_atoms"] == s.n_atoms
+    eng.close()
+
+
 def test_box_too_small_is_geometry_error():
     from paper_2401_03180_amd.md import MDError, MD_ERR_GEOMETRY
     s = _tiny_system(20, True, L=2.1)
