@@ -654,8 +654,7 @@ def main():
         sb = subbox_rows(sys32)
     k32 = knobs(a.config, md.MD_FP32_KAHAN)
     log("config", a.config, "atoms", sys32.n_atoms, "steps", a.steps, "warmup", a.warmup, k32)
-    sched = (min(sys32.n_steps, schedule_len(a.config, a.dt_fs))
-             if sys32.n_systems == 1 and not a.no_schedule else 0)
+    sched = min(sys32.n_steps, schedule_len(a.config, a.dt_fs)) if not a.no_schedule else 0
     r32 = run_gpu(sys32, md.MD_FP32_KAHAN, a.steps, a.warmup, k32["cluster_group"], k32["skin"],
                   use_graph=not a.eager, fast_capacity=k32["fast_capacity"], langevin=lg,
                   hybrid=hy, ff=ffb, schedule_steps=sched, subbox=sb, preroll_max=PREROLL)

@@ -407,13 +407,16 @@ struct ForceFinalizeArgs {
     int64_t N;
 };
 
-__device__ inline void force_finalize_block(const ForceFinalizeArgs& F)
+// b_first, b_stride: the systems this work-group sums (several work-groups share a
+// batch of many systems; each system's sum is the same whichever takes it).
+__device__ inline void force_finalize_block(const ForceFinalizeArgs& F, int b_first = 0,
+                                            int b_stride = 1)
 {
     __shared__ double s_red[16];
     if (F.epot) {
         const int nf = F.dsc->n_fast;
         const int nw = blockDim.x >> 6;
-        for (int b = 0; b < F.B; ++b) {
+        for (int b = b_first; b < F.B; b += b_stride) {
             const int g0 = F.sys_grp0[b], g1 = F.sys_grp0[b + 1];
             // the group energies in passes of 16 per thread (16 loads in flight
             // together) into 16 partial sums, then the rest one at a time; combined
@@ -467,7 +470,7 @@ __device__ inline void force_finalize_block(const ForceFinalizeArgs& F)
             }
         }
     }
-    if (threadIdx.x == 0) F.dsc->lists_pending = 0;
+    if (threadIdx.x == 0 && b_first == 0) F.dsc->lists_pending = 0;
 }
 
 }  // namespace md
