@@ -299,10 +299,8 @@ __global__ void __launch_bounds__(256) k_scatter_cols(ScatterArgs A)
 // the slot order, and with it every summation order, never depends on the order of
 // the binning atomics.
 // In-place heap sort of a[0 .. m), ascending, by one thread: m log m steps where an
-// insertion sort takes ~m^2 / 4, for the bins that hold many atoms (a vacuum grid whose
-// box has grown around an expanding cluster keeps its dense core in few bins; a pile-up
-// of atoms, or atoms clamped into an edge bin from far outside a periodic box, puts
-// thousands in one).
+// insertion sort takes ~m^2 / 4 (bins of a few dozen atoms: the dense cores of vacuum
+// grids).
 __device__ inline void heap_sort_i32(int32_t* a, int m)
 {
     // move a[root]'s value down the max-heap a[0 .. end) to its place
@@ -333,56 +331,122 @@ __device__ inline void heap_sort_i32(int32_t* a, int m)
 }
 
 constexpr int kBinInsertionMax = 32;     // above this, the heap sort
+constexpr int kBinThreadMax = 128;       // above this, the whole work-group (rank sort)
+constexpr int kRankTile = 1024;          // values of the bin staged in LDS at a time
+constexpr int kRankPer = 4;              // values ranked per thread and pass
+constexpr int kSortBlockMax = 1024;      // largest work-group calling ph_bin_sort
 
-__device__ void ph_bin_sort(const int32_t* bin_start, int32_t* sorted, int32_t* bin_cnt,
-                            int64_t cap_bins, const DevScalars* dsc, int64_t gid, int64_t stride)
+// Sort a[0 .. m) (distinct values) by the whole work-group: each value's place is the
+// number of smaller values (counted against LDS tiles of the bin), written to tmp and
+// copied back.  m^2 / blockDim compares per thread: a bin of thousands of atoms (a
+// vacuum grid stretched by a far ion keeps a whole cluster in one bin) takes tens of
+// microseconds where one thread's heap sort took milliseconds.  Called by every thread
+// of the work-group; returns after a barrier.
+__device__ void block_rank_sort(int32_t* a, int32_t* tmp, int m, int32_t* s_tile)
 {
-    const int nbins = dsc->n_bins;
-    for (int64_t b = gid; b < cap_bins; b += stride) {
-        bin_cnt[b] = 0;
-        if (b >= nbins) continue;
-        const int s = bin_start[b], e = bin_start[b + 1];
-        if (e - s < 2) continue;
-        if (e - s > kBinInsertionMax) {
-            heap_sort_i32(sorted + s, e - s);
-            continue;
+    const int nt = blockDim.x;
+    for (int e0 = 0; e0 < m; e0 += nt * kRankPer) {
+        int32_t v[kRankPer];
+        int cnt[kRankPer];
+#pragma unroll
+        for (int u = 0; u < kRankPer; ++u) {
+            const int e = e0 + u * nt + (int)threadIdx.x;
+            v[u] = e < m ? a[e] : INT_MAX;
+            cnt[u] = 0;
         }
-        if (e - s <= 8) {
-            // the common case (a bin holds ~2 atoms): all loads at once, a sorting
-            // network in registers (Batcher's odd-even merge for 8 inputs), all stores
-            constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6},
-                                         {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
-                                         {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
-            int v[8];
+        for (int j0 = 0; j0 < m; j0 += kRankTile) {
+            const int nj = min(kRankTile, m - j0);
+            __syncthreads();                              // the previous tile is consumed
+            for (int j = threadIdx.x; j < nj; j += nt) s_tile[j] = a[j0 + j];
+            __syncthreads();
+            for (int j = 0; j < nj; ++j) {
+                const int32_t w = s_tile[j];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = s + i < e ? sorted[s + i] : INT_MAX;
-#pragma unroll
-            for (int c = 0; c < 19; ++c) {
-                const int lo = min(v[kNet[c][0]], v[kNet[c][1]]);
-                const int hi = max(v[kNet[c][0]], v[kNet[c][1]]);
-                v[kNet[c][0]] = lo;
-                v[kNet[c][1]] = hi;
+                for (int u = 0; u < kRankPer; ++u) cnt[u] += w < v[u] ? 1 : 0;
             }
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (s + i < e) sorted[s + i] = v[i];
-            continue;
         }
-        for (int i = s + 1; i < e; ++i) {
-            const int v = sorted[i];
-            int j = i - 1;
-            while (j >= s && sorted[j] > v) { sorted[j + 1] = sorted[j]; --j; }
-            sorted[j + 1] = v;
+#pragma unroll
+        for (int u = 0; u < kRankPer; ++u) {
+            const int e = e0 + u * nt + (int)threadIdx.x;
+            if (e < m) tmp[cnt[u]] = v[u];
+        }
+    }
+    __syncthreads();                                      // every place written
+    for (int e = threadIdx.x; e < m; e += nt) a[e] = tmp[e];
+    __syncthreads();
+}
+
+// Every bin's atoms in index order (deterministic slot order), bins dealt to the
+// work-group's threads in tiles of blockDim.x: up to 8 atoms a sorting network in
+// registers, up to kBinInsertionMax an insertion sort, up to kBinThreadMax a heap sort,
+// larger bins by the whole work-group after its tile.  tmp: N scratch words (the
+// binning ranks, free once the atoms are scattered).  gid - threadIdx.x and stride must
+// be multiples of blockDim.x (every thread of a work-group takes the same tiles).
+__device__ void ph_bin_sort(const int32_t* bin_start, int32_t* sorted, int32_t* tmp,
+                            int32_t* bin_cnt, int64_t cap_bins, const DevScalars* dsc,
+                            int64_t gid, int64_t stride)
+{
+    __shared__ int32_t s_big[kSortBlockMax];
+    __shared__ int32_t s_tile[kRankTile];
+    __shared__ int s_nbig;
+    const int nbins = dsc->n_bins;
+    for (int64_t base = gid - threadIdx.x; base < cap_bins; base += stride) {
+        if (threadIdx.x == 0) s_nbig = 0;
+        __syncthreads();
+        const int64_t b = base + threadIdx.x;
+        if (b < cap_bins) {
+            bin_cnt[b] = 0;
+            const int s = b < nbins ? bin_start[b] : 0, e = b < nbins ? bin_start[b + 1] : 0;
+            if (e - s > kBinThreadMax) {
+                s_big[atomicAdd(&s_nbig, 1)] = (int32_t)b;    // sorted below
+            } else if (e - s > kBinInsertionMax) {
+                heap_sort_i32(sorted + s, e - s);
+            } else if (e - s > 8) {
+                for (int i = s + 1; i < e; ++i) {
+                    const int v = sorted[i];
+                    int j = i - 1;
+                    while (j >= s && sorted[j] > v) { sorted[j + 1] = sorted[j]; --j; }
+                    sorted[j + 1] = v;
+                }
+            } else if (e - s >= 2) {
+                // the common case (a bin holds ~2 atoms): all loads at once, a sorting
+                // network in registers (Batcher's odd-even merge for 8 inputs), all stores
+                constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3},
+                                             {4, 6}, {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5},
+                                             {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4},
+                                             {5, 6}};
+                int v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = s + i < e ? sorted[s + i] : INT_MAX;
+#pragma unroll
+                for (int c = 0; c < 19; ++c) {
+                    const int lo = min(v[kNet[c][0]], v[kNet[c][1]]);
+                    const int hi = max(v[kNet[c][0]], v[kNet[c][1]]);
+                    v[kNet[c][0]] = lo;
+                    v[kNet[c][1]] = hi;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (s + i < e) sorted[s + i] = v[i];
+            }
+        }
+        __syncthreads();
+        const int nbig = s_nbig;
+        for (int i = 0; i < nbig; ++i) {
+            const int bb = s_big[i];
+            const int s = bin_start[bb], e = bin_start[bb + 1];
+            block_rank_sort(sorted + s, tmp + s, e - s, s_tile);
         }
     }
 }
 
 __global__ void __launch_bounds__(256) k_bin_sort(const int32_t* bin_start, int32_t* sorted,
-                                                  int32_t* bin_cnt, int64_t cap_bins,
-                                                  const DevScalars* dsc, const int32_t* gate)
+                                                  int32_t* tmp, int32_t* bin_cnt,
+                                                  int64_t cap_bins, const DevScalars* dsc,
+                                                  const int32_t* gate)
 {
     if (gated_off(gate)) return;
-    ph_bin_sort(bin_start, sorted, bin_cnt, cap_bins, dsc,
+    ph_bin_sort(bin_start, sorted, tmp, bin_cnt, cap_bins, dsc,
                 blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
@@ -839,7 +903,7 @@ void launch_build(Ctx* c, const double* x, const double* y, const double* z,
     {
         const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(c->cap_bins, 256), wide));
         hipLaunchKernelGGL(k_bin_sort, dim3(nb), dim3(256), 0, st, c->d_bin_start, c->d_sorted,
-                           c->d_bin_cnt, c->cap_bins, c->dsc, gate);
+                           c->d_rank, c->d_bin_cnt, c->cap_bins, c->dsc, gate);
     }
     launch_scan64(c->d_col_cnt, c->d_col_pre, c->cap_cols + 1, c->d_scan_tmp, gate, st);
     {
@@ -979,6 +1043,7 @@ struct StepBuildArgs {
 // 1024 threads per work-group: one work-group per CU fits (registers), which gives
 // the latency-bound phases 16 waves per CU and each grid barrier one release per CU.
 constexpr int kBuildStepThreads = 1024;
+static_assert(kBuildStepThreads <= kSortBlockMax, "the bin sort lists one large bin per thread");
 
 __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs S)
 {
@@ -1021,7 +1086,7 @@ __global__ void __launch_bounds__(kBuildStepThreads) k_build_step(StepBuildArgs 
         return;
     ph_scatter_cols(S.sc, gid, gstride);
     if (!grid_barrier(gb, d)) return;
-    ph_bin_sort(S.bin_start, S.sorted, S.bin_cnt, S.cap_bins, d, gid, gstride);
+    ph_bin_sort(S.bin_start, S.sorted, S.bin.rank, S.bin_cnt, S.cap_bins, d, gid, gstride);
     if (!grid_barrier(gb, d)) return;
     if (S.n_col_scan <= kLocalScanMax) {
         ph_scan_local<int64_t>(S.col_cnt, S.col_pre, S.n_col_scan);

@@ -441,10 +441,10 @@ def _pile_system(n_pile, spacing, seed):
 
 def test_dense_bins_are_sorted_and_exact():
     """Grid bins holding over a hundred atoms (their slot order comes from the heap sort
-    above 32 atoms per bin): the pair set is the oracle's in both precisions and the
-    FP64 forces match it; two builds give bit-identical forces.  The grid is sized
-    from the mean density (about a hundredth of the pile's), the per-atom list
-    capacity is given for the pile."""
+    above 32 atoms per bin, from the work-group's rank sort above 128): the pair set is
+    the oracle's in both precisions and the FP64 forces match it; two builds give
+    bit-identical forces.  The grid is sized from the mean density (about a hundredth
+    of the pile's), the per-atom list capacity is given for the pile."""
     from paper_2401_03180_amd import md
     s = _pile_system(216, 0.05, 3)
     ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 0))
@@ -463,14 +463,21 @@ def test_dense_bins_are_sorted_and_exact():
         assert all(np.array_equal(a, b) for a, b in zip(F, F2))
         assert eng.sync_check(raise_on_flags=False) == 0
         eng.close()
-    # 600 atoms within 1e-6 nm of one point: one bin of ~600, built without a flag
-    s = _pile_system(600, 1e-7, 5)
+    # 600 atoms 0.003 nm apart: one bin of 600, sorted by the whole work-group (FP64:
+    # the LJ cores at that distance overflow FP32)
+    s = _pile_system(600, 0.003, 5)
+    ref = oracle.forces(s, q=s.q, kappa=oracle_kappa(s, 0))
     say("dense bins: 600 atoms in one bin")
-    eng = make_engine(s, 1)
+    eng = make_engine(s, 0, density_hint=2000.0)
+    set_q(eng, s.q)
     eng.build()
-    flags = eng.sync_check(raise_on_flags=False)
-    assert (flags & (md.MD_FLAG_CELL_OVERFLOW | md.MD_FLAG_NONFINITE)) == 0
-    assert eng.stats()["n_atoms"] == s.n_atoms
+    assert np.array_equal(sorted_pairs(eng.debug_pairs(prec=0)), oracle.pairs(s))
+    F, _ = gpu_forces(eng, 0)
+    assert force_error(F, ref) <= TOL[0]
+    eng.build(md.MD_BUILD_FORCE)
+    F2, _ = gpu_forces(eng, 0)
+    assert all(np.array_equal(a, b) for a, b in zip(F, F2))
+    assert eng.sync_check(raise_on_flags=False) == 0
     eng.close()
 
 
