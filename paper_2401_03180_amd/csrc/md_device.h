@@ -407,6 +407,12 @@ struct ForceFinalizeArgs {
     int64_t N;
 };
 
+// Work-groups that sum the per-system energies of a batch (one per system up to this
+// many; each takes every kFinMax-th system): one work-group took ~2.8 us per system
+// in turn, 0.7 ms per step for 256 systems.
+constexpr int kFinMax = 64;
+inline __host__ __device__ int fin_blocks(int B) { return B < 1 ? 1 : (B < kFinMax ? B : kFinMax); }
+
 // b_first, b_stride: the systems this work-group sums (several work-groups share a
 // batch of many systems; each system's sum is the same whichever takes it).
 __device__ inline void force_finalize_block(const ForceFinalizeArgs& F, int b_first = 0,

@@ -115,7 +115,7 @@ constexpr int kExclRegs = 8;     // excluded partners per atom held in registers
 
 __global__ void __launch_bounds__(256) k_force_finalize(ForceFinalizeArgs F)
 {
-    force_finalize_block(F);
+    force_finalize_block(F, (int)blockIdx.x, (int)gridDim.x);   // fin_blocks(B) of them
 }
 
 template <class T>
@@ -1220,7 +1220,7 @@ hipError_t launch_forces(Ctx* c, md_precision prec, const double* x, const doubl
     if (c->fast_cap > 0) launch_fast(c, x, y, z, q, fx, fy, fz, E, emit, emit_max, st);
     if (c->n_bonds + c->n_angles > 0) launch_bonded(c, x, y, z, q, fx, fy, fz, st);
     if (finalize)
-        hipLaunchKernelGGL(k_force_finalize, dim3(1), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_force_finalize, dim3(fin_blocks(c->B)), dim3(256), 0, st,
                            force_finalize_args(c, epot));
     return hipGetLastError();
 }

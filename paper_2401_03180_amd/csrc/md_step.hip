@@ -291,11 +291,6 @@ __device__ inline void langevin_normals(uint32_t id, uint32_t s, uint32_t b, uin
 
 constexpr unsigned long long kEkSlotEmpty = ~0ull;   // a NaN no arithmetic produces
 
-// Work-groups that sum the per-system energies of a batch (one per system up to this
-// many; each takes every kFinMax-th system): one work-group took ~2.8 us per system
-// in turn, 0.7 ms per step for 256 systems.
-constexpr int kFinMax = 64;
-inline __host__ __device__ int fin_blocks(int B) { return B < 1 ? 1 : (B < kFinMax ? B : kFinMax); }
 
 // Phase 1 of the fused step: an extra work-group sums the kinetic-energy partials of
 // its systems (b_first, b_first + b_stride, ...) in the order of the finalize kernel
