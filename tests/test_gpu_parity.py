@@ -730,6 +730,47 @@ def test_graph_step_kinetic_energy_every_replay():
         eng.close()
 
 
+def test_many_systems_energy_sums():
+    """150 systems, more than the 64 work-groups that share a batch's per-system sums:
+    after each graph replay every system's kinetic energy is the oracle's sum over the
+    velocities reached; at the end the potential energies of the last replay equal an
+    eager force call's at the same state bit for bit, and the oracle's within the force
+    tolerance."""
+    import torch
+    from paper_2401_03180_amd import md
+    s = synth.methane_clusters(n_clusters=150, lo=100, hi=400, n_steps=40)
+    s.base[:] = np.where(s.base > 0, 0.05, 0.0)       # charged ions from the first steps
+    s.g[:] = 1.0
+    assert s.n_systems == 150
+    say("energy sums of 150 systems")
+    eng = make_engine(s, 1, density_hint=100.0)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        eng.set_step(0, st)
+        eng.build(md.MD_BUILD_FORCE, st)
+        eng.forces(energy=True, stream=st)
+        g = eng.graph(md.MD_BUILD_AUTO, st, energy=True, ekin=True)
+        for rep in range(8):
+            md.md_graph_launch(g, st)
+            st.synchronize()
+            ek = oracle.ekin(s, eng.host("vx"), eng.host("vy"), eng.host("vz"))
+            assert np.allclose(eng.host("ekin"), ek, rtol=1e-12, atol=0.0), rep
+        ep_graph = eng.host("epot").copy()
+        eng.forces(energy=True, stream=st)
+        st.synchronize()
+        assert np.array_equal(eng.host("epot"), ep_graph)
+    q = eng.host("q")
+    assert (q > 0).any()
+    ref = oracle.forces(s, q=q, kappa=oracle_kappa(s, eng.get_step()), x=eng.host("x"),
+                        y=eng.host("y"), z=eng.host("z"))
+    for b in range(s.n_systems):
+        a0, a1 = s.sys_offsets[b], s.sys_offsets[b + 1]
+        esc = 2 * np.abs(ref["e_atom"][a0:a1]).sum()
+        assert abs(ep_graph[b] - ref["epot"][b]) <= TOL[1] * esc, b
+    assert eng.sync_check(raise_on_flags=False) == 0
+    eng.close()
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_water_large_groups_of_eight_no_overflow(prec):
     """4,194,304-atom water box with 8 i-clusters per group, skin 0.09 nm: a group of 8
